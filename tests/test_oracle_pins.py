@@ -1,0 +1,401 @@
+"""Pins of the CPU oracle against the paper and against mathematics that does not
+come from the oracle itself (printed tables, closed forms, brute force,
+invariants).  CPU only."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ewald2d as ew
+from oracle import fast
+from oracle.direct import gaussian_lattice_sum, sog_direct
+from oracle.sog import SOG, TABLE1, continuity_residuals, far, solve_r0_omega, weights
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _table1_fixture():
+    rows = []
+    with open(os.path.join(GOLDEN, "table1.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                v = line.split()
+                rows.append((float(v[0]), float(v[1]), float(v[2]), float(v[3]), int(v[4]), float(v[5]), int(v[6])))
+    return rows
+
+
+# ---------------------------------------------------------------- SOG decomposition (Sec. 2.2, Table 1)
+
+def test_table1_matches_paper_fixture():
+    fx = _table1_fixture()
+    assert len(fx) == len(TABLE1) == 6
+    for a, b in zip(fx, TABLE1):
+        assert a == pytest.approx(b, rel=1e-15)
+
+
+@pytest.mark.parametrize("row", range(6))
+def test_table1_rows_satisfy_c1_continuity(row):
+    b, r0, om = _table1_fixture()[row][:3]
+    g0, g1 = continuity_residuals(b, r0, om)
+    assert abs(g0) < 1e-13 and abs(g1) < 1e-13
+
+
+def test_newton_recovers_table_row():
+    b, r0, om = _table1_fixture()[3][:3]
+    r, o = solve_r0_omega(b, r0 * 0.99, 1.0)
+    g = continuity_residuals(b, r, o)
+    assert max(abs(g[0]), abs(g[1])) < 1e-13
+    # the C^1 system is very flat in r0 (the u-series error oscillation is ~1e-8), so r0 is
+    # fixed only to ~1e-5 relative while omega is fixed to ~1e-11
+    assert abs(o - om) < 1e-9 and abs(r - r0) < 1e-4 * r0
+
+
+@pytest.mark.parametrize("row", [2, 3, 4])
+def test_far_part_reproduces_one_over_r(row):
+    """BSA (eq. BSA / pointwiseerror): beyond r_c the far part alone is 1/r up to the
+    aliasing error 2 sqrt(2) exp(-pi^2/(2 log b)) and the omitted l<0 terms."""
+    b, r0, om = _table1_fixture()[row][:3]
+    sigma = 0.7
+    rc = r0 * sigma
+    w, s = weights(b, sigma, om, 400)
+    r = np.linspace(rc, 50 * rc, 200)
+    relerr = np.abs(r * far(r, w, s) - 1.0)
+    bound = 2 * math.sqrt(2) * math.exp(-math.pi ** 2 / (2 * math.log(b))) + b * math.exp(-(rc / (s[0] / b)) ** 2) * 10
+    assert relerr.max() < bound
+
+
+def test_near_kernel_is_c1_at_cutoff():
+    """r_c is a root of 1/r - F and of its derivative (eqs. 2.20, 2.22)."""
+    b, r0, om = _table1_fixture()[3][:3]
+    sog = SOG(b, r0, om, 3.0, 300)
+    rc = sog.rc
+    f = 1 / rc - far(rc, sog.w, sog.s)
+    h = 1e-5
+    fp = ((1 / (rc + h) - far(rc + h, sog.w, sog.s)) - (1 / (rc - h) - far(rc - h, sog.w, sog.s))) / (2 * h)
+    assert abs(f) < 1e-12 and abs(fp) < 1e-8
+
+
+# ---------------------------------------------------------------- Ewald2D
+
+def _small_system(seed=3, N=6, box=(1.0, 1.3, 2.0)):
+    rng = np.random.default_rng(seed)
+    x = rng.random((N, 3)) * box
+    q = np.array([1, -1, 1, -1, 2, -2.0])[:N]
+    return x, q, box
+
+
+def test_ewald2d_alpha_independent():
+    x, q, box = _small_system()
+    a = ew.ewald2d(x, q, box, alpha=2.0)
+    for alpha in (1.0, 4.5):
+        b = ew.ewald2d(x, q, box, alpha=alpha)
+        assert np.max(np.abs(a["phi"] - b["phi"])) < 1e-12 * np.max(np.abs(a["phi"]))
+        assert np.max(np.abs(a["grad"] - b["grad"])) < 1e-12 * np.max(np.abs(a["grad"]))
+
+
+def test_ewald2d_matches_brute_force_image_sum():
+    """Plain image sums of 1/r (Gaussian-damped lattice, extrapolated to no damping)."""
+    x, q, box = _small_system()
+    e = ew.ewald2d(x, q, box)["phi"]
+    bf = ew.brute_force_extrapolated(x, q, box)
+    assert np.max(np.abs(bf - e)) < 1e-9 * np.max(np.abs(e))
+
+
+def test_ewald2d_forces_are_minus_energy_gradient():
+    x, q, box = _small_system(seed=5)
+    g = ew.ewald2d(x, q, box)["grad"]
+    h = 1e-5
+    for i in range(3):
+        for d in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, d] += h
+            xm[i, d] -= h
+            dU = (ew.energy(q, ew.ewald2d(xp, q, box, forces=False)["phi"])
+                  - ew.energy(q, ew.ewald2d(xm, q, box, forces=False)["phi"])) / (2 * h)
+            assert dU == pytest.approx(q[i] * g[i, d], abs=1e-8)
+
+
+def test_ewald2d_translation_invariance():
+    x, q, box = _small_system(seed=7)
+    a = ew.ewald2d(x, q, box)["phi"]
+    y = x + np.array([0.37, -0.21, 0.15])
+    b = ew.ewald2d(y, q, box)["phi"]
+    assert np.max(np.abs(a - b)) < 1e-12
+
+
+# ---------------------------------------------------------------- SOG-direct
+
+def test_gaussian_lattice_sum_poisson_identity():
+    """Real-space image sum == Poisson-summed Fourier form (App. A.5), both ways."""
+    rng = np.random.default_rng(0)
+    box = (3.0, 2.5, 4.0)
+    d = (rng.random((40, 3)) - 0.5) * box
+    q = rng.choice([-1.0, 1.0], 40)
+    q[-1] = -q[:-1].sum()  # neutral, as the expm1 form of k = 0 requires
+    # width where both forms are affordable: force each form by the box scale trick
+    s = 1.6
+    v_auto, g_auto = gaussian_lattice_sum(d, q, s, box)
+    # explicit real-space sum
+    val, g = 0.0, np.zeros(3)
+    for nx in range(-20, 21):
+        for ny in range(-20, 21):
+            dd = d + np.array([nx * box[0], ny * box[1], 0])
+            e = q * np.exp(-np.sum(dd * dd, 1) / s ** 2)
+            val += e.sum()
+            g += -2 / s ** 2 * (e @ dd)
+    assert v_auto == pytest.approx(val, abs=1e-12)
+    assert np.allclose(g_auto, g, atol=1e-12)
+    # explicit Fourier sum
+    A = box[0] * box[1]
+    vf = 0.0
+    for nx in range(-30, 31):
+        for ny in range(-30, 31):
+            kx, ky = 2 * math.pi * nx / box[0], 2 * math.pi * ny / box[1]
+            vf += np.sum(q * math.pi * s * s / A * np.exp(-d[:, 2] ** 2 / s ** 2) * math.exp(-s * s * (kx * kx + ky * ky) / 4)
+                         * np.cos(kx * d[:, 0] + ky * d[:, 1]))
+    assert vf == pytest.approx(val, abs=1e-12)
+
+
+def _fig1_system():
+    """Sec. 2.3: 100 random monovalent particles in a unit cube, r_c = 0.3 (Fig. 1 setup)."""
+    x, q = workloads.uniform(100, (1.0, 1.0, 1.0), seed=11)
+    return x, q, (1.0, 1.0, 1.0)
+
+
+@pytest.fixture(scope="module")
+def fig1_reference():
+    x, q, box = _fig1_system()
+    return x, q, box, ew.ewald2d(x, q, box)
+
+
+@pytest.mark.parametrize("row", [2, 3, 4, 5])
+def test_sog_direct_within_table1_error(fig1_reference, row):
+    """SOG decomposition error vs Ewald2D is within Table 1's printed energy and force errors."""
+    x, q, box, ref = fig1_reference
+    b, r0, om, eE, ME, eF, MF = _table1_fixture()[row]
+    sog = SOG(b, r0, om, 0.3, ME)
+    o = sog_direct(x, q, box, sog, m=sog.split_index(0.5, 1.0), targets=np.arange(q.size))
+    Uref = ew.energy(q, ref["phi"])
+    eU = abs(ew.energy(q, o["phi"]) - Uref) / abs(Uref)
+    Fref = -q[:, None] * ref["grad"]
+    F = -q[:, None] * o["grad"]
+    eFm = np.max(np.abs(F - Fref)) / np.max(np.abs(Fref))
+    assert eU <= max(eE, 1e-14)
+    assert eFm <= max(eF, 1e-13)
+
+
+def test_sog_direct_split_and_cutoff_invariance(fig1_reference):
+    """m only moves Gaussians between two sums; r_c changes the decomposition but not the
+    answer (both tested against Ewald2D at b = 1.1488, error ~1e-15)."""
+    x, q, box, ref = fig1_reference
+    b, r0, om = _table1_fixture()[5][:3]
+    T = np.arange(0, 100, 7)
+    outs = []
+    for rc, eta in ((0.3, 0.2), (0.3, 0.8), (0.45, 0.5)):
+        sog = SOG(b, r0, om, rc, 320)
+        outs.append(sog_direct(x, q, box, sog, m=sog.split_index(eta, 1.0), targets=T))
+    for o in outs:
+        assert np.max(np.abs(o["phi"] - ref["phi"][T])) < 1e-12 * np.max(np.abs(ref["phi"]))
+    assert np.max(np.abs(outs[0]["phi_mid"] - outs[1]["phi_mid"])) > 1e-3  # the split really moved
+
+
+# ---------------------------------------------------------------- Chebyshev (App. A.2, Thm thm::Che)
+
+def test_lagrange_basis_interpolates_polynomials_exactly():
+    P = 9
+    t = np.linspace(-1, 1, 57)
+    L, dL = fast.lagrange(t, P)
+    tc = fast.cheb_nodes(P)
+    for deg in range(P):
+        c = np.random.default_rng(deg).normal(size=deg + 1)
+        f = np.polynomial.polynomial.polyval(tc, c)
+        assert np.allclose(L @ f, np.polynomial.polynomial.polyval(t, c), atol=1e-12)
+        dc = np.polynomial.polynomial.polyder(c)
+        assert np.allclose(dL @ f, np.polynomial.polynomial.polyval(t, dc) if deg else 0 * t, atol=1e-10)
+    assert np.allclose(L.sum(axis=1), 1.0, atol=1e-14)
+    # cardinal property at the nodes
+    Ln, _ = fast.lagrange(tc, P)
+    assert np.allclose(Ln, np.eye(P), atol=1e-13)
+
+
+def test_chebyshev_digits_of_theorem_che():
+    rows = []
+    with open(os.path.join(GOLDEN, "chebyshev_digits.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                eta, P, dig = line.split()
+                rows.append((float(eta), int(P), int(dig)))
+    Lz = 1.0
+    z = np.linspace(-Lz / 2, Lz / 2, 2001)
+    for eta, P, dig in rows:
+        s = eta * Lz
+        f = lambda zz: np.exp(-zz ** 2 / s ** 2)
+        L, _ = fast.lagrange(2 * z / Lz, P)
+        err = np.max(np.abs(L @ f(0.5 * Lz * fast.cheb_nodes(P)) - f(z)))
+        # Thm thm::Che's bound with the two constants its proof drops: the monic Chebyshev
+        # node polynomial has max 2^(1-P) (not 2^-P) and Cramer's Hermite-function
+        # inequality behind eq. 2.38 carries a factor 1.0865
+        bound = 2 * 1.0865 / (math.sqrt(math.factorial(P)) * (2 * math.sqrt(2) * eta) ** P)
+        assert err <= bound + 1e-14  # 1e-14: the FP64 round-off floor of the evaluation
+        assert err <= max(5 * 10.0 ** (-dig), 1e-14)  # "about dig digits"
+
+
+# ---------------------------------------------------------------- fast method vs SOG-direct
+
+@pytest.fixture(scope="module")
+def cube_case():
+    """N=1000 in a 20^3 box (Sec. 5.1's accuracy-test box), b = 1.3207, r_c = 4, eta = 0.4."""
+    x, q = workloads.uniform(1000, (20.0, 20.0, 20.0), seed=1)
+    box = (20.0, 20.0, 20.0)
+    b, r0, om = _table1_fixture()[3][:3]
+    sog = SOG(b, r0, om, 4.0, 100)
+    m = sog.split_index(0.4, 20.0)
+    T = np.arange(0, 1000, 25)
+    ref = sog_direct(x, q, box, sog, m, T)
+    return x, q, box, sog, m, T, ref
+
+
+def test_fast_near_is_exact(cube_case):
+    x, q, box, sog, m, T, ref = cube_case
+    p, g = fast.near_field(fast.centered(x, box), q, box, sog)
+    assert np.max(np.abs(p[T] - ref["phi_near"])) < 1e-12
+    assert np.max(np.abs(g[T] - ref["grad_near"])) < 1e-11
+
+
+def test_fast_mid_converges_gaussian_rate_in_grid(cube_case):
+    """Fig. 2(b) / Thm thm::trunFour: error falls like exp(-C I^2) with the grid size I."""
+    x, q, box, sog, m, T, ref = cube_case
+    xc = fast.centered(x, box)
+    scale = np.max(np.abs(ref["phi"]))
+    errs = []
+    for I in (24, 28, 32):
+        mid = dict(I=(I, I, I), Izs=2 * I + 40, Pw=(19, 19, 19), S=0.455 * math.pi * 19)
+        p, _ = fast.mid_range(xc, q, box, sog, m, mid)
+        errs.append(np.max(np.abs(p[T] - ref["phi_mid"])) / scale)
+    # exp(-(pi s0 / 2h)^2) times a constant: successive ratios must match the Gaussian rate
+    s0 = sog.s[0]
+    for (I1, e1), (I2, e2) in zip(((24, errs[0]), (28, errs[1])), ((28, errs[1]), (32, errs[2]))):
+        pred = math.exp(-(math.pi * s0 / 2) ** 2 * ((I2 / 20.0) ** 2 - (I1 / 20.0) ** 2))
+        assert 0.2 * pred < e2 / e1 < 5 * pred
+    assert errs[-1] < 1e-5
+
+
+def test_fast_mid_converges_in_window_support(cube_case):
+    """Fig. 2(a) / Thm thm::scal: error falls with the window support P_w."""
+    x, q, box, sog, m, T, ref = cube_case
+    xc = fast.centered(x, box)
+    scale = np.max(np.abs(ref["phi"]))
+    prev = 1.0
+    for Pw in (5, 9, 13):
+        mid = dict(I=(48, 48, 48), Izs=140, Pw=(Pw, Pw, Pw), S=0.455 * math.pi * Pw)
+        p, g = fast.mid_range(xc, q, box, sog, m, mid)
+        e = np.max(np.abs(p[T] - ref["phi_mid"])) / scale
+        assert e < 0.1 * prev
+        prev = e
+    assert prev < 2e-7
+    assert np.max(np.abs(g[T] - ref["grad_mid"])) < 1e-6 * np.max(np.abs(ref["grad"]))
+
+
+def test_fast_long_direct_converges_spectrally(cube_case):
+    x, q, box, sog, m, T, ref = cube_case
+    xc = fast.centered(x, box)
+    scale = np.max(np.abs(ref["phi"]))
+    errs = []
+    for P, nk in ((8, 3), (12, 4), (20, 6)):
+        p, g = fast.long_range_direct(xc, q, box, sog, m, dict(form="direct", P=P, nk=(nk, nk)))
+        errs.append(np.max(np.abs(p[T] - ref["phi_long"])) / scale)
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-11
+    assert np.max(np.abs(g[T] - ref["grad_long"])) < 1e-10 * np.max(np.abs(ref["grad"]))
+
+
+def test_fast_long_fft_form_converges(cube_case):
+    x, q, box, sog, m, T, ref = cube_case
+    xc = fast.centered(x, box)
+    scale = np.max(np.abs(ref["phi"]))
+    errs = []
+    for I2, Pw2 in ((16, 7), (24, 11), (32, 15)):
+        lp = dict(form="fft", P=16, I=(I2, I2), Pw=(Pw2, Pw2), S=0.455 * math.pi * Pw2)
+        p, g = fast.long_range_fft(xc, q, box, sog, m, lp)
+        errs.append(np.max(np.abs(p[T] - ref["phi_long"])) / scale)
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 1e-8
+
+
+# ---------------------------------------------------------------- invariants of the fast discrete operator
+
+@pytest.fixture(scope="module")
+def small_fast():
+    x, q = workloads.uniform(200, (8.0, 9.0, 7.0), seed=21)
+    box = (8.0, 9.0, 7.0)
+    b, r0, om = _table1_fixture()[3][:3]
+    rc = 2.5
+    sog = SOG(b, r0, om, rc, 120)
+    m = sog.split_index(0.35, box[2])
+    params = fast.make_params(b, r0, om, rc, 120, m,
+                              mid=dict(I=(20, 24, 18), Izs=44, Pw=(9, 9, 9), S=0.455 * math.pi * 9),
+                              long=dict(form="direct", P=14, nk=(5, 5)))
+    return x, q, box, params
+
+
+def test_fast_forces_are_minus_gradient_of_discrete_energy(small_fast):
+    x, q, box, params = small_fast
+    o = fast.solve(x, q, box, params)
+    h = 1e-6
+    for i in (0, 57, 133):
+        for d in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, d] += h
+            xm[i, d] -= h
+            dU = (fast.solve(xp, q, box, params)["U"] - fast.solve(xm, q, box, params)["U"]) / (2 * h)
+            assert -dU == pytest.approx(o["force"][i, d], abs=2e-6 * max(1.0, abs(o["force"][i, d])))
+
+
+def test_fast_charge_flip_and_net_force(small_fast):
+    x, q, box, params = small_fast
+    a = fast.solve(x, q, box, params)
+    b = fast.solve(x, -q, box, params)
+    assert a["U"] == pytest.approx(b["U"], rel=1e-12)
+    assert np.allclose(a["phi"], -b["phi"], atol=1e-11)
+    assert np.allclose(a["force"], b["force"], atol=1e-10)
+    # Newton's third law holds for the exact operator; the grid breaks translation
+    # invariance, so the discrete one keeps it only to its discretisation error (~2e-4
+    # per particle at these coarse parameters)
+    assert np.max(np.abs(a["force"].sum(axis=0))) < 1e-2 * np.max(np.abs(a["force"]))
+
+
+def test_fast_total_matches_ewald2d():
+    """End to end: the fast method at tight parameters reproduces Ewald2D (Sec. 5.1 box)."""
+    x, q = workloads.uniform(1000, (20.0, 20.0, 20.0), seed=1)
+    box = (20.0, 20.0, 20.0)
+    b, r0, om = _table1_fixture()[4][:3]
+    rc = 4.0
+    sog = SOG(b, r0, om, rc, 200)
+    m = sog.split_index(0.4, 20.0)
+    params = fast.make_params(b, r0, om, rc, 200, m,
+                              mid=dict(I=(64, 64, 64), Izs=200, Pw=(17, 17, 17), S=0.455 * math.pi * 17),
+                              long=dict(form="direct", P=20, nk=(6, 6)))
+    o = fast.solve(x, q, box, params)
+    T = np.arange(0, 1000, 9)
+    ref = ew.ewald2d(x, q, box, targets=T)
+    assert np.max(np.abs(o["phi"][T] - ref["phi"])) < 1e-8 * np.max(np.abs(ref["phi"]))
+    Fref = -q[T, None] * ref["grad"]
+    assert np.max(np.abs(o["force"][T] - Fref)) < 1e-7 * np.max(np.abs(Fref))
+
+
+def test_all_long_regime_matches_mid_plus_long():
+    """Remark after the range-splitting definition: with every Gaussian long-range the
+    mid-range solver is skipped and the answer is unchanged."""
+    x, q = workloads.uniform(300, (12.0, 12.0, 1.5), seed=9)
+    box = (12.0, 12.0, 1.5)
+    b, r0, om = _table1_fixture()[4][:3]
+    rc = 2.0
+    sog = SOG(b, r0, om, rc, 200)
+    ref = sog_direct(x, q, box, sog, m=-1, targets=np.arange(0, 300, 11))
+    # s_0 = 0.5 is narrow, so the direct form needs |k| up to ~21 (nk = 40) here
+    params = fast.make_params(b, r0, om, rc, 200, -1, long=dict(form="direct", P=20, nk=(40, 40)))
+    o = fast.solve(x, q, box, params)
+    T = np.arange(0, 300, 11)
+    assert np.max(np.abs(o["phi"][T] - ref["phi"])) < 1e-8 * np.max(np.abs(ref["phi"]))
