@@ -1,0 +1,176 @@
+/*
+ * sog.h -- C ABI of the MI355X (gfx950) fast spectral sum-of-Gaussians solver for
+ * quasi-2D electrostatics: x and y periodic, z free.
+ *
+ * The problem (paper Sec. 2.1, eqs. Poisson, chargeneutral, Phi): N point charges
+ * q_i at r_i in the box [0,Lx) x [0,Ly) x [0,Lz], periodic in x and y, free in z,
+ * with sum_i q_i = 0.  In Gaussian units
+ *
+ *     Phi_i = sum_j sum'_{n in Z^2 x {0}} q_j / |r_i - r_j + n o L|     (prime: no j = i, n = 0)
+ *     U     = 1/2 sum_i q_i Phi_i
+ *     F_i   = -q_i grad Phi(r_i) = -dU/dr_i
+ *
+ * The solver splits 1/r with the u-series sum-of-Gaussians decomposition
+ * (eq. SOGdecomp): a near-field part summed directly over cell lists (eq. phiNDR),
+ * a mid-range part by a 3D Fourier spectral solver without upsampling (Alg. al::mid),
+ * and a long-range part by a Fourier-Chebyshev solver with Chebyshev interpolation
+ * and anterpolation in z (Alg. al::long_nonfft, or Alg. al::long with 2D FFTs), and
+ * subtracts the self term (eq. phiNDR).  Every step runs in the library's own HIP
+ * kernels (including its FFTs); the host only plans.
+ *
+ * Conventions shared by every entry point
+ *   - Coordinates: x (n x 3, row-major, float64).  x and y may be any finite value
+ *     (wrapped modulo Lx, Ly); z must lie in [0, Lz].
+ *   - Charges: q (n, float64), charge neutral to |sum q| <= 1e-10 sum |q|
+ *     (Prop. lem::summation: the lattice sum converges only for a neutral cell).
+ *   - Ownership: the caller owns x, q and all outputs; the plan owns all device
+ *     workspace, allocated at plan time.  Pointers are host pointers unless the plan
+ *     was created with options.pointers_on_device = 1, in which case every array
+ *     argument (inputs and outputs) is a device pointer on options.device.
+ *   - Streams: all work of a call is ordered on options.stream (NULL = the default
+ *     stream).  A call returns after its results are complete when pointers are on
+ *     the host, or when check_inputs is on; otherwise it may return before the
+ *     device finishes (outputs are then ready in stream order).
+ *   - Errors: every entry point returns a status and never aborts the process.
+ *     Outputs are unspecified when the status is not SOG_OK.  sog_last_error()
+ *     returns a message for the last failure on the calling thread.
+ *   - Thread safety: a plan must not be used by two calls at once; distinct plans
+ *     are independent.
+ */
+#ifndef SOG_H
+#define SOG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sog_plan_s* sog_plan_t;
+
+typedef enum {
+    SOG_OK = 0,
+    SOG_ERR_INVALID_ARG = 1,     /* null pointer, n <= 0, bad box, non-finite input, bad override */
+    SOG_ERR_NOT_NEUTRAL = 2,     /* |sum q| > 1e-10 sum |q| (Prop. lem::summation)                */
+    SOG_ERR_OUT_OF_BOX = 3,      /* some z outside [0, Lz]                                          */
+    SOG_ERR_TOL_UNREACHABLE = 4, /* tol outside [1e-12, 1e-2] (FP64) or [1e-5, 1e-2] (FP32 bulk)   */
+    SOG_ERR_OUT_OF_MEMORY = 5,   /* device allocation failed, or above SOG_MAX_DEVICE_BYTES       */
+    SOG_ERR_DEVICE = 6           /* any other HIP runtime error                                    */
+} sog_status;
+
+typedef enum {
+    SOG_PREC_FP64 = 0,      /* every step in float64                                             */
+    SOG_PREC_FP32_BULK = 1  /* spread, FFTs, gathers, near and long-range arithmetic in float32;  */
+                            /* float64 for the decomposition, tables, reductions over particles  */
+                            /* and the final energy; particle coordinates enter float32 only as  */
+                            /* offsets from a cell or grid point, formed in float64              */
+} sog_precision;
+
+typedef enum { SOG_LONG_AUTO = 0, SOG_LONG_DIRECT = 1, SOG_LONG_FFT = 2 } sog_long_form;
+
+/*
+ * Discretisation parameters.  In options, a zero field means "choose it from tol";
+ * sog_plan_info() returns the fully resolved set.  Symbols follow the paper.
+ */
+typedef struct {
+    /* SOG decomposition (Sec. 2.2-2.3, Table 1): b, r0, omega as a set, or all 0. */
+    double b, r0, omega;
+    double rc;          /* near-field cutoff r_c (sigma = r_c / r0), <= min(Lx,Ly)/2      */
+    int32_t M;          /* index of the last Gaussian, w_0..w_M                            */
+    int32_t m;          /* index of the last mid-range Gaussian (Sec. 3.1); -1: no mid    */
+    int32_t set_m;      /* options only: 1 = use m as given (else chosen by cost)         */
+    /* mid range (Alg. al::mid, Sec. 3.4): I_x, I_y, I_z grid intervals over the box,  */
+    /* I_z* points in the padded free direction (even), window points P_w (odd) and   */
+    /* the Gaussian window shape S (eq. GS).                                           */
+    int32_t mid_I[3];
+    int32_t mid_Izs;
+    int32_t mid_Pw[3];
+    double mid_S;
+    /* long range (Sec. 3.3, App. B): form, Chebyshev points P, Fourier modes          */
+    /* |n_x| <= nk_x, |n_y| <= nk_y for the direct form, or an I^long grid, window     */
+    /* points and shape for the FFT form.                                              */
+    int32_t long_form;
+    int32_t long_P;
+    int32_t long_nk[2];
+    int32_t long_I[2];
+    int32_t long_Pw[2];
+    double long_S;
+} sog_params;
+
+typedef struct {
+    int32_t precision;          /* sog_precision                                              */
+    int32_t device;             /* HIP device ordinal                                         */
+    void* stream;               /* hipStream_t, or NULL for the default stream                */
+    int32_t pointers_on_device; /* 1: x, q and outputs are device pointers                    */
+    int32_t check_inputs;       /* 1: check neutrality and z range on the device; costs one   */
+                                /*    device-to-host synchronisation per call                  */
+    int32_t timing;             /* 1: time every kernel with HIP events (sog_kernel_times)    */
+    sog_params params;          /* overrides; all zero = choose everything from tol          */
+} sog_options;
+
+/* Fill *opt with the defaults: FP64, device 0, default stream, host pointers, checks on,
+ * timing off, no overrides. */
+void sog_options_default(sog_options* opt);
+
+/* Plan for n particles in box (Lx, Ly, Lz) at relative tolerance tol with the default
+ * options.  tol is the target relative error of potentials, energy and forces. */
+sog_status sog_plan(const double box[3], int64_t n, double tol, sog_plan_t* out);
+
+/* As sog_plan with explicit options (opt may be NULL for the defaults). */
+sog_status sog_plan_ex(const double box[3], int64_t n, double tol, const sog_options* opt,
+                       sog_plan_t* out);
+
+/* Energy, potentials and forces (eqs. splitting and phisplit):
+ *   energy: 1 value or NULL; phi: n values or NULL; force: n x 3 row-major or NULL.
+ * x: n x 3 row-major positions; q: n charges (see the conventions above). */
+sog_status sog_energy_potential_force(sog_plan_t plan, const double* x, const double* q,
+                                      double* energy, double* phi, double* force);
+
+/* The parts of the potential and its gradient (eq. splitting), for checking each solver
+ * on its own: phi_parts is 3 x n (near, mid, long; the self term is not included),
+ * grad_parts is 3 x n x 3 (gradient of each part at r_i).  Same pointer rules. */
+sog_status sog_potential_parts(sog_plan_t plan, const double* x, const double* q,
+                               double* phi_parts, double* grad_parts);
+
+/* Run only the planner (no device work, no allocation): the parameters sog_plan_ex would
+ * use for this box, n, tol and options.  Works on a machine without a GPU. */
+sog_status sog_plan_resolve(const double box[3], int64_t n, double tol, const sog_options* opt,
+                            sog_params* out);
+
+/* The resolved parameters of a plan. */
+sog_status sog_plan_info(sog_plan_t plan, sog_params* out);
+
+/* Sizes of the plan: grid points of the mid-range grid, long-range modes or grid
+ * points, device bytes held, near-field cells. */
+typedef struct {
+    int64_t mid_grid_points;   /* I_x I_y I_z*                                */
+    int64_t long_points;       /* direct: modes (full plane); fft: I^long_x I^long_y */
+    int64_t device_bytes;      /* workspace held by the plan                  */
+    int32_t near_cells[3];
+    int32_t tile[3];           /* mid-range spread/gather tile, grid points  */
+} sog_plan_sizes;
+sog_status sog_plan_sizes_get(sog_plan_t plan, sog_plan_sizes* out);
+
+/* Per-kernel device times of the calls made since the plan was created (or since the
+ * last reset), when the plan was made with options.timing = 1.  Fills up to max
+ * entries (name, total milliseconds, launches) and returns the number of kernels in
+ * *count.  Names are static strings owned by the library. */
+typedef struct {
+    const char* name;
+    double total_ms;
+    int64_t launches;
+} sog_kernel_time;
+sog_status sog_kernel_times(sog_plan_t plan, sog_kernel_time* out, int32_t max, int32_t* count);
+sog_status sog_kernel_times_reset(sog_plan_t plan);
+
+/* Release the plan and its device workspace.  NULL is ignored. */
+void sog_destroy(sog_plan_t plan);
+
+const char* sog_status_string(sog_status s);
+const char* sog_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOG_H */

@@ -1,0 +1,656 @@
+// The C ABI (include/sog.h): plans, device workspace, the call pipeline and timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace sog {
+
+namespace {
+thread_local std::string g_last_error;
+const double kPi = 3.14159265358979323846;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+size_t real_size(const Resolved& r) { return r.prec == SOG_PREC_FP64 ? 8 : 4; }
+
+sog_status hip_status(hipError_t e, const char* what) {
+    if (e == hipSuccess) return SOG_OK;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    if (e == hipErrorOutOfMemory) return SOG_ERR_OUT_OF_MEMORY;
+    return SOG_ERR_DEVICE;
+}
+
+// Allocation with an optional cap (SOG_MAX_DEVICE_BYTES) so that the out-of-memory
+// path can be exercised from the host.
+struct Allocator {
+    std::vector<void*> ptrs;
+    size_t total = 0;
+    size_t cap = SIZE_MAX;
+    hipError_t err = hipSuccess;
+    bool capped = false;
+    Allocator() {
+        const char* c = std::getenv("SOG_MAX_DEVICE_BYTES");
+        if (c && *c) cap = (size_t)std::strtoull(c, nullptr, 10);
+    }
+    template <typename T>
+    void get(T*& out, size_t bytes) {
+        out = nullptr;
+        if (err != hipSuccess || capped) return;
+        bytes = std::max<size_t>(bytes, 16);
+        bytes = (bytes + 255) & ~(size_t)255;
+        if (total + bytes > cap) { capped = true; return; }
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) { err = e; return; }
+        ptrs.push_back(p);
+        total += bytes;
+        out = (T*)p;
+    }
+};
+
+template <typename T>
+std::vector<T> to_real(const std::vector<double>& v) {
+    std::vector<T> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = (T)v[i];
+    return o;
+}
+
+// e^{-2 pi i t / n}, t < n, as interleaved (re, im)
+std::vector<double> twiddles(int n, int count) {
+    std::vector<double> t(2 * (size_t)count);
+    for (int k = 0; k < count; ++k) {
+        double a = -2.0 * kPi * (double)k / (double)n;
+        t[2 * k] = std::cos(a);
+        t[2 * k + 1] = std::sin(a);
+    }
+    return t;
+}
+
+hipError_t upload(void* dst, const std::vector<double>& v, bool f64) {
+    if (v.empty()) return hipSuccess;
+    if (f64) return hipMemcpy(dst, v.data(), v.size() * 8, hipMemcpyHostToDevice);
+    std::vector<float> f = to_real<float>(v);
+    return hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+}
+
+// 1 / What(k)^2 for the Gaussian window (eq. GS), exponent returned separately
+double inv_what2_log(double k, double H, double S, double* pref) {
+    *pref = S / (kPi * H * H);
+    return k * k * H * H / (2.0 * S);
+}
+
+sog_status build_plan(Plan& p) {
+    Resolved& r = p.r;
+    Workspace& ws = p.ws;
+    const bool f64 = r.prec == SOG_PREC_FP64;
+    const size_t rs = real_size(r), cs = 2 * rs;
+    const int64_t n = r.n;
+    Allocator A;
+    if (!p.on_device) {
+        A.get(ws.x, 3 * n * 8);
+        A.get(ws.q, n * 8);
+        A.get(ws.phi, n * 8);
+        A.get(ws.force, 3 * n * 8);
+        A.get(ws.energy, 8);
+    }
+    A.get(ws.qsum, 2 * 8);
+    A.get(ws.status, 4);
+    A.get(ws.parts_phi, 3 * n * rs);
+    A.get(ws.parts_grad, 9 * n * rs);
+    A.get(ws.key, n * 4);
+    A.get(ws.perm, n * 4);
+    const int ncells = r.nc[0] * r.nc[1] * r.nc[2];
+    int64_t maxbins = ncells;
+    A.get(ws.cell_start, (ncells + 1) * 4);
+    A.get(ws.cell_cursor, ncells * 4);
+    A.get(ws.near_cell, n * 4);
+    A.get(ws.near_orig, n * 4);
+    A.get(ws.near_pos, n * 4 * rs);
+    if (r.has_mid) {
+        const int ntiles = r.ntile[0] * r.ntile[1] * r.ntile[2];
+        maxbins = std::max<int64_t>(maxbins, ntiles);
+        const int Kz = r.Izs / 2 + 1;
+        A.get(ws.tile_start, (ntiles + 1) * 4);
+        A.get(ws.tile_cursor, ntiles * 4);
+        A.get(ws.dup_start, (ntiles + 1) * 4);
+        A.get(ws.dup_cursor, ntiles * 4);
+        A.get(ws.dup_list, (size_t)n * r.max_dup * 4);
+        A.get(ws.mid_g, n * 16);
+        A.get(ws.mid_u, n * 4 * rs);
+        A.get(ws.grid, (size_t)r.I[0] * r.I[1] * r.Izs * rs);
+        A.get(ws.cgrid, (size_t)r.I[0] * r.I[1] * Kz * cs);
+        A.get(ws.tw_x, r.I[0] * cs);
+        A.get(ws.tw_y, r.I[1] * cs);
+        A.get(ws.tw_z, (r.Izs / 2) * cs);
+        A.get(ws.tw_zpost, Kz * cs);
+        A.get(ws.mult_ax, (size_t)(r.m + 1) * r.I[0] * rs);
+        A.get(ws.mult_ay, (size_t)(r.m + 1) * r.I[1] * rs);
+        A.get(ws.mult_az, (size_t)(r.m + 1) * Kz * rs);
+        A.get(ws.mult_c, (size_t)(r.m + 1) * rs);
+    }
+    if (r.has_long) {
+        if (r.form == SOG_LONG_DIRECT) {
+            ws.long_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 1023) / 1024));
+            A.get(ws.long_kt, (size_t)r.nh * r.P * r.P * 8);
+            A.get(ws.long_mu, (size_t)ws.long_blocks * r.nh * r.P * 16);
+            A.get(ws.long_a, (size_t)r.nh * r.P * cs);
+        } else {
+            const int nt2 = r.ntile2[0] * r.ntile2[1];
+            maxbins = std::max<int64_t>(maxbins, nt2);
+            A.get(ws.l2_tile_start, (nt2 + 1) * 4);
+            A.get(ws.l2_tile_cursor, nt2 * 4);
+            A.get(ws.l2_dup_start, (nt2 + 1) * 4);
+            A.get(ws.l2_dup_cursor, nt2 * 4);
+            A.get(ws.l2_dup_list, (size_t)n * r.max_dup2 * 4);
+            A.get(ws.l2_g, n * 16);
+            A.get(ws.l2_u, n * 4 * rs);
+            A.get(ws.l2_grid, (size_t)r.P * r.I2[0] * r.I2[1] * cs);
+            A.get(ws.l2_tw_x, r.I2[0] * cs);
+            A.get(ws.l2_tw_y, r.I2[1] * cs);
+            A.get(ws.l2_kt_r, (size_t)(r.I2[0] / 2 + 1) * (r.I2[1] / 2 + 1) * r.P * r.P * rs);
+        }
+    }
+    A.get(ws.scan_tmp, ((maxbins + 1) / 1024 + 2) * 4);
+    ws.red_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256));
+    A.get(ws.red, ws.red_blocks * 8);
+    ws.bytes = A.total;
+    auto release = [&]() {
+        for (void* q : A.ptrs) (void)hipFree(q);
+        ws = Workspace();
+    };
+    if (A.capped) {
+        release();
+        set_error("device workspace exceeds SOG_MAX_DEVICE_BYTES");
+        return SOG_ERR_OUT_OF_MEMORY;
+    }
+    if (A.err != hipSuccess) {
+        sog_status s = hip_status(A.err, "hipMalloc");
+        release();
+        return s;
+    }
+    // tables (float64 on the host)
+    hipError_t e = hipSuccess;
+    if (r.has_mid) {
+        if (!factor_fft(r.I[0], p.fx) || !factor_fft(r.I[1], p.fy) || !factor_fft(r.Izs / 2, p.fz)) {
+            release();
+            set_error("mid FFT length is not 2,3,5,7-smooth");
+            return SOG_ERR_INVALID_ARG;
+        }
+        const int Kz = r.Izs / 2 + 1;
+        if (e == hipSuccess) e = upload(ws.tw_x, twiddles(r.I[0], r.I[0]), f64);
+        if (e == hipSuccess) e = upload(ws.tw_y, twiddles(r.I[1], r.I[1]), f64);
+        if (e == hipSuccess) e = upload(ws.tw_z, twiddles(r.Izs / 2, r.Izs / 2), f64);
+        if (e == hipSuccess) e = upload(ws.tw_zpost, twiddles(r.Izs, Kz), f64);
+        // separable factors of Ghat_mid(k) / What(k)^2 per Gaussian
+        const int nl = r.m + 1;
+        std::vector<double> ax((size_t)nl * r.I[0]), ay((size_t)nl * r.I[1]), az((size_t)nl * Kz), cl(nl);
+        const double Ng = (double)r.I[0] * r.I[1] * r.Izs;
+        auto fill = [&](std::vector<double>& t, int cnt, int N, double Ld, double H) {
+            for (int l = 0; l < nl; ++l)
+                for (int i = 0; i < cnt; ++i) {
+                    // FFT frequency index: 0, 1, .., -1 over a full line (x, y); 0 .. N/2
+                    // over the half spectrum (z)
+                    const int f = (cnt == N && i >= (N + 1) / 2) ? i - N : i;
+                    double k = 2.0 * kPi * f / Ld;
+                    double pref;
+                    double ex = -r.s[l] * r.s[l] * k * k / 4.0 + inv_what2_log(k, H, r.S, &pref);
+                    t[(size_t)l * cnt + i] = pref * std::exp(std::min(ex, 80.0));
+                }
+        };
+        fill(ax, r.I[0], r.I[0], r.L[0], r.H[0]);
+        fill(ay, r.I[1], r.I[1], r.L[1], r.H[1]);
+        fill(az, Kz, r.Izs, r.Lzs, r.H[2]);
+        for (int l = 0; l < nl; ++l) cl[l] = std::pow(kPi, 1.5) * r.w[l] * r.s[l] * r.s[l] * r.s[l] / Ng;
+        if (e == hipSuccess) e = upload(ws.mult_ax, ax, f64);
+        if (e == hipSuccess) e = upload(ws.mult_ay, ay, f64);
+        if (e == hipSuccess) e = upload(ws.mult_az, az, f64);
+        if (e == hipSuccess) e = upload(ws.mult_c, cl, f64);
+    }
+    if (r.has_long) {
+        if (r.form == SOG_LONG_DIRECT) {
+            std::vector<double> k2(r.nh);
+            int kk = 0;
+            for (int ny = 0; ny <= r.nk[1]; ++ny)
+                for (int nx = (ny == 0 ? 0 : -r.nk[0]); nx <= r.nk[0]; ++nx, ++kk) {
+                    double kx = 2.0 * kPi * nx / r.L[0], ky = 2.0 * kPi * ny / r.L[1];
+                    k2[kk] = kx * kx + ky * ky;
+                }
+            std::vector<double> kt((size_t)r.nh * r.P * r.P);
+            long_kernel_cheb_basis(r, k2.data(), r.nh, kt.data());
+            if (e == hipSuccess) e = hipMemcpy(ws.long_kt, kt.data(), kt.size() * 8, hipMemcpyHostToDevice);
+        } else {
+            if (!factor_fft(r.I2[0], p.f2x) || !factor_fft(r.I2[1], p.f2y)) {
+                release();
+                set_error("long-range FFT length is not 2,3,5,7-smooth");
+                return SOG_ERR_INVALID_ARG;
+            }
+            if (e == hipSuccess) e = upload(ws.l2_tw_x, twiddles(r.I2[0], r.I2[0]), f64);
+            if (e == hipSuccess) e = upload(ws.l2_tw_y, twiddles(r.I2[1], r.I2[1]), f64);
+            const int jx = r.I2[0] / 2 + 1, jy = r.I2[1] / 2 + 1;
+            std::vector<double> k2((size_t)jx * jy), scale((size_t)jx * jy);
+            for (int a = 0; a < jx; ++a)
+                for (int b = 0; b < jy; ++b) {
+                    double kx = 2.0 * kPi * a / r.L[0], ky = 2.0 * kPi * b / r.L[1];
+                    k2[(size_t)a * jy + b] = kx * kx + ky * ky;
+                    double px, py;
+                    double ex = inv_what2_log(kx, r.H2[0], r.S2, &px) + inv_what2_log(ky, r.H2[1], r.S2, &py);
+                    scale[(size_t)a * jy + b] = px * py * std::exp(std::min(ex, 80.0)) / ((double)r.I2[0] * r.I2[1]);
+                }
+            std::vector<double> kt((size_t)jx * jy * r.P * r.P);
+            long_kernel_cheb_basis(r, k2.data(), jx * jy, kt.data());
+            for (size_t k = 0; k < (size_t)jx * jy; ++k)
+                for (int i = 0; i < r.P * r.P; ++i) kt[k * r.P * r.P + i] *= scale[k];
+            if (e == hipSuccess) e = upload(ws.l2_kt_r, kt, f64);
+        }
+    }
+    if (e != hipSuccess) {
+        sog_status s = hip_status(e, "table upload");
+        release();
+        return s;
+    }
+    return SOG_OK;
+}
+
+void free_plan(Plan& p) {
+    Workspace& ws = p.ws;
+    void* ptrs[] = {ws.x, ws.q, ws.phi, ws.force, ws.energy, ws.qsum, ws.status, ws.parts_phi, ws.parts_grad,
+                    ws.key, ws.perm, ws.scan_tmp, ws.cell_start, ws.cell_cursor, ws.near_cell, ws.near_orig,
+                    ws.near_pos, ws.tile_start, ws.tile_cursor, ws.dup_start, ws.dup_cursor, ws.dup_list, ws.mid_g,
+                    ws.mid_u, ws.grid, ws.cgrid, ws.tw_x, ws.tw_y, ws.tw_z, ws.tw_zpost, ws.mult_ax, ws.mult_ay,
+                    ws.mult_az, ws.mult_c, ws.long_modes, ws.long_kt, ws.long_mu, ws.long_a, ws.l2_tile_start,
+                    ws.l2_tile_cursor, ws.l2_dup_start, ws.l2_dup_cursor, ws.l2_dup_list, ws.l2_g, ws.l2_u,
+                    ws.l2_grid, ws.l2_tw_x, ws.l2_tw_y, ws.l2_kt, ws.l2_kt_r, ws.red};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    ws = Workspace();
+    for (hipEvent_t ev : p.ev_pool) (void)hipEventDestroy(ev);
+    for (auto& pe : p.pending) {
+        (void)hipEventDestroy(pe.second.first);
+        (void)hipEventDestroy(pe.second.second);
+    }
+    p.ev_pool.clear();
+    p.pending.clear();
+}
+
+hipEvent_t take_event(Plan& p) {
+    if (!p.ev_pool.empty()) {
+        hipEvent_t e = p.ev_pool.back();
+        p.ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+hipError_t collect_timers(Plan& p) {
+    if (!p.timing) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(p.stream);
+    for (auto& pe : p.pending) {
+        float ms = 0;
+        if (pe.second.first && pe.second.second && hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
+            p.timers[pe.first].total_ms += ms;
+            p.timers[pe.first].launches += 1;
+        }
+        if (pe.second.first) p.ev_pool.push_back(pe.second.first);
+        if (pe.second.second) p.ev_pool.push_back(pe.second.second);
+    }
+    p.pending.clear();
+    return e;
+}
+
+sog_status run(Plan& p, const double* x_in, const double* q_in, double* energy, double* phi, double* force,
+               double* phi_parts, double* grad_parts) {
+    if (!x_in || !q_in) {
+        set_error("x and q must not be NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    DeviceGuard dg(p.device);
+    Workspace& ws = p.ws;
+    const int64_t n = p.r.n;
+    const double* x = x_in;
+    const double* q = q_in;
+    hipError_t e = hipSuccess;
+    if (!p.on_device) {
+        e = hipMemcpyAsync(ws.x, x_in, 3 * n * 8, hipMemcpyHostToDevice, p.stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(ws.q, q_in, n * 8, hipMemcpyHostToDevice, p.stream);
+        if (e != hipSuccess) return hip_status(e, "input copy");
+        x = ws.x;
+        q = ws.q;
+    }
+    if ((e = launch_prep(p, x, q)) != hipSuccess) return hip_status(e, "validate");
+    if ((e = launch_near(p, x, q)) != hipSuccess) return hip_status(e, "near field");
+    if (p.r.has_mid) {
+        if ((e = launch_mid(p, x, q)) != hipSuccess) return hip_status(e, "mid range");
+    } else if ((e = launch_zero_parts(p, 1)) != hipSuccess) {
+        return hip_status(e, "mid range");
+    }
+    if (p.r.has_long) {
+        if ((e = launch_long(p, x, q)) != hipSuccess) return hip_status(e, "long range");
+    } else if ((e = launch_zero_parts(p, 2)) != hipSuccess) {
+        return hip_status(e, "long range");
+    }
+    if (phi_parts || grad_parts) {
+        double *dpp = nullptr, *dgp = nullptr;
+        if (p.on_device) {
+            if ((e = launch_parts_out(p, phi_parts, grad_parts)) != hipSuccess) return hip_status(e, "parts");
+        } else {
+            // temporary device buffers for the parts (diagnostic entry point only)
+            if (phi_parts && (e = hipMalloc((void**)&dpp, 3 * n * 8)) != hipSuccess) return hip_status(e, "parts alloc");
+            if (grad_parts && (e = hipMalloc((void**)&dgp, 9 * n * 8)) != hipSuccess) {
+                if (dpp) (void)hipFree(dpp);
+                return hip_status(e, "parts alloc");
+            }
+            e = launch_parts_out(p, dpp, dgp);
+            if (e == hipSuccess && phi_parts) e = hipMemcpyAsync(phi_parts, dpp, 3 * n * 8, hipMemcpyDeviceToHost, p.stream);
+            if (e == hipSuccess && grad_parts) e = hipMemcpyAsync(grad_parts, dgp, 9 * n * 8, hipMemcpyDeviceToHost, p.stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+            if (dpp) (void)hipFree(dpp);
+            if (dgp) (void)hipFree(dgp);
+            if (e != hipSuccess) return hip_status(e, "parts");
+        }
+    } else {
+        double* dphi = p.on_device ? phi : (phi ? ws.phi : nullptr);
+        double* dforce = p.on_device ? force : (force ? ws.force : nullptr);
+        double* denergy = p.on_device ? energy : (energy ? ws.energy : nullptr);
+        if ((e = launch_combine(p, q, dphi, dforce, denergy)) != hipSuccess) return hip_status(e, "combine");
+        if (!p.on_device) {
+            if (phi && e == hipSuccess) e = hipMemcpyAsync(phi, ws.phi, n * 8, hipMemcpyDeviceToHost, p.stream);
+            if (force && e == hipSuccess) e = hipMemcpyAsync(force, ws.force, 3 * n * 8, hipMemcpyDeviceToHost, p.stream);
+            if (energy && e == hipSuccess) e = hipMemcpyAsync(energy, ws.energy, 8, hipMemcpyDeviceToHost, p.stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+            if (e != hipSuccess) return hip_status(e, "output copy");
+        }
+    }
+    if ((e = collect_timers(p)) != hipSuccess) return hip_status(e, "timing");
+    if (p.check) {
+        double qs[2];
+        int st = 0;
+        e = hipMemcpyAsync(qs, ws.qsum, 16, hipMemcpyDeviceToHost, p.stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&st, ws.status, 4, hipMemcpyDeviceToHost, p.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+        if (e != hipSuccess) return hip_status(e, "status copy");
+        if (st & 1) {
+            set_error("non-finite position or charge");
+            return SOG_ERR_INVALID_ARG;
+        }
+        if (st & 2) {
+            set_error("some z is outside [0, Lz]");
+            return SOG_ERR_OUT_OF_BOX;
+        }
+        if (std::fabs(qs[0]) > 1e-10 * qs[1]) {
+            set_error("charges are not neutral (|sum q| > 1e-10 sum |q|)");
+            return SOG_ERR_NOT_NEUTRAL;
+        }
+    }
+    return SOG_OK;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int timer_id(Plan& p, const char* name) {
+    if (!p.timing) return -1;
+    for (size_t i = 0; i < p.timers.size(); ++i)
+        if (p.timers[i].name == name || std::strcmp(p.timers[i].name, name) == 0) return (int)i;
+    p.timers.push_back(KernelTimer{name, 0.0, 0});
+    return (int)p.timers.size() - 1;
+}
+
+void timer_begin(Plan& p, int id) {
+    if (!p.timing || id < 0) return;
+    hipEvent_t a = take_event(p), b = take_event(p);
+    if (a) (void)hipEventRecord(a, p.stream);
+    p.pending.push_back({id, {a, b}});
+}
+
+void timer_end(Plan& p, int id) {
+    if (!p.timing || id < 0) return;
+    for (auto it = p.pending.rbegin(); it != p.pending.rend(); ++it)
+        if (it->first == id) {
+            if (it->second.second) (void)hipEventRecord(it->second.second, p.stream);
+            return;
+        }
+}
+
+}  // namespace sog
+
+using namespace sog;
+
+extern "C" {
+
+void sog_options_default(sog_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = SOG_PREC_FP64;
+    opt->check_inputs = 1;
+}
+
+sog_status sog_plan(const double box[3], int64_t n, double tol, sog_plan_t* out) {
+    return sog_plan_ex(box, n, tol, nullptr, out);
+}
+
+sog_status sog_plan_ex(const double box[3], int64_t n, double tol, const sog_options* opt_in, sog_plan_t* out) {
+    if (!out || !box) {
+        set_error("box and out must not be NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    sog_options opt;
+    sog_options_default(&opt);
+    if (opt_in) opt = *opt_in;
+    Plan* p = new (std::nothrow) Plan();
+    if (!p) {
+        set_error("host allocation failed");
+        return SOG_ERR_OUT_OF_MEMORY;
+    }
+    std::string err;
+    sog_status s = resolve(box, n, tol, opt, p->r, err);
+    if (s != SOG_OK) {
+        set_error(err);
+        delete p;
+        return s;
+    }
+    p->device = opt.device;
+    p->stream = (hipStream_t)opt.stream;
+    p->on_device = opt.pointers_on_device != 0;
+    p->check = opt.check_inputs != 0;
+    p->timing = opt.timing != 0;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        set_error("no HIP device available");
+        delete p;
+        return SOG_ERR_DEVICE;
+    }
+    if (opt.device < 0 || opt.device >= ndev) {
+        set_error("device ordinal out of range");
+        delete p;
+        return SOG_ERR_INVALID_ARG;
+    }
+    DeviceGuard dg(p->device);
+    s = build_plan(*p);
+    if (s != SOG_OK) {
+        delete p;
+        return s;
+    }
+    *out = reinterpret_cast<sog_plan_t>(p);
+    return SOG_OK;
+}
+
+sog_status sog_energy_potential_force(sog_plan_t plan, const double* x, const double* q, double* energy,
+                                      double* phi, double* force) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    return run(*reinterpret_cast<Plan*>(plan), x, q, energy, phi, force, nullptr, nullptr);
+}
+
+sog_status sog_potential_parts(sog_plan_t plan, const double* x, const double* q, double* phi_parts,
+                               double* grad_parts) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    if (!phi_parts && !grad_parts) {
+        set_error("phi_parts and grad_parts are both NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    return run(*reinterpret_cast<Plan*>(plan), x, q, nullptr, nullptr, nullptr, phi_parts, grad_parts);
+}
+
+static void fill_params(const Resolved& r, sog_params* o);
+
+sog_status sog_plan_resolve(const double box[3], int64_t n, double tol, const sog_options* opt_in, sog_params* out) {
+    if (!box || !out) {
+        set_error("box and out must not be NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    sog_options opt;
+    sog_options_default(&opt);
+    if (opt_in) opt = *opt_in;
+    Resolved r;
+    std::string err;
+    sog_status s = resolve(box, n, tol, opt, r, err);
+    if (s != SOG_OK) {
+        set_error(err);
+        return s;
+    }
+    fill_params(r, out);
+    return SOG_OK;
+}
+
+sog_status sog_plan_info(sog_plan_t plan, sog_params* o) {
+    if (!plan || !o) {
+        set_error("plan and out must not be NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    fill_params(reinterpret_cast<Plan*>(plan)->r, o);
+    return SOG_OK;
+}
+
+static void fill_params(const Resolved& r, sog_params* o) {
+    std::memset(o, 0, sizeof(*o));
+    o->b = r.b;
+    o->r0 = r.r0;
+    o->omega = r.omega;
+    o->rc = r.rc;
+    o->M = r.M;
+    o->m = r.m;
+    o->set_m = 1;
+    if (r.has_mid) {
+        for (int d = 0; d < 3; ++d) {
+            o->mid_I[d] = r.I[d];
+            o->mid_Pw[d] = r.Pw;
+        }
+        o->mid_Izs = r.Izs;
+        o->mid_S = r.S;
+    }
+    if (r.has_long) {
+        o->long_form = r.form;
+        o->long_P = r.P;
+        if (r.form == SOG_LONG_DIRECT) {
+            o->long_nk[0] = r.nk[0];
+            o->long_nk[1] = r.nk[1];
+        } else {
+            o->long_I[0] = r.I2[0];
+            o->long_I[1] = r.I2[1];
+            o->long_Pw[0] = o->long_Pw[1] = r.Pw2;
+            o->long_S = r.S2;
+        }
+    }
+}
+
+sog_status sog_plan_sizes_get(sog_plan_t plan, sog_plan_sizes* o) {
+    if (!plan || !o) {
+        set_error("plan and out must not be NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    const Plan& p = *reinterpret_cast<Plan*>(plan);
+    const Resolved& r = p.r;
+    std::memset(o, 0, sizeof(*o));
+    o->mid_grid_points = r.has_mid ? (int64_t)r.I[0] * r.I[1] * r.Izs : 0;
+    if (r.has_long)
+        o->long_points = (r.form == SOG_LONG_DIRECT) ? (int64_t)(2 * r.nk[0] + 1) * (2 * r.nk[1] + 1)
+                                                     : (int64_t)r.I2[0] * r.I2[1];
+    o->device_bytes = (int64_t)p.ws.bytes;
+    for (int d = 0; d < 3; ++d) {
+        o->near_cells[d] = r.nc[d];
+        o->tile[d] = r.B[d];
+    }
+    return SOG_OK;
+}
+
+sog_status sog_kernel_times(sog_plan_t plan, sog_kernel_time* out, int32_t max, int32_t* count) {
+    if (!plan || !count) {
+        set_error("plan and count must not be NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    const Plan& p = *reinterpret_cast<Plan*>(plan);
+    *count = (int32_t)p.timers.size();
+    for (int32_t i = 0; i < max && i < (int32_t)p.timers.size() && out; ++i) {
+        out[i].name = p.timers[i].name;
+        out[i].total_ms = p.timers[i].total_ms;
+        out[i].launches = p.timers[i].launches;
+    }
+    return SOG_OK;
+}
+
+sog_status sog_kernel_times_reset(sog_plan_t plan) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    Plan& p = *reinterpret_cast<Plan*>(plan);
+    for (auto& t : p.timers) {
+        t.total_ms = 0;
+        t.launches = 0;
+    }
+    return SOG_OK;
+}
+
+void sog_destroy(sog_plan_t plan) {
+    if (!plan) return;
+    Plan* p = reinterpret_cast<Plan*>(plan);
+    {
+        DeviceGuard dg(p->device);
+        (void)hipStreamSynchronize(p->stream);
+        free_plan(*p);
+    }
+    delete p;
+}
+
+const char* sog_status_string(sog_status s) {
+    switch (s) {
+        case SOG_OK: return "SOG_OK";
+        case SOG_ERR_INVALID_ARG: return "SOG_ERR_INVALID_ARG";
+        case SOG_ERR_NOT_NEUTRAL: return "SOG_ERR_NOT_NEUTRAL";
+        case SOG_ERR_OUT_OF_BOX: return "SOG_ERR_OUT_OF_BOX";
+        case SOG_ERR_TOL_UNREACHABLE: return "SOG_ERR_TOL_UNREACHABLE";
+        case SOG_ERR_OUT_OF_MEMORY: return "SOG_ERR_OUT_OF_MEMORY";
+        case SOG_ERR_DEVICE: return "SOG_ERR_DEVICE";
+    }
+    return "SOG_ERR_UNKNOWN";
+}
+
+const char* sog_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

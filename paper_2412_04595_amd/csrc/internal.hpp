@@ -1,0 +1,195 @@
+// Internal declarations of the SOG library: the resolved plan, the device
+// workspace and the kernel launchers.  Host code only (no device code here).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sog.h"
+
+namespace sog {
+
+constexpr int kMaxStages = 24;    // radix stages of one 1D FFT
+constexpr int kMaxNearDeg = 63;   // Chebyshev degree of the near-field polynomials
+constexpr int kMaxMid = 96;       // max number of mid-range Gaussians (m + 1)
+
+// A 1D FFT of length n as a product of small radices (Stockham, natural order).
+struct FFTFactors {
+    int n = 0;
+    int nstages = 0;
+    int radix[kMaxStages] = {0};
+};
+
+// Everything the planner decides (float64, host).  Symbols follow the paper.
+struct Resolved {
+    double L[3] = {0, 0, 0};
+    int64_t n = 0;
+    double tol = 0;
+    int prec = SOG_PREC_FP64;
+
+    // decomposition (Sec. 2.2)
+    double b = 0, r0 = 0, omega = 0, rc = 0, sigma = 0;
+    int M = 0, m = -1;
+    std::vector<double> w, s;
+    double self_coeff = 0;  // sum_l w_l
+
+    // near field: cells of side >= r_c; polynomials in x = 2 r^2/r_c^2 - 1
+    int nc[3] = {1, 1, 1};
+    double ch[3] = {0, 0, 0};
+    int near_deg = 0;
+    double near_cF[kMaxNearDeg + 1] = {0};  // F(r)
+    double near_cG[kMaxNearDeg + 1] = {0};  // F'(r)/r
+
+    // mid range (Alg. al::mid)
+    bool has_mid = false;
+    int I[3] = {0, 0, 0};  // I_x, I_y, I_z (intervals over the box)
+    int Izs = 0;           // padded z points I_z*
+    int Pw = 0;            // window points (same in every direction)
+    double S = 0;          // Gaussian window shape
+    double h[3] = {0, 0, 0};
+    double H[3] = {0, 0, 0};
+    double Lzs = 0;
+    int B[3] = {0, 0, 0};      // spread/gather tile
+    int ntile[3] = {0, 0, 0};
+    int max_dup = 1;           // max tiles a particle's window touches
+
+    // long range (Sec. 3.3 / App. B)
+    bool has_long = false;
+    int form = SOG_LONG_DIRECT;
+    int P = 0;
+    int nk[2] = {0, 0};        // direct form
+    int nh = 0;                // half-plane modes of the direct form
+    int I2[2] = {0, 0};        // FFT form grid
+    int Pw2 = 0;
+    double S2 = 0;
+    double h2[2] = {0, 0};
+    double H2[2] = {0, 0};
+    int B2[2] = {0, 0};
+    int ntile2[2] = {0, 0};
+    int max_dup2 = 1;
+};
+
+struct KernelTimer {
+    const char* name;
+    double total_ms = 0;
+    int64_t launches = 0;
+};
+
+// Device workspace; every pointer is owned by the plan.
+struct Workspace {
+    // staging of host inputs/outputs
+    double* x = nullptr;
+    double* q = nullptr;
+    double* phi = nullptr;
+    double* force = nullptr;
+    double* energy = nullptr;
+    // validation: [0] sum q, [1] sum |q| (double), status bits in an int
+    double* qsum = nullptr;
+    int* status = nullptr;
+    // per-part results in the particle's own order: 3 x n potentials, 3 x n x 3 gradients
+    void* parts_phi = nullptr;
+    void* parts_grad = nullptr;
+    // counting sorts
+    int* key = nullptr;       // n
+    int* perm = nullptr;      // n
+    int* scan_tmp = nullptr;  // block sums
+    // near field
+    int* cell_start = nullptr;  // ncells + 1
+    int* cell_cursor = nullptr; // ncells
+    int* near_cell = nullptr;   // n, cell of each sorted particle
+    int* near_orig = nullptr;   // n
+    void* near_pos = nullptr;   // n x real4 (cell-relative x, y, z, q)
+    // mid range
+    int* tile_start = nullptr;  // ntiles + 1 (owners)
+    int* tile_cursor = nullptr; // ntiles
+    int* dup_start = nullptr;   // ntiles + 1 (every tile a window touches)
+    int* dup_cursor = nullptr;  // ntiles
+    int* dup_list = nullptr;    // n * max_dup
+    int* mid_g = nullptr;       // n x int4 (grid point of each sorted particle, original index)
+    void* mid_u = nullptr;      // n x real4 (offset from the grid point in units of h, q)
+    void* grid = nullptr;       // I_x I_y I_z* reals
+    void* cgrid = nullptr;      // I_x I_y (I_z*/2 + 1) complex
+    void* tw_x = nullptr;       // twiddles e^{-2 pi i t/n} for each FFT length
+    void* tw_y = nullptr;
+    void* tw_z = nullptr;       // length I_z*/2
+    void* tw_zpost = nullptr;   // e^{-2 pi i k / I_z*}, k = 0..I_z*/2
+    void* mult_ax = nullptr;    // (m+1) x I_x: exp(-s^2 kx^2/4) / What_x^2
+    void* mult_ay = nullptr;    // (m+1) x I_y
+    void* mult_az = nullptr;    // (m+1) x (I_z*/2+1)
+    void* mult_c = nullptr;     // (m+1): pi^{3/2} w_l s_l^3 / (I_x I_y I_z*)
+    // long range
+    int* long_modes = nullptr;  // nh x int2 (direct form)
+    double* long_kt = nullptr;  // per mode P x P kernel in the Chebyshev basis (float64)
+    double* long_mu = nullptr;  // blocks x nh x P complex partial moments (float64)
+    void* long_a = nullptr;     // nh x P complex coefficients a(k,n) (real type)
+    int long_blocks = 0;
+    // FFT form of the long range
+    int* l2_tile_start = nullptr;
+    int* l2_tile_cursor = nullptr;
+    int* l2_dup_start = nullptr;
+    int* l2_dup_cursor = nullptr;
+    int* l2_dup_list = nullptr;
+    int* l2_g = nullptr;        // n x int4 (gx, gy, -, orig)
+    void* l2_u = nullptr;       // n x real4 (ux, uy, t = 2z/Lz, q)
+    void* l2_grid = nullptr;    // P x I2x x I2y complex
+    void* l2_tw_x = nullptr;
+    void* l2_tw_y = nullptr;
+    double* l2_kt = nullptr;    // (I2x/2+1) x (I2y/2+1) x P x P, divided by What2^2 and I2x I2y
+    void* l2_kt_r = nullptr;    // same in the working precision
+    // energy reduction
+    double* red = nullptr;
+    int red_blocks = 0;
+    size_t bytes = 0;
+};
+
+struct Plan {
+    Resolved r;
+    Workspace ws;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool on_device = false;
+    bool check = true;
+    bool timing = false;
+    FFTFactors fx, fy, fz;          // mid-range FFT lengths I_x, I_y, I_z*/2
+    FFTFactors f2x, f2y;            // long-range FFT form
+    std::vector<KernelTimer> timers;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+};
+
+// planner.cpp
+sog_status resolve(const double box[3], int64_t n, double tol, const sog_options& opt, Resolved& r,
+                   std::string& err);
+bool factor_fft(int n, FFTFactors& f);
+int long_fft_tile(int prec, int Pw2, int P);
+int next_smooth(int n, bool even);
+void near_chebyshev(Resolved& r);
+void long_kernel_cheb_basis(const Resolved& r, const double* k2, int nk, double* out);
+void cheb_V_inverse(int P, double* C);
+
+// error reporting
+void set_error(const std::string& msg);
+
+// kernel launchers (k_*.hip); every launcher checks its own shapes on the host
+struct Timed;  // RAII helper in api.cpp
+hipError_t launch_fill_int(int* p, int value, int64_t n, hipStream_t s);
+hipError_t launch_fill_bytes_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_prep(Plan& p, const double* x, const double* q);
+hipError_t launch_counting_sort(Plan& p, const int* key, int n, int nbins, int* start, int* cursor, int* perm);
+hipError_t launch_exclusive_scan(Plan& p, int* data, int nbins);  // in place, data has nbins+1 entries
+hipError_t launch_near(Plan& p, const double* x, const double* q);
+hipError_t launch_mid(Plan& p, const double* x, const double* q);
+hipError_t launch_long(Plan& p, const double* x, const double* q);
+hipError_t launch_combine(Plan& p, const double* q, double* phi, double* force, double* energy);
+hipError_t launch_parts_out(Plan& p, double* phi_parts, double* grad_parts);
+hipError_t launch_zero_parts(Plan& p, int part);
+
+// timing hooks (api.cpp)
+void timer_begin(Plan& p, int id);
+void timer_end(Plan& p, int id);
+int timer_id(Plan& p, const char* name);
+
+}  // namespace sog

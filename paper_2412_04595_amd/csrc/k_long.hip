@@ -1,0 +1,354 @@
+// Long range, Fourier-Chebyshev solver in its direct form (App. B, Alg. al::long_nonfft;
+// Sec. 3.3), with Chebyshev interpolation in the target z and anterpolation in the
+// source z (the "interpolation/anterpolation" of the abstract).
+//
+// With t = 2 z / Lz, first-kind Chebyshev nodes t_c and L_c(t) = sum_n C[c][n] T_n(t)
+// (C = V^{-1}, App. A.2), the kernel of eq. trun2 sampled on the nodes,
+//   K(k; c, c') = pi sum_{l>m} w_l s_l^2 exp(-s_l^2 |k|^2 / 4) exp(-(z_c - z_c')^2 / s_l^2),
+// gives
+//   Phi^long_i = (1/A) Re sum_k e^{i k.r_i} sum_c L_c(t_i) sum_c' K(k;c,c') sum_j q_j e^{-i k.r_j} L_c'(t_j).
+// In the Chebyshev coefficient basis this is
+//   mu(k, n)  = sum_j q_j e^{-i k.r_j} T_n(t_j)                 (moments: gridding + interpolation)
+//   a(k, n)   = (w_k / A) sum_n' Kt(k)[n][n'] mu(k, n'),  Kt = C^T K C   (scaling, built on the host)
+//   Phi^long_i = sum_{k in half plane} Re( e^{i k.r_i} sum_n T_n(t_i) a(k, n) )   (gathering)
+// with w_k = 1 for k = 0 and 2 otherwise (the output is real, mu(-k) = conj mu(k)).
+// The gradient uses i k in x, y and dT_n/dz = (2/Lz) n U_{n-1}(t) in z.
+//
+// Moments are summed per block in the working precision and across blocks in float64
+// in a fixed order.
+#include "device_common.hpp"
+
+namespace sog {
+
+namespace {
+
+constexpr int kMomThreads = 256;
+constexpr int kMomItems = 4;   // items per thread; an item is (mode, 4 consecutive n)
+
+template <typename real>
+struct MomArgs {
+    const double* x;
+    const double* q;
+    int n;
+    double L[3];
+    int nkx, nky, nh, P;
+    int per_block;  // particles per block
+    int chunk;      // particles per LDS batch (<= kMomThreads)
+    int item0, nitems;
+    double* mu;     // blocks x nh x P complex
+};
+
+__device__ __forceinline__ void mode_of(int kk, int nkx, int* nx, int* ny) {
+    if (kk <= nkx) {
+        *ny = 0;
+        *nx = kk;
+    } else {
+        const int r = kk - (nkx + 1);
+        *ny = 1 + r / (2 * nkx + 1);
+        *nx = r % (2 * nkx + 1) - nkx;
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(kMomThreads) void k_long_moments(MomArgs<real> a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int CH = a.chunk, P = a.P;
+    const int NX = 2 * a.nkx + 1, NY = a.nky + 1;
+    real* Tn = reinterpret_cast<real*>(smem_raw);                    // P x CH
+    cpx<real>* ex = reinterpret_cast<cpx<real>*>(Tn + P * CH);        // NX x CH (includes q)
+    cpx<real>* ey = ex + NX * CH;                                     // NY x CH
+    const int PB = (P + 3) / 4;
+    int kk[kMomItems], n0[kMomItems], nxs[kMomItems], nys[kMomItems];
+    bool act[kMomItems];
+    cpx<real> acc[kMomItems][4];
+#pragma unroll
+    for (int it = 0; it < kMomItems; ++it) {
+        const int item = a.item0 + threadIdx.x + it * kMomThreads;
+        act[it] = (item < a.nitems);
+        kk[it] = act[it] ? item / PB : 0;
+        n0[it] = act[it] ? (item % PB) * 4 : 0;
+        mode_of(kk[it], a.nkx, &nxs[it], &nys[it]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[it][c] = cpx<real>{0, 0};
+    }
+    const int pbeg = blockIdx.x * a.per_block;
+    const int pend = min(a.n, pbeg + a.per_block);
+    const double kx0 = 2.0 * 3.14159265358979323846 / a.L[0], ky0 = 2.0 * 3.14159265358979323846 / a.L[1];
+    for (int s = pbeg; s < pend; s += CH) {
+        const int cnt = min(CH, pend - s);
+        if (threadIdx.x < CH) {
+            const int t = threadIdx.x;
+            if (t < cnt) {
+                const int i = s + t;
+                double xx = a.x[3 * i], yy = a.x[3 * i + 1], zz = a.x[3 * i + 2], qq = a.q[i];
+                if (!(isfinite(xx) && isfinite(yy) && isfinite(zz) && isfinite(qq))) { xx = yy = zz = 0; qq = 0; }
+                const double xc = wrap_periodic(xx, a.L[0]) - 0.5 * a.L[0];
+                const double yc = wrap_periodic(yy, a.L[1]) - 0.5 * a.L[1];
+                double tt = 2.0 * (zz - 0.5 * a.L[2]) / a.L[2];
+                tt = fmin(1.0, fmax(-1.0, tt));
+                const real tr = (real)tt;
+                real T0 = 1, T1 = tr;
+                Tn[t] = T0;
+                if (P > 1) Tn[CH + t] = T1;
+                for (int k = 2; k < P; ++k) {
+                    const real T2 = (real)2 * tr * T1 - T0;
+                    Tn[k * CH + t] = T2;
+                    T0 = T1;
+                    T1 = T2;
+                }
+                real sx, cx, sy, cy;
+                dsincos((real)(kx0 * xc), &sx, &cx);
+                dsincos((real)(ky0 * yc), &sy, &cy);
+                const cpx<real> e1 = {cx, -sx};  // e^{-i kx0 x}
+                const cpx<real> e2 = {cy, -sy};
+                // e^{-i nx kx0 x} for nx = -nkx..nkx, times q
+                cpx<real> pw = {(real)qq, 0};
+                ex[a.nkx * CH + t] = pw;
+                cpx<real> pp = pw, pm = pw;
+                for (int k = 1; k <= a.nkx; ++k) {
+                    pp = cmul(pp, e1);
+                    pm = cmulc(pm, e1);
+                    ex[(a.nkx + k) * CH + t] = pp;
+                    ex[(a.nkx - k) * CH + t] = pm;
+                }
+                cpx<real> py = {1, 0};
+                ey[t] = py;
+                for (int k = 1; k <= a.nky; ++k) {
+                    py = cmul(py, e2);
+                    ey[k * CH + t] = py;
+                }
+            } else {
+                for (int k = 0; k < P; ++k) Tn[k * CH + t] = 0;
+                for (int k = 0; k < NX; ++k) ex[k * CH + t] = cpx<real>{0, 0};
+                for (int k = 0; k < NY; ++k) ey[k * CH + t] = cpx<real>{0, 0};
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kMomItems; ++it) {
+            if (!act[it]) continue;
+            const cpx<real>* exr = ex + (nxs[it] + a.nkx) * CH;
+            const cpx<real>* eyr = ey + nys[it] * CH;
+            for (int j = 0; j < cnt; ++j) {
+                const cpx<real> e = cmul(exr[j], eyr[j]);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int nn = n0[it] + c;
+                    if (nn < P) {
+                        const real tv = Tn[nn * CH + j];
+                        acc[it][c].x += e.x * tv;
+                        acc[it][c].y += e.y * tv;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int it = 0; it < kMomItems; ++it) {
+        if (!act[it]) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int nn = n0[it] + c;
+            if (nn < P) {
+                double* o = a.mu + 2 * (((size_t)blockIdx.x * a.nh + kk[it]) * P + nn);
+                o[0] = (double)acc[it][c].x;
+                o[1] = (double)acc[it][c].y;
+            }
+        }
+    }
+}
+
+// one block per mode: float64 sum over blocks, then a = (w_k/A) Kt mu
+template <typename real>
+__global__ void k_long_contract(const double* __restrict__ mu, int nblocks, int nh, int P, const double* __restrict__ kt,
+                                double invA, cpx<real>* __restrict__ aout) {
+    __shared__ double smu[2 * 64];
+    const int k = blockIdx.x;
+    for (int nn = threadIdx.x; nn < P; nn += blockDim.x) {
+        double sr = 0, si = 0;
+        for (int b = 0; b < nblocks; ++b) {
+            const double* o = mu + 2 * (((size_t)b * nh + k) * P + nn);
+            sr += o[0];
+            si += o[1];
+        }
+        smu[2 * nn] = sr;
+        smu[2 * nn + 1] = si;
+    }
+    __syncthreads();
+    const double wk = (k == 0 ? 1.0 : 2.0) * invA;
+    for (int nn = threadIdx.x; nn < P; nn += blockDim.x) {
+        const double* row = kt + ((size_t)k * P + nn) * P;
+        double sr = 0, si = 0;
+        for (int e = 0; e < P; ++e) {
+            sr += row[e] * smu[2 * e];
+            si += row[e] * smu[2 * e + 1];
+        }
+        aout[(size_t)k * P + nn] = cpx<real>{(real)(wk * sr), (real)(wk * si)};
+    }
+}
+
+template <typename real>
+struct EvalArgs {
+    const double* x;
+    int n;
+    double L[3];
+    int nkx, nky, nh, P;
+    const cpx<real>* acoef;
+    real* pphi;   // part 2
+    real* pgrad;
+};
+
+template <typename real>
+__global__ void k_long_eval(EvalArgs<real> a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int P = a.P, nh = a.nh;
+    cpx<real>* sa = reinterpret_cast<cpx<real>*>(smem_raw);  // nh x P
+    real* Tt = reinterpret_cast<real*>(sa + nh * P);          // P x blockDim: T_n(t)
+    real* Td = Tt + P * blockDim.x;                           // P x blockDim: dT_n/dt
+    for (int idx = threadIdx.x; idx < nh * P; idx += blockDim.x) sa[idx] = a.acoef[idx];
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int B = blockDim.x, t = threadIdx.x;
+    double xx = a.x[3 * i], yy = a.x[3 * i + 1], zz = a.x[3 * i + 2];
+    if (!(isfinite(xx) && isfinite(yy) && isfinite(zz))) xx = yy = zz = 0;
+    const double xc = wrap_periodic(xx, a.L[0]) - 0.5 * a.L[0];
+    const double yc = wrap_periodic(yy, a.L[1]) - 0.5 * a.L[1];
+    double tt = 2.0 * (zz - 0.5 * a.L[2]) / a.L[2];
+    tt = fmin(1.0, fmax(-1.0, tt));
+    const real tr = (real)tt;
+    {
+        // T_n and T_n' = n U_{n-1}
+        real T0 = 1, T1 = tr, U0 = 1, U1 = 2 * tr;
+        Tt[t] = 1;
+        Td[t] = 0;
+        if (P > 1) {
+            Tt[B + t] = tr;
+            Td[B + t] = 1;
+        }
+        for (int k = 2; k < P; ++k) {
+            const real T2 = (real)2 * tr * T1 - T0;
+            Tt[k * B + t] = T2;
+            Td[k * B + t] = (real)k * U1;
+            const real U2 = (real)2 * tr * U1 - U0;
+            T0 = T1; T1 = T2;
+            U0 = U1; U1 = U2;
+        }
+    }
+    const double kx0 = 2.0 * 3.14159265358979323846 / a.L[0], ky0 = 2.0 * 3.14159265358979323846 / a.L[1];
+    real sx, cx, sy, cy;
+    dsincos((real)(kx0 * xc), &sx, &cx);
+    dsincos((real)(ky0 * yc), &sy, &cy);
+    const cpx<real> e1 = {cx, sx}, e2 = {cy, sy};
+    real phi = 0, gx = 0, gy = 0, gz = 0;
+    const real rkx0 = (real)kx0, rky0 = (real)ky0;
+    // e^{-i nkx kx0 x}
+    cpx<real> eneg = {1, 0};
+    for (int k = 0; k < a.nkx; ++k) eneg = cmulc(eneg, e1);
+    cpx<real> phy = {1, 0};
+    int kk = 0;
+    for (int ny = 0; ny <= a.nky; ++ny) {
+        cpx<real> ph = (ny == 0) ? phy : cmul(phy, eneg);
+        const int nxlo = (ny == 0) ? 0 : -a.nkx;
+        for (int nx = nxlo; nx <= a.nkx; ++nx, ++kk) {
+            const cpx<real>* row = sa + (size_t)kk * P;
+            real ur = 0, ui = 0, dr = 0, di = 0;
+            for (int k = 0; k < P; ++k) {
+                const cpx<real> c = row[k];
+                const real tv = Tt[k * B + t], dv = Td[k * B + t];
+                ur += tv * c.x;
+                ui += tv * c.y;
+                dr += dv * c.x;
+                di += dv * c.y;
+            }
+            // e^{i k.r} (U)
+            const real re = ph.x * ur - ph.y * ui, im = ph.x * ui + ph.y * ur;
+            phi += re;
+            gx -= (real)nx * rkx0 * im;
+            gy -= (real)ny * rky0 * im;
+            gz += ph.x * dr - ph.y * di;
+            ph = cmul(ph, e1);
+        }
+        phy = cmul(phy, e2);
+    }
+    a.pphi[i] = phi;
+    a.pgrad[3 * i] = gx;
+    a.pgrad[3 * i + 1] = gy;
+    a.pgrad[3 * i + 2] = gz * (real)(2.0 / a.L[2]);
+}
+
+template <typename real>
+hipError_t run_long_direct(Plan& p, const double* x, const double* q) {
+    const Resolved& r = p.r;
+    Workspace& ws = p.ws;
+    const int n = (int)r.n, P = r.P, nh = r.nh;
+    const int NX = 2 * r.nk[0] + 1, NY = r.nk[1] + 1;
+    MomArgs<real> a;
+    a.x = x;
+    a.q = q;
+    a.n = n;
+    for (int d = 0; d < 3; ++d) a.L[d] = r.L[d];
+    a.nkx = r.nk[0];
+    a.nky = r.nk[1];
+    a.nh = nh;
+    a.P = P;
+    const int nb = ws.long_blocks;
+    a.per_block = (n + nb - 1) / nb;
+    int CH = kMomThreads;
+    while (CH > 16 && (size_t)CH * (P * sizeof(real) + (NX + NY) * sizeof(cpx<real>)) > 49152) CH >>= 1;
+    if ((size_t)CH * (P * sizeof(real) + (NX + NY) * sizeof(cpx<real>)) > 65536) return hipErrorInvalidConfiguration;
+    a.chunk = CH;
+    a.mu = ws.long_mu;
+    const int PB = (P + 3) / 4;
+    const int nitems = nh * PB;
+    a.nitems = nitems;
+    size_t lds = (size_t)CH * (P * sizeof(real) + (NX + NY) * sizeof(cpx<real>));
+    int t = timer_id(p, "long_moments");
+    timer_begin(p, t);
+    for (int i0 = 0; i0 < nitems; i0 += kMomThreads * kMomItems) {
+        a.item0 = i0;
+        k_long_moments<real><<<nb, kMomThreads, lds, p.stream>>>(a);
+    }
+    timer_end(p, t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    t = timer_id(p, "long_contract");
+    timer_begin(p, t);
+    k_long_contract<real><<<nh, 64, 0, p.stream>>>(ws.long_mu, nb, nh, P, ws.long_kt, 1.0 / (r.L[0] * r.L[1]),
+                                                   (cpx<real>*)ws.long_a);
+    timer_end(p, t);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    EvalArgs<real> ea;
+    ea.x = x;
+    ea.n = n;
+    for (int d = 0; d < 3; ++d) ea.L[d] = r.L[d];
+    ea.nkx = r.nk[0];
+    ea.nky = r.nk[1];
+    ea.nh = nh;
+    ea.P = P;
+    ea.acoef = (const cpx<real>*)ws.long_a;
+    ea.pphi = (real*)ws.parts_phi + 2 * r.n;
+    ea.pgrad = (real*)ws.parts_grad + 6 * r.n;
+    int B = 256;
+    while (B > 64 && (size_t)nh * P * sizeof(cpx<real>) + 2 * (size_t)P * B * sizeof(real) > 65536) B >>= 1;
+    size_t lds2 = (size_t)nh * P * sizeof(cpx<real>) + 2 * (size_t)P * B * sizeof(real);
+    if (lds2 > 65536) return hipErrorInvalidConfiguration;
+    t = timer_id(p, "long_eval");
+    timer_begin(p, t);
+    k_long_eval<real><<<(n + B - 1) / B, B, lds2, p.stream>>>(ea);
+    timer_end(p, t);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_long_fft(Plan& p, const double* x, const double* q);  // k_long2.hip
+
+hipError_t launch_long(Plan& p, const double* x, const double* q) {
+    if (p.r.form == SOG_LONG_FFT) return launch_long_fft(p, x, q);
+    if (p.r.prec == SOG_PREC_FP64) return run_long_direct<double>(p, x, q);
+    return run_long_direct<float>(p, x, q);
+}
+
+}  // namespace sog

@@ -1,0 +1,256 @@
+// Utility kernels: fills, input validation, counting sort (histogram, exclusive scan,
+// scatter), and the final combination of the parts (eqs. splitting and phisplit):
+// Phi_i = Phi_N + Phi_mid + Phi_long - q_i sum_l w_l, F_i = -q_i grad Phi_i,
+// U = 1/2 sum_i q_i Phi_i (float64 reduction in a fixed order).
+#include "device_common.hpp"
+
+namespace sog {
+
+namespace {
+
+__global__ void k_fill_int(int* p, int v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_fill_zero_u32(uint32_t* p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// Validation (problem statement, Sec. 2.1): finite inputs, z in [0, Lz], and the
+// charge sums used for the neutrality test of Prop. lem::summation.
+__global__ void k_prep(const double* __restrict__ x, const double* __restrict__ q, int64_t n, double Lz,
+                       double* __restrict__ qsum, int* __restrict__ status) {
+    __shared__ double red[16];
+    double s = 0, sa = 0;
+    int flags = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double xx = x[3 * i], yy = x[3 * i + 1], zz = x[3 * i + 2], qq = q[i];
+        if (!(isfinite(xx) && isfinite(yy) && isfinite(zz) && isfinite(qq))) {
+            flags |= 1;
+            continue;
+        }
+        if (zz < 0.0 || zz > Lz) flags |= 2;
+        s += qq;
+        sa += fabs(qq);
+    }
+    if (flags) atomicOr(status, flags);
+    double t = block_sum_double(s, red);
+    if (threadIdx.x == 0) atomicAdd(&qsum[0], t);
+    t = block_sum_double(sa, red);
+    if (threadIdx.x == 0) atomicAdd(&qsum[1], t);
+}
+
+__global__ void k_hist(const int* __restrict__ key, int n, int* __restrict__ count) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) atomicAdd(&count[key[i]], 1);
+}
+
+__global__ void k_scatter(const int* __restrict__ key, int n, const int* __restrict__ start, int* __restrict__ cursor,
+                          int* __restrict__ perm) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int k = key[i];
+        int pos = start[k] + atomicAdd(&cursor[k], 1);
+        perm[pos] = i;
+    }
+}
+
+constexpr int kScanPer = 4;
+constexpr int kScanThreads = 256;
+constexpr int kScanChunk = kScanPer * kScanThreads;
+
+// Exclusive scan of 256 per-thread totals in LDS; returns this thread's exclusive prefix,
+// and the block total in *total.
+__device__ int block_exclusive_scan(int v, int* lds, int* total) {
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < kScanThreads; o <<= 1) {
+        int add = (threadIdx.x >= o) ? lds[threadIdx.x - o] : 0;
+        __syncthreads();
+        lds[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int incl = lds[threadIdx.x];
+    *total = lds[kScanThreads - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(int* data, int len, int* block_sums) {
+    __shared__ int lds[kScanThreads];
+    const int base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+    int v[kScanPer];
+    int sum = 0;
+    for (int j = 0; j < kScanPer; ++j) {
+        v[j] = (base + j < len) ? data[base + j] : 0;
+        sum += v[j];
+    }
+    int total;
+    int pre = block_exclusive_scan(sum, lds, &total);
+    for (int j = 0; j < kScanPer; ++j) {
+        if (base + j < len) data[base + j] = pre;
+        pre += v[j];
+    }
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// single block: exclusive scan of nb block sums, chunk by chunk with a running carry
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(int* block_sums, int nb) {
+    __shared__ int lds[kScanThreads];
+    int carry = 0;
+    for (int c0 = 0; c0 < nb; c0 += kScanChunk) {
+        const int base = c0 + threadIdx.x * kScanPer;
+        int v[kScanPer];
+        int sum = 0;
+        for (int j = 0; j < kScanPer; ++j) {
+            v[j] = (base + j < nb) ? block_sums[base + j] : 0;
+            sum += v[j];
+        }
+        int total;
+        int pre = block_exclusive_scan(sum, lds, &total);
+        pre += carry;
+        for (int j = 0; j < kScanPer; ++j) {
+            if (base + j < nb) block_sums[base + j] = pre;
+            pre += v[j];
+        }
+        carry += total;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(int* data, int len, const int* block_sums) {
+    const int add = block_sums[blockIdx.x];
+    const int base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+    for (int j = 0; j < kScanPer; ++j)
+        if (base + j < len) data[base + j] += add;
+}
+
+template <typename real>
+__global__ void k_combine(const real* __restrict__ pphi, const real* __restrict__ pgrad, const double* __restrict__ q,
+                          int64_t n, double self_coeff, double* __restrict__ phi, double* __restrict__ force,
+                          double* __restrict__ red) {
+    __shared__ double lds[16];
+    double e = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double qi = q[i];
+        double ph = (double)pphi[i] + (double)pphi[n + i] + (double)pphi[2 * n + i] - qi * self_coeff;
+        double g[3];
+        for (int d = 0; d < 3; ++d)
+            g[d] = (double)pgrad[3 * i + d] + (double)pgrad[3 * (n + i) + d] + (double)pgrad[3 * (2 * n + i) + d];
+        if (phi) phi[i] = ph;
+        if (force)
+            for (int d = 0; d < 3; ++d) force[3 * i + d] = -qi * g[d];
+        e += qi * ph;
+    }
+    double t = block_sum_double(e, lds);
+    if (threadIdx.x == 0) red[blockIdx.x] = t;
+}
+
+__global__ void k_energy_final(const double* __restrict__ red, int nb, double* __restrict__ energy) {
+    __shared__ double lds[16];
+    double s = 0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += red[i];
+    // fixed-order tree: each thread's strided partial, then the block sum
+    double t = block_sum_double(s, lds);
+    if (threadIdx.x == 0) energy[0] = 0.5 * t;
+}
+
+template <typename real>
+__global__ void k_parts_out(const real* __restrict__ pphi, const real* __restrict__ pgrad, int64_t n,
+                            double* __restrict__ phi_parts, double* __restrict__ grad_parts) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 3 * n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (phi_parts) phi_parts[i] = (double)pphi[i];
+        if (grad_parts)
+            for (int d = 0; d < 3; ++d) grad_parts[3 * i + d] = (double)pgrad[3 * i + d];
+    }
+}
+
+int grid_for(int64_t n, int threads, int maxb = 4096) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > maxb) b = maxb;
+    return (int)b;
+}
+
+}  // namespace
+
+hipError_t launch_fill_int(int* p, int value, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_fill_int<<<grid_for(n, 256), 256, 0, s>>>(p, value, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_bytes_zero(void* p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    if (bytes % 4) return hipErrorInvalidValue;
+    int64_t n = (int64_t)(bytes / 4);
+    k_fill_zero_u32<<<grid_for(n, 256), 256, 0, s>>>((uint32_t*)p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(Plan& p, const double* x, const double* q) {
+    hipError_t e = launch_fill_bytes_zero(p.ws.qsum, 2 * sizeof(double), p.stream);
+    if (e != hipSuccess) return e;
+    e = launch_fill_int(p.ws.status, 0, 1, p.stream);
+    if (e != hipSuccess) return e;
+    int t = timer_id(p, "validate");
+    timer_begin(p, t);
+    k_prep<<<grid_for(p.r.n, 256, 1024), 256, 0, p.stream>>>(x, q, p.r.n, p.r.L[2], p.ws.qsum, p.ws.status);
+    timer_end(p, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_exclusive_scan(Plan& p, int* data, int len) {
+    int nb = (len + kScanChunk - 1) / kScanChunk;
+    k_scan_local<<<nb, kScanThreads, 0, p.stream>>>(data, len, p.ws.scan_tmp);
+    k_scan_sums<<<1, kScanThreads, 0, p.stream>>>(p.ws.scan_tmp, nb);
+    k_scan_add<<<nb, kScanThreads, 0, p.stream>>>(data, len, p.ws.scan_tmp);
+    return hipGetLastError();
+}
+
+// start has nbins + 1 entries; cursor has nbins; keys must lie in [0, nbins).
+hipError_t launch_counting_sort(Plan& p, const int* key, int n, int nbins, int* start, int* cursor, int* perm) {
+    hipError_t e = launch_fill_int(start, 0, (int64_t)nbins + 1, p.stream);
+    if (e != hipSuccess) return e;
+    e = launch_fill_int(cursor, 0, nbins, p.stream);
+    if (e != hipSuccess) return e;
+    k_hist<<<grid_for(n, 256), 256, 0, p.stream>>>(key, n, start);
+    e = launch_exclusive_scan(p, start, nbins + 1);
+    if (e != hipSuccess) return e;
+    k_scatter<<<grid_for(n, 256), 256, 0, p.stream>>>(key, n, start, cursor, perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(Plan& p, const double* q, double* phi, double* force, double* energy) {
+    int nb = p.ws.red_blocks;
+    int t = timer_id(p, "combine");
+    timer_begin(p, t);
+    if (p.r.prec == SOG_PREC_FP64)
+        k_combine<double><<<nb, 256, 0, p.stream>>>((const double*)p.ws.parts_phi, (const double*)p.ws.parts_grad, q,
+                                                     p.r.n, p.r.self_coeff, phi, force, p.ws.red);
+    else
+        k_combine<float><<<nb, 256, 0, p.stream>>>((const float*)p.ws.parts_phi, (const float*)p.ws.parts_grad, q,
+                                                    p.r.n, p.r.self_coeff, phi, force, p.ws.red);
+    if (energy) k_energy_final<<<1, 256, 0, p.stream>>>(p.ws.red, nb, energy);
+    timer_end(p, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_parts_out(Plan& p, double* phi_parts, double* grad_parts) {
+    if (p.r.prec == SOG_PREC_FP64)
+        k_parts_out<double><<<grid_for(3 * p.r.n, 256), 256, 0, p.stream>>>(
+            (const double*)p.ws.parts_phi, (const double*)p.ws.parts_grad, p.r.n, phi_parts, grad_parts);
+    else
+        k_parts_out<float><<<grid_for(3 * p.r.n, 256), 256, 0, p.stream>>>(
+            (const float*)p.ws.parts_phi, (const float*)p.ws.parts_grad, p.r.n, phi_parts, grad_parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_parts(Plan& p, int part) {
+    size_t rs = (p.r.prec == SOG_PREC_FP64) ? 8 : 4;
+    char* ph = (char*)p.ws.parts_phi + (size_t)part * p.r.n * rs;
+    char* gr = (char*)p.ws.parts_grad + (size_t)part * p.r.n * 3 * rs;
+    hipError_t e = launch_fill_bytes_zero(ph, p.r.n * rs, p.stream);
+    if (e != hipSuccess) return e;
+    return launch_fill_bytes_zero(gr, 3 * p.r.n * rs, p.stream);
+}
+
+}  // namespace sog

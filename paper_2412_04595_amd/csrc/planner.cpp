@@ -1,0 +1,516 @@
+// Parameter selection and host-side tables (float64).
+//
+// The choices follow the paper's parameter-selection procedure (Sec. 4.3) with the
+// error estimates of Sec. 2.3 (Thm thm:SOG, Table 1), Sec. 4.1 (Thms thm::trunFour,
+// thm::scal, thm::pad) and Sec. 4.2 (Thm thm::Fcheb, with Thm thm::Che), and a cost
+// model for this GPU in place of eq. optimiz's CPU cost ratio.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace sog {
+
+namespace {
+
+struct Row {
+    double b, r0, omega, eE;
+    int ME;
+    double eF;
+    int MF;
+};
+// Table 1 (tabl:parameter).
+const Row kTable1[6] = {
+    {2.0, 1.9892536839080267, 0.9944464927622323, 3.12e-2, 16, 9.93e-3, 11},
+    {1.62976708826776469, 2.7520026668023417, 1.0078069793438068, 2.33e-3, 31, 6.21e-4, 16},
+    {1.48783512395703226, 3.7554672283554990, 0.9919117057598183, 2.29e-4, 46, 7.98e-5, 26},
+    {1.32070036405934420, 4.3914554711638349, 1.0018891411481198, 1.18e-6, 76, 5.76e-7, 41},
+    {1.21812525709410644, 5.6355288151271085, 1.0009014615603334, 7.14e-10, 166, 5.14e-10, 71},
+    {1.14878150173321925, 7.2956245490719404, 1.0000368348358225, 1.30e-15, 271, 1.98e-14, 116},
+};
+
+// GPU cost model, seconds per unit of work (calibrated with rocprofv3 on MI355X).
+constexpr double kCostNearPair = 1.5e-12;   // per neighbour pair within r_c
+constexpr double kCostWindowPt = 3.0e-13;   // per particle per window point, spread + gather
+constexpr double kCostFFTPt = 6.0e-12;      // per real grid point, forward + inverse 3D FFT chain
+constexpr double kCostLongDirect = 4.0e-13; // per particle per (half-plane mode x Chebyshev term)
+constexpr double kCostWindow2Pt = 3.0e-13;  // per particle per 2D window point per Chebyshev term
+constexpr double kCostFFT2Pt = 1.2e-11;     // per 2D grid point per Chebyshev term
+
+const double kPi = 3.14159265358979323846;
+
+bool is_smooth(int n) {
+    if (n <= 0) return false;
+    for (int p : {2, 3, 5, 7})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+// Exponent E of the Gaussian-window error exp(-E) for P_w points at spacing h for the
+// narrowest Gaussian s: the larger of erfc(sqrt(S)) ~ exp(-S) and the aliasing term
+// exp(-pi^2 mu (P_w-1)^2 / (4 s^2 S)), mu = s^2 - H^2/S (Thm thm::scal), balanced over S.
+// Returns E and the balancing S.
+double window_exponent(int Pw, double h, double s, double* S_out) {
+    double u = Pw - 1;
+    double a = kPi * kPi * u * u / 4.0;
+    double c = (u * h / 2.0) * (u * h / 2.0) / (s * s);  // H^2 / s^2
+    if (8.0 * c * c >= a) {
+        // the aliasing exponent a/S - a c/S^2 peaks below S: best S is its peak
+        if (S_out) *S_out = 2.0 * c;
+        return a / (4.0 * c);
+    }
+    double lo = 2.0 * c, hi = std::sqrt(a);  // root of S^3 - a S + a c in (2c, sqrt(a))
+    for (int it = 0; it < 100; ++it) {
+        double mid = 0.5 * (lo + hi);
+        double f = mid * mid * mid - a * mid + a * c;
+        if (f < 0) lo = mid; else hi = mid;
+    }
+    double S = 0.5 * (lo + hi);
+    if (S_out) *S_out = S;
+    return S;
+}
+
+int tile_edge(int prec, int Pw) {
+    // spread LDS: B^3 reals; gather LDS: (B + Pw - 1)^3 reals; both <= 64 KiB
+    int lim = (prec == SOG_PREC_FP64) ? 20 : 25;
+    int B = std::min(16, lim - (Pw - 1));
+    return std::max(B, 1);
+}
+
+struct MidChoice {
+    bool ok = false;
+    int I[3] = {0, 0, 0};
+    int Izs = 0, Pw = 0;
+    double S = 0, cost = 1e300;
+};
+
+MidChoice plan_mid(const double L[3], int64_t n, double s0, double sm, double eps, int prec,
+                   const sog_params& ov) {
+    MidChoice best;
+    const double eps_t = eps, eps_w = eps, eps_p = eps;
+    double hmax = kPi * s0 / (2.0 * std::sqrt(std::log(0.1 / eps_t)));
+    const double fr[] = {1.0, 0.92, 0.85, 0.78, 0.7, 0.62, 0.55, 0.48};
+    for (double f : fr) {
+        MidChoice c;
+        double h = f * hmax;
+        for (int d = 0; d < 2; ++d) c.I[d] = next_smooth((int)std::ceil(L[d] / h - 1e-9), true);
+        c.I[2] = std::max(1, (int)std::ceil(L[2] / h - 1e-9));
+        if (ov.mid_I[0] > 0) for (int d = 0; d < 3; ++d) c.I[d] = ov.mid_I[d];
+        double hd[3] = {L[0] / c.I[0], L[1] / c.I[1], L[2] / c.I[2]};
+        double hw = std::max(hd[0], std::max(hd[1], hd[2]));
+        int Pw = 0;
+        double S = 0;
+        if (ov.mid_Pw[0] > 0) {
+            Pw = ov.mid_Pw[0];
+            window_exponent(Pw, hw, s0, &S);
+        } else {
+            for (int p = 5; p <= 31; p += 2) {
+                double Sp;
+                double E = window_exponent(p, hw, s0, &Sp);
+                if (std::exp(-E) <= eps_w) { Pw = p; S = Sp; break; }
+            }
+            if (Pw == 0) continue;
+        }
+        if (ov.mid_S > 0) S = ov.mid_S;
+        for (int d = 0; d < 2; ++d)
+            if (c.I[d] < 2 * Pw) c.I[d] = next_smooth(2 * Pw, true);
+        hd[0] = L[0] / c.I[0];
+        hd[1] = L[1] / c.I[1];
+        double Hz = 0.5 * (Pw - 1) * hd[2];
+        // padding (Thm thm::pad): the widest mid-range Gaussian must decay over the
+        // extension beyond the window's reach
+        double delta = sm * std::sqrt(std::log(1.0 / eps_p) / 2.0);
+        double Lzs = L[2] + 2.0 * Hz + delta;
+        int half = next_smooth((int)std::ceil(Lzs / hd[2] / 2.0 - 1e-9), false);
+        c.Izs = 2 * half;
+        while (c.Izs < c.I[2] + Pw + 2) c.Izs = 2 * next_smooth(c.Izs / 2 + 1, false);
+        if (ov.mid_Izs > 0) c.Izs = ov.mid_Izs;
+        c.Pw = Pw;
+        c.S = S;
+        double Ng = (double)c.I[0] * c.I[1] * c.Izs;
+        c.cost = kCostWindowPt * (double)n * Pw * Pw * Pw + kCostFFTPt * Ng;
+        c.ok = true;
+        if (c.cost < best.cost) best = c;
+        if (ov.mid_I[0] > 0) break;
+    }
+    (void)prec;
+    return best;
+}
+
+}  // namespace
+
+// Largest 2D tile edge B <= 16 for the long-range FFT form whose LDS use fits 64 KiB:
+// spread B^2 P + 128 P reals, gather (B + P_w - 1)^2 P + 64 (2 P) reals.  0 if none.
+int long_fft_tile(int prec, int Pw2, int P) {
+    const size_t rs = (prec == SOG_PREC_FP64) ? 8 : 4;
+    for (int B = 16; B >= 1; --B) {
+        size_t spread = ((size_t)B * B * P + 128 * (size_t)P) * rs;
+        size_t gather = ((size_t)(B + Pw2 - 1) * (B + Pw2 - 1) * P + 64 * 2 * (size_t)P) * rs;
+        if (spread <= 65536 && gather <= 65536) return B;
+    }
+    return 0;
+}
+
+namespace {
+
+struct LongChoice {
+    bool ok = false;
+    int form = SOG_LONG_DIRECT, P = 0, nk[2] = {0, 0}, I2[2] = {0, 0}, Pw2 = 0;
+    double S2 = 0, cost = 1e300;
+};
+
+LongChoice plan_long(const double L[3], int64_t n, double sl, double eps, int prec, const sog_params& ov) {
+    LongChoice best;
+    double eta = sl / L[2];
+    int P = ov.long_P;
+    if (P <= 0) {
+        // Thm thm::Che with the constants its proof drops (2 x 1.0865), doubled for
+        // interpolation in both the source and the target z
+        for (P = 2; P <= 64; ++P) {
+            double lg = 0.5 * std::lgamma(P + 1.0) + P * std::log(2.0 * std::sqrt(2.0) * eta);
+            if (std::log(4.0 * 1.0865) - lg <= std::log(eps)) break;
+        }
+        if (P > 64) return best;  // not reachable with this split
+    }
+    // direct form (App. B): |k| <= 2 sqrt(log(1/eps)) / s_{m+1} (Thm thm::Fcheb)
+    LongChoice d;
+    d.form = SOG_LONG_DIRECT;
+    d.P = P;
+    double K = 2.0 * std::sqrt(std::log(1.0 / eps)) / sl;
+    for (int a = 0; a < 2; ++a) d.nk[a] = (int)std::floor(K * L[a] / (2.0 * kPi));
+    if (ov.long_nk[0] > 0 || ov.long_nk[1] > 0) { d.nk[0] = ov.long_nk[0]; d.nk[1] = ov.long_nk[1]; }
+    double nh = (d.nk[0] + 1.0) + d.nk[1] * (2.0 * d.nk[0] + 1.0);
+    d.cost = kCostLongDirect * (double)n * nh * P;
+    d.ok = true;
+    // FFT form (Alg. al::long): 2D window + grid, same error rules as the mid range
+    LongChoice f;
+    f.form = SOG_LONG_FFT;
+    f.P = P;
+    double hmax = kPi * sl / (2.0 * std::sqrt(std::log(0.1 / eps)));
+    for (int a = 0; a < 2; ++a) f.I2[a] = next_smooth((int)std::ceil(L[a] / hmax - 1e-9), true);
+    if (ov.long_I[0] > 0) { f.I2[0] = ov.long_I[0]; f.I2[1] = ov.long_I[1]; }
+    double hw = std::max(L[0] / f.I2[0], L[1] / f.I2[1]);
+    f.Pw2 = 0;
+    if (ov.long_Pw[0] > 0) {
+        f.Pw2 = ov.long_Pw[0];
+        window_exponent(f.Pw2, hw, sl, &f.S2);
+    } else {
+        for (int p = 5; p <= 31; p += 2) {
+            double Sp;
+            if (std::exp(-window_exponent(p, hw, sl, &Sp)) <= eps) { f.Pw2 = p; f.S2 = Sp; break; }
+        }
+    }
+    if (ov.long_S > 0) f.S2 = ov.long_S;
+    if (f.Pw2 > 0 && f.Pw2 <= 15 && long_fft_tile(prec, f.Pw2, P) > 0) {
+        for (int a = 0; a < 2; ++a)
+            if (f.I2[a] < 2 * f.Pw2) f.I2[a] = next_smooth(2 * f.Pw2, true);
+        f.cost = kCostWindow2Pt * (double)n * f.Pw2 * f.Pw2 * P + kCostFFT2Pt * P * (double)f.I2[0] * f.I2[1];
+        f.ok = true;
+    }
+    if (ov.long_form == SOG_LONG_DIRECT) return d;
+    if (ov.long_form == SOG_LONG_FFT) return f;
+    best = (f.ok && f.cost < d.cost) ? f : d;
+    return best;
+}
+
+void sog_weights(double b, double sigma, double omega, int M, std::vector<double>& w, std::vector<double>& s) {
+    // Sec. 2.2: w_l = (pi/2)^{-1/2} b^{-l} log(b) / sigma, w_0 scaled by omega, s_l = sqrt(2) b^l sigma
+    w.resize(M + 1);
+    s.resize(M + 1);
+    for (int l = 0; l <= M; ++l) {
+        w[l] = std::sqrt(2.0 / kPi) * std::log(b) / sigma * std::pow(b, -(double)l);
+        s[l] = std::sqrt(2.0) * std::pow(b, (double)l) * sigma;
+    }
+    w[0] *= omega;
+}
+
+}  // namespace
+
+int next_smooth(int n, bool even) {
+    if (n < 1) n = 1;
+    for (int m = n;; ++m) {
+        if (even && (m % 2)) continue;
+        if (is_smooth(m)) return m;
+    }
+}
+
+bool factor_fft(int n, FFTFactors& f) {
+    f.n = n;
+    f.nstages = 0;
+    int m = n;
+    while (m % 4 == 0) { if (f.nstages >= kMaxStages) return false; f.radix[f.nstages++] = 4; m /= 4; }
+    for (int p : {2, 3, 5, 7})
+        while (m % p == 0) { if (f.nstages >= kMaxStages) return false; f.radix[f.nstages++] = p; m /= p; }
+    return m == 1;
+}
+
+// C[c][n] = (2 - delta_{n0}) / P * T_n(t_c): L_c(t) = sum_n C[c][n] T_n(t) (App. A.2, V^{-1}).
+void cheb_V_inverse(int P, double* C) {
+    std::vector<double> T(P);
+    for (int c = 0; c < P; ++c) {
+        double tc = std::cos((c + 0.5) * kPi / P);
+        T[0] = 1.0;
+        if (P > 1) T[1] = tc;
+        for (int k = 2; k < P; ++k) T[k] = 2.0 * tc * T[k - 1] - T[k - 2];
+        for (int k = 0; k < P; ++k) C[c * P + k] = (k == 0 ? 1.0 : 2.0) / P * T[k];
+    }
+}
+
+// Long-range kernel K(k; c, c') = pi sum_{l>m} w_l s_l^2 e^{-s_l^2 k^2/4} e^{-(z_c - z_c')^2/s_l^2}
+// (from eq. trun2; the k = 0 constant, which multiplies sum_j q_j = 0, is dropped via
+// expm1), moved to the Chebyshev coefficient basis: Kt = C^T K C.  out: nk x P x P.
+void long_kernel_cheb_basis(const Resolved& r, const double* k2, int nk, double* out) {
+    const int P = r.P;
+    std::vector<double> C(P * P), K(P * P), T(P * P), zc(P);
+    cheb_V_inverse(P, C.data());
+    for (int c = 0; c < P; ++c) zc[c] = 0.5 * r.L[2] * std::cos((c + 0.5) * kPi / P);
+    for (int ik = 0; ik < nk; ++ik) {
+        std::fill(K.begin(), K.end(), 0.0);
+        for (int l = r.m + 1; l <= r.M; ++l) {
+            double s2 = r.s[l] * r.s[l];
+            double coef = kPi * r.w[l] * s2;
+            if (k2[ik] == 0.0) {
+                for (int c = 0; c < P; ++c)
+                    for (int e = 0; e < P; ++e) {
+                        double dz = zc[c] - zc[e];
+                        K[c * P + e] += coef * std::expm1(-dz * dz / s2);
+                    }
+            } else {
+                double ek = std::exp(-s2 * k2[ik] / 4.0);
+                if (ek == 0.0) continue;
+                for (int c = 0; c < P; ++c)
+                    for (int e = 0; e < P; ++e) {
+                        double dz = zc[c] - zc[e];
+                        K[c * P + e] += coef * ek * std::exp(-dz * dz / s2);
+                    }
+            }
+        }
+        // T = K C, out = C^T T
+        for (int c = 0; c < P; ++c)
+            for (int nn = 0; nn < P; ++nn) {
+                double acc = 0;
+                for (int e = 0; e < P; ++e) acc += K[c * P + e] * C[e * P + nn];
+                T[c * P + nn] = acc;
+            }
+        double* o = out + (size_t)ik * P * P;
+        for (int a = 0; a < P; ++a)
+            for (int nn = 0; nn < P; ++nn) {
+                double acc = 0;
+                for (int c = 0; c < P; ++c) acc += C[c * P + a] * T[c * P + nn];
+                o[a * P + nn] = acc;
+            }
+    }
+}
+
+// Chebyshev series of F(r) and F'(r)/r in x = 2 r^2 / r_c^2 - 1 on r in [0, r_c]
+// (the near-field kernel N(r) = 1/r - F(r) of eq. SOGDEcomp, made independent of M as
+// Remark rmk::sum asks; polynomial in r^2 is this library's choice).
+void near_chebyshev(Resolved& r) {
+    const int Np = kMaxNearDeg + 1;
+    std::vector<double> fF(Np), fG(Np), xs(Np);
+    for (int j = 0; j < Np; ++j) {
+        double x = std::cos(kPi * (j + 0.5) / Np);
+        xs[j] = x;
+        double rr2 = 0.5 * (x + 1.0) * r.rc * r.rc;
+        double F = 0, G = 0;
+        for (int l = 0; l <= r.M; ++l) {
+            double e = std::exp(-rr2 / (r.s[l] * r.s[l]));
+            F += r.w[l] * e;
+            G += -2.0 * r.w[l] / (r.s[l] * r.s[l]) * e;
+        }
+        fF[j] = F;
+        fG[j] = G;
+    }
+    double cmaxF = 0, cmaxG = 0;
+    for (int k = 0; k < Np; ++k) {
+        double aF = 0, aG = 0;
+        for (int j = 0; j < Np; ++j) {
+            double Tk = std::cos(k * kPi * (j + 0.5) / Np);
+            aF += fF[j] * Tk;
+            aG += fG[j] * Tk;
+        }
+        aF *= 2.0 / Np;
+        aG *= 2.0 / Np;
+        if (k == 0) { aF *= 0.5; aG *= 0.5; }
+        r.near_cF[k] = aF;
+        r.near_cG[k] = aG;
+        cmaxF = std::max(cmaxF, std::fabs(aF));
+        cmaxG = std::max(cmaxG, std::fabs(aG));
+    }
+    double thr = (r.prec == SOG_PREC_FP64) ? 1e-18 : 1e-10;
+    int deg = kMaxNearDeg;
+    while (deg > 1 && std::fabs(r.near_cF[deg]) < thr * cmaxF && std::fabs(r.near_cG[deg]) < thr * cmaxG) --deg;
+    r.near_deg = deg;
+    for (int k = deg + 1; k <= kMaxNearDeg; ++k) r.near_cF[k] = r.near_cG[k] = 0.0;
+}
+
+sog_status resolve(const double box[3], int64_t n, double tol, const sog_options& opt, Resolved& r,
+                   std::string& err) {
+    const sog_params& ov = opt.params;
+    for (int d = 0; d < 3; ++d) {
+        if (!(box[d] > 0) || !std::isfinite(box[d])) { err = "box lengths must be finite and > 0"; return SOG_ERR_INVALID_ARG; }
+        r.L[d] = box[d];
+    }
+    if (n <= 1 || n > (int64_t)1 << 30) { err = "n must be in [2, 2^30]"; return SOG_ERR_INVALID_ARG; }
+    r.n = n;
+    r.prec = opt.precision;
+    if (r.prec != SOG_PREC_FP64 && r.prec != SOG_PREC_FP32_BULK) { err = "unknown precision"; return SOG_ERR_INVALID_ARG; }
+    double tmin = (r.prec == SOG_PREC_FP64) ? 1e-12 : 1e-5;
+    if (!(tol >= tmin && tol <= 1e-2)) { err = "tol outside the reachable range for this precision"; return SOG_ERR_TOL_UNREACHABLE; }
+    r.tol = tol;
+    if (ov.mid_Pw[0] != ov.mid_Pw[1] || ov.mid_Pw[0] != ov.mid_Pw[2]) { err = "mid_Pw must be equal in x, y, z"; return SOG_ERR_INVALID_ARG; }
+    if (ov.mid_Pw[0] < 0 || (ov.mid_Pw[0] > 0 && (ov.mid_Pw[0] % 2 == 0 || ov.mid_Pw[0] < 3 || ov.mid_Pw[0] > 31))) { err = "mid_Pw must be odd in [3, 31]"; return SOG_ERR_INVALID_ARG; }
+    if (ov.long_Pw[0] != ov.long_Pw[1] || (ov.long_Pw[0] > 0 && (ov.long_Pw[0] % 2 == 0 || ov.long_Pw[0] < 3 || ov.long_Pw[0] > 31))) { err = "long_Pw must be odd in [3, 31] and equal in x, y"; return SOG_ERR_INVALID_ARG; }
+    if (ov.long_P < 0 || ov.long_P > 64) { err = "long_P must be in [1, 64]"; return SOG_ERR_INVALID_ARG; }
+    if (ov.mid_Izs % 2) { err = "mid_Izs must be even"; return SOG_ERR_INVALID_ARG; }
+
+    // decomposition parameters
+    bool custom = ov.b > 0 || ov.r0 > 0 || ov.omega > 0;
+    int ME = 0;
+    if (custom) {
+        if (!(ov.b > 1 && ov.r0 > std::sqrt(2.0) && ov.omega > 0)) { err = "b, r0, omega must be given together (b > 1, r0 > sqrt 2)"; return SOG_ERR_INVALID_ARG; }
+        r.b = ov.b; r.r0 = ov.r0; r.omega = ov.omega;
+    } else {
+        const Row* row = &kTable1[5];
+        for (const Row& t : kTable1)
+            if (t.eE <= 0.5 * tol && t.eF <= 0.5 * tol) { row = &t; break; }
+        r.b = row->b; r.r0 = row->r0; r.omega = row->omega; ME = row->ME;
+    }
+    const double V = r.L[0] * r.L[1] * r.L[2];
+    const double A = r.L[0] * r.L[1];
+    const double rho = (double)n / V;
+    const double rc_max = 0.5 * std::min(r.L[0], r.L[1]);
+    std::vector<double> rcs;
+    if (ov.rc > 0) {
+        if (ov.rc > rc_max * (1 + 1e-12)) { err = "rc must be <= min(Lx, Ly)/2 (Assumption ass:SOG)"; return SOG_ERR_INVALID_ARG; }
+        rcs.push_back(ov.rc);
+    } else {
+        for (double c : {2.0, 2.5, 3.0, 3.5, 4.0, 5.0}) rcs.push_back(std::min(c * std::cbrt(1.0 / rho), rc_max));
+    }
+    const double eps = tol / 20.0;
+    double best_cost = 1e300;
+    Resolved best = r;
+    bool found = false;
+    for (double rc : rcs) {
+        Resolved c = r;
+        c.rc = rc;
+        c.sigma = rc / c.r0;
+        // M: the omitted wide Gaussians leave -(pi/A) sum_{l>M} w_l sum_j q_j z_ij^2 in Phi;
+        // bound sum_j |q_j| z_ij^2 by n Lz^2 and keep it below 1e-2 eps
+        double wl1 = std::sqrt(2.0 / kPi) * std::log(c.b) / c.sigma;
+        double rhs = 1e-2 * eps * A / (kPi * (double)n * r.L[2] * r.L[2]) * (1.0 - 1.0 / c.b) / wl1;
+        int M = (int)std::ceil(-std::log(rhs) / std::log(c.b));
+        M = std::max(M, ME);
+        if (ov.M > 0) M = ov.M;
+        M = std::min(M, 4000);
+        c.M = M;
+        sog_weights(c.b, c.sigma, c.omega, M, c.w, c.s);
+        double near_cost = kCostNearPair * (double)n * (4.0 * kPi / 3.0) * rc * rc * rc * rho;
+        // candidate splits: m = -1 (all long) .. last l with s_l <= 2 Lz
+        int mlo = -1, mhi = -1;
+        for (int l = 0; l <= M; ++l)
+            if (c.s[l] <= 2.0 * r.L[2]) mhi = l;
+        mhi = std::min(mhi, std::min(M - 1, kMaxMid - 1));
+        if (ov.set_m) { mlo = mhi = ov.m; }
+        if (ov.set_m && (ov.m < -1 || ov.m > M || ov.m >= kMaxMid)) { err = "m out of range"; return SOG_ERR_INVALID_ARG; }
+        for (int m = mlo; m <= mhi; ++m) {
+            double cost = near_cost;
+            MidChoice mc;
+            LongChoice lc;
+            if (m >= 0) {
+                mc = plan_mid(r.L, n, c.s[0], c.s[m], eps, r.prec, ov);
+                if (!mc.ok) continue;
+                cost += mc.cost;
+            }
+            if (m < M) {
+                lc = plan_long(r.L, n, c.s[m + 1], eps, r.prec, ov);
+                if (!lc.ok) continue;
+                cost += lc.cost;
+            }
+            if (cost < best_cost) {
+                best_cost = cost;
+                best = c;
+                best.m = m;
+                best.has_mid = m >= 0;
+                best.has_long = m < M;
+                if (best.has_mid) {
+                    for (int d = 0; d < 3; ++d) best.I[d] = mc.I[d];
+                    best.Izs = mc.Izs;
+                    best.Pw = mc.Pw;
+                    best.S = mc.S;
+                }
+                if (best.has_long) {
+                    best.form = lc.form;
+                    best.P = lc.P;
+                    best.nk[0] = lc.nk[0]; best.nk[1] = lc.nk[1];
+                    best.I2[0] = lc.I2[0]; best.I2[1] = lc.I2[1];
+                    best.Pw2 = lc.Pw2;
+                    best.S2 = lc.S2;
+                }
+                found = true;
+            }
+        }
+    }
+    if (!found) { err = "no feasible discretisation for this box and tolerance"; return SOG_ERR_TOL_UNREACHABLE; }
+    r = best;
+    r.self_coeff = 0;
+    for (double v : r.w) r.self_coeff += v;
+
+    // near-field cells
+    for (int d = 0; d < 3; ++d) {
+        r.nc[d] = std::max(1, (int)std::floor(r.L[d] / r.rc));
+        r.ch[d] = r.L[d] / r.nc[d];
+    }
+    if ((int64_t)r.nc[0] * r.nc[1] * r.nc[2] > (int64_t)1 << 26) { err = "too many near-field cells"; return SOG_ERR_INVALID_ARG; }
+    near_chebyshev(r);
+
+    if (r.has_mid) {
+        if (r.I[0] < r.Pw || r.I[1] < r.Pw) { err = "mid grid smaller than the window"; return SOG_ERR_INVALID_ARG; }
+        if (r.Izs < r.I[2] + r.Pw + 2) { err = "mid_Izs too small for the window support"; return SOG_ERR_INVALID_ARG; }
+        for (int d = 0; d < 3; ++d) r.h[d] = r.L[d] / r.I[d];
+        r.Lzs = r.Izs * r.h[2];
+        for (int d = 0; d < 3; ++d) r.H[d] = 0.5 * (r.Pw - 1) * r.h[d];
+        int B = tile_edge(r.prec, r.Pw);
+        int gI[3] = {r.I[0], r.I[1], r.Izs};
+        r.max_dup = 1;
+        for (int d = 0; d < 3; ++d) {
+            r.B[d] = std::min(B, gI[d]);
+            r.ntile[d] = (gI[d] + r.B[d] - 1) / r.B[d];
+            // a run of P_w consecutive nodes meets at most ceil((P_w-1)/B) + 1 tiles, plus one
+            // more when it wraps past a partial last tile
+            int per = std::min(r.ntile[d], (r.Pw - 1 + r.B[d] - 1) / r.B[d] + 2);
+            if ((r.Pw + r.B[d] - 1) / r.B[d] + 1 > 8) { err = "window too wide for the tile"; return SOG_ERR_INVALID_ARG; }
+            r.max_dup *= per;
+        }
+        if (!is_smooth(r.I[0]) || !is_smooth(r.I[1]) || !is_smooth(r.Izs / 2)) { err = "mid grid sizes must have only factors 2, 3, 5, 7 (and I_z*/2 as well)"; return SOG_ERR_INVALID_ARG; }
+        if (r.I[0] % 2 || r.I[1] % 2) { err = "mid I_x, I_y must be even"; return SOG_ERR_INVALID_ARG; }
+        if (r.I[0] > 4096 || r.I[1] > 4096 || r.Izs > 8192) { err = "mid grid too large"; return SOG_ERR_INVALID_ARG; }
+    }
+    if (r.has_long) {
+        if (r.P < 1 || r.P > 64) { err = "long P out of range"; return SOG_ERR_INVALID_ARG; }
+        if (r.form == SOG_LONG_DIRECT) {
+            r.nh = (r.nk[0] + 1) + r.nk[1] * (2 * r.nk[0] + 1);
+            if ((int64_t)r.nh * r.P > 65536) { err = "too many long-range modes for the direct form"; return SOG_ERR_INVALID_ARG; }
+        } else {
+            if (r.Pw2 < 3 || r.I2[0] < r.Pw2 || r.I2[1] < r.Pw2) { err = "long-range FFT grid smaller than its window"; return SOG_ERR_INVALID_ARG; }
+            if (!is_smooth(r.I2[0]) || !is_smooth(r.I2[1])) { err = "long-range grid sizes must have only factors 2, 3, 5, 7"; return SOG_ERR_INVALID_ARG; }
+            for (int a = 0; a < 2; ++a) {
+                r.h2[a] = r.L[a] / r.I2[a];
+                r.H2[a] = 0.5 * (r.Pw2 - 1) * r.h2[a];
+            }
+            int B = long_fft_tile(r.prec, r.Pw2, r.P);
+            if (B == 0) { err = "long-range FFT form does not fit in LDS for this P and window"; return SOG_ERR_INVALID_ARG; }
+            r.max_dup2 = 1;
+            for (int a = 0; a < 2; ++a) {
+                r.B2[a] = std::min(B, r.I2[a]);
+                r.ntile2[a] = (r.I2[a] + r.B2[a] - 1) / r.B2[a];
+                if ((r.Pw2 + r.B2[a] - 1) / r.B2[a] + 1 > 8) { err = "long window too wide for the tile"; return SOG_ERR_INVALID_ARG; }
+                r.max_dup2 *= std::min(r.ntile2[a], (r.Pw2 - 1 + r.B2[a] - 1) / r.B2[a] + 2);
+            }
+        }
+    }
+    return SOG_OK;
+}
+
+}  // namespace sog

@@ -1,0 +1,66 @@
+"""Explicit parameter sets shared by the GPU parity tests: the same dict configures the
+HIP plan (sog_params overrides) and the oracle (oracle.fast.make_params).  Nothing here
+is computed by the HIP library."""
+import math
+
+TABLE1_ROWS = {
+    3: (1.32070036405934420, 4.3914554711638349, 1.0018891411481198),
+    4: (1.21812525709410644, 5.6355288151271085, 1.0009014615603334),
+}
+
+# name: N, box, seed, decomposition row, r_c, M, m, mid (I, I_z*, P_w), long
+CASES = {
+    # the Sec. 5.1 box; several 16^3 tiles, mid + direct long range
+    "cube_small": dict(N=1000, box=(20.0, 20.0, 20.0), seed=1, row=3, rc=4.0, M=100, m=6,
+                       mid=dict(I=(32, 32, 32), Izs=80, Pw=9), long=dict(form="direct", P=12, nk=(4, 4))),
+    # non-cubic box, grid sizes that are not multiples of the tile (ragged tiles), P_w = 7
+    "ragged": dict(N=2000, box=(13.0, 17.0, 9.0), seed=7, row=3, rc=3.0, M=120, m=5,
+                   mid=dict(I=(30, 40, 24), Izs=64, Pw=7), long=dict(form="direct", P=10, nk=(3, 4))),
+    # flat slab, every Gaussian long range (Remark after the range-splitting definition),
+    # Fourier-Chebyshev solver with 2D FFTs
+    "slab_all_long_fft": dict(N=1500, box=(24.0, 20.0, 4.0), seed=8, row=3, rc=2.5, M=120, m=-1,
+                              mid=None, long=dict(form="fft", P=24, I=(72, 60), Pw=9)),
+    # mid range plus the FFT form of the long range
+    "slab_mid_fft": dict(N=2400, box=(30.0, 30.0, 6.0), seed=12, row=3, rc=3.0, M=120, m=3,
+                         mid=dict(I=(50, 50, 10), Izs=40, Pw=9), long=dict(form="fft", P=14, I=(40, 40), Pw=9)),
+    # tall cell: long z lines in the FFT, many Chebyshev terms
+    "tall": dict(N=1200, box=(10.0, 10.0, 60.0), seed=13, row=3, rc=3.0, M=140, m=8,
+                 mid=dict(I=(20, 20, 120), Izs=252, Pw=9), long=dict(form="direct", P=20, nk=(1, 1))),
+    # window 13 and odd-radix FFT lengths (3, 5, 7)
+    "radix_mix": dict(N=900, box=(21.0, 15.0, 10.0), seed=14, row=4, rc=3.5, M=200, m=5,
+                      mid=dict(I=(42, 30, 20), Izs=70, Pw=13), long=dict(form="direct", P=14, nk=(3, 2))),
+}
+
+
+def _window_S(Pw):
+    # the shape used with a P_w-point Gaussian window in the paper's experiments (Sec. 5.1)
+    return 0.455 * math.pi * Pw
+
+
+def gpu_params(c):
+    b, r0, om = TABLE1_ROWS[c["row"]]
+    p = dict(b=b, r0=r0, omega=om, rc=c["rc"], M=c["M"], m=c["m"], set_m=1)
+    if c["mid"]:
+        p.update(mid_I=list(c["mid"]["I"]), mid_Izs=c["mid"]["Izs"], mid_Pw=[c["mid"]["Pw"]] * 3,
+                 mid_S=_window_S(c["mid"]["Pw"]))
+    lp = c["long"]
+    if lp:
+        p.update(long_form=lp["form"], long_P=lp["P"])
+        if lp["form"] == "direct":
+            p.update(long_nk=list(lp["nk"]))
+        else:
+            p.update(long_I=list(lp["I"]), long_Pw=[lp["Pw"]] * 2, long_S=_window_S(lp["Pw"]))
+    return p
+
+
+def oracle_params(c):
+    from oracle import fast
+    b, r0, om = TABLE1_ROWS[c["row"]]
+    mid = None
+    if c["mid"]:
+        Pw = c["mid"]["Pw"]
+        mid = dict(I=tuple(c["mid"]["I"]), Izs=c["mid"]["Izs"], Pw=(Pw, Pw, Pw), S=_window_S(Pw))
+    lp = dict(c["long"]) if c["long"] else None
+    if lp and lp["form"] == "fft":
+        lp = dict(form="fft", P=lp["P"], I=tuple(lp["I"]), Pw=(lp["Pw"], lp["Pw"]), S=_window_S(lp["Pw"]))
+    return fast.make_params(b, r0, om, c["rc"], c["M"], c["m"], mid=mid, long=lp)
