@@ -1,0 +1,237 @@
+#!/usr/bin/env python
+"""Benchmark of the MI355X SOG solver: particles/s for one energy + potential + force
+evaluation at 1e-4 relative tolerance, N = 10^6 (uniform, 100^3 box), FP32-bulk form
+and plain FP64 form, inputs resident in HBM.
+
+Prints ONE JSON line.  Timed region: K calls of sog_energy_potential_force with device
+pointers, bracketed by torch.cuda.synchronize().  Per-kernel device times come from the
+library's HIP events, recorded on the plan's stream (torch's current stream) during
+the same timed calls; the roofline entry uses them for the dominant kernel.
+
+Only this benchmark's cpu_baseline leg runs the CPU oracle (on a bounded sample).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"hbm_GBs": 8000.0, "fp32_TFs": 157.3, "fp64_TFs": 78.6}
+METRIC = "particles/s energy+forces at 1e-4 rel err, N=1e6; FP32-bulk vs FP64 plain"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_models(info, sizes, N, box, prec_bytes):
+    """Algorithmic work per launch (flops, bytes) of the main kernels; see the design doc."""
+    Pw = info["mid_Pw"][0]
+    Ng = sizes["mid_grid_points"]
+    rc = info["rc"]
+    rho = N / (box[0] * box[1] * box[2])
+    rs = prec_bytes
+    pairs = N * (4.0 * math.pi / 3.0) * rc ** 3 * rho
+    m = {}
+    # near: per pair ~ 2 Clenshaw series of degree ~15 (4 flops per degree) + 15
+    m["near"] = dict(flops=pairs * (4 * 15 + 15), bytes=N * (4 * rs + 4 * rs), bound="alu")
+    # spread: per particle P_w^3 multiply-adds into the tile; grid written once
+    m["mid_spread"] = dict(flops=N * (2 * Pw ** 3 + 2 * Pw ** 2), bytes=N * (16 + 4 * rs) + Ng * rs, bound="alu")
+    # gather: per particle 2 P_w^3 FMAs (value and z derivative) + 3 P_w^2; grid read once
+    m["mid_gather"] = dict(flops=N * (4 * Pw ** 3 + 6 * Pw ** 2), bytes=N * (16 + 4 * rs + 4 * rs) + Ng * rs,
+                           bound="alu")
+    Kz = info["mid_Izs"] // 2 + 1
+    cg = info["mid_I"][0] * info["mid_I"][1] * Kz * 2 * rs
+    m["fft_z_fwd"] = dict(flops=None, bytes=Ng * rs + cg, bound="hbm")
+    m["fft_z_inv"] = dict(flops=None, bytes=Ng * rs + cg, bound="hbm")
+    m["fft_y_fwd"] = dict(flops=None, bytes=2 * cg, bound="hbm")
+    m["fft_y_inv"] = dict(flops=None, bytes=2 * cg, bound="hbm")
+    m["fft_x_scale"] = dict(flops=None, bytes=2 * cg, bound="hbm")
+    return m
+
+
+def source_digest():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2412_04595_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they were
+    taken on the current sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    digest = source_digest()
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if len(f) >= 5 and f[0] == kernel and f[4] == digest:
+            return float(f[1]) * float(f[3]) + float(f[2]) * float(f[3])
+    return None
+
+
+def accuracy(workload, phi, F, q):
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_targets.txt")
+    if not os.path.exists(path):
+        return None
+    d = np.loadtxt(path, comments="#")
+    idx = d[:, 0].astype(np.int64)
+    rphi, rgrad = d[:, 1], d[:, 2:5]
+    rF = -q[idx, None] * rgrad
+    return dict(
+        n_targets=int(idx.size),
+        phi_rel_linf=float(np.max(np.abs(phi[idx] - rphi)) / np.max(np.abs(rphi))),
+        force_rel_linf=float(np.max(np.abs(F[idx] - rF)) / np.max(np.abs(rF))),
+        force_rel_rms=float(np.sqrt(np.mean(np.sum((F[idx] - rF) ** 2, 1)) / np.mean(np.sum(rF ** 2, 1)))),
+        reference="oracle SOG-direct (exact decomposition, b=1.2181), tests/golden",
+    )
+
+
+def cpu_baseline(tol):
+    """The oracle (plain NumPy fast SOG method) on a bounded sample of the workload:
+    N = 8000 uniform particles at the same density (box 20^3), same tolerance,
+    parameters from oracle.planner; single-threaded BLAS."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import fast, planner
+    import workloads
+    Ns, L = 8000, 20.0
+    box = (L, L, L)
+    x, q = workloads.uniform(Ns, box, 2)
+    p = planner.plan(box, Ns, tol)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        fast.solve(x, q, box, p)
+        t = time.perf_counter() - t0
+    return dict(value=Ns / t, unit="particles/s", cores=1, kind="oracle",
+                sample=f"oracle.fast.solve, N={Ns} uniform in {L:g}^3 (density 1 as the workload), tol {tol:g}, "
+                       f"oracle.planner parameters, 1 thread: {t:.1f} s")
+
+
+def run_form(sog, torch, xt, qt, box, N, tol, precision, steps, warmup):
+    s = sog.Solver(box, N, tol, precision=precision, on_device=True, check_inputs=False, timing=True)
+    # one checked call first: inputs valid, neutral, z in range
+    chk = sog.Solver(box, N, tol, precision=precision, on_device=True, check_inputs=True, timing=False)
+    chk(xt, qt)
+    chk.close()
+    for _ in range(warmup):
+        s(xt, qt)
+    torch.cuda.synchronize()
+    s.reset_kernel_times()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        U, phi, F = s(xt, qt)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    kt = s.kernel_times()
+    info, sizes = s.info(), s.sizes()
+    s.close()
+    return dict(dt=dt, U=U, phi=phi, F=F, kt=kt, info=info, sizes=sizes)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cube_1e6")
+    ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(the multi-GPU design is described in DESIGN.md but not built)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2412_04595_amd as sog
+    import workloads
+
+    x, q, box = workloads.named(args.workload)
+    N = len(q)
+    dev = torch.device("cuda:0")
+    xt = torch.from_numpy(x).to(dev)
+    qt = torch.from_numpy(q).to(dev)
+    torch.cuda.synchronize()
+    log(f"[bench] {args.workload} N={N} box={box} tol={args.tol}")
+    r32 = run_form(sog, torch, xt, qt, box, N, args.tol, "fp32", args.steps, args.warmup)
+    log(f"[bench] fp32-bulk {r32['dt'] * 1e3:.3f} ms/step")
+    r64 = None
+    if not args.no_fp64:
+        r64 = run_form(sog, torch, xt, qt, box, N, args.tol, "fp64", max(3, args.steps // 2), 1)
+        log(f"[bench] fp64 {r64['dt'] * 1e3:.3f} ms/step")
+    phi32 = r32["phi"].cpu().numpy()
+    F32 = r32["F"].cpu().numpy()
+    acc32 = accuracy(args.workload, phi32, F32, q)
+    acc64 = accuracy(args.workload, r64["phi"].cpu().numpy(), r64["F"].cpu().numpy(), q) if r64 else None
+
+    # roofline of the dominant kernel (FP32-bulk run)
+    kt = r32["kt"]
+    per_launch = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
+    per_step = {k: v[0] / args.steps for k, v in kt.items()}
+    dom = max(per_step, key=per_step.get)
+    models = kernel_models(r32["info"], r32["sizes"], N, box, 4)
+    roof = None
+    if dom in models:
+        mdl = models[dom]
+        t = per_launch[dom] * 1e-3
+        if mdl["bound"] == "hbm":
+            ach = mdl["bytes"] / t / 1e9
+            roof = dict(bound="hbm", achieved=ach, peak=PEAK["hbm_GBs"], unit="GB/s", frac=ach / PEAK["hbm_GBs"])
+        else:
+            ach = mdl["flops"] / t / 1e12
+            roof = dict(bound="alu", achieved=ach, peak=PEAK["fp32_TFs"], unit="TFLOP/s", frac=ach / PEAK["fp32_TFs"])
+        roof["kernel"] = dom
+        roof["kernel_ms"] = per_launch[dom]
+        roof["traffic"] = traffic_from_profiles(dom, args.workload)
+        roof["algorithmic_bytes"] = mdl["bytes"]
+        roof["hbm_frac_algorithmic"] = mdl["bytes"] / t / 1e9 / PEAK["hbm_GBs"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle on a bounded sample)")
+        cpu = cpu_baseline(args.tol)
+    value = N / r32["dt"]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["dt"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: N={N} uniform +/-1 neutral in {box[0]:g}x{box[1]:g}x{box[2]:g}, "
+                               f"seed {workloads.NAMED_SEED[args.workload]}, tol {args.tol:g}, FP32-bulk form",
+                   "N": N, "box": list(box), "tol": args.tol},
+        "fp64": None if r64 is None else {"value": N / r64["dt"], "ms_per_step": r64["dt"] * 1e3,
+                                         "accuracy": acc64},
+        "speedup_fp32_vs_fp64": None if r64 is None else r64["dt"] / r32["dt"],
+        "accuracy": acc32,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
+        "plan": {k: r32["info"][k] for k in ("rc", "M", "m", "mid_I", "mid_Izs", "mid_Pw", "long_form", "long_P",
+                                              "long_nk", "long_I", "long_Pw")},
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

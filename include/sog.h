@@ -112,7 +112,7 @@ typedef struct {
  * timing off, no overrides. */
 void sog_options_default(sog_options* opt);
 
-/* Plan for n particles in box (Lx, Ly, Lz) at relative tolerance tol with the default
+/* Plan for n particles (2 <= n <= 2^27) in box (Lx, Ly, Lz) at relative tolerance tol with the default
  * options.  tol is the target relative error of potentials, energy and forces. */
 sog_status sog_plan(const double box[3], int64_t n, double tol, sog_plan_t* out);
 

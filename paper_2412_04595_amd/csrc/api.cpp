@@ -120,7 +120,6 @@ sog_status build_plan(Plan& p) {
     int64_t maxbins = ncells;
     A.get(ws.cell_start, (ncells + 1) * 4);
     A.get(ws.cell_cursor, ncells * 4);
-    A.get(ws.near_cell, n * 4);
     A.get(ws.near_orig, n * 4);
     A.get(ws.near_pos, n * 4 * rs);
     if (r.has_mid) {
@@ -129,9 +128,6 @@ sog_status build_plan(Plan& p) {
         const int Kz = r.Izs / 2 + 1;
         A.get(ws.tile_start, (ntiles + 1) * 4);
         A.get(ws.tile_cursor, ntiles * 4);
-        A.get(ws.dup_start, (ntiles + 1) * 4);
-        A.get(ws.dup_cursor, ntiles * 4);
-        A.get(ws.dup_list, (size_t)n * r.max_dup * 4);
         A.get(ws.mid_g, n * 16);
         A.get(ws.mid_u, n * 4 * rs);
         A.get(ws.grid, (size_t)r.I[0] * r.I[1] * r.Izs * rs);
@@ -271,8 +267,8 @@ sog_status build_plan(Plan& p) {
 void free_plan(Plan& p) {
     Workspace& ws = p.ws;
     void* ptrs[] = {ws.x, ws.q, ws.phi, ws.force, ws.energy, ws.qsum, ws.status, ws.parts_phi, ws.parts_grad,
-                    ws.key, ws.perm, ws.scan_tmp, ws.cell_start, ws.cell_cursor, ws.near_cell, ws.near_orig,
-                    ws.near_pos, ws.tile_start, ws.tile_cursor, ws.dup_start, ws.dup_cursor, ws.dup_list, ws.mid_g,
+                    ws.key, ws.perm, ws.scan_tmp, ws.cell_start, ws.cell_cursor, ws.near_orig,
+                    ws.near_pos, ws.tile_start, ws.tile_cursor, ws.mid_g,
                     ws.mid_u, ws.grid, ws.cgrid, ws.tw_x, ws.tw_y, ws.tw_z, ws.tw_zpost, ws.mult_ax, ws.mult_ay,
                     ws.mult_az, ws.mult_c, ws.long_modes, ws.long_kt, ws.long_mu, ws.long_a, ws.l2_tile_start,
                     ws.l2_tile_cursor, ws.l2_dup_start, ws.l2_dup_cursor, ws.l2_dup_list, ws.l2_g, ws.l2_u,

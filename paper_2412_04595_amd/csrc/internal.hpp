@@ -39,6 +39,7 @@ struct Resolved {
     // near field: cells of side >= r_c; polynomials in x = 2 r^2/r_c^2 - 1
     int nc[3] = {1, 1, 1};
     double ch[3] = {0, 0, 0};
+    int near_zc = 1;  // cells per z-block (the near kernel's work unit)
     int near_deg = 0;
     double near_cF[kMaxNearDeg + 1] = {0};  // F(r)
     double near_cG[kMaxNearDeg + 1] = {0};  // F'(r)/r
@@ -54,7 +55,8 @@ struct Resolved {
     double Lzs = 0;
     int B[3] = {0, 0, 0};      // spread/gather tile
     int ntile[3] = {0, 0, 0};
-    int max_dup = 1;           // max tiles a particle's window touches
+    int ncolour[3] = {1, 1, 1};  // spread colours per direction (halo blocks of one colour are disjoint)
+    int atomic_flush = 0;        // 1 when the grid is too small to colour: halo blocks added atomically
 
     // long range (Sec. 3.3 / App. B)
     bool has_long = false;
@@ -99,15 +101,11 @@ struct Workspace {
     // near field
     int* cell_start = nullptr;  // ncells + 1
     int* cell_cursor = nullptr; // ncells
-    int* near_cell = nullptr;   // n, cell of each sorted particle
     int* near_orig = nullptr;   // n
-    void* near_pos = nullptr;   // n x real4 (cell-relative x, y, z, q)
+    void* near_pos = nullptr;   // n x real4 (x, y, z relative to the z-block corner; q)
     // mid range
     int* tile_start = nullptr;  // ntiles + 1 (owners)
     int* tile_cursor = nullptr; // ntiles
-    int* dup_start = nullptr;   // ntiles + 1 (every tile a window touches)
-    int* dup_cursor = nullptr;  // ntiles
-    int* dup_list = nullptr;    // n * max_dup
     int* mid_g = nullptr;       // n x int4 (grid point of each sorted particle, original index)
     void* mid_u = nullptr;      // n x real4 (offset from the grid point in units of h, q)
     void* grid = nullptr;       // I_x I_y I_z* reals

@@ -5,12 +5,12 @@
 // stored z-fastest: grid[(a * I_y + b) * I_z* + c].  Window on P_w nodes around the
 // nearest node, W(d) = exp(-S (d/H)^2) for |d| <= H = (P_w - 1) h / 2, else 0.
 //
-// Gridding is output-stationary: the grid is cut into tiles of B_x x B_y x B_z nodes; one
-// workgroup owns a tile, accumulates into it in LDS every particle whose window touches
-// it (lists built per call by a counting sort), and writes the tile once.  No global
-// atomics and no clearing pass: every node is written exactly once.
-// Gathering: one workgroup per tile loads the tile plus a (P_w - 1) halo into LDS and
-// evaluates Phi and grad Phi for the particles whose nearest node lies in the tile.
+// The grid is cut into tiles of B_x x B_y x B_z nodes and particles are sorted by the tile
+// of their nearest node (a counting sort).  Gridding: the workgroup of a tile spreads its
+// particles into an LDS copy of the tile plus a (P_w - 1) halo and adds that block into
+// the grid; tiles are coloured so that blocks added concurrently never overlap (no
+// global atomics).  Gathering: the workgroup of a tile loads the tile plus halo into LDS
+// and evaluates Phi and grad Phi for its particles.
 #include "device_common.hpp"
 
 namespace sog {
@@ -75,60 +75,6 @@ __global__ void k_mid_pack(const double* __restrict__ x, const double* __restric
     }
 }
 
-// distinct tiles touched along one direction by the window nodes a0-HW .. a0+HW
-__device__ __forceinline__ int touched(int a0, int HW, int I, int B, bool periodic, int* out) {
-    int cnt = 0;
-    for (int o = -HW; o <= HW; ++o) {
-        int gi = a0 + o;
-        if (periodic) gi = imod(gi, I);
-        else if (gi < 0 || gi >= I) continue;
-        int t = gi / B;
-        bool seen = false;
-        for (int k = 0; k < cnt; ++k) seen |= (out[k] == t);
-        if (!seen && cnt < 8) out[cnt++] = t;
-    }
-    return cnt;
-}
-
-__global__ void k_dup(const int4* __restrict__ gp, int n, MidGeom g, int* __restrict__ count, const int* __restrict__ start,
-                      int* __restrict__ cursor, int* __restrict__ list, int cap, int fill) {
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-        int4 a = gp[p];
-        int tx[8], ty[8], tz[8];
-        int nx = touched(a.x, g.HW, g.I[0], g.B[0], true, tx);
-        int ny = touched(a.y, g.HW, g.I[1], g.B[1], true, ty);
-        int nz = touched(a.z, g.HW, g.I[2], g.B[2], false, tz);
-        for (int i = 0; i < nx; ++i)
-            for (int j = 0; j < ny; ++j)
-                for (int k = 0; k < nz; ++k) {
-                    int t = (tx[i] * g.nt[1] + ty[j]) * g.nt[2] + tz[k];
-                    if (!fill) {
-                        atomicAdd(&count[t], 1);
-                    } else {
-                        int pos = start[t] + atomicAdd(&cursor[t], 1);
-                        if (pos < cap) list[pos] = p;
-                    }
-                }
-    }
-}
-
-template <typename real>
-struct SpreadArgs {
-    const int4* gp;
-    const vec4<real>* up;
-    const int* dstart;
-    const int* dlist;
-    int cap;  // entries in dlist
-    real* grid;
-    int I[3];
-    int B[3];
-    int nt[3];
-    int ntiles;
-    real S;
-    real inv_hw2;  // 1 / HW^2
-};
-
-// window weights on the P_w nodes: W((node - particle) h) with node - particle = o - HW - u
 template <typename real, int PW>
 __device__ __forceinline__ real win(int o, real u, real S, real inv_hw2) {
     constexpr int HW = (PW - 1) / 2;
@@ -137,66 +83,152 @@ __device__ __forceinline__ real win(int o, real u, real S, real inv_hw2) {
     return (r2 <= (real)1) ? dexp(-S * r2) : (real)0;
 }
 
-constexpr int kSpreadThreads = 128;
+constexpr int kSpreadThreads = 256;
+constexpr int kSpreadWaves = kSpreadThreads / 64;
+constexpr int kSpreadStage = 64;  // particles staged in LDS at a time
+constexpr int kFlushILP = 8;
 
+template <typename real>
+struct SpreadArgs {
+    const int4* gp;
+    const vec4<real>* up;
+    const int* tstart;  // owned particles of each tile (the gather's lists)
+    real* grid;
+    int I[3];
+    int B[3];
+    int nt[3];
+    int ntiles;
+    real S;
+    real inv_hw2;
+    // tiles of colour (cx, cy, cz): per direction, tiles t with t % 2 == c (and, when the
+    // tile count is odd, the last tile alone as colour 2); ncol[d] colours per direction
+    int col[3];
+    int ncol[3];
+    int nsel[3];   // selected tiles per direction for this colour
+    int atomic_flush;
+};
+
+__device__ __forceinline__ int colour_tile(int k, int c, int ncolours, int nt) {
+    // k-th tile of colour c along one direction
+    if (ncolours == 1) return k;
+    if (ncolours == 3 && c == 2) return nt - 1;
+    return 2 * k + c;
+}
+
+__host__ __device__ inline int colour_count(int c, int ncolours, int nt) {
+    if (ncolours == 1) return nt;
+    const int nreg = (ncolours == 3) ? nt - 1 : nt;  // tiles below the odd last one
+    if (c == 2) return 1;
+    return (nreg - c + 1) / 2;
+}
+
+// Owner-tile gridding: the workgroup of a tile spreads the particles whose nearest node
+// lies in the tile into an LDS copy of the tile plus a (P_w - 1) halo -- every window
+// fits, nothing is clipped -- and then adds that block into the global grid.  Tiles of
+// one colour have disjoint halo blocks, so the adds are plain read-modify-writes; the
+// colours run one launch after another.
+// Inside the tile no LDS atomics are used (float LDS atomics are slow on this GPU): the
+// window weights of a batch of particles are computed once into LDS, and the four waves
+// split the halo block by x plane (wave w owns the planes with x = w mod 4).  Each wave
+// walks every particle of the batch; its lanes take the window's (y, z) nodes, so the
+// lanes of one read-modify-write hit distinct addresses and no two waves touch the same
+// node.
 template <typename real, int PW>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    real* tile = reinterpret_cast<real*>(smem_raw);
-    const int T = a.B[0] * a.B[1] * a.B[2];
-    real* wts = tile + T;  // kSpreadThreads x 2 PW
-    const int t = xcd_logical_block(a.ntiles);
-    if (t < 0) return;
-    const int tz = t % a.nt[2], ty = (t / a.nt[2]) % a.nt[1], tx = t / (a.nt[2] * a.nt[1]);
-    const int x0 = tx * a.B[0], y0 = ty * a.B[1], z0 = tz * a.B[2];
-    const int ex = min(a.B[0], a.I[0] - x0), ey = min(a.B[1], a.I[1] - y0), ez = min(a.B[2], a.I[2] - z0);
-    for (int k = threadIdx.x; k < T; k += blockDim.x) tile[k] = 0;
-    __syncthreads();
     constexpr int HW = (PW - 1) / 2;
-    real* myw = wts + threadIdx.x * 2 * PW;
-    const int beg = min(a.dstart[t], a.cap), end = min(a.dstart[t + 1], a.cap);
-    for (int e = beg + threadIdx.x; e < end; e += blockDim.x) {
-        const int p = a.dlist[e];
-        const int4 g = a.gp[p];
-        const vec4<real> u = a.up[p];
-        real wz[PW];
+    constexpr int NPASS = (PW * PW + 63) / 64;
+    const int nwork = a.nsel[0] * a.nsel[1] * a.nsel[2];
+    const int w = xcd_logical_block(nwork);
+    if (w < 0) return;
+    const int kz = w % a.nsel[2], ky = (w / a.nsel[2]) % a.nsel[1], kx = w / (a.nsel[2] * a.nsel[1]);
+    const int tx = colour_tile(kx, a.col[0], a.ncol[0], a.nt[0]);
+    const int ty = colour_tile(ky, a.col[1], a.ncol[1], a.nt[1]);
+    const int tz = colour_tile(kz, a.col[2], a.ncol[2], a.nt[2]);
+    const int t = (tx * a.nt[1] + ty) * a.nt[2] + tz;
+    const int beg = a.tstart[t], end = a.tstart[t + 1];
+    if (beg == end) return;
+    const int x0 = tx * a.B[0], y0 = ty * a.B[1], z0 = tz * a.B[2];
+    const int HX = a.B[0] + PW - 1, HY = a.B[1] + PW - 1, HZ = a.B[2] + PW - 1;
+    const int tot = HX * HY * HZ;
+    real* halo = reinterpret_cast<real*>(smem_raw);
+    real* wts = halo + tot;  // kSpreadStage x 3 x PW: q wx, wy, wz of each staged particle
+    const size_t stage_off = (((size_t)tot + (size_t)kSpreadStage * 3 * PW) * sizeof(real) + 15) & ~(size_t)15;
+    int4* sg = reinterpret_cast<int4*>(smem_raw + stage_off);
+    for (int k = threadIdx.x; k < tot; k += blockDim.x) halo[k] = 0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // this lane's (y, z) nodes of a window, relative to the window corner
+    int oyz[NPASS], oy[NPASS], oz[NPASS];
 #pragma unroll
-        for (int o = 0; o < PW; ++o) {
-            myw[o] = u.w * win<real, PW>(o, u.x, a.S, a.inv_hw2);
-            myw[PW + o] = win<real, PW>(o, u.y, a.S, a.inv_hw2);
-            wz[o] = win<real, PW>(o, u.z, a.S, a.inv_hw2);
+    for (int ps = 0; ps < NPASS; ++ps) {
+        const int k = lane + 64 * ps;
+        oy[ps] = k / PW;
+        oz[ps] = k % PW;
+        oyz[ps] = (k < PW * PW) ? oy[ps] * HZ + oz[ps] : -1;
+    }
+    for (int c0 = beg; c0 < end; c0 += kSpreadStage) {
+        const int cnt = min(kSpreadStage, end - c0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) sg[i] = a.gp[c0 + i];
+        for (int idx = threadIdx.x; idx < cnt * 3 * PW; idx += blockDim.x) {
+            const int i = idx / (3 * PW), r = idx - i * 3 * PW, d = r / PW, o = r - d * PW;
+            const vec4<real> u = a.up[c0 + i];
+            const real ud = (d == 0) ? u.x : ((d == 1) ? u.y : u.z);
+            const real wv = win<real, PW>(o, ud, a.S, a.inv_hw2);
+            wts[idx] = (d == 0) ? u.w * wv : wv;
         }
-        const int sx0 = g.x - HW, sy0 = g.y - HW, sz = g.z - HW;
-        const int zlo = max(sz, z0), zhi = min(sz + PW, z0 + ez);
-        if (zlo >= zhi) continue;
-        for (int ix = -1; ix <= 1; ++ix) {
-            const int sx = sx0 + ix * a.I[0];
-            const int xlo = max(sx, x0), xhi = min(sx + PW, x0 + ex);
-            if (xlo >= xhi) continue;
-            for (int iy = -1; iy <= 1; ++iy) {
-                const int sy = sy0 + iy * a.I[1];
-                const int ylo = max(sy, y0), yhi = min(sy + PW, y0 + ey);
-                if (ylo >= yhi) continue;
-                for (int gx = xlo; gx < xhi; ++gx) {
-                    const real wx = myw[gx - sx];
-                    for (int gy = ylo; gy < yhi; ++gy) {
-                        const real wxy = wx * myw[PW + gy - sy];
-                        real* row = tile + ((gx - x0) * a.B[1] + (gy - y0)) * a.B[2] - z0;
+        __syncthreads();
+        for (int i = 0; i < cnt; ++i) {
+            const int4 g = sg[i];
+            const real* wp = wts + i * 3 * PW;
+            const int lx0 = g.x - x0;
+            real wyz[NPASS];
 #pragma unroll
-                        for (int o = 0; o < PW; ++o) {
-                            const int gz = sz + o;
-                            if (gz >= zlo && gz < zhi) atomicAdd(row + gz, wxy * wz[o]);
-                        }
-                    }
-                }
+            for (int ps = 0; ps < NPASS; ++ps) wyz[ps] = (oyz[ps] >= 0) ? wp[PW + oy[ps]] * wp[2 * PW + oz[ps]] : (real)0;
+            real* corner = halo + (g.y - y0) * HZ + (g.z - z0);
+            for (int ox = imod(wave - lx0, kSpreadWaves); ox < PW; ox += kSpreadWaves) {
+                const real wxv = wp[ox];
+                real* plane = corner + (lx0 + ox) * HY * HZ;
+#pragma unroll
+                for (int ps = 0; ps < NPASS; ++ps)
+                    if (oyz[ps] >= 0) plane[oyz[ps]] += wxv * wyz[ps];
             }
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < T; k += blockDim.x) {
-        const int lz = k % a.B[2], ly = (k / a.B[2]) % a.B[1], lx = k / (a.B[2] * a.B[1]);
-        if (lx < ex && ly < ey && lz < ez)
-            a.grid[((size_t)(x0 + lx) * a.I[1] + (y0 + ly)) * a.I[2] + (z0 + lz)] = tile[k];
+    // add the block into the grid, kFlushILP independent read-modify-writes per thread in
+    // flight (only nodes some window reached are touched)
+    for (int k0 = threadIdx.x; k0 < tot; k0 += blockDim.x * kFlushILP) {
+        real v[kFlushILP], old[kFlushILP];
+        size_t at[kFlushILP];
+#pragma unroll
+        for (int j = 0; j < kFlushILP; ++j) {
+            const int k = k0 + j * blockDim.x;
+            v[j] = 0;
+            at[j] = 0;
+            if (k < tot) {
+                const int lz = k % HZ, ly = (k / HZ) % HY, lx = k / (HZ * HY);
+                const int gz = z0 - HW + lz;
+                if (gz >= 0 && gz < a.I[2]) {
+                    v[j] = halo[k];
+                    const int gx = imod(x0 - HW + lx, a.I[0]);
+                    const int gy = imod(y0 - HW + ly, a.I[1]);
+                    at[j] = ((size_t)gx * a.I[1] + gy) * a.I[2] + gz;
+                }
+            }
+        }
+        if (a.atomic_flush) {
+#pragma unroll
+            for (int j = 0; j < kFlushILP; ++j)
+                if (v[j] != (real)0) atomicAdd(a.grid + at[j], v[j]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kFlushILP; ++j)
+                old[j] = (v[j] != (real)0) ? a.grid[at[j]] : (real)0;
+#pragma unroll
+            for (int j = 0; j < kFlushILP; ++j)
+                if (v[j] != (real)0) a.grid[at[j]] = old[j] + v[j];
+        }
     }
 }
 
@@ -231,12 +263,27 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs<real> a) {
     const int x0 = tx * a.B[0], y0 = ty * a.B[1], z0 = tz * a.B[2];
     const int HX = a.B[0] + PW - 1, HY = a.B[1] + PW - 1, HZ = a.B[2] + PW - 1;
     const int tot = HX * HY * HZ;
-    for (int k = threadIdx.x; k < tot; k += blockDim.x) {
-        const int lz = k % HZ, ly = (k / HZ) % HY, lx = k / (HZ * HY);
-        const int gx = imod(x0 - HW + lx, a.I[0]);
-        const int gy = imod(y0 - HW + ly, a.I[1]);
-        const int gz = z0 - HW + lz;
-        halo[k] = (gz >= 0 && gz < a.I[2]) ? a.grid[((size_t)gx * a.I[1] + gy) * a.I[2] + gz] : (real)0;
+    for (int k0 = threadIdx.x; k0 < tot; k0 += blockDim.x * kFlushILP) {
+        real v[kFlushILP];
+#pragma unroll
+        for (int j = 0; j < kFlushILP; ++j) {
+            const int k = k0 + j * blockDim.x;
+            v[j] = 0;
+            if (k < tot) {
+                const int lz = k % HZ, ly = (k / HZ) % HY, lx = k / (HZ * HY);
+                const int gz = z0 - HW + lz;
+                if (gz >= 0 && gz < a.I[2]) {
+                    const int gx = imod(x0 - HW + lx, a.I[0]);
+                    const int gy = imod(y0 - HW + ly, a.I[1]);
+                    v[j] = a.grid[((size_t)gx * a.I[1] + gy) * a.I[2] + gz];
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kFlushILP; ++j) {
+            const int k = k0 + j * blockDim.x;
+            if (k < tot) halo[k] = v[j];
+        }
     }
     __syncthreads();
     for (int p = beg + threadIdx.x; p < end; p += blockDim.x) {
@@ -295,18 +342,31 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         SpreadArgs<real> a;
         a.gp = (const int4*)ws.mid_g;
         a.up = (const vec4<real>*)ws.mid_u;
-        a.dstart = ws.dup_start;
-        a.dlist = ws.dup_list;
-        a.cap = (int)std::min<int64_t>((int64_t)r.n * r.max_dup, INT32_MAX);
+        a.tstart = ws.tile_start;
         a.grid = (real*)ws.grid;
         a.I[0] = r.I[0]; a.I[1] = r.I[1]; a.I[2] = r.Izs;
-        for (int d = 0; d < 3; ++d) { a.B[d] = r.B[d]; a.nt[d] = r.ntile[d]; }
+        for (int d = 0; d < 3; ++d) { a.B[d] = r.B[d]; a.nt[d] = r.ntile[d]; a.ncol[d] = r.ncolour[d]; }
         a.ntiles = ntiles;
         a.S = S;
         a.inv_hw2 = inv_hw2;
-        size_t lds = ((size_t)r.B[0] * r.B[1] * r.B[2] + (size_t)kSpreadThreads * 2 * PW) * sizeof(real);
+        a.atomic_flush = r.atomic_flush;
+        size_t lds = ((((size_t)(r.B[0] + PW - 1) * (r.B[1] + PW - 1) * (r.B[2] + PW - 1) + (size_t)kSpreadStage * 3 * PW) *
+                           sizeof(real) + 15) & ~(size_t)15) +
+                     (size_t)kSpreadStage * sizeof(int4);
         if (lds > 65536) return hipErrorInvalidConfiguration;
-        k_spread<real, PW><<<xcd_grid(ntiles), kSpreadThreads, lds, p.stream>>>(a);
+        hipError_t e = launch_fill_bytes_zero(ws.grid, (size_t)r.I[0] * r.I[1] * r.Izs * sizeof(real), p.stream);
+        if (e != hipSuccess) return e;
+        for (int cx = 0; cx < r.ncolour[0]; ++cx)
+            for (int cy = 0; cy < r.ncolour[1]; ++cy)
+                for (int cz = 0; cz < r.ncolour[2]; ++cz) {
+                    a.col[0] = cx; a.col[1] = cy; a.col[2] = cz;
+                    a.nsel[0] = colour_count(cx, r.ncolour[0], r.ntile[0]);
+                    a.nsel[1] = colour_count(cy, r.ncolour[1], r.ntile[1]);
+                    a.nsel[2] = colour_count(cz, r.ncolour[2], r.ntile[2]);
+                    const int nwork = a.nsel[0] * a.nsel[1] * a.nsel[2];
+                    if (nwork <= 0) continue;
+                    k_spread<real, PW><<<xcd_grid(nwork), kSpreadThreads, lds, p.stream>>>(a);
+                }
     } else {
         GatherArgs<real> a;
         a.gp = (const int4*)ws.mid_g;
@@ -374,16 +434,6 @@ hipError_t run_mid_prepare(Plan& p, const double* x, const double* q) {
     hipError_t e = launch_counting_sort(p, ws.key, n, ntiles, ws.tile_start, ws.tile_cursor, ws.perm);
     if (e != hipSuccess) return e;
     k_mid_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.perm, (int4*)ws.mid_g, (vec4<real>*)ws.mid_u);
-    // window lists: count, scan, fill
-    e = launch_fill_int(ws.dup_start, 0, (int64_t)ntiles + 1, p.stream);
-    if (e != hipSuccess) return e;
-    e = launch_fill_int(ws.dup_cursor, 0, ntiles, p.stream);
-    if (e != hipSuccess) return e;
-    k_dup<<<blocks, 256, 0, p.stream>>>((const int4*)ws.mid_g, n, g, ws.dup_start, nullptr, nullptr, nullptr, 0, 0);
-    e = launch_exclusive_scan(p, ws.dup_start, ntiles + 1);
-    if (e != hipSuccess) return e;
-    k_dup<<<blocks, 256, 0, p.stream>>>((const int4*)ws.mid_g, n, g, nullptr, ws.dup_start, ws.dup_cursor, ws.dup_list,
-                                         (int)std::min<int64_t>((int64_t)n * r.max_dup, INT32_MAX), 1);
     return hipGetLastError();
 }
 

@@ -2,13 +2,19 @@
 // N(r) = 1/r - F(r) (eq. SOGDEcomp), over xy images only (z is free), with a cell list
 // of cells at least r_c wide (the paper's cell list, Sec. 2.2).
 //
-// F(r) and F'(r)/r are evaluated as Chebyshev series in x = 2 r^2/r_c^2 - 1 (Clenshaw),
-// so the cost per pair does not depend on the number of Gaussians M (Remark rmk::sum
-// asks for that; a polynomial in r^2 is this library's way of getting it).
+// F(r) and F'(r)/r are evaluated as Chebyshev series in x = 2 r^2/r_c^2 - 1 (fitted in
+// float64 at plan time), so the cost per pair does not depend on the number of
+// Gaussians M (Remark rmk::sum asks for that; a polynomial in r^2 is this library's way
+// of getting it).
 //
-// Coordinates enter the pair kernel as offsets from the particle's cell corner, formed
-// in float64, so the float32 form does not lose the ~1e-5 absolute precision that raw
-// float32 coordinates of a 100-wide box would.
+// Work unit: a z-block of zc consecutive cells of one (x, y) column (zc chosen so that a
+// block holds about one wave of targets).  Its candidate sources are the particles of 27
+// contiguous ranges of the cell-sorted array: for each of the 9 neighbouring columns, the
+// cell just below the block, the block's own cells and the cell just above.
+//
+// Coordinates enter the pair kernel as offsets from the corner of the particle's
+// z-block (x, y: its cell's corner), formed in float64, so the float32 form does not lose
+// the ~1e-5 absolute precision that raw float32 coordinates of a 100-wide box would.
 #include "device_common.hpp"
 
 namespace sog {
@@ -19,6 +25,7 @@ struct NearGeom {
     double L[3];
     double ch[3];
     int nc[3];
+    int zc;  // cells per z-block
 };
 
 __device__ __forceinline__ void cell_of(const NearGeom& g, double xw, double yw, double z, int c[3]) {
@@ -44,8 +51,7 @@ __global__ void k_near_key(const double* __restrict__ x, int n, NearGeom g, int*
 
 template <typename real>
 __global__ void k_near_pack(const double* __restrict__ x, const double* __restrict__ q, int n, NearGeom g,
-                            const int* __restrict__ perm, vec4<real>* __restrict__ pos, int* __restrict__ cell,
-                            int* __restrict__ orig) {
+                            const int* __restrict__ perm, vec4<real>* __restrict__ pos, int* __restrict__ orig) {
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
         int i = perm[p];
         double xw = wrap_periodic(x[3 * i], g.L[0]), yw = wrap_periodic(x[3 * i + 1], g.L[1]);
@@ -60,23 +66,23 @@ __global__ void k_near_pack(const double* __restrict__ x, const double* __restri
         vec4<real> v;
         v.x = (real)(xw - c[0] * g.ch[0]);
         v.y = (real)(yw - c[1] * g.ch[1]);
-        v.z = (real)(z - c[2] * g.ch[2]);
+        v.z = (real)(z - (c[2] / g.zc) * g.zc * g.ch[2]);
         v.w = (real)qq;
         pos[p] = v;
-        cell[p] = (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
         orig[p] = i;
     }
 }
 
 template <typename real>
 struct NearArgs {
-    const vec4<real>* pos;
-    const int* cell;
-    const int* orig;
-    const int* cell_start;
-    real* pphi;   // part 0 potentials (n)
-    real* pgrad;  // part 0 gradients (n x 3)
-    int n;
+    const vec4<real>* __restrict__ pos;
+    const int* __restrict__ orig;
+    const int* __restrict__ cell_start;
+    real* __restrict__ pphi;   // part 0 potentials (n)
+    real* __restrict__ pgrad;  // part 0 gradients (n x 3)
+    int nitems;                // work units: columns x z-blocks
+    int nbz;                   // z-blocks per column
+    int zc;                    // cells per z-block
     int nc[3];
     real ch[3];
     real rc2, inv_rc2;
@@ -85,64 +91,159 @@ struct NearArgs {
     real cG[kMaxNearDeg + 1];
 };
 
-// One thread per target, targets in cell order so a wave walks the same neighbour cells.
+constexpr int kNearWaves = 4;   // independent waves per block
+constexpr int kNearCap = 48;    // hit-list entries per lane
 template <typename real>
-__global__ __launch_bounds__(256) void k_near(NearArgs<real> a) {
-    const int nblk = (a.n + blockDim.x - 1) / blockDim.x;
-    const int lb = xcd_logical_block(nblk);
+constexpr int kNearBatch = sizeof(real) == 4 ? 8 : 4;  // candidates tested between checks of the list's room
+constexpr int kNearCodeShift = 27;  // hit entry: source index | (neighbour range << 27)
+
+template <typename real, int DEG>
+__device__ __forceinline__ void near_pair(const NearArgs<real>& a, real rx, real ry, real rz, real qj, real& phi,
+                                          real& gx, real& gy, real& gz) {
+    const real r2 = rx * rx + ry * ry + rz * rz;
+    // F(r) and F'(r)/r as Chebyshev series in xs = 2 r^2/r_c^2 - 1, one forward
+    // recurrence for both (coefficients above the fitted degree are zero)
+    const real xs = (real)2 * r2 * a.inv_rc2 - (real)1;
+    const real x2 = xs + xs;
+    real T0 = 1, T1 = xs;
+    real F = a.cF[0] + a.cF[1] * xs, G = a.cG[0] + a.cG[1] * xs;
+#pragma unroll
+    for (int k = 2; k <= DEG; ++k) {
+        const real T2 = x2 * T1 - T0;
+        F += a.cF[k] * T2;
+        G += a.cG[k] * T2;
+        T0 = T1;
+        T1 = T2;
+    }
+    const real ri = drsqrt(r2);
+    phi += qj * (ri - F);                       // N(r) = 1/r - F(r)
+    const real c = qj * (-ri * ri * ri - G);   // N'(r)/r
+    gx += c * rx;
+    gy += c * ry;
+    gz += c * rz;
+}
+
+// Each wave takes one z-block.  Its lanes hold up to 64 targets; the candidate sources
+// are walked in uniform order (so their loads are the same address in every lane), each
+// lane tests every candidate and appends the ones within r_c to its own hit list in LDS;
+// the lists are evaluated when one is nearly full and at the end, so the polynomial runs
+// only for pairs inside r_c (about 15% of the candidates) and the lanes' evaluation loops
+// have similar lengths.  A pair is the particle with itself exactly when r^2 == 0 (same
+// stored coordinates, zero shift); that pair is skipped.
+template <typename real, int DEG>
+__global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
+    __shared__ uint32_t hits_all[kNearWaves][kNearCap * 64];
+    __shared__ vec4<real> shift_all[kNearWaves][27];
+    // the candidates' addresses are the same in every lane: read them through the
+    // constant address space, which gives scalar loads (the array is not written here)
+    const __attribute__((address_space(4))) vec4<real>* cpos = (const __attribute__((address_space(4))) vec4<real>*)a.pos;
+    const int lb = xcd_logical_block((a.nitems + kNearWaves - 1) / kNearWaves);
     if (lb < 0) return;
-    const int p = lb * blockDim.x + threadIdx.x;
-    if (p >= a.n) return;
-    const vec4<real> me = a.pos[p];
-    const int cid = a.cell[p];
-    const int cz = cid % a.nc[2], cy = (cid / a.nc[2]) % a.nc[1], cx = cid / (a.nc[2] * a.nc[1]);
-    real phi = 0, gx = 0, gy = 0, gz = 0;
-    for (int dz = -1; dz <= 1; ++dz) {
-        const int zz = cz + dz;
-        if (zz < 0 || zz >= a.nc[2]) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-            const int yy = imod(cy + dy, a.nc[1]);
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int xx = imod(cx + dx, a.nc[0]);
-                const int nb = (xx * a.nc[1] + yy) * a.nc[2] + zz;
-                // geometric position of the neighbour cell's corner relative to ours
-                const real ox = dx * a.ch[0], oy = dy * a.ch[1], oz = dz * a.ch[2];
-                const bool same = (dx == 0 && dy == 0 && dz == 0);
-                const int b = a.cell_start[nb], e = a.cell_start[nb + 1];
-                for (int j = b; j < e; ++j) {
-                    const vec4<real> o = a.pos[j];
-                    const real rx = me.x - (o.x + ox), ry = me.y - (o.y + oy), rz = me.z - (o.z + oz);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int item = lb * kNearWaves + wv;
+    if (item >= a.nitems) return;  // no block-wide barrier below: waves are independent
+    uint32_t* hits = hits_all[wv];
+    vec4<real>* shift = shift_all[wv];
+    const int bz = item % a.nbz, col = item / a.nbz;
+    const int cy = col % a.nc[1], cx = col / a.nc[1];
+    const int z0 = bz * a.zc, z1 = min(z0 + a.zc, a.nc[2]);
+    const int tb = a.cell_start[col * a.nc[2] + z0], te = a.cell_start[col * a.nc[2] + z1];
+    if (tb == te) return;
+    // lane k < 27: neighbour range k = (dx, dy) column x {cell below, block, cell above}
+    int rs = 0, re = 0;
+    if (lane < 27) {
+        const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dzi = lane / 9;
+        const int ncol = imod(cx + dx, a.nc[0]) * a.nc[1] + imod(cy + dy, a.nc[1]);
+        int za = z0, zb = z1;
+        if (dzi == 0) { za = z0 - 1; zb = z0; }
+        if (dzi == 2) { za = z1; zb = z1 + 1; }
+        if (za >= 0 && zb <= a.nc[2]) {
+            rs = a.cell_start[ncol * a.nc[2] + za];
+            re = a.cell_start[ncol * a.nc[2] + zb];
+        }
+        shift[lane] = vec4<real>{(real)dx * a.ch[0], (real)dy * a.ch[1], (real)((dzi - 1) * a.zc) * a.ch[2], (real)0};
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int t0 = tb; t0 < te; t0 += 64) {
+        const int p = t0 + lane;
+        const bool act = p < te;
+        const vec4<real> me = act ? a.pos[p] : vec4<real>{(real)1e30, (real)1e30, (real)1e30, (real)0};
+        real phi = 0, gx = 0, gy = 0, gz = 0;
+        int cnt = 0;
+        // evaluate the hit list, four entries at a time with their loads issued first
+        auto flush = [&]() {
+            for (int h = 0; h < cnt; h += 4) {
+                vec4<real> o[4], sh[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t e = hits[min(h + u, cnt - 1) * 64 + lane];
+                    o[u] = a.pos[e & ((1u << kNearCodeShift) - 1)];
+                    sh[u] = shift[e >> kNearCodeShift];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (h + u < cnt)
+                        near_pair<real, DEG>(a, me.x - (o[u].x + sh[u].x), me.y - (o[u].y + sh[u].y),
+                                             me.z - (o[u].z + sh[u].z), o[u].w, phi, gx, gy, gz);
+            }
+            cnt = 0;
+        };
+        for (int k = 0; k < 27; ++k) {
+            const int js = __builtin_amdgcn_readlane(rs, k), je = __builtin_amdgcn_readlane(re, k);
+            if (js == je) continue;
+            const vec4<real> sh = shift[k];
+            const real mx = me.x - sh.x, my = me.y - sh.y, mz = me.z - sh.z;
+            const uint32_t code = (uint32_t)k << kNearCodeShift;
+            for (int j0 = js; j0 < je; j0 += kNearBatch<real>) {
+                if (__ballot(cnt > kNearCap - kNearBatch<real>)) flush();
+                // a batch of candidates; indices past the range re-read its last element
+                // and are masked out of the count
+                vec4<real> o[kNearBatch<real>];
+#pragma unroll
+                for (int u = 0; u < kNearBatch<real>; ++u) {
+                    const int jj = min(j0 + u, je - 1);
+                    o[u].x = cpos[jj].x;
+                    o[u].y = cpos[jj].y;
+                    o[u].z = cpos[jj].z;
+                }
+#pragma unroll
+                for (int u = 0; u < kNearBatch<real>; ++u) {
+                    const real rx = mx - o[u].x, ry = my - o[u].y, rz = mz - o[u].z;
                     const real r2 = rx * rx + ry * ry + rz * rz;
-                    if (r2 < a.rc2 && !(same && j == p)) {
-                        const real xs = (real)2 * r2 * a.inv_rc2 - (real)1;
-                        // Clenshaw for both series
-                        real bF1 = 0, bF2 = 0, bG1 = 0, bG2 = 0;
-                        for (int k = a.deg; k >= 1; --k) {
-                            const real tF = a.cF[k] + (real)2 * xs * bF1 - bF2;
-                            const real tG = a.cG[k] + (real)2 * xs * bG1 - bG2;
-                            bF2 = bF1; bF1 = tF;
-                            bG2 = bG1; bG1 = tG;
-                        }
-                        const real F = a.cF[0] + xs * bF1 - bF2;
-                        const real G = a.cG[0] + xs * bG1 - bG2;  // F'(r)/r
-                        const real ri = drsqrt(r2);
-                        const real N = ri - F;
-                        const real dNr = -ri * ri * ri - G;  // N'(r)/r
-                        phi += o.w * N;
-                        const real c = o.w * dNr;
-                        gx += c * rx;
-                        gy += c * ry;
-                        gz += c * rz;
-                    }
+                    hits[cnt * 64 + lane] = (uint32_t)(j0 + u) | code;
+                    cnt += (r2 < a.rc2 && r2 > (real)0 && j0 + u < je) ? 1 : 0;
                 }
             }
         }
+        flush();
+        if (act) {
+            const int i = a.orig[p];
+            a.pphi[i] = phi;
+            a.pgrad[3 * i] = gx;
+            a.pgrad[3 * i + 1] = gy;
+            a.pgrad[3 * i + 2] = gz;
+        }
     }
-    const int i = a.orig[p];
-    a.pphi[i] = phi;
-    a.pgrad[3 * i] = gx;
-    a.pgrad[3 * i + 1] = gy;
-    a.pgrad[3 * i + 2] = gz;
+}
+
+// polynomial degrees compiled; the fitted degree is rounded up to one of these
+template <typename real, int DEG>
+void launch_near_deg(const NearArgs<real>& a, hipStream_t st) {
+    k_near<real, DEG><<<xcd_grid((a.nitems + kNearWaves - 1) / kNearWaves), 64 * kNearWaves, 0, st>>>(a);
+}
+
+template <typename real>
+void launch_near_kernel(const NearArgs<real>& a, hipStream_t st) {
+    if (a.deg <= 8) launch_near_deg<real, 8>(a, st);
+    else if (a.deg <= 12) launch_near_deg<real, 12>(a, st);
+    else if (a.deg <= 16) launch_near_deg<real, 16>(a, st);
+    else if (a.deg <= 20) launch_near_deg<real, 20>(a, st);
+    else if (a.deg <= 24) launch_near_deg<real, 24>(a, st);
+    else if (a.deg <= 32) launch_near_deg<real, 32>(a, st);
+    else if (a.deg <= 48) launch_near_deg<real, 48>(a, st);
+    else launch_near_deg<real, kMaxNearDeg>(a, st);
 }
 
 template <typename real>
@@ -156,6 +257,7 @@ hipError_t run_near(Plan& p, const double* x, const double* q) {
         g.ch[d] = r.ch[d];
         g.nc[d] = r.nc[d];
     }
+    g.zc = r.near_zc;
     const int ncells = r.nc[0] * r.nc[1] * r.nc[2];
     int t = timer_id(p, "near_sort");
     timer_begin(p, t);
@@ -163,17 +265,17 @@ hipError_t run_near(Plan& p, const double* x, const double* q) {
     k_near_key<<<blocks, 256, 0, p.stream>>>(x, n, g, ws.key);
     hipError_t e = launch_counting_sort(p, ws.key, n, ncells, ws.cell_start, ws.cell_cursor, ws.perm);
     if (e != hipSuccess) return e;
-    k_near_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.perm, (vec4<real>*)ws.near_pos, ws.near_cell,
-                                                     ws.near_orig);
+    k_near_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.perm, (vec4<real>*)ws.near_pos, ws.near_orig);
     timer_end(p, t);
     NearArgs<real> a;
     a.pos = (const vec4<real>*)ws.near_pos;
-    a.cell = ws.near_cell;
     a.orig = ws.near_orig;
+    a.zc = r.near_zc;
+    a.nbz = (r.nc[2] + r.near_zc - 1) / r.near_zc;
+    a.nitems = r.nc[0] * r.nc[1] * a.nbz;
     a.cell_start = ws.cell_start;
     a.pphi = (real*)ws.parts_phi;
     a.pgrad = (real*)ws.parts_grad;
-    a.n = n;
     for (int d = 0; d < 3; ++d) {
         a.nc[d] = r.nc[d];
         a.ch[d] = (real)r.ch[d];
@@ -187,7 +289,7 @@ hipError_t run_near(Plan& p, const double* x, const double* q) {
     }
     t = timer_id(p, "near");
     timer_begin(p, t);
-    k_near<real><<<xcd_grid((n + 255) / 256), 256, 0, p.stream>>>(a);
+    launch_near_kernel<real>(a, p.stream);
     timer_end(p, t);
     return hipGetLastError();
 }

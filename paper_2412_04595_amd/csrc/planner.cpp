@@ -72,10 +72,16 @@ double window_exponent(int Pw, double h, double s, double* S_out) {
 }
 
 int tile_edge(int prec, int Pw) {
-    // spread LDS: B^3 reals; gather LDS: (B + Pw - 1)^3 reals; both <= 64 KiB
-    int lim = (prec == SOG_PREC_FP64) ? 20 : 25;
-    int B = std::min(16, lim - (Pw - 1));
-    return std::max(B, 1);
+    // LDS: (B + P_w - 1)^3 reals for the tile plus halo (gridding and gathering), plus the
+    // window weights of 64 staged particles (64 x 3 P_w reals) and their grid points
+    // (1 KiB) in gridding; <= 64 KiB in all
+    const size_t rs = (prec == SOG_PREC_FP64) ? 8 : 4;
+    for (int B = 16; B >= 1; --B) {
+        size_t e = (size_t)(B + Pw - 1);
+        size_t lds = ((e * e * e + 64 * 3 * (size_t)Pw) * rs + 15) / 16 * 16 + 64 * 16;
+        if (lds <= 65536) return B;
+    }
+    return 1;
 }
 
 struct MidChoice {
@@ -338,7 +344,7 @@ void near_chebyshev(Resolved& r) {
         cmaxF = std::max(cmaxF, std::fabs(aF));
         cmaxG = std::max(cmaxG, std::fabs(aG));
     }
-    double thr = (r.prec == SOG_PREC_FP64) ? 1e-18 : 1e-10;
+    double thr = (r.prec == SOG_PREC_FP64) ? 1e-14 : 2e-8;
     int deg = kMaxNearDeg;
     while (deg > 1 && std::fabs(r.near_cF[deg]) < thr * cmaxF && std::fabs(r.near_cG[deg]) < thr * cmaxG) --deg;
     r.near_deg = deg;
@@ -352,7 +358,7 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         if (!(box[d] > 0) || !std::isfinite(box[d])) { err = "box lengths must be finite and > 0"; return SOG_ERR_INVALID_ARG; }
         r.L[d] = box[d];
     }
-    if (n <= 1 || n > (int64_t)1 << 30) { err = "n must be in [2, 2^30]"; return SOG_ERR_INVALID_ARG; }
+    if (n <= 1 || n > (int64_t)1 << 27) { err = "n must be in [2, 2^27]"; return SOG_ERR_INVALID_ARG; }
     r.n = n;
     r.prec = opt.precision;
     if (r.prec != SOG_PREC_FP64 && r.prec != SOG_PREC_FP32_BULK) { err = "unknown precision"; return SOG_ERR_INVALID_ARG; }
@@ -463,6 +469,11 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         r.ch[d] = r.L[d] / r.nc[d];
     }
     if ((int64_t)r.nc[0] * r.nc[1] * r.nc[2] > (int64_t)1 << 26) { err = "too many near-field cells"; return SOG_ERR_INVALID_ARG; }
+    {
+        // about 56 targets per z-block: one wave of lanes, with room for fluctuations
+        const double per_cell = (double)n / ((double)r.nc[0] * r.nc[1] * r.nc[2]);
+        r.near_zc = std::max(1, std::min(r.nc[2], (int)std::floor(56.0 / std::max(per_cell, 1e-9))));
+    }
     near_chebyshev(r);
 
     if (r.has_mid) {
@@ -471,17 +482,29 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         for (int d = 0; d < 3; ++d) r.h[d] = r.L[d] / r.I[d];
         r.Lzs = r.Izs * r.h[2];
         for (int d = 0; d < 3; ++d) r.H[d] = 0.5 * (r.Pw - 1) * r.h[d];
+        // tiles: LDS holds (B + P_w - 1)^3 reals for both gridding and gathering; for the
+        // coloured gridding a periodic direction needs B >= P_w - 1 and either an odd tile
+        // count (3 colours, the last tile alone) or a last tile of at least P_w - 1 nodes
         int B = tile_edge(r.prec, r.Pw);
         int gI[3] = {r.I[0], r.I[1], r.Izs};
-        r.max_dup = 1;
+        r.atomic_flush = 0;
         for (int d = 0; d < 3; ++d) {
-            r.B[d] = std::min(B, gI[d]);
-            r.ntile[d] = (gI[d] + r.B[d] - 1) / r.B[d];
-            // a run of P_w consecutive nodes meets at most ceil((P_w-1)/B) + 1 tiles, plus one
-            // more when it wraps past a partial last tile
-            int per = std::min(r.ntile[d], (r.Pw - 1 + r.B[d] - 1) / r.B[d] + 2);
-            if ((r.Pw + r.B[d] - 1) / r.B[d] + 1 > 8) { err = "window too wide for the tile"; return SOG_ERR_INVALID_ARG; }
-            r.max_dup *= per;
+            int Bd = std::min(B, gI[d]);
+            int chosen = 0;
+            for (int b2 = Bd; b2 >= std::max(1, r.Pw - 1) && !chosen; --b2) {
+                int nt = (gI[d] + b2 - 1) / b2;
+                int rem = gI[d] - (nt - 1) * b2;
+                bool ok = (d == 2) ? nt >= 1 : ((nt >= 3 && nt % 2 == 1) || (nt >= 2 && nt % 2 == 0 && rem >= r.Pw - 1));
+                if (ok) chosen = b2;
+            }
+            if (!chosen) { chosen = Bd; r.atomic_flush = 1; }
+            r.B[d] = chosen;
+            r.ntile[d] = (gI[d] + chosen - 1) / chosen;
+        }
+        for (int d = 0; d < 3; ++d) {
+            if (r.atomic_flush) r.ncolour[d] = 1;
+            else if (d == 2) r.ncolour[d] = (r.ntile[2] >= 2) ? 2 : 1;
+            else r.ncolour[d] = (r.ntile[d] % 2) ? 3 : 2;
         }
         if (!is_smooth(r.I[0]) || !is_smooth(r.I[1]) || !is_smooth(r.Izs / 2)) { err = "mid grid sizes must have only factors 2, 3, 5, 7 (and I_z*/2 as well)"; return SOG_ERR_INVALID_ARG; }
         if (r.I[0] % 2 || r.I[1] % 2) { err = "mid I_x, I_y must be even"; return SOG_ERR_INVALID_ARG; }

@@ -1,0 +1,90 @@
+"""Write the sampled-target reference values for the full-size workloads.
+
+Calls only oracle/ (SOG-direct: the exact value of the SOG decomposition, pinned
+against Ewald2D in tests/test_oracle_pins.py) and the seeded generators in
+workloads/.  Decomposition: Table 1 row b = 1.2181 (printed errors 7e-10 / 5e-10),
+r_c = 3 rho^{-1/3}, M from the omitted-tail bound; the values are therefore the
+potentials and gradients of the quasi-2D Coulomb sum itself to ~1e-9 relative.
+
+Usage: python tests/golden/make_golden.py [name ...]   (default: every workload)
+Output: tests/golden/<name>_targets.txt
+"""
+import math
+import os
+import sys
+import time
+from multiprocessing import Pool
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle.direct import sog_direct  # noqa: E402
+from oracle.sog import SOG, TABLE1  # noqa: E402
+import workloads  # noqa: E402
+
+NTARGETS = 24
+ROW = 4  # b = 1.21812525709410644
+
+
+def decomposition(N, box):
+    Lx, Ly, Lz = box
+    b, r0, om = TABLE1[ROW][:3]
+    rho = N / (Lx * Ly * Lz)
+    rc = min(3.0 * rho ** (-1 / 3), 0.5 * min(Lx, Ly))
+    sigma = rc / r0
+    # omitted wide Gaussians leave (pi/A) sum_{l>M} w_l sum_j q_j z_ij^2; keep below 1e-13
+    wl1 = math.sqrt(2 / math.pi) * math.log(b) / sigma
+    rhs = 1e-13 * Lx * Ly / (math.pi * N * Lz * Lz) * (1 - 1 / b) / wl1
+    M = int(math.ceil(-math.log(rhs) / math.log(b)))
+    return b, r0, om, rc, M
+
+
+_CTX = {}
+
+
+def _init(name):
+    x, q, box = workloads.named(name)
+    b, r0, om, rc, M = decomposition(len(q), box)
+    _CTX.update(x=x, q=q, box=box, sog=SOG(b, r0, om, rc, M))
+
+
+def _one(i):
+    c = _CTX
+    o = sog_direct(c["x"], c["q"], c["box"], c["sog"], m=c["sog"].M, targets=np.array([i]))
+    return i, float(o["phi"][0]), o["grad"][0].tolist()
+
+
+def make(name, procs=8):
+    x, q, box = workloads.named(name)
+    N = len(q)
+    rng = np.random.default_rng(12345)
+    targets = np.sort(rng.choice(N, NTARGETS, replace=False))
+    b, r0, om, rc, M = decomposition(N, box)
+    t0 = time.time()
+    with Pool(procs, initializer=_init, initargs=(name,)) as pool:
+        rows = pool.map(_one, targets.tolist())
+    path = os.path.join(HERE, f"{name}_targets.txt")
+    with open(path, "w") as f:
+        f.write(f"# Reference potentials and gradients of sampled particles of workload {name}\n")
+        f.write(f"# (N={N}, box={box}, seed={workloads.NAMED_SEED[name]}), written by tests/golden/make_golden.py\n")
+        f.write("# with oracle.direct.sog_direct: exact SOG decomposition, Table 1 row\n")
+        f.write(f"# b={b!r} r0={r0!r} omega={om!r}, r_c={rc!r}, M={M}.\n")
+        f.write("# columns: index phi dphi/dx dphi/dy dphi/dz\n")
+        for i, phi, g in rows:
+            f.write(f"{i} {phi:.17g} {g[0]:.17g} {g[1]:.17g} {g[2]:.17g}\n")
+    print(f"{name}: {len(rows)} targets in {time.time() - t0:.0f} s -> {path}", flush=True)
+
+
+def load(name):
+    """(indices, phi, grad) from tests/golden/<name>_targets.txt"""
+    d = np.loadtxt(os.path.join(HERE, f"{name}_targets.txt"), comments="#")
+    return d[:, 0].astype(np.int64), d[:, 1], d[:, 2:5]
+
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or ["cube_1e6", "slab_1e6", "tall_1e6", "layered_2e5"]
+    for n in names:
+        make(n)
