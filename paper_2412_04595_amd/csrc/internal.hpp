@@ -15,6 +15,16 @@ namespace sog {
 constexpr int kMaxStages = 24;    // radix stages of one 1D FFT
 constexpr int kMaxNearDeg = 63;   // Chebyshev degree of the near-field polynomials
 constexpr int kMaxMid = 96;       // max number of mid-range Gaussians (m + 1)
+constexpr int kSpreadStage = 32;  // particles whose window weights the gridding kernel stages at a time
+
+// LDS bytes of the mid-range gridding kernel: the tile plus its (P_w - 1) halo, 64 sink
+// slots for masked lanes, and per staged particle its y and z window weights (2 P_w), its
+// x weights rotated for the four plane groups (16) and the four groups' plane offsets.
+inline size_t spread_lds_bytes(size_t real_bytes, int Pw, int Bx, int By, int Bz) {
+    const size_t tot = (size_t)(Bx + Pw - 1) * (By + Pw - 1) * (Bz + Pw - 1);
+    const size_t reals = tot + 64 + (size_t)kSpreadStage * (2 * Pw + 16);
+    return (reals * real_bytes + 15) / 16 * 16 + (size_t)kSpreadStage * 16;
+}
 
 // A 1D FFT of length n as a product of small radices (Stockham, natural order).
 struct FFTFactors {

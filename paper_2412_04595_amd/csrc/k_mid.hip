@@ -83,9 +83,7 @@ __device__ __forceinline__ real win(int o, real u, real S, real inv_hw2) {
     return (r2 <= (real)1) ? dexp(-S * r2) : (real)0;
 }
 
-constexpr int kSpreadThreads = 256;
-constexpr int kSpreadWaves = kSpreadThreads / 64;
-constexpr int kSpreadStage = 64;  // particles staged in LDS at a time
+constexpr int kSpreadThreads = 256;  // 4 waves, one per group of x planes
 constexpr int kFlushILP = 8;
 
 template <typename real>
@@ -127,17 +125,22 @@ __host__ __device__ inline int colour_count(int c, int ncolours, int nt) {
 // fits, nothing is clipped -- and then adds that block into the global grid.  Tiles of
 // one colour have disjoint halo blocks, so the adds are plain read-modify-writes; the
 // colours run one launch after another.
-// Inside the tile no LDS atomics are used (float LDS atomics are slow on this GPU): the
-// window weights of a batch of particles are computed once into LDS, and the four waves
-// split the halo block by x plane (wave w owns the planes with x = w mod 4).  Each wave
-// walks every particle of the batch; its lanes take the window's (y, z) nodes, so the
-// lanes of one read-modify-write hit distinct addresses and no two waves touch the same
-// node.
+// Inside the tile no LDS atomics are used (float LDS atomics are slow on this GPU): wave w
+// owns the x planes of the halo block with x = w mod 4 and its lanes take the window's
+// (y, z) nodes, so within a particle the lanes touch distinct nodes and no two waves ever
+// touch the same node; each wave walks the staged particles in order without
+// synchronising with the others.  Per staged particle the batch holds its y and z
+// weights, its x weights already rotated to each wave's planes and each wave's offset of
+// its first plane, so a wave's reads of the next particle do not depend on each other and
+// are issued before the current particle's writes.  Lanes with nothing to update read and
+// write a private sink slot instead of branching.
 template <typename real, int PW>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int HW = (PW - 1) / 2;
-    constexpr int NPASS = (PW * PW + 63) / 64;
+    constexpr int NPASS = (PW * PW + 63) / 64;   // groups of 64 (y, z) window nodes
+    constexpr int NPL = (PW + 3) / 4;            // x planes of a window per wave (at most)
+    static_assert(NPL <= 4, "window too wide for four plane groups");
     const int nwork = a.nsel[0] * a.nsel[1] * a.nsel[2];
     const int w = xcd_logical_block(nwork);
     if (w < 0) return;
@@ -150,72 +153,127 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
     if (beg == end) return;
     const int x0 = tx * a.B[0], y0 = ty * a.B[1], z0 = tz * a.B[2];
     const int HX = a.B[0] + PW - 1, HY = a.B[1] + PW - 1, HZ = a.B[2] + PW - 1;
-    const int tot = HX * HY * HZ;
+    const int HYZ = HY * HZ;
+    const int tot = HX * HYZ;
     real* halo = reinterpret_cast<real*>(smem_raw);
-    real* wts = halo + tot;  // kSpreadStage x 3 x PW: q wx, wy, wz of each staged particle
-    const size_t stage_off = (((size_t)tot + (size_t)kSpreadStage * 3 * PW) * sizeof(real) + 15) & ~(size_t)15;
-    int4* sg = reinterpret_cast<int4*>(smem_raw + stage_off);
-    for (int k = threadIdx.x; k < tot; k += blockDim.x) halo[k] = 0;
+    const int sink0 = tot;                         // 64 sink slots
+    real* wyzs = halo + tot + 64;                  // kSpreadStage x 2 PW: wy, wz
+    real* wxs = wyzs + kSpreadStage * 2 * PW;      // kSpreadStage x 16: q wx rotated per wave
+    const size_t meta_off = (((size_t)tot + 64 + (size_t)kSpreadStage * (2 * PW + 16)) * sizeof(real) + 15) & ~(size_t)15;
+    int4* meta = reinterpret_cast<int4*>(smem_raw + meta_off);  // per wave: first plane offset, plane count
+    for (int k = threadIdx.x; k < tot + 64; k += kSpreadThreads) halo[k] = 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // this lane's (y, z) nodes of a window, relative to the window corner
-    int oyz[NPASS], oy[NPASS], oz[NPASS];
+    int oyz[NPASS], oy2[NPASS], oz2[NPASS];
 #pragma unroll
     for (int ps = 0; ps < NPASS; ++ps) {
         const int k = lane + 64 * ps;
-        oy[ps] = k / PW;
-        oz[ps] = k % PW;
-        oyz[ps] = (k < PW * PW) ? oy[ps] * HZ + oz[ps] : -1;
+        const bool in = k < PW * PW;
+        oy2[ps] = in ? k / PW : 0;
+        oz2[ps] = in ? PW + k % PW : PW;
+        oyz[ps] = in ? (k / PW) * HZ + k % PW : -1;
     }
+    const int planestep = 4 * HYZ;
     for (int c0 = beg; c0 < end; c0 += kSpreadStage) {
         const int cnt = min(kSpreadStage, end - c0);
         __syncthreads();
-        for (int i = threadIdx.x; i < cnt; i += blockDim.x) sg[i] = a.gp[c0 + i];
-        for (int idx = threadIdx.x; idx < cnt * 3 * PW; idx += blockDim.x) {
-            const int i = idx / (3 * PW), r = idx - i * 3 * PW, d = r / PW, o = r - d * PW;
-            const vec4<real> u = a.up[c0 + i];
-            const real ud = (d == 0) ? u.x : ((d == 1) ? u.y : u.z);
-            const real wv = win<real, PW>(o, ud, a.S, a.inv_hw2);
-            wts[idx] = (d == 0) ? u.w * wv : wv;
+        // stage: y, z weights; per wave g the x weights of its planes (the planes with
+        // x = g mod 4) and the offset of its first plane, packed with the plane count
+        for (int idx = threadIdx.x; idx < cnt * (2 * PW + 16); idx += kSpreadThreads) {
+            if (idx < cnt * 2 * PW) {
+                const int i = idx / (2 * PW), r = idx - i * 2 * PW;
+                const vec4<real> u = a.up[c0 + i];
+                wyzs[idx] = win<real, PW>(r < PW ? r : r - PW, r < PW ? u.y : u.z, a.S, a.inv_hw2);
+            } else {
+                const int jdx = idx - cnt * 2 * PW;
+                const int i = jdx >> 4, g = (jdx >> 2) & 3, pl = jdx & 3;
+                const int4 gp = a.gp[c0 + i];
+                const vec4<real> u = a.up[c0 + i];
+                const int ox = ((g - (gp.x - x0)) & 3) + 4 * pl;
+                wxs[jdx] = (ox < PW) ? u.w * win<real, PW>(ox, u.x, a.S, a.inv_hw2) : (real)0;
+            }
+        }
+        for (int i = threadIdx.x; i < cnt; i += kSpreadThreads) {
+            const int4 gp = a.gp[c0 + i];
+            const int lx0 = gp.x - x0;
+            const int corner = lx0 * HYZ + (gp.y - y0) * HZ + (gp.z - z0);
+            int m[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int ox0 = (g - lx0) & 3;
+                m[g] = corner + ox0 * HYZ;
+                m[g] = (m[g] << 3) | ((PW - ox0 + 3) >> 2);  // planes of this wave: ceil((PW - ox0) / 4)
+            }
+            meta[i] = int4{m[0], m[1], m[2], m[3]};
         }
         __syncthreads();
-        for (int i = 0; i < cnt; ++i) {
-            const int4 g = sg[i];
-            const real* wp = wts + i * 3 * PW;
-            const int lx0 = g.x - x0;
-            real wyz[NPASS];
+        // software pipeline: the next particle's weights and offsets are read before this
+        // particle's writes (they are read-only here, so the order is free)
+        const int* metaw = reinterpret_cast<const int*>(meta) + wave;
+        int mk = metaw[0];
+        real wx4[4], wy[NPASS], wz[NPASS];
+        {
+            const real* wq = wxs + wave * 4;
 #pragma unroll
-            for (int ps = 0; ps < NPASS; ++ps) wyz[ps] = (oyz[ps] >= 0) ? wp[PW + oy[ps]] * wp[2 * PW + oz[ps]] : (real)0;
-            real* corner = halo + (g.y - y0) * HZ + (g.z - z0);
-            for (int ox = imod(wave - lx0, kSpreadWaves); ox < PW; ox += kSpreadWaves) {
-                const real wxv = wp[ox];
-                real* plane = corner + (lx0 + ox) * HY * HZ;
+            for (int pl = 0; pl < 4; ++pl) wx4[pl] = wq[pl];
 #pragma unroll
-                for (int ps = 0; ps < NPASS; ++ps)
-                    if (oyz[ps] >= 0) plane[oyz[ps]] += wxv * wyz[ps];
+            for (int ps = 0; ps < NPASS; ++ps) {
+                wy[ps] = wyzs[oy2[ps]];
+                wz[ps] = wyzs[oz2[ps]];
             }
+        }
+        for (int i = 0; i < cnt; ++i) {
+            const int base = mk >> 3, npl = mk & 7;
+            real wyz[NPASS], wx[NPL];
+#pragma unroll
+            for (int ps = 0; ps < NPASS; ++ps) wyz[ps] = wy[ps] * wz[ps];
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) wx[pl] = wx4[pl];
+            real cur[NPL][NPASS];
+            int at[NPL][NPASS];
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+                for (int ps = 0; ps < NPASS; ++ps) {
+                    at[pl][ps] = (pl < npl && oyz[ps] >= 0) ? base + pl * planestep + oyz[ps] : sink0 + lane;
+                    cur[pl][ps] = halo[at[pl][ps]];
+                }
+            {
+                const int in = min(i + 1, cnt - 1);
+                mk = metaw[4 * in];
+                const real* wq = wxs + in * 16 + wave * 4;
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl) wx4[pl] = wq[pl];
+                const real* wp = wyzs + in * 2 * PW;
+#pragma unroll
+                for (int ps = 0; ps < NPASS; ++ps) {
+                    wy[ps] = wp[oy2[ps]];
+                    wz[ps] = wp[oz2[ps]];
+                }
+            }
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl)
+#pragma unroll
+                for (int ps = 0; ps < NPASS; ++ps) halo[at[pl][ps]] = cur[pl][ps] + wx[pl] * wyz[ps];
         }
     }
     __syncthreads();
-    // add the block into the grid, kFlushILP independent read-modify-writes per thread in
-    // flight (only nodes some window reached are touched)
-    for (int k0 = threadIdx.x; k0 < tot; k0 += blockDim.x * kFlushILP) {
+    // add the block into the grid: each item is one (y, z) column of the block and a run of
+    // kFlushILP x planes, whose read-modify-writes are in flight together (only nodes some
+    // window reached are touched)
+    const int nch = (HX + kFlushILP - 1) / kFlushILP;
+    for (int it = threadIdx.x; it < HYZ * nch; it += kSpreadThreads) {
+        const int c = it / HYZ, k = it - c * HYZ;
+        const int ly = k / HZ, lz = k - ly * HZ;
+        const int gz = z0 - HW + lz;
+        if (gz < 0 || gz >= a.I[2]) continue;
+        const size_t colyz = (size_t)imod(y0 - HW + ly, a.I[1]) * a.I[2] + gz;
         real v[kFlushILP], old[kFlushILP];
         size_t at[kFlushILP];
 #pragma unroll
         for (int j = 0; j < kFlushILP; ++j) {
-            const int k = k0 + j * blockDim.x;
-            v[j] = 0;
-            at[j] = 0;
-            if (k < tot) {
-                const int lz = k % HZ, ly = (k / HZ) % HY, lx = k / (HZ * HY);
-                const int gz = z0 - HW + lz;
-                if (gz >= 0 && gz < a.I[2]) {
-                    v[j] = halo[k];
-                    const int gx = imod(x0 - HW + lx, a.I[0]);
-                    const int gy = imod(y0 - HW + ly, a.I[1]);
-                    at[j] = ((size_t)gx * a.I[1] + gy) * a.I[2] + gz;
-                }
-            }
+            const int lx = c * kFlushILP + j;
+            v[j] = (lx < HX) ? halo[lx * HYZ + k] : (real)0;
+            at[j] = (size_t)imod(x0 - HW + lx, a.I[0]) * a.I[1] * a.I[2] + colyz;
         }
         if (a.atomic_flush) {
 #pragma unroll
@@ -350,9 +408,7 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         a.S = S;
         a.inv_hw2 = inv_hw2;
         a.atomic_flush = r.atomic_flush;
-        size_t lds = ((((size_t)(r.B[0] + PW - 1) * (r.B[1] + PW - 1) * (r.B[2] + PW - 1) + (size_t)kSpreadStage * 3 * PW) *
-                           sizeof(real) + 15) & ~(size_t)15) +
-                     (size_t)kSpreadStage * sizeof(int4);
+        const size_t lds = spread_lds_bytes(sizeof(real), PW, r.B[0], r.B[1], r.B[2]);
         if (lds > 65536) return hipErrorInvalidConfiguration;
         hipError_t e = launch_fill_bytes_zero(ws.grid, (size_t)r.I[0] * r.I[1] * r.Izs * sizeof(real), p.stream);
         if (e != hipSuccess) return e;

@@ -72,15 +72,11 @@ double window_exponent(int Pw, double h, double s, double* S_out) {
 }
 
 int tile_edge(int prec, int Pw) {
-    // LDS: (B + P_w - 1)^3 reals for the tile plus halo (gridding and gathering), plus the
-    // window weights of 64 staged particles (64 x 3 P_w reals) and their grid points
-    // (1 KiB) in gridding; <= 64 KiB in all
+    // LDS of the gridding kernel (tile, halo and staging; the gathering kernel needs less)
+    // within 64 KiB
     const size_t rs = (prec == SOG_PREC_FP64) ? 8 : 4;
-    for (int B = 16; B >= 1; --B) {
-        size_t e = (size_t)(B + Pw - 1);
-        size_t lds = ((e * e * e + 64 * 3 * (size_t)Pw) * rs + 15) / 16 * 16 + 64 * 16;
-        if (lds <= 65536) return B;
-    }
+    for (int B = 16; B >= 1; --B)
+        if (spread_lds_bytes(rs, Pw, B, B, B) <= 65536) return B;
     return 1;
 }
 
