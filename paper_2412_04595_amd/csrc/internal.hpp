@@ -19,11 +19,12 @@ constexpr int kSpreadStage = 32;  // particles whose window weights the gridding
 
 // LDS bytes of the mid-range gridding kernel: the tile plus its (P_w - 1) halo, 64 sink
 // slots for masked lanes, and per staged particle its y and z window weights (2 P_w), its
-// x weights rotated for the four plane groups (16) and the four groups' plane offsets.
+// x weights rotated for the four plane groups (16), its offset from the grid point and
+// charge (4 reals), the four groups' plane offsets (16 bytes) and its x node (4 bytes).
 inline size_t spread_lds_bytes(size_t real_bytes, int Pw, int Bx, int By, int Bz) {
     const size_t tot = (size_t)(Bx + Pw - 1) * (By + Pw - 1) * (Bz + Pw - 1);
-    const size_t reals = tot + 64 + (size_t)kSpreadStage * (2 * Pw + 16);
-    return (reals * real_bytes + 15) / 16 * 16 + (size_t)kSpreadStage * 16;
+    const size_t reals = tot + 64 + (size_t)kSpreadStage * (2 * Pw + 16 + 4);
+    return (reals * real_bytes + 15) / 16 * 16 + (size_t)kSpreadStage * 20;
 }
 
 // A 1D FFT of length n as a product of small radices (Stockham, natural order).
@@ -65,8 +66,6 @@ struct Resolved {
     double Lzs = 0;
     int B[3] = {0, 0, 0};      // spread/gather tile
     int ntile[3] = {0, 0, 0};
-    int ncolour[3] = {1, 1, 1};  // spread colours per direction (halo blocks of one colour are disjoint)
-    int atomic_flush = 0;        // 1 when the grid is too small to colour: halo blocks added atomically
 
     // long range (Sec. 3.3 / App. B)
     bool has_long = false;

@@ -8,9 +8,10 @@
 // The grid is cut into tiles of B_x x B_y x B_z nodes and particles are sorted by the tile
 // of their nearest node (a counting sort).  Gridding: the workgroup of a tile spreads its
 // particles into an LDS copy of the tile plus a (P_w - 1) halo and adds that block into
-// the grid; tiles are coloured so that blocks added concurrently never overlap (no
-// global atomics).  Gathering: the workgroup of a tile loads the tile plus halo into LDS
-// and evaluates Phi and grad Phi for its particles.
+// the grid with float atomics (one launch for all tiles; measured faster than colouring
+// the tiles into launches whose blocks never overlap).  Gathering: the workgroup of a
+// tile loads the tile plus halo into LDS and evaluates Phi and grad Phi for its
+// particles.
 #include "device_common.hpp"
 
 namespace sog {
@@ -98,33 +99,11 @@ struct SpreadArgs {
     int ntiles;
     real S;
     real inv_hw2;
-    // tiles of colour (cx, cy, cz): per direction, tiles t with t % 2 == c (and, when the
-    // tile count is odd, the last tile alone as colour 2); ncol[d] colours per direction
-    int col[3];
-    int ncol[3];
-    int nsel[3];   // selected tiles per direction for this colour
-    int atomic_flush;
 };
-
-__device__ __forceinline__ int colour_tile(int k, int c, int ncolours, int nt) {
-    // k-th tile of colour c along one direction
-    if (ncolours == 1) return k;
-    if (ncolours == 3 && c == 2) return nt - 1;
-    return 2 * k + c;
-}
-
-__host__ __device__ inline int colour_count(int c, int ncolours, int nt) {
-    if (ncolours == 1) return nt;
-    const int nreg = (ncolours == 3) ? nt - 1 : nt;  // tiles below the odd last one
-    if (c == 2) return 1;
-    return (nreg - c + 1) / 2;
-}
 
 // Owner-tile gridding: the workgroup of a tile spreads the particles whose nearest node
 // lies in the tile into an LDS copy of the tile plus a (P_w - 1) halo -- every window
-// fits, nothing is clipped -- and then adds that block into the global grid.  Tiles of
-// one colour have disjoint halo blocks, so the adds are plain read-modify-writes; the
-// colours run one launch after another.
+// fits, nothing is clipped -- and then adds that block into the global grid atomically.
 // Inside the tile no LDS atomics are used (float LDS atomics are slow on this GPU): wave w
 // owns the x planes of the halo block with x = w mod 4 and its lanes take the window's
 // (y, z) nodes, so within a particle the lanes touch distinct nodes and no two waves ever
@@ -141,14 +120,9 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
     constexpr int NPASS = (PW * PW + 63) / 64;   // groups of 64 (y, z) window nodes
     constexpr int NPL = (PW + 3) / 4;            // x planes of a window per wave (at most)
     static_assert(NPL <= 4, "window too wide for four plane groups");
-    const int nwork = a.nsel[0] * a.nsel[1] * a.nsel[2];
-    const int w = xcd_logical_block(nwork);
-    if (w < 0) return;
-    const int kz = w % a.nsel[2], ky = (w / a.nsel[2]) % a.nsel[1], kx = w / (a.nsel[2] * a.nsel[1]);
-    const int tx = colour_tile(kx, a.col[0], a.ncol[0], a.nt[0]);
-    const int ty = colour_tile(ky, a.col[1], a.ncol[1], a.nt[1]);
-    const int tz = colour_tile(kz, a.col[2], a.ncol[2], a.nt[2]);
-    const int t = (tx * a.nt[1] + ty) * a.nt[2] + tz;
+    const int t = xcd_logical_block(a.ntiles);
+    if (t < 0) return;
+    const int tz = t % a.nt[2], ty = (t / a.nt[2]) % a.nt[1], tx = t / (a.nt[2] * a.nt[1]);
     const int beg = a.tstart[t], end = a.tstart[t + 1];
     if (beg == end) return;
     const int x0 = tx * a.B[0], y0 = ty * a.B[1], z0 = tz * a.B[2];
@@ -159,8 +133,10 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
     const int sink0 = tot;                         // 64 sink slots
     real* wyzs = halo + tot + 64;                  // kSpreadStage x 2 PW: wy, wz
     real* wxs = wyzs + kSpreadStage * 2 * PW;      // kSpreadStage x 16: q wx rotated per wave
-    const size_t meta_off = (((size_t)tot + 64 + (size_t)kSpreadStage * (2 * PW + 16)) * sizeof(real) + 15) & ~(size_t)15;
+    vec4<real>* sup = reinterpret_cast<vec4<real>*>(wxs + kSpreadStage * 16);  // kSpreadStage: u, q
+    const size_t meta_off = (((size_t)tot + 64 + (size_t)kSpreadStage * (2 * PW + 16 + 4)) * sizeof(real) + 15) & ~(size_t)15;
     int4* meta = reinterpret_cast<int4*>(smem_raw + meta_off);  // per wave: first plane offset, plane count
+    int* slx = reinterpret_cast<int*>(meta + kSpreadStage);      // x node of the particle in the block
     for (int k = threadIdx.x; k < tot + 64; k += kSpreadThreads) halo[k] = 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int oyz[NPASS], oy2[NPASS], oz2[NPASS];
@@ -173,37 +149,50 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
         oyz[ps] = in ? (k / PW) * HZ + k % PW : -1;
     }
     const int planestep = 4 * HYZ;
+    // the first kSpreadStage threads hold the next batch's particles, loaded one batch ahead
+    int4 gq = int4{0, 0, 0, 0};
+    vec4<real> uq = vec4<real>{0, 0, 0, 0};
+    if (threadIdx.x < kSpreadStage && beg + (int)threadIdx.x < end) {
+        gq = a.gp[beg + threadIdx.x];
+        uq = a.up[beg + threadIdx.x];
+    }
     for (int c0 = beg; c0 < end; c0 += kSpreadStage) {
         const int cnt = min(kSpreadStage, end - c0);
         __syncthreads();
-        // stage: y, z weights; per wave g the x weights of its planes (the planes with
-        // x = g mod 4) and the offset of its first plane, packed with the plane count
-        for (int idx = threadIdx.x; idx < cnt * (2 * PW + 16); idx += kSpreadThreads) {
-            if (idx < cnt * 2 * PW) {
-                const int i = idx / (2 * PW), r = idx - i * 2 * PW;
-                const vec4<real> u = a.up[c0 + i];
-                wyzs[idx] = win<real, PW>(r < PW ? r : r - PW, r < PW ? u.y : u.z, a.S, a.inv_hw2);
-            } else {
-                const int jdx = idx - cnt * 2 * PW;
-                const int i = jdx >> 4, g = (jdx >> 2) & 3, pl = jdx & 3;
-                const int4 gp = a.gp[c0 + i];
-                const vec4<real> u = a.up[c0 + i];
-                const int ox = ((g - (gp.x - x0)) & 3) + 4 * pl;
-                wxs[jdx] = (ox < PW) ? u.w * win<real, PW>(ox, u.x, a.S, a.inv_hw2) : (real)0;
-            }
-        }
-        for (int i = threadIdx.x; i < cnt; i += kSpreadThreads) {
-            const int4 gp = a.gp[c0 + i];
-            const int lx0 = gp.x - x0;
-            const int corner = lx0 * HYZ + (gp.y - y0) * HZ + (gp.z - z0);
+        if ((int)threadIdx.x < cnt) {
+            const int lx0 = gq.x - x0;
+            const int corner = lx0 * HYZ + (gq.y - y0) * HZ + (gq.z - z0);
             int m[4];
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 const int ox0 = (g - lx0) & 3;
-                m[g] = corner + ox0 * HYZ;
-                m[g] = (m[g] << 3) | ((PW - ox0 + 3) >> 2);  // planes of this wave: ceil((PW - ox0) / 4)
+                m[g] = ((corner + ox0 * HYZ) << 3) | ((PW - ox0 + 3) >> 2);  // planes: ceil((PW - ox0) / 4)
             }
-            meta[i] = int4{m[0], m[1], m[2], m[3]};
+            meta[threadIdx.x] = int4{m[0], m[1], m[2], m[3]};
+            slx[threadIdx.x] = lx0;
+            sup[threadIdx.x] = uq;
+        }
+        {
+            const int nx = c0 + kSpreadStage + (int)threadIdx.x;
+            if (threadIdx.x < kSpreadStage && nx < end) {
+                gq = a.gp[nx];
+                uq = a.up[nx];
+            }
+        }
+        __syncthreads();
+        // y, z weights; per wave g the x weights of its planes (x = g mod 4)
+        for (int idx = threadIdx.x; idx < cnt * (2 * PW + 16); idx += kSpreadThreads) {
+            if (idx < cnt * 2 * PW) {
+                const int i = idx / (2 * PW), r = idx - i * 2 * PW;
+                const vec4<real> u = sup[i];
+                wyzs[idx] = win<real, PW>(r < PW ? r : r - PW, r < PW ? u.y : u.z, a.S, a.inv_hw2);
+            } else {
+                const int jdx = idx - cnt * 2 * PW;
+                const int i = jdx >> 4, g = (jdx >> 2) & 3, pl = jdx & 3;
+                const vec4<real> u = sup[i];
+                const int ox = ((g - slx[i]) & 3) + 4 * pl;
+                wxs[jdx] = (ox < PW) ? u.w * win<real, PW>(ox, u.x, a.S, a.inv_hw2) : (real)0;
+            }
         }
         __syncthreads();
         // software pipeline: the next particle's weights and offsets are read before this
@@ -258,8 +247,8 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
     }
     __syncthreads();
     // add the block into the grid: each item is one (y, z) column of the block and a run of
-    // kFlushILP x planes, whose read-modify-writes are in flight together (only nodes some
-    // window reached are touched)
+    // kFlushILP x planes, whose atomic adds are in flight together (only nodes some window
+    // reached are touched)
     const int nch = (HX + kFlushILP - 1) / kFlushILP;
     for (int it = threadIdx.x; it < HYZ * nch; it += kSpreadThreads) {
         const int c = it / HYZ, k = it - c * HYZ;
@@ -267,7 +256,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
         const int gz = z0 - HW + lz;
         if (gz < 0 || gz >= a.I[2]) continue;
         const size_t colyz = (size_t)imod(y0 - HW + ly, a.I[1]) * a.I[2] + gz;
-        real v[kFlushILP], old[kFlushILP];
+        real v[kFlushILP];
         size_t at[kFlushILP];
 #pragma unroll
         for (int j = 0; j < kFlushILP; ++j) {
@@ -275,18 +264,9 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
             v[j] = (lx < HX) ? halo[lx * HYZ + k] : (real)0;
             at[j] = (size_t)imod(x0 - HW + lx, a.I[0]) * a.I[1] * a.I[2] + colyz;
         }
-        if (a.atomic_flush) {
 #pragma unroll
-            for (int j = 0; j < kFlushILP; ++j)
-                if (v[j] != (real)0) atomicAdd(a.grid + at[j], v[j]);
-        } else {
-#pragma unroll
-            for (int j = 0; j < kFlushILP; ++j)
-                old[j] = (v[j] != (real)0) ? a.grid[at[j]] : (real)0;
-#pragma unroll
-            for (int j = 0; j < kFlushILP; ++j)
-                if (v[j] != (real)0) a.grid[at[j]] = old[j] + v[j];
-        }
+        for (int j = 0; j < kFlushILP; ++j)
+            if (v[j] != (real)0) atomicAdd(a.grid + at[j], v[j]);
     }
 }
 
@@ -403,26 +383,15 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         a.tstart = ws.tile_start;
         a.grid = (real*)ws.grid;
         a.I[0] = r.I[0]; a.I[1] = r.I[1]; a.I[2] = r.Izs;
-        for (int d = 0; d < 3; ++d) { a.B[d] = r.B[d]; a.nt[d] = r.ntile[d]; a.ncol[d] = r.ncolour[d]; }
+        for (int d = 0; d < 3; ++d) { a.B[d] = r.B[d]; a.nt[d] = r.ntile[d]; }
         a.ntiles = ntiles;
         a.S = S;
         a.inv_hw2 = inv_hw2;
-        a.atomic_flush = r.atomic_flush;
         const size_t lds = spread_lds_bytes(sizeof(real), PW, r.B[0], r.B[1], r.B[2]);
         if (lds > 65536) return hipErrorInvalidConfiguration;
         hipError_t e = launch_fill_bytes_zero(ws.grid, (size_t)r.I[0] * r.I[1] * r.Izs * sizeof(real), p.stream);
         if (e != hipSuccess) return e;
-        for (int cx = 0; cx < r.ncolour[0]; ++cx)
-            for (int cy = 0; cy < r.ncolour[1]; ++cy)
-                for (int cz = 0; cz < r.ncolour[2]; ++cz) {
-                    a.col[0] = cx; a.col[1] = cy; a.col[2] = cz;
-                    a.nsel[0] = colour_count(cx, r.ncolour[0], r.ntile[0]);
-                    a.nsel[1] = colour_count(cy, r.ncolour[1], r.ntile[1]);
-                    a.nsel[2] = colour_count(cz, r.ncolour[2], r.ntile[2]);
-                    const int nwork = a.nsel[0] * a.nsel[1] * a.nsel[2];
-                    if (nwork <= 0) continue;
-                    k_spread<real, PW><<<xcd_grid(nwork), kSpreadThreads, lds, p.stream>>>(a);
-                }
+        k_spread<real, PW><<<xcd_grid(ntiles), kSpreadThreads, lds, p.stream>>>(a);
     } else {
         GatherArgs<real> a;
         a.gp = (const int4*)ws.mid_g;

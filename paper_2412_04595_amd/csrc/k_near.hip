@@ -97,6 +97,10 @@ template <typename real>
 constexpr int kNearBatch = sizeof(real) == 4 ? 8 : 4;  // candidates tested between checks of the list's room
 constexpr int kNearCodeShift = 27;  // hit entry: source index | (neighbour range << 27)
 
+// 1/sqrt: the hardware reciprocal square root in float32 (r^2 is far from denormal here)
+__device__ __forceinline__ float near_rsqrt(float v) { return __builtin_amdgcn_rsqf(v); }
+__device__ __forceinline__ double near_rsqrt(double v) { return rsqrt(v); }
+
 template <typename real, int DEG>
 __device__ __forceinline__ void near_pair(const NearArgs<real>& a, real rx, real ry, real rz, real qj, real& phi,
                                           real& gx, real& gy, real& gz) {
@@ -115,7 +119,7 @@ __device__ __forceinline__ void near_pair(const NearArgs<real>& a, real rx, real
         T0 = T1;
         T1 = T2;
     }
-    const real ri = drsqrt(r2);
+    const real ri = near_rsqrt(r2);
     phi += qj * (ri - F);                       // N(r) = 1/r - F(r)
     const real c = qj * (-ri * ri * ri - G);   // N'(r)/r
     gx += c * rx;
@@ -196,10 +200,31 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
             const vec4<real> sh = shift[k];
             const real mx = me.x - sh.x, my = me.y - sh.y, mz = me.z - sh.z;
             const uint32_t code = (uint32_t)k << kNearCodeShift;
-            for (int j0 = js; j0 < je; j0 += kNearBatch<real>) {
+            // the particle itself is among the candidates only in the centre column
+            // ranges (zero shift); there it is the pair with r^2 == 0
+            const real r2min = (k % 9 == 4) ? (real)0 : (real)-1;
+            int j0 = js;
+            for (; j0 + kNearBatch<real> <= je; j0 += kNearBatch<real>) {
                 if (__ballot(cnt > kNearCap - kNearBatch<real>)) flush();
-                // a batch of candidates; indices past the range re-read its last element
+                vec4<real> o[kNearBatch<real>];
+#pragma unroll
+                for (int u = 0; u < kNearBatch<real>; ++u) {
+                    o[u].x = cpos[j0 + u].x;
+                    o[u].y = cpos[j0 + u].y;
+                    o[u].z = cpos[j0 + u].z;
+                }
+#pragma unroll
+                for (int u = 0; u < kNearBatch<real>; ++u) {
+                    const real rx = mx - o[u].x, ry = my - o[u].y, rz = mz - o[u].z;
+                    const real r2 = rx * rx + ry * ry + rz * rz;
+                    hits[cnt * 64 + lane] = (uint32_t)(j0 + u) | code;
+                    cnt += (r2 < a.rc2 && r2 > r2min) ? 1 : 0;
+                }
+            }
+            if (j0 < je) {
+                // the range's last partial batch; indices past it re-read its last element
                 // and are masked out of the count
+                if (__ballot(cnt > kNearCap - kNearBatch<real>)) flush();
                 vec4<real> o[kNearBatch<real>];
 #pragma unroll
                 for (int u = 0; u < kNearBatch<real>; ++u) {
@@ -213,7 +238,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
                     const real rx = mx - o[u].x, ry = my - o[u].y, rz = mz - o[u].z;
                     const real r2 = rx * rx + ry * ry + rz * rz;
                     hits[cnt * 64 + lane] = (uint32_t)(j0 + u) | code;
-                    cnt += (r2 < a.rc2 && r2 > (real)0 && j0 + u < je) ? 1 : 0;
+                    cnt += (r2 < a.rc2 && r2 > r2min && j0 + u < je) ? 1 : 0;
                 }
             }
         }

@@ -340,7 +340,9 @@ void near_chebyshev(Resolved& r) {
         cmaxF = std::max(cmaxF, std::fabs(aF));
         cmaxG = std::max(cmaxG, std::fabs(aG));
     }
-    double thr = (r.prec == SOG_PREC_FP64) ? 1e-14 : 2e-8;
+    // coefficients below thr x the largest are dropped: far below float32 rounding of the
+    // pair terms in the float32 form, near float64 rounding in the float64 form
+    double thr = (r.prec == SOG_PREC_FP64) ? 1e-14 : 1e-7;
     int deg = kMaxNearDeg;
     while (deg > 1 && std::fabs(r.near_cF[deg]) < thr * cmaxF && std::fabs(r.near_cG[deg]) < thr * cmaxG) --deg;
     r.near_deg = deg;
@@ -478,29 +480,13 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         for (int d = 0; d < 3; ++d) r.h[d] = r.L[d] / r.I[d];
         r.Lzs = r.Izs * r.h[2];
         for (int d = 0; d < 3; ++d) r.H[d] = 0.5 * (r.Pw - 1) * r.h[d];
-        // tiles: LDS holds (B + P_w - 1)^3 reals for both gridding and gathering; for the
-        // coloured gridding a periodic direction needs B >= P_w - 1 and either an odd tile
-        // count (3 colours, the last tile alone) or a last tile of at least P_w - 1 nodes
-        int B = tile_edge(r.prec, r.Pw);
-        int gI[3] = {r.I[0], r.I[1], r.Izs};
-        r.atomic_flush = 0;
+        // tiles: LDS holds the tile plus its (P_w - 1) halo for gridding and gathering;
+        // gridding adds each tile's block into the grid with atomics, so any tile count works
+        const int B = tile_edge(r.prec, r.Pw);
+        const int gI[3] = {r.I[0], r.I[1], r.Izs};
         for (int d = 0; d < 3; ++d) {
-            int Bd = std::min(B, gI[d]);
-            int chosen = 0;
-            for (int b2 = Bd; b2 >= std::max(1, r.Pw - 1) && !chosen; --b2) {
-                int nt = (gI[d] + b2 - 1) / b2;
-                int rem = gI[d] - (nt - 1) * b2;
-                bool ok = (d == 2) ? nt >= 1 : ((nt >= 3 && nt % 2 == 1) || (nt >= 2 && nt % 2 == 0 && rem >= r.Pw - 1));
-                if (ok) chosen = b2;
-            }
-            if (!chosen) { chosen = Bd; r.atomic_flush = 1; }
-            r.B[d] = chosen;
-            r.ntile[d] = (gI[d] + chosen - 1) / chosen;
-        }
-        for (int d = 0; d < 3; ++d) {
-            if (r.atomic_flush) r.ncolour[d] = 1;
-            else if (d == 2) r.ncolour[d] = (r.ntile[2] >= 2) ? 2 : 1;
-            else r.ncolour[d] = (r.ntile[d] % 2) ? 3 : 2;
+            r.B[d] = std::min(B, gI[d]);
+            r.ntile[d] = (gI[d] + r.B[d] - 1) / r.B[d];
         }
         if (!is_smooth(r.I[0]) || !is_smooth(r.I[1]) || !is_smooth(r.Izs / 2)) { err = "mid grid sizes must have only factors 2, 3, 5, 7 (and I_z*/2 as well)"; return SOG_ERR_INVALID_ARG; }
         if (r.I[0] % 2 || r.I[1] % 2) { err = "mid I_x, I_y must be even"; return SOG_ERR_INVALID_ARG; }
