@@ -92,7 +92,7 @@ struct NearArgs {
 };
 
 constexpr int kNearWaves = 4;   // independent waves per block
-constexpr int kNearCap = 48;    // hit-list entries per lane
+constexpr int kNearCap = 32;    // hit-list entries per lane (a ring; power of two)
 template <typename real>
 constexpr int kNearBatch = sizeof(real) == 4 ? 8 : 4;  // candidates tested between checks of the list's room
 constexpr int kNearCodeShift = 27;  // hit entry: source index | (neighbour range << 27)
@@ -167,6 +167,9 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
         }
         shift[lane] = vec4<real>{(real)dx * a.ch[0], (real)dy * a.ch[1], (real)((dzi - 1) * a.zc) * a.ch[2], (real)0};
     }
+    // longest of the 27 ranges
+    int maxlen = re - rs;
+    for (int o = 32; o > 0; o >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, o, 64));
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -175,74 +178,87 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
         const bool act = p < te;
         const vec4<real> me = act ? a.pos[p] : vec4<real>{(real)1e30, (real)1e30, (real)1e30, (real)0};
         real phi = 0, gx = 0, gy = 0, gz = 0;
-        int cnt = 0;
-        // evaluate the hit list, four entries at a time with their loads issued first
-        auto flush = [&]() {
-            for (int h = 0; h < cnt; h += 4) {
-                vec4<real> o[4], sh[4];
+        // each lane's hit list is a ring of kNearCap entries: tail tp, head hd
+        int tp = 0, hd = 0;
+        constexpr int kMask = kNearCap - 1;
+        // evaluate up to four entries of every lane's list, their loads issued first
+        auto chunk = [&]() {
+            const int cnt = (tp - hd) & kMask;
+            vec4<real> o[4], sh[4];
+            // a lane with an empty list loads a valid dummy (the block's first particle)
+            const uint32_t dummy = (uint32_t)tb | (13u << kNearCodeShift);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint32_t e = hits[min(h + u, cnt - 1) * 64 + lane];
-                    o[u] = a.pos[e & ((1u << kNearCodeShift) - 1)];
-                    sh[u] = shift[e >> kNearCodeShift];
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (h + u < cnt)
-                        near_pair<real, DEG>(a, me.x - (o[u].x + sh[u].x), me.y - (o[u].y + sh[u].y),
-                                             me.z - (o[u].z + sh[u].z), o[u].w, phi, gx, gy, gz);
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t e = (cnt > 0) ? hits[((hd + min(u, cnt - 1)) & kMask) * 64 + lane] : dummy;
+                o[u] = a.pos[e & ((1u << kNearCodeShift) - 1)];
+                sh[u] = shift[e >> kNearCodeShift];
             }
-            cnt = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u < cnt)
+                    near_pair<real, DEG>(a, me.x - (o[u].x + sh[u].x), me.y - (o[u].y + sh[u].y),
+                                         me.z - (o[u].z + sh[u].z), o[u].w, phi, gx, gy, gz);
+            hd = (hd + min(cnt, 4)) & kMask;
         };
-        for (int k = 0; k < 27; ++k) {
-            const int js = __builtin_amdgcn_readlane(rs, k), je = __builtin_amdgcn_readlane(re, k);
-            if (js == je) continue;
-            const vec4<real> sh = shift[k];
-            const real mx = me.x - sh.x, my = me.y - sh.y, mz = me.z - sh.z;
-            const uint32_t code = (uint32_t)k << kNearCodeShift;
-            // the particle itself is among the candidates only in the centre column
-            // ranges (zero shift); there it is the pair with r^2 == 0
-            const real r2min = (k % 9 == 4) ? (real)0 : (real)-1;
-            int j0 = js;
-            for (; j0 + kNearBatch<real> <= je; j0 += kNearBatch<real>) {
-                if (__ballot(cnt > kNearCap - kNearBatch<real>)) flush();
-                vec4<real> o[kNearBatch<real>];
-#pragma unroll
-                for (int u = 0; u < kNearBatch<real>; ++u) {
-                    o[u].x = cpos[j0 + u].x;
-                    o[u].y = cpos[j0 + u].y;
-                    o[u].z = cpos[j0 + u].z;
-                }
-#pragma unroll
-                for (int u = 0; u < kNearBatch<real>; ++u) {
-                    const real rx = mx - o[u].x, ry = my - o[u].y, rz = mz - o[u].z;
-                    const real r2 = rx * rx + ry * ry + rz * rz;
-                    hits[cnt * 64 + lane] = (uint32_t)(j0 + u) | code;
-                    cnt += (r2 < a.rc2 && r2 > r2min) ? 1 : 0;
-                }
+        // a chunk is evaluated as soon as every active lane has four entries waiting (all
+        // lanes busy), or when some list is too full for the next batch of candidates
+        auto drain_ready = [&]() {
+            while (true) {
+                const int cnt = (tp - hd) & kMask;
+                if (__ballot(act && cnt < 4) != 0 && __ballot(cnt > kNearCap - 1 - kNearBatch<real>) == 0) break;
+                chunk();
             }
-            if (j0 < je) {
-                // the range's last partial batch; indices past it re-read its last element
-                // and are masked out of the count
-                if (__ballot(cnt > kNearCap - kNearBatch<real>)) flush();
+        };
+        // the 27 ranges are walked round-robin, one batch of each in turn, so that every
+        // lane's list grows at about the same rate and a list that fills up finds the
+        // others nearly as full (the evaluation runs as long as the longest list)
+        for (int off = 0; off < maxlen; off += kNearBatch<real>) {
+            for (int k = 0; k < 27; ++k) {
+                const int js = __builtin_amdgcn_readlane(rs, k) + off, je = __builtin_amdgcn_readlane(re, k);
+                if (js >= je) continue;
+                const vec4<real> sh = shift[k];
+                const real mx = me.x - sh.x, my = me.y - sh.y, mz = me.z - sh.z;
+                const uint32_t code = (uint32_t)k << kNearCodeShift;
+                // the particle itself is among the candidates only in the centre column
+                // ranges (zero shift); there it is the pair with r^2 == 0
+                const real r2min = (k % 9 == 4) ? (real)0 : (real)-1;
+                drain_ready();
                 vec4<real> o[kNearBatch<real>];
+                if (js + kNearBatch<real> <= je) {
 #pragma unroll
-                for (int u = 0; u < kNearBatch<real>; ++u) {
-                    const int jj = min(j0 + u, je - 1);
-                    o[u].x = cpos[jj].x;
-                    o[u].y = cpos[jj].y;
-                    o[u].z = cpos[jj].z;
-                }
+                    for (int u = 0; u < kNearBatch<real>; ++u) {
+                        o[u].x = cpos[js + u].x;
+                        o[u].y = cpos[js + u].y;
+                        o[u].z = cpos[js + u].z;
+                    }
 #pragma unroll
-                for (int u = 0; u < kNearBatch<real>; ++u) {
-                    const real rx = mx - o[u].x, ry = my - o[u].y, rz = mz - o[u].z;
-                    const real r2 = rx * rx + ry * ry + rz * rz;
-                    hits[cnt * 64 + lane] = (uint32_t)(j0 + u) | code;
-                    cnt += (r2 < a.rc2 && r2 > r2min && j0 + u < je) ? 1 : 0;
+                    for (int u = 0; u < kNearBatch<real>; ++u) {
+                        const real rx = mx - o[u].x, ry = my - o[u].y, rz = mz - o[u].z;
+                        const real r2 = rx * rx + ry * ry + rz * rz;
+                        hits[tp * 64 + lane] = (uint32_t)(js + u) | code;
+                        tp = (tp + ((r2 < a.rc2 && r2 > r2min) ? 1 : 0)) & kMask;
+                    }
+                } else {
+                    // the range's last partial batch; indices past it re-read its last
+                    // element and are masked out of the count
+#pragma unroll
+                    for (int u = 0; u < kNearBatch<real>; ++u) {
+                        const int jj = min(js + u, je - 1);
+                        o[u].x = cpos[jj].x;
+                        o[u].y = cpos[jj].y;
+                        o[u].z = cpos[jj].z;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kNearBatch<real>; ++u) {
+                        const real rx = mx - o[u].x, ry = my - o[u].y, rz = mz - o[u].z;
+                        const real r2 = rx * rx + ry * ry + rz * rz;
+                        hits[tp * 64 + lane] = (uint32_t)(js + u) | code;
+                        tp = (tp + ((r2 < a.rc2 && r2 > r2min && js + u < je) ? 1 : 0)) & kMask;
+                    }
                 }
             }
         }
-        flush();
+        while (__ballot(tp != hd)) chunk();
         if (act) {
             const int i = a.orig[p];
             a.pphi[i] = phi;
@@ -262,7 +278,9 @@ void launch_near_deg(const NearArgs<real>& a, hipStream_t st) {
 template <typename real>
 void launch_near_kernel(const NearArgs<real>& a, hipStream_t st) {
     if (a.deg <= 8) launch_near_deg<real, 8>(a, st);
+    else if (a.deg <= 10) launch_near_deg<real, 10>(a, st);
     else if (a.deg <= 12) launch_near_deg<real, 12>(a, st);
+    else if (a.deg <= 14) launch_near_deg<real, 14>(a, st);
     else if (a.deg <= 16) launch_near_deg<real, 16>(a, st);
     else if (a.deg <= 20) launch_near_deg<real, 20>(a, st);
     else if (a.deg <= 24) launch_near_deg<real, 24>(a, st);
