@@ -22,8 +22,7 @@ namespace sog {
 
 namespace {
 
-constexpr int kMomThreads = 256;
-constexpr int kMomItems = 4;   // items per thread; an item is (mode, 4 consecutive n)
+constexpr int kMomThreads = 256;  // an item is (mode, 4 consecutive n); G threads share an item
 
 template <typename real>
 struct MomArgs {
@@ -35,6 +34,7 @@ struct MomArgs {
     int per_block;  // particles per block
     int chunk;      // particles per LDS batch (<= kMomThreads)
     int item0, nitems;
+    int group;      // threads per item in this launch (they split the particles)
     double* mu;     // blocks x nh x P complex
 };
 
@@ -57,20 +57,19 @@ __global__ __launch_bounds__(kMomThreads) void k_long_moments(MomArgs<real> a) {
     real* Tn = reinterpret_cast<real*>(smem_raw);                    // P x CH
     cpx<real>* ex = reinterpret_cast<cpx<real>*>(Tn + P * CH);        // NX x CH (includes q)
     cpx<real>* ey = ex + NX * CH;                                     // NY x CH
+    cpx<real>* red = ey + NY * CH;                                    // kMomThreads x 4
     const int PB = (P + 3) / 4;
-    int kk[kMomItems], n0[kMomItems], nxs[kMomItems], nys[kMomItems];
-    bool act[kMomItems];
-    cpx<real> acc[kMomItems][4];
+    const int G = a.group;
+    const int item_l = threadIdx.x / G, sub = threadIdx.x - item_l * G;
+    const int item = a.item0 + item_l;
+    const bool act = item_l * G + G <= kMomThreads && item < a.nitems;
+    const int kk = act ? item / PB : 0;
+    const int n0 = act ? (item % PB) * 4 : 0;
+    int nxs, nys;
+    mode_of(kk, a.nkx, &nxs, &nys);
+    cpx<real> acc[4];
 #pragma unroll
-    for (int it = 0; it < kMomItems; ++it) {
-        const int item = a.item0 + threadIdx.x + it * kMomThreads;
-        act[it] = (item < a.nitems);
-        kk[it] = act[it] ? item / PB : 0;
-        n0[it] = act[it] ? (item % PB) * 4 : 0;
-        mode_of(kk[it], a.nkx, &nxs[it], &nys[it]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[it][c] = cpx<real>{0, 0};
-    }
+    for (int c = 0; c < 4; ++c) acc[c] = cpx<real>{0, 0};
     const int pbeg = blockIdx.x * a.per_block;
     const int pend = min(a.n, pbeg + a.per_block);
     const double kx0 = 2.0 * 3.14159265358979323846 / a.L[0], ky0 = 2.0 * 3.14159265358979323846 / a.L[1];
@@ -117,67 +116,81 @@ __global__ __launch_bounds__(kMomThreads) void k_long_moments(MomArgs<real> a) {
                     py = cmul(py, e2);
                     ey[k * CH + t] = py;
                 }
-            } else {
-                for (int k = 0; k < P; ++k) Tn[k * CH + t] = 0;
-                for (int k = 0; k < NX; ++k) ex[k * CH + t] = cpx<real>{0, 0};
-                for (int k = 0; k < NY; ++k) ey[k * CH + t] = cpx<real>{0, 0};
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int it = 0; it < kMomItems; ++it) {
-            if (!act[it]) continue;
-            const cpx<real>* exr = ex + (nxs[it] + a.nkx) * CH;
-            const cpx<real>* eyr = ey + nys[it] * CH;
-            for (int j = 0; j < cnt; ++j) {
+        if (act) {
+            const cpx<real>* exr = ex + (nxs + a.nkx) * CH;
+            const cpx<real>* eyr = ey + nys * CH;
+            for (int j = sub; j < cnt; j += G) {
                 const cpx<real> e = cmul(exr[j], eyr[j]);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const int nn = n0[it] + c;
-                    if (nn < P) {
-                        const real tv = Tn[nn * CH + j];
-                        acc[it][c].x += e.x * tv;
-                        acc[it][c].y += e.y * tv;
-                    }
+                    const real tv = Tn[min(n0 + c, P - 1) * CH + j];
+                    acc[c].x += e.x * tv;
+                    acc[c].y += e.y * tv;
                 }
             }
         }
         __syncthreads();
     }
+    // sum the G partial results of each item in a fixed order
 #pragma unroll
-    for (int it = 0; it < kMomItems; ++it) {
-        if (!act[it]) continue;
+    for (int c = 0; c < 4; ++c) red[threadIdx.x * 4 + c] = acc[c];
+    __syncthreads();
+    if (act && sub == 0) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const int nn = n0[it] + c;
-            if (nn < P) {
-                double* o = a.mu + 2 * (((size_t)blockIdx.x * a.nh + kk[it]) * P + nn);
-                o[0] = (double)acc[it][c].x;
-                o[1] = (double)acc[it][c].y;
+            const int nn = n0 + c;
+            if (nn >= P) continue;
+            double sr = 0, si = 0;
+            for (int g = 0; g < G; ++g) {
+                const cpx<real> v = red[(threadIdx.x + g) * 4 + c];
+                sr += (double)v.x;
+                si += (double)v.y;
             }
+            double* o = a.mu + 2 * (((size_t)blockIdx.x * a.nh + kk) * P + nn);
+            o[0] = sr;
+            o[1] = si;
         }
     }
 }
 
-// one block per mode: float64 sum over blocks, then a = (w_k/A) Kt mu
+// one block per mode: float64 sum over blocks (each thread a strided subset, then a
+// fixed-order tree in LDS), then a = (w_k/A) Kt mu
+constexpr int kContractThreads = 256;
 template <typename real>
-__global__ void k_long_contract(const double* __restrict__ mu, int nblocks, int nh, int P, const double* __restrict__ kt,
-                                double invA, cpx<real>* __restrict__ aout) {
+__global__ __launch_bounds__(kContractThreads) void k_long_contract(const double* __restrict__ mu, int nblocks, int nh,
+                                                                   int P, const double* __restrict__ kt, double invA,
+                                                                   cpx<real>* __restrict__ aout) {
     __shared__ double smu[2 * 64];
+    __shared__ double tre[kContractThreads], tim[kContractThreads];
     const int k = blockIdx.x;
-    for (int nn = threadIdx.x; nn < P; nn += blockDim.x) {
+    for (int nn = 0; nn < P; ++nn) {
         double sr = 0, si = 0;
-        for (int b = 0; b < nblocks; ++b) {
+        for (int b = threadIdx.x; b < nblocks; b += kContractThreads) {
             const double* o = mu + 2 * (((size_t)b * nh + k) * P + nn);
             sr += o[0];
             si += o[1];
         }
-        smu[2 * nn] = sr;
-        smu[2 * nn + 1] = si;
+        tre[threadIdx.x] = sr;
+        tim[threadIdx.x] = si;
+        __syncthreads();
+        for (int h = kContractThreads / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) {
+                tre[threadIdx.x] += tre[threadIdx.x + h];
+                tim[threadIdx.x] += tim[threadIdx.x + h];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            smu[2 * nn] = tre[0];
+            smu[2 * nn + 1] = tim[0];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     const double wk = (k == 0 ? 1.0 : 2.0) * invA;
-    for (int nn = threadIdx.x; nn < P; nn += blockDim.x) {
+    for (int nn = threadIdx.x; nn < P; nn += kContractThreads) {
         const double* row = kt + ((size_t)k * P + nn) * P;
         double sr = 0, si = 0;
         for (int e = 0; e < P; ++e) {
@@ -296,18 +309,21 @@ hipError_t run_long_direct(Plan& p, const double* x, const double* q) {
     const int nb = ws.long_blocks;
     a.per_block = (n + nb - 1) / nb;
     int CH = kMomThreads;
-    while (CH > 16 && (size_t)CH * (P * sizeof(real) + (NX + NY) * sizeof(cpx<real>)) > 49152) CH >>= 1;
-    if ((size_t)CH * (P * sizeof(real) + (NX + NY) * sizeof(cpx<real>)) > 65536) return hipErrorInvalidConfiguration;
+    const size_t red_bytes = (size_t)kMomThreads * 4 * sizeof(cpx<real>);
+    auto lds_of = [&](int ch) { return (size_t)ch * (P * sizeof(real) + (NX + NY) * sizeof(cpx<real>)) + red_bytes; };
+    while (CH > 16 && lds_of(CH) > 49152) CH >>= 1;
+    if (lds_of(CH) > 65536) return hipErrorInvalidConfiguration;
     a.chunk = CH;
     a.mu = ws.long_mu;
     const int PB = (P + 3) / 4;
     const int nitems = nh * PB;
     a.nitems = nitems;
-    size_t lds = (size_t)CH * (P * sizeof(real) + (NX + NY) * sizeof(cpx<real>));
+    const size_t lds = lds_of(CH);
     int t = timer_id(p, "long_moments");
     timer_begin(p, t);
-    for (int i0 = 0; i0 < nitems; i0 += kMomThreads * kMomItems) {
+    for (int i0 = 0; i0 < nitems; i0 += kMomThreads) {
         a.item0 = i0;
+        a.group = std::max(1, kMomThreads / std::min(kMomThreads, nitems - i0));
         k_long_moments<real><<<nb, kMomThreads, lds, p.stream>>>(a);
     }
     timer_end(p, t);
@@ -315,7 +331,7 @@ hipError_t run_long_direct(Plan& p, const double* x, const double* q) {
     if (e != hipSuccess) return e;
     t = timer_id(p, "long_contract");
     timer_begin(p, t);
-    k_long_contract<real><<<nh, 64, 0, p.stream>>>(ws.long_mu, nb, nh, P, ws.long_kt, 1.0 / (r.L[0] * r.L[1]),
+    k_long_contract<real><<<nh, kContractThreads, 0, p.stream>>>(ws.long_mu, nb, nh, P, ws.long_kt, 1.0 / (r.L[0] * r.L[1]),
                                                    (cpx<real>*)ws.long_a);
     timer_end(p, t);
     if ((e = hipGetLastError()) != hipSuccess) return e;
