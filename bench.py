@@ -21,7 +21,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"hbm_GBs": 8000.0, "fp32_TFs": 157.3, "fp64_TFs": 78.6}
+# MI355X peaks.  HBM3E 8 TB/s.  The kernels are built without packed-FP32 instructions,
+# so the FP32 vector peak this code can reach is one FMA per lane per clock:
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s (the published 157.3
+# counts packed FP32); FP64 vector 78.6 TFLOP/s.
+PEAK = {"hbm_GBs": 8000.0, "fp32_alu_TFs": 78.6, "fp64_alu_TFs": 78.6}
 METRIC = "particles/s energy+forces at 1e-4 rel err, N=1e6; FP32-bulk vs FP64 plain"
 
 
@@ -29,21 +33,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_models(info, sizes, N, box, prec_bytes):
-    """Algorithmic work per launch (flops, bytes) of the main kernels; see the design doc."""
+def kernel_models(info, sizes, N, box, rs):
+    """Algorithmic work of one launch of the main kernels (flops, HBM bytes); rs is the
+    working precision's bytes per real.  The per-unit figures are stated in the design doc."""
     Pw = info["mid_Pw"][0]
     Ng = sizes["mid_grid_points"]
     rc = info["rc"]
+    deg = sizes["near_degree"]
     rho = N / (box[0] * box[1] * box[2])
-    rs = prec_bytes
-    pairs = N * (4.0 * math.pi / 3.0) * rc ** 3 * rho
+    pairs = N * (4.0 * math.pi / 3.0) * rc ** 3 * rho   # ordered pairs within r_c (uniform density)
     m = {}
-    # near: per pair ~ 2 Clenshaw series of degree ~15 (4 flops per degree) + 15
-    m["near"] = dict(flops=pairs * (4 * 15 + 15), bytes=N * (4 * rs + 4 * rs), bound="alu")
-    # spread: per particle P_w^3 multiply-adds into the tile; grid written once
-    m["mid_spread"] = dict(flops=N * (2 * Pw ** 3 + 2 * Pw ** 2), bytes=N * (16 + 4 * rs) + Ng * rs, bound="alu")
-    # gather: per particle 2 P_w^3 FMAs (value and z derivative) + 3 P_w^2; grid read once
-    m["mid_gather"] = dict(flops=N * (4 * Pw ** 3 + 6 * Pw ** 2), bytes=N * (16 + 4 * rs + 4 * rs) + Ng * rs,
+    # near: per pair 6 flops per Chebyshev degree above 1 (recurrence + two series) and 30
+    # for distance, rsqrt and accumulation; bytes: the packed particle in, 4 results out
+    m["near"] = dict(flops=pairs * (6 * (deg - 1) + 30), bytes=N * (4 * rs + 4 + 4 * rs), bound="alu")
+    # spread: one FMA per window node; particle records in, grid read and written once
+    m["mid_spread"] = dict(flops=N * 2 * Pw ** 3, bytes=N * (16 + 4 * rs) + 2 * Ng * rs, bound="alu")
+    # gather: two FMAs per window node (value and z derivative) plus the y and x sums
+    m["mid_gather"] = dict(flops=N * (4 * Pw ** 3 + 6 * Pw ** 2 + 8 * Pw), bytes=N * (16 + 4 * rs + 4 * rs) + Ng * rs,
                            bound="alu")
     Kz = info["mid_Izs"] // 2 + 1
     cg = info["mid_I"][0] * info["mid_I"][1] * Kz * 2 * rs
@@ -53,6 +59,15 @@ def kernel_models(info, sizes, N, box, prec_bytes):
     m["fft_y_inv"] = dict(flops=None, bytes=2 * cg, bound="hbm")
     m["fft_x_scale"] = dict(flops=None, bytes=2 * cg, bound="hbm")
     return m
+
+
+def roofline_of(mdl, t_s, fp64=False):
+    if mdl["bound"] == "hbm":
+        ach = mdl["bytes"] / t_s / 1e9
+        return dict(bound="hbm", achieved=ach, peak=PEAK["hbm_GBs"], unit="GB/s", frac=ach / PEAK["hbm_GBs"])
+    pk = PEAK["fp64_alu_TFs"] if fp64 else PEAK["fp32_alu_TFs"]
+    ach = mdl["flops"] / t_s / 1e12
+    return dict(bound="alu", achieved=ach, peak=pk, unit="TFLOP/s", frac=ach / pk)
 
 
 def source_digest():
@@ -65,8 +80,8 @@ def source_digest():
 
 
 def traffic_from_profiles(kernel, workload):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they were
-    taken on the current sources (else None)."""
+    """HBM bytes per launch (fetched + written) from the committed rocprofv3 counter
+    summary, if it was taken on the current sources (else None)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -75,8 +90,8 @@ def traffic_from_profiles(kernel, workload):
         if line.startswith("#") or not line.strip():
             continue
         f = line.split()
-        if len(f) >= 5 and f[0] == kernel and f[4] == digest:
-            return float(f[1]) * float(f[3]) + float(f[2]) * float(f[3])
+        if len(f) >= 4 and f[0] == kernel and f[3] == digest:
+            return float(f[1]) + float(f[2])
     return None
 
 
@@ -100,13 +115,12 @@ def accuracy(workload, phi, F, q):
 
 def cpu_baseline(tol):
     """The oracle (plain NumPy fast SOG method) on a bounded sample of the workload:
-    N = 8000 uniform particles at the same density (box 20^3), same tolerance,
-    parameters from oracle.planner; single-threaded BLAS."""
-    import numpy as np
+    N = 27000 uniform particles at the same density (box 30^3), same tolerance,
+    parameters from oracle.planner; single-threaded BLAS/FFT."""
     from threadpoolctl import threadpool_limits
     from oracle import fast, planner
     import workloads
-    Ns, L = 8000, 20.0
+    Ns, L = 27000, 30.0
     box = (L, L, L)
     x, q = workloads.uniform(Ns, box, 2)
     p = planner.plan(box, Ns, tol)
@@ -150,6 +164,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run three 256 MiB device-to-device copies (the known-size copy that scales the "
+                         "HBM counters of a profiling run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
@@ -173,12 +190,20 @@ def main():
     if not args.no_fp64:
         r64 = run_form(sog, torch, xt, qt, box, N, args.tol, "fp64", max(3, args.steps // 2), 1)
         log(f"[bench] fp64 {r64['dt'] * 1e3:.3f} ms/step")
+    if args.copy_calibration:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     phi32 = r32["phi"].cpu().numpy()
     F32 = r32["F"].cpu().numpy()
     acc32 = accuracy(args.workload, phi32, F32, q)
     acc64 = accuracy(args.workload, r64["phi"].cpu().numpy(), r64["F"].cpu().numpy(), q) if r64 else None
 
-    # roofline of the dominant kernel (FP32-bulk run)
+    # roofline of the dominant kernel (FP32-bulk run), from the library's HIP events on
+    # the plan's stream during the timed calls
     kt = r32["kt"]
     per_launch = {k: v[0] / max(v[1], 1) for k, v in kt.items()}
     per_step = {k: v[0] / args.steps for k, v in kt.items()}
@@ -187,18 +212,19 @@ def main():
     roof = None
     if dom in models:
         mdl = models[dom]
-        t = per_launch[dom] * 1e-3
-        if mdl["bound"] == "hbm":
-            ach = mdl["bytes"] / t / 1e9
-            roof = dict(bound="hbm", achieved=ach, peak=PEAK["hbm_GBs"], unit="GB/s", frac=ach / PEAK["hbm_GBs"])
-        else:
-            ach = mdl["flops"] / t / 1e12
-            roof = dict(bound="alu", achieved=ach, peak=PEAK["fp32_TFs"], unit="TFLOP/s", frac=ach / PEAK["fp32_TFs"])
+        roof = roofline_of(mdl, per_launch[dom] * 1e-3)
+        roof["traffic"] = traffic_from_profiles(dom, args.workload)
         roof["kernel"] = dom
         roof["kernel_ms"] = per_launch[dom]
-        roof["traffic"] = traffic_from_profiles(dom, args.workload)
         roof["algorithmic_bytes"] = mdl["bytes"]
-        roof["hbm_frac_algorithmic"] = mdl["bytes"] / t / 1e9 / PEAK["hbm_GBs"]
+        if mdl["flops"] is not None:
+            roof["algorithmic_flops"] = mdl["flops"]
+    others = {}
+    for k, mdl in models.items():
+        if k in per_launch:
+            rf = roofline_of(mdl, per_launch[k] * 1e-3)
+            others[k] = {"bound": rf["bound"], "frac": round(rf["frac"], 4), "achieved": round(rf["achieved"], 3),
+                         "unit": rf["unit"], "ms": round(per_launch[k], 4)}
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a bounded sample)")
@@ -225,6 +251,7 @@ def main():
         "speedup_fp32_vs_fp64": None if r64 is None else r64["dt"] / r32["dt"],
         "accuracy": acc32,
         "roofline": roof,
+        "roofline_kernels": others,
         "cpu_baseline": cpu,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "plan": {k: r32["info"][k] for k in ("rc", "M", "m", "mid_I", "mid_Izs", "mid_Pw", "long_form", "long_P",

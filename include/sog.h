@@ -148,6 +148,8 @@ typedef struct {
     int64_t device_bytes;      /* workspace held by the plan                  */
     int32_t near_cells[3];
     int32_t tile[3];           /* mid-range spread/gather tile, grid points  */
+    int32_t near_degree;       /* Chebyshev degree of the near-field kernel  */
+    int32_t near_cells_per_block; /* z cells per near-field work unit       */
 } sog_plan_sizes;
 sog_status sog_plan_sizes_get(sog_plan_t plan, sog_plan_sizes* out);
 

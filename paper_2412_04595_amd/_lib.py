@@ -12,6 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsog_hip.so")
 
 SOG_OK = 0
+(SOG_ERR_INVALID_ARG, SOG_ERR_NOT_NEUTRAL, SOG_ERR_OUT_OF_BOX, SOG_ERR_TOL_UNREACHABLE, SOG_ERR_OUT_OF_MEMORY,
+ SOG_ERR_DEVICE) = range(1, 7)
 STATUS = {
     0: "SOG_OK",
     1: "SOG_ERR_INVALID_ARG",
@@ -71,6 +73,7 @@ class sog_plan_sizes(C.Structure):
     _fields_ = [
         ("mid_grid_points", C.c_int64), ("long_points", C.c_int64), ("device_bytes", C.c_int64),
         ("near_cells", C.c_int32 * 3), ("tile", C.c_int32 * 3),
+        ("near_degree", C.c_int32), ("near_cells_per_block", C.c_int32),
     ]
 
 
@@ -87,6 +90,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise OSError(f"{LIB_PATH} is missing: build it with `python -m paper_2412_04595_amd.build`")
+        # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7 (same soname
+        # as the system one this library links), and whichever loads first serves both.
+        # Load torch's first when torch is installed, so that torch device tensors and
+        # streams keep working after the library is loaded.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         dp = C.POINTER(C.c_double)

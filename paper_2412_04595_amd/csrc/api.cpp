@@ -592,6 +592,8 @@ sog_status sog_plan_sizes_get(sog_plan_t plan, sog_plan_sizes* o) {
         o->near_cells[d] = r.nc[d];
         o->tile[d] = r.B[d];
     }
+    o->near_degree = r.near_deg;
+    o->near_cells_per_block = r.near_zc;
     return SOG_OK;
 }
 

@@ -1,0 +1,153 @@
+"""Host-side checks of the C ABI (no GPU needed, no compute calls).
+
+* the library loads and exports every function include/sog.h declares;
+* status strings, option defaults;
+* the planner (sog_plan_resolve runs on a machine without a GPU): argument checks, and
+  the structural properties every plan must have for the workloads of the benchmark.
+"""
+import math
+import os
+import re
+
+import pytest
+
+import paper_2412_04595_amd as sog
+from paper_2412_04595_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sog.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(sog_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for must in ("sog_plan", "sog_energy_potential_force", "sog_destroy", "sog_plan_resolve"):
+        assert must in names
+
+
+def test_library_exports_every_declared_function():
+    L = _lib.lib()
+    missing = [n for n in _declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+    # and the binding covers exactly what the header declares
+    assert sorted(_lib.EXPORTS) == _declared_functions()
+
+
+def test_status_strings():
+    for code, name in _lib.STATUS.items():
+        assert sog.sog_status_string(code) == name
+    assert "unknown" in sog.sog_status_string(99).lower()
+
+
+def test_option_defaults():
+    o = sog.sog_options_default()
+    assert o.precision == sog.SOG_PREC_FP64 and o.device == 0 and not o.stream
+    assert o.pointers_on_device == 0 and o.check_inputs == 1 and o.timing == 0
+    assert o.params.mid_I[0] == 0 and o.params.long_P == 0
+
+
+def _resolve_status(box, n, tol, precision="fp64", params=None):
+    try:
+        sog.plan_parameters(box, n, tol, precision, params)
+        return _lib.SOG_OK
+    except sog.SogError as e:
+        assert sog.sog_last_error()  # every failure leaves a message
+        return e.status
+
+
+@pytest.mark.parametrize("box,n,tol,prec,status", [
+    ((0, 10, 10), 100, 1e-4, "fp64", 1),
+    ((10, -1, 10), 100, 1e-4, "fp64", 1),
+    ((10, 10, float("inf")), 100, 1e-4, "fp64", 1),
+    ((10, 10, 10), 1, 1e-4, "fp64", 1),
+    ((10, 10, 10), (1 << 27) + 1, 1e-4, "fp64", 1),
+    ((10, 10, 10), 100, 1e-13, "fp64", 4),
+    ((10, 10, 10), 100, 1e-6, "fp32", 4),
+    ((10, 10, 10), 100, 0.5, "fp64", 4),
+    ((10, 10, 10), 100, float("nan"), "fp64", 4),
+])
+def test_resolve_rejects_bad_arguments(box, n, tol, prec, status):
+    assert _resolve_status(box, n, tol, prec) == status
+
+
+@pytest.mark.parametrize("params", [
+    dict(mid_Pw=[8, 8, 8]),        # even window
+    dict(mid_Pw=[9, 9, 7]),        # not equal in x, y, z
+    dict(long_P=65),
+    dict(mid_Izs=81),              # odd padded z grid
+])
+def test_resolve_rejects_bad_overrides(params):
+    assert _resolve_status((20, 20, 20), 1000, 1e-4, "fp64", params) == _lib.SOG_ERR_INVALID_ARG
+
+
+def _smooth(n):
+    for p in (2, 3, 5, 7):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+WORKLOADS = {
+    "cube_small": ((20.0, 20.0, 20.0), 1000),
+    "cube_1e6": ((100.0, 100.0, 100.0), 1000000),
+    "slab_1e6": ((400.0, 400.0, 25.0), 1000000),
+    "tall_1e6": ((50.0, 50.0, 800.0), 1000000),
+    "layered_2e5": ((150.0, 150.0, 60.0), 200000),
+}
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-4), ("fp64", 1e-4), ("fp64", 1e-6)])
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_plan_structure(name, prec, tol):
+    box, n = WORKLOADS[name]
+    p = sog.plan_parameters(box, n, tol, prec)
+    Lx, Ly, Lz = box
+    # the cut-off fits the periodic cell (minimum image in x, y)
+    assert 0 < p["rc"] <= 0.5 * min(Lx, Ly) + 1e-12
+    # Table-1 rows: b in (1, 2]; the decomposition has M >= m
+    assert 1.0 < p["b"] <= 2.0 and p["M"] >= p["m"] >= -1
+    sigma = p["rc"] / p["r0"]
+    s = [math.sqrt(2.0) * sigma * p["b"] ** l for l in range(p["M"] + 1)]  # s_l = sqrt(2) b^l sigma
+    if p["m"] >= 0:
+        I, Izs, Pw = p["mid_I"], p["mid_Izs"], p["mid_Pw"][0]
+        # mid range: the split m = max{l : s_l <= eta Lz} with the planner's eta <= 2;
+        # grids even, FFT-smooth, window odd
+        assert s[p["m"]] <= 2.0 * Lz * (1 + 1e-12)
+        assert I[0] % 2 == 0 and I[1] % 2 == 0 and Izs % 2 == 0
+        assert _smooth(I[0]) and _smooth(I[1]) and _smooth(Izs // 2)
+        assert Pw % 2 == 1 and 3 <= Pw <= 31
+        # the padded z grid holds the box, the window support and some padding
+        hz = Lz / I[2]
+        assert Izs * hz >= Lz + (Pw - 1) * hz
+        # the grid resolves the narrowest mid-range Gaussian: exp(-(s0 pi / (2 h))^2) < tol
+        h = max(Lx / I[0], Ly / I[1], hz)
+        assert math.exp(-(s[0] * math.pi / (2 * h)) ** 2) < tol
+    if p["m"] < p["M"]:
+        assert 1 <= p["long_P"] <= 64
+        assert p["long_form"] in (_lib.SOG_LONG_DIRECT, _lib.SOG_LONG_FFT)
+        if p["long_form"] == _lib.SOG_LONG_DIRECT:
+            assert p["long_nk"][0] >= 0 and p["long_nk"][1] >= 0
+        else:
+            assert _smooth(p["long_I"][0]) and _smooth(p["long_I"][1]) and p["long_Pw"][0] % 2 == 1
+
+
+def test_resolve_is_deterministic_and_respects_overrides():
+    a = sog.plan_parameters((20, 20, 20), 1000, 1e-6, "fp64")
+    b = sog.plan_parameters((20, 20, 20), 1000, 1e-6, "fp64")
+    assert a == b
+    c = sog.plan_parameters((20, 20, 20), 1000, 1e-6, "fp64",
+                            dict(mid_I=[32, 32, 32], mid_Izs=80, mid_Pw=[9, 9, 9]))
+    assert c["mid_I"] == [32, 32, 32] and c["mid_Izs"] == 80 and c["mid_Pw"] == [9, 9, 9]
+
+
+def test_tighter_tolerance_refines():
+    lo = sog.plan_parameters((100, 100, 100), 1000000, 1e-4, "fp64")
+    hi = sog.plan_parameters((100, 100, 100), 1000000, 1e-8, "fp64")
+    assert hi["b"] <= lo["b"]
+    assert hi["mid_Pw"][0] >= lo["mid_Pw"][0]

@@ -1,0 +1,94 @@
+"""Full-size workloads on the GPU, at the planner's own parameters and in the launch
+configuration the benchmark times (device pointers, torch's current stream).
+
+* sampled targets against tests/golden/<workload>_targets.txt (the oracle's exact SOG
+  sum at a 7e-10 decomposition, written by tests/golden/make_golden.py): relative L-inf
+  of the potential and of the force over the samples within the requested tolerance;
+* properties that hold at any size: U = 1/2 sum q phi, the float32-bulk and float64
+  forms agree within the tolerance, sum_i F_i is small against sum_i |F_i|, and a
+  periodic shift of all x, y coordinates leaves the result unchanged within tol.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = 1e-4
+
+
+def _golden(name):
+    d = np.loadtxt(os.path.join(HERE, "golden", f"{name}_targets.txt"), comments="#")
+    return d[:, 0].astype(np.int64), d[:, 1], d[:, 2:5]
+
+
+def _device_solve(name, precision, x=None, q=None):
+    import torch
+    import paper_2412_04595_amd as sog
+    if x is None:
+        x, q, box = workloads.named(name)
+    else:
+        box = workloads.NAMED[name][1]
+    xt = torch.from_numpy(x).cuda()
+    qt = torch.from_numpy(q).cuda()
+    s = sog.Solver(box, len(q), TOL, precision=precision, on_device=True, check_inputs=True)
+    U, phi, F = s(xt, qt)
+    torch.cuda.synchronize()
+    info = s.info()
+    s.close()
+    return U, phi.cpu().numpy(), F.cpu().numpy(), info
+
+
+def _sample_errors(name, phi, F, q):
+    idx, rphi, rgrad = _golden(name)
+    rF = -q[idx, None] * rgrad
+    ephi = np.max(np.abs(phi[idx] - rphi)) / np.max(np.abs(rphi))
+    eF = np.max(np.abs(F[idx] - rF)) / np.max(np.abs(rF))
+    return ephi, eF
+
+
+CASES = [("cube_1e6", "fp32"), ("cube_1e6", "fp64"), ("slab_1e6", "fp32"), ("tall_1e6", "fp32"),
+         ("layered_2e5", "fp32"), ("layered_2e5", "fp64")]
+
+
+@pytest.mark.parametrize("name,precision", CASES)
+def test_sampled_targets_meet_tolerance(name, precision):
+    print(f"[gpu] full size {name} {precision}", flush=True)
+    x, q, box = workloads.named(name)
+    U, phi, F, info = _device_solve(name, precision, x, q)
+    ephi, eF = _sample_errors(name, phi, F, q)
+    print(f"    rc={info['rc']:.3f} m={info['m']} M={info['M']} I={info['mid_I']} Pw={info['mid_Pw'][0]} "
+          f"long={info['long_form']} P={info['long_P']}: phi {ephi:.2e} F {eF:.2e}", flush=True)
+    assert ephi < TOL and eF < TOL
+    assert abs(U - 0.5 * float(q @ phi)) <= 1e-10 * float(np.sum(np.abs(q * phi)))
+    Ftot = np.abs(F.sum(axis=0))
+    assert np.all(Ftot <= TOL * np.sum(np.abs(F), axis=0))
+
+
+def test_fp32_bulk_matches_fp64_at_full_size():
+    name = "cube_1e6"
+    x, q, box = workloads.named(name)
+    print(f"[gpu] fp32 vs fp64 {name}", flush=True)
+    U32, p32, F32, _ = _device_solve(name, "fp32", x, q)
+    U64, p64, F64, _ = _device_solve(name, "fp64", x, q)
+    assert abs(U32 - U64) / abs(U64) < TOL
+    assert np.max(np.abs(p32 - p64)) / np.max(np.abs(p64)) < TOL
+    assert np.max(np.abs(F32 - F64)) / np.max(np.abs(F64)) < TOL
+
+
+def test_periodic_shift_invariance():
+    name = "layered_2e5"
+    x, q, box = workloads.named(name)
+    print(f"[gpu] shift invariance {name}", flush=True)
+    U0, p0, F0, _ = _device_solve(name, "fp64", x, q)
+    xs = x.copy()
+    xs[:, 0] += 0.37 * box[0] + 3.0   # not wrapped: the solver wraps x, y itself
+    xs[:, 1] -= 1.7 * box[1]
+    U1, p1, F1, _ = _device_solve(name, "fp64", xs, q)
+    assert abs(U1 - U0) / abs(U0) < TOL
+    assert np.max(np.abs(p1 - p0)) / np.max(np.abs(p0)) < TOL
+    assert np.max(np.abs(F1 - F0)) / np.max(np.abs(F0)) < TOL
