@@ -112,8 +112,7 @@ sog_status build_plan(Plan& p) {
     }
     A.get(ws.qsum, 2 * 8);
     A.get(ws.status, 4);
-    A.get(ws.parts_phi, 3 * n * rs);
-    A.get(ws.parts_grad, 9 * n * rs);
+    A.get(ws.parts, 12 * n * rs);
     A.get(ws.key, n * 4);
     A.get(ws.perm, n * 4);
     const int ncells = r.nc[0] * r.nc[1] * r.nc[2];
@@ -131,7 +130,7 @@ sog_status build_plan(Plan& p) {
         A.get(ws.mid_g, n * 16);
         A.get(ws.mid_u, n * 4 * rs);
         A.get(ws.grid, (size_t)r.I[0] * r.I[1] * r.Izs * rs);
-        A.get(ws.cgrid, (size_t)r.I[0] * r.I[1] * Kz * cs);
+        A.get(ws.cgrid, (size_t)r.I[0] * r.I[1] * cgrid_stride(r.Izs) * cs);
         A.get(ws.tw_x, r.I[0] * cs);
         A.get(ws.tw_y, r.I[1] * cs);
         A.get(ws.tw_z, (r.Izs / 2) * cs);
@@ -266,7 +265,7 @@ sog_status build_plan(Plan& p) {
 
 void free_plan(Plan& p) {
     Workspace& ws = p.ws;
-    void* ptrs[] = {ws.x, ws.q, ws.phi, ws.force, ws.energy, ws.qsum, ws.status, ws.parts_phi, ws.parts_grad,
+    void* ptrs[] = {ws.x, ws.q, ws.phi, ws.force, ws.energy, ws.qsum, ws.status, ws.parts,
                     ws.key, ws.perm, ws.scan_tmp, ws.cell_start, ws.cell_cursor, ws.near_orig,
                     ws.near_pos, ws.tile_start, ws.tile_cursor, ws.mid_g,
                     ws.mid_u, ws.grid, ws.cgrid, ws.tw_x, ws.tw_y, ws.tw_z, ws.tw_zpost, ws.mult_ax, ws.mult_ay,

@@ -26,8 +26,10 @@ __device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.x - b.x, 
 template <typename T>
 __device__ __forceinline__ cpx<T> cconj(cpx<T> a) { return {a.x, -a.y}; }
 
+// four reals on their natural 16 (float) / 32 (double) byte boundary, so a record moves
+// with one vector load or store
 template <typename T>
-struct vec4 {
+struct alignas(4 * sizeof(T)) vec4 {
     T x, y, z, w;
 };
 

@@ -17,15 +17,23 @@ constexpr int kMaxNearDeg = 63;   // Chebyshev degree of the near-field polynomi
 constexpr int kMaxMid = 96;       // max number of mid-range Gaussians (m + 1)
 constexpr int kSpreadStage = 32;  // particles whose window weights the gridding kernel stages at a time
 
-// LDS bytes of the mid-range gridding kernel: the tile plus its (P_w - 1) halo, 64 sink
-// slots for masked lanes, and per staged particle its y and z window weights (2 P_w), its
-// x weights rotated for the four plane groups (16), its offset from the grid point and
-// charge (4 reals), the four groups' plane offsets (16 bytes) and its x node (4 bytes).
-inline size_t spread_lds_bytes(size_t real_bytes, int Pw, int Bx, int By, int Bz) {
+// LDS layout of the mid-range gridding kernel: the tile plus its (P_w - 1) halo, 64 sink
+// slots for masked lanes, and per staged particle its y and z window weights (2 P_w) and
+// its x weights rotated for the four plane groups (16 reals); then, on a 32-byte boundary,
+// the staged particles' offsets from their grid points and charges (real4 each), the four
+// groups' plane offsets (int4) and the x nodes (int).
+inline size_t spread_lds_offset_records(size_t real_bytes, int Pw, int Bx, int By, int Bz) {
     const size_t tot = (size_t)(Bx + Pw - 1) * (By + Pw - 1) * (Bz + Pw - 1);
-    const size_t reals = tot + 64 + (size_t)kSpreadStage * (2 * Pw + 16 + 4);
-    return (reals * real_bytes + 15) / 16 * 16 + (size_t)kSpreadStage * 20;
+    return ((tot + 64 + (size_t)kSpreadStage * (2 * Pw + 16)) * real_bytes + 31) / 32 * 32;
 }
+inline size_t spread_lds_bytes(size_t real_bytes, int Pw, int Bx, int By, int Bz) {
+    return spread_lds_offset_records(real_bytes, Pw, Bx, By, Bz) + (size_t)kSpreadStage * (4 * real_bytes + 20);
+}
+
+// Row stride (complex entries) of the mid-range half spectrum: I_z*/2 + 1 rounded up to a
+// multiple of 16, so that the 16-entry row segments the y and x passes move are whole
+// 128-byte lines.
+inline int cgrid_stride(int Izs) { return ((Izs / 2 + 1) + 15) / 16 * 16; }
 
 // A 1D FFT of length n as a product of small radices (Stockham, natural order).
 struct FFTFactors {
@@ -100,9 +108,8 @@ struct Workspace {
     // validation: [0] sum q, [1] sum |q| (double), status bits in an int
     double* qsum = nullptr;
     int* status = nullptr;
-    // per-part results in the particle's own order: 3 x n potentials, 3 x n x 3 gradients
-    void* parts_phi = nullptr;
-    void* parts_grad = nullptr;
+    // per-part results in the particles' own order, one record per particle and part
+    void* parts = nullptr;      // 3 x n x real4 (phi, dphi/dx, dphi/dy, dphi/dz): near, mid, long
     // counting sorts
     int* key = nullptr;       // n
     int* perm = nullptr;      // n
@@ -118,7 +125,7 @@ struct Workspace {
     int* mid_g = nullptr;       // n x int4 (grid point of each sorted particle, original index)
     void* mid_u = nullptr;      // n x real4 (offset from the grid point in units of h, q)
     void* grid = nullptr;       // I_x I_y I_z* reals
-    void* cgrid = nullptr;      // I_x I_y (I_z*/2 + 1) complex
+    void* cgrid = nullptr;      // I_x I_y rows of I_z*/2 + 1 complex, row stride cgrid_stride(I_z*)
     void* tw_x = nullptr;       // twiddles e^{-2 pi i t/n} for each FFT length
     void* tw_y = nullptr;
     void* tw_z = nullptr;       // length I_z*/2
@@ -186,6 +193,9 @@ hipError_t launch_fill_int(int* p, int value, int64_t n, hipStream_t s);
 hipError_t launch_fill_bytes_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_prep(Plan& p, const double* x, const double* q);
 hipError_t launch_counting_sort(Plan& p, const int* key, int n, int nbins, int* start, int* cursor, int* perm);
+// zero the counts (nbins + 1) and cursors (nbins) of a counting sort whose histogram the
+// caller's key kernel builds; launch_exclusive_scan then turns counts into starts
+hipError_t launch_sort_clear(Plan& p, int nbins, int* start, int* cursor);
 hipError_t launch_exclusive_scan(Plan& p, int* data, int nbins);  // in place, data has nbins+1 entries
 hipError_t launch_near(Plan& p, const double* x, const double* q);
 hipError_t launch_mid(Plan& p, const double* x, const double* q);

@@ -195,7 +195,7 @@ int lines_per_block(int n) {
 // 1. real-to-complex along z for W lines per block.  m = I_z*/2.
 template <typename T>
 __global__ __launch_bounds__(kFFTThreads) void k_fft_z_r2c(const T* __restrict__ grid, cpx<T>* __restrict__ cg,
-                                                           int nlines, int Izs, int Kz, int W, FFTDev f,
+                                                           int nlines, int Izs, int Kz, int Kzs, int W, FFTDev f,
                                                            const cpx<T>* __restrict__ tw,
                                                            const cpx<T>* __restrict__ twpost) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_z_r2c(const T* __restrict__
             const cpx<T> e = {(zk.x + zmk.x) * (T)0.5, (zk.y + zmk.y) * (T)0.5};
             const cpx<T> dd = csub(zk, zmk);
             const cpx<T> o = {dd.y * (T)0.5, -dd.x * (T)0.5};  // (zk - zmk) / (2i)
-            cg[(size_t)line * Kz + k] = cadd(e, cmul(twpost[k], o));
+            cg[(size_t)line * Kzs + k] = cadd(e, cmul(twpost[k], o));
         }
     }
 }
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_z_r2c(const T* __restrict__
 // 5. complex-to-real along z (unnormalised inverse).
 template <typename T>
 __global__ __launch_bounds__(kFFTThreads) void k_fft_z_c2r(const cpx<T>* __restrict__ cg, T* __restrict__ grid,
-                                                           int nlines, int Izs, int Kz, int W, FFTDev f,
+                                                           int nlines, int Izs, int Kz, int Kzs, int W, FFTDev f,
                                                            const cpx<T>* __restrict__ tw,
                                                            const cpx<T>* __restrict__ twpost) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_z_c2r(const cpx<T>* __restr
     load_twiddles(twl, tw, m);
     for (int w = 0; w < W; ++w) {
         const int line = line0 + w;
-        const cpx<T>* row = cg + (size_t)min(line, nlines - 1) * Kz;
+        const cpx<T>* row = cg + (size_t)min(line, nlines - 1) * Kzs;
         for (int k = threadIdx.x; k < m; k += kFFTThreads) {
             const cpx<T> xk = row[k];
             const cpx<T> xmk = cconj(row[m - k]);
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_z_c2r(const cpx<T>* __restr
 
 // 2./4. complex FFT along y for (x, a batch of W consecutive k_z)
 template <typename T, int SIGN>
-__global__ __launch_bounds__(kFFTThreads) void k_fft_y(cpx<T>* __restrict__ cg, int Ix, int Iy, int Kz, int W,
+__global__ __launch_bounds__(kFFTThreads) void k_fft_y(cpx<T>* __restrict__ cg, int Ix, int Iy, int Kz, int Kzs, int W,
                                                        FFTDev f, const cpx<T>* __restrict__ tw) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -270,16 +270,16 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_y(cpx<T>* __restrict__ cg, 
     if (ix >= Ix) return;
     const int lw = __ffs(W) - 1;
     load_twiddles(twl, tw, Iy);
-    cpx<T>* base = cg + (size_t)ix * Iy * Kz + kz0;
+    cpx<T>* base = cg + (size_t)ix * Iy * Kzs + kz0;
     for (int idx = threadIdx.x; idx < Iy * W; idx += kFFTThreads) {
         const int w = idx & (W - 1), iy = idx >> lw;
-        A[idx] = (kz0 + w < Kz) ? base[(size_t)iy * Kz + w] : cpx<T>{0, 0};
+        A[idx] = (kz0 + w < Kz) ? base[(size_t)iy * Kzs + w] : cpx<T>{0, 0};
     }
     __syncthreads();
     lds_fft<T, SIGN>(A, twl, W, f);
     for (int idx = threadIdx.x; idx < Iy * W; idx += kFFTThreads) {
         const int w = idx & (W - 1), iy = idx >> lw;
-        if (kz0 + w < Kz) base[(size_t)iy * Kz + w] = A[idx];
+        if (kz0 + w < Kz) base[(size_t)iy * Kzs + w] = A[idx];
     }
 }
 
@@ -287,7 +287,8 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_y(cpx<T>* __restrict__ cg, 
 // sum_l c_l ax_l(k_x) ay_l(k_y) az_l(k_z): the block's (k_y, k_z) factors and ax are
 // staged in LDS.
 template <typename T>
-__global__ __launch_bounds__(kFFTThreads) void k_fft_x_scale(cpx<T>* __restrict__ cg, int Ix, int Iy, int Kz, int W,
+__global__ __launch_bounds__(kFFTThreads) void k_fft_x_scale(cpx<T>* __restrict__ cg, int Ix, int Iy, int Kz, int Kzs,
+                                                             int W,
                                                              FFTDev f, const cpx<T>* __restrict__ tw, int nl,
                                                              const T* __restrict__ ax, const T* __restrict__ ay,
                                                              const T* __restrict__ az, const T* __restrict__ cl) {
@@ -300,8 +301,8 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_scale(cpx<T>* __restrict_
     const int iy = blockIdx.x / nkb, kz0 = (blockIdx.x % nkb) * W;
     if (iy >= Iy) return;
     const int lw = __ffs(W) - 1;
-    const size_t stride = (size_t)Iy * Kz;
-    cpx<T>* base = cg + (size_t)iy * Kz + kz0;
+    const size_t stride = (size_t)Iy * Kzs;
+    cpx<T>* base = cg + (size_t)iy * Kzs + kz0;
     load_twiddles(twl, tw, Ix);
     for (int idx = threadIdx.x; idx < Ix * W; idx += kFFTThreads) {
         const int w = idx & (W - 1), ix = idx >> lw;
@@ -365,7 +366,7 @@ template <typename T>
 hipError_t run_fft_mid(Plan& p) {
     const Resolved& r = p.r;
     Workspace& ws = p.ws;
-    const int Ix = r.I[0], Iy = r.I[1], Izs = r.Izs, Kz = Izs / 2 + 1, m = Izs / 2;
+    const int Ix = r.I[0], Iy = r.I[1], Izs = r.Izs, Kz = Izs / 2 + 1, m = Izs / 2, Kzs = cgrid_stride(Izs);
     const int nlines = Ix * Iy;
     const size_t ce = sizeof(cpx<T>);
     const size_t budget = 65536;
@@ -381,7 +382,7 @@ hipError_t run_fft_mid(Plan& p) {
         int t = timer_id(p, "fft_z_fwd");
         timer_begin(p, t);
         k_fft_z_r2c<T><<<(nlines + Wz - 1) / Wz, kFFTThreads, ldsz, p.stream>>>(
-            (const T*)ws.grid, (cpx<T>*)ws.cgrid, nlines, Izs, Kz, Wz, to_dev(p.fz), (const cpx<T>*)ws.tw_z,
+            (const T*)ws.grid, (cpx<T>*)ws.cgrid, nlines, Izs, Kz, Kzs, Wz, to_dev(p.fz), (const cpx<T>*)ws.tw_z,
             (const cpx<T>*)ws.tw_zpost);
         timer_end(p, t);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -394,7 +395,7 @@ hipError_t run_fft_mid(Plan& p) {
     {
         int t = timer_id(p, "fft_y_fwd");
         timer_begin(p, t);
-        k_fft_y<T, -1><<<nby, kFFTThreads, ldsy, p.stream>>>((cpx<T>*)ws.cgrid, Ix, Iy, Kz, Wy, to_dev(p.fy),
+        k_fft_y<T, -1><<<nby, kFFTThreads, ldsy, p.stream>>>((cpx<T>*)ws.cgrid, Ix, Iy, Kz, Kzs, Wy, to_dev(p.fy),
                                                              (const cpx<T>*)ws.tw_y);
         timer_end(p, t);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -409,7 +410,7 @@ hipError_t run_fft_mid(Plan& p) {
         int nb = Iy * ((Kz + W - 1) / W);
         int t = timer_id(p, "fft_x_scale");
         timer_begin(p, t);
-        k_fft_x_scale<T><<<nb, kFFTThreads, lds, p.stream>>>((cpx<T>*)ws.cgrid, Ix, Iy, Kz, W, to_dev(p.fx),
+        k_fft_x_scale<T><<<nb, kFFTThreads, lds, p.stream>>>((cpx<T>*)ws.cgrid, Ix, Iy, Kz, Kzs, W, to_dev(p.fx),
                                                              (const cpx<T>*)ws.tw_x, nl, (const T*)ws.mult_ax,
                                                              (const T*)ws.mult_ay, (const T*)ws.mult_az,
                                                              (const T*)ws.mult_c);
@@ -420,7 +421,7 @@ hipError_t run_fft_mid(Plan& p) {
     {
         int t = timer_id(p, "fft_y_inv");
         timer_begin(p, t);
-        k_fft_y<T, +1><<<nby, kFFTThreads, ldsy, p.stream>>>((cpx<T>*)ws.cgrid, Ix, Iy, Kz, Wy, to_dev(p.fy),
+        k_fft_y<T, +1><<<nby, kFFTThreads, ldsy, p.stream>>>((cpx<T>*)ws.cgrid, Ix, Iy, Kz, Kzs, Wy, to_dev(p.fy),
                                                              (const cpx<T>*)ws.tw_y);
         timer_end(p, t);
         if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -430,7 +431,7 @@ hipError_t run_fft_mid(Plan& p) {
         int t = timer_id(p, "fft_z_inv");
         timer_begin(p, t);
         k_fft_z_c2r<T><<<(nlines + Wz - 1) / Wz, kFFTThreads, ldsz, p.stream>>>(
-            (const cpx<T>*)ws.cgrid, (T*)ws.grid, nlines, Izs, Kz, Wz, to_dev(p.fz), (const cpx<T>*)ws.tw_z,
+            (const cpx<T>*)ws.cgrid, (T*)ws.grid, nlines, Izs, Kz, Kzs, Wz, to_dev(p.fz), (const cpx<T>*)ws.tw_z,
             (const cpx<T>*)ws.tw_zpost);
         timer_end(p, t);
         if ((e = hipGetLastError()) != hipSuccess) return e;

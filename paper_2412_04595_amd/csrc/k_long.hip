@@ -208,8 +208,7 @@ struct EvalArgs {
     double L[3];
     int nkx, nky, nh, P;
     const cpx<real>* acoef;
-    real* pphi;   // part 2
-    real* pgrad;
+    vec4<real>* part;  // long part of each particle: phi, grad
 };
 
 template <typename real>
@@ -285,10 +284,7 @@ __global__ void k_long_eval(EvalArgs<real> a) {
         }
         phy = cmul(phy, e2);
     }
-    a.pphi[i] = phi;
-    a.pgrad[3 * i] = gx;
-    a.pgrad[3 * i + 1] = gy;
-    a.pgrad[3 * i + 2] = gz * (real)(2.0 / a.L[2]);
+    a.part[i] = vec4<real>{phi, gx, gy, gz * (real)(2.0 / a.L[2])};
 }
 
 template <typename real>
@@ -344,8 +340,7 @@ hipError_t run_long_direct(Plan& p, const double* x, const double* q) {
     ea.nh = nh;
     ea.P = P;
     ea.acoef = (const cpx<real>*)ws.long_a;
-    ea.pphi = (real*)ws.parts_phi + 2 * r.n;
-    ea.pgrad = (real*)ws.parts_grad + 6 * r.n;
+    ea.part = (vec4<real>*)ws.parts + 2 * r.n;
     int B = 256;
     while (B > 64 && (size_t)nh * P * sizeof(cpx<real>) + 2 * (size_t)P * B * sizeof(real) > 65536) B >>= 1;
     size_t lds2 = (size_t)nh * P * sizeof(cpx<real>) + 2 * (size_t)P * B * sizeof(real);

@@ -216,8 +216,7 @@ struct L2GatherArgs {
     const vec4<real>* up;
     const int* tstart;
     const cpx<real>* grid;
-    real* pphi;
-    real* pgrad;
+    vec4<real>* part;  // long part of each particle: phi, grad
     int I[2], B[2], nt[2], ntiles, P;
     real S, inv_hw2, dcoef[2], area, dzf;
 };
@@ -292,10 +291,7 @@ __global__ __launch_bounds__(64) void k_l2_gather(L2GatherArgs<real> a) {
             gz += wx * s2;
         }
         const int i = g.w;
-        a.pphi[i] = a.area * phi;
-        a.pgrad[3 * i] = a.area * gx;
-        a.pgrad[3 * i + 1] = a.area * gy;
-        a.pgrad[3 * i + 2] = a.area * a.dzf * gz;
+        a.part[i] = vec4<real>{a.area * phi, a.area * gx, a.area * gy, a.area * a.dzf * gz};
     }
 }
 
@@ -328,8 +324,7 @@ hipError_t l2_spread_gather_pw(Plan& p, bool spread) {
         a.up = (const vec4<real>*)ws.l2_u;
         a.tstart = ws.l2_tile_start;
         a.grid = (const cpx<real>*)ws.l2_grid;
-        a.pphi = (real*)ws.parts_phi + 2 * r.n;
-        a.pgrad = (real*)ws.parts_grad + 6 * r.n;
+        a.part = (vec4<real>*)ws.parts + 2 * r.n;
         for (int d = 0; d < 2; ++d) {
             a.I[d] = r.I2[d];
             a.B[d] = r.B2[d];

@@ -47,20 +47,28 @@ __device__ __forceinline__ void grid_point(const MidGeom& g, double x, double y,
     }
 }
 
-__global__ void k_mid_key(const double* __restrict__ x, int n, MidGeom g, int* __restrict__ key) {
+// tile of every particle's nearest node, and the tile histogram of the counting sort
+__global__ void k_mid_key(const double* __restrict__ x, int n, MidGeom g, int* __restrict__ key,
+                          int* __restrict__ count) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         int a[3];
         double u[3];
         grid_point(g, x[3 * i], x[3 * i + 1], x[3 * i + 2], a, u);
-        key[i] = ((a[0] / g.B[0]) * g.nt[1] + a[1] / g.B[1]) * g.nt[2] + a[2] / g.B[2];
+        const int k = ((a[0] / g.B[0]) * g.nt[1] + a[1] / g.B[1]) * g.nt[2] + a[2] / g.B[2];
+        key[i] = k;
+        atomicAdd(&count[k], 1);
     }
 }
 
+// Scatter of the counting sort: each particle's grid point and offset record written at
+// its place in tile order (particles read in their own order).
 template <typename real>
 __global__ void k_mid_pack(const double* __restrict__ x, const double* __restrict__ q, int n, MidGeom g,
-                           const int* __restrict__ perm, int4* __restrict__ gp, vec4<real>* __restrict__ up) {
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-        int i = perm[p];
+                           const int* __restrict__ key, const int* __restrict__ start, int* __restrict__ cursor,
+                           int4* __restrict__ gp, vec4<real>* __restrict__ up) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int k = key[i];
+        const int p = start[k] + atomicAdd(&cursor[k], 1);
         int a[3];
         double u[3];
         grid_point(g, x[3 * i], x[3 * i + 1], x[3 * i + 2], a, u);
@@ -133,9 +141,9 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
     const int sink0 = tot;                         // 64 sink slots
     real* wyzs = halo + tot + 64;                  // kSpreadStage x 2 PW: wy, wz
     real* wxs = wyzs + kSpreadStage * 2 * PW;      // kSpreadStage x 16: q wx rotated per wave
-    vec4<real>* sup = reinterpret_cast<vec4<real>*>(wxs + kSpreadStage * 16);  // kSpreadStage: u, q
-    const size_t meta_off = (((size_t)tot + 64 + (size_t)kSpreadStage * (2 * PW + 16 + 4)) * sizeof(real) + 15) & ~(size_t)15;
-    int4* meta = reinterpret_cast<int4*>(smem_raw + meta_off);  // per wave: first plane offset, plane count
+    const size_t rec_off = ((((size_t)tot + 64 + (size_t)kSpreadStage * (2 * PW + 16)) * sizeof(real)) + 31) & ~(size_t)31;
+    vec4<real>* sup = reinterpret_cast<vec4<real>*>(smem_raw + rec_off);  // kSpreadStage: u, q
+    int4* meta = reinterpret_cast<int4*>(sup + kSpreadStage);  // per wave: first plane offset, plane count
     int* slx = reinterpret_cast<int*>(meta + kSpreadStage);      // x node of the particle in the block
     for (int k = threadIdx.x; k < tot + 64; k += kSpreadThreads) halo[k] = 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -276,8 +284,7 @@ struct GatherArgs {
     const vec4<real>* up;
     const int* tstart;
     const real* grid;
-    real* pphi;   // part 1 (n)
-    real* pgrad;  // part 1 (n x 3)
+    vec4<real>* part;  // mid part of each particle: phi, grad
     int I[3];
     int B[3];
     int nt[3];
@@ -361,10 +368,7 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs<real> a) {
             gz += wx * s2;
         }
         const int i = g.w;
-        a.pphi[i] = a.vol * phi;
-        a.pgrad[3 * i] = a.vol * gx;
-        a.pgrad[3 * i + 1] = a.vol * gy;
-        a.pgrad[3 * i + 2] = a.vol * gz;
+        a.part[i] = vec4<real>{a.vol * phi, a.vol * gx, a.vol * gy, a.vol * gz};
     }
 }
 
@@ -398,8 +402,7 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         a.up = (const vec4<real>*)ws.mid_u;
         a.tstart = ws.tile_start;
         a.grid = (const real*)ws.grid;
-        a.pphi = (real*)ws.parts_phi + r.n;
-        a.pgrad = (real*)ws.parts_grad + 3 * r.n;
+        a.part = (vec4<real>*)ws.parts + r.n;
         a.I[0] = r.I[0]; a.I[1] = r.I[1]; a.I[2] = r.Izs;
         for (int d = 0; d < 3; ++d) {
             a.B[d] = r.B[d];
@@ -455,10 +458,12 @@ hipError_t run_mid_prepare(Plan& p, const double* x, const double* q) {
     MidGeom g = mid_geom(r);
     const int ntiles = r.ntile[0] * r.ntile[1] * r.ntile[2];
     const int blocks = std::min((n + 255) / 256, 8192);
-    k_mid_key<<<blocks, 256, 0, p.stream>>>(x, n, g, ws.key);
-    hipError_t e = launch_counting_sort(p, ws.key, n, ntiles, ws.tile_start, ws.tile_cursor, ws.perm);
+    hipError_t e = launch_sort_clear(p, ntiles, ws.tile_start, ws.tile_cursor);
     if (e != hipSuccess) return e;
-    k_mid_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.perm, (int4*)ws.mid_g, (vec4<real>*)ws.mid_u);
+    k_mid_key<<<blocks, 256, 0, p.stream>>>(x, n, g, ws.key, ws.tile_start);
+    if ((e = launch_exclusive_scan(p, ws.tile_start, ntiles + 1)) != hipSuccess) return e;
+    k_mid_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.key, ws.tile_start, ws.tile_cursor,
+                                                    (int4*)ws.mid_g, (vec4<real>*)ws.mid_u);
     return hipGetLastError();
 }
 

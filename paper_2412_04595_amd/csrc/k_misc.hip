@@ -124,17 +124,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int* data, int len, c
 }
 
 template <typename real>
-__global__ void k_combine(const real* __restrict__ pphi, const real* __restrict__ pgrad, const double* __restrict__ q,
+__global__ void k_combine(const vec4<real>* __restrict__ part, const double* __restrict__ q,
                           int64_t n, double self_coeff, double* __restrict__ phi, double* __restrict__ force,
                           double* __restrict__ red) {
     __shared__ double lds[16];
     double e = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double qi = q[i];
-        double ph = (double)pphi[i] + (double)pphi[n + i] + (double)pphi[2 * n + i] - qi * self_coeff;
-        double g[3];
-        for (int d = 0; d < 3; ++d)
-            g[d] = (double)pgrad[3 * i + d] + (double)pgrad[3 * (n + i) + d] + (double)pgrad[3 * (2 * n + i) + d];
+        const vec4<real> a = part[i], b = part[n + i], c = part[2 * n + i];
+        double ph = (double)a.x + (double)b.x + (double)c.x - qi * self_coeff;
+        const double g[3] = {(double)a.y + (double)b.y + (double)c.y, (double)a.z + (double)b.z + (double)c.z,
+                             (double)a.w + (double)b.w + (double)c.w};
         if (phi) phi[i] = ph;
         if (force)
             for (int d = 0; d < 3; ++d) force[3 * i + d] = -qi * g[d];
@@ -154,12 +154,16 @@ __global__ void k_energy_final(const double* __restrict__ red, int nb, double* _
 }
 
 template <typename real>
-__global__ void k_parts_out(const real* __restrict__ pphi, const real* __restrict__ pgrad, int64_t n,
-                            double* __restrict__ phi_parts, double* __restrict__ grad_parts) {
+__global__ void k_parts_out(const vec4<real>* __restrict__ part, int64_t n, double* __restrict__ phi_parts,
+                            double* __restrict__ grad_parts) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < 3 * n; i += (int64_t)gridDim.x * blockDim.x) {
-        if (phi_parts) phi_parts[i] = (double)pphi[i];
-        if (grad_parts)
-            for (int d = 0; d < 3; ++d) grad_parts[3 * i + d] = (double)pgrad[3 * i + d];
+        const vec4<real> v = part[i];
+        if (phi_parts) phi_parts[i] = (double)v.x;
+        if (grad_parts) {
+            grad_parts[3 * i] = (double)v.y;
+            grad_parts[3 * i + 1] = (double)v.z;
+            grad_parts[3 * i + 2] = (double)v.w;
+        }
     }
 }
 
@@ -219,15 +223,21 @@ hipError_t launch_counting_sort(Plan& p, const int* key, int n, int nbins, int* 
     return hipGetLastError();
 }
 
+hipError_t launch_sort_clear(Plan& p, int nbins, int* start, int* cursor) {
+    hipError_t e = launch_fill_int(start, 0, (int64_t)nbins + 1, p.stream);
+    if (e != hipSuccess) return e;
+    return launch_fill_int(cursor, 0, nbins, p.stream);
+}
+
 hipError_t launch_combine(Plan& p, const double* q, double* phi, double* force, double* energy) {
     int nb = p.ws.red_blocks;
     int t = timer_id(p, "combine");
     timer_begin(p, t);
     if (p.r.prec == SOG_PREC_FP64)
-        k_combine<double><<<nb, 256, 0, p.stream>>>((const double*)p.ws.parts_phi, (const double*)p.ws.parts_grad, q,
+        k_combine<double><<<nb, 256, 0, p.stream>>>((const vec4<double>*)p.ws.parts, q,
                                                      p.r.n, p.r.self_coeff, phi, force, p.ws.red);
     else
-        k_combine<float><<<nb, 256, 0, p.stream>>>((const float*)p.ws.parts_phi, (const float*)p.ws.parts_grad, q,
+        k_combine<float><<<nb, 256, 0, p.stream>>>((const vec4<float>*)p.ws.parts, q,
                                                     p.r.n, p.r.self_coeff, phi, force, p.ws.red);
     if (energy) k_energy_final<<<1, 256, 0, p.stream>>>(p.ws.red, nb, energy);
     timer_end(p, t);
@@ -237,20 +247,17 @@ hipError_t launch_combine(Plan& p, const double* q, double* phi, double* force, 
 hipError_t launch_parts_out(Plan& p, double* phi_parts, double* grad_parts) {
     if (p.r.prec == SOG_PREC_FP64)
         k_parts_out<double><<<grid_for(3 * p.r.n, 256), 256, 0, p.stream>>>(
-            (const double*)p.ws.parts_phi, (const double*)p.ws.parts_grad, p.r.n, phi_parts, grad_parts);
+            (const vec4<double>*)p.ws.parts, p.r.n, phi_parts, grad_parts);
     else
         k_parts_out<float><<<grid_for(3 * p.r.n, 256), 256, 0, p.stream>>>(
-            (const float*)p.ws.parts_phi, (const float*)p.ws.parts_grad, p.r.n, phi_parts, grad_parts);
+            (const vec4<float>*)p.ws.parts, p.r.n, phi_parts, grad_parts);
     return hipGetLastError();
 }
 
 hipError_t launch_zero_parts(Plan& p, int part) {
     size_t rs = (p.r.prec == SOG_PREC_FP64) ? 8 : 4;
-    char* ph = (char*)p.ws.parts_phi + (size_t)part * p.r.n * rs;
-    char* gr = (char*)p.ws.parts_grad + (size_t)part * p.r.n * 3 * rs;
-    hipError_t e = launch_fill_bytes_zero(ph, p.r.n * rs, p.stream);
-    if (e != hipSuccess) return e;
-    return launch_fill_bytes_zero(gr, 3 * p.r.n * rs, p.stream);
+    char* pp = (char*)p.ws.parts + (size_t)part * p.r.n * 4 * rs;
+    return launch_fill_bytes_zero(pp, p.r.n * 4 * rs, p.stream);
 }
 
 }  // namespace sog

@@ -36,7 +36,9 @@ __device__ __forceinline__ void cell_of(const NearGeom& g, double xw, double yw,
     }
 }
 
-__global__ void k_near_key(const double* __restrict__ x, int n, NearGeom g, int* __restrict__ key) {
+// cell of every particle, and the cell histogram of the counting sort
+__global__ void k_near_key(const double* __restrict__ x, int n, NearGeom g, int* __restrict__ key,
+                           int* __restrict__ count) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double xw = wrap_periodic(x[3 * i], g.L[0]), yw = wrap_periodic(x[3 * i + 1], g.L[1]);
         double z = x[3 * i + 2];
@@ -45,15 +47,21 @@ __global__ void k_near_key(const double* __restrict__ x, int n, NearGeom g, int*
         if (!isfinite(z)) z = 0;
         int c[3];
         cell_of(g, xw, yw, z, c);
-        key[i] = (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
+        const int k = (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
+        key[i] = k;
+        atomicAdd(&count[k], 1);
     }
 }
 
+// Scatter of the counting sort, writing each particle's packed record at its place in
+// cell order (particles read in their own order, records written once).
 template <typename real>
 __global__ void k_near_pack(const double* __restrict__ x, const double* __restrict__ q, int n, NearGeom g,
-                            const int* __restrict__ perm, vec4<real>* __restrict__ pos, int* __restrict__ orig) {
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-        int i = perm[p];
+                            const int* __restrict__ key, const int* __restrict__ start, int* __restrict__ cursor,
+                            vec4<real>* __restrict__ pos, int* __restrict__ orig) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int k = key[i];
+        const int p = start[k] + atomicAdd(&cursor[k], 1);
         double xw = wrap_periodic(x[3 * i], g.L[0]), yw = wrap_periodic(x[3 * i + 1], g.L[1]);
         double z = x[3 * i + 2];
         double qq = q[i];
@@ -78,8 +86,7 @@ struct NearArgs {
     const vec4<real>* __restrict__ pos;
     const int* __restrict__ orig;
     const int* __restrict__ cell_start;
-    real* __restrict__ pphi;   // part 0 potentials (n)
-    real* __restrict__ pgrad;  // part 0 gradients (n x 3)
+    vec4<real>* __restrict__ part;  // near part of each particle: phi, grad
     int nitems;                // work units: columns x z-blocks
     int nbz;                   // z-blocks per column
     int zc;                    // cells per z-block
@@ -261,10 +268,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
         while (__ballot(tp != hd)) chunk();
         if (act) {
             const int i = a.orig[p];
-            a.pphi[i] = phi;
-            a.pgrad[3 * i] = gx;
-            a.pgrad[3 * i + 1] = gy;
-            a.pgrad[3 * i + 2] = gz;
+            a.part[i] = vec4<real>{phi, gx, gy, gz};
         }
     }
 }
@@ -305,10 +309,12 @@ hipError_t run_near(Plan& p, const double* x, const double* q) {
     int t = timer_id(p, "near_sort");
     timer_begin(p, t);
     const int blocks = std::min((n + 255) / 256, 8192);
-    k_near_key<<<blocks, 256, 0, p.stream>>>(x, n, g, ws.key);
-    hipError_t e = launch_counting_sort(p, ws.key, n, ncells, ws.cell_start, ws.cell_cursor, ws.perm);
+    hipError_t e = launch_sort_clear(p, ncells, ws.cell_start, ws.cell_cursor);
     if (e != hipSuccess) return e;
-    k_near_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.perm, (vec4<real>*)ws.near_pos, ws.near_orig);
+    k_near_key<<<blocks, 256, 0, p.stream>>>(x, n, g, ws.key, ws.cell_start);
+    if ((e = launch_exclusive_scan(p, ws.cell_start, ncells + 1)) != hipSuccess) return e;
+    k_near_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.key, ws.cell_start, ws.cell_cursor,
+                                                     (vec4<real>*)ws.near_pos, ws.near_orig);
     timer_end(p, t);
     NearArgs<real> a;
     a.pos = (const vec4<real>*)ws.near_pos;
@@ -317,8 +323,7 @@ hipError_t run_near(Plan& p, const double* x, const double* q) {
     a.nbz = (r.nc[2] + r.near_zc - 1) / r.near_zc;
     a.nitems = r.nc[0] * r.nc[1] * a.nbz;
     a.cell_start = ws.cell_start;
-    a.pphi = (real*)ws.parts_phi;
-    a.pgrad = (real*)ws.parts_grad;
+    a.part = (vec4<real>*)ws.parts;
     for (int d = 0; d < 3; ++d) {
         a.nc[d] = r.nc[d];
         a.ch[d] = (real)r.ch[d];
