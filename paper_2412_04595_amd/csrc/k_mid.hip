@@ -93,7 +93,16 @@ __device__ __forceinline__ real win(int o, real u, real S, real inv_hw2) {
 }
 
 constexpr int kSpreadThreads = 256;  // 4 waves, one per group of x planes
-constexpr int kFlushILP = 8;
+constexpr int kHaloILP = 24;  // x planes of a halo column loaded or added in flight together
+
+// a halo node index into [0, n): it lies in [-n, 3n), since the halo half-width is below
+// n (I >= 2 P_w) and a tile's first node plus its edge is below 2n
+__device__ __forceinline__ int wrap_once(int i, int n) {
+    if (i < 0) i += n;
+    if (i >= n) i -= n;
+    if (i >= n) i -= n;
+    return i;
+}
 
 template <typename real>
 struct SpreadArgs {
@@ -255,25 +264,26 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
     }
     __syncthreads();
     // add the block into the grid: each item is one (y, z) column of the block and a run of
-    // kFlushILP x planes, whose atomic adds are in flight together (only nodes some window
-    // reached are touched)
-    const int nch = (HX + kFlushILP - 1) / kFlushILP;
+    // up to kHaloILP x planes, whose atomic adds are in flight together (only nodes some
+    // window reached are touched)
+    const int nch = (HX + kHaloILP - 1) / kHaloILP;
+    const size_t plane = (size_t)a.I[1] * a.I[2];
     for (int it = threadIdx.x; it < HYZ * nch; it += kSpreadThreads) {
         const int c = it / HYZ, k = it - c * HYZ;
         const int ly = k / HZ, lz = k - ly * HZ;
         const int gz = z0 - HW + lz;
         if (gz < 0 || gz >= a.I[2]) continue;
-        const size_t colyz = (size_t)imod(y0 - HW + ly, a.I[1]) * a.I[2] + gz;
-        real v[kFlushILP];
-        size_t at[kFlushILP];
+        const size_t colyz = (size_t)wrap_once(y0 - HW + ly, a.I[1]) * a.I[2] + gz;
+        real v[kHaloILP];
+        size_t at[kHaloILP];
 #pragma unroll
-        for (int j = 0; j < kFlushILP; ++j) {
-            const int lx = c * kFlushILP + j;
+        for (int j = 0; j < kHaloILP; ++j) {
+            const int lx = c * kHaloILP + j;
             v[j] = (lx < HX) ? halo[lx * HYZ + k] : (real)0;
-            at[j] = (size_t)imod(x0 - HW + lx, a.I[0]) * a.I[1] * a.I[2] + colyz;
+            at[j] = (size_t)wrap_once(x0 - HW + lx, a.I[0]) * plane + colyz;
         }
 #pragma unroll
-        for (int j = 0; j < kFlushILP; ++j)
+        for (int j = 0; j < kHaloILP; ++j)
             if (v[j] != (real)0) atomicAdd(a.grid + at[j], v[j]);
     }
 }
@@ -307,27 +317,27 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs<real> a) {
     const int tz = t % a.nt[2], ty = (t / a.nt[2]) % a.nt[1], tx = t / (a.nt[2] * a.nt[1]);
     const int x0 = tx * a.B[0], y0 = ty * a.B[1], z0 = tz * a.B[2];
     const int HX = a.B[0] + PW - 1, HY = a.B[1] + PW - 1, HZ = a.B[2] + PW - 1;
-    const int tot = HX * HY * HZ;
-    for (int k0 = threadIdx.x; k0 < tot; k0 += blockDim.x * kFlushILP) {
-        real v[kFlushILP];
+    const int HYZ = HY * HZ;
+    // load the tile plus halo: each item is one (y, z) column of the block and a run of
+    // up to kHaloILP x planes, whose loads are all in flight together
+    const int nch = (HX + kHaloILP - 1) / kHaloILP;
+    const size_t plane = (size_t)a.I[1] * a.I[2];
+    for (int it = threadIdx.x; it < HYZ * nch; it += blockDim.x) {
+        const int c = it / HYZ, k = it - c * HYZ;
+        const int ly = k / HZ, lz = k - ly * HZ;
+        const int gz = z0 - HW + lz;
+        const bool zin = gz >= 0 && gz < a.I[2];
+        const size_t colyz = (size_t)wrap_once(y0 - HW + ly, a.I[1]) * a.I[2] + (zin ? gz : 0);
+        real v[kHaloILP];
 #pragma unroll
-        for (int j = 0; j < kFlushILP; ++j) {
-            const int k = k0 + j * blockDim.x;
-            v[j] = 0;
-            if (k < tot) {
-                const int lz = k % HZ, ly = (k / HZ) % HY, lx = k / (HZ * HY);
-                const int gz = z0 - HW + lz;
-                if (gz >= 0 && gz < a.I[2]) {
-                    const int gx = imod(x0 - HW + lx, a.I[0]);
-                    const int gy = imod(y0 - HW + ly, a.I[1]);
-                    v[j] = a.grid[((size_t)gx * a.I[1] + gy) * a.I[2] + gz];
-                }
-            }
+        for (int j = 0; j < kHaloILP; ++j) {
+            const int lx = c * kHaloILP + j;
+            v[j] = (zin && lx < HX) ? a.grid[(size_t)wrap_once(x0 - HW + lx, a.I[0]) * plane + colyz] : (real)0;
         }
 #pragma unroll
-        for (int j = 0; j < kFlushILP; ++j) {
-            const int k = k0 + j * blockDim.x;
-            if (k < tot) halo[k] = v[j];
+        for (int j = 0; j < kHaloILP; ++j) {
+            const int lx = c * kHaloILP + j;
+            if (lx < HX) halo[lx * HYZ + k] = v[j];
         }
     }
     __syncthreads();

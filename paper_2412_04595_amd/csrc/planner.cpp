@@ -30,13 +30,15 @@ const Row kTable1[6] = {
     {1.14878150173321925, 7.2956245490719404, 1.0000368348358225, 1.30e-15, 271, 1.98e-14, 116},
 };
 
-// GPU cost model, seconds per unit of work (calibrated with rocprofv3 on MI355X).
-constexpr double kCostNearPair = 1.5e-12;   // per neighbour pair within r_c
-constexpr double kCostWindowPt = 3.0e-13;   // per particle per window point, spread + gather
-constexpr double kCostFFTPt = 6.0e-12;      // per real grid point, forward + inverse 3D FFT chain
-constexpr double kCostLongDirect = 4.0e-13; // per particle per (half-plane mode x Chebyshev term)
-constexpr double kCostWindow2Pt = 3.0e-13;  // per particle per 2D window point per Chebyshev term
-constexpr double kCostFFT2Pt = 1.2e-11;     // per 2D grid point per Chebyshev term
+// GPU cost model: seconds per unit of work of the float32 kernels on MI355X, fitted to
+// rocprofv3 times at N = 10^6 for two grid sizes (float64 takes about twice as long in
+// every term).  It only ranks candidate discretisations.
+constexpr double kCostNearPair = 1.2e-11;   // per neighbour pair within r_c
+constexpr double kCostWindowPt = 4.5e-13;   // per particle per window point, spread + gather
+constexpr double kCostFFTPt = 3.9e-11;      // per real grid point: FFT chain, tile halo loads and adds
+constexpr double kCostLongDirect = 1.0e-12; // per particle per (half-plane mode x Chebyshev term)
+constexpr double kCostWindow2Pt = 9.0e-13;  // per particle per 2D window point per Chebyshev term
+constexpr double kCostFFT2Pt = 3.6e-11;     // per 2D grid point per Chebyshev term
 
 const double kPi = 3.14159265358979323846;
 
@@ -390,7 +392,7 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         if (ov.rc > rc_max * (1 + 1e-12)) { err = "rc must be <= min(Lx, Ly)/2 (Assumption ass:SOG)"; return SOG_ERR_INVALID_ARG; }
         rcs.push_back(ov.rc);
     } else {
-        for (double c : {2.0, 2.5, 3.0, 3.5, 4.0, 5.0}) rcs.push_back(std::min(c * std::cbrt(1.0 / rho), rc_max));
+        for (double c : {2.0, 2.5, 2.75, 3.0, 3.25, 3.5, 4.0, 5.0}) rcs.push_back(std::min(c * std::cbrt(1.0 / rho), rc_max));
     }
     const double eps = tol / 20.0;
     double best_cost = 1e300;
