@@ -127,6 +127,7 @@ sog_status build_plan(Plan& p) {
         const int Kz = r.Izs / 2 + 1;
         A.get(ws.tile_start, (ntiles + 1) * 4);
         A.get(ws.tile_cursor, ntiles * 4);
+        A.get(ws.spread_nodes, 2 * 4 * 64);
         A.get(ws.mid_g, n * 16);
         A.get(ws.mid_u, n * 4 * rs);
         A.get(ws.grid, (size_t)r.I[0] * r.I[1] * r.Izs * rs);
@@ -217,6 +218,8 @@ sog_status build_plan(Plan& p) {
         if (e == hipSuccess) e = upload(ws.mult_ay, ay, f64);
         if (e == hipSuccess) e = upload(ws.mult_az, az, f64);
         if (e == hipSuccess) e = upload(ws.mult_c, cl, f64);
+        if (e == hipSuccess) e = hipMemcpy(ws.spread_nodes, r.node_oy, 4 * 64, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(ws.spread_nodes + 4 * 64, r.node_oz, 4 * 64, hipMemcpyHostToDevice);
     }
     if (r.has_long) {
         if (r.form == SOG_LONG_DIRECT) {
@@ -267,7 +270,7 @@ void free_plan(Plan& p) {
     Workspace& ws = p.ws;
     void* ptrs[] = {ws.x, ws.q, ws.phi, ws.force, ws.energy, ws.qsum, ws.status, ws.parts,
                     ws.key, ws.perm, ws.scan_tmp, ws.cell_start, ws.cell_cursor, ws.near_orig,
-                    ws.near_pos, ws.tile_start, ws.tile_cursor, ws.mid_g,
+                    ws.near_pos, ws.tile_start, ws.tile_cursor, ws.spread_nodes, ws.mid_g,
                     ws.mid_u, ws.grid, ws.cgrid, ws.tw_x, ws.tw_y, ws.tw_z, ws.tw_zpost, ws.mult_ax, ws.mult_ay,
                     ws.mult_az, ws.mult_c, ws.long_modes, ws.long_kt, ws.long_mu, ws.long_a, ws.l2_tile_start,
                     ws.l2_tile_cursor, ws.l2_dup_start, ws.l2_dup_cursor, ws.l2_dup_list, ws.l2_g, ws.l2_u,

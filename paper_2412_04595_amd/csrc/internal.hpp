@@ -73,6 +73,10 @@ struct Resolved {
     double H[3] = {0, 0, 0};
     double Lzs = 0;
     int B[3] = {0, 0, 0};      // spread/gather tile
+    // gridding: (y, z) window node of each lane in each of up to 4 passes of 64 lanes
+    // (-1: none), chosen so that the 64 nodes of a pass fall in distinct LDS banks
+    signed char node_oy[4 * 64] = {0};
+    signed char node_oz[4 * 64] = {0};
     int ntile[3] = {0, 0, 0};
 
     // long range (Sec. 3.3 / App. B)
@@ -122,6 +126,7 @@ struct Workspace {
     // mid range
     int* tile_start = nullptr;  // ntiles + 1 (owners)
     int* tile_cursor = nullptr; // ntiles
+    signed char* spread_nodes = nullptr;  // 2 x 256: node_oy, node_oz of the plan
     int* mid_g = nullptr;       // n x int4 (grid point of each sorted particle, original index)
     void* mid_u = nullptr;      // n x real4 (offset from the grid point in units of h, q)
     void* grid = nullptr;       // I_x I_y I_z* reals

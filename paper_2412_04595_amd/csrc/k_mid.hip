@@ -109,6 +109,7 @@ struct SpreadArgs {
     const int4* gp;
     const vec4<real>* up;
     const int* tstart;  // owned particles of each tile (the gather's lists)
+    const signed char* nodes;  // (y, z) window node of each lane per pass: 256 oy, then 256 oz
     real* grid;
     int I[3];
     int B[3];
@@ -156,14 +157,16 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
     int* slx = reinterpret_cast<int*>(meta + kSpreadStage);      // x node of the particle in the block
     for (int k = threadIdx.x; k < tot + 64; k += kSpreadThreads) halo[k] = 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // this lane's (y, z) node of the window in each pass (chosen by the planner so that
+    // the 64 lanes of a pass hit distinct LDS banks for any window corner)
     int oyz[NPASS], oy2[NPASS], oz2[NPASS];
 #pragma unroll
     for (int ps = 0; ps < NPASS; ++ps) {
-        const int k = lane + 64 * ps;
-        const bool in = k < PW * PW;
-        oy2[ps] = in ? k / PW : 0;
-        oz2[ps] = in ? PW + k % PW : PW;
-        oyz[ps] = in ? (k / PW) * HZ + k % PW : -1;
+        const int oy = a.nodes[ps * 64 + lane], oz = a.nodes[256 + ps * 64 + lane];
+        const bool in = oy >= 0;
+        oy2[ps] = in ? oy : 0;
+        oz2[ps] = in ? PW + oz : PW;
+        oyz[ps] = in ? oy * HZ + oz : -1;
     }
     const int planestep = 4 * HYZ;
     // the first kSpreadStage threads hold the next batch's particles, loaded one batch ahead
@@ -395,6 +398,7 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         a.gp = (const int4*)ws.mid_g;
         a.up = (const vec4<real>*)ws.mid_u;
         a.tstart = ws.tile_start;
+        a.nodes = ws.spread_nodes;
         a.grid = (real*)ws.grid;
         a.I[0] = r.I[0]; a.I[1] = r.I[1]; a.I[2] = r.Izs;
         for (int d = 0; d < 3; ++d) { a.B[d] = r.B[d]; a.nt[d] = r.ntile[d]; }

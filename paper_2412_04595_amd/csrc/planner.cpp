@@ -82,6 +82,64 @@ int tile_edge(int prec, int Pw) {
     return 1;
 }
 
+// The gridding kernel's lanes take the (y, z) nodes of a window, 64 per pass; node
+// (oy, oz) of a window whose corner is at LDS word c sits at c + oy HZ + oz.  When every
+// residue of oy HZ + oz modulo 64 occurs at most once per pass, lane (oy HZ + oz) mod 64
+// can take it and the 64 lanes of a pass hit 64 distinct banks for any corner.
+bool spread_pitch_conflict_free(int Pw, int HZ) {
+    const int npass = (Pw * Pw + 63) / 64;
+    int cnt[64] = {0};
+    for (int oy = 0; oy < Pw; ++oy)
+        for (int oz = 0; oz < Pw; ++oz)
+            if (++cnt[(oy * HZ + oz) % 64] > npass) return false;
+    return true;
+}
+
+// Tile of the gridding and gathering kernels.  float32: among z extents whose halo pitch
+// is conflict-free, the tile with the largest share of owned nodes in its halo block that
+// fits 64 KiB of LDS; float64 (two banks per value anyway), or no such extent: the
+// largest cube.
+void spread_tile(int prec, int Pw, int B[3]) {
+    const int c = tile_edge(prec, Pw);
+    B[0] = B[1] = B[2] = c;
+    if (prec == SOG_PREC_FP64) return;
+    double best = (double)c * c * c / std::pow((double)(c + Pw - 1), 3);
+    for (int bz = std::max(1, Pw - 1); bz <= 40; ++bz) {
+        const int HZ = bz + Pw - 1;
+        if (!spread_pitch_conflict_free(Pw, HZ)) continue;
+        int bxy = 32;
+        while (bxy > 1 && spread_lds_bytes(4, Pw, bxy, bxy, bz) > 65536) --bxy;
+        if (spread_lds_bytes(4, Pw, bxy, bxy, bz) > 65536) continue;
+        const double eff = (double)bxy * bxy * bz / ((double)(bxy + Pw - 1) * (bxy + Pw - 1) * HZ);
+        if (eff >= 0.97 * best) {
+            best = std::max(best, eff);
+            B[0] = B[1] = bxy;
+            B[2] = bz;
+        }
+    }
+}
+
+// Lane of each window node per pass (see spread_pitch_conflict_free); when the pitch is
+// not conflict-free, nodes in row order.
+void spread_lane_nodes(int Pw, int HZ, signed char* noy, signed char* noz) {
+    for (int i = 0; i < 4 * 64; ++i) noy[i] = noz[i] = -1;
+    if (spread_pitch_conflict_free(Pw, HZ)) {
+        int used[64] = {0};
+        for (int oy = 0; oy < Pw; ++oy)
+            for (int oz = 0; oz < Pw; ++oz) {
+                const int lane = (oy * HZ + oz) % 64;
+                const int ps = used[lane]++;
+                noy[ps * 64 + lane] = (signed char)oy;
+                noz[ps * 64 + lane] = (signed char)oz;
+            }
+    } else {
+        for (int k = 0; k < Pw * Pw && k < 4 * 64; ++k) {
+            noy[k] = (signed char)(k / Pw);
+            noz[k] = (signed char)(k % Pw);
+        }
+    }
+}
+
 struct MidChoice {
     bool ok = false;
     int I[3] = {0, 0, 0};
@@ -484,12 +542,14 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         for (int d = 0; d < 3; ++d) r.H[d] = 0.5 * (r.Pw - 1) * r.h[d];
         // tiles: LDS holds the tile plus its (P_w - 1) halo for gridding and gathering;
         // gridding adds each tile's block into the grid with atomics, so any tile count works
-        const int B = tile_edge(r.prec, r.Pw);
+        int Bt[3];
+        spread_tile(r.prec, r.Pw, Bt);
         const int gI[3] = {r.I[0], r.I[1], r.Izs};
         for (int d = 0; d < 3; ++d) {
-            r.B[d] = std::min(B, gI[d]);
+            r.B[d] = std::min(Bt[d], gI[d]);
             r.ntile[d] = (gI[d] + r.B[d] - 1) / r.B[d];
         }
+        spread_lane_nodes(r.Pw, r.B[2] + r.Pw - 1, r.node_oy, r.node_oz);
         if (!is_smooth(r.I[0]) || !is_smooth(r.I[1]) || !is_smooth(r.Izs / 2)) { err = "mid grid sizes must have only factors 2, 3, 5, 7 (and I_z*/2 as well)"; return SOG_ERR_INVALID_ARG; }
         if (r.I[0] % 2 || r.I[1] % 2) { err = "mid I_x, I_y must be even"; return SOG_ERR_INVALID_ARG; }
         if (r.I[0] > 4096 || r.I[1] > 4096 || r.Izs > 8192) { err = "mid grid too large"; return SOG_ERR_INVALID_ARG; }
