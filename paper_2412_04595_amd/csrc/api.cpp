@@ -164,6 +164,10 @@ sog_status build_plan(Plan& p) {
         }
     }
     A.get(ws.scan_tmp, ((maxbins + 1) / 1024 + 2) * 4);
+    if (r.has_mid) {
+        A.get(ws.key2, n * 4);
+        A.get(ws.scan_tmp2, ((maxbins + 1) / 1024 + 2) * 4);
+    }
     ws.red_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256));
     A.get(ws.red, ws.red_blocks * 8);
     ws.bytes = A.total;
@@ -269,7 +273,7 @@ sog_status build_plan(Plan& p) {
 void free_plan(Plan& p) {
     Workspace& ws = p.ws;
     void* ptrs[] = {ws.x, ws.q, ws.phi, ws.force, ws.energy, ws.qsum, ws.status, ws.parts,
-                    ws.key, ws.perm, ws.scan_tmp, ws.cell_start, ws.cell_cursor, ws.near_orig,
+                    ws.key, ws.perm, ws.scan_tmp, ws.key2, ws.scan_tmp2, ws.cell_start, ws.cell_cursor, ws.near_orig,
                     ws.near_pos, ws.tile_start, ws.tile_cursor, ws.spread_nodes, ws.mid_g,
                     ws.mid_u, ws.grid, ws.cgrid, ws.tw_x, ws.tw_y, ws.tw_z, ws.tw_zpost, ws.mult_ax, ws.mult_ay,
                     ws.mult_az, ws.mult_c, ws.long_modes, ws.long_kt, ws.long_mu, ws.long_a, ws.l2_tile_start,
@@ -279,6 +283,12 @@ void free_plan(Plan& p) {
         if (q) (void)hipFree(q);
     ws = Workspace();
     for (hipEvent_t ev : p.ev_pool) (void)hipEventDestroy(ev);
+    if (p.ev_fork) (void)hipEventDestroy(p.ev_fork);
+    if (p.ev_join) (void)hipEventDestroy(p.ev_join);
+    if (p.ev_grid) (void)hipEventDestroy(p.ev_grid);
+    if (p.side) (void)hipStreamDestroy(p.side);
+    p.ev_fork = p.ev_join = p.ev_grid = nullptr;
+    p.side = nullptr;
     for (auto& pe : p.pending) {
         (void)hipEventDestroy(pe.second.first);
         (void)hipEventDestroy(pe.second.second);
@@ -334,17 +344,41 @@ sog_status run(Plan& p, const double* x_in, const double* q_in, double* energy, 
         q = ws.q;
     }
     if ((e = launch_prep(p, x, q)) != hipSuccess) return hip_status(e, "validate");
-    if ((e = launch_near(p, x, q)) != hipSuccess) return hip_status(e, "near field");
-    if (p.r.has_mid) {
-        if ((e = launch_mid(p, x, q)) != hipSuccess) return hip_status(e, "mid range");
-    } else if ((e = launch_zero_parts(p, 1)) != hipSuccess) {
-        return hip_status(e, "mid range");
+    // Two streams: the near field and the long range on the plan's side stream, the mid
+    // range on the caller's stream (they share no buffers: separate sort keys, scan space
+    // and part records).  The ALU-bound near-field kernel waits for the gridding so that it
+    // runs next to the memory-bound FFT passes and the gathering rather than next to the
+    // gridding; the caller's stream waits for the side stream before the combination.
+    const hipStream_t main_stream = p.stream;
+    {
+        struct Restore {
+            Plan& p;
+            hipStream_t s;
+            ~Restore() { p.stream = s; }
+        } restore{p, main_stream};
+        if ((e = hipEventRecord(p.ev_fork, main_stream)) != hipSuccess) return hip_status(e, "fork");
+        if ((e = hipStreamWaitEvent(p.side, p.ev_fork, 0)) != hipSuccess) return hip_status(e, "fork");
+        p.stream = p.side;
+        if ((e = launch_near(p, x, q, 1)) != hipSuccess) return hip_status(e, "near field");
+        if (p.r.has_long) {
+            if ((e = launch_long(p, x, q)) != hipSuccess) return hip_status(e, "long range");
+        } else if ((e = launch_zero_parts(p, 2)) != hipSuccess) {
+            return hip_status(e, "long range");
+        }
+        p.stream = main_stream;
+        if (p.r.has_mid) {
+            if ((e = launch_mid(p, x, q, 1)) != hipSuccess) return hip_status(e, "mid range");
+        } else if ((e = launch_zero_parts(p, 1)) != hipSuccess) {
+            return hip_status(e, "mid range");
+        }
+        if ((e = hipEventRecord(p.ev_grid, main_stream)) != hipSuccess) return hip_status(e, "fork");
+        if ((e = hipStreamWaitEvent(p.side, p.ev_grid, 0)) != hipSuccess) return hip_status(e, "fork");
+        p.stream = p.side;
+        if ((e = launch_near(p, x, q, 2)) != hipSuccess) return hip_status(e, "near field");
+        if ((e = hipEventRecord(p.ev_join, p.side)) != hipSuccess) return hip_status(e, "join");
     }
-    if (p.r.has_long) {
-        if ((e = launch_long(p, x, q)) != hipSuccess) return hip_status(e, "long range");
-    } else if ((e = launch_zero_parts(p, 2)) != hipSuccess) {
-        return hip_status(e, "long range");
-    }
+    if (p.r.has_mid && (e = launch_mid(p, x, q, 2)) != hipSuccess) return hip_status(e, "mid range");
+    if ((e = hipStreamWaitEvent(main_stream, p.ev_join, 0)) != hipSuccess) return hip_status(e, "join");
     if (phi_parts || grad_parts) {
         double *dpp = nullptr, *dgp = nullptr;
         if (p.on_device) {
@@ -486,6 +520,16 @@ sog_status sog_plan_ex(const double box[3], int64_t n, double tol, const sog_opt
     DeviceGuard dg(p->device);
     s = build_plan(*p);
     if (s != SOG_OK) {
+        delete p;
+        return s;
+    }
+    hipError_t he = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&p->ev_grid, hipEventDisableTiming);
+    if (he != hipSuccess) {
+        s = hip_status(he, "stream creation");
+        free_plan(*p);
         delete p;
         return s;
     }
@@ -633,6 +677,7 @@ void sog_destroy(sog_plan_t plan) {
     {
         DeviceGuard dg(p->device);
         (void)hipStreamSynchronize(p->stream);
+        if (p->side) (void)hipStreamSynchronize(p->side);
         free_plan(*p);
     }
     delete p;

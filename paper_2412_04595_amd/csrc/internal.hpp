@@ -118,6 +118,8 @@ struct Workspace {
     int* key = nullptr;       // n
     int* perm = nullptr;      // n
     int* scan_tmp = nullptr;  // block sums
+    int* key2 = nullptr;      // n: the mid range's sort keys (it runs on the main stream while
+    int* scan_tmp2 = nullptr; //    the near field and long range sort on the side stream)
     // near field
     int* cell_start = nullptr;  // ncells + 1
     int* cell_cursor = nullptr; // ncells
@@ -168,7 +170,9 @@ struct Plan {
     Resolved r;
     Workspace ws;
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;   // the stream kernels are launched on (the caller's, or side)
+    hipStream_t side = nullptr;     // plan-owned stream: near field and long range
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_grid = nullptr;
     bool on_device = false;
     bool check = true;
     bool timing = false;
@@ -201,9 +205,11 @@ hipError_t launch_counting_sort(Plan& p, const int* key, int n, int nbins, int* 
 // zero the counts (nbins + 1) and cursors (nbins) of a counting sort whose histogram the
 // caller's key kernel builds; launch_exclusive_scan then turns counts into starts
 hipError_t launch_sort_clear(Plan& p, int nbins, int* start, int* cursor);
-hipError_t launch_exclusive_scan(Plan& p, int* data, int nbins);  // in place, data has nbins+1 entries
-hipError_t launch_near(Plan& p, const double* x, const double* q);
-hipError_t launch_mid(Plan& p, const double* x, const double* q);
+hipError_t launch_exclusive_scan(Plan& p, int* data, int nbins, int* tmp);  // in place; tmp: block sums
+// stages (bit mask): near 1 = cell sort, 2 = pair kernel; mid 1 = tile sort and gridding,
+// 2 = FFT chain and gathering
+hipError_t launch_near(Plan& p, const double* x, const double* q, int stages = 3);
+hipError_t launch_mid(Plan& p, const double* x, const double* q, int stages = 3);
 hipError_t launch_long(Plan& p, const double* x, const double* q);
 hipError_t launch_combine(Plan& p, const double* q, double* phi, double* force, double* energy);
 hipError_t launch_parts_out(Plan& p, double* phi_parts, double* grad_parts);

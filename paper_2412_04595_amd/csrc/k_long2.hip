@@ -383,7 +383,7 @@ hipError_t run_long_fft(Plan& p, const double* x, const double* q) {
     if ((e = launch_fill_int(ws.l2_dup_start, 0, (int64_t)ntiles + 1, p.stream)) != hipSuccess) return e;
     if ((e = launch_fill_int(ws.l2_dup_cursor, 0, ntiles, p.stream)) != hipSuccess) return e;
     k_l2_dup<<<blocks, 256, 0, p.stream>>>((const int4*)ws.l2_g, n, g, ws.l2_dup_start, nullptr, nullptr, nullptr, 0, 0);
-    if ((e = launch_exclusive_scan(p, ws.l2_dup_start, ntiles + 1)) != hipSuccess) return e;
+    if ((e = launch_exclusive_scan(p, ws.l2_dup_start, ntiles + 1, ws.scan_tmp)) != hipSuccess) return e;
     k_l2_dup<<<blocks, 256, 0, p.stream>>>((const int4*)ws.l2_g, n, g, nullptr, ws.l2_dup_start, ws.l2_dup_cursor,
                                             ws.l2_dup_list, (int)std::min<int64_t>((int64_t)n * r.max_dup2, INT32_MAX), 1);
     timer_end(p, t);

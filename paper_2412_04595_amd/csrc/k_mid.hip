@@ -474,9 +474,9 @@ hipError_t run_mid_prepare(Plan& p, const double* x, const double* q) {
     const int blocks = std::min((n + 255) / 256, 8192);
     hipError_t e = launch_sort_clear(p, ntiles, ws.tile_start, ws.tile_cursor);
     if (e != hipSuccess) return e;
-    k_mid_key<<<blocks, 256, 0, p.stream>>>(x, n, g, ws.key, ws.tile_start);
-    if ((e = launch_exclusive_scan(p, ws.tile_start, ntiles + 1)) != hipSuccess) return e;
-    k_mid_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.key, ws.tile_start, ws.tile_cursor,
+    k_mid_key<<<blocks, 256, 0, p.stream>>>(x, n, g, ws.key2, ws.tile_start);
+    if ((e = launch_exclusive_scan(p, ws.tile_start, ntiles + 1, ws.scan_tmp2)) != hipSuccess) return e;
+    k_mid_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.key2, ws.tile_start, ws.tile_cursor,
                                                     (int4*)ws.mid_g, (vec4<real>*)ws.mid_u);
     return hipGetLastError();
 }
@@ -485,24 +485,29 @@ hipError_t run_mid_prepare(Plan& p, const double* x, const double* q) {
 
 hipError_t launch_fft_mid(Plan& p);  // k_fft.hip
 
-hipError_t launch_mid(Plan& p, const double* x, const double* q) {
+hipError_t launch_mid(Plan& p, const double* x, const double* q, int stages) {
     const bool f64 = p.r.prec == SOG_PREC_FP64;
-    int t = timer_id(p, "mid_sort");
-    timer_begin(p, t);
-    hipError_t e = f64 ? run_mid_prepare<double>(p, x, q) : run_mid_prepare<float>(p, x, q);
-    timer_end(p, t);
-    if (e != hipSuccess) return e;
-    t = timer_id(p, "mid_spread");
-    timer_begin(p, t);
-    e = f64 ? spread_gather<double>(p, true) : spread_gather<float>(p, true);
-    timer_end(p, t);
-    if (e != hipSuccess) return e;
-    e = launch_fft_mid(p);
-    if (e != hipSuccess) return e;
-    t = timer_id(p, "mid_gather");
-    timer_begin(p, t);
-    e = f64 ? spread_gather<double>(p, false) : spread_gather<float>(p, false);
-    timer_end(p, t);
+    hipError_t e = hipSuccess;
+    if (stages & 1) {
+        int t = timer_id(p, "mid_sort");
+        timer_begin(p, t);
+        e = f64 ? run_mid_prepare<double>(p, x, q) : run_mid_prepare<float>(p, x, q);
+        timer_end(p, t);
+        if (e != hipSuccess) return e;
+        t = timer_id(p, "mid_spread");
+        timer_begin(p, t);
+        e = f64 ? spread_gather<double>(p, true) : spread_gather<float>(p, true);
+        timer_end(p, t);
+        if (e != hipSuccess) return e;
+    }
+    if (stages & 2) {
+        e = launch_fft_mid(p);
+        if (e != hipSuccess) return e;
+        const int t = timer_id(p, "mid_gather");
+        timer_begin(p, t);
+        e = f64 ? spread_gather<double>(p, false) : spread_gather<float>(p, false);
+        timer_end(p, t);
+    }
     return e;
 }
 

@@ -202,11 +202,11 @@ hipError_t launch_prep(Plan& p, const double* x, const double* q) {
     return hipGetLastError();
 }
 
-hipError_t launch_exclusive_scan(Plan& p, int* data, int len) {
+hipError_t launch_exclusive_scan(Plan& p, int* data, int len, int* tmp) {
     int nb = (len + kScanChunk - 1) / kScanChunk;
-    k_scan_local<<<nb, kScanThreads, 0, p.stream>>>(data, len, p.ws.scan_tmp);
-    k_scan_sums<<<1, kScanThreads, 0, p.stream>>>(p.ws.scan_tmp, nb);
-    k_scan_add<<<nb, kScanThreads, 0, p.stream>>>(data, len, p.ws.scan_tmp);
+    k_scan_local<<<nb, kScanThreads, 0, p.stream>>>(data, len, tmp);
+    k_scan_sums<<<1, kScanThreads, 0, p.stream>>>(tmp, nb);
+    k_scan_add<<<nb, kScanThreads, 0, p.stream>>>(data, len, tmp);
     return hipGetLastError();
 }
 
@@ -217,7 +217,7 @@ hipError_t launch_counting_sort(Plan& p, const int* key, int n, int nbins, int* 
     e = launch_fill_int(cursor, 0, nbins, p.stream);
     if (e != hipSuccess) return e;
     k_hist<<<grid_for(n, 256), 256, 0, p.stream>>>(key, n, start);
-    e = launch_exclusive_scan(p, start, nbins + 1);
+    e = launch_exclusive_scan(p, start, nbins + 1, p.ws.scan_tmp);
     if (e != hipSuccess) return e;
     k_scatter<<<grid_for(n, 256), 256, 0, p.stream>>>(key, n, start, cursor, perm);
     return hipGetLastError();

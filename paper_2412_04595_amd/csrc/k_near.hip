@@ -294,7 +294,7 @@ void launch_near_kernel(const NearArgs<real>& a, hipStream_t st) {
 }
 
 template <typename real>
-hipError_t run_near(Plan& p, const double* x, const double* q) {
+hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
     const Resolved& r = p.r;
     Workspace& ws = p.ws;
     const int n = (int)r.n;
@@ -306,16 +306,19 @@ hipError_t run_near(Plan& p, const double* x, const double* q) {
     }
     g.zc = r.near_zc;
     const int ncells = r.nc[0] * r.nc[1] * r.nc[2];
-    int t = timer_id(p, "near_sort");
-    timer_begin(p, t);
-    const int blocks = std::min((n + 255) / 256, 8192);
-    hipError_t e = launch_sort_clear(p, ncells, ws.cell_start, ws.cell_cursor);
-    if (e != hipSuccess) return e;
-    k_near_key<<<blocks, 256, 0, p.stream>>>(x, n, g, ws.key, ws.cell_start);
-    if ((e = launch_exclusive_scan(p, ws.cell_start, ncells + 1)) != hipSuccess) return e;
-    k_near_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.key, ws.cell_start, ws.cell_cursor,
-                                                     (vec4<real>*)ws.near_pos, ws.near_orig);
-    timer_end(p, t);
+    if (stages & 1) {
+        const int t = timer_id(p, "near_sort");
+        timer_begin(p, t);
+        const int blocks = std::min((n + 255) / 256, 8192);
+        hipError_t e = launch_sort_clear(p, ncells, ws.cell_start, ws.cell_cursor);
+        if (e != hipSuccess) return e;
+        k_near_key<<<blocks, 256, 0, p.stream>>>(x, n, g, ws.key, ws.cell_start);
+        if ((e = launch_exclusive_scan(p, ws.cell_start, ncells + 1, ws.scan_tmp)) != hipSuccess) return e;
+        k_near_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.key, ws.cell_start, ws.cell_cursor,
+                                                         (vec4<real>*)ws.near_pos, ws.near_orig);
+        timer_end(p, t);
+        if (!(stages & 2)) return hipGetLastError();
+    }
     NearArgs<real> a;
     a.pos = (const vec4<real>*)ws.near_pos;
     a.orig = ws.near_orig;
@@ -335,7 +338,7 @@ hipError_t run_near(Plan& p, const double* x, const double* q) {
         a.cF[k] = (real)r.near_cF[k];
         a.cG[k] = (real)r.near_cG[k];
     }
-    t = timer_id(p, "near");
+    const int t = timer_id(p, "near");
     timer_begin(p, t);
     launch_near_kernel<real>(a, p.stream);
     timer_end(p, t);
@@ -344,9 +347,9 @@ hipError_t run_near(Plan& p, const double* x, const double* q) {
 
 }  // namespace
 
-hipError_t launch_near(Plan& p, const double* x, const double* q) {
-    if (p.r.prec == SOG_PREC_FP64) return run_near<double>(p, x, q);
-    return run_near<float>(p, x, q);
+hipError_t launch_near(Plan& p, const double* x, const double* q, int stages) {
+    if (p.r.prec == SOG_PREC_FP64) return run_near<double>(p, x, q, stages);
+    return run_near<float>(p, x, q, stages);
 }
 
 }  // namespace sog
