@@ -112,7 +112,7 @@ typedef struct {
  * timing off, no overrides. */
 void sog_options_default(sog_options* opt);
 
-/* Plan for n particles (2 <= n <= 2^27) in box (Lx, Ly, Lz) at relative tolerance tol with the default
+/* Plan for n particles (2 <= n <= 2^26) in box (Lx, Ly, Lz) at relative tolerance tol with the default
  * options.  tol is the target relative error of potentials, energy and forces. */
 sog_status sog_plan(const double box[3], int64_t n, double tol, sog_plan_t* out);
 
@@ -149,7 +149,6 @@ typedef struct {
     int32_t near_cells[3];
     int32_t tile[3];           /* mid-range spread/gather tile, grid points  */
     int32_t near_degree;       /* Chebyshev degree of the near-field kernel  */
-    int32_t near_cells_per_block; /* z cells per near-field work unit       */
 } sog_plan_sizes;
 sog_status sog_plan_sizes_get(sog_plan_t plan, sog_plan_sizes* out);
 

@@ -124,8 +124,7 @@ class Solver:
     def sizes(self):
         s = sog_plan_sizes_get(self.plan)
         return dict(mid_grid_points=s.mid_grid_points, long_points=s.long_points, device_bytes=s.device_bytes,
-                    near_cells=list(s.near_cells), tile=list(s.tile), near_degree=s.near_degree,
-                    near_cells_per_block=s.near_cells_per_block)
+                    near_cells=list(s.near_cells), tile=list(s.tile), near_degree=s.near_degree)
 
     def kernel_times(self):
         return sog_kernel_times(self.plan)

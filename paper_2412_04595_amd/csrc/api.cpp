@@ -121,6 +121,7 @@ sog_status build_plan(Plan& p) {
     A.get(ws.cell_cursor, ncells * 4);
     A.get(ws.near_orig, n * 4);
     A.get(ws.near_pos, n * 4 * rs);
+    A.get(ws.near_units, (size_t)ncells * 16);
     if (r.has_mid) {
         const int ntiles = r.ntile[0] * r.ntile[1] * r.ntile[2];
         maxbins = std::max<int64_t>(maxbins, ntiles);
@@ -273,7 +274,7 @@ sog_status build_plan(Plan& p) {
 void free_plan(Plan& p) {
     Workspace& ws = p.ws;
     void* ptrs[] = {ws.x, ws.q, ws.phi, ws.force, ws.energy, ws.qsum, ws.status, ws.parts,
-                    ws.key, ws.perm, ws.scan_tmp, ws.key2, ws.scan_tmp2, ws.cell_start, ws.cell_cursor, ws.near_orig,
+                    ws.key, ws.perm, ws.scan_tmp, ws.key2, ws.scan_tmp2, ws.cell_start, ws.cell_cursor, ws.near_orig, ws.near_units,
                     ws.near_pos, ws.tile_start, ws.tile_cursor, ws.spread_nodes, ws.mid_g,
                     ws.mid_u, ws.grid, ws.cgrid, ws.tw_x, ws.tw_y, ws.tw_z, ws.tw_zpost, ws.mult_ax, ws.mult_ay,
                     ws.mult_az, ws.mult_c, ws.long_modes, ws.long_kt, ws.long_mu, ws.long_a, ws.l2_tile_start,
@@ -639,7 +640,6 @@ sog_status sog_plan_sizes_get(sog_plan_t plan, sog_plan_sizes* o) {
         o->tile[d] = r.B[d];
     }
     o->near_degree = r.near_deg;
-    o->near_cells_per_block = r.near_zc;
     return SOG_OK;
 }
 

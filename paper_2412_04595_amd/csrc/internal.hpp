@@ -58,7 +58,6 @@ struct Resolved {
     // near field: cells of side >= r_c; polynomials in x = 2 r^2/r_c^2 - 1
     int nc[3] = {1, 1, 1};
     double ch[3] = {0, 0, 0};
-    int near_zc = 1;  // cells per z-block (the near kernel's work unit)
     int near_deg = 0;
     double near_cF[kMaxNearDeg + 1] = {0};  // F(r)
     double near_cG[kMaxNearDeg + 1] = {0};  // F'(r)/r
@@ -124,7 +123,8 @@ struct Workspace {
     int* cell_start = nullptr;  // ncells + 1
     int* cell_cursor = nullptr; // ncells
     int* near_orig = nullptr;   // n
-    void* near_pos = nullptr;   // n x real4 (x, y, z relative to the z-block corner; q)
+    void* near_pos = nullptr;   // n x real4 (x, y, z relative to the cell corner; q)
+    void* near_units = nullptr; // ncells x int4 work units (column, first cell, end cell)
     // mid range
     int* tile_start = nullptr;  // ntiles + 1 (owners)
     int* tile_cursor = nullptr; // ntiles

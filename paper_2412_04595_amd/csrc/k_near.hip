@@ -7,14 +7,19 @@
 // Gaussians M (Remark rmk::sum asks for that; a polynomial in r^2 is this library's way
 // of getting it).
 //
-// Work unit: a z-block of zc consecutive cells of one (x, y) column (zc chosen so that a
-// block holds about one wave of targets).  Its candidate sources are the particles of 27
-// contiguous ranges of the cell-sorted array: for each of the 9 neighbouring columns, the
-// cell just below the block, the block's own cells and the cell just above.
+// Work unit: a run of consecutive cells of one (x, y) column holding at most one wave of
+// targets (at most kNearUnitCells cells; a cell with more targets is a unit of its own,
+// walked in several passes).  The units are formed per column on the device after the
+// cell sort.  A unit's candidate sources are the cells of the 9 neighbouring columns from
+// the cell below the run to the cell above it: per column one contiguous range of the
+// cell-sorted array, cut where it crosses a z frame (below).
 //
-// Coordinates enter the pair kernel as offsets from the corner of the particle's
-// z-block (x, y: its cell's corner), formed in float64, so the float32 form does not lose
-// the ~1e-5 absolute precision that raw float32 coordinates of a 100-wide box would.
+// Coordinates enter the pair kernel as offsets from the corner of the particle's x, y
+// cell and of its z frame (kNearFrameCells cells), formed in float64, so the float32 form
+// does not lose the ~1e-5 absolute precision that raw float32 coordinates of a 100-wide
+// box would.  A candidate is seen from a target shifted by the geometric offset of their
+// columns and frames; that shift is an exact zero for the target's own column and frame,
+// so the pair of a particle with itself has r^2 == 0 exactly.
 #include "device_common.hpp"
 
 namespace sog {
@@ -25,8 +30,12 @@ struct NearGeom {
     double L[3];
     double ch[3];
     int nc[3];
-    int zc;  // cells per z-block
 };
+
+constexpr int kNearFrameCells = 8;  // z cells per coordinate frame
+constexpr int kNearUnitCells = 7;   // cells per work unit at most: its candidate z range
+                                    // (<= 9 cells) crosses at most one frame boundary
+constexpr int kNearUnitTargets = 64;
 
 __device__ __forceinline__ void cell_of(const NearGeom& g, double xw, double yw, double z, int c[3]) {
     double v[3] = {xw, yw, z};
@@ -74,11 +83,48 @@ __global__ void k_near_pack(const double* __restrict__ x, const double* __restri
         vec4<real> v;
         v.x = (real)(xw - c[0] * g.ch[0]);
         v.y = (real)(yw - c[1] * g.ch[1]);
-        v.z = (real)(z - (c[2] / g.zc) * g.zc * g.ch[2]);
+        v.z = (real)(z - (c[2] / kNearFrameCells) * kNearFrameCells * g.ch[2]);
         v.w = (real)qq;
         pos[p] = v;
         orig[p] = i;
     }
+}
+
+// Work units: each column's cells grouped greedily into runs of at most kNearUnitCells
+// cells and kNearUnitTargets particles; unit = (column, first cell, end cell), stored in
+// the column's own slots (column x cells) in z order, unused slots marked by -1, so that
+// consecutive units are neighbours in space.  One wave per column: the column's cell
+// starts are read in parallel into LDS, then lane 0 walks them.
+constexpr int kUnitsLds = 4096;  // cells of a column staged in LDS at a time
+__global__ __launch_bounds__(64) void k_near_units(const int* __restrict__ cell_start, int ncz,
+                                                    int4* __restrict__ units) {
+    __shared__ int cs[kUnitsLds + 1];
+    const int col = blockIdx.x;
+    const int* gcs = cell_start + (size_t)col * ncz;
+    int4* us = units + (size_t)col * ncz;
+    int z0 = 0, u = 0;
+    for (int c0 = 0; c0 < ncz; c0 += kUnitsLds) {
+        const int cnt = min(kUnitsLds, ncz - c0);
+        __syncthreads();
+        for (int i = threadIdx.x; i <= cnt; i += 64) cs[i] = gcs[c0 + i];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            // runs end within this chunk of cells (a run may not cross it)
+            while (z0 < c0 + cnt) {
+                int z1 = z0 + 1, n = cs[z0 + 1 - c0] - cs[z0 - c0];
+                while (z1 < c0 + cnt && z1 - z0 < kNearUnitCells &&
+                       n + (cs[z1 + 1 - c0] - cs[z1 - c0]) <= kNearUnitTargets) {
+                    n += cs[z1 + 1 - c0] - cs[z1 - c0];
+                    ++z1;
+                }
+                if (n > 0) us[u++] = make_int4(col, z0, z1, 0);
+                z0 = z1;
+            }
+        }
+    }
+    __syncthreads();
+    u = __shfl(u, 0, 64);
+    for (int i = u + (int)threadIdx.x; i < ncz; i += 64) us[i] = make_int4(col, -1, -1, 0);
 }
 
 template <typename real>
@@ -87,9 +133,8 @@ struct NearArgs {
     const int* __restrict__ orig;
     const int* __restrict__ cell_start;
     vec4<real>* __restrict__ part;  // near part of each particle: phi, grad
-    int nitems;                // work units: columns x z-blocks
-    int nbz;                   // z-blocks per column
-    int zc;                    // cells per z-block
+    const int4* __restrict__ units;  // (column, first cell, end cell); first cell -1: none
+    int max_units;
     int nc[3];
     real ch[3];
     real rc2, inv_rc2;
@@ -102,7 +147,7 @@ constexpr int kNearWaves = 4;   // independent waves per block
 constexpr int kNearCap = 32;    // hit-list entries per lane (a ring; power of two)
 template <typename real>
 constexpr int kNearBatch = sizeof(real) == 4 ? 8 : 4;  // candidates tested between checks of the list's room
-constexpr int kNearCodeShift = 27;  // hit entry: source index | (neighbour range << 27)
+constexpr int kNearCodeShift = 26;  // hit entry: source index | (neighbour range << 26)
 
 // 1/sqrt: the hardware reciprocal square root in float32 (r^2 is far from denormal here)
 __device__ __forceinline__ float near_rsqrt(float v) { return __builtin_amdgcn_rsqf(v); }
@@ -144,37 +189,41 @@ __device__ __forceinline__ void near_pair(const NearArgs<real>& a, real rx, real
 template <typename real, int DEG>
 __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
     __shared__ uint32_t hits_all[kNearWaves][kNearCap * 64];
-    __shared__ vec4<real> shift_all[kNearWaves][27];
+    __shared__ vec4<real> shift_all[kNearWaves][18];
     // the candidates' addresses are the same in every lane: read them through the
     // constant address space, which gives scalar loads (the array is not written here)
     const __attribute__((address_space(4))) vec4<real>* cpos = (const __attribute__((address_space(4))) vec4<real>*)a.pos;
-    const int lb = xcd_logical_block((a.nitems + kNearWaves - 1) / kNearWaves);
+    const int lb = xcd_logical_block((a.max_units + kNearWaves - 1) / kNearWaves);
     if (lb < 0) return;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int item = lb * kNearWaves + wv;
-    if (item >= a.nitems) return;  // no block-wide barrier below: waves are independent
+    if (item >= a.max_units) return;  // no block-wide barrier below: waves are independent
+    const int4 unit = a.units[item];
+    if (unit.y < 0) return;
     uint32_t* hits = hits_all[wv];
     vec4<real>* shift = shift_all[wv];
-    const int bz = item % a.nbz, col = item / a.nbz;
+    const int col = unit.x, z0 = unit.y, z1 = unit.z;
     const int cy = col % a.nc[1], cx = col / a.nc[1];
-    const int z0 = bz * a.zc, z1 = min(z0 + a.zc, a.nc[2]);
     const int tb = a.cell_start[col * a.nc[2] + z0], te = a.cell_start[col * a.nc[2] + z1];
-    if (tb == te) return;
-    // lane k < 27: neighbour range k = (dx, dy) column x {cell below, block, cell above}
+    // lane k < 18: neighbour range k = column (dx, dy) = k / 2, piece k % 2 of the cells
+    // from below the run to above it, cut at the z frame boundary; shift.z holds the frame
     int rs = 0, re = 0;
-    if (lane < 27) {
-        const int dx = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dzi = lane / 9;
+    if (lane < 18) {
+        const int c9 = lane >> 1, piece = lane & 1;
+        const int dx = c9 % 3 - 1, dy = c9 / 3 - 1;
         const int ncol = imod(cx + dx, a.nc[0]) * a.nc[1] + imod(cy + dy, a.nc[1]);
-        int za = z0, zb = z1;
-        if (dzi == 0) { za = z0 - 1; zb = z0; }
-        if (dzi == 2) { za = z1; zb = z1 + 1; }
-        if (za >= 0 && zb <= a.nc[2]) {
-            rs = a.cell_start[ncol * a.nc[2] + za];
-            re = a.cell_start[ncol * a.nc[2] + zb];
+        const int za = max(z0 - 1, 0), zb = min(z1 + 1, a.nc[2]);
+        const int bnd = (za / kNearFrameCells + 1) * kNearFrameCells;
+        const int pa = piece ? bnd : za, pb = piece ? zb : min(zb, bnd);
+        if (pa < pb) {
+            rs = a.cell_start[ncol * a.nc[2] + pa];
+            re = a.cell_start[ncol * a.nc[2] + pb];
         }
-        shift[lane] = vec4<real>{(real)dx * a.ch[0], (real)dy * a.ch[1], (real)((dzi - 1) * a.zc) * a.ch[2], (real)0};
+        shift[lane] = vec4<real>{(real)dx * a.ch[0], (real)dy * a.ch[1], (real)(pa / kNearFrameCells), (real)0};
     }
-    // longest of the 27 ranges
+    constexpr int nranges = 18;
+    const real fh = (real)kNearFrameCells * a.ch[2];  // frame height
+    // longest of the ranges
     int maxlen = re - rs;
     for (int o = 32; o > 0; o >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, o, 64));
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -184,6 +233,11 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
         const int p = t0 + lane;
         const bool act = p < te;
         const vec4<real> me = act ? a.pos[p] : vec4<real>{(real)1e30, (real)1e30, (real)1e30, (real)0};
+        // the target's z frame (the run's cells are consecutive in p)
+        int tcz = z0;
+        for (int c = z0 + 1; c < z1; ++c)
+            if (p >= a.cell_start[col * a.nc[2] + c]) tcz = c;
+        const real tczr = (real)(tcz / kNearFrameCells);
         real phi = 0, gx = 0, gy = 0, gz = 0;
         // each lane's hit list is a ring of kNearCap entries: tail tp, head hd
         int tp = 0, hd = 0;
@@ -193,7 +247,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
             const int cnt = (tp - hd) & kMask;
             vec4<real> o[4], sh[4];
             // a lane with an empty list loads a valid dummy (the block's first particle)
-            const uint32_t dummy = (uint32_t)tb | (13u << kNearCodeShift);
+            const uint32_t dummy = (uint32_t)tb;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const uint32_t e = (cnt > 0) ? hits[((hd + min(u, cnt - 1)) & kMask) * 64 + lane] : dummy;
@@ -204,7 +258,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
             for (int u = 0; u < 4; ++u)
                 if (u < cnt)
                     near_pair<real, DEG>(a, me.x - (o[u].x + sh[u].x), me.y - (o[u].y + sh[u].y),
-                                         me.z - (o[u].z + sh[u].z), o[u].w, phi, gx, gy, gz);
+                                         me.z - (o[u].z + (sh[u].z - tczr) * fh), o[u].w, phi, gx, gy, gz);
             hd = (hd + min(cnt, 4)) & kMask;
         };
         // a chunk is evaluated as soon as every active lane has four entries waiting (all
@@ -216,19 +270,19 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
                 chunk();
             }
         };
-        // the 27 ranges are walked round-robin, one batch of each in turn, so that every
+        // the ranges are walked round-robin, one batch of each in turn, so that every
         // lane's list grows at about the same rate and a list that fills up finds the
         // others nearly as full (the evaluation runs as long as the longest list)
         for (int off = 0; off < maxlen; off += kNearBatch<real>) {
-            for (int k = 0; k < 27; ++k) {
+            for (int k = 0; k < nranges; ++k) {
                 const int js = __builtin_amdgcn_readlane(rs, k) + off, je = __builtin_amdgcn_readlane(re, k);
                 if (js >= je) continue;
                 const vec4<real> sh = shift[k];
-                const real mx = me.x - sh.x, my = me.y - sh.y, mz = me.z - sh.z;
+                const real mx = me.x - sh.x, my = me.y - sh.y, mz = me.z - (sh.z - tczr) * fh;
                 const uint32_t code = (uint32_t)k << kNearCodeShift;
                 // the particle itself is among the candidates only in the centre column
-                // ranges (zero shift); there it is the pair with r^2 == 0
-                const real r2min = (k % 9 == 4) ? (real)0 : (real)-1;
+                // (zero x, y shift), in its own frame, where the pair has r^2 == 0
+                const real r2min = ((k >> 1) == 4) ? (real)0 : (real)-1;
                 drain_ready();
                 vec4<real> o[kNearBatch<real>];
                 if (js + kNearBatch<real> <= je) {
@@ -276,7 +330,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
 // polynomial degrees compiled; the fitted degree is rounded up to one of these
 template <typename real, int DEG>
 void launch_near_deg(const NearArgs<real>& a, hipStream_t st) {
-    k_near<real, DEG><<<xcd_grid((a.nitems + kNearWaves - 1) / kNearWaves), 64 * kNearWaves, 0, st>>>(a);
+    k_near<real, DEG><<<xcd_grid((a.max_units + kNearWaves - 1) / kNearWaves), 64 * kNearWaves, 0, st>>>(a);
 }
 
 template <typename real>
@@ -304,7 +358,6 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
         g.ch[d] = r.ch[d];
         g.nc[d] = r.nc[d];
     }
-    g.zc = r.near_zc;
     const int ncells = r.nc[0] * r.nc[1] * r.nc[2];
     if (stages & 1) {
         const int t = timer_id(p, "near_sort");
@@ -316,15 +369,16 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
         if ((e = launch_exclusive_scan(p, ws.cell_start, ncells + 1, ws.scan_tmp)) != hipSuccess) return e;
         k_near_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.key, ws.cell_start, ws.cell_cursor,
                                                          (vec4<real>*)ws.near_pos, ws.near_orig);
+        const int ncols = r.nc[0] * r.nc[1];
+        k_near_units<<<ncols, 64, 0, p.stream>>>(ws.cell_start, r.nc[2], (int4*)ws.near_units);
         timer_end(p, t);
         if (!(stages & 2)) return hipGetLastError();
     }
     NearArgs<real> a;
     a.pos = (const vec4<real>*)ws.near_pos;
     a.orig = ws.near_orig;
-    a.zc = r.near_zc;
-    a.nbz = (r.nc[2] + r.near_zc - 1) / r.near_zc;
-    a.nitems = r.nc[0] * r.nc[1] * a.nbz;
+    a.units = (const int4*)ws.near_units;
+    a.max_units = ncells;
     a.cell_start = ws.cell_start;
     a.part = (vec4<real>*)ws.parts;
     for (int d = 0; d < 3; ++d) {

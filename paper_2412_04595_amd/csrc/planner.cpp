@@ -416,7 +416,7 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         if (!(box[d] > 0) || !std::isfinite(box[d])) { err = "box lengths must be finite and > 0"; return SOG_ERR_INVALID_ARG; }
         r.L[d] = box[d];
     }
-    if (n <= 1 || n > (int64_t)1 << 27) { err = "n must be in [2, 2^27]"; return SOG_ERR_INVALID_ARG; }
+    if (n <= 1 || n > (int64_t)1 << 26) { err = "n must be in [2, 2^26]"; return SOG_ERR_INVALID_ARG; }
     r.n = n;
     r.prec = opt.precision;
     if (r.prec != SOG_PREC_FP64 && r.prec != SOG_PREC_FP32_BULK) { err = "unknown precision"; return SOG_ERR_INVALID_ARG; }
@@ -527,11 +527,6 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         r.ch[d] = r.L[d] / r.nc[d];
     }
     if ((int64_t)r.nc[0] * r.nc[1] * r.nc[2] > (int64_t)1 << 26) { err = "too many near-field cells"; return SOG_ERR_INVALID_ARG; }
-    {
-        // about 56 targets per z-block: one wave of lanes, with room for fluctuations
-        const double per_cell = (double)n / ((double)r.nc[0] * r.nc[1] * r.nc[2]);
-        r.near_zc = std::max(1, std::min(r.nc[2], (int)std::floor(56.0 / std::max(per_cell, 1e-9))));
-    }
     near_chebyshev(r);
 
     if (r.has_mid) {

@@ -66,7 +66,7 @@ def _resolve_status(box, n, tol, precision="fp64", params=None):
     ((10, -1, 10), 100, 1e-4, "fp64", 1),
     ((10, 10, float("inf")), 100, 1e-4, "fp64", 1),
     ((10, 10, 10), 1, 1e-4, "fp64", 1),
-    ((10, 10, 10), (1 << 27) + 1, 1e-4, "fp64", 1),
+    ((10, 10, 10), (1 << 26) + 1, 1e-4, "fp64", 1),
     ((10, 10, 10), 100, 1e-13, "fp64", 4),
     ((10, 10, 10), 100, 1e-6, "fp32", 4),
     ((10, 10, 10), 100, 0.5, "fp64", 4),
