@@ -149,6 +149,8 @@ typedef struct {
     int32_t near_cells[3];
     int32_t tile[3];           /* mid-range spread/gather tile, grid points  */
     int32_t near_degree;       /* Chebyshev degree of the near-field kernel  */
+    int32_t mid_zband[2];      /* stored z planes [lo, hi) that can carry window mass for z in
+                                  [0, Lz]; the z transforms read and write only these      */
 } sog_plan_sizes;
 sog_status sog_plan_sizes_get(sog_plan_t plan, sog_plan_sizes* out);
 

@@ -124,7 +124,8 @@ class Solver:
     def sizes(self):
         s = sog_plan_sizes_get(self.plan)
         return dict(mid_grid_points=s.mid_grid_points, long_points=s.long_points, device_bytes=s.device_bytes,
-                    near_cells=list(s.near_cells), tile=list(s.tile), near_degree=s.near_degree)
+                    near_cells=list(s.near_cells), tile=list(s.tile), near_degree=s.near_degree,
+                    mid_zband=list(s.mid_zband))
 
     def kernel_times(self):
         return sog_kernel_times(self.plan)

@@ -73,7 +73,7 @@ class sog_plan_sizes(C.Structure):
     _fields_ = [
         ("mid_grid_points", C.c_int64), ("long_points", C.c_int64), ("device_bytes", C.c_int64),
         ("near_cells", C.c_int32 * 3), ("tile", C.c_int32 * 3),
-        ("near_degree", C.c_int32),
+        ("near_degree", C.c_int32), ("mid_zband", C.c_int32 * 2),
     ]
 
 

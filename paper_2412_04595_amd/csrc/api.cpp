@@ -640,6 +640,8 @@ sog_status sog_plan_sizes_get(sog_plan_t plan, sog_plan_sizes* o) {
         o->tile[d] = r.B[d];
     }
     o->near_degree = r.near_deg;
+    o->mid_zband[0] = r.zband[0];
+    o->mid_zband[1] = r.zband[1];
     return SOG_OK;
 }
 

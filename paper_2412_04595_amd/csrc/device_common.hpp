@@ -7,8 +7,9 @@
 
 namespace sog {
 
+// a complex value on its natural 8 (float) / 16 (double) byte boundary
 template <typename T>
-struct cpx {
+struct alignas(2 * sizeof(T)) cpx {
     T x, y;
 };
 template <typename T>

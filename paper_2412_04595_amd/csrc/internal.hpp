@@ -43,6 +43,10 @@ struct FFTFactors {
 };
 
 // Everything the planner decides (float64, host).  Symbols follow the paper.
+// Longest line the LDS line transforms take (a batch holds at most this many elements):
+// 4608 complex in the float32 form, 2304 in float64.
+constexpr int fft_max_line(int prec) { return prec == SOG_PREC_FP64 ? 2304 : 4608; }
+
 struct Resolved {
     double L[3] = {0, 0, 0};
     int64_t n = 0;
@@ -71,6 +75,9 @@ struct Resolved {
     double h[3] = {0, 0, 0};
     double H[3] = {0, 0, 0};
     double Lzs = 0;
+    // stored z planes [zband[0], zband[1]) (even bounds) that can carry window mass for
+    // z in [0, L_z]: the z transforms read and write only these, the rest stays zero
+    int zband[2] = {0, 0};
     int B[3] = {0, 0, 0};      // spread/gather tile
     // gridding: (y, z) window node of each lane in each of up to 4 passes of 64 lanes
     // (-1: none), chosen so that the 64 nodes of a pass fall in distinct LDS banks

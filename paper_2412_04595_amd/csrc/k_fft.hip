@@ -115,17 +115,71 @@ __device__ __forceinline__ void small_dft(const cpx<T> (&v)[R], cpx<T> (&o)[R]) 
 }
 
 // Largest line batch (elements per block: n x W) of the in-place LDS transform; also
-// bounds the butterflies a thread holds in registers during a stage.
+// bounds the butterflies a thread holds in registers during a stage and the elements it
+// holds while a batch moves between HBM and LDS.
 template <typename T>
-constexpr int kFFTCap = (sizeof(T) == 4) ? 4096 : 2048;
+constexpr int kFFTCap = (sizeof(T) == 4) ? 4608 : 2304;  // 18 / 9 elements per thread
 constexpr int kFFTThreads = 256;
+static_assert(kFFTCap<float> == fft_max_line(SOG_PREC_FP32_BULK) && kFFTCap<double> == fft_max_line(SOG_PREC_FP64),
+              "the planner's line limit is the batch capacity");
+template <typename T>
+constexpr int kStageK = kFFTCap<T> / kFFTThreads;
 
-// One Stockham stage of radix R, in place on A (element i of line w at A[i W + w]):
+// e / d for 0 <= e < 2^16, 2 <= d < 2^16: multiply-high by ceil(2^32 / d) (exact while
+// e d < 2^32)
+struct UDiv {
+    int d;
+    unsigned mul;
+};
+UDiv make_udiv(int d) { return UDiv{d, (unsigned)((((uint64_t)1 << 32) + (uint64_t)d - 1) / (uint64_t)d)}; }
+__device__ __forceinline__ int udiv(int e, UDiv u) { return (int)__umulhi((unsigned)e, u.mul); }
+
+// dst[i] = src[i] for i < count, with up to K loads of a thread in flight together
+template <int K, typename V>
+__device__ __forceinline__ void copy_in(V* dst, const V* __restrict__ src, int count) {
+    for (int b = 0; b < count; b += K * kFFTThreads) {
+        V v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = b + threadIdx.x + k * kFFTThreads;
+            if (i < count) v[k] = src[i];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = b + threadIdx.x + k * kFFTThreads;
+            if (i < count) dst[i] = v[k];
+        }
+    }
+}
+
+// Moves the E <= kFFTCap elements of a batch from HBM into LDS.  Each thread issues all
+// its loads before its first LDS write, so a block waits for one round trip, not one per
+// element row; side() runs between the loads and the writes (small table copies whose
+// loads then overlap the batch's).  Element e is src(e) and lands at A[dst(e)].
+template <typename T, class Src, class Dst, class Side>
+__device__ __forceinline__ void stage_in(cpx<T>* A, int E, Src src, Dst dst, Side side) {
+    constexpr int K = kStageK<T>;
+    cpx<T> v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = threadIdx.x + k * kFFTThreads;
+        if (e < E) v[k] = src(e);
+    }
+    side();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int e = threadIdx.x + k * kFFTThreads;
+        if (e < E) A[dst(e)] = v[k];
+    }
+}
+
+// One Stockham stage of radix R, in place on A (element i of line w at A[i P + w], the
+// row pitch P >= W):
 // every thread first reads all the butterflies it owns into registers, the block
 // synchronises, then the results are written back.  twl: the twiddles e^{-2 pi i t/n}.
 template <typename T, int R, int SIGN>
-__device__ __forceinline__ void fft_stage(cpx<T>* A, const cpx<T>* __restrict__ twl, int W, int lw, int nR, int Ns,
-                                          unsigned mNs, int tws) {
+__device__ __forceinline__ void fft_stage(cpx<T>* A, const cpx<T>* __restrict__ twl, int W, int lw, int P, int nR,
+                                          int Ns, unsigned mNs, int tws) {
     constexpr int MAXB = (kFFTCap<T> / R + kFFTThreads - 1) / kFFTThreads;
     const int nb = nR * W;
     cpx<T> o[MAXB][R];
@@ -140,7 +194,7 @@ __device__ __forceinline__ void fft_stage(cpx<T>* A, const cpx<T>* __restrict__ 
             const int k = j - g * Ns;
             cpx<T> v[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[r] = A[(j + r * nR) * W + w];
+            for (int r = 0; r < R; ++r) v[r] = A[(j + r * nR) * P + w];
             if (Ns > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
@@ -150,7 +204,7 @@ __device__ __forceinline__ void fft_stage(cpx<T>* A, const cpx<T>* __restrict__ 
                 }
             }
             small_dft<T, R, SIGN>(v, o[b]);
-            dst[b] = (g * Ns * R + k) * W + w;
+            dst[b] = (g * Ns * R + k) * P + w;
         }
     }
     __syncthreads();
@@ -158,30 +212,26 @@ __device__ __forceinline__ void fft_stage(cpx<T>* A, const cpx<T>* __restrict__ 
     for (int b = 0; b < MAXB; ++b)
         if (dst[b] >= 0) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) A[dst[b] + r * Ns * W] = o[b][r];
+            for (int r = 0; r < R; ++r) A[dst[b] + r * Ns * P] = o[b][r];
         }
     __syncthreads();
 }
 
-// In-LDS transform of W interleaved lines (W a power of two, n W <= kFFTCap).  The
-// caller synchronises before (data in A) and may read A after the return.
+// In-LDS transform of W interleaved lines (W a power of two, n W <= kFFTCap; element i
+// of line w at A[i P + w]).  The caller synchronises before (data in A) and may read A
+// after the return.
 template <typename T, int SIGN>
-__device__ void lds_fft(cpx<T>* A, const cpx<T>* __restrict__ twl, int W, const FFTDev& f) {
+__device__ void lds_fft(cpx<T>* A, const cpx<T>* __restrict__ twl, int W, int P, const FFTDev& f) {
     const int lw = __ffs(W) - 1;
     for (int s = 0; s < f.nstages; ++s) {
         switch (f.radix[s]) {
-            case 4: fft_stage<T, 4, SIGN>(A, twl, W, lw, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
-            case 2: fft_stage<T, 2, SIGN>(A, twl, W, lw, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
-            case 3: fft_stage<T, 3, SIGN>(A, twl, W, lw, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
-            case 5: fft_stage<T, 5, SIGN>(A, twl, W, lw, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
-            default: fft_stage<T, 7, SIGN>(A, twl, W, lw, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
+            case 4: fft_stage<T, 4, SIGN>(A, twl, W, lw, P, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
+            case 2: fft_stage<T, 2, SIGN>(A, twl, W, lw, P, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
+            case 3: fft_stage<T, 3, SIGN>(A, twl, W, lw, P, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
+            case 5: fft_stage<T, 5, SIGN>(A, twl, W, lw, P, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
+            default: fft_stage<T, 7, SIGN>(A, twl, W, lw, P, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
         }
     }
-}
-
-template <typename T>
-__device__ __forceinline__ void load_twiddles(cpx<T>* twl, const cpx<T>* __restrict__ tw, int n) {
-    for (int t = threadIdx.x; t < n; t += kFFTThreads) twl[t] = tw[t];
 }
 
 // lines per block: a power of two, n W <= kFFTCap, at most 16
@@ -192,69 +242,108 @@ int lines_per_block(int n) {
     return W;
 }
 
-// 1. real-to-complex along z for W lines per block.  m = I_z*/2.
+// 1. real-to-complex along z for W lines per block.  m = I_z*/2 packed pairs per line;
+// only the pairs [t0, t0 + span) can be nonzero (the planes windows reach), the others
+// are zero rows of the batch.  LDS rows have pitch W + 1, so the line-to-row transpose of
+// the load and the k-ordered reads of the split hit distinct banks.
 template <typename T>
 __global__ __launch_bounds__(kFFTThreads) void k_fft_z_r2c(const T* __restrict__ grid, cpx<T>* __restrict__ cg,
-                                                           int nlines, int Izs, int Kz, int Kzs, int W, FFTDev f,
-                                                           const cpx<T>* __restrict__ tw,
+                                                           int nlines, int Izs, int Kzs, int W, int t0, UDiv span,
+                                                           UDiv m1, FFTDev f, const cpx<T>* __restrict__ tw,
                                                            const cpx<T>* __restrict__ twpost) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int m = f.n;
-    cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* twl = A + m * W;
+    const int m = f.n, P = W + 1, lw = __ffs(W) - 1;
+    cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);  // (m + 1) rows of pitch P
+    cpx<T>* twl = A + (m + 1) * P;                     // m
+    cpx<T>* tpl = twl + m;                             // m + 1
     const int line0 = blockIdx.x * W;
-    load_twiddles(twl, tw, m);
-    for (int w = 0; w < W; ++w) {
-        const int line = line0 + w;
-        const cpx<T>* row = reinterpret_cast<const cpx<T>*>(grid + (size_t)min(line, nlines - 1) * Izs);
-        for (int t = threadIdx.x; t < m; t += kFFTThreads) A[t * W + w] = (line < nlines) ? row[t] : cpx<T>{0, 0};
+    const size_t hz = (size_t)(Izs / 2);
+    const cpx<T>* rows = reinterpret_cast<const cpx<T>*>(grid);
+    for (int idx = threadIdx.x; idx < (m - span.d) * W; idx += kFFTThreads) {
+        const int rr = idx >> lw, w = idx & (W - 1);
+        A[(rr < t0 ? rr : rr + span.d) * P + w] = cpx<T>{0, 0};
     }
+    stage_in<T>(A, span.d * W,
+                [&](int e) {
+                    const int w = udiv(e, span);
+                    return rows[(size_t)min(line0 + w, nlines - 1) * hz + t0 + (e - w * span.d)];
+                },
+                [&](int e) {
+                    const int w = udiv(e, span);
+                    return (t0 + e - w * span.d) * P + w;
+                },
+                [&] {
+                    copy_in<4>(twl, tw, m);
+                    copy_in<4>(tpl, twpost, m + 1);
+                });
     __syncthreads();
-    lds_fft<T, -1>(A, twl, W, f);
-    for (int w = 0; w < W; ++w) {
+    lds_fft<T, -1>(A, twl, W, P, f);
+    // half spectrum k = 0..m of each line, k fastest
+    for (int e = threadIdx.x; e < m1.d * W; e += kFFTThreads) {
+        const int w = udiv(e, m1), k = e - w * m1.d;
         const int line = line0 + w;
-        if (line >= nlines) break;
-        for (int k = threadIdx.x; k <= m; k += kFFTThreads) {
-            const cpx<T> zk = A[(k == m ? 0 : k) * W + w];
-            const cpx<T> zmk = cconj(A[(k == 0 ? 0 : m - k) * W + w]);
-            const cpx<T> e = {(zk.x + zmk.x) * (T)0.5, (zk.y + zmk.y) * (T)0.5};
-            const cpx<T> dd = csub(zk, zmk);
-            const cpx<T> o = {dd.y * (T)0.5, -dd.x * (T)0.5};  // (zk - zmk) / (2i)
-            cg[(size_t)line * Kzs + k] = cadd(e, cmul(twpost[k], o));
-        }
+        if (line >= nlines) break;  // e grows: every later element is past nlines too
+        const cpx<T> zk = A[(k == m ? 0 : k) * P + w];
+        const cpx<T> zmk = cconj(A[(k == 0 ? 0 : m - k) * P + w]);
+        const cpx<T> ev = {(zk.x + zmk.x) * (T)0.5, (zk.y + zmk.y) * (T)0.5};
+        const cpx<T> dd = csub(zk, zmk);
+        const cpx<T> od = {dd.y * (T)0.5, -dd.x * (T)0.5};  // (zk - zmk) / (2i)
+        cg[(size_t)line * Kzs + k] = cadd(ev, cmul(tpl[k], od));
     }
 }
 
-// 5. complex-to-real along z (unnormalised inverse).
+// Z_k of the packed inverse from X_k and conj X_{m-k}: (X_k + conj X_{m-k}) + i (X_k -
+// conj X_{m-k}) e^{+2 pi i k / I_z*}
+template <typename T>
+__device__ __forceinline__ cpx<T> c2r_pre(cpx<T> xk, cpx<T> xmkc, cpx<T> tp) {
+    const cpx<T> ev = cadd(xk, xmkc);
+    const cpx<T> od = cmulc(csub(xk, xmkc), tp);
+    return cpx<T>{ev.x - od.y, ev.y + od.x};
+}
+
+// 5. complex-to-real along z (unnormalised inverse); only the pairs [t0, t0 + span) are
+// stored (the planes the gathering reads).
 template <typename T>
 __global__ __launch_bounds__(kFFTThreads) void k_fft_z_c2r(const cpx<T>* __restrict__ cg, T* __restrict__ grid,
-                                                           int nlines, int Izs, int Kz, int Kzs, int W, FFTDev f,
-                                                           const cpx<T>* __restrict__ tw,
+                                                           int nlines, int Izs, int Kzs, int W, int t0, UDiv span,
+                                                           UDiv m1, FFTDev f, const cpx<T>* __restrict__ tw,
                                                            const cpx<T>* __restrict__ twpost) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int m = f.n;
+    const int m = f.n, P = W + 1, lw = __ffs(W) - 1;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* twl = A + m * W;
+    cpx<T>* twl = A + (m + 1) * P;
+    cpx<T>* tpl = twl + m;
     const int line0 = blockIdx.x * W;
-    load_twiddles(twl, tw, m);
-    for (int w = 0; w < W; ++w) {
-        const int line = line0 + w;
-        const cpx<T>* row = cg + (size_t)min(line, nlines - 1) * Kzs;
-        for (int k = threadIdx.x; k < m; k += kFFTThreads) {
-            const cpx<T> xk = row[k];
-            const cpx<T> xmk = cconj(row[m - k]);
-            const cpx<T> e = cadd(xk, xmk);
-            const cpx<T> o = cmulc(csub(xk, xmk), twpost[k]);  // times e^{+2 pi i k / I_z*}
-            A[k * W + w] = (line < nlines) ? cpx<T>{e.x - o.y, e.y + o.x} : cpx<T>{0, 0};  // e + i o
-        }
+    const size_t hz = (size_t)(Izs / 2);
+    stage_in<T>(A, m1.d * W,
+                [&](int e) {
+                    const int w = udiv(e, m1);
+                    return cg[(size_t)min(line0 + w, nlines - 1) * Kzs + (e - w * m1.d)];
+                },
+                [&](int e) {
+                    const int w = udiv(e, m1);
+                    return (e - w * m1.d) * P + w;
+                },
+                [&] {
+                    copy_in<4>(twl, tw, m);
+                    copy_in<4>(tpl, twpost, m + 1);
+                });
+    __syncthreads();
+    // in place, pair (k, m - k) by one thread; row m holds X_m, the partner of k = 0
+    for (int idx = threadIdx.x; idx < (m / 2 + 1) * W; idx += kFFTThreads) {
+        const int k = idx >> lw, w = idx & (W - 1);
+        const cpx<T> a = A[k * P + w], b = A[(m - k) * P + w];
+        A[k * P + w] = c2r_pre(a, cconj(b), tpl[k]);
+        if (k > 0 && 2 * k != m) A[(m - k) * P + w] = c2r_pre(b, cconj(a), tpl[m - k]);
     }
     __syncthreads();
-    lds_fft<T, +1>(A, twl, W, f);
-    for (int w = 0; w < W; ++w) {
+    lds_fft<T, +1>(A, twl, W, P, f);
+    cpx<T>* rows = reinterpret_cast<cpx<T>*>(grid);
+    for (int e = threadIdx.x; e < span.d * W; e += kFFTThreads) {
+        const int w = udiv(e, span), t = t0 + e - w * span.d;
         const int line = line0 + w;
         if (line >= nlines) break;
-        cpx<T>* row = reinterpret_cast<cpx<T>*>(grid + (size_t)line * Izs);
-        for (int t = threadIdx.x; t < m; t += kFFTThreads) row[t] = A[t * W + w];
+        rows[(size_t)line * hz + t] = A[t * P + w];
     }
 }
 
@@ -269,17 +358,19 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_y(cpx<T>* __restrict__ cg, 
     const int ix = blockIdx.x / nkb, kz0 = (blockIdx.x % nkb) * W;
     if (ix >= Ix) return;
     const int lw = __ffs(W) - 1;
-    load_twiddles(twl, tw, Iy);
     cpx<T>* base = cg + (size_t)ix * Iy * Kzs + kz0;
-    for (int idx = threadIdx.x; idx < Iy * W; idx += kFFTThreads) {
-        const int w = idx & (W - 1), iy = idx >> lw;
-        A[idx] = (kz0 + w < Kz) ? base[(size_t)iy * Kzs + w] : cpx<T>{0, 0};
-    }
+    const int nw = min(W, Kz - kz0);
+    stage_in<T>(A, Iy * W,
+                [&](int e) {
+                    const int w = e & (W - 1);
+                    return (w < nw) ? base[(size_t)(e >> lw) * Kzs + w] : cpx<T>{0, 0};
+                },
+                [&](int e) { return e; }, [&] { copy_in<4>(twl, tw, Iy); });
     __syncthreads();
-    lds_fft<T, SIGN>(A, twl, W, f);
+    lds_fft<T, SIGN>(A, twl, W, W, f);
     for (int idx = threadIdx.x; idx < Iy * W; idx += kFFTThreads) {
         const int w = idx & (W - 1), iy = idx >> lw;
-        if (kz0 + w < Kz) base[(size_t)iy * Kzs + w] = A[idx];
+        if (w < nw) base[(size_t)iy * Kzs + w] = A[idx];
     }
 }
 
@@ -303,19 +394,24 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_scale(cpx<T>* __restrict_
     const int lw = __ffs(W) - 1;
     const size_t stride = (size_t)Iy * Kzs;
     cpx<T>* base = cg + (size_t)iy * Kzs + kz0;
-    load_twiddles(twl, tw, Ix);
-    for (int idx = threadIdx.x; idx < Ix * W; idx += kFFTThreads) {
-        const int w = idx & (W - 1), ix = idx >> lw;
-        A[idx] = (kz0 + w < Kz) ? base[ix * stride + w] : cpx<T>{0, 0};
-    }
-    for (int idx = threadIdx.x; idx < nl * W; idx += kFFTThreads) {
-        const int w = idx & (W - 1), l = idx >> lw;
-        const int kz = min(kz0 + w, Kz - 1);
-        cyz[idx] = cl[l] * ay[l * Iy + iy] * az[l * Kz + kz];
-    }
-    for (int idx = threadIdx.x; idx < nl * Ix; idx += kFFTThreads) axl[idx] = ax[idx];
+    const int nw = min(W, Kz - kz0);
+    stage_in<T>(A, Ix * W,
+                [&](int e) {
+                    const int w = e & (W - 1);
+                    return (w < nw) ? base[(size_t)(e >> lw) * stride + w] : cpx<T>{0, 0};
+                },
+                [&](int e) { return e; },
+                [&] {
+                    copy_in<4>(twl, tw, Ix);
+                    copy_in<16>(axl, ax, nl * Ix);
+                    for (int idx = threadIdx.x; idx < nl * W; idx += kFFTThreads) {
+                        const int w = idx & (W - 1), l = idx >> lw;
+                        const int kz = min(kz0 + w, Kz - 1);
+                        cyz[idx] = cl[l] * ay[l * Iy + iy] * az[l * Kz + kz];
+                    }
+                });
     __syncthreads();
-    lds_fft<T, -1>(A, twl, W, f);
+    lds_fft<T, -1>(A, twl, W, W, f);
     for (int idx = threadIdx.x; idx < Ix * W; idx += kFFTThreads) {
         const int w = idx & (W - 1), ix = idx >> lw;
         T mlt = 0;
@@ -326,10 +422,10 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_scale(cpx<T>* __restrict_
         A[idx] = v;
     }
     __syncthreads();
-    lds_fft<T, +1>(A, twl, W, f);
+    lds_fft<T, +1>(A, twl, W, W, f);
     for (int idx = threadIdx.x; idx < Ix * W; idx += kFFTThreads) {
         const int w = idx & (W - 1), ix = idx >> lw;
-        if (kz0 + w < Kz) base[ix * stride + w] = A[idx];
+        if (w < nw) base[(size_t)ix * stride + w] = A[idx];
     }
 }
 
@@ -346,15 +442,16 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_lines(cpx<T>* __restrict__ 
     cpx<T>* twl = A + n * W;
     const int line0 = blockIdx.x * W;
     const int lw = __ffs(W) - 1;
-    load_twiddles(twl, tw, n);
-    for (int idx = threadIdx.x; idx < n * W; idx += kFFTThreads) {
-        const int w = idx & (W - 1), e = idx >> lw, line = line0 + w;
-        cpx<T> v = {0, 0};
-        if (line < nlines) v = d[(size_t)(line / ncols) * outer_stride + (size_t)(line % ncols) * col_stride + (size_t)e * elem_stride];
-        A[idx] = v;
-    }
+    stage_in<T>(A, n * W,
+                [&](int idx) {
+                    const int line = line0 + (idx & (W - 1));
+                    return (line < nlines) ? d[(size_t)(line / ncols) * outer_stride + (size_t)(line % ncols) * col_stride +
+                                               (size_t)(idx >> lw) * elem_stride]
+                                           : cpx<T>{0, 0};
+                },
+                [&](int idx) { return idx; }, [&] { copy_in<4>(twl, tw, n); });
     __syncthreads();
-    lds_fft<T, SIGN>(A, twl, W, f);
+    lds_fft<T, SIGN>(A, twl, W, W, f);
     for (int idx = threadIdx.x; idx < n * W; idx += kFFTThreads) {
         const int w = idx & (W - 1), e = idx >> lw, line = line0 + w;
         if (line < nlines)
@@ -374,21 +471,27 @@ hipError_t run_fft_mid(Plan& p) {
     hipError_t e;
     if ((size_t)m > (size_t)kFFTCap<T> || (size_t)Ix > (size_t)kFFTCap<T> || (size_t)Iy > (size_t)kFFTCap<T>)
         return hipErrorInvalidConfiguration;
-    // 1. z forward
-    const int Wz = lines_per_block<T>(m);
-    const size_t ldsz = (size_t)m * (Wz + 1) * ce;
+    // 1. z forward: W lines per block, LDS rows of pitch W + 1 (plus row m) and the two
+    // twiddle tables
+    const int t0 = r.zband[0] / 2, span = (r.zband[1] - r.zband[0]) / 2;
+    if (span < 2 || t0 + span > m) return hipErrorInvalidConfiguration;
+    auto ldsz_of = [&](int w) { return ((size_t)(m + 1) * (w + 1) + 2 * (size_t)m + 1) * ce; };
+    int Wz = lines_per_block<T>(m + 1);  // the inverse's batch holds rows 0..m
+    while (Wz > 1 && ldsz_of(Wz) > budget) Wz >>= 1;
+    const size_t ldsz = ldsz_of(Wz);
     if (ldsz > budget) return hipErrorInvalidConfiguration;
     {
         int t = timer_id(p, "fft_z_fwd");
         timer_begin(p, t);
         k_fft_z_r2c<T><<<(nlines + Wz - 1) / Wz, kFFTThreads, ldsz, p.stream>>>(
-            (const T*)ws.grid, (cpx<T>*)ws.cgrid, nlines, Izs, Kz, Kzs, Wz, to_dev(p.fz), (const cpx<T>*)ws.tw_z,
-            (const cpx<T>*)ws.tw_zpost);
+            (const T*)ws.grid, (cpx<T>*)ws.cgrid, nlines, Izs, Kzs, Wz, t0, make_udiv(span), make_udiv(m + 1),
+            to_dev(p.fz), (const cpx<T>*)ws.tw_z, (const cpx<T>*)ws.tw_zpost);
         timer_end(p, t);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     // 2. y forward
-    const int Wy = lines_per_block<T>(Iy);
+    int Wy = lines_per_block<T>(Iy);
+    while (Wy > 1 && (size_t)Iy * (Wy + 1) * ce > budget) Wy >>= 1;
     const size_t ldsy = (size_t)Iy * (Wy + 1) * ce;
     if (ldsy > budget) return hipErrorInvalidConfiguration;
     const int nby = Ix * ((Kz + Wy - 1) / Wy);
@@ -431,8 +534,8 @@ hipError_t run_fft_mid(Plan& p) {
         int t = timer_id(p, "fft_z_inv");
         timer_begin(p, t);
         k_fft_z_c2r<T><<<(nlines + Wz - 1) / Wz, kFFTThreads, ldsz, p.stream>>>(
-            (const cpx<T>*)ws.cgrid, (T*)ws.grid, nlines, Izs, Kz, Kzs, Wz, to_dev(p.fz), (const cpx<T>*)ws.tw_z,
-            (const cpx<T>*)ws.tw_zpost);
+            (const cpx<T>*)ws.cgrid, (T*)ws.grid, nlines, Izs, Kzs, Wz, t0, make_udiv(span), make_udiv(m + 1),
+            to_dev(p.fz), (const cpx<T>*)ws.tw_z, (const cpx<T>*)ws.tw_zpost);
         timer_end(p, t);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -448,7 +551,7 @@ hipError_t launch_fft_lines(Plan& p, void* data, const FFTFactors& f, const void
     const int cap = f64 ? kFFTCap<double> : kFFTCap<float>;
     int Wp = 1;
     while (Wp * 2 <= W) Wp *= 2;  // a power of two
-    while (Wp > 1 && (size_t)f.n * Wp > (size_t)cap) Wp >>= 1;
+    while (Wp > 1 && ((size_t)f.n * Wp > (size_t)cap || (size_t)f.n * (Wp + 1) * ce > 65536)) Wp >>= 1;
     const size_t lds = (size_t)f.n * (Wp + 1) * ce;
     if (f.n > cap || lds > 65536 || nlines <= 0) return hipErrorInvalidConfiguration;
     const int nb = (nlines + Wp - 1) / Wp;

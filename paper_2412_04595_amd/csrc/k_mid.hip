@@ -26,6 +26,7 @@ struct MidGeom {
     int B[3];
     int nt[3];
     int HW;     // (P_w - 1) / 2
+    int zlo, zhi;  // z planes that may carry window mass
 };
 
 __device__ __forceinline__ void grid_point(const MidGeom& g, double x, double y, double z, int a[3], double u[3]) {
@@ -41,7 +42,7 @@ __device__ __forceinline__ void grid_point(const MidGeom& g, double x, double y,
         if (d < 2) {
             a[d] = imod(k, g.I[d]);
         } else {
-            a[d] = min(max(k, g.HW), g.I[2] - 1 - g.HW);  // only invalid input hits the clamp
+            a[d] = min(max(k, g.zlo + g.HW), g.zhi - 1 - g.HW);  // only invalid input hits the clamp
             if (k != a[d]) u[d] = 0.0;
         }
     }
@@ -291,6 +292,18 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
     }
 }
 
+// zero planes [zlo, zlo + 2 span2) of every (x, y) line of the real grid, one wave per
+// line (the other planes are never read or written)
+template <typename real>
+__global__ __launch_bounds__(256) void k_zero_band(real* __restrict__ grid, int nlines, int Izs, int zlo, int span2) {
+    struct alignas(2 * sizeof(real)) pair { real a, b; };
+    const int lane = threadIdx.x & 63;
+    for (int line = blockIdx.x * 4 + (threadIdx.x >> 6); line < nlines; line += gridDim.x * 4) {
+        pair* row = reinterpret_cast<pair*>(grid + (size_t)line * Izs + zlo);
+        for (int c = lane; c < span2; c += 64) row[c] = pair{0, 0};
+    }
+}
+
 template <typename real>
 struct GatherArgs {
     const int4* gp;
@@ -407,7 +420,10 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         a.inv_hw2 = inv_hw2;
         const size_t lds = spread_lds_bytes(sizeof(real), PW, r.B[0], r.B[1], r.B[2]);
         if (lds > 65536) return hipErrorInvalidConfiguration;
-        hipError_t e = launch_fill_bytes_zero(ws.grid, (size_t)r.I[0] * r.I[1] * r.Izs * sizeof(real), p.stream);
+        const int nlines = r.I[0] * r.I[1];
+        k_zero_band<real><<<std::min((nlines + 3) / 4, 16384), 256, 0, p.stream>>>(
+            (real*)ws.grid, nlines, r.Izs, r.zband[0], (r.zband[1] - r.zband[0]) / 2);
+        hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         k_spread<real, PW><<<xcd_grid(ntiles), kSpreadThreads, lds, p.stream>>>(a);
     } else {
@@ -461,6 +477,8 @@ MidGeom mid_geom(const Resolved& r) {
     g.I[1] = r.I[1];
     g.I[2] = r.Izs;
     g.HW = (r.Pw - 1) / 2;
+    g.zlo = r.zband[0];
+    g.zhi = r.zband[1];
     return g;
 }
 

@@ -535,6 +535,15 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         for (int d = 0; d < 3; ++d) r.h[d] = r.L[d] / r.I[d];
         r.Lzs = r.Izs * r.h[2];
         for (int d = 0; d < 3; ++d) r.H[d] = 0.5 * (r.Pw - 1) * r.h[d];
+        {
+            // nearest nodes of z in [0, L_z] lie in [(I_z* - I_z)/2, (I_z* + I_z)/2]; one node
+            // of slack on each side, then the window half-width
+            const int HWz = (r.Pw - 1) / 2;
+            const int lo = (r.Izs - r.I[2]) / 2 - 1 - HWz;
+            const int hi = (r.Izs + r.I[2] + 1) / 2 + 2 + HWz;
+            r.zband[0] = std::max(0, lo) & ~1;
+            r.zband[1] = std::min(r.Izs, (hi + 1) & ~1);
+        }
         // tiles: LDS holds the tile plus its (P_w - 1) halo for gridding and gathering;
         // gridding adds each tile's block into the grid with atomics, so any tile count works
         int Bt[3];
@@ -548,6 +557,10 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         if (!is_smooth(r.I[0]) || !is_smooth(r.I[1]) || !is_smooth(r.Izs / 2)) { err = "mid grid sizes must have only factors 2, 3, 5, 7 (and I_z*/2 as well)"; return SOG_ERR_INVALID_ARG; }
         if (r.I[0] % 2 || r.I[1] % 2) { err = "mid I_x, I_y must be even"; return SOG_ERR_INVALID_ARG; }
         if (r.I[0] > 4096 || r.I[1] > 4096 || r.Izs > 8192) { err = "mid grid too large"; return SOG_ERR_INVALID_ARG; }
+        if (std::max(std::max(r.I[0], r.I[1]), r.Izs / 2) > fft_max_line(r.prec)) {
+            err = "mid grid line too long for the FFT kernels in this precision";
+            return SOG_ERR_INVALID_ARG;
+        }
     }
     if (r.has_long) {
         if (r.P < 1 || r.P > 64) { err = "long P out of range"; return SOG_ERR_INVALID_ARG; }
@@ -557,6 +570,7 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         } else {
             if (r.Pw2 < 3 || r.I2[0] < r.Pw2 || r.I2[1] < r.Pw2) { err = "long-range FFT grid smaller than its window"; return SOG_ERR_INVALID_ARG; }
             if (!is_smooth(r.I2[0]) || !is_smooth(r.I2[1])) { err = "long-range grid sizes must have only factors 2, 3, 5, 7"; return SOG_ERR_INVALID_ARG; }
+            if (std::max(r.I2[0], r.I2[1]) > fft_max_line(r.prec)) { err = "long-range grid line too long for the FFT kernels in this precision"; return SOG_ERR_INVALID_ARG; }
             for (int a = 0; a < 2; ++a) {
                 r.h2[a] = r.L[a] / r.I2[a];
                 r.H2[a] = 0.5 * (r.Pw2 - 1) * r.h2[a];
