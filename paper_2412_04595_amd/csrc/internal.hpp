@@ -22,9 +22,13 @@ constexpr int kSpreadStage = 32;  // particles whose window weights the gridding
 // its x weights rotated for the four plane groups (16 reals); then, on a 32-byte boundary,
 // the staged particles' offsets from their grid points and charges (real4 each), the four
 // groups' plane offsets (int4) and the x nodes (int).
+// LDS of the gridding kernel: the tile's halo block plus 4 ceil(P_w / 4) - P_w padding
+// planes, 64 sink slots, the staged weights (kSpreadStage x (2 P_w + 1 + 16) reals), then
+// 32-byte aligned particle records.
 inline size_t spread_lds_offset_records(size_t real_bytes, int Pw, int Bx, int By, int Bz) {
-    const size_t tot = (size_t)(Bx + Pw - 1) * (By + Pw - 1) * (Bz + Pw - 1);
-    return ((tot + 64 + (size_t)kSpreadStage * (2 * Pw + 16)) * real_bytes + 31) / 32 * 32;
+    const size_t plane = (size_t)(By + Pw - 1) * (Bz + Pw - 1);
+    const size_t tot = (size_t)(Bx + Pw - 1 + 4 * ((Pw + 3) / 4) - Pw) * plane;
+    return ((tot + 64 + (size_t)kSpreadStage * (2 * Pw + 17)) * real_bytes + 31) / 32 * 32;
 }
 inline size_t spread_lds_bytes(size_t real_bytes, int Pw, int Bx, int By, int Bz) {
     return spread_lds_offset_records(real_bytes, Pw, Bx, By, Bz) + (size_t)kSpreadStage * (4 * real_bytes + 20);
@@ -83,6 +87,7 @@ struct Resolved {
     // (-1: none), chosen so that the 64 nodes of a pass fall in distinct LDS banks
     signed char node_oy[4 * 64] = {0};
     signed char node_oz[4 * 64] = {0};
+    bool spread_dummy = false;  // every lane without a node has a dummy node (oz >= P_w)
     int ntile[3] = {0, 0, 0};
 
     // long range (Sec. 3.3 / App. B)

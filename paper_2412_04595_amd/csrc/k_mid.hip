@@ -128,16 +128,22 @@ struct SpreadArgs {
 // (y, z) nodes, so within a particle the lanes touch distinct nodes and no two waves ever
 // touch the same node; each wave walks the staged particles in order without
 // synchronising with the others.  Per staged particle the batch holds its y and z
-// weights, its x weights already rotated to each wave's planes and each wave's offset of
-// its first plane, so a wave's reads of the next particle do not depend on each other and
-// are issued before the current particle's writes.  Lanes with nothing to update read and
-// write a private sink slot instead of branching.
-template <typename real, int PW>
+// weights, its x weights already rotated to each wave's planes and each wave's byte
+// offset of its first plane, so a wave's reads of the next particle do not depend on each
+// other and are issued before the current particle's writes.  Every wave updates
+// ceil(P_w / 4) planes x P_w^2-node passes per particle without branching: a plane past
+// the window has zero weight (it is one of the wave's own planes, possibly one of the
+// padding planes after the block), and a lane without a node in a pass updates, with
+// zero weight, a dummy node of the same plane that no window node uses (DUMMY) or its
+// private sink slot.
+template <typename real, int PW, bool DUMMY>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int HW = (PW - 1) / 2;
     constexpr int NPASS = (PW * PW + 63) / 64;   // groups of 64 (y, z) window nodes
     constexpr int NPL = (PW + 3) / 4;            // x planes of a window per wave (at most)
+    constexpr int NPAD = 4 * NPL - PW;           // padding planes after the block
+    constexpr int NW = 2 * PW + 1;               // staged y, z weights and a zero per particle
     static_assert(NPL <= 4, "window too wide for four plane groups");
     const int t = xcd_logical_block(a.ntiles);
     if (t < 0) return;
@@ -147,29 +153,34 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
     const int x0 = tx * a.B[0], y0 = ty * a.B[1], z0 = tz * a.B[2];
     const int HX = a.B[0] + PW - 1, HY = a.B[1] + PW - 1, HZ = a.B[2] + PW - 1;
     const int HYZ = HY * HZ;
-    const int tot = HX * HYZ;
+    const int totp = (HX + NPAD) * HYZ;
     real* halo = reinterpret_cast<real*>(smem_raw);
-    const int sink0 = tot;                         // 64 sink slots
-    real* wyzs = halo + tot + 64;                  // kSpreadStage x 2 PW: wy, wz
-    real* wxs = wyzs + kSpreadStage * 2 * PW;      // kSpreadStage x 16: q wx rotated per wave
-    const size_t rec_off = ((((size_t)tot + 64 + (size_t)kSpreadStage * (2 * PW + 16)) * sizeof(real)) + 31) & ~(size_t)31;
+    unsigned char* hb = smem_raw;                  // byte view: node offsets are LDS addresses
+    real* wyzs = halo + totp + 64;                 // kSpreadStage x NW: wy, wz, 0
+    real* wxs = wyzs + kSpreadStage * NW;          // kSpreadStage x 16: q wx rotated per wave
+    const size_t rec_off = ((((size_t)totp + 64 + (size_t)kSpreadStage * (NW + 16)) * sizeof(real)) + 31) & ~(size_t)31;
     vec4<real>* sup = reinterpret_cast<vec4<real>*>(smem_raw + rec_off);  // kSpreadStage: u, q
-    int4* meta = reinterpret_cast<int4*>(sup + kSpreadStage);  // per wave: first plane offset, plane count
+    int4* meta = reinterpret_cast<int4*>(sup + kSpreadStage);  // per wave: byte offset of its first plane
     int* slx = reinterpret_cast<int*>(meta + kSpreadStage);      // x node of the particle in the block
-    for (int k = threadIdx.x; k < tot + 64; k += kSpreadThreads) halo[k] = 0;
+    for (int k = threadIdx.x; k < totp + 64; k += kSpreadThreads) halo[k] = 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int planestep = 4 * HYZ;
     // this lane's (y, z) node of the window in each pass (chosen by the planner so that
-    // the 64 lanes of a pass hit distinct LDS banks for any window corner)
-    int oyz[NPASS], oy2[NPASS], oz2[NPASS];
+    // the 64 lanes of a pass hit distinct LDS banks for any window corner), as byte
+    // offsets per plane; its y and z weight slots (the zero slot for a dummy node)
+    int off[NPL][NPASS], oy2[NPASS], oz2[NPASS];
+    bool has[NPASS];
 #pragma unroll
     for (int ps = 0; ps < NPASS; ++ps) {
         const int oy = a.nodes[ps * 64 + lane], oz = a.nodes[256 + ps * 64 + lane];
-        const bool in = oy >= 0;
-        oy2[ps] = in ? oy : 0;
-        oz2[ps] = in ? PW + oz : PW;
-        oyz[ps] = in ? oy * HZ + oz : -1;
+        has[ps] = oy >= 0;
+        oy2[ps] = has[ps] ? oy : 0;
+        oz2[ps] = (has[ps] && oz < PW) ? PW + oz : 2 * PW;
+        const int o = has[ps] ? oy * HZ + oz : 0;
+#pragma unroll
+        for (int pl = 0; pl < NPL; ++pl) off[pl][ps] = (pl * planestep + o) * (int)sizeof(real);
     }
-    const int planestep = 4 * HYZ;
+    const int sinkb = (totp + lane) * (int)sizeof(real);
     // the first kSpreadStage threads hold the next batch's particles, loaded one batch ahead
     int4 gq = int4{0, 0, 0, 0};
     vec4<real> uq = vec4<real>{0, 0, 0, 0};
@@ -185,10 +196,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
             const int corner = lx0 * HYZ + (gq.y - y0) * HZ + (gq.z - z0);
             int m[4];
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int ox0 = (g - lx0) & 3;
-                m[g] = ((corner + ox0 * HYZ) << 3) | ((PW - ox0 + 3) >> 2);  // planes: ceil((PW - ox0) / 4)
-            }
+            for (int g = 0; g < 4; ++g) m[g] = (corner + ((g - lx0) & 3) * HYZ) * (int)sizeof(real);
             meta[threadIdx.x] = int4{m[0], m[1], m[2], m[3]};
             slx[threadIdx.x] = lx0;
             sup[threadIdx.x] = uq;
@@ -201,14 +209,15 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
             }
         }
         __syncthreads();
-        // y, z weights; per wave g the x weights of its planes (x = g mod 4)
-        for (int idx = threadIdx.x; idx < cnt * (2 * PW + 16); idx += kSpreadThreads) {
-            if (idx < cnt * 2 * PW) {
-                const int i = idx / (2 * PW), r = idx - i * 2 * PW;
+        // y, z weights and a zero; per wave g the x weights of its planes (x = g mod 4)
+        for (int idx = threadIdx.x; idx < cnt * (NW + 16); idx += kSpreadThreads) {
+            if (idx < cnt * NW) {
+                const int i = idx / NW, r = idx - i * NW;
                 const vec4<real> u = sup[i];
-                wyzs[idx] = win<real, PW>(r < PW ? r : r - PW, r < PW ? u.y : u.z, a.S, a.inv_hw2);
+                wyzs[idx] = (r < 2 * PW) ? win<real, PW>(r < PW ? r : r - PW, r < PW ? u.y : u.z, a.S, a.inv_hw2)
+                                         : (real)0;
             } else {
-                const int jdx = idx - cnt * 2 * PW;
+                const int jdx = idx - cnt * NW;
                 const int i = jdx >> 4, g = (jdx >> 2) & 3, pl = jdx & 3;
                 const vec4<real> u = sup[i];
                 const int ox = ((g - slx[i]) & 3) + 4 * pl;
@@ -232,7 +241,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
             }
         }
         for (int i = 0; i < cnt; ++i) {
-            const int base = mk >> 3, npl = mk & 7;
+            const int base = mk;
             real wyz[NPASS], wx[NPL];
 #pragma unroll
             for (int ps = 0; ps < NPASS; ++ps) wyz[ps] = wy[ps] * wz[ps];
@@ -244,8 +253,8 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
             for (int pl = 0; pl < NPL; ++pl)
 #pragma unroll
                 for (int ps = 0; ps < NPASS; ++ps) {
-                    at[pl][ps] = (pl < npl && oyz[ps] >= 0) ? base + pl * planestep + oyz[ps] : sink0 + lane;
-                    cur[pl][ps] = halo[at[pl][ps]];
+                    at[pl][ps] = (DUMMY || has[ps]) ? base + off[pl][ps] : sinkb;
+                    cur[pl][ps] = *reinterpret_cast<const real*>(hb + at[pl][ps]);
                 }
             {
                 const int in = min(i + 1, cnt - 1);
@@ -253,7 +262,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
                 const real* wq = wxs + in * 16 + wave * 4;
 #pragma unroll
                 for (int pl = 0; pl < 4; ++pl) wx4[pl] = wq[pl];
-                const real* wp = wyzs + in * 2 * PW;
+                const real* wp = wyzs + in * NW;
 #pragma unroll
                 for (int ps = 0; ps < NPASS; ++ps) {
                     wy[ps] = wp[oy2[ps]];
@@ -263,7 +272,8 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
 #pragma unroll
             for (int pl = 0; pl < NPL; ++pl)
 #pragma unroll
-                for (int ps = 0; ps < NPASS; ++ps) halo[at[pl][ps]] = cur[pl][ps] + wx[pl] * wyz[ps];
+                for (int ps = 0; ps < NPASS; ++ps)
+                    *reinterpret_cast<real*>(hb + at[pl][ps]) = cur[pl][ps] + wx[pl] * wyz[ps];
         }
     }
     __syncthreads();
@@ -425,7 +435,10 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
             (real*)ws.grid, nlines, r.Izs, r.zband[0], (r.zband[1] - r.zband[0]) / 2);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        k_spread<real, PW><<<xcd_grid(ntiles), kSpreadThreads, lds, p.stream>>>(a);
+        if (r.spread_dummy)
+            k_spread<real, PW, true><<<xcd_grid(ntiles), kSpreadThreads, lds, p.stream>>>(a);
+        else
+            k_spread<real, PW, false><<<xcd_grid(ntiles), kSpreadThreads, lds, p.stream>>>(a);
     } else {
         GatherArgs<real> a;
         a.gp = (const int4*)ws.mid_g;

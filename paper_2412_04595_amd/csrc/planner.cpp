@@ -6,6 +6,7 @@
 // model for this GPU in place of eq. optimiz's CPU cost ratio.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 #include <cstring>
 
 #include "internal.hpp"
@@ -120,8 +121,13 @@ void spread_tile(int prec, int Pw, int B[3]) {
 }
 
 // Lane of each window node per pass (see spread_pitch_conflict_free); when the pitch is
-// not conflict-free, nodes in row order.
-void spread_lane_nodes(int Pw, int HZ, signed char* noy, signed char* noz) {
+// not conflict-free, nodes in row order.  A lane left without a node in a pass gets, where
+// possible, a dummy node that the kernel updates with zero weight: an offset from the
+// window corner that no window node has, that stays in the corner's x plane for every
+// corner in the tile (offset <= P_w H_Z - B_z), that no other dummy uses, and preferably
+// one in the lane's own bank.  Returns false, leaving such lanes at -1, when there are
+// not enough of them.
+bool spread_lane_nodes(int Pw, int HZ, int Bz, signed char* noy, signed char* noz) {
     for (int i = 0; i < 4 * 64; ++i) noy[i] = noz[i] = -1;
     if (spread_pitch_conflict_free(Pw, HZ)) {
         int used[64] = {0};
@@ -138,6 +144,33 @@ void spread_lane_nodes(int Pw, int HZ, signed char* noy, signed char* noz) {
             noz[k] = (signed char)(k % Pw);
         }
     }
+    const int npass = (Pw * Pw + 63) / 64;
+    std::vector<int> cand;
+    for (int oy = 0; oy < Pw; ++oy)
+        for (int oz = Pw; oz < HZ; ++oz)
+            if (oy * HZ + oz <= Pw * HZ - Bz) cand.push_back(oy * HZ + oz);
+    std::vector<char> taken(cand.size(), 0);
+    std::vector<int> open;
+    for (int k = 0; k < npass * 64; ++k)
+        if (noy[k] < 0) open.push_back(k);
+    std::vector<int> pick(open.size(), -1);
+    for (int round = 0; round < 2; ++round)
+        for (size_t i = 0; i < open.size(); ++i) {
+            if (pick[i] >= 0) continue;
+            for (size_t c = 0; c < cand.size(); ++c)
+                if (!taken[c] && (round == 1 || cand[c] % 64 == open[i] % 64)) {
+                    taken[c] = 1;
+                    pick[i] = (int)c;
+                    break;
+                }
+        }
+    for (size_t i = 0; i < open.size(); ++i)
+        if (pick[i] < 0) return false;
+    for (size_t i = 0; i < open.size(); ++i) {
+        noy[open[i]] = (signed char)(cand[pick[i]] / HZ);
+        noz[open[i]] = (signed char)(cand[pick[i]] % HZ);
+    }
+    return true;
 }
 
 struct MidChoice {
@@ -553,7 +586,7 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
             r.B[d] = std::min(Bt[d], gI[d]);
             r.ntile[d] = (gI[d] + r.B[d] - 1) / r.B[d];
         }
-        spread_lane_nodes(r.Pw, r.B[2] + r.Pw - 1, r.node_oy, r.node_oz);
+        r.spread_dummy = spread_lane_nodes(r.Pw, r.B[2] + r.Pw - 1, r.B[2], r.node_oy, r.node_oz);
         if (!is_smooth(r.I[0]) || !is_smooth(r.I[1]) || !is_smooth(r.Izs / 2)) { err = "mid grid sizes must have only factors 2, 3, 5, 7 (and I_z*/2 as well)"; return SOG_ERR_INVALID_ARG; }
         if (r.I[0] % 2 || r.I[1] % 2) { err = "mid I_x, I_y must be even"; return SOG_ERR_INVALID_ARG; }
         if (r.I[0] > 4096 || r.I[1] > 4096 || r.Izs > 8192) { err = "mid grid too large"; return SOG_ERR_INVALID_ARG; }
