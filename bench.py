@@ -140,7 +140,8 @@ def cpu_baseline(tol):
     note = ""
     if t < 10.0:
         first = f"; a first sample of {Ns} took {t:.1f} s"
-        L = min(100, max(L + 1, int(round(L * (15.0 / t) ** (1.0 / 3.0)))))
+        # oracle time grows about as N^1.3 here; even side: even N
+        L = min(100, max(L + 2, 2 * int(round(L * (15.0 / t) ** (1.0 / 3.9) / 2))))
         Ns, t = timed(L)
         note = first
     return dict(value=Ns / t, unit="particles/s", cores=1, kind="oracle",
