@@ -121,7 +121,7 @@ sog_status build_plan(Plan& p) {
     A.get(ws.cell_cursor, ncells * 4);
     A.get(ws.near_orig, n * 4);
     A.get(ws.near_pos, n * 4 * rs);
-    A.get(ws.near_units, (size_t)ncells * 16);
+    A.get(ws.near_units, ((size_t)ncells * 16 + 127) / 128 * 128 + 8 * 128);  // units, then 8 work counters
     if (r.has_mid) {
         const int ntiles = r.ntile[0] * r.ntile[1] * r.ntile[2];
         maxbins = std::max<int64_t>(maxbins, ntiles);
@@ -519,6 +519,11 @@ sog_status sog_plan_ex(const double box[3], int64_t n, double tol, const sog_opt
         return SOG_ERR_INVALID_ARG;
     }
     DeviceGuard dg(p->device);
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
+            p->num_cus = cus;
+    }
     s = build_plan(*p);
     if (s != SOG_OK) {
         delete p;

@@ -136,7 +136,7 @@ struct Workspace {
     int* cell_cursor = nullptr; // ncells
     int* near_orig = nullptr;   // n
     void* near_pos = nullptr;   // n x real4 (x, y, z relative to the cell corner; q)
-    void* near_units = nullptr; // ncells x int4 work units (column, first cell, end cell)
+    void* near_units = nullptr; // ncells x int4 work units (column, first cell, end cell), then 8 work counters
     // mid range
     int* tile_start = nullptr;  // ntiles + 1 (owners)
     int* tile_cursor = nullptr; // ntiles
@@ -182,6 +182,7 @@ struct Plan {
     Resolved r;
     Workspace ws;
     int device = 0;
+    int num_cus = 256;              // compute units of the device
     hipStream_t stream = nullptr;   // the stream kernels are launched on (the caller's, or side)
     hipStream_t side = nullptr;     // plan-owned stream: near field and long range
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_grid = nullptr;

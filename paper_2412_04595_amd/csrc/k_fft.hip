@@ -387,7 +387,7 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_scale(cpx<T>* __restrict_
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* twl = A + Ix * W;
     T* cyz = reinterpret_cast<T*>(twl + Ix);  // nl x W
-    T* axl = cyz + nl * W;                    // nl x Ix
+    T* axl = cyz + nl * W;                    // nl x Ix, then kStageK (256 / W) - Ix zeros
     const int nkb = (Kz + W - 1) / W;
     const int iy = blockIdx.x / nkb, kz0 = (blockIdx.x % nkb) * W;
     if (iy >= Iy) return;
@@ -404,6 +404,8 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_scale(cpx<T>* __restrict_
                 [&] {
                     copy_in<4>(twl, tw, Ix);
                     copy_in<16>(axl, ax, nl * Ix);
+                    for (int i = threadIdx.x; i < kStageK<T> * (kFFTThreads >> lw) - Ix; i += kFFTThreads)
+                        axl[nl * Ix + i] = 0;
                     for (int idx = threadIdx.x; idx < nl * W; idx += kFFTThreads) {
                         const int w = idx & (W - 1), l = idx >> lw;
                         const int kz = min(kz0 + w, Kz - 1);
@@ -412,14 +414,31 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_scale(cpx<T>* __restrict_
                 });
     __syncthreads();
     lds_fft<T, -1>(A, twl, W, W, f);
-    for (int idx = threadIdx.x; idx < Ix * W; idx += kFFTThreads) {
-        const int w = idx & (W - 1), ix = idx >> lw;
-        T mlt = 0;
-        for (int l = 0; l < nl; ++l) mlt += axl[l * Ix + ix] * cyz[l * W + w];
-        cpx<T> v = A[idx];
-        v.x *= mlt;
-        v.y *= mlt;
-        A[idx] = v;
+    {
+        // a thread's elements share one k_z (256 is a multiple of W): per Gaussian one read
+        // of its (k_y, k_z) factor, then one read and FMA per element (the table of ax is
+        // followed by K 256 / W - I_x zeros, so the unused tail elements read inside it)
+        constexpr int K = kStageK<T>;
+        const int w = threadIdx.x & (W - 1), ix0 = threadIdx.x >> lw, dix = kFFTThreads >> lw;
+        T mlt[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) mlt[k] = 0;
+        for (int l = 0; l < nl; ++l) {
+            const T c = cyz[l * W + w];
+            const T* ar = axl + l * Ix + ix0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) mlt[k] += ar[k * dix] * c;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int idx = threadIdx.x + k * kFFTThreads;
+            if (idx < Ix * W) {
+                cpx<T> v = A[idx];
+                v.x *= mlt[k];
+                v.y *= mlt[k];
+                A[idx] = v;
+            }
+        }
     }
     __syncthreads();
     lds_fft<T, +1>(A, twl, W, W, f);
@@ -506,7 +525,9 @@ hipError_t run_fft_mid(Plan& p) {
     // 3. x forward, scale, x inverse
     {
         int W = lines_per_block<T>(Ix);
-        auto lds_of = [&](int w) { return (size_t)Ix * (w + 1) * ce + (size_t)nl * (w + Ix) * sizeof(T); };
+        auto lds_of = [&](int w) {
+            return (size_t)Ix * (w + 1) * ce + ((size_t)nl * (w + Ix) + (size_t)kStageK<T> * (kFFTThreads / w) - Ix) * sizeof(T);
+        };
         while (W > 1 && lds_of(W) > budget) W >>= 1;
         const size_t lds = lds_of(W);
         if (lds > budget) return hipErrorInvalidConfiguration;

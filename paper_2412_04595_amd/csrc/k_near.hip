@@ -96,10 +96,12 @@ __global__ void k_near_pack(const double* __restrict__ x, const double* __restri
 // consecutive units are neighbours in space.  One wave per column: the column's cell
 // starts are read in parallel into LDS, then lane 0 walks them.
 constexpr int kUnitsLds = 4096;  // cells of a column staged in LDS at a time
+constexpr int kGrabStride = 32;  // ints between the per-XCD work counters (own 128-byte lines)
 __global__ __launch_bounds__(64) void k_near_units(const int* __restrict__ cell_start, int ncz,
-                                                    int4* __restrict__ units) {
+                                                    int4* __restrict__ units, int* __restrict__ grab) {
     __shared__ int cs[kUnitsLds + 1];
     const int col = blockIdx.x;
+    if (col == 0 && threadIdx.x < 8) grab[threadIdx.x * kGrabStride] = 0;  // the pair kernel's work counters
     const int* gcs = cell_start + (size_t)col * ncz;
     int4* us = units + (size_t)col * ncz;
     int z0 = 0, u = 0;
@@ -127,6 +129,11 @@ __global__ __launch_bounds__(64) void k_near_units(const int* __restrict__ cell_
     for (int i = u + (int)threadIdx.x; i < ncz; i += 64) us[i] = make_int4(col, -1, -1, 0);
 }
 
+// the 8 work counters live after the units, on 128-byte boundaries
+inline int* near_grab(const Workspace& ws, int ncells) {
+    return reinterpret_cast<int*>(static_cast<char*>(ws.near_units) + ((size_t)ncells * 16 + 127) / 128 * 128);
+}
+
 template <typename real>
 struct NearArgs {
     const vec4<real>* __restrict__ pos;
@@ -134,6 +141,7 @@ struct NearArgs {
     const int* __restrict__ cell_start;
     vec4<real>* __restrict__ part;  // near part of each particle: phi, grad
     const int4* __restrict__ units;  // (column, first cell, end cell); first cell -1: none
+    int* grab;                       // per-XCD counters of units taken (zeroed by k_near_units)
     int max_units;
     int nc[3];
     real ch[3];
@@ -144,6 +152,10 @@ struct NearArgs {
 };
 
 constexpr int kNearWaves = 4;   // independent waves per block
+// resident near-field blocks per compute unit: the kernel is persistent, and at this
+// occupancy the FFT passes and the gathering launched on the other stream find room
+// (LDS and waves) on every compute unit beside it
+constexpr int kNearBlocksPerCU = 4;
 constexpr int kNearCap = 32;    // hit-list entries per lane (a ring; power of two)
 template <typename real>
 constexpr int kNearBatch = sizeof(real) == 4 ? 8 : 4;  // candidates tested between checks of the list's room
@@ -193,15 +205,23 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
     // the candidates' addresses are the same in every lane: read them through the
     // constant address space, which gives scalar loads (the array is not written here)
     const __attribute__((address_space(4))) vec4<real>* cpos = (const __attribute__((address_space(4))) vec4<real>*)a.pos;
-    const int lb = xcd_logical_block((a.max_units + kNearWaves - 1) / kNearWaves);
-    if (lb < 0) return;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int item = lb * kNearWaves + wv;
-    if (item >= a.max_units) return;  // no block-wide barrier below: waves are independent
-    const int4 unit = a.units[item];
-    if (unit.y < 0) return;
     uint32_t* hits = hits_all[wv];
     vec4<real>* shift = shift_all[wv];
+    // persistent waves (no block-wide barrier below: waves are independent): the blocks
+    // of XCD x (block b runs on XCD b % 8) take the units of the x-th eighth one at a
+    // time from that eighth's counter, so that neighbouring columns share an L2 and the
+    // waves finish together
+    const int per = (a.max_units + 7) >> 3;
+    const int ibeg = (blockIdx.x & 7) * per, iend = min(a.max_units, ibeg + per);
+    int* grab = a.grab + (blockIdx.x & 7) * kGrabStride;
+    for (;;) {
+    int g = 0;
+    if (lane == 0) g = atomicAdd(grab, 1);
+    const int item = ibeg + __builtin_amdgcn_readfirstlane(g);
+    if (item >= iend) break;
+    const int4 unit = a.units[item];
+    if (unit.y < 0) continue;
     const int col = unit.x, z0 = unit.y, z1 = unit.z;
     const int cy = col % a.nc[1], cx = col / a.nc[1];
     const int tb = a.cell_start[col * a.nc[2] + z0], te = a.cell_start[col * a.nc[2] + z1];
@@ -325,26 +345,27 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
             a.part[i] = vec4<real>{phi, gx, gy, gz};
         }
     }
+    }
 }
 
 // polynomial degrees compiled; the fitted degree is rounded up to one of these
 template <typename real, int DEG>
-void launch_near_deg(const NearArgs<real>& a, hipStream_t st) {
-    k_near<real, DEG><<<xcd_grid((a.max_units + kNearWaves - 1) / kNearWaves), 64 * kNearWaves, 0, st>>>(a);
+void launch_near_deg(const NearArgs<real>& a, int blocks, hipStream_t st) {
+    k_near<real, DEG><<<blocks, 64 * kNearWaves, 0, st>>>(a);
 }
 
 template <typename real>
-void launch_near_kernel(const NearArgs<real>& a, hipStream_t st) {
-    if (a.deg <= 8) launch_near_deg<real, 8>(a, st);
-    else if (a.deg <= 10) launch_near_deg<real, 10>(a, st);
-    else if (a.deg <= 12) launch_near_deg<real, 12>(a, st);
-    else if (a.deg <= 14) launch_near_deg<real, 14>(a, st);
-    else if (a.deg <= 16) launch_near_deg<real, 16>(a, st);
-    else if (a.deg <= 20) launch_near_deg<real, 20>(a, st);
-    else if (a.deg <= 24) launch_near_deg<real, 24>(a, st);
-    else if (a.deg <= 32) launch_near_deg<real, 32>(a, st);
-    else if (a.deg <= 48) launch_near_deg<real, 48>(a, st);
-    else launch_near_deg<real, kMaxNearDeg>(a, st);
+void launch_near_kernel(const NearArgs<real>& a, int blocks, hipStream_t st) {
+    if (a.deg <= 8) launch_near_deg<real, 8>(a, blocks, st);
+    else if (a.deg <= 10) launch_near_deg<real, 10>(a, blocks, st);
+    else if (a.deg <= 12) launch_near_deg<real, 12>(a, blocks, st);
+    else if (a.deg <= 14) launch_near_deg<real, 14>(a, blocks, st);
+    else if (a.deg <= 16) launch_near_deg<real, 16>(a, blocks, st);
+    else if (a.deg <= 20) launch_near_deg<real, 20>(a, blocks, st);
+    else if (a.deg <= 24) launch_near_deg<real, 24>(a, blocks, st);
+    else if (a.deg <= 32) launch_near_deg<real, 32>(a, blocks, st);
+    else if (a.deg <= 48) launch_near_deg<real, 48>(a, blocks, st);
+    else launch_near_deg<real, kMaxNearDeg>(a, blocks, st);
 }
 
 template <typename real>
@@ -370,7 +391,8 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
         k_near_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.key, ws.cell_start, ws.cell_cursor,
                                                          (vec4<real>*)ws.near_pos, ws.near_orig);
         const int ncols = r.nc[0] * r.nc[1];
-        k_near_units<<<ncols, 64, 0, p.stream>>>(ws.cell_start, r.nc[2], (int4*)ws.near_units);
+        k_near_units<<<ncols, 64, 0, p.stream>>>(ws.cell_start, r.nc[2], (int4*)ws.near_units,
+                                                 near_grab(ws, ncells));
         timer_end(p, t);
         if (!(stages & 2)) return hipGetLastError();
     }
@@ -378,6 +400,7 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
     a.pos = (const vec4<real>*)ws.near_pos;
     a.orig = ws.near_orig;
     a.units = (const int4*)ws.near_units;
+    a.grab = near_grab(ws, ncells);
     a.max_units = ncells;
     a.cell_start = ws.cell_start;
     a.part = (vec4<real>*)ws.parts;
@@ -394,7 +417,8 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
     }
     const int t = timer_id(p, "near");
     timer_begin(p, t);
-    launch_near_kernel<real>(a, p.stream);
+    const int want = std::min(p.num_cus * kNearBlocksPerCU, (ncells + kNearWaves - 1) / kNearWaves);
+    launch_near_kernel<real>(a, std::max(8, (want + 7) / 8 * 8), p.stream);
     timer_end(p, t);
     return hipGetLastError();
 }
