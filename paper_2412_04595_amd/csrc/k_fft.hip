@@ -53,26 +53,93 @@ FFTDev to_dev(const FFTFactors& f) {
     return d;
 }
 
-// cos and sin of 2 pi q / R for the odd radices (exact to double precision)
+// cos and sin of 2 pi q / R for the radices of the small DFTs (the doubles nearest the
+// exact values; q taken mod R)
 __host__ __device__ constexpr double rot_c(int R, int q) {
-    return R == 3 ? (q == 0 ? 1.0 : -0.5)
-         : R == 5 ? (q == 0 ? 1.0 : (q == 1 || q == 4) ? 0.309016994374947424102293 : -0.809016994374947424102293)
-         : (q == 0 ? 1.0 : (q == 1 || q == 6) ? 0.623489801858733530525004
-                         : (q == 2 || q == 5) ? -0.222520933956314404288902 : -0.900968867902419126236102);
+    q = ((q % R) + R) % R;
+    if (R == 3) return q == 0 ? 1.0 : q == 1 ? -0.5 : -0.5;
+    if (R == 5) return q == 0 ? 1.0 : q == 1 ? 0.30901699437494745 : q == 2 ? -0.8090169943749475 : q == 3 ? -0.8090169943749475 : 0.30901699437494745;
+    if (R == 6) return q == 0 ? 1.0 : q == 1 ? 0.5 : q == 2 ? -0.5 : q == 3 ? -1.0 : q == 4 ? -0.5 : 0.5;
+    if (R == 7) return q == 0 ? 1.0 : q == 1 ? 0.6234898018587335 : q == 2 ? -0.2225209339563144 : q == 3 ? -0.9009688679024191 : q == 4 ? -0.9009688679024191 : q == 5 ? -0.2225209339563144 : 0.6234898018587335;
+    if (R == 8) return q == 0 ? 1.0 : q == 1 ? 0.7071067811865476 : q == 2 ? 0.0 : q == 3 ? -0.7071067811865476 : q == 4 ? -1.0 : q == 5 ? -0.7071067811865476 : q == 6 ? 0.0 : 0.7071067811865476;
+    if (R == 9) return q == 0 ? 1.0 : q == 1 ? 0.766044443118978 : q == 2 ? 0.17364817766693036 : q == 3 ? -0.5 : q == 4 ? -0.9396926207859084 : q == 5 ? -0.9396926207859084 : q == 6 ? -0.5 : q == 7 ? 0.17364817766693036 : 0.766044443118978;
+    if (R == 10) return q == 0 ? 1.0 : q == 1 ? 0.8090169943749475 : q == 2 ? 0.30901699437494745 : q == 3 ? -0.30901699437494745 : q == 4 ? -0.8090169943749475 : q == 5 ? -1.0 : q == 6 ? -0.8090169943749475 : q == 7 ? -0.30901699437494745 : q == 8 ? 0.30901699437494745 : 0.8090169943749475;
+    if (R == 12) return q == 0 ? 1.0 : q == 1 ? 0.8660254037844386 : q == 2 ? 0.5 : q == 3 ? 0.0 : q == 4 ? -0.5 : q == 5 ? -0.8660254037844386 : q == 6 ? -1.0 : q == 7 ? -0.8660254037844386 : q == 8 ? -0.5 : q == 9 ? 0.0 : q == 10 ? 0.5 : 0.8660254037844386;
+    if (R == 15) return q == 0 ? 1.0 : q == 1 ? 0.9135454576426009 : q == 2 ? 0.6691306063588582 : q == 3 ? 0.30901699437494745 : q == 4 ? -0.10452846326765347 : q == 5 ? -0.5 : q == 6 ? -0.8090169943749475 : q == 7 ? -0.9781476007338057 : q == 8 ? -0.9781476007338057 : q == 9 ? -0.8090169943749475 : q == 10 ? -0.5 : q == 11 ? -0.10452846326765347 : q == 12 ? 0.30901699437494745 : q == 13 ? 0.6691306063588582 : 0.9135454576426009;
+    if (R == 16) return q == 0 ? 1.0 : q == 1 ? 0.9238795325112867 : q == 2 ? 0.7071067811865476 : q == 3 ? 0.3826834323650898 : q == 4 ? 0.0 : q == 5 ? -0.3826834323650898 : q == 6 ? -0.7071067811865476 : q == 7 ? -0.9238795325112867 : q == 8 ? -1.0 : q == 9 ? -0.9238795325112867 : q == 10 ? -0.7071067811865476 : q == 11 ? -0.3826834323650898 : q == 12 ? 0.0 : q == 13 ? 0.3826834323650898 : q == 14 ? 0.7071067811865476 : 0.9238795325112867;
+    return 0.0;
 }
 __host__ __device__ constexpr double rot_s(int R, int q) {
-    return R == 3 ? (q == 0 ? 0.0 : q == 1 ? 0.866025403784438646763723 : -0.866025403784438646763723)
-         : R == 5 ? (q == 0 ? 0.0 : q == 1 ? 0.951056516295153572116439 : q == 2 ? 0.587785252292473129168706
-                    : q == 3 ? -0.587785252292473129168706 : -0.951056516295153572116439)
-         : (q == 0 ? 0.0 : q == 1 ? 0.781831482468029808708444 : q == 2 ? 0.974927912181823607018131
-            : q == 3 ? 0.433883739117558120475768 : q == 4 ? -0.433883739117558120475768
-            : q == 5 ? -0.974927912181823607018131 : -0.781831482468029808708444);
+    q = ((q % R) + R) % R;
+    if (R == 3) return q == 0 ? 0.0 : q == 1 ? 0.8660254037844386 : -0.8660254037844386;
+    if (R == 5) return q == 0 ? 0.0 : q == 1 ? 0.9510565162951535 : q == 2 ? 0.5877852522924731 : q == 3 ? -0.5877852522924731 : -0.9510565162951535;
+    if (R == 6) return q == 0 ? 0.0 : q == 1 ? 0.8660254037844386 : q == 2 ? 0.8660254037844386 : q == 3 ? 0.0 : q == 4 ? -0.8660254037844386 : -0.8660254037844386;
+    if (R == 7) return q == 0 ? 0.0 : q == 1 ? 0.7818314824680298 : q == 2 ? 0.9749279121818236 : q == 3 ? 0.4338837391175581 : q == 4 ? -0.4338837391175581 : q == 5 ? -0.9749279121818236 : -0.7818314824680298;
+    if (R == 8) return q == 0 ? 0.0 : q == 1 ? 0.7071067811865476 : q == 2 ? 1.0 : q == 3 ? 0.7071067811865476 : q == 4 ? 0.0 : q == 5 ? -0.7071067811865476 : q == 6 ? -1.0 : -0.7071067811865476;
+    if (R == 9) return q == 0 ? 0.0 : q == 1 ? 0.6427876096865394 : q == 2 ? 0.984807753012208 : q == 3 ? 0.8660254037844386 : q == 4 ? 0.3420201433256687 : q == 5 ? -0.3420201433256687 : q == 6 ? -0.8660254037844386 : q == 7 ? -0.984807753012208 : -0.6427876096865394;
+    if (R == 10) return q == 0 ? 0.0 : q == 1 ? 0.5877852522924731 : q == 2 ? 0.9510565162951535 : q == 3 ? 0.9510565162951535 : q == 4 ? 0.5877852522924731 : q == 5 ? 0.0 : q == 6 ? -0.5877852522924731 : q == 7 ? -0.9510565162951535 : q == 8 ? -0.9510565162951535 : -0.5877852522924731;
+    if (R == 12) return q == 0 ? 0.0 : q == 1 ? 0.5 : q == 2 ? 0.8660254037844386 : q == 3 ? 1.0 : q == 4 ? 0.8660254037844386 : q == 5 ? 0.5 : q == 6 ? 0.0 : q == 7 ? -0.5 : q == 8 ? -0.8660254037844386 : q == 9 ? -1.0 : q == 10 ? -0.8660254037844386 : -0.5;
+    if (R == 15) return q == 0 ? 0.0 : q == 1 ? 0.4067366430758002 : q == 2 ? 0.7431448254773942 : q == 3 ? 0.9510565162951535 : q == 4 ? 0.9945218953682733 : q == 5 ? 0.8660254037844386 : q == 6 ? 0.5877852522924731 : q == 7 ? 0.20791169081775934 : q == 8 ? -0.20791169081775934 : q == 9 ? -0.5877852522924731 : q == 10 ? -0.8660254037844386 : q == 11 ? -0.9945218953682733 : q == 12 ? -0.9510565162951535 : q == 13 ? -0.7431448254773942 : -0.4067366430758002;
+    if (R == 16) return q == 0 ? 0.0 : q == 1 ? 0.3826834323650898 : q == 2 ? 0.7071067811865476 : q == 3 ? 0.9238795325112867 : q == 4 ? 1.0 : q == 5 ? 0.9238795325112867 : q == 6 ? 0.7071067811865476 : q == 7 ? 0.3826834323650898 : q == 8 ? 0.0 : q == 9 ? -0.3826834323650898 : q == 10 ? -0.7071067811865476 : q == 11 ? -0.9238795325112867 : q == 12 ? -1.0 : q == 13 ? -0.9238795325112867 : q == 14 ? -0.7071067811865476 : -0.3826834323650898;
+    return 0.0;
+}
+
+template <typename T, int R, int SIGN>
+__device__ __forceinline__ void small_dft(const cpx<T> (&v)[R], cpx<T> (&o)[R]);
+
+// x e^{SIGN 2 pi i q / R} for a constant q; the factors 1, -1 and +-i cost nothing
+template <typename T, int R, int SIGN>
+__device__ __forceinline__ cpx<T> twiddle_const(cpx<T> x, int q) {
+    q %= R;
+    if (q == 0) return x;
+    if (2 * q == R) return cpx<T>{-x.x, -x.y};
+    if (4 * q == R) return (SIGN > 0) ? cpx<T>{-x.y, x.x} : cpx<T>{x.y, -x.x};
+    if (4 * q == 3 * R) return (SIGN > 0) ? cpx<T>{x.y, -x.x} : cpx<T>{-x.y, x.x};
+    const T c = (T)rot_c(R, q), sn = (T)SIGN * (T)rot_s(R, q);
+    return cpx<T>{x.x * c - x.y * sn, x.x * sn + x.y * c};
+}
+
+// DFT of length R = R1 R2 in registers (Cooley-Tukey): inner DFTs of length R1 over the
+// inputs n = R2 n1 + n2, the twiddles e^{SIGN 2 pi i n2 k1 / R}, outer DFTs of length R2;
+// output k = k1 + R1 k2
+template <typename T, int R1, int R2, int SIGN>
+__device__ __forceinline__ void composite_dft(const cpx<T> (&v)[R1 * R2], cpx<T> (&o)[R1 * R2]) {
+    constexpr int R = R1 * R2;
+    cpx<T> a[R2][R1];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+        cpx<T> in[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) in[n1] = v[R2 * n1 + n2];
+        small_dft<T, R1, SIGN>(in, a[n2]);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) a[n2][k1] = twiddle_const<T, R, SIGN>(a[n2][k1], n2 * k1);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+        cpx<T> in[R2], out[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) in[n2] = a[n2][k1];
+        small_dft<T, R2, SIGN>(in, out);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) o[k1 + R1 * k2] = out[k2];
+    }
 }
 
 // o_p = sum_r v_r e^{SIGN 2 pi i p r / R}
 template <typename T, int R, int SIGN>
 __device__ __forceinline__ void small_dft(const cpx<T> (&v)[R], cpx<T> (&o)[R]) {
-    if constexpr (R == 2) {
+    if constexpr (R == 6) {
+        composite_dft<T, 2, 3, SIGN>(v, o);
+    } else if constexpr (R == 8) {
+        composite_dft<T, 2, 4, SIGN>(v, o);
+    } else if constexpr (R == 9) {
+        composite_dft<T, 3, 3, SIGN>(v, o);
+    } else if constexpr (R == 10) {
+        composite_dft<T, 2, 5, SIGN>(v, o);
+    } else if constexpr (R == 16) {
+        composite_dft<T, 4, 4, SIGN>(v, o);
+    } else if constexpr (R == 2) {
         o[0] = cadd(v[0], v[1]);
         o[1] = csub(v[0], v[1]);
     } else if constexpr (R == 4) {
@@ -134,16 +201,14 @@ struct UDiv {
 UDiv make_udiv(int d) { return UDiv{d, (unsigned)((((uint64_t)1 << 32) + (uint64_t)d - 1) / (uint64_t)d)}; }
 __device__ __forceinline__ int udiv(int e, UDiv u) { return (int)__umulhi((unsigned)e, u.mul); }
 
-// dst[i] = src[i] for i < count, with up to K loads of a thread in flight together
+// dst[i] = src[i] for i < count, with up to K loads of a thread in flight together (every
+// slot loads a valid element, so the staging array stays in registers)
 template <int K, typename V>
 __device__ __forceinline__ void copy_in(V* dst, const V* __restrict__ src, int count) {
     for (int b = 0; b < count; b += K * kFFTThreads) {
         V v[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = b + threadIdx.x + k * kFFTThreads;
-            if (i < count) v[k] = src[i];
-        }
+        for (int k = 0; k < K; ++k) v[k] = src[min(b + (int)threadIdx.x + k * kFFTThreads, count - 1)];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int i = b + threadIdx.x + k * kFFTThreads;
@@ -229,6 +294,11 @@ __device__ void lds_fft(cpx<T>* A, const cpx<T>* __restrict__ twl, int W, int P,
             case 2: fft_stage<T, 2, SIGN>(A, twl, W, lw, P, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
             case 3: fft_stage<T, 3, SIGN>(A, twl, W, lw, P, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
             case 5: fft_stage<T, 5, SIGN>(A, twl, W, lw, P, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
+            case 6: fft_stage<T, 6, SIGN>(A, twl, W, lw, P, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
+            case 8: fft_stage<T, 8, SIGN>(A, twl, W, lw, P, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
+            case 9: fft_stage<T, 9, SIGN>(A, twl, W, lw, P, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
+            case 10: fft_stage<T, 10, SIGN>(A, twl, W, lw, P, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
+            case 16: fft_stage<T, 16, SIGN>(A, twl, W, lw, P, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
             default: fft_stage<T, 7, SIGN>(A, twl, W, lw, P, f.nR[s], f.Ns[s], f.mNs[s], f.tws[s]); break;
         }
     }

@@ -181,13 +181,11 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
         for (int pl = 0; pl < NPL; ++pl) off[pl][ps] = (pl * planestep + o) * (int)sizeof(real);
     }
     const int sinkb = (totp + lane) * (int)sizeof(real);
-    // the first kSpreadStage threads hold the next batch's particles, loaded one batch ahead
-    int4 gq = int4{0, 0, 0, 0};
-    vec4<real> uq = vec4<real>{0, 0, 0, 0};
-    if (threadIdx.x < kSpreadStage && beg + (int)threadIdx.x < end) {
-        gq = a.gp[beg + threadIdx.x];
-        uq = a.up[beg + threadIdx.x];
-    }
+    // thread t holds particle t mod kSpreadStage of the next batch, loaded one batch ahead
+    // (indices clamped into the tile's list, so every load is valid and unconditional)
+    const int slot = threadIdx.x & (kSpreadStage - 1);
+    int4 gq = a.gp[min(beg + slot, end - 1)];
+    vec4<real> uq = a.up[min(beg + slot, end - 1)];
     for (int c0 = beg; c0 < end; c0 += kSpreadStage) {
         const int cnt = min(kSpreadStage, end - c0);
         __syncthreads();
@@ -199,14 +197,12 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
             for (int g = 0; g < 4; ++g) m[g] = (corner + ((g - lx0) & 3) * HYZ) * (int)sizeof(real);
             meta[threadIdx.x] = int4{m[0], m[1], m[2], m[3]};
             slx[threadIdx.x] = lx0;
-            sup[threadIdx.x] = uq;
+            sup[threadIdx.x] = vec4<real>{uq.x, uq.y, uq.z, uq.w};
         }
         {
-            const int nx = c0 + kSpreadStage + (int)threadIdx.x;
-            if (threadIdx.x < kSpreadStage && nx < end) {
-                gq = a.gp[nx];
-                uq = a.up[nx];
-            }
+            const int nx = min(c0 + kSpreadStage + slot, end - 1);
+            gq = a.gp[nx];
+            uq = a.up[nx];
         }
         __syncthreads();
         // y, z weights and a zero; per wave g the x weights of its planes (x = g mod 4)

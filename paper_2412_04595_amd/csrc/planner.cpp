@@ -330,14 +330,27 @@ int next_smooth(int n, bool even) {
     }
 }
 
+// Radix sequence of a length-n transform with the fewest stages (each stage is one pass
+// over the batch in LDS); the radices are those the line kernels have butterflies for,
+// composite ones (6, 8, 9, 10, 16) computed in registers.  Ties: the larger first radix.
 bool factor_fft(int n, FFTFactors& f) {
+    static const int kRadices[] = {16, 10, 9, 8, 7, 6, 5, 4, 3, 2};
     f.n = n;
     f.nstages = 0;
-    int m = n;
-    while (m % 4 == 0) { if (f.nstages >= kMaxStages) return false; f.radix[f.nstages++] = 4; m /= 4; }
-    for (int p : {2, 3, 5, 7})
-        while (m % p == 0) { if (f.nstages >= kMaxStages) return false; f.radix[f.nstages++] = p; m /= p; }
-    return m == 1;
+    if (n < 1) return false;
+    std::vector<int> best(n + 1, 1 << 20), pick(n + 1, 0);
+    best[1] = 0;
+    for (int m = 2; m <= n; ++m) {
+        if (n % m) continue;  // only divisors of n are reached
+        for (int R : kRadices)
+            if (m % R == 0 && best[m / R] + 1 < best[m]) {
+                best[m] = best[m / R] + 1;
+                pick[m] = R;
+            }
+    }
+    if (best[n] >= (1 << 20) || best[n] > kMaxStages) return false;
+    for (int m = n; m > 1; m /= pick[m]) f.radix[f.nstages++] = pick[m];
+    return true;
 }
 
 // C[c][n] = (2 - delta_{n0}) / P * T_n(t_c): L_c(t) = sum_n C[c][n] T_n(t) (App. A.2, V^{-1}).
