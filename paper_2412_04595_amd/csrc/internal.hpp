@@ -16,6 +16,9 @@ constexpr int kMaxStages = 24;    // radix stages of one 1D FFT
 constexpr int kMaxNearDeg = 63;   // Chebyshev degree of the near-field polynomials
 constexpr int kMaxMid = 96;       // max number of mid-range Gaussians (m + 1)
 constexpr int kSpreadStage = 32;  // particles whose window weights the gridding kernel stages at a time
+// LDS of one gridding or gathering workgroup at most: two of them fill the 160 KiB of a
+// compute unit
+constexpr size_t kTileLdsBytes = 81920;
 
 // LDS layout of the mid-range gridding kernel: the tile plus its (P_w - 1) halo, 64 sink
 // slots for masked lanes, and per staged particle its y and z window weights (2 P_w) and

@@ -425,7 +425,7 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         a.S = S;
         a.inv_hw2 = inv_hw2;
         const size_t lds = spread_lds_bytes(sizeof(real), PW, r.B[0], r.B[1], r.B[2]);
-        if (lds > 65536) return hipErrorInvalidConfiguration;
+        if (lds > kTileLdsBytes) return hipErrorInvalidConfiguration;
         const int nlines = r.I[0] * r.I[1];
         k_zero_band<real><<<std::min((nlines + 3) / 4, 16384), 256, 0, p.stream>>>(
             (real*)ws.grid, nlines, r.Izs, r.zband[0], (r.zband[1] - r.zband[0]) / 2);
@@ -453,7 +453,7 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         a.inv_hw2 = inv_hw2;
         a.vol = (real)(r.h[0] * r.h[1] * r.h[2]);
         size_t lds = (size_t)(r.B[0] + PW - 1) * (r.B[1] + PW - 1) * (r.B[2] + PW - 1) * sizeof(real);
-        if (lds > 65536) return hipErrorInvalidConfiguration;
+        if (lds > kTileLdsBytes) return hipErrorInvalidConfiguration;
         k_gather<real, PW><<<xcd_grid(ntiles), 256, lds, p.stream>>>(a);
     }
     return hipGetLastError();
