@@ -1,0 +1,158 @@
+// Host-side invariants of the planner's tables that the GPU kernels rely on for memory
+// safety and correctness (compiled with the host compiler by test_planner_invariants.py;
+// no GPU needed):
+//
+//  1. gridding lane nodes: every window node (y, z) is taken by exactly one lane of one
+//     pass; a dummy node has z >= P_w, an offset no window node has, stays in the corner's
+//     x plane for every corner in the tile, and is used by no other lane;
+//  2. the gridding kernel's LDS addressing (a model of k_spread's index arithmetic): for
+//     every corner in the tile, wave, plane and pass, the address lies in the padded halo
+//     block, in an x plane the wave owns (x = wave mod 4), and the addresses of one
+//     particle are distinct;
+//  3. FFT factorisation: every length up to the longest line the kernels take factors
+//     exactly when it has no prime factor above 7, into compiled radices;
+//  4. the z band: for z in [0, L_z] the nearest node is never clamped, so every window
+//     lies inside the band of planes the z transforms read and write.
+//
+// Prints one line per failure and "bad N"; exit status 0 when N == 0.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <set>
+#include <vector>
+
+#include "../paper_2412_04595_amd/csrc/planner.cpp"
+
+using namespace sog;
+
+static long bad = 0;
+#define CHECK(cond, ...)                      \
+    do {                                      \
+        if (!(cond)) {                        \
+            ++bad;                            \
+            if (bad < 20) {                   \
+                std::printf(__VA_ARGS__);     \
+                std::printf("\n");            \
+            }                                 \
+        }                                     \
+    } while (0)
+
+static void check_lane_nodes_and_addresses() {
+    for (int prec : {SOG_PREC_FP32_BULK, SOG_PREC_FP64})
+        for (int Pw = 3; Pw <= 15; Pw += 2) {
+            int B[3];
+            spread_tile(prec, Pw, B);
+            CHECK(spread_lds_bytes(prec == SOG_PREC_FP64 ? 8 : 4, Pw, B[0], B[1], B[2]) <= kTileLdsBytes,
+                  "tile LDS over budget Pw %d", Pw);
+            for (int bz : {B[2], 2, 3, 5, 8}) {
+                if (bz > B[2]) continue;  // tiles are clipped to small grids, never grown
+                const int HX = B[0] + Pw - 1, HY = B[1] + Pw - 1, HZ = bz + Pw - 1, HYZ = HY * HZ;
+                const int NPL = (Pw + 3) / 4, NPAD = 4 * NPL - Pw, NPASS = (Pw * Pw + 63) / 64;
+                signed char noy[256], noz[256];
+                const bool dummy = spread_lane_nodes(Pw, HZ, bz, noy, noz);
+                // 1. the node table
+                std::set<int> window, seen;
+                for (int oy = 0; oy < Pw; ++oy)
+                    for (int oz = 0; oz < Pw; ++oz) window.insert(oy * HZ + oz);
+                int nreal = 0, none = 0;
+                for (int k = 0; k < NPASS * 64; ++k) {
+                    if (noy[k] < 0) {
+                        ++none;
+                        continue;
+                    }
+                    const int d = noy[k] * HZ + noz[k];
+                    CHECK(!seen.count(d), "Pw %d bz %d: offset %d used twice", Pw, bz, d);
+                    seen.insert(d);
+                    CHECK(noz[k] < HZ, "Pw %d bz %d: node z beyond the pitch", Pw, bz);
+                    if (noz[k] < Pw) {
+                        ++nreal;
+                        CHECK(window.count(d), "Pw %d bz %d: real node outside the window", Pw, bz);
+                    } else {
+                        CHECK(!window.count(d), "Pw %d bz %d: dummy on a window node", Pw, bz);
+                        CHECK(d <= Pw * HZ - bz, "Pw %d bz %d: dummy leaves the plane", Pw, bz);
+                    }
+                }
+                CHECK(nreal == Pw * Pw, "Pw %d bz %d: %d of %d window nodes", Pw, bz, nreal, Pw * Pw);
+                CHECK(!dummy || none == 0, "Pw %d bz %d: dummy table with empty lanes", Pw, bz);
+                // 2. the addresses of k_spread for every corner of the tile
+                const int totp = (HX + NPAD) * HYZ;
+                std::vector<int> mark(totp, -1);
+                int stamp = 0;
+                for (int lx = 0; lx < B[0]; ++lx)
+                    for (int ly = 0; ly < B[1]; ++ly)
+                        for (int lz = 0; lz < bz; ++lz) {
+                            ++stamp;
+                            const int corner = lx * HYZ + ly * HZ + lz;
+                            for (int g = 0; g < 4; ++g) {
+                                const int first = corner + ((g - lx) & 3) * HYZ;
+                                for (int pl = 0; pl < NPL; ++pl)
+                                    for (int k = 0; k < NPASS * 64; ++k) {
+                                        if (noy[k] < 0) continue;  // the lane's private sink
+                                        const int at = first + pl * 4 * HYZ + noy[k] * HZ + noz[k];
+                                        if (at < 0 || at >= totp) {
+                                            CHECK(false, "Pw %d bz %d: address %d outside [0, %d)", Pw, bz, at, totp);
+                                            continue;
+                                        }
+                                        CHECK((at / HYZ) % 4 == g, "Pw %d bz %d: plane not owned by wave %d", Pw, bz, g);
+                                        CHECK(mark[at] != stamp, "Pw %d bz %d: address reused in one particle", Pw, bz);
+                                        mark[at] = stamp;
+                                    }
+                            }
+                        }
+            }
+        }
+}
+
+static void check_fft_factors() {
+    const int compiled[] = {2, 3, 4, 5, 6, 7, 8, 9, 10, 16};
+    for (int n = 1; n <= fft_max_line(SOG_PREC_FP32_BULK); ++n) {
+        int m = n;
+        for (int p : {2, 3, 5, 7})
+            while (m % p == 0) m /= p;
+        FFTFactors f;
+        const bool ok = factor_fft(n, f);
+        CHECK(ok == (m == 1), "factor_fft(%d) = %d", n, (int)ok);
+        if (!ok) continue;
+        long prod = 1;
+        for (int i = 0; i < f.nstages; ++i) {
+            bool known = false;
+            for (int R : compiled) known |= (R == f.radix[i]);
+            CHECK(known, "factor_fft(%d): radix %d has no kernel", n, f.radix[i]);
+            prod *= f.radix[i];
+        }
+        CHECK(prod == n && f.nstages <= kMaxStages, "factor_fft(%d): product %ld", n, prod);
+    }
+}
+
+static void check_z_band() {
+    const double boxes[][3] = {{100, 100, 100}, {400, 400, 25}, {50, 50, 800}, {150, 150, 60},
+                               {20, 20, 20},    {30, 40, 7.3},  {12, 12, 95}};
+    const int64_t ns[] = {1000000, 1000000, 1000000, 200000, 1000, 5000, 3000};
+    for (int prec : {SOG_PREC_FP32_BULK, SOG_PREC_FP64})
+        for (int b = 0; b < 7; ++b) {
+            sog_options opt;
+            std::memset(&opt, 0, sizeof(opt));
+            opt.precision = prec;
+            Resolved r;
+            std::string err;
+            if (resolve(boxes[b], ns[b], 1e-4, opt, r, err) != SOG_OK || !r.has_mid) continue;
+            const int HW = (r.Pw - 1) / 2;
+            CHECK(r.zband[0] >= 0 && r.zband[1] <= r.Izs && r.zband[0] % 2 == 0 && r.zband[1] % 2 == 0,
+                  "box %d: band [%d, %d) of %d", b, r.zband[0], r.zband[1], r.Izs);
+            for (int i = 0; i <= 20000; ++i) {
+                const double z = r.L[2] * i / 20000.0;
+                const double v = (z - 0.5 * r.L[2] + 0.5 * r.Lzs) / r.h[2];
+                const int k = (int)std::rint(v);
+                CHECK(k - HW >= r.zband[0] && k + HW < r.zband[1], "box %d: z %g window [%d, %d] leaves the band",
+                      b, z, k - HW, k + HW);
+            }
+        }
+}
+
+int main() {
+    check_lane_nodes_and_addresses();
+    check_fft_factors();
+    check_z_band();
+    std::printf("bad %ld\n", bad);
+    return bad == 0 ? 0 : 1;
+}
