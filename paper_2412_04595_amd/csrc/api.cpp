@@ -113,12 +113,11 @@ sog_status build_plan(Plan& p) {
     A.get(ws.qsum, 2 * 8);
     A.get(ws.status, 4);
     A.get(ws.parts, 12 * n * rs);
-    A.get(ws.key, n * 4);
+    A.get(ws.key, n * 8);  // near-field (cell, rank) pairs; the long-range FFT form's keys
     A.get(ws.perm, n * 4);
     const int ncells = r.nc[0] * r.nc[1] * r.nc[2];
     int64_t maxbins = ncells;
     A.get(ws.cell_start, (ncells + 1) * 4);
-    A.get(ws.cell_cursor, ncells * 4);
     A.get(ws.near_orig, n * 4);
     A.get(ws.near_pos, n * 4 * rs);
     A.get(ws.near_units, ((size_t)ncells * 16 + 127) / 128 * 128 + 8 * 128);  // units, then 8 work counters
@@ -127,7 +126,6 @@ sog_status build_plan(Plan& p) {
         maxbins = std::max<int64_t>(maxbins, ntiles);
         const int Kz = r.Izs / 2 + 1;
         A.get(ws.tile_start, (ntiles + 1) * 4);
-        A.get(ws.tile_cursor, ntiles * 4);
         A.get(ws.spread_nodes, 2 * 4 * 64);
         A.get(ws.mid_g, n * 16);
         A.get(ws.mid_u, n * 4 * rs);
@@ -166,7 +164,7 @@ sog_status build_plan(Plan& p) {
     }
     A.get(ws.scan_tmp, ((maxbins + 1) / 1024 + 2) * 4);
     if (r.has_mid) {
-        A.get(ws.key2, n * 4);
+        A.get(ws.key2, n * 8);  // mid-range (tile, rank) pairs
         A.get(ws.scan_tmp2, ((maxbins + 1) / 1024 + 2) * 4);
     }
     ws.red_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256));
@@ -274,8 +272,8 @@ sog_status build_plan(Plan& p) {
 void free_plan(Plan& p) {
     Workspace& ws = p.ws;
     void* ptrs[] = {ws.x, ws.q, ws.phi, ws.force, ws.energy, ws.qsum, ws.status, ws.parts,
-                    ws.key, ws.perm, ws.scan_tmp, ws.key2, ws.scan_tmp2, ws.cell_start, ws.cell_cursor, ws.near_orig, ws.near_units,
-                    ws.near_pos, ws.tile_start, ws.tile_cursor, ws.spread_nodes, ws.mid_g,
+                    ws.key, ws.perm, ws.scan_tmp, ws.key2, ws.scan_tmp2, ws.cell_start, ws.near_orig, ws.near_units,
+                    ws.near_pos, ws.tile_start, ws.spread_nodes, ws.mid_g,
                     ws.mid_u, ws.grid, ws.cgrid, ws.tw_x, ws.tw_y, ws.tw_z, ws.tw_zpost, ws.mult_ax, ws.mult_ay,
                     ws.mult_az, ws.mult_c, ws.long_modes, ws.long_kt, ws.long_mu, ws.long_a, ws.l2_tile_start,
                     ws.l2_tile_cursor, ws.l2_dup_start, ws.l2_dup_cursor, ws.l2_dup_list, ws.l2_g, ws.l2_u,
@@ -344,7 +342,6 @@ sog_status run(Plan& p, const double* x_in, const double* q_in, double* energy, 
         x = ws.x;
         q = ws.q;
     }
-    if ((e = launch_prep(p, x, q)) != hipSuccess) return hip_status(e, "validate");
     // Two streams: the near field and the long range on the plan's side stream, the mid
     // range on the caller's stream (they share no buffers: separate sort keys, scan space
     // and part records).  The ALU-bound near-field kernel waits for the gridding so that it

@@ -129,20 +129,18 @@ struct Workspace {
     // per-part results in the particles' own order, one record per particle and part
     void* parts = nullptr;      // 3 x n x real4 (phi, dphi/dx, dphi/dy, dphi/dz): near, mid, long
     // counting sorts
-    int* key = nullptr;       // n
+    int* key = nullptr;       // 2n: near-field (cell, rank) pairs; the long-range FFT form reuses n of it
     int* perm = nullptr;      // n
     int* scan_tmp = nullptr;  // block sums
-    int* key2 = nullptr;      // n: the mid range's sort keys (it runs on the main stream while
+    int* key2 = nullptr;      // 2n: the mid range's (tile, rank) pairs (it runs on the main stream while
     int* scan_tmp2 = nullptr; //    the near field and long range sort on the side stream)
     // near field
     int* cell_start = nullptr;  // ncells + 1
-    int* cell_cursor = nullptr; // ncells
     int* near_orig = nullptr;   // n
     void* near_pos = nullptr;   // n x real4 (x, y, z relative to the cell corner; q)
     void* near_units = nullptr; // ncells x int4 work units (column, first cell, end cell), then 8 work counters
     // mid range
     int* tile_start = nullptr;  // ntiles + 1 (owners)
-    int* tile_cursor = nullptr; // ntiles
     signed char* spread_nodes = nullptr;  // 2 x 256: node_oy, node_oz of the plan
     int* mid_g = nullptr;       // n x int4 (grid point of each sorted particle, original index)
     void* mid_u = nullptr;      // n x real4 (offset from the grid point in units of h, q)
@@ -216,11 +214,9 @@ void set_error(const std::string& msg);
 struct Timed;  // RAII helper in api.cpp
 hipError_t launch_fill_int(int* p, int value, int64_t n, hipStream_t s);
 hipError_t launch_fill_bytes_zero(void* p, size_t bytes, hipStream_t s);
-hipError_t launch_prep(Plan& p, const double* x, const double* q);
 hipError_t launch_counting_sort(Plan& p, const int* key, int n, int nbins, int* start, int* cursor, int* perm);
 // zero the counts (nbins + 1) and cursors (nbins) of a counting sort whose histogram the
 // caller's key kernel builds; launch_exclusive_scan then turns counts into starts
-hipError_t launch_sort_clear(Plan& p, int nbins, int* start, int* cursor);
 hipError_t launch_exclusive_scan(Plan& p, int* data, int nbins, int* tmp);  // in place; tmp: block sums
 // stages (bit mask): near 1 = cell sort, 2 = pair kernel; mid 1 = tile sort and gridding,
 // 2 = FFT chain and gathering

@@ -48,28 +48,29 @@ __device__ __forceinline__ void grid_point(const MidGeom& g, double x, double y,
     }
 }
 
-// tile of every particle's nearest node, and the tile histogram of the counting sort
-__global__ void k_mid_key(const double* __restrict__ x, int n, MidGeom g, int* __restrict__ key,
+// tile of every particle's nearest node and its rank within the tile (the counting sort's
+// histogram)
+__global__ void k_mid_key(const double* __restrict__ x, int n, MidGeom g, int2* __restrict__ key,
                           int* __restrict__ count) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         int a[3];
         double u[3];
         grid_point(g, x[3 * i], x[3 * i + 1], x[3 * i + 2], a, u);
         const int k = ((a[0] / g.B[0]) * g.nt[1] + a[1] / g.B[1]) * g.nt[2] + a[2] / g.B[2];
-        key[i] = k;
-        atomicAdd(&count[k], 1);
+        key[i] = make_int2(k, atomicAdd(&count[k], 1));
     }
 }
 
 // Scatter of the counting sort: each particle's grid point and offset record written at
-// its place in tile order (particles read in their own order).
+// its place in tile order, tile start plus rank (particles read in their own order, no
+// atomics).
 template <typename real>
 __global__ void k_mid_pack(const double* __restrict__ x, const double* __restrict__ q, int n, MidGeom g,
-                           const int* __restrict__ key, const int* __restrict__ start, int* __restrict__ cursor,
+                           const int2* __restrict__ key, const int* __restrict__ start,
                            int4* __restrict__ gp, vec4<real>* __restrict__ up) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int k = key[i];
-        const int p = start[k] + atomicAdd(&cursor[k], 1);
+        const int2 kr = key[i];
+        const int p = start[kr.x] + kr.y;
         int a[3];
         double u[3];
         grid_point(g, x[3 * i], x[3 * i + 1], x[3 * i + 2], a, u);
@@ -499,11 +500,11 @@ hipError_t run_mid_prepare(Plan& p, const double* x, const double* q) {
     MidGeom g = mid_geom(r);
     const int ntiles = r.ntile[0] * r.ntile[1] * r.ntile[2];
     const int blocks = std::min((n + 255) / 256, 8192);
-    hipError_t e = launch_sort_clear(p, ntiles, ws.tile_start, ws.tile_cursor);
+    hipError_t e = launch_fill_int(ws.tile_start, 0, (int64_t)ntiles + 1, p.stream);
     if (e != hipSuccess) return e;
-    k_mid_key<<<blocks, 256, 0, p.stream>>>(x, n, g, ws.key2, ws.tile_start);
+    k_mid_key<<<blocks, 256, 0, p.stream>>>(x, n, g, (int2*)ws.key2, ws.tile_start);
     if ((e = launch_exclusive_scan(p, ws.tile_start, ntiles + 1, ws.scan_tmp2)) != hipSuccess) return e;
-    k_mid_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.key2, ws.tile_start, ws.tile_cursor,
+    k_mid_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, (const int2*)ws.key2, ws.tile_start,
                                                     (int4*)ws.mid_g, (vec4<real>*)ws.mid_u);
     return hipGetLastError();
 }

@@ -16,30 +16,6 @@ __global__ void k_fill_zero_u32(uint32_t* p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
 }
 
-// Validation (problem statement, Sec. 2.1): finite inputs, z in [0, Lz], and the
-// charge sums used for the neutrality test of Prop. lem::summation.
-__global__ void k_prep(const double* __restrict__ x, const double* __restrict__ q, int64_t n, double Lz,
-                       double* __restrict__ qsum, int* __restrict__ status) {
-    __shared__ double red[16];
-    double s = 0, sa = 0;
-    int flags = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        double xx = x[3 * i], yy = x[3 * i + 1], zz = x[3 * i + 2], qq = q[i];
-        if (!(isfinite(xx) && isfinite(yy) && isfinite(zz) && isfinite(qq))) {
-            flags |= 1;
-            continue;
-        }
-        if (zz < 0.0 || zz > Lz) flags |= 2;
-        s += qq;
-        sa += fabs(qq);
-    }
-    if (flags) atomicOr(status, flags);
-    double t = block_sum_double(s, red);
-    if (threadIdx.x == 0) atomicAdd(&qsum[0], t);
-    t = block_sum_double(sa, red);
-    if (threadIdx.x == 0) atomicAdd(&qsum[1], t);
-}
-
 __global__ void k_hist(const int* __restrict__ key, int n, int* __restrict__ count) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) atomicAdd(&count[key[i]], 1);
 }
@@ -190,18 +166,6 @@ hipError_t launch_fill_bytes_zero(void* p, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_prep(Plan& p, const double* x, const double* q) {
-    hipError_t e = launch_fill_bytes_zero(p.ws.qsum, 2 * sizeof(double), p.stream);
-    if (e != hipSuccess) return e;
-    e = launch_fill_int(p.ws.status, 0, 1, p.stream);
-    if (e != hipSuccess) return e;
-    int t = timer_id(p, "validate");
-    timer_begin(p, t);
-    k_prep<<<grid_for(p.r.n, 256, 1024), 256, 0, p.stream>>>(x, q, p.r.n, p.r.L[2], p.ws.qsum, p.ws.status);
-    timer_end(p, t);
-    return hipGetLastError();
-}
-
 hipError_t launch_exclusive_scan(Plan& p, int* data, int len, int* tmp) {
     int nb = (len + kScanChunk - 1) / kScanChunk;
     k_scan_local<<<nb, kScanThreads, 0, p.stream>>>(data, len, tmp);
@@ -221,12 +185,6 @@ hipError_t launch_counting_sort(Plan& p, const int* key, int n, int nbins, int* 
     if (e != hipSuccess) return e;
     k_scatter<<<grid_for(n, 256), 256, 0, p.stream>>>(key, n, start, cursor, perm);
     return hipGetLastError();
-}
-
-hipError_t launch_sort_clear(Plan& p, int nbins, int* start, int* cursor) {
-    hipError_t e = launch_fill_int(start, 0, (int64_t)nbins + 1, p.stream);
-    if (e != hipSuccess) return e;
-    return launch_fill_int(cursor, 0, nbins, p.stream);
 }
 
 hipError_t launch_combine(Plan& p, const double* q, double* phi, double* force, double* energy) {

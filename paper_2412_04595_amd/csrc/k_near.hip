@@ -45,32 +45,52 @@ __device__ __forceinline__ void cell_of(const NearGeom& g, double xw, double yw,
     }
 }
 
-// cell of every particle, and the cell histogram of the counting sort
-__global__ void k_near_key(const double* __restrict__ x, int n, NearGeom g, int* __restrict__ key,
-                           int* __restrict__ count) {
+// Cell of every particle and the cell histogram of the counting sort; in the same pass
+// the input checks of the problem statement (Sec. 2.1): finite inputs, z in [0, L_z]
+// (status bits 1 and 2), and the charge sums sum q, sum |q| for the neutrality test of
+// Prop. lem::summation.  Block sums need blockDim.x a multiple of 64.
+__global__ __launch_bounds__(256) void k_near_key(const double* __restrict__ x, const double* __restrict__ q, int n,
+                                                  NearGeom g, int2* __restrict__ key, int* __restrict__ count,
+                                                  double* __restrict__ qsum, int* __restrict__ status) {
+    __shared__ double red[16];
+    double s = 0, sa = 0;
+    int flags = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        double xw = wrap_periodic(x[3 * i], g.L[0]), yw = wrap_periodic(x[3 * i + 1], g.L[1]);
-        double z = x[3 * i + 2];
+        const double x0 = x[3 * i], y0 = x[3 * i + 1], z0 = x[3 * i + 2], qq = q[i];
+        if (!(isfinite(x0) && isfinite(y0) && isfinite(z0) && isfinite(qq))) {
+            flags |= 1;
+        } else {
+            if (z0 < 0.0 || z0 > g.L[2]) flags |= 2;
+            s += qq;
+            sa += fabs(qq);
+        }
+        double xw = wrap_periodic(x0, g.L[0]), yw = wrap_periodic(y0, g.L[1]);
+        double z = z0;
         if (!isfinite(xw)) xw = 0;
         if (!isfinite(yw)) yw = 0;
         if (!isfinite(z)) z = 0;
         int c[3];
         cell_of(g, xw, yw, z, c);
         const int k = (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
-        key[i] = k;
-        atomicAdd(&count[k], 1);
+        key[i] = make_int2(k, atomicAdd(&count[k], 1));  // cell and rank within it
     }
+    if (flags) atomicOr(status, flags);
+    double t = block_sum_double(s, red);
+    if (threadIdx.x == 0) atomicAdd(&qsum[0], t);
+    t = block_sum_double(sa, red);
+    if (threadIdx.x == 0) atomicAdd(&qsum[1], t);
 }
 
 // Scatter of the counting sort, writing each particle's packed record at its place in
-// cell order (particles read in their own order, records written once).
+// cell order, cell start plus the rank the histogram pass gave it (particles read in their
+// own order, records written once, no atomics).
 template <typename real>
 __global__ void k_near_pack(const double* __restrict__ x, const double* __restrict__ q, int n, NearGeom g,
-                            const int* __restrict__ key, const int* __restrict__ start, int* __restrict__ cursor,
+                            const int2* __restrict__ key, const int* __restrict__ start,
                             vec4<real>* __restrict__ pos, int* __restrict__ orig) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int k = key[i];
-        const int p = start[k] + atomicAdd(&cursor[k], 1);
+        const int2 kr = key[i];
+        const int p = start[kr.x] + kr.y;
         double xw = wrap_periodic(x[3 * i], g.L[0]), yw = wrap_periodic(x[3 * i + 1], g.L[1]);
         double z = x[3 * i + 2];
         double qq = q[i];
@@ -384,11 +404,13 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
         const int t = timer_id(p, "near_sort");
         timer_begin(p, t);
         const int blocks = std::min((n + 255) / 256, 8192);
-        hipError_t e = launch_sort_clear(p, ncells, ws.cell_start, ws.cell_cursor);
+        hipError_t e = launch_fill_int(ws.cell_start, 0, (int64_t)ncells + 1, p.stream);
+        if (e == hipSuccess) e = launch_fill_bytes_zero(ws.qsum, 2 * sizeof(double), p.stream);
+        if (e == hipSuccess) e = launch_fill_int(ws.status, 0, 1, p.stream);
         if (e != hipSuccess) return e;
-        k_near_key<<<blocks, 256, 0, p.stream>>>(x, n, g, ws.key, ws.cell_start);
+        k_near_key<<<blocks, 256, 0, p.stream>>>(x, q, n, g, (int2*)ws.key, ws.cell_start, ws.qsum, ws.status);
         if ((e = launch_exclusive_scan(p, ws.cell_start, ncells + 1, ws.scan_tmp)) != hipSuccess) return e;
-        k_near_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.key, ws.cell_start, ws.cell_cursor,
+        k_near_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, (const int2*)ws.key, ws.cell_start,
                                                          (vec4<real>*)ws.near_pos, ws.near_orig);
         const int ncols = r.nc[0] * r.nc[1];
         k_near_units<<<ncols, 64, 0, p.stream>>>(ws.cell_start, r.nc[2], (int4*)ws.near_units,
