@@ -328,8 +328,10 @@ struct GatherArgs {
     real vol;       // h_x h_y h_z
 };
 
+constexpr int kGatherChunk = 256;  // particles sorted and dealt to the lanes at a time (the block size)
+
 template <typename real, int PW>
-__global__ __launch_bounds__(256) void k_gather(GatherArgs<real> a) {
+__global__ __launch_bounds__(kGatherChunk) void k_gather(GatherArgs<real> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real* halo = reinterpret_cast<real*>(smem_raw);
     const int t = xcd_logical_block(a.ntiles);
@@ -363,8 +365,42 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs<real> a) {
             if (lx < HX) halo[lx * HYZ + k] = v[j];
         }
     }
-    __syncthreads();
-    for (int p = beg + threadIdx.x; p < end; p += blockDim.x) {
+    // Lanes and LDS banks: a lane reads the rows of its particle's window at the window
+    // corner plus offsets that are the same in every lane (mostly paired dword reads), so
+    // two lanes collide in a bank when their corners are within one of each other mod 64.
+    // Each chunk of up to 256 particles is counting-sorted by corner mod 64 and dealt to
+    // the lanes so that each half-wave holds increasing residues about two apart.
+    __shared__ int rcount[64], rstart[64], order[kGatherChunk];
+    for (int c0 = beg; c0 < end; c0 += kGatherChunk) {
+        const int cnt = min(kGatherChunk, end - c0);
+        if (threadIdx.x < 64) rcount[threadIdx.x] = 0;
+        __syncthreads();
+        int res = 0, rank = 0;
+        if ((int)threadIdx.x < cnt) {
+            const int4 g = a.gp[c0 + threadIdx.x];
+            res = (((g.x - x0) * HY + (g.y - y0)) * HZ + (g.z - z0)) & 63;
+            rank = atomicAdd(&rcount[res], 1);
+        }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            int v = rcount[threadIdx.x];
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(v, o, 64);
+                if ((int)threadIdx.x >= o) v += u;
+            }
+            rstart[threadIdx.x] = v - rcount[threadIdx.x];
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) order[rstart[res] + rank] = threadIdx.x;
+        __syncthreads();
+        // wave w takes sorted positions w + 4 j; lane l its j = 2 (l mod 32) + l / 32, so the
+        // residues in each half-wave are about two apart (paired reads then rarely share a
+        // bank in either half-wave)
+        const int lane = threadIdx.x & 63;
+        const int k = (((lane & 31) << 1) | (lane >> 5)) * 4 + (threadIdx.x >> 6);  // sorted position
+        if (k < cnt) {
+        const int p = c0 + order[k];
         const int4 g = a.gp[p];
         const vec4<real> u = a.up[p];
         real wy[PW], dwy[PW], wz[PW], dwz[PW];
@@ -402,6 +438,8 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs<real> a) {
         }
         const int i = g.w;
         a.part[i] = vec4<real>{a.vol * phi, a.vol * gx, a.vol * gy, a.vol * gz};
+        }
+        __syncthreads();  // the next chunk reuses rcount and order
     }
 }
 
@@ -454,8 +492,9 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         a.inv_hw2 = inv_hw2;
         a.vol = (real)(r.h[0] * r.h[1] * r.h[2]);
         size_t lds = (size_t)(r.B[0] + PW - 1) * (r.B[1] + PW - 1) * (r.B[2] + PW - 1) * sizeof(real);
-        if (lds > kTileLdsBytes) return hipErrorInvalidConfiguration;
-        k_gather<real, PW><<<xcd_grid(ntiles), 256, lds, p.stream>>>(a);
+        // plus the static residue sort: 128 + kGatherChunk ints
+        if (lds + (128 + kGatherChunk) * sizeof(int) > kTileLdsBytes) return hipErrorInvalidConfiguration;
+        k_gather<real, PW><<<xcd_grid(ntiles), kGatherChunk, lds, p.stream>>>(a);
     }
     return hipGetLastError();
 }
