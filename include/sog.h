@@ -53,7 +53,11 @@ typedef enum {
     SOG_ERR_INVALID_ARG = 1,     /* null pointer, n <= 0, bad box, non-finite input, bad override */
     SOG_ERR_NOT_NEUTRAL = 2,     /* |sum q| > 1e-10 sum |q| (Prop. lem::summation)                */
     SOG_ERR_OUT_OF_BOX = 3,      /* some z outside [0, Lz]                                          */
-    SOG_ERR_TOL_UNREACHABLE = 4, /* tol outside [1e-12, 1e-2] (FP64) or [1e-5, 1e-2] (FP32 bulk)   */
+    SOG_ERR_TOL_UNREACHABLE = 4, /* tol outside [1e-12, 1e-2] (FP64) or [1e-5, 1e-2] (FP32 bulk),  */
+                                 /* or no discretisation within the kernels' limits reaches tol     */
+                                 /* (Gaussian windows of at most 15 points, FFT lines of at most    */
+                                 /* 4608 / 2304 points): about 1e-8 for boxes that need the mid     */
+                                 /* range                                                            */
     SOG_ERR_OUT_OF_MEMORY = 5,   /* device allocation failed, or above SOG_MAX_DEVICE_BYTES       */
     SOG_ERR_DEVICE = 6           /* any other HIP runtime error                                    */
 } sog_status;
@@ -125,6 +129,16 @@ sog_status sog_plan_ex(const double box[3], int64_t n, double tol, const sog_opt
  * x: n x 3 row-major positions; q: n charges (see the conventions above). */
 sog_status sog_energy_potential_force(sog_plan_t plan, const double* x, const double* q,
                                       double* energy, double* phi, double* force);
+
+/* As sog_energy_potential_force, with the gradient of the potential at each particle,
+ * grad_i = grad Phi(r_i) (n x 3 row-major, or NULL), in place of the force F_i = -q_i grad_i
+ * (Sec. 2.1; the same gathers).  Phi is linear in q through a symmetric operator, so this
+ * call with the cotangent of the potentials as charges gives the gradients of any loss of
+ * the potentials (the differentiable binding uses it that way); such charges need not be
+ * neutral when the plan's check_inputs is 0 (the sum of the charges then multiplies only
+ * the k = 0 constant, which every call leaves out). */
+sog_status sog_energy_potential_gradient(sog_plan_t plan, const double* x, const double* q,
+                                         double* energy, double* phi, double* grad);
 
 /* The parts of the potential and its gradient (eq. splitting), for checking each solver
  * on its own: phi_parts is 3 x n (near, mid, long; the self term is not included),

@@ -11,7 +11,8 @@ import numpy as np
 
 from . import _lib
 from ._lib import (SOG_LONG_AUTO, SOG_LONG_DIRECT, SOG_LONG_FFT, SOG_PREC_FP32_BULK, SOG_PREC_FP64, SogError,
-                   sog_destroy, sog_energy_potential_force, sog_kernel_times, sog_kernel_times_reset,
+                   sog_destroy, sog_energy_potential_force, sog_energy_potential_gradient, sog_kernel_times,
+                   sog_kernel_times_reset,
                    sog_last_error, sog_options_default, sog_plan, sog_plan_ex, sog_plan_info, sog_plan_resolve,
                    sog_plan_sizes_get,
                    sog_potential_parts, sog_status_string)
@@ -109,6 +110,17 @@ class Solver:
         if U is not None:
             U = float(U[0])
         return U, phi, F
+
+    def potential_gradient(self, x, q, energy=True):
+        """Returns (U, phi, grad phi at the particles) from one call."""
+        x, q = self._inputs(x, q)
+        U = self._alloc(1) if energy else None
+        phi = self._alloc(self.n)
+        g = self._alloc(self.n, 3)
+        sog_energy_potential_gradient(self.plan, _ptr(x), _ptr(q), _ptr(U), _ptr(phi), _ptr(g))
+        if U is not None:
+            U = float(U[0])
+        return U, phi, g
 
     def parts(self, x, q):
         """(phi_parts (3,N), grad_parts (3,N,3)) for the near, mid and long parts."""

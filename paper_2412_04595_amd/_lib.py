@@ -31,6 +31,7 @@ EXPORTS = (
     "sog_plan",
     "sog_plan_ex",
     "sog_energy_potential_force",
+    "sog_energy_potential_gradient",
     "sog_potential_parts",
     "sog_plan_resolve",
     "sog_plan_info",
@@ -109,6 +110,8 @@ def lib():
         L.sog_plan_ex.restype = C.c_int
         L.sog_energy_potential_force.argtypes = [P, P, P, P, P, P]
         L.sog_energy_potential_force.restype = C.c_int
+        L.sog_energy_potential_gradient.argtypes = [P, P, P, P, P, P]
+        L.sog_energy_potential_gradient.restype = C.c_int
         L.sog_potential_parts.argtypes = [P, P, P, P, P]
         L.sog_potential_parts.restype = C.c_int
         L.sog_plan_resolve.argtypes = [dp, C.c_int64, C.c_double, C.POINTER(sog_options), C.POINTER(sog_params)]
@@ -174,6 +177,10 @@ def sog_energy_potential_force(plan, x_ptr, q_ptr, energy_ptr, phi_ptr, force_pt
     """Pointers are integers (host or device addresses, as the plan was made for) or None."""
     st = lib().sog_energy_potential_force(plan, x_ptr, q_ptr, energy_ptr, phi_ptr, force_ptr)
     _check(st)
+
+
+def sog_energy_potential_gradient(plan, x_ptr, q_ptr, energy_ptr, phi_ptr, grad_ptr):
+    _check(lib().sog_energy_potential_gradient(plan, x_ptr, q_ptr, energy_ptr, phi_ptr, grad_ptr))
 
 
 def sog_potential_parts(plan, x_ptr, q_ptr, phi_parts_ptr, grad_parts_ptr):

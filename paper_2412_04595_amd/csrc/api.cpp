@@ -324,7 +324,7 @@ hipError_t collect_timers(Plan& p) {
 }
 
 sog_status run(Plan& p, const double* x_in, const double* q_in, double* energy, double* phi, double* force,
-               double* phi_parts, double* grad_parts) {
+               double* grad, double* phi_parts, double* grad_parts) {
     if (!x_in || !q_in) {
         set_error("x and q must not be NULL");
         return SOG_ERR_INVALID_ARG;
@@ -399,11 +399,14 @@ sog_status run(Plan& p, const double* x_in, const double* q_in, double* energy, 
     } else {
         double* dphi = p.on_device ? phi : (phi ? ws.phi : nullptr);
         double* dforce = p.on_device ? force : (force ? ws.force : nullptr);
+        // host mode stages the gradient in the force buffer (the entry points ask for one of them)
+        double* dgrad = p.on_device ? grad : (grad ? ws.force : nullptr);
         double* denergy = p.on_device ? energy : (energy ? ws.energy : nullptr);
-        if ((e = launch_combine(p, q, dphi, dforce, denergy)) != hipSuccess) return hip_status(e, "combine");
+        if ((e = launch_combine(p, q, dphi, dforce, dgrad, denergy)) != hipSuccess) return hip_status(e, "combine");
         if (!p.on_device) {
             if (phi && e == hipSuccess) e = hipMemcpyAsync(phi, ws.phi, n * 8, hipMemcpyDeviceToHost, p.stream);
             if (force && e == hipSuccess) e = hipMemcpyAsync(force, ws.force, 3 * n * 8, hipMemcpyDeviceToHost, p.stream);
+            if (grad && e == hipSuccess) e = hipMemcpyAsync(grad, ws.force, 3 * n * 8, hipMemcpyDeviceToHost, p.stream);
             if (energy && e == hipSuccess) e = hipMemcpyAsync(energy, ws.energy, 8, hipMemcpyDeviceToHost, p.stream);
             if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
             if (e != hipSuccess) return hip_status(e, "output copy");
@@ -546,7 +549,16 @@ sog_status sog_energy_potential_force(sog_plan_t plan, const double* x, const do
         set_error("plan is NULL");
         return SOG_ERR_INVALID_ARG;
     }
-    return run(*reinterpret_cast<Plan*>(plan), x, q, energy, phi, force, nullptr, nullptr);
+    return run(*reinterpret_cast<Plan*>(plan), x, q, energy, phi, force, nullptr, nullptr, nullptr);
+}
+
+sog_status sog_energy_potential_gradient(sog_plan_t plan, const double* x, const double* q, double* energy,
+                                         double* phi, double* grad) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    return run(*reinterpret_cast<Plan*>(plan), x, q, energy, phi, nullptr, grad, nullptr, nullptr);
 }
 
 sog_status sog_potential_parts(sog_plan_t plan, const double* x, const double* q, double* phi_parts,
@@ -559,7 +571,7 @@ sog_status sog_potential_parts(sog_plan_t plan, const double* x, const double* q
         set_error("phi_parts and grad_parts are both NULL");
         return SOG_ERR_INVALID_ARG;
     }
-    return run(*reinterpret_cast<Plan*>(plan), x, q, nullptr, nullptr, nullptr, phi_parts, grad_parts);
+    return run(*reinterpret_cast<Plan*>(plan), x, q, nullptr, nullptr, nullptr, nullptr, phi_parts, grad_parts);
 }
 
 static void fill_params(const Resolved& r, sog_params* o);

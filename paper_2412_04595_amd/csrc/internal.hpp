@@ -15,6 +15,7 @@ namespace sog {
 constexpr int kMaxStages = 24;    // radix stages of one 1D FFT
 constexpr int kMaxNearDeg = 63;   // Chebyshev degree of the near-field polynomials
 constexpr int kMaxMid = 96;       // max number of mid-range Gaussians (m + 1)
+constexpr int kMaxPw = 15;        // widest mid-range window the gridding and gathering kernels take
 constexpr int kSpreadStage = 32;  // particles whose window weights the gridding kernel stages at a time
 // LDS of one gridding or gathering workgroup at most: two of them fill the 160 KiB of a
 // compute unit
@@ -223,7 +224,7 @@ hipError_t launch_exclusive_scan(Plan& p, int* data, int nbins, int* tmp);  // i
 hipError_t launch_near(Plan& p, const double* x, const double* q, int stages = 3);
 hipError_t launch_mid(Plan& p, const double* x, const double* q, int stages = 3);
 hipError_t launch_long(Plan& p, const double* x, const double* q);
-hipError_t launch_combine(Plan& p, const double* q, double* phi, double* force, double* energy);
+hipError_t launch_combine(Plan& p, const double* q, double* phi, double* force, double* grad, double* energy);
 hipError_t launch_parts_out(Plan& p, double* phi_parts, double* grad_parts);
 hipError_t launch_zero_parts(Plan& p, int part);
 

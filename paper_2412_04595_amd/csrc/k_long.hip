@@ -211,14 +211,20 @@ struct EvalArgs {
     vec4<real>* part;  // long part of each particle: phi, grad
 };
 
-template <typename real>
+// STAGED: the coefficient table (nh x P) is copied to LDS; otherwise (a table larger than
+// LDS) it is read where it is, through scalar loads (every thread reads the same entry)
+template <typename real, bool STAGED>
 __global__ void k_long_eval(EvalArgs<real> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int P = a.P, nh = a.nh;
-    cpx<real>* sa = reinterpret_cast<cpx<real>*>(smem_raw);  // nh x P
-    real* Tt = reinterpret_cast<real*>(sa + nh * P);          // P x blockDim: T_n(t)
+    cpx<real>* sa = reinterpret_cast<cpx<real>*>(smem_raw);  // nh x P when staged
+    real* Tt = reinterpret_cast<real*>(sa + (STAGED ? nh * P : 0));  // P x blockDim: T_n(t)
     real* Td = Tt + P * blockDim.x;                           // P x blockDim: dT_n/dt
-    for (int idx = threadIdx.x; idx < nh * P; idx += blockDim.x) sa[idx] = a.acoef[idx];
+    using ctab = const __attribute__((address_space(4))) cpx<real>;
+    ctab* ga = (ctab*)a.acoef;
+    if (STAGED) {
+        for (int idx = threadIdx.x; idx < nh * P; idx += blockDim.x) sa[idx] = a.acoef[idx];
+    }
     __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
@@ -264,10 +270,15 @@ __global__ void k_long_eval(EvalArgs<real> a) {
         cpx<real> ph = (ny == 0) ? phy : cmul(phy, eneg);
         const int nxlo = (ny == 0) ? 0 : -a.nkx;
         for (int nx = nxlo; nx <= a.nkx; ++nx, ++kk) {
-            const cpx<real>* row = sa + (size_t)kk * P;
             real ur = 0, ui = 0, dr = 0, di = 0;
             for (int k = 0; k < P; ++k) {
-                const cpx<real> c = row[k];
+                cpx<real> c;
+                if (STAGED) {
+                    c = sa[(size_t)kk * P + k];
+                } else {
+                    c.x = ga[(size_t)kk * P + k].x;
+                    c.y = ga[(size_t)kk * P + k].y;
+                }
                 const real tv = Tt[k * B + t], dv = Td[k * B + t];
                 ur += tv * c.x;
                 ui += tv * c.y;
@@ -344,10 +355,19 @@ hipError_t run_long_direct(Plan& p, const double* x, const double* q) {
     int B = 256;
     while (B > 64 && (size_t)nh * P * sizeof(cpx<real>) + 2 * (size_t)P * B * sizeof(real) > 65536) B >>= 1;
     size_t lds2 = (size_t)nh * P * sizeof(cpx<real>) + 2 * (size_t)P * B * sizeof(real);
-    if (lds2 > 65536) return hipErrorInvalidConfiguration;
+    const bool staged = lds2 <= 65536;
+    if (!staged) {
+        B = 256;
+        while (B > 64 && 2 * (size_t)P * B * sizeof(real) > 65536) B >>= 1;
+        lds2 = 2 * (size_t)P * B * sizeof(real);
+        if (lds2 > 65536) return hipErrorInvalidConfiguration;
+    }
     t = timer_id(p, "long_eval");
     timer_begin(p, t);
-    k_long_eval<real><<<(n + B - 1) / B, B, lds2, p.stream>>>(ea);
+    if (staged)
+        k_long_eval<real, true><<<(n + B - 1) / B, B, lds2, p.stream>>>(ea);
+    else
+        k_long_eval<real, false><<<(n + B - 1) / B, B, lds2, p.stream>>>(ea);
     timer_end(p, t);
     return hipGetLastError();
 }

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(int* data, int len, c
 template <typename real>
 __global__ void k_combine(const vec4<real>* __restrict__ part, const double* __restrict__ q,
                           int64_t n, double self_coeff, double* __restrict__ phi, double* __restrict__ force,
-                          double* __restrict__ red) {
+                          double* __restrict__ grad, double* __restrict__ red) {
     __shared__ double lds[16];
     double e = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -114,6 +114,8 @@ __global__ void k_combine(const vec4<real>* __restrict__ part, const double* __r
         if (phi) phi[i] = ph;
         if (force)
             for (int d = 0; d < 3; ++d) force[3 * i + d] = -qi * g[d];
+        if (grad)
+            for (int d = 0; d < 3; ++d) grad[3 * i + d] = g[d];
         e += qi * ph;
     }
     double t = block_sum_double(e, lds);
@@ -187,16 +189,16 @@ hipError_t launch_counting_sort(Plan& p, const int* key, int n, int nbins, int* 
     return hipGetLastError();
 }
 
-hipError_t launch_combine(Plan& p, const double* q, double* phi, double* force, double* energy) {
+hipError_t launch_combine(Plan& p, const double* q, double* phi, double* force, double* grad, double* energy) {
     int nb = p.ws.red_blocks;
     int t = timer_id(p, "combine");
     timer_begin(p, t);
     if (p.r.prec == SOG_PREC_FP64)
         k_combine<double><<<nb, 256, 0, p.stream>>>((const vec4<double>*)p.ws.parts, q,
-                                                     p.r.n, p.r.self_coeff, phi, force, p.ws.red);
+                                                     p.r.n, p.r.self_coeff, phi, force, grad, p.ws.red);
     else
         k_combine<float><<<nb, 256, 0, p.stream>>>((const vec4<float>*)p.ws.parts, q,
-                                                    p.r.n, p.r.self_coeff, phi, force, p.ws.red);
+                                                    p.r.n, p.r.self_coeff, phi, force, grad, p.ws.red);
     if (energy) k_energy_final<<<1, 256, 0, p.stream>>>(p.ws.red, nb, energy);
     timer_end(p, t);
     return hipGetLastError();

@@ -129,6 +129,7 @@ void spread_tile(int prec, int Pw, int B[3]) {
 // not enough of them.
 bool spread_lane_nodes(int Pw, int HZ, int Bz, signed char* noy, signed char* noz) {
     for (int i = 0; i < 4 * 64; ++i) noy[i] = noz[i] = -1;
+    if (Pw < 1 || Pw > kMaxPw) return false;  // the table holds 4 passes of 64 nodes
     if (spread_pitch_conflict_free(Pw, HZ)) {
         int used[64] = {0};
         for (int oy = 0; oy < Pw; ++oy)
@@ -185,7 +186,9 @@ MidChoice plan_mid(const double L[3], int64_t n, double s0, double sm, double ep
     MidChoice best;
     const double eps_t = eps, eps_w = eps, eps_p = eps;
     double hmax = kPi * s0 / (2.0 * std::sqrt(std::log(0.1 / eps_t)));
-    const double fr[] = {1.0, 0.92, 0.85, 0.78, 0.7, 0.62, 0.55, 0.48};
+    // grid spacings as fractions of the coarsest that resolves s_0; the finer ones let the
+    // widest window the kernels take (P_w = 15) reach tight tolerances
+    const double fr[] = {1.0, 0.92, 0.85, 0.78, 0.7, 0.62, 0.55, 0.48, 0.42, 0.36};
     for (double f : fr) {
         MidChoice c;
         double h = f * hmax;
@@ -200,7 +203,7 @@ MidChoice plan_mid(const double L[3], int64_t n, double s0, double sm, double ep
             Pw = ov.mid_Pw[0];
             window_exponent(Pw, hw, s0, &S);
         } else {
-            for (int p = 5; p <= 31; p += 2) {
+            for (int p = 5; p <= kMaxPw; p += 2) {
                 double Sp;
                 double E = window_exponent(p, hw, s0, &Sp);
                 if (std::exp(-E) <= eps_w) { Pw = p; S = Sp; break; }
@@ -291,7 +294,7 @@ LongChoice plan_long(const double L[3], int64_t n, double sl, double eps, int pr
         f.Pw2 = ov.long_Pw[0];
         window_exponent(f.Pw2, hw, sl, &f.S2);
     } else {
-        for (int p = 5; p <= 31; p += 2) {
+        for (int p = 5; p <= kMaxPw; p += 2) {
             double Sp;
             if (std::exp(-window_exponent(p, hw, sl, &Sp)) <= eps) { f.Pw2 = p; f.S2 = Sp; break; }
         }
@@ -470,8 +473,8 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
     if (!(tol >= tmin && tol <= 1e-2)) { err = "tol outside the reachable range for this precision"; return SOG_ERR_TOL_UNREACHABLE; }
     r.tol = tol;
     if (ov.mid_Pw[0] != ov.mid_Pw[1] || ov.mid_Pw[0] != ov.mid_Pw[2]) { err = "mid_Pw must be equal in x, y, z"; return SOG_ERR_INVALID_ARG; }
-    if (ov.mid_Pw[0] < 0 || (ov.mid_Pw[0] > 0 && (ov.mid_Pw[0] % 2 == 0 || ov.mid_Pw[0] < 3 || ov.mid_Pw[0] > 31))) { err = "mid_Pw must be odd in [3, 31]"; return SOG_ERR_INVALID_ARG; }
-    if (ov.long_Pw[0] != ov.long_Pw[1] || (ov.long_Pw[0] > 0 && (ov.long_Pw[0] % 2 == 0 || ov.long_Pw[0] < 3 || ov.long_Pw[0] > 31))) { err = "long_Pw must be odd in [3, 31] and equal in x, y"; return SOG_ERR_INVALID_ARG; }
+    if (ov.mid_Pw[0] < 0 || (ov.mid_Pw[0] > 0 && (ov.mid_Pw[0] % 2 == 0 || ov.mid_Pw[0] < 3 || ov.mid_Pw[0] > kMaxPw))) { err = "mid_Pw must be odd in [3, 15]"; return SOG_ERR_INVALID_ARG; }
+    if (ov.long_Pw[0] != ov.long_Pw[1] || (ov.long_Pw[0] > 0 && (ov.long_Pw[0] % 2 == 0 || ov.long_Pw[0] < 3 || ov.long_Pw[0] > kMaxPw))) { err = "long_Pw must be odd in [3, 15] and equal in x, y"; return SOG_ERR_INVALID_ARG; }
     if (ov.long_P < 0 || ov.long_P > 64) { err = "long_P must be in [1, 64]"; return SOG_ERR_INVALID_ARG; }
     if (ov.mid_Izs % 2) { err = "mid_Izs must be even"; return SOG_ERR_INVALID_ARG; }
 

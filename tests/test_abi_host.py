@@ -81,6 +81,7 @@ def test_resolve_rejects_bad_arguments(box, n, tol, prec, status):
     dict(mid_Pw=[9, 9, 7]),        # not equal in x, y, z
     dict(long_P=65),
     dict(mid_Izs=81),              # odd padded z grid
+    dict(mid_Pw=[17, 17, 17]),     # wider than the kernels are built for
 ])
 def test_resolve_rejects_bad_overrides(params):
     assert _resolve_status((20, 20, 20), 1000, 1e-4, "fp64", params) == _lib.SOG_ERR_INVALID_ARG
@@ -121,7 +122,7 @@ def test_plan_structure(name, prec, tol):
         assert s[p["m"]] <= 2.0 * Lz * (1 + 1e-12)
         assert I[0] % 2 == 0 and I[1] % 2 == 0 and Izs % 2 == 0
         assert _smooth(I[0]) and _smooth(I[1]) and _smooth(Izs // 2)
-        assert Pw % 2 == 1 and 3 <= Pw <= 31
+        assert Pw % 2 == 1 and 3 <= Pw <= 15  # the widest window the kernels are built for
         # the padded z grid holds the box, the window support and some padding
         hz = Lz / I[2]
         assert Izs * hz >= Lz + (Pw - 1) * hz
@@ -151,3 +152,14 @@ def test_tighter_tolerance_refines():
     hi = sog.plan_parameters((100, 100, 100), 1000000, 1e-8, "fp64")
     assert hi["b"] <= lo["b"]
     assert hi["mid_Pw"][0] >= lo["mid_Pw"][0]
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-8, 1e-10, 1e-12])
+def test_tight_tolerance_small_box_plans(tol):
+    # every window the planner picks fits the kernels (P_w <= 15); the lane-node table of
+    # the gridding kernel holds 4 passes of 64 nodes
+    p = sog.plan_parameters((24.0, 24.0, 12.0), 400, tol, "fp64")
+    if p["m"] >= 0:
+        assert p["mid_Pw"][0] <= 15
+    if p["m"] < p["M"] and p["long_form"] == _lib.SOG_LONG_FFT:
+        assert p["long_Pw"][0] <= 15
