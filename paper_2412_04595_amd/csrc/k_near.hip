@@ -187,8 +187,7 @@ __device__ __forceinline__ double near_rsqrt(double v) { return rsqrt(v); }
 
 template <typename real, int DEG>
 __device__ __forceinline__ void near_pair(const NearArgs<real>& a, real rx, real ry, real rz, real qj, real& phi,
-                                          real& gx, real& gy, real& gz) {
-    const real r2 = rx * rx + ry * ry + rz * rz;
+                                          real& gx, real& gy, real& gz, real r2) {
     // F(r) and F'(r)/r as Chebyshev series in xs = 2 r^2/r_c^2 - 1, one forward
     // recurrence for both (coefficients above the fitted degree are zero)
     const real xs = (real)2 * r2 * a.inv_rc2 - (real)1;
@@ -209,6 +208,12 @@ __device__ __forceinline__ void near_pair(const NearArgs<real>& a, real rx, real
     gx += c * rx;
     gy += c * ry;
     gz += c * rz;
+}
+
+template <typename real, int DEG>
+__device__ __forceinline__ void near_pair(const NearArgs<real>& a, real rx, real ry, real rz, real qj, real& phi,
+                                          real& gx, real& gy, real& gz) {
+    near_pair<real, DEG>(a, rx, ry, rz, qj, phi, gx, gy, gz, rx * rx + ry * ry + rz * rz);
 }
 
 // Each wave takes one z-block.  Its lanes hold up to 64 targets; the candidate sources
@@ -368,10 +373,239 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
     }
 }
 
+// The float32 pair kernel with the candidate test on the matrix cores.  A pass takes 32
+// targets; lanes l and l + 32 share target l % 32 and split its candidates between their
+// hit lists.  The unit's 18 candidate ranges are walked as one sequence in blocks of 32,
+// and one block against the pass's targets is a 32 x 32 matrix
+//     D[i][j] = |c_i|^2 - 2 c_i . t_j  =  r_ij^2 - |t_j|^2,
+// the product of the rows (c_x, c_y, c_z, |c|^2) and the columns (-2 t_x, -2 t_y,
+// -2 t_z, 1), two v_mfma_f32_32x32x2f32 steps.  Candidate i of the block sits in lane
+// i and i + 32 (k = 0 and 1 of the contraction), target j in lanes j and j + 32;
+// register r of lane l holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].  A pair is a hit
+// when D < r_c^2 - |t_j|^2.  Coordinates are offsets from the centre of the unit's
+// column cell in x, y and from the middle of its run in z, so |c|^2 stays below about
+// 25 cells^2 and the rounding of D is far below the cut-off's width.
+// The pairs are evaluated from the hit lists with r computed directly as t - c; the
+// target and a candidate of its own column and frame get their coordinates by adding
+// the same shift to the same stored values, so the particle paired with itself has
+// r^2 == 0 exactly and is dropped there.
+typedef float near_v16f __attribute__((ext_vector_type(16)));
+
+// lane k's value of a float (the builtin moves 32-bit integers: pass the bits, not the value)
+__device__ __forceinline__ float readlane_f(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+constexpr int kNearMfmaRows = 16;  // hit-list slots a block appends per lane
+
+template <int DEG>
+__device__ __forceinline__ void near_pair_nz(const NearArgs<float>& a, float rx, float ry, float rz, float qj,
+                                             float& phi, float& gx, float& gy, float& gz) {
+    const float r2 = rx * rx + ry * ry + rz * rz;
+    const bool nz = r2 > 0.f;
+    near_pair<float, DEG>(a, rx, ry, rz, nz ? qj : 0.f, phi, gx, gy, gz, nz ? r2 : 1.f);
+}
+
+template <int DEG>
+__global__ __launch_bounds__(64 * kNearWaves) void k_near_mfma(NearArgs<float> a) {
+    __shared__ uint32_t hits_all[kNearWaves][kNearCap * 64];
+    __shared__ vec4<float> shift_all[kNearWaves][18];
+    __shared__ alignas(16) uint32_t codes_all[kNearWaves][32];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, half = lane >> 5, jl = lane & 31;
+    uint32_t* hits = hits_all[wv];
+    vec4<float>* shift = shift_all[wv];
+    uint32_t* codes = codes_all[wv];
+    char* hits_bytes = reinterpret_cast<char*>(&hits_all[0][0]);
+    static_assert(kNearCap * 256 == 8192, "list slot bits 8..12 between the lane and wave bits");
+    const uint32_t lb = (uint32_t)wv * (kNearCap * 256) | (uint32_t)lane * 4;
+    const int per = (a.max_units + 7) >> 3;
+    const int ibeg = (blockIdx.x & 7) * per, iend = min(a.max_units, ibeg + per);
+    int* grab = a.grab + (blockIdx.x & 7) * kGrabStride;
+    const float fh = (float)kNearFrameCells * a.ch[2];  // frame height
+    for (;;) {
+    int g = 0;
+    if (lane == 0) g = atomicAdd(grab, 1);
+    const int item = ibeg + __builtin_amdgcn_readfirstlane(g);
+    if (item >= iend) break;
+    const int4 unit = a.units[item];
+    if (unit.y < 0) continue;
+    const int col = unit.x, z0 = unit.y, z1 = unit.z;
+    const int cy = col % a.nc[1], cx = col / a.nc[1];
+    const int tb = a.cell_start[col * a.nc[2] + z0], te = a.cell_start[col * a.nc[2] + z1];
+    const int za = max(z0 - 1, 0), zb = min(z1 + 1, a.nc[2]);
+    const int bnd = (za / kNearFrameCells + 1) * kNearFrameCells;
+    const float zmid = 0.5f * (float)(z0 + z1) * a.ch[2];
+    // lane k < 18: range k = column (dx, dy) = k / 2, piece k % 2 of the cells from below
+    // the run to above it, cut at the frame boundary; its shift into the unit frame
+    int rs = 0, len = 0;
+    vec4<float> sk = {0.f, 0.f, 0.f, 0.f};
+    if (lane < 18) {
+        const int c9 = lane >> 1, piece = lane & 1;
+        const int dx = c9 % 3 - 1, dy = c9 / 3 - 1;
+        const int ncol = imod(cx + dx, a.nc[0]) * a.nc[1] + imod(cy + dy, a.nc[1]);
+        const int pa = piece ? bnd : za, pb = piece ? zb : min(zb, bnd);
+        if (pa < pb) {
+            rs = a.cell_start[ncol * a.nc[2] + pa];
+            len = a.cell_start[ncol * a.nc[2] + pb] - rs;
+        }
+        sk = vec4<float>{((float)dx - 0.5f) * a.ch[0], ((float)dy - 0.5f) * a.ch[1],
+                         (float)(pa / kNearFrameCells) * fh - zmid, 0.f};
+        shift[lane] = sk;
+    }
+    // the ranges as one sequence: range k holds positions [pre_k, pre_k + len_k), and
+    // position v of it is particle base_k + v
+    int inc = len;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    const int pre = inc - len, base = rs - pre;
+    const int total = __builtin_amdgcn_readlane(inc, 17);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int t0 = tb; t0 < te; t0 += 32) {
+        const int p = t0 + jl;
+        const bool act = p < te;
+        const vec4<float> me = act ? a.pos[p] : vec4<float>{0.f, 0.f, 0.f, 0.f};
+        int tcz = z0;
+        for (int c = z0 + 1; c < z1; ++c)
+            if (p >= a.cell_start[col * a.nc[2] + c]) tcz = c;
+        // the target in the unit frame: the shift of its own column (dx = dy = 0, ranges
+        // 8 and 9) in its own frame
+        const vec4<float> st = shift[8 + ((tcz / kNearFrameCells) != (za / kNearFrameCells) ? 1 : 0)];
+        const float tx = me.x + st.x, ty = me.y + st.y, tz = me.z + st.z;
+        const float thr = act ? a.rc2 - (tx * tx + ty * ty + tz * tz) : -INFINITY;
+        const float b1 = half ? -2.f * ty : -2.f * tx;
+        const float b2 = half ? 1.f : -2.f * tz;
+        float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        int tp = 0, hd = 0;
+        constexpr int kMask = kNearCap - 1;
+        auto chunk = [&]() {
+            const int cnt = (tp - hd) & kMask;
+            vec4<float> o[4], sh[4];
+            const uint32_t dummy = (uint32_t)tb | (8u << kNearCodeShift);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t e = (cnt > 0) ? hits[((hd + min(u, cnt - 1)) & kMask) * 64 + lane] : dummy;
+                o[u] = a.pos[e & ((1u << kNearCodeShift) - 1)];
+                sh[u] = shift[e >> kNearCodeShift];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u < cnt)
+                    near_pair_nz<DEG>(a, tx - (o[u].x + sh[u].x), ty - (o[u].y + sh[u].y), tz - (o[u].z + sh[u].z),
+                                      o[u].w, phi, gx, gy, gz);
+            hd = (hd + min(cnt, 4)) & kMask;
+        };
+        auto drain_ready = [&]() {
+            while (true) {
+                const int cnt = (tp - hd) & kMask;
+                if (__ballot(act && cnt < 4) != 0 && __ballot(cnt > kNearCap - 1 - kNearMfmaRows) == 0) break;
+                chunk();
+            }
+        };
+        // this lane's candidate of a block at v0: the range it falls in, its particle and
+        // shift.  Every lane starts from the range holding v0 (k0, uniform, found from
+        // the previous block's) and moves on to each later range that starts at or
+        // before its own position v0 + lane % 32.  The next block's record is loaded
+        // while the current one is tested.
+        int k0 = 0, kl = 0, bl = 0;
+        float sx = 0.f, sy = 0.f, sz = 0.f;
+        auto advance = [&](int v0) {
+            while (k0 + 1 < 18 && __builtin_amdgcn_readlane(pre, k0 + 1) <= v0) ++k0;
+            kl = k0;
+            bl = __builtin_amdgcn_readlane(base, k0);
+            sx = readlane_f(sk.x, k0);
+            sy = readlane_f(sk.y, k0);
+            sz = readlane_f(sk.z, k0);
+            const int v = v0 + jl;
+            for (int kk = k0 + 1; kk < 18 && __builtin_amdgcn_readlane(pre, kk) <= v0 + 31; ++kk) {
+                const int bk = __builtin_amdgcn_readlane(base, kk);
+                const float xk = readlane_f(sk.x, kk), yk = readlane_f(sk.y, kk),
+                            zk = readlane_f(sk.z, kk);
+                if (v >= __builtin_amdgcn_readlane(pre, kk)) {
+                    kl = kk;
+                    bl = bk;
+                    sx = xk;
+                    sy = yk;
+                    sz = zk;
+                }
+            }
+        };
+        advance(0);
+        bool vn = jl < total;
+        uint32_t cn = (uint32_t)(vn ? bl + jl : tb) | ((uint32_t)kl << kNearCodeShift);
+        vec4<float> on = a.pos[cn & ((1u << kNearCodeShift) - 1)];
+        float sxn = sx, syn = sy, szn = sz;
+        for (int v0 = 0; v0 < total; v0 += 32) {
+            const bool valid = vn;
+            const uint32_t code = cn;
+            const vec4<float> o = on;
+            const float csx = sxn, csy = syn, csz = szn;
+            if (v0 + 32 < total) {
+                advance(v0 + 32);
+                vn = v0 + 32 + jl < total;
+                cn = (uint32_t)(vn ? bl + v0 + 32 + jl : tb) | ((uint32_t)kl << kNearCodeShift);
+                on = a.pos[cn & ((1u << kNearCodeShift) - 1)];
+                sxn = sx;
+                syn = sy;
+                szn = sz;
+            }
+            float ux = o.x + csx, uy = o.y + csy, uz = o.z + csz;
+            float u2 = ux * ux + uy * uy + uz * uz;
+            if (!valid) {
+                ux = uy = uz = 0.f;
+                u2 = 1e30f;
+            }
+            const float a1 = half ? uy : ux;
+            const float a2 = half ? u2 : uz;
+            drain_ready();
+            if (half == 0) codes[jl] = code;
+            near_v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, b2, acc, 0, 0, 0);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            uint4 cd[4];
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) cd[q4] = *reinterpret_cast<const uint4*>(&codes[8 * q4 + 4 * half]);
+            // the tail slot as a byte offset into the lists of all waves: wave, slot and
+            // lane bits are disjoint, so stepping the slot is an add and an and-or
+            uint32_t at = lb | ((uint32_t)tp << 8);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t cr = r % 4 == 0 ? cd[r / 4].x : r % 4 == 1 ? cd[r / 4].y : r % 4 == 2 ? cd[r / 4].z : cd[r / 4].w;
+                *reinterpret_cast<uint32_t*>(hits_bytes + at) = cr;
+                const uint32_t nx = ((at + 256u) & ((uint32_t)kMask << 8)) | lb;
+                at = acc[r] < thr ? nx : at;
+            }
+            tp = (int)(at >> 8) & kMask;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        while (__ballot(tp != hd)) chunk();
+        phi += __shfl_xor(phi, 32, 64);
+        gx += __shfl_xor(gx, 32, 64);
+        gy += __shfl_xor(gy, 32, 64);
+        gz += __shfl_xor(gz, 32, 64);
+        if (act && half == 0) {
+            const int i = a.orig[p];
+            a.part[i] = vec4<float>{phi, gx, gy, gz};
+        }
+    }
+    }
+}
+
 // polynomial degrees compiled; the fitted degree is rounded up to one of these
 template <typename real, int DEG>
 void launch_near_deg(const NearArgs<real>& a, int blocks, hipStream_t st) {
-    k_near<real, DEG><<<blocks, 64 * kNearWaves, 0, st>>>(a);
+    if constexpr (sizeof(real) == 4)
+        k_near_mfma<DEG><<<blocks, 64 * kNearWaves, 0, st>>>(a);
+    else
+        k_near<real, DEG><<<blocks, 64 * kNearWaves, 0, st>>>(a);
 }
 
 template <typename real>
