@@ -120,7 +120,7 @@ sog_status build_plan(Plan& p) {
     A.get(ws.cell_start, (ncells + 1) * 4);
     A.get(ws.near_orig, n * 4);
     A.get(ws.near_pos, n * 4 * rs);
-    A.get(ws.near_units, ((size_t)ncells * 16 + 127) / 128 * 128 + 8 * 128);  // units, then 8 work counters
+    A.get(ws.near_units, ((size_t)near_unit_slots(r) * 16 + 127) / 128 * 128 + 8 * 128);  // units, then 8 work counters
     if (r.has_mid) {
         const int ntiles = r.ntile[0] * r.ntile[1] * r.ntile[2];
         maxbins = std::max<int64_t>(maxbins, ntiles);

@@ -110,6 +110,50 @@ struct Resolved {
     int max_dup2 = 1;
 };
 
+// Near-field work units.  Float64: runs of at most kNearUnitCells cells of a column with at
+// most 64 targets, one slot per cell.  Float32: chunks of at most kNearChunk consecutive
+// targets of a column within at most kNearUnitCells cells, formed greedily; a column of
+// ncz cells needs at most floor(count / kNearChunk) full chunks, one last chunk and
+// ceil(ncz / kNearUnitCells) - 1 chunks cut short (their first cells lie below
+// ncz - kNearUnitCells, kNearUnitCells apart), so column c's slots start at
+// floor(first particle of c / kNearChunk) + c * (ceil(ncz / kNearUnitCells) + 1), one
+// slot of slack per column.
+constexpr int kNearUnitCells = 7;
+constexpr int kNearChunk = 32;
+inline int near_chunk_extra(int ncz) { return (ncz + kNearUnitCells - 1) / kNearUnitCells + 1; }
+
+#if defined(__HIP__)
+#define SOG_HOST_DEVICE __host__ __device__
+#else
+#define SOG_HOST_DEVICE
+#endif
+// The greedy chunking of one column, given its ncz + 1 cell starts cs (particle indices):
+// emit(first cell, first target, end target, end cell) for each chunk in z order;
+// returns the number of chunks.
+template <class Emit>
+SOG_HOST_DEVICE inline int near_chunk_walk(const int* cs, int ncz, Emit&& emit) {
+    const int pend = cs[ncz];
+    int p = cs[0], z = 0, u = 0;
+    while (p < pend) {
+        while (cs[z + 1] <= p) ++z;  // the cell holding p
+        const int za = z;
+        int e = p + kNearChunk < pend ? p + kNearChunk : pend;
+        const int lim = za + kNearUnitCells < ncz ? za + kNearUnitCells : ncz;
+        if (cs[lim] < e) e = cs[lim];
+        int zb = za;
+        while (cs[zb + 1] < e) ++zb;  // the cell holding e - 1
+        emit(za, p, e, zb + 1);
+        ++u;
+        p = e;
+    }
+    return u;
+}
+inline int64_t near_unit_slots(const Resolved& r) {
+    const int64_t ncols = (int64_t)r.nc[0] * r.nc[1];
+    if (r.prec == SOG_PREC_FP64) return ncols * r.nc[2];
+    return r.n / kNearChunk + ncols * near_chunk_extra(r.nc[2]);
+}
+
 struct KernelTimer {
     const char* name;
     double total_ms = 0;
@@ -139,7 +183,7 @@ struct Workspace {
     int* cell_start = nullptr;  // ncells + 1
     int* near_orig = nullptr;   // n
     void* near_pos = nullptr;   // n x real4 (x, y, z relative to the cell corner; q)
-    void* near_units = nullptr; // ncells x int4 work units (column, first cell, end cell), then 8 work counters
+    void* near_units = nullptr; // near_unit_slots() int4 work units, then 8 work counters
     // mid range
     int* tile_start = nullptr;  // ntiles + 1 (owners)
     signed char* spread_nodes = nullptr;  // 2 x 256: node_oy, node_oz of the plan

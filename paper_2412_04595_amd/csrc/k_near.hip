@@ -32,9 +32,10 @@ struct NearGeom {
     int nc[3];
 };
 
-constexpr int kNearFrameCells = 8;  // z cells per coordinate frame
-constexpr int kNearUnitCells = 7;   // cells per work unit at most: its candidate z range
+constexpr int kNearFrameCells = 8;  // z cells per coordinate frame; a work unit spans at most
+                                    // kNearUnitCells = 7 cells, so its candidate z range
                                     // (<= 9 cells) crosses at most one frame boundary
+static_assert(kNearUnitCells + 2 <= kNearFrameCells + 1, "candidate range crosses two frame boundaries");
 constexpr int kNearUnitTargets = 64;
 
 __device__ __forceinline__ void cell_of(const NearGeom& g, double xw, double yw, double z, int c[3]) {
@@ -149,9 +150,37 @@ __global__ __launch_bounds__(64) void k_near_units(const int* __restrict__ cell_
     for (int i = u + (int)threadIdx.x; i < ncz; i += 64) us[i] = make_int4(col, -1, -1, 0);
 }
 
+// Work units of the float32 pair kernel: chunks of at most kNearChunk consecutive targets
+// of a column, cut where a chunk would span more than kNearUnitCells cells; unit =
+// (cell of the first target, first target, end target, end cell), in the column's slots
+// (see near_unit_slots), unused slots marked by -1.  One wave per column: the column's
+// cell starts are staged in LDS when they fit, and lane 0 walks them.
+__global__ __launch_bounds__(64) void k_near_chunks(const int* __restrict__ cell_start, int ncz, int extra,
+                                                     int4* __restrict__ units, int* __restrict__ grab) {
+    __shared__ int cs_lds[kUnitsLds + 1];
+    const int col = blockIdx.x;
+    if (col == 0 && threadIdx.x < 8) grab[threadIdx.x * kGrabStride] = 0;  // the pair kernel's work counters
+    const int* gcs = cell_start + (size_t)col * ncz;
+    const int* cs = gcs;
+    if (ncz <= kUnitsLds) {
+        for (int i = threadIdx.x; i <= ncz; i += 64) cs_lds[i] = gcs[i];
+        __syncthreads();
+        cs = cs_lds;
+    }
+    const int64_t s0 = (int64_t)(gcs[0] / kNearChunk) + (int64_t)col * extra;
+    const int64_t s1 = (int64_t)(gcs[ncz] / kNearChunk) + (int64_t)(col + 1) * extra;
+    int u = 0;
+    if (threadIdx.x == 0) {
+        int4* us = units + s0;
+        u = near_chunk_walk(cs, ncz, [&](int za, int p, int e, int z1) { *us++ = make_int4(col * ncz + za, p, e, z1); });
+    }
+    u = __shfl(u, 0, 64);
+    for (int64_t i = s0 + u + (int)threadIdx.x; i < s1; i += 64) units[i] = make_int4(0, -1, -1, 0);
+}
+
 // the 8 work counters live after the units, on 128-byte boundaries
-inline int* near_grab(const Workspace& ws, int ncells) {
-    return reinterpret_cast<int*>(static_cast<char*>(ws.near_units) + ((size_t)ncells * 16 + 127) / 128 * 128);
+inline int* near_grab(const Workspace& ws, int64_t slots) {
+    return reinterpret_cast<int*>(static_cast<char*>(ws.near_units) + ((size_t)slots * 16 + 127) / 128 * 128);
 }
 
 template <typename real>
@@ -428,9 +457,9 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near_mfma(NearArgs<float> a
     if (item >= iend) break;
     const int4 unit = a.units[item];
     if (unit.y < 0) continue;
-    const int col = unit.x, z0 = unit.y, z1 = unit.z;
+    const int col = unit.x / a.nc[2], z0 = unit.x - col * a.nc[2], z1 = unit.w;
     const int cy = col % a.nc[1], cx = col / a.nc[1];
-    const int tb = a.cell_start[col * a.nc[2] + z0], te = a.cell_start[col * a.nc[2] + z1];
+    const int tb = unit.y, te = unit.z;
     const int za = max(z0 - 1, 0), zb = min(z1 + 1, a.nc[2]);
     const int bnd = (za / kNearFrameCells + 1) * kNearFrameCells;
     const float zmid = 0.5f * (float)(z0 + z1) * a.ch[2];
@@ -647,8 +676,12 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
         k_near_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, (const int2*)ws.key, ws.cell_start,
                                                          (vec4<real>*)ws.near_pos, ws.near_orig);
         const int ncols = r.nc[0] * r.nc[1];
-        k_near_units<<<ncols, 64, 0, p.stream>>>(ws.cell_start, r.nc[2], (int4*)ws.near_units,
-                                                 near_grab(ws, ncells));
+        if (sizeof(real) == 4)
+            k_near_chunks<<<ncols, 64, 0, p.stream>>>(ws.cell_start, r.nc[2], near_chunk_extra(r.nc[2]),
+                                                      (int4*)ws.near_units, near_grab(ws, near_unit_slots(r)));
+        else
+            k_near_units<<<ncols, 64, 0, p.stream>>>(ws.cell_start, r.nc[2], (int4*)ws.near_units,
+                                                     near_grab(ws, near_unit_slots(r)));
         timer_end(p, t);
         if (!(stages & 2)) return hipGetLastError();
     }
@@ -656,8 +689,8 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
     a.pos = (const vec4<real>*)ws.near_pos;
     a.orig = ws.near_orig;
     a.units = (const int4*)ws.near_units;
-    a.grab = near_grab(ws, ncells);
-    a.max_units = ncells;
+    a.grab = near_grab(ws, near_unit_slots(r));
+    a.max_units = (int)near_unit_slots(r);
     a.cell_start = ws.cell_start;
     a.part = (vec4<real>*)ws.parts;
     for (int d = 0; d < 3; ++d) {
@@ -673,7 +706,7 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
     }
     const int t = timer_id(p, "near");
     timer_begin(p, t);
-    const int want = std::min(p.num_cus * kNearBlocksPerCU, (ncells + kNearWaves - 1) / kNearWaves);
+    const int want = std::min(p.num_cus * kNearBlocksPerCU, (a.max_units + kNearWaves - 1) / kNearWaves);
     launch_near_kernel<real>(a, std::max(8, (want + 7) / 8 * 8), p.stream);
     timer_end(p, t);
     return hipGetLastError();

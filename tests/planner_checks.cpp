@@ -12,7 +12,8 @@
 //  3. FFT factorisation: every length up to the longest line the kernels take factors
 //     exactly when it has no prime factor above 7, into compiled radices;
 //  4. the z band: for z in [0, L_z] the nearest node is never clamped, so every window
-//     lies inside the band of planes the z transforms read and write.
+//     lies inside the band of planes the z transforms read and write;
+//  5. the near-field chunks of the float32 pair kernel fit their slots (below).
 //
 // Prints one line per failure and "bad N"; exit status 0 when N == 0.
 #include <cmath>
@@ -149,7 +150,50 @@ static void check_z_band() {
         }
 }
 
+// 5. near-field chunks (float32 pair kernel): for random columns (empty cells, dense
+//    cells, one crowded cell, long sparse columns) the chunks tile the column's particles
+//    in order, hold 1..kNearChunk targets within at most kNearUnitCells cells, name the
+//    cells of their first and last targets, and fit the column's slots
+//    [floor(first / kNearChunk) + c * extra, floor(end / kNearChunk) + (c + 1) * extra).
+static void check_near_chunks() {
+    unsigned long long st = 12345;
+    auto rnd = [&]() {
+        st = st * 6364136223846793005ULL + 1442695040888963407ULL;
+        return (unsigned)(st >> 33);
+    };
+    for (int trial = 0; trial < 4000; ++trial) {
+        const int ncz = 1 + (int)(rnd() % (trial < 2000 ? 40 : 400));
+        const int mode = trial % 5;
+        std::vector<int> cs(ncz + 1);
+        cs[0] = (int)(rnd() % 1000);
+        for (int z = 0; z < ncz; ++z) {
+            int c = 0;
+            if (mode == 0) c = (int)(rnd() % 43);                  // about 21 per cell
+            if (mode == 1) c = (rnd() % 4 == 0) ? (int)(rnd() % 9) : 0;  // sparse
+            if (mode == 2) c = (int)(rnd() % 200);                 // dense
+            if (mode == 3) c = (z == ncz / 2) ? 1000 : (int)(rnd() % 3);  // one crowded cell
+            if (mode == 4) c = (int)(rnd() % 2);                   // long, nearly empty
+            cs[z + 1] = cs[z] + c;
+        }
+        const int extra = near_chunk_extra(ncz);
+        const long col = rnd() % 1000;
+        const long s0 = cs[0] / kNearChunk + col * extra, s1 = cs[ncz] / kNearChunk + (col + 1) * extra;
+        int expect = cs[0];
+        const int nu = near_chunk_walk(cs.data(), ncz, [&](int za, int p, int e, int z1) {
+            CHECK(p == expect && e > p && e - p <= kNearChunk, "chunks: trial %d [%d, %d) after %d", trial, p, e, expect);
+            CHECK(za >= 0 && z1 <= ncz && z1 - za <= kNearUnitCells && z1 > za, "chunks: trial %d cells [%d, %d)", trial,
+                  za, z1);
+            CHECK(cs[za] <= p && p < cs[za + 1], "chunks: trial %d first target not in cell %d", trial, za);
+            CHECK(cs[z1 - 1] <= e - 1 && e - 1 < cs[z1], "chunks: trial %d last target not in cell %d", trial, z1 - 1);
+            expect = e;
+        });
+        CHECK(expect == cs[ncz], "chunks: trial %d ends at %d of %d", trial, expect, cs[ncz]);
+        CHECK(s0 + nu <= s1, "chunks: trial %d: %d chunks in %ld slots", trial, nu, s1 - s0);
+    }
+}
+
 int main() {
+    check_near_chunks();
     check_lane_nodes_and_addresses();
     check_fft_factors();
     check_z_band();
