@@ -26,6 +26,11 @@ CASES = {
     # tall cell: long z lines in the FFT, many Chebyshev terms
     "tall": dict(N=1200, box=(10.0, 10.0, 60.0), seed=13, row=3, rc=3.0, M=140, m=8,
                  mid=dict(I=(20, 20, 120), Izs=252, Pw=9), long=dict(form="direct", P=20, nk=(1, 1))),
+    # clustered input in a tall box (workloads.clustered): cells holding hundreds of
+    # particles next to long runs of nearly empty cells, several z frames of the near
+    # field's coordinates
+    "clustered": dict(N=3000, box=(12.0, 12.0, 48.0), seed=15, row=3, rc=3.0, M=140, m=8, gen="clustered",
+                      mid=dict(I=(24, 24, 96), Izs=200, Pw=9), long=dict(form="direct", P=20, nk=(1, 1))),
     # window 13 and odd-radix FFT lengths (3, 5, 7)
     "radix_mix": dict(N=900, box=(21.0, 15.0, 10.0), seed=14, row=4, rc=3.5, M=200, m=5,
                       mid=dict(I=(42, 30, 20), Izs=70, Pw=13), long=dict(form="direct", P=14, nk=(3, 2))),

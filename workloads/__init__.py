@@ -18,6 +18,11 @@ Sec. 5; the layered set stands in for an electrolyte between two interfaces):
   layer the complement, so the cell is neutral with a large z dipole.
 * ``batch_specs(n_systems, seed, ...)``: N_s log-uniform in [Nmin, Nmax] (even),
   aspect Lz/Lx from {1/8, 1, 8}, density 1.
+* ``clustered(N, box, seed, ...)``: a fraction ``frac`` of the particles in a Gaussian
+  cluster (standard deviation ``sd`` in each direction, z redrawn into [0, L_z], x and y
+  wrapped) about the box centre; of the rest, a fraction ``top`` uniform in the upper
+  half of the box and the others uniform in the lower half.  Dense cells next to long
+  runs of nearly empty ones, for the near field's work division.
 """
 import numpy as np
 
@@ -77,6 +82,28 @@ def layered(N, box, seed, z1=5.0, z2=55.0, sd=3.0, enrich=0.6):
     rng.shuffle(qu)
     q[:half], q[half:] = ql, qu
     return x, q
+
+
+def clustered(N, box, seed, frac=0.4, sd=0.7, top=0.05):
+    rng = np.random.default_rng(seed)
+    Lx, Ly, Lz = box
+    nc = int(round(frac * N))
+    nt = int(round(top * (N - nc)))
+    nb = N - nc - nt
+    x = np.empty((N, 3))
+    c = rng.normal(0.0, sd, (nc, 3)) + 0.5 * np.asarray(box, dtype=np.float64)
+    bad = (c[:, 2] < 0.0) | (c[:, 2] > Lz)
+    while bad.any():
+        c[bad, 2] = rng.normal(0.5 * Lz, sd, int(bad.sum()))
+        bad = (c[:, 2] < 0.0) | (c[:, 2] > Lz)
+    c[:, 0] %= Lx
+    c[:, 1] %= Ly
+    x[:nc] = c
+    x[nc:, 0] = rng.random(N - nc) * Lx
+    x[nc:, 1] = rng.random(N - nc) * Ly
+    x[nc:nc + nb, 2] = rng.random(nb) * (0.5 * Lz)
+    x[nc + nb:, 2] = 0.5 * Lz + rng.random(nt) * (0.5 * Lz)
+    return x, _charges(rng, N)
 
 
 def named(name):
