@@ -570,8 +570,19 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near_mfma(NearArgs<float> a
         for (int v0 = 0; v0 < total; v0 += 32) {
             const bool valid = vn;
             const uint32_t code = cn;
-            const vec4<float> o = on;
-            const float csx = sxn, csy = syn, csz = szn;
+            float ux = on.x + sxn, uy = on.y + syn, uz = on.z + szn;
+            float u2 = ux * ux + uy * uy + uz * uz;
+            if (!valid) {
+                ux = uy = uz = 0.f;
+                u2 = 1e30f;
+            }
+            const float a1 = half ? uy : ux;
+            const float a2 = half ? u2 : uz;
+            if (half == 0) codes[jl] = code;
+            near_v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, b2, acc, 0, 0, 0);
+            // while the matrix core works: the next block's record, and room in the lists
             if (v0 + 32 < total) {
                 advance(v0 + 32);
                 vn = v0 + 32 + jl < total;
@@ -581,19 +592,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near_mfma(NearArgs<float> a
                 syn = sy;
                 szn = sz;
             }
-            float ux = o.x + csx, uy = o.y + csy, uz = o.z + csz;
-            float u2 = ux * ux + uy * uy + uz * uz;
-            if (!valid) {
-                ux = uy = uz = 0.f;
-                u2 = 1e30f;
-            }
-            const float a1 = half ? uy : ux;
-            const float a2 = half ? u2 : uz;
             drain_ready();
-            if (half == 0) codes[jl] = code;
-            near_v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, b2, acc, 0, 0, 0);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
