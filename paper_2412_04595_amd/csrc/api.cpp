@@ -110,7 +110,7 @@ sog_status build_plan(Plan& p) {
         A.get(ws.force, 3 * n * 8);
         A.get(ws.energy, 8);
     }
-    A.get(ws.qsum, 2 * 8);
+    A.get(ws.qsum, kQsumSlots * 2 * 8);
     A.get(ws.status, 4);
     A.get(ws.parts, 12 * n * rs);
     A.get(ws.key, n * 8);  // near-field (cell, rank) pairs; the long-range FFT form's keys
@@ -414,12 +414,16 @@ sog_status run(Plan& p, const double* x_in, const double* q_in, double* energy, 
     }
     if ((e = collect_timers(p)) != hipSuccess) return hip_status(e, "timing");
     if (p.check) {
-        double qs[2];
+        double qslots[2 * kQsumSlots], qs[2] = {0.0, 0.0};
         int st = 0;
-        e = hipMemcpyAsync(qs, ws.qsum, 16, hipMemcpyDeviceToHost, p.stream);
+        e = hipMemcpyAsync(qslots, ws.qsum, sizeof(qslots), hipMemcpyDeviceToHost, p.stream);
         if (e == hipSuccess) e = hipMemcpyAsync(&st, ws.status, 4, hipMemcpyDeviceToHost, p.stream);
         if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
         if (e != hipSuccess) return hip_status(e, "status copy");
+        for (int k = 0; k < kQsumSlots; ++k) {
+            qs[0] += qslots[2 * k];
+            qs[1] += qslots[2 * k + 1];
+        }
         if (st & 1) {
             set_error("non-finite position or charge");
             return SOG_ERR_INVALID_ARG;

@@ -15,6 +15,7 @@ namespace sog {
 constexpr int kMaxStages = 24;    // radix stages of one 1D FFT
 constexpr int kMaxNearDeg = 63;   // Chebyshev degree of the near-field polynomials
 constexpr int kMaxMid = 96;       // max number of mid-range Gaussians (m + 1)
+constexpr int kQsumSlots = 64;    // slots of the charge sums (spreads the float64 atomics of the key pass)
 constexpr int kMaxPw = 15;        // widest mid-range window the gridding and gathering kernels take
 constexpr int kSpreadStage = 32;  // particles whose window weights the gridding kernel stages at a time
 // LDS of one gridding or gathering workgroup at most: two of them fill the 160 KiB of a
@@ -169,7 +170,7 @@ struct Workspace {
     double* force = nullptr;
     double* energy = nullptr;
     // validation: [0] sum q, [1] sum |q| (double), status bits in an int
-    double* qsum = nullptr;
+    double* qsum = nullptr;     // kQsumSlots x (sum q, sum |q|): block b adds into slot b mod kQsumSlots
     int* status = nullptr;
     // per-part results in the particles' own order, one record per particle and part
     void* parts = nullptr;      // 3 x n x real4 (phi, dphi/dx, dphi/dy, dphi/dz): near, mid, long

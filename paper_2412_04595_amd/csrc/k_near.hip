@@ -49,7 +49,8 @@ __device__ __forceinline__ void cell_of(const NearGeom& g, double xw, double yw,
 // Cell of every particle and the cell histogram of the counting sort; in the same pass
 // the input checks of the problem statement (Sec. 2.1): finite inputs, z in [0, L_z]
 // (status bits 1 and 2), and the charge sums sum q, sum |q| for the neutrality test of
-// Prop. lem::summation.  Block sums need blockDim.x a multiple of 64.
+// Prop. lem::summation (block b adds into slot b mod kQsumSlots; the host adds the
+// slots).  Block sums need blockDim.x a multiple of 64.
 __global__ __launch_bounds__(256) void k_near_key(const double* __restrict__ x, const double* __restrict__ q, int n,
                                                   NearGeom g, int2* __restrict__ key, int* __restrict__ count,
                                                   double* __restrict__ qsum, int* __restrict__ status) {
@@ -76,10 +77,11 @@ __global__ __launch_bounds__(256) void k_near_key(const double* __restrict__ x, 
         key[i] = make_int2(k, atomicAdd(&count[k], 1));  // cell and rank within it
     }
     if (flags) atomicOr(status, flags);
+    double* slot = qsum + 2 * (blockIdx.x % kQsumSlots);  // spread over slots: few adds per address
     double t = block_sum_double(s, red);
-    if (threadIdx.x == 0) atomicAdd(&qsum[0], t);
+    if (threadIdx.x == 0) atomicAdd(&slot[0], t);
     t = block_sum_double(sa, red);
-    if (threadIdx.x == 0) atomicAdd(&qsum[1], t);
+    if (threadIdx.x == 0) atomicAdd(&slot[1], t);
 }
 
 // Scatter of the counting sort, writing each particle's packed record at its place in
@@ -667,7 +669,7 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
         timer_begin(p, t);
         const int blocks = std::min((n + 255) / 256, 8192);
         hipError_t e = launch_fill_int(ws.cell_start, 0, (int64_t)ncells + 1, p.stream);
-        if (e == hipSuccess) e = launch_fill_bytes_zero(ws.qsum, 2 * sizeof(double), p.stream);
+        if (e == hipSuccess) e = launch_fill_bytes_zero(ws.qsum, 2 * kQsumSlots * sizeof(double), p.stream);
         if (e == hipSuccess) e = launch_fill_int(ws.status, 0, 1, p.stream);
         if (e != hipSuccess) return e;
         k_near_key<<<blocks, 256, 0, p.stream>>>(x, q, n, g, (int2*)ws.key, ws.cell_start, ws.qsum, ws.status);
