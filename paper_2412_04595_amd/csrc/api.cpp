@@ -123,9 +123,9 @@ sog_status build_plan(Plan& p) {
     A.get(ws.near_units, ((size_t)near_unit_slots(r) * 16 + 127) / 128 * 128 + 8 * 128);  // units, then 8 work counters
     if (r.has_mid) {
         const int ntiles = r.ntile[0] * r.ntile[1] * r.ntile[2];
-        maxbins = std::max<int64_t>(maxbins, ntiles);
+        maxbins = std::max<int64_t>(maxbins, (int64_t)ntiles * kMidSub);
         const int Kz = r.Izs / 2 + 1;
-        A.get(ws.tile_start, (ntiles + 1) * 4);
+        A.get(ws.tile_start, ((int64_t)ntiles * kMidSub + 1) * 4);
         A.get(ws.spread_nodes, 2 * 4 * 64);
         A.get(ws.mid_g, n * 16);
         A.get(ws.mid_u, n * 4 * rs);

@@ -15,6 +15,8 @@ namespace sog {
 constexpr int kMaxStages = 24;    // radix stages of one 1D FFT
 constexpr int kMaxNearDeg = 63;   // Chebyshev degree of the near-field polynomials
 constexpr int kMaxMid = 96;       // max number of mid-range Gaussians (m + 1)
+constexpr int kMidSub = 8;        // rank counters per mid-range tile in the counting sort (fewer atomics per address)
+static_assert((kMidSub & (kMidSub - 1)) == 0, "kMidSub is a power of two");
 constexpr int kQsumSlots = 64;    // slots of the charge sums (spreads the float64 atomics of the key pass)
 constexpr int kMaxPw = 15;        // widest mid-range window the gridding and gathering kernels take
 constexpr int kSpreadStage = 32;  // particles whose window weights the gridding kernel stages at a time
@@ -186,7 +188,7 @@ struct Workspace {
     void* near_pos = nullptr;   // n x real4 (x, y, z relative to the cell corner; q)
     void* near_units = nullptr; // near_unit_slots() int4 work units, then 8 work counters
     // mid range
-    int* tile_start = nullptr;  // ntiles + 1 (owners)
+    int* tile_start = nullptr;  // ntiles * kMidSub + 1: tile t owns [tile_start[t kMidSub], tile_start[(t+1) kMidSub])
     signed char* spread_nodes = nullptr;  // 2 x 256: node_oy, node_oz of the plan
     int* mid_g = nullptr;       // n x int4 (grid point of each sorted particle, original index)
     void* mid_u = nullptr;      // n x real4 (offset from the grid point in units of h, q)

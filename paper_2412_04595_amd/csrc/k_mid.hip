@@ -57,7 +57,10 @@ __global__ void k_mid_key(const double* __restrict__ x, int n, MidGeom g, int2* 
         double u[3];
         grid_point(g, x[3 * i], x[3 * i + 1], x[3 * i + 2], a, u);
         const int k = ((a[0] / g.B[0]) * g.nt[1] + a[1] / g.B[1]) * g.nt[2] + a[2] / g.B[2];
-        key[i] = make_int2(k, atomicAdd(&count[k], 1));
+        // kMidSub counters per tile, taken in turn by consecutive particles: the returning
+        // atomics cost less with fewer of them on one address
+        const int kb = k * kMidSub + (i & (kMidSub - 1));
+        key[i] = make_int2(kb, atomicAdd(&count[kb], 1));
     }
 }
 
@@ -110,7 +113,7 @@ template <typename real>
 struct SpreadArgs {
     const int4* gp;
     const vec4<real>* up;
-    const int* tstart;  // owned particles of each tile (the gather's lists)
+    const int* tstart;  // tile t owns particles [tstart[t kMidSub], tstart[(t + 1) kMidSub]) (the gather's lists)
     const signed char* nodes;  // (y, z) window node of each lane per pass: 256 oy, then 256 oz
     real* grid;
     int I[3];
@@ -149,7 +152,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
     const int t = xcd_logical_block(a.ntiles);
     if (t < 0) return;
     const int tz = t % a.nt[2], ty = (t / a.nt[2]) % a.nt[1], tx = t / (a.nt[2] * a.nt[1]);
-    const int beg = a.tstart[t], end = a.tstart[t + 1];
+    const int beg = a.tstart[t * kMidSub], end = a.tstart[(t + 1) * kMidSub];
     if (beg == end) return;
     const int x0 = tx * a.B[0], y0 = ty * a.B[1], z0 = tz * a.B[2];
     const int HX = a.B[0] + PW - 1, HY = a.B[1] + PW - 1, HZ = a.B[2] + PW - 1;
@@ -336,7 +339,7 @@ __global__ __launch_bounds__(kGatherChunk) void k_gather(GatherArgs<real> a) {
     real* halo = reinterpret_cast<real*>(smem_raw);
     const int t = xcd_logical_block(a.ntiles);
     if (t < 0) return;
-    const int beg = a.tstart[t], end = a.tstart[t + 1];
+    const int beg = a.tstart[t * kMidSub], end = a.tstart[(t + 1) * kMidSub];
     if (beg == end) return;
     constexpr int HW = (PW - 1) / 2;
     const int tz = t % a.nt[2], ty = (t / a.nt[2]) % a.nt[1], tx = t / (a.nt[2] * a.nt[1]);
@@ -539,10 +542,11 @@ hipError_t run_mid_prepare(Plan& p, const double* x, const double* q) {
     MidGeom g = mid_geom(r);
     const int ntiles = r.ntile[0] * r.ntile[1] * r.ntile[2];
     const int blocks = std::min((n + 255) / 256, 8192);
-    hipError_t e = launch_fill_int(ws.tile_start, 0, (int64_t)ntiles + 1, p.stream);
+    const int nbins = ntiles * kMidSub;
+    hipError_t e = launch_fill_int(ws.tile_start, 0, (int64_t)nbins + 1, p.stream);
     if (e != hipSuccess) return e;
     k_mid_key<<<blocks, 256, 0, p.stream>>>(x, n, g, (int2*)ws.key2, ws.tile_start);
-    if ((e = launch_exclusive_scan(p, ws.tile_start, ntiles + 1, ws.scan_tmp2)) != hipSuccess) return e;
+    if ((e = launch_exclusive_scan(p, ws.tile_start, nbins + 1, ws.scan_tmp2)) != hipSuccess) return e;
     k_mid_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, (const int2*)ws.key2, ws.tile_start,
                                                     (int4*)ws.mid_g, (vec4<real>*)ws.mid_u);
     return hipGetLastError();
