@@ -20,6 +20,7 @@ period L_z*, Sec. 3.4):
   3. multiply by Ghat_mid(k) / What(k)^2   (k = 2 pi fftfreq)
   4. u = ifftn(.)
   5. Phi_mid_i = h_x h_y h_z sum_g W(r_i - g) u(g), grad with dW.
+  Optionally the ES window (window_1d_es) with its transform by quadrature.
 
 Long range, direct form (App. B, Alg. al::long_nonfft), with Chebyshev
 interpolation in the target z and anterpolation in the source z (the
@@ -61,7 +62,8 @@ from .sog import SOG
 def make_params(b, r0, omega, rc, M, m, mid=None, long=None):
     """Explicit parameter set.
 
-    mid: dict(I=(Ix,Iy,Iz), Izs=I_z*, Pw=(px,py,pz), S=shape) or None (m < 0).
+    mid: dict(I=(Ix,Iy,Iz), Izs=I_z*, Pw=(px,py,pz), S=shape) or None (m < 0); with
+         window='es' and beta=beta the ES window replaces the Gaussian (S unused).
     long: dict(form='direct', P=P, nk=(nkx,nky)) or
           dict(form='fft', P=P, I=(Ix,Iy), Pw=(px,py), S=shape) or None (m == M)."""
     return dict(sog=dict(b=b, r0=r0, omega=omega, rc=rc, M=M), m=m, mid=mid, long=long)
@@ -103,6 +105,51 @@ def window_hat(k, h, Pw, S):
     return math.sqrt(math.pi / S) * H * np.exp(-(k * k) * H * H / (4.0 * S))
 
 
+# The "exponential of semicircle" window, one of the compactly supported windows of the
+# Kaiser-Bessel family that Sec. 5's experiments use in place of the Gaussian (the paper
+# prints no formula for them; this is the reading of the library's window option):
+#   W(x) = exp(beta (sqrt(1 - (x/a)^2) - 1)) for |x| < a,  0 otherwise,  a = P_w h / 2,
+# so the P_w nodes nearest a particle are exactly the nodes inside the support.  Its
+# transform has no closed form and is computed by quadrature.
+
+def window_1d_es(xc, origin, h, n, Pw, beta, periodic):
+    """ES-window weights of every particle on its Pw nearest grid points; same returns as
+    window_1d (d/dx_particle of W(x_p - x_g) in dW)."""
+    a = 0.5 * Pw * h
+    a0 = np.round((xc - origin) / h).astype(np.int64)
+    off = np.arange(Pw) - (Pw - 1) // 2
+    idx = a0[:, None] + off[None, :]
+    dx = xc[:, None] - (origin + idx * h)  # x_p - x_g
+    t2 = (dx / a) ** 2
+    inside = t2 < 1.0
+    root = np.sqrt(np.where(inside, 1.0 - t2, 1.0))
+    W = np.where(inside, np.exp(beta * (root - 1.0)), 0.0)
+    dW = np.where(inside, -beta * dx / (a * a * root) * W, 0.0)
+    if periodic:
+        idx = np.mod(idx, n)
+    else:
+        if np.any(idx < 0) or np.any(idx >= n):
+            raise ValueError("window support leaves the padded z grid")
+    return idx, W, dW
+
+
+def window_hat_es(k, h, Pw, beta):
+    """Fourier transform of the ES window, What(k) = int W(x) exp(-i k x) dx.  With
+    x = a sin(theta) the integrand exp(beta (cos theta - 1)) cos(k a sin theta) a cos theta
+    is smooth on [0, pi/2]; Gauss-Legendre with enough nodes for the oscillation."""
+    a = 0.5 * Pw * h
+    k = np.asarray(k, dtype=np.float64)
+    kmax = float(np.max(np.abs(k))) if k.size else 0.0
+    nq = 64 + int(math.ceil(2.0 * kmax * a))
+    t, w = np.polynomial.legendre.leggauss(nq)
+    th = 0.25 * math.pi * (t + 1.0)
+    wt = 0.25 * math.pi * w
+    f = np.exp(beta * (np.cos(th) - 1.0)) * a * np.cos(th) * wt
+    kf = k.reshape(-1)
+    out = 2.0 * (np.cos(np.outer(kf * a, np.sin(th))) @ f)
+    return out.reshape(k.shape)
+
+
 # ----------------------------------------------------------------------------- mid range
 
 def mid_range(xc, q, box, sog: SOG, m, mid):
@@ -111,12 +158,14 @@ def mid_range(xc, q, box, sog: SOG, m, mid):
     Ix, Iy, Iz = mid["I"]
     Izs = mid["Izs"]
     px, py, pz = mid["Pw"]
-    S = mid["S"]
+    es = mid.get("window", "gaussian") == "es"
+    S = mid["beta"] if es else mid["S"]
+    wfun, hfun = (window_1d_es, window_hat_es) if es else (window_1d, window_hat)
     hx, hy, hz = Lx / Ix, Ly / Iy, Lz / Iz
     Lzs = Izs * hz
-    ix, Wx, dWx = window_1d(xc[:, 0], -Lx / 2, hx, Ix, px, S, True)
-    iy, Wy, dWy = window_1d(xc[:, 1], -Ly / 2, hy, Iy, py, S, True)
-    iz, Wz, dWz = window_1d(xc[:, 2], -Lzs / 2, hz, Izs, pz, S, False)
+    ix, Wx, dWx = wfun(xc[:, 0], -Lx / 2, hx, Ix, px, S, True)
+    iy, Wy, dWy = wfun(xc[:, 1], -Ly / 2, hy, Iy, py, S, True)
+    iz, Wz, dWz = wfun(xc[:, 2], -Lzs / 2, hz, Izs, pz, S, False)
     N = xc.shape[0]
     # 1. gridding
     grid = np.zeros(Ix * Iy * Izs)
@@ -135,8 +184,8 @@ def mid_range(xc, q, box, sog: SOG, m, mid):
     G = np.zeros_like(k2)
     for ell in range(m + 1):
         G += math.pi ** 1.5 * sog.w[ell] * sog.s[ell] ** 3 * np.exp(-sog.s[ell] ** 2 * k2 / 4.0)
-    What2 = (window_hat(kx, hx, px, S)[:, None, None] ** 2 * window_hat(ky, hy, py, S)[None, :, None] ** 2
-             * window_hat(kz, hz, pz, S)[None, None, :] ** 2)
+    What2 = (hfun(kx, hx, px, S)[:, None, None] ** 2 * hfun(ky, hy, py, S)[None, :, None] ** 2
+             * hfun(kz, hz, pz, S)[None, None, :] ** 2)
     u = np.real(np.fft.ifftn(G / What2 * np.fft.fftn(grid))).ravel()
     # 5. gathering
     phi = np.zeros(N)

@@ -399,3 +399,57 @@ def test_all_long_regime_matches_mid_plus_long():
     o = fast.solve(x, q, box, params)
     T = np.arange(0, 300, 11)
     assert np.max(np.abs(o["phi"][T] - ref["phi"])) < 1e-8 * np.max(np.abs(ref["phi"]))
+
+
+# ---------------------------------------------------------------- ES window (oracle option)
+
+def test_es_window_transform_pins():
+    """The quadrature transform of the ES window: beta = 0 is the box window, whose
+    transform is 2 sin(k a)/k; for beta = 2.3 P_w it agrees with a fine midpoint sum of
+    the definition (an independent rule)."""
+    h, Pw = 0.4, 7
+    a = 0.5 * Pw * h
+    k = np.array([0.1, 1.0, 3.0, 7.7, 15.0])
+    assert np.max(np.abs(fast.window_hat_es(k, h, Pw, 0.0) - 2 * np.sin(k * a) / k)) < 1e-12
+    beta = 2.3 * Pw
+    M = 400_000
+    xm = (np.arange(M) + 0.5) / M * 2 * a - a
+    W = np.exp(beta * (np.sqrt(1 - (xm / a) ** 2) - 1))
+    for kk in (0.0, 2.0, 7.8):
+        bf = np.sum(W * np.cos(kk * xm)) * (2 * a / M)
+        assert abs(fast.window_hat_es(np.array([kk]), h, Pw, beta)[0] - bf) < 1e-9 * abs(bf) + 1e-13
+
+
+def test_es_window_weights_and_derivative():
+    """Weights: the P_w nodes nearest x are exactly the nodes inside the support, W is 1 at
+    the centre and exp(-beta) at the edge; dW agrees with central differences of W."""
+    h, Pw, beta = 0.5, 7, 16.0
+    xs = np.array([0.013, 1.2345, -0.74, 3.0 - 1e-3])
+    idx, W, dW = fast.window_1d_es(xs, 0.0, h, 100, Pw, beta, True)
+    dx = xs[:, None] - idx * h
+    dx = dx - 100 * h * np.round(dx / (100 * h))
+    assert np.all(np.abs(dx) < 0.5 * Pw * h)
+    i0, W0, _ = fast.window_1d_es(np.array([0.0]), 0.0, h, 100, Pw, beta, True)
+    assert abs(W0[0, (Pw - 1) // 2] - 1.0) < 1e-15
+    e = 1e-6
+    _, Wp, _ = fast.window_1d_es(xs + e, 0.0, h, 100, Pw, beta, True)
+    _, Wm, _ = fast.window_1d_es(xs - e, 0.0, h, 100, Pw, beta, True)
+    assert np.max(np.abs((Wp - Wm) / (2 * e) - dW)) < 1e-6 * np.max(np.abs(dW))
+
+
+def test_fast_mid_es_window_converges(cube_case):
+    """With the ES window the mid range converges to SOG-direct as the support grows,
+    faster than the Gaussian window (at I = 48: P_w = 9 beats the Gaussian's P_w = 13)."""
+    x, q, box, sog, m, T, ref = cube_case
+    xc = fast.centered(x, box)
+    scale = np.max(np.abs(ref["phi"]))
+    gscale = np.max(np.abs(ref["grad"]))
+    prev = 1.0
+    for Pw in (5, 7, 9):
+        mid = dict(I=(48, 48, 48), Izs=144, Pw=(Pw, Pw, Pw), window="es", beta=2.3 * Pw)
+        p, g = fast.mid_range(xc, q, box, sog, m, mid)
+        e = np.max(np.abs(p[T] - ref["phi_mid"])) / scale
+        assert e < 0.05 * prev
+        prev = e
+    assert prev < 2e-8
+    assert np.max(np.abs(g[T] - ref["grad_mid"])) < 2e-7 * gscale
