@@ -72,6 +72,14 @@ typedef enum {
 
 typedef enum { SOG_LONG_AUTO = 0, SOG_LONG_DIRECT = 1, SOG_LONG_FFT = 2 } sog_long_form;
 
+/* Mid-range window.  GAUSSIAN: the truncated Gaussian of eq. GS, shape mid_S.  ES: the
+ * "exponential of semicircle" W(x) = exp(beta (sqrt(1 - (x/a)^2) - 1)), |x| < a = P_w h/2,
+ * a compactly supported window of the Kaiser-Bessel family the paper's experiments use
+ * (Sec. 5; the paper prints no formula for it), shape mid_beta; its transform is computed
+ * by quadrature.  AUTO: the cheaper of the two that meets the tolerance (the Gaussian when
+ * mid_S is given). */
+typedef enum { SOG_WINDOW_AUTO = 0, SOG_WINDOW_GAUSSIAN = 1, SOG_WINDOW_ES = 2 } sog_window;
+
 /*
  * Discretisation parameters.  In options, a zero field means "choose it from tol";
  * sog_plan_info() returns the fully resolved set.  Symbols follow the paper.
@@ -99,6 +107,9 @@ typedef struct {
     int32_t long_I[2];
     int32_t long_Pw[2];
     double long_S;
+    /* mid-range window (sog_window) and the ES shape beta (0: chosen)                 */
+    int32_t mid_window;
+    double mid_beta;
 } sog_params;
 
 typedef struct {

@@ -25,6 +25,7 @@ STATUS = {
 }
 SOG_PREC_FP64, SOG_PREC_FP32_BULK = 0, 1
 SOG_LONG_AUTO, SOG_LONG_DIRECT, SOG_LONG_FFT = 0, 1, 2
+SOG_WINDOW_AUTO, SOG_WINDOW_GAUSSIAN, SOG_WINDOW_ES = 0, 1, 2
 
 EXPORTS = (
     "sog_options_default",
@@ -52,6 +53,7 @@ class sog_params(C.Structure):
         ("mid_I", C.c_int32 * 3), ("mid_Izs", C.c_int32), ("mid_Pw", C.c_int32 * 3), ("mid_S", C.c_double),
         ("long_form", C.c_int32), ("long_P", C.c_int32), ("long_nk", C.c_int32 * 2),
         ("long_I", C.c_int32 * 2), ("long_Pw", C.c_int32 * 2), ("long_S", C.c_double),
+        ("mid_window", C.c_int32), ("mid_beta", C.c_double),
     ]
 
     def as_dict(self):

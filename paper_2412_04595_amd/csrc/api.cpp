@@ -201,21 +201,35 @@ sog_status build_plan(Plan& p) {
         const int nl = r.m + 1;
         std::vector<double> ax((size_t)nl * r.I[0]), ay((size_t)nl * r.I[1]), az((size_t)nl * Kz), cl(nl);
         const double Ng = (double)r.I[0] * r.I[1] * r.Izs;
-        auto fill = [&](std::vector<double>& t, int cnt, int N, double Ld, double H) {
+        auto fill = [&](std::vector<double>& t, int cnt, int N, double Ld, double H, double hd) {
+            // 1 / What(k)^2 of the ES window: h What_g(k h), What_g by quadrature
+            std::vector<double> inv_es2;
+            if (r.window == SOG_WINDOW_ES) {
+                inv_es2.resize(cnt);
+                for (int i = 0; i < cnt; ++i) {
+                    const int f = (cnt == N && i >= (N + 1) / 2) ? i - N : i;
+                    const double w = hd * es_hat_grid(2.0 * kPi * f / Ld * hd, r.Pw, r.beta);
+                    inv_es2[i] = 1.0 / (w * w);
+                }
+            }
             for (int l = 0; l < nl; ++l)
                 for (int i = 0; i < cnt; ++i) {
                     // FFT frequency index: 0, 1, .., -1 over a full line (x, y); 0 .. N/2
                     // over the half spectrum (z)
                     const int f = (cnt == N && i >= (N + 1) / 2) ? i - N : i;
                     double k = 2.0 * kPi * f / Ld;
+                    if (r.window == SOG_WINDOW_ES) {
+                        t[(size_t)l * cnt + i] = inv_es2[i] * std::exp(-r.s[l] * r.s[l] * k * k / 4.0);
+                        continue;
+                    }
                     double pref;
                     double ex = -r.s[l] * r.s[l] * k * k / 4.0 + inv_what2_log(k, H, r.S, &pref);
                     t[(size_t)l * cnt + i] = pref * std::exp(std::min(ex, 80.0));
                 }
         };
-        fill(ax, r.I[0], r.I[0], r.L[0], r.H[0]);
-        fill(ay, r.I[1], r.I[1], r.L[1], r.H[1]);
-        fill(az, Kz, r.Izs, r.Lzs, r.H[2]);
+        fill(ax, r.I[0], r.I[0], r.L[0], r.H[0], r.h[0]);
+        fill(ay, r.I[1], r.I[1], r.L[1], r.H[1], r.h[1]);
+        fill(az, Kz, r.Izs, r.Lzs, r.H[2], r.h[2]);
         for (int l = 0; l < nl; ++l) cl[l] = std::pow(kPi, 1.5) * r.w[l] * r.s[l] * r.s[l] * r.s[l] / Ng;
         if (e == hipSuccess) e = upload(ws.mult_ax, ax, f64);
         if (e == hipSuccess) e = upload(ws.mult_ay, ay, f64);
@@ -623,7 +637,11 @@ static void fill_params(const Resolved& r, sog_params* o) {
             o->mid_Pw[d] = r.Pw;
         }
         o->mid_Izs = r.Izs;
-        o->mid_S = r.S;
+        o->mid_window = r.window;
+        if (r.window == SOG_WINDOW_ES)
+            o->mid_beta = r.beta;
+        else
+            o->mid_S = r.S;
     }
     if (r.has_long) {
         o->long_form = r.form;

@@ -58,6 +58,25 @@ struct FFTFactors {
 // 4608 complex in the float32 form, 2304 in float64.
 constexpr int fft_max_line(int prec) { return prec == SOG_PREC_FP64 ? 2304 : 4608; }
 
+// LDS of the mid-range x pass (forward FFT along x, multiplier, inverse) with W lines per
+// block: the lines (complex), the x multipliers of the nl mid-range Gaussians and the
+// staging of each thread's line loads (k_fft.hip).
+inline size_t fft_x_lds_bytes(int prec, int Ix, int nl, int W) {
+    const size_t rs = prec == SOG_PREC_FP64 ? 8 : 4;
+    const size_t stage = (size_t)(fft_max_line(prec) / 256) * (256 / W);
+    return (size_t)Ix * (W + 1) * 2 * rs + ((size_t)nl * (W + Ix) + stage - Ix) * rs;
+}
+
+// The same without the x multipliers (read from global memory instead)
+inline size_t fft_x_lds_min_bytes(int prec, int Ix, int nl, int W) {
+    const size_t rs = prec == SOG_PREC_FP64 ? 8 : 4;
+    return (size_t)Ix * (W + 1) * 2 * rs + (size_t)nl * W * rs;
+}
+
+// Transform of the ES window in grid units, What_g(kappa) = int psi(d) cos(kappa d) dd
+// over |d| < P_w/2 (planner.cpp); the physical transform is h What_g(k h).
+double es_hat_grid(double kappa, int Pw, double beta);
+
 struct Resolved {
     double L[3] = {0, 0, 0};
     int64_t n = 0;
@@ -83,6 +102,8 @@ struct Resolved {
     int Izs = 0;           // padded z points I_z*
     int Pw = 0;            // window points (same in every direction)
     double S = 0;          // Gaussian window shape
+    int window = SOG_WINDOW_GAUSSIAN;  // SOG_WINDOW_GAUSSIAN or SOG_WINDOW_ES
+    double beta = 0;       // ES window shape
     double h[3] = {0, 0, 0};
     double H[3] = {0, 0, 0};
     double Lzs = 0;

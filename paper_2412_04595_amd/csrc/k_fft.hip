@@ -445,9 +445,9 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_y(cpx<T>* __restrict__ cg, 
 }
 
 // 3. forward FFT along x, the SOG multiplier, inverse FFT along x.  The multiplier is
-// sum_l c_l ax_l(k_x) ay_l(k_y) az_l(k_z): the block's (k_y, k_z) factors and ax are
-// staged in LDS.
-template <typename T>
+// sum_l c_l ax_l(k_x) ay_l(k_y) az_l(k_z): the block's (k_y, k_z) factors are staged in
+// LDS, and ax too when it fits (AXLDS); otherwise ax is read from global memory (L2).
+template <typename T, bool AXLDS>
 __global__ __launch_bounds__(kFFTThreads) void k_fft_x_scale(cpx<T>* __restrict__ cg, int Ix, int Iy, int Kz, int Kzs,
                                                              int W,
                                                              FFTDev f, const cpx<T>* __restrict__ tw, int nl,
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_scale(cpx<T>* __restrict_
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* twl = A + Ix * W;
     T* cyz = reinterpret_cast<T*>(twl + Ix);  // nl x W
-    T* axl = cyz + nl * W;                    // nl x Ix, then kStageK (256 / W) - Ix zeros
+    T* axl = cyz + nl * W;                    // AXLDS: nl x Ix, then kStageK (256 / W) - Ix zeros
     const int nkb = (Kz + W - 1) / W;
     const int iy = blockIdx.x / nkb, kz0 = (blockIdx.x % nkb) * W;
     if (iy >= Iy) return;
@@ -473,9 +473,11 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_scale(cpx<T>* __restrict_
                 [&](int e) { return e; },
                 [&] {
                     copy_in<4>(twl, tw, Ix);
-                    copy_in<16>(axl, ax, nl * Ix);
-                    for (int i = threadIdx.x; i < kStageK<T> * (kFFTThreads >> lw) - Ix; i += kFFTThreads)
-                        axl[nl * Ix + i] = 0;
+                    if constexpr (AXLDS) {
+                        copy_in<16>(axl, ax, nl * Ix);
+                        for (int i = threadIdx.x; i < kStageK<T> * (kFFTThreads >> lw) - Ix; i += kFFTThreads)
+                            axl[nl * Ix + i] = 0;
+                    }
                     for (int idx = threadIdx.x; idx < nl * W; idx += kFFTThreads) {
                         const int w = idx & (W - 1), l = idx >> lw;
                         const int kz = min(kz0 + w, Kz - 1);
@@ -495,9 +497,18 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_scale(cpx<T>* __restrict_
         for (int k = 0; k < K; ++k) mlt[k] = 0;
         for (int l = 0; l < nl; ++l) {
             const T c = cyz[l * W + w];
-            const T* ar = axl + l * Ix + ix0;
+            if constexpr (AXLDS) {
+                const T* ar = axl + l * Ix + ix0;
 #pragma unroll
-            for (int k = 0; k < K; ++k) mlt[k] += ar[k * dix] * c;
+                for (int k = 0; k < K; ++k) mlt[k] += ar[k * dix] * c;
+            } else {
+                const T* ar = ax + (size_t)l * Ix;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int ix = ix0 + k * dix;
+                    mlt[k] += (ix < Ix ? ar[ix] : (T)0) * c;
+                }
+            }
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -595,19 +606,31 @@ hipError_t run_fft_mid(Plan& p) {
     // 3. x forward, scale, x inverse
     {
         int W = lines_per_block<T>(Ix);
-        auto lds_of = [&](int w) {
-            return (size_t)Ix * (w + 1) * ce + ((size_t)nl * (w + Ix) + (size_t)kStageK<T> * (kFFTThreads / w) - Ix) * sizeof(T);
-        };
+        static_assert(kFFTThreads == 256 && kFFTCap<T> == fft_max_line(sizeof(T) == 8 ? SOG_PREC_FP64 : SOG_PREC_FP32_BULK),
+                      "fft_x_lds_bytes models this launch");
+        const int prec = sizeof(T) == 8 ? SOG_PREC_FP64 : SOG_PREC_FP32_BULK;
+        auto lds_of = [&](int w) { return fft_x_lds_bytes(prec, Ix, nl, w); };
         while (W > 1 && lds_of(W) > budget) W >>= 1;
-        const size_t lds = lds_of(W);
+        // the x multipliers stay in global memory when even one line per block leaves no
+        // room for them in LDS
+        const bool axlds = lds_of(W) <= budget;
+        if (!axlds) {
+            W = lines_per_block<T>(Ix);
+            while (W > 1 && fft_x_lds_min_bytes(prec, Ix, nl, W) > budget) W >>= 1;
+        }
+        const size_t lds = axlds ? lds_of(W) : fft_x_lds_min_bytes(prec, Ix, nl, W);
         if (lds > budget) return hipErrorInvalidConfiguration;
         int nb = Iy * ((Kz + W - 1) / W);
         int t = timer_id(p, "fft_x_scale");
         timer_begin(p, t);
-        k_fft_x_scale<T><<<nb, kFFTThreads, lds, p.stream>>>((cpx<T>*)ws.cgrid, Ix, Iy, Kz, Kzs, W, to_dev(p.fx),
-                                                             (const cpx<T>*)ws.tw_x, nl, (const T*)ws.mult_ax,
-                                                             (const T*)ws.mult_ay, (const T*)ws.mult_az,
-                                                             (const T*)ws.mult_c);
+        if (axlds)
+            k_fft_x_scale<T, true><<<nb, kFFTThreads, lds, p.stream>>>(
+                (cpx<T>*)ws.cgrid, Ix, Iy, Kz, Kzs, W, to_dev(p.fx), (const cpx<T>*)ws.tw_x, nl, (const T*)ws.mult_ax,
+                (const T*)ws.mult_ay, (const T*)ws.mult_az, (const T*)ws.mult_c);
+        else
+            k_fft_x_scale<T, false><<<nb, kFFTThreads, lds, p.stream>>>(
+                (cpx<T>*)ws.cgrid, Ix, Iy, Kz, Kzs, W, to_dev(p.fx), (const cpx<T>*)ws.tw_x, nl, (const T*)ws.mult_ax,
+                (const T*)ws.mult_ay, (const T*)ws.mult_az, (const T*)ws.mult_c);
         timer_end(p, t);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

@@ -89,12 +89,47 @@ __global__ void k_mid_pack(const double* __restrict__ x, const double* __restric
     }
 }
 
+// The window on the P_w nodes nearest a particle, at offset d = node - particle (units of
+// h): the truncated Gaussian exp(-S d^2 / HW^2), |d| <= HW (eq. GS), or the ES window
+// exp(beta (sqrt(1 - (d/a)^2) - 1)), |d| < a = P_w / 2 (the planner's option; its
+// transform enters the multiplier tables).
+template <typename real>
+struct WinShape {
+    real S, inv_hw2;  // Gaussian
+    real beta, inv_a; // ES
+    int es;
+};
+
 template <typename real, int PW>
-__device__ __forceinline__ real win(int o, real u, real S, real inv_hw2) {
+__device__ __forceinline__ real win(int o, real u, const WinShape<real>& s) {
     constexpr int HW = (PW - 1) / 2;
     const real d = (real)(o - HW) - u;
-    const real r2 = d * d * inv_hw2;
-    return (r2 <= (real)1) ? dexp(-S * r2) : (real)0;
+    if (s.es) {
+        const real t = fabs(d) * s.inv_a;
+        const real r1 = ((real)1 - t) * ((real)1 + t);
+        return (r1 > (real)0) ? dexp(s.beta * (sqrt(r1) - (real)1)) : (real)0;
+    }
+    const real r2 = d * d * s.inv_hw2;
+    return (r2 <= (real)1) ? dexp(-s.S * r2) : (real)0;
+}
+
+// the weight and its derivative in the particle coordinate, dcoef d W (Gaussian, dcoef =
+// 2 S / (HW^2 h)) or dcoef d W / sqrt(1 - (d/a)^2) (ES, dcoef = beta / (a^2 h))
+template <typename real, int PW>
+__device__ __forceinline__ void win_d(int o, real u, const WinShape<real>& s, real dcoef, real& w, real& dw) {
+    constexpr int HW = (PW - 1) / 2;
+    const real d = (real)(o - HW) - u;
+    if (s.es) {
+        const real t = fabs(d) * s.inv_a;
+        const real r1 = ((real)1 - t) * ((real)1 + t);
+        const real sq = sqrt(r1 > (real)0 ? r1 : (real)1);
+        w = (r1 > (real)0) ? dexp(s.beta * (sq - (real)1)) : (real)0;
+        dw = dcoef * d * w / sq;
+        return;
+    }
+    const real r2 = d * d * s.inv_hw2;
+    w = (r2 <= (real)1) ? dexp(-s.S * r2) : (real)0;
+    dw = dcoef * d * w;
 }
 
 constexpr int kSpreadThreads = 256;  // 4 waves, one per group of x planes
@@ -120,8 +155,7 @@ struct SpreadArgs {
     int B[3];
     int nt[3];
     int ntiles;
-    real S;
-    real inv_hw2;
+    WinShape<real> ws;
 };
 
 // Owner-tile gridding: the workgroup of a tile spreads the particles whose nearest node
@@ -214,14 +248,14 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
             if (idx < cnt * NW) {
                 const int i = idx / NW, r = idx - i * NW;
                 const vec4<real> u = sup[i];
-                wyzs[idx] = (r < 2 * PW) ? win<real, PW>(r < PW ? r : r - PW, r < PW ? u.y : u.z, a.S, a.inv_hw2)
+                wyzs[idx] = (r < 2 * PW) ? win<real, PW>(r < PW ? r : r - PW, r < PW ? u.y : u.z, a.ws)
                                          : (real)0;
             } else {
                 const int jdx = idx - cnt * NW;
                 const int i = jdx >> 4, g = (jdx >> 2) & 3, pl = jdx & 3;
                 const vec4<real> u = sup[i];
                 const int ox = ((g - slx[i]) & 3) + 4 * pl;
-                wxs[jdx] = (ox < PW) ? u.w * win<real, PW>(ox, u.x, a.S, a.inv_hw2) : (real)0;
+                wxs[jdx] = (ox < PW) ? u.w * win<real, PW>(ox, u.x, a.ws) : (real)0;
             }
         }
         __syncthreads();
@@ -325,9 +359,8 @@ struct GatherArgs {
     int B[3];
     int nt[3];
     int ntiles;
-    real S;
-    real inv_hw2;
-    real dcoef[3];  // 2 S / (HW^2 h_d): d/dx_particle of W is dcoef * (node - particle in h) * W
+    WinShape<real> ws;
+    real dcoef[3];  // the derivative factors of win_d per direction
     real vol;       // h_x h_y h_z
 };
 
@@ -409,16 +442,14 @@ __global__ __launch_bounds__(kGatherChunk) void k_gather(GatherArgs<real> a) {
         real wy[PW], dwy[PW], wz[PW], dwz[PW];
 #pragma unroll
         for (int o = 0; o < PW; ++o) {
-            wy[o] = win<real, PW>(o, u.y, a.S, a.inv_hw2);
-            dwy[o] = a.dcoef[1] * ((real)(o - HW) - u.y) * wy[o];
-            wz[o] = win<real, PW>(o, u.z, a.S, a.inv_hw2);
-            dwz[o] = a.dcoef[2] * ((real)(o - HW) - u.z) * wz[o];
+            win_d<real, PW>(o, u.y, a.ws, a.dcoef[1], wy[o], dwy[o]);
+            win_d<real, PW>(o, u.z, a.ws, a.dcoef[2], wz[o], dwz[o]);
         }
         const int lx0 = g.x - x0, ly0 = g.y - y0, lz0 = g.z - z0;
         real phi = 0, gx = 0, gy = 0, gz = 0;
         for (int ox = 0; ox < PW; ++ox) {
-            const real wx = win<real, PW>(ox, u.x, a.S, a.inv_hw2);
-            const real dwx = a.dcoef[0] * ((real)(ox - HW) - u.x) * wx;
+            real wx, dwx;
+            win_d<real, PW>(ox, u.x, a.ws, a.dcoef[0], wx, dwx);
             real s0 = 0, s1 = 0, s2 = 0;  // sum_y wy * (sum_z wz u), sum_y dwy * (...), sum_y wy * (sum_z dwz u)
 #pragma unroll
             for (int oy = 0; oy < PW; ++oy) {
@@ -452,8 +483,13 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
     Workspace& ws = p.ws;
     const int ntiles = r.ntile[0] * r.ntile[1] * r.ntile[2];
     const int HW = (PW - 1) / 2;
-    const real S = (real)r.S;
-    const real inv_hw2 = (real)(1.0 / ((double)HW * HW));
+    const bool es = r.window == SOG_WINDOW_ES;
+    WinShape<real> shape;
+    shape.S = (real)r.S;
+    shape.inv_hw2 = (real)(HW > 0 ? 1.0 / ((double)HW * HW) : 0.0);
+    shape.beta = (real)r.beta;
+    shape.inv_a = (real)(2.0 / PW);
+    shape.es = es ? 1 : 0;
     if (spread) {
         SpreadArgs<real> a;
         a.gp = (const int4*)ws.mid_g;
@@ -464,8 +500,7 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         a.I[0] = r.I[0]; a.I[1] = r.I[1]; a.I[2] = r.Izs;
         for (int d = 0; d < 3; ++d) { a.B[d] = r.B[d]; a.nt[d] = r.ntile[d]; }
         a.ntiles = ntiles;
-        a.S = S;
-        a.inv_hw2 = inv_hw2;
+        a.ws = shape;
         const size_t lds = spread_lds_bytes(sizeof(real), PW, r.B[0], r.B[1], r.B[2]);
         if (lds > kTileLdsBytes) return hipErrorInvalidConfiguration;
         const int nlines = r.I[0] * r.I[1];
@@ -488,11 +523,11 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         for (int d = 0; d < 3; ++d) {
             a.B[d] = r.B[d];
             a.nt[d] = r.ntile[d];
-            a.dcoef[d] = (real)(2.0 * r.S / ((double)HW * HW * r.h[d]));
+            a.dcoef[d] = es ? (real)(4.0 * r.beta / ((double)PW * PW * r.h[d]))
+                            : (real)(2.0 * r.S / ((double)HW * HW * r.h[d]));
         }
         a.ntiles = ntiles;
-        a.S = S;
-        a.inv_hw2 = inv_hw2;
+        a.ws = shape;
         a.vol = (real)(r.h[0] * r.h[1] * r.h[2]);
         size_t lds = (size_t)(r.B[0] + PW - 1) * (r.B[1] + PW - 1) * (r.B[2] + PW - 1) * sizeof(real);
         // plus the static residue sort: 128 + kGatherChunk ints

@@ -6,12 +6,31 @@
 // model for this GPU in place of eq. optimiz's CPU cost ratio.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 #include <cstring>
 
 #include "internal.hpp"
 
 namespace sog {
+
+// The ES window psi(d) = exp(beta (sqrt(1 - (d/a)^2) - 1)), |d| < a = P_w/2 (grid units).
+// Its transform by x = a sin(theta): 2 a int_0^{pi/2} exp(beta (cos theta - 1))
+// cos(kappa a sin theta) cos theta dtheta, a smooth integrand; composite Simpson with
+// enough panels for the oscillation.
+double es_hat_grid(double kappa, int Pw, double beta) {
+    const double a = 0.5 * Pw;
+    const int n = 2 * (48 + (int)std::ceil(2.0 * std::fabs(kappa) * a));
+    const double dth = 0.5 * 3.14159265358979323846 / n;
+    double sum = 0;
+    for (int i = 0; i <= n; ++i) {
+        const double th = i * dth;
+        const double f = std::exp(beta * (std::cos(th) - 1.0)) * std::cos(kappa * a * std::sin(th)) * std::cos(th);
+        sum += f * ((i == 0 || i == n) ? 1.0 : ((i & 1) ? 4.0 : 2.0));
+    }
+    return 2.0 * a * sum * dth / 3.0;
+}
 
 namespace {
 
@@ -32,11 +51,13 @@ const Row kTable1[6] = {
 };
 
 // GPU cost model: seconds per unit of work of the float32 kernels on MI355X, fitted to
-// rocprofv3 times at N = 10^6 for two grid sizes (float64 takes about twice as long in
-// every term).  It only ranks candidate discretisations.
-constexpr double kCostNearPair = 1.2e-11;   // per neighbour pair within r_c
-constexpr double kCostWindowPt = 4.5e-13;   // per particle per window point, spread + gather
-constexpr double kCostFFTPt = 3.9e-11;      // per real grid point: FFT chain, tile halo loads and adds
+// the kernels' event times at N = 10^6 on the cube for two windows and grid sizes (float64
+// takes about twice as long in every term but the near field's, about three times).  It
+// only ranks candidate discretisations, all of which meet the error model.
+constexpr double kCostNearPair = 5.6e-12;   // per neighbour pair within r_c
+constexpr double kCostSpreadSlot = 1.0e-10; // per particle per gridding lane update (x planes of a wave x 64-node passes)
+constexpr double kCostGatherPt = 1.7e-13;   // per particle per window point of the gathering
+constexpr double kCostFFTPt = 1.4e-11;      // per real grid point: FFT chain, tile halo loads and adds
 constexpr double kCostLongDirect = 1.0e-12; // per particle per (half-plane mode x Chebyshev term)
 constexpr double kCostWindow2Pt = 9.0e-13;  // per particle per 2D window point per Chebyshev term
 constexpr double kCostFFT2Pt = 3.6e-11;     // per 2D grid point per Chebyshev term
@@ -179,9 +200,106 @@ struct MidChoice {
     int I[3] = {0, 0, 0};
     int Izs = 0, Pw = 0;
     double S = 0, cost = 1e300;
+    int window = SOG_WINDOW_GAUSSIAN;
+    double beta = 0;
 };
 
-MidChoice plan_mid(const double L[3], int64_t n, double s0, double sm, double eps, int prec,
+// Aliasing estimate of the ES window.  Gridding and gathering each fold the spectrum of
+// the spread charge onto the grid's band; for the narrowest mid-range Gaussian s (1D,
+// normalised to G(0) = 1) the error is about
+//   (1/pi) int_0^pi sqrt(pi) (s/h) exp(-(s/h)^2 kappa^2 / 4) R(kappa) dkappa,
+//   R(kappa) = sum_{n=1,2} (|What_g(2 pi n - kappa)| + |What_g(2 pi n + kappa)|) / What_g(kappa),
+// in grid units.  R depends only on (P_w, beta), so it is tabulated once per pair.  Against
+// a 1D simulation of gridding, FFT, deconvolution and gathering the estimate is within a
+// factor 2 of the measured error.
+constexpr int kEsK = 65;                                   // kappa points on [0, pi]
+constexpr double kEsShape[] = {1.6, 1.8, 2.0, 2.2, 2.4, 2.6};  // beta / P_w candidates
+constexpr int kEsNShape = sizeof(kEsShape) / sizeof(kEsShape[0]);
+
+// Per (P_w, beta): R(kappa_i) in [0, kEsK) and What_g(kappa_i) / What_g(0) in [kEsK, 2 kEsK).
+const std::vector<double>& es_ratio(int Pw, double beta) {
+    static std::mutex mu;
+    static std::map<std::pair<int, long long>, std::vector<double>> cache;
+    const std::pair<int, long long> key(Pw, std::llround(beta * 1e9));
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    // es_hat_grid's rule with the panels its largest argument (5 pi) needs, the theta
+    // nodes shared by every argument
+    const double a = 0.5 * Pw;
+    const int nq = 2 * (48 + (int)std::ceil(2.0 * 5.0 * kPi * a));
+    const double dth = 0.5 * kPi / nq;
+    std::vector<double> f(nq + 1), x(nq + 1);
+    for (int i = 0; i <= nq; ++i) {
+        const double th = i * dth;
+        f[i] = std::exp(beta * (std::cos(th) - 1.0)) * std::cos(th) * ((i == 0 || i == nq) ? 1.0 : ((i & 1) ? 4.0 : 2.0));
+        x[i] = a * std::sin(th);
+    }
+    auto hat = [&](double kappa) {
+        double sum = 0;
+        for (int i = 0; i <= nq; ++i) sum += f[i] * std::cos(kappa * x[i]);
+        return 2.0 * a * sum * dth / 3.0;
+    };
+    std::vector<double> R(2 * kEsK);
+    const double wzero = hat(0.0);
+    for (int i = 0; i < kEsK; ++i) {
+        const double k = kPi * i / (kEsK - 1);
+        double al = 0;
+        for (int nn = 1; nn <= 2; ++nn) al += std::fabs(hat(2 * kPi * nn - k)) + std::fabs(hat(2 * kPi * nn + k));
+        const double w0 = hat(k);
+        R[i] = w0 > 0 ? al / w0 : 1e300;
+        R[kEsK + i] = w0 / wzero;
+    }
+    return cache.emplace(key, std::move(R)).first->second;
+}
+
+// The deconvolution multiplies each direction's spectrum by Ghat(k) / What(k)^2; where that
+// grows above its value at k = 0 it amplifies the rounding of the spread grid (float32: a
+// window with What(pi) / What(0) ~ 1e-5, a flat ES window on a coarse grid, amplified it
+// 1.5e5-fold and cost 1e-4 in the potential).  ES windows are accepted only where the
+// growth stays below kEsAmpMax in every direction, as the Gaussian's does (it never grows).
+constexpr double kEsAmpMax = 4.0;
+
+double es_alias_estimate(int Pw, double beta, double s_over_h) {
+    const std::vector<double>& R = es_ratio(Pw, beta);
+    double acc = 0;
+    for (int i = 0; i < kEsK; ++i) {
+        const double k = kPi * i / (kEsK - 1);
+        const double e = std::exp(-s_over_h * s_over_h * k * k / 4.0);
+        const double wn = R[kEsK + i];
+        if (!(wn > 0) || e / (wn * wn) > kEsAmpMax) return 1e300;
+        acc += std::sqrt(kPi) * s_over_h * e * R[i] * ((i == 0 || i == kEsK - 1) ? 0.5 : 1.0);
+    }
+    return acc * (kPi / (kEsK - 1)) / kPi;
+}
+
+// The ES window for spacing h: the smallest P_w (odd, at most kMaxPw) whose estimate
+// meets eps / kEsMargin with the best beta of kEsShape (or the given P_w / beta); false if
+// none.  The margin covers the estimate's shortfall on coarse grids (up to 2.5x against the
+// 1D simulation at s/h = 2) and the forces, whose error is about 8x the potential's in the
+// same simulation for either window.
+constexpr double kEsMargin = 4.0;
+bool es_window(double h, double s0, double eps, const sog_params& ov, int* Pw_out, double* beta_out) {
+    eps /= kEsMargin;
+    for (int p = 3; p <= kMaxPw; p += 2) {
+        if (ov.mid_Pw[0] > 0 && p != ov.mid_Pw[0]) continue;
+        double best = 1e300, bbest = 0;
+        for (int ci = 0; ci < kEsNShape; ++ci) {
+            const double beta = ov.mid_beta > 0 ? ov.mid_beta : kEsShape[ci] * p;
+            const double e = es_alias_estimate(p, beta, s0 / h);
+            if (bbest == 0 || e < best) { best = e; bbest = beta; }
+            if (ov.mid_beta > 0) break;
+        }
+        if (best <= eps || ov.mid_Pw[0] > 0) {
+            *Pw_out = p;
+            *beta_out = bbest;
+            return true;
+        }
+    }
+    return false;
+}
+
+MidChoice plan_mid(const double L[3], int64_t n, double s0, double sm, int nl, double eps, int prec,
                    const sog_params& ov) {
     MidChoice best;
     const double eps_t = eps, eps_w = eps, eps_p = eps;
@@ -197,42 +315,64 @@ MidChoice plan_mid(const double L[3], int64_t n, double s0, double sm, double ep
         if (ov.mid_I[0] > 0) for (int d = 0; d < 3; ++d) c.I[d] = ov.mid_I[d];
         double hd[3] = {L[0] / c.I[0], L[1] / c.I[1], L[2] / c.I[2]};
         double hw = std::max(hd[0], std::max(hd[1], hd[2]));
-        int Pw = 0;
-        double S = 0;
-        if (ov.mid_Pw[0] > 0) {
-            Pw = ov.mid_Pw[0];
-            window_exponent(Pw, hw, s0, &S);
-        } else {
-            for (int p = 5; p <= kMaxPw; p += 2) {
-                double Sp;
-                double E = window_exponent(p, hw, s0, &Sp);
-                if (std::exp(-E) <= eps_w) { Pw = p; S = Sp; break; }
+        const MidChoice grid = c;
+        // the Gaussian window (eq. GS) and the ES window, each where allowed
+        const bool try_gauss = ov.mid_window != SOG_WINDOW_ES;
+        const bool try_es = ov.mid_window == SOG_WINDOW_ES || (ov.mid_window == SOG_WINDOW_AUTO && !(ov.mid_S > 0));
+        for (int win = 0; win < 2; ++win) {
+            c = grid;
+            int Pw = 0;
+            double S = 0, beta = 0;
+            if (win == 0) {
+                if (!try_gauss) continue;
+                if (ov.mid_Pw[0] > 0) {
+                    Pw = ov.mid_Pw[0];
+                    window_exponent(Pw, hw, s0, &S);
+                } else {
+                    for (int p = 5; p <= kMaxPw; p += 2) {
+                        double Sp;
+                        double E = window_exponent(p, hw, s0, &Sp);
+                        if (std::exp(-E) <= eps_w) { Pw = p; S = Sp; break; }
+                    }
+                    if (Pw == 0) continue;
+                }
+                if (ov.mid_S > 0) S = ov.mid_S;
+            } else {
+                if (!try_es || !es_window(hw, s0, eps_w, ov, &Pw, &beta)) continue;
             }
-            if (Pw == 0) continue;
+            for (int d = 0; d < 2; ++d)
+                if (c.I[d] < 2 * Pw) c.I[d] = next_smooth(2 * Pw, true);
+            // the x and y passes hold at least one complex line (and pitch) per block in LDS
+            if (fft_x_lds_min_bytes(prec, c.I[0], nl, 1) > 65536 || fft_x_lds_min_bytes(prec, c.I[1], 0, 1) > 65536)
+                continue;
+            hd[0] = L[0] / c.I[0];
+            hd[1] = L[1] / c.I[1];
+            // the window's reach in z: (P_w - 1)/2 nodes (Gaussian), its support P_w/2 (ES)
+            double Hz = (win == 0 ? 0.5 * (Pw - 1) : 0.5 * Pw) * hd[2];
+            // padding (Thm thm::pad): the widest mid-range Gaussian must decay to eps over
+            // the extension beyond the window's reach.  (Decay to sqrt(eps) was too little
+            // for a cell with a large z dipole, whose image errors add up coherently: the
+            // 2e5-particle layered electrolyte missed 1e-4 in the forces at m = 10.)
+            double delta = sm * std::sqrt(std::log(1.0 / eps_p));
+            double Lzs = L[2] + 2.0 * Hz + delta;
+            int half = next_smooth((int)std::ceil(Lzs / hd[2] / 2.0 - 1e-9), false);
+            c.Izs = 2 * half;
+            while (c.Izs < c.I[2] + Pw + 2) c.Izs = 2 * next_smooth(c.Izs / 2 + 1, false);
+            if (ov.mid_Izs > 0) c.Izs = ov.mid_Izs;
+            c.Pw = Pw;
+            c.S = S;
+            c.window = win == 0 ? SOG_WINDOW_GAUSSIAN : SOG_WINDOW_ES;
+            c.beta = beta;
+            double Ng = (double)c.I[0] * c.I[1] * c.Izs;
+            // gridding: each wave updates ceil(P_w / 4) x planes times ceil(P_w^2 / 64)
+            // passes of 64 (y, z) nodes per particle; gathering: P_w^3 points per particle
+            const double slots = (double)((Pw + 3) / 4) * ((Pw * Pw + 63) / 64);
+            c.cost = (double)n * (kCostSpreadSlot * slots + kCostGatherPt * Pw * Pw * Pw) + kCostFFTPt * Ng;
+            c.ok = true;
+            if (c.cost < best.cost) best = c;
         }
-        if (ov.mid_S > 0) S = ov.mid_S;
-        for (int d = 0; d < 2; ++d)
-            if (c.I[d] < 2 * Pw) c.I[d] = next_smooth(2 * Pw, true);
-        hd[0] = L[0] / c.I[0];
-        hd[1] = L[1] / c.I[1];
-        double Hz = 0.5 * (Pw - 1) * hd[2];
-        // padding (Thm thm::pad): the widest mid-range Gaussian must decay over the
-        // extension beyond the window's reach
-        double delta = sm * std::sqrt(std::log(1.0 / eps_p) / 2.0);
-        double Lzs = L[2] + 2.0 * Hz + delta;
-        int half = next_smooth((int)std::ceil(Lzs / hd[2] / 2.0 - 1e-9), false);
-        c.Izs = 2 * half;
-        while (c.Izs < c.I[2] + Pw + 2) c.Izs = 2 * next_smooth(c.Izs / 2 + 1, false);
-        if (ov.mid_Izs > 0) c.Izs = ov.mid_Izs;
-        c.Pw = Pw;
-        c.S = S;
-        double Ng = (double)c.I[0] * c.I[1] * c.Izs;
-        c.cost = kCostWindowPt * (double)n * Pw * Pw * Pw + kCostFFTPt * Ng;
-        c.ok = true;
-        if (c.cost < best.cost) best = c;
         if (ov.mid_I[0] > 0) break;
     }
-    (void)prec;
     return best;
 }
 
@@ -473,6 +613,9 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
     if (!(tol >= tmin && tol <= 1e-2)) { err = "tol outside the reachable range for this precision"; return SOG_ERR_TOL_UNREACHABLE; }
     r.tol = tol;
     if (ov.mid_Pw[0] != ov.mid_Pw[1] || ov.mid_Pw[0] != ov.mid_Pw[2]) { err = "mid_Pw must be equal in x, y, z"; return SOG_ERR_INVALID_ARG; }
+    if (ov.mid_window < SOG_WINDOW_AUTO || ov.mid_window > SOG_WINDOW_ES) { err = "mid_window must be 0, 1 or 2"; return SOG_ERR_INVALID_ARG; }
+    if (ov.mid_beta < 0 || !std::isfinite(ov.mid_beta)) { err = "mid_beta must be finite and >= 0"; return SOG_ERR_INVALID_ARG; }
+    if (ov.mid_window == SOG_WINDOW_ES && ov.mid_S > 0) { err = "mid_S is the Gaussian window's shape; use mid_beta with the ES window"; return SOG_ERR_INVALID_ARG; }
     if (ov.mid_Pw[0] < 0 || (ov.mid_Pw[0] > 0 && (ov.mid_Pw[0] % 2 == 0 || ov.mid_Pw[0] < 3 || ov.mid_Pw[0] > kMaxPw))) { err = "mid_Pw must be odd in [3, 15]"; return SOG_ERR_INVALID_ARG; }
     if (ov.long_Pw[0] != ov.long_Pw[1] || (ov.long_Pw[0] > 0 && (ov.long_Pw[0] % 2 == 0 || ov.long_Pw[0] < 3 || ov.long_Pw[0] > kMaxPw))) { err = "long_Pw must be odd in [3, 15] and equal in x, y"; return SOG_ERR_INVALID_ARG; }
     if (ov.long_P < 0 || ov.long_P > 64) { err = "long_P must be in [1, 64]"; return SOG_ERR_INVALID_ARG; }
@@ -519,7 +662,8 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         M = std::min(M, 4000);
         c.M = M;
         sog_weights(c.b, c.sigma, c.omega, M, c.w, c.s);
-        double near_cost = kCostNearPair * (double)n * (4.0 * kPi / 3.0) * rc * rc * rc * rho;
+        double near_cost = kCostNearPair * (r.prec == SOG_PREC_FP64 ? 3.0 : 1.0) * (double)n * (4.0 * kPi / 3.0) *
+                           rc * rc * rc * rho;
         // candidate splits: m = -1 (all long) .. last l with s_l <= 2 Lz
         int mlo = -1, mhi = -1;
         for (int l = 0; l <= M; ++l)
@@ -532,7 +676,7 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
             MidChoice mc;
             LongChoice lc;
             if (m >= 0) {
-                mc = plan_mid(r.L, n, c.s[0], c.s[m], eps, r.prec, ov);
+                mc = plan_mid(r.L, n, c.s[0], c.s[m], m + 1, eps, r.prec, ov);
                 if (!mc.ok) continue;
                 cost += mc.cost;
             }
@@ -552,6 +696,8 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
                     best.Izs = mc.Izs;
                     best.Pw = mc.Pw;
                     best.S = mc.S;
+                    best.window = mc.window;
+                    best.beta = mc.beta;
                 }
                 if (best.has_long) {
                     best.form = lc.form;

@@ -31,6 +31,14 @@ CASES = {
     # field's coordinates
     "clustered": dict(N=3000, box=(12.0, 12.0, 48.0), seed=15, row=3, rc=3.0, M=140, m=8, gen="clustered",
                       mid=dict(I=(24, 24, 96), Izs=200, Pw=9), long=dict(form="direct", P=20, nk=(1, 1))),
+    # the ES window (sog_window ES, oracle window="es"): the cube with P_w = 7 and a tall
+    # box (z frames, long z lines) with P_w = 9
+    "cube_es": dict(N=1000, box=(20.0, 20.0, 20.0), seed=1, row=3, rc=4.0, M=100, m=6,
+                    mid=dict(I=(32, 32, 32), Izs=80, Pw=7, window="es", beta=16.1),
+                    long=dict(form="direct", P=12, nk=(4, 4))),
+    "tall_es": dict(N=1200, box=(10.0, 10.0, 60.0), seed=13, row=3, rc=3.0, M=140, m=8,
+                    mid=dict(I=(20, 20, 120), Izs=252, Pw=9, window="es", beta=19.8),
+                    long=dict(form="direct", P=20, nk=(1, 1))),
     # window 13 and odd-radix FFT lengths (3, 5, 7)
     "radix_mix": dict(N=900, box=(21.0, 15.0, 10.0), seed=14, row=4, rc=3.5, M=200, m=5,
                       mid=dict(I=(42, 30, 20), Izs=70, Pw=13), long=dict(form="direct", P=14, nk=(3, 2))),
@@ -46,8 +54,11 @@ def gpu_params(c):
     b, r0, om = TABLE1_ROWS[c["row"]]
     p = dict(b=b, r0=r0, omega=om, rc=c["rc"], M=c["M"], m=c["m"], set_m=1)
     if c["mid"]:
-        p.update(mid_I=list(c["mid"]["I"]), mid_Izs=c["mid"]["Izs"], mid_Pw=[c["mid"]["Pw"]] * 3,
-                 mid_S=_window_S(c["mid"]["Pw"]))
+        p.update(mid_I=list(c["mid"]["I"]), mid_Izs=c["mid"]["Izs"], mid_Pw=[c["mid"]["Pw"]] * 3)
+        if c["mid"].get("window") == "es":
+            p.update(mid_window=2, mid_beta=c["mid"]["beta"])
+        else:
+            p.update(mid_window=1, mid_S=_window_S(c["mid"]["Pw"]))
     lp = c["long"]
     if lp:
         p.update(long_form=lp["form"], long_P=lp["P"])
@@ -65,6 +76,8 @@ def oracle_params(c):
     if c["mid"]:
         Pw = c["mid"]["Pw"]
         mid = dict(I=tuple(c["mid"]["I"]), Izs=c["mid"]["Izs"], Pw=(Pw, Pw, Pw), S=_window_S(Pw))
+        if c["mid"].get("window") == "es":
+            mid.update(window="es", beta=c["mid"]["beta"])
     lp = dict(c["long"]) if c["long"] else None
     if lp and lp["form"] == "fft":
         lp = dict(form="fft", P=lp["P"], I=tuple(lp["I"]), Pw=(lp["Pw"], lp["Pw"]), S=_window_S(lp["Pw"]))

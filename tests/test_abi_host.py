@@ -82,6 +82,9 @@ def test_resolve_rejects_bad_arguments(box, n, tol, prec, status):
     dict(long_P=65),
     dict(mid_Izs=81),              # odd padded z grid
     dict(mid_Pw=[17, 17, 17]),     # wider than the kernels are built for
+    dict(mid_window=3),            # no such window
+    dict(mid_window=2, mid_S=12.0),  # the Gaussian's shape given for the ES window
+    dict(mid_beta=-1.0),
 ])
 def test_resolve_rejects_bad_overrides(params):
     assert _resolve_status((20, 20, 20), 1000, 1e-4, "fp64", params) == _lib.SOG_ERR_INVALID_ARG
@@ -163,3 +166,28 @@ def test_tight_tolerance_small_box_plans(tol):
         assert p["mid_Pw"][0] <= 15
     if p["m"] < p["M"] and p["long_form"] == _lib.SOG_LONG_FFT:
         assert p["long_Pw"][0] <= 15
+
+
+def test_window_choice():
+    """AUTO takes the ES window where it is cheaper (the 10^6 cube), the Gaussian when its
+    shape is given; each explicit choice is honoured and reported with its shape."""
+    box, n = (100.0, 100.0, 100.0), 1000000
+    auto = sog.plan_parameters(box, n, 1e-4, "fp32")
+    assert auto["mid_window"] == _lib.SOG_WINDOW_ES and auto["mid_beta"] > 0 and auto["mid_S"] == 0
+    g = sog.plan_parameters(box, n, 1e-4, "fp32", dict(mid_window=_lib.SOG_WINDOW_GAUSSIAN))
+    assert g["mid_window"] == _lib.SOG_WINDOW_GAUSSIAN and g["mid_S"] > 0 and g["mid_beta"] == 0
+    assert auto["mid_Pw"][0] < g["mid_Pw"][0]  # the compact window needs fewer points
+    gs = sog.plan_parameters(box, n, 1e-4, "fp32", dict(mid_S=12.0))
+    assert gs["mid_window"] == _lib.SOG_WINDOW_GAUSSIAN and gs["mid_S"] == 12.0
+    es = sog.plan_parameters((20, 20, 20), 1000, 1e-6, "fp64",
+                             dict(mid_window=_lib.SOG_WINDOW_ES, mid_Pw=[9, 9, 9], mid_beta=19.0))
+    assert es["mid_window"] == _lib.SOG_WINDOW_ES and es["mid_Pw"] == [9, 9, 9] and es["mid_beta"] == 19.0
+    # a forced window keeps its shape even where the planner would not pick it (a coarse
+    # grid on which its deconvolution grows at the band edge)
+    t = sog.plan_parameters((10, 10, 60), 1200, 1e-6, "fp64",
+                            dict(mid_window=_lib.SOG_WINDOW_ES, mid_I=[20, 20, 120], mid_Izs=252, mid_Pw=[9, 9, 9],
+                                 mid_beta=19.8))
+    assert t["mid_beta"] == 19.8
+    t = sog.plan_parameters((10, 10, 60), 1200, 1e-6, "fp64",
+                            dict(mid_window=_lib.SOG_WINDOW_ES, mid_I=[20, 20, 120], mid_Izs=252, mid_Pw=[9, 9, 9]))
+    assert t["mid_beta"] > 0

@@ -51,7 +51,9 @@ def _sample_errors(name, phi, F, q):
     return ephi, eF
 
 
-CASES = [("cube_1e6", "fp32"), ("cube_1e6", "fp64"), ("slab_1e6", "fp32"), ("tall_1e6", "fp32"),
+# slab_1e6 in FP64 runs the x pass with the multiplier table in global memory (12 mid-range
+# Gaussians x 672 points do not fit in LDS beside the lines)
+CASES = [("cube_1e6", "fp32"), ("cube_1e6", "fp64"), ("slab_1e6", "fp32"), ("slab_1e6", "fp64"), ("tall_1e6", "fp32"),
          ("layered_2e5", "fp32"), ("layered_2e5", "fp64")]
 
 
