@@ -97,10 +97,10 @@ double window_exponent(int Pw, double h, double s, double* S_out) {
 
 int tile_edge(int prec, int Pw) {
     // LDS of the gridding kernel (tile, halo and staging; the gathering kernel needs less)
-    // within kTileLdsBytes
+    // within tile_lds_budget(P_w)
     const size_t rs = (prec == SOG_PREC_FP64) ? 8 : 4;
     for (int B = 16; B >= 1; --B)
-        if (spread_lds_bytes(rs, Pw, B, B, B) <= kTileLdsBytes) return B;
+        if (spread_lds_bytes(rs, Pw, B, B, B) <= tile_lds_budget(Pw)) return B;
     return 1;
 }
 
@@ -119,7 +119,7 @@ bool spread_pitch_conflict_free(int Pw, int HZ) {
 
 // Tile of the gridding and gathering kernels.  float32: among z extents whose halo pitch
 // is conflict-free, the tile with the largest share of owned nodes in its halo block that
-// fits kTileLdsBytes of LDS; float64 (two banks per value anyway), or no such extent: the
+// fits tile_lds_budget(P_w) of LDS; float64 (two banks per value anyway), or no such extent: the
 // largest cube.
 void spread_tile(int prec, int Pw, int B[3]) {
     const int c = tile_edge(prec, Pw);
@@ -130,8 +130,8 @@ void spread_tile(int prec, int Pw, int B[3]) {
         const int HZ = bz + Pw - 1;
         if (!spread_pitch_conflict_free(Pw, HZ)) continue;
         int bxy = 32;
-        while (bxy > 1 && spread_lds_bytes(4, Pw, bxy, bxy, bz) > kTileLdsBytes) --bxy;
-        if (spread_lds_bytes(4, Pw, bxy, bxy, bz) > kTileLdsBytes) continue;
+        while (bxy > 1 && spread_lds_bytes(4, Pw, bxy, bxy, bz) > tile_lds_budget(Pw)) --bxy;
+        if (spread_lds_bytes(4, Pw, bxy, bxy, bz) > tile_lds_budget(Pw)) continue;
         const double eff = (double)bxy * bxy * bz / ((double)(bxy + Pw - 1) * (bxy + Pw - 1) * HZ);
         if (eff >= 0.97 * best) {
             best = std::max(best, eff);

@@ -5,6 +5,7 @@
 //  1. gridding lane nodes: every window node (y, z) is taken by exactly one lane of one
 //     pass; a dummy node has z >= P_w, an offset no window node has, stays in the corner's
 //     x plane for every corner in the tile, and is used by no other lane;
+//     both kernels' LDS within the tile budget;
 //  2. the gridding kernel's LDS addressing (a model of k_spread's index arithmetic): for
 //     every corner in the tile, wave, plane and pass, the address lies in the padded halo
 //     block, in an x plane the wave owns (x = wave mod 4), and the addresses of one
@@ -43,8 +44,12 @@ static void check_lane_nodes_and_addresses() {
         for (int Pw = 3; Pw <= 15; Pw += 2) {
             int B[3];
             spread_tile(prec, Pw, B);
-            CHECK(spread_lds_bytes(prec == SOG_PREC_FP64 ? 8 : 4, Pw, B[0], B[1], B[2]) <= kTileLdsBytes,
+            CHECK(spread_lds_bytes(prec == SOG_PREC_FP64 ? 8 : 4, Pw, B[0], B[1], B[2]) <= tile_lds_budget(Pw),
                   "tile LDS over budget Pw %d", Pw);
+            // the gathering kernel: the halo block plus its residue-sort scratch (128 + 256 ints)
+            CHECK((size_t)(B[0] + Pw - 1) * (B[1] + Pw - 1) * (B[2] + Pw - 1) * (prec == SOG_PREC_FP64 ? 8 : 4) +
+                          (128 + 256) * 4 <= tile_lds_budget(Pw),
+                  "gather LDS over budget Pw %d", Pw);
             for (int bz : {B[2], 2, 3, 5, 8}) {
                 if (bz > B[2]) continue;  // tiles are clipped to small grids, never grown
                 const int HX = B[0] + Pw - 1, HY = B[1] + Pw - 1, HZ = bz + Pw - 1, HYZ = HY * HZ;
