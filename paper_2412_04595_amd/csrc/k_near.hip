@@ -180,6 +180,76 @@ __global__ __launch_bounds__(64) void k_near_chunks(const int* __restrict__ cell
     for (int64_t i = s0 + u + (int)threadIdx.x; i < s1; i += 64) units[i] = make_int4(0, -1, -1, 0);
 }
 
+// Particles of each cell sorted by z (float32 pair kernel).  The columns become z-ordered,
+// so a chunk of consecutive targets spans the least z and the candidates of a neighbour
+// column within r_c of the chunk in z form one contiguous range, which the pair kernel
+// finds by bisection.  One wave per cell: a bitonic network over the cell's (z, index)
+// pairs in LDS, then the records written back in order.  A cell of more than
+// kZsortMax particles stays unsorted and sets status bit 4, which switches the
+// bisection off for the call.
+constexpr int kZsortMax = 256;
+__global__ __launch_bounds__(256) void k_near_zsort(const int* __restrict__ cell_start, int ncells,
+                                                     vec4<float>* __restrict__ pos, int* __restrict__ orig,
+                                                     int* __restrict__ status) {
+    __shared__ float key_all[4][kZsortMax];
+    __shared__ int idx_all[4][kZsortMax];
+    __shared__ vec4<float> rec_all[4][kZsortMax];
+    __shared__ int org_all[4][kZsortMax];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int c = blockIdx.x * 4 + wv;
+    if (c >= ncells) return;
+    const int b = cell_start[c], n = cell_start[c + 1] - b;
+    if (n <= 1) return;
+    if (n > kZsortMax) {
+        if (lane == 0) atomicOr(status, 4);
+        return;
+    }
+    float* key = key_all[wv];
+    int* idx = idx_all[wv];
+    vec4<float>* rec = rec_all[wv];
+    int* org = org_all[wv];
+    int S = 2;
+    while (S < n) S <<= 1;
+    for (int i = lane; i < S; i += 64) {
+        if (i < n) {
+            rec[i] = pos[b + i];
+            org[i] = orig[b + i];
+            key[i] = rec[i].z;
+        } else {
+            key[i] = INFINITY;
+        }
+        idx[i] = i;
+    }
+    auto sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    sync();
+    // ascending by (z, original index): a strict order, so the result is unique
+    for (int k = 2; k <= S; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int pi = lane; pi < S / 2; pi += 64) {
+                const int i = 2 * j * (pi / j) + pi % j, q = i + j;
+                const float ki = key[i], kq = key[q];
+                const int ii = idx[i], iq = idx[q];
+                const bool gt = ki > kq || (ki == kq && ii > iq);
+                if (gt == ((i & k) == 0)) {
+                    key[i] = kq;
+                    key[q] = ki;
+                    idx[i] = iq;
+                    idx[q] = ii;
+                }
+            }
+            sync();
+        }
+    for (int i = lane; i < n; i += 64) {
+        const int src = idx[i];
+        pos[b + i] = rec[src];
+        orig[b + i] = org[src];
+    }
+}
+
 // the 8 work counters live after the units, on 128-byte boundaries
 inline int* near_grab(const Workspace& ws, int64_t slots) {
     return reinterpret_cast<int*>(static_cast<char*>(ws.near_units) + ((size_t)slots * 16 + 127) / 128 * 128);
@@ -193,6 +263,8 @@ struct NearArgs {
     vec4<real>* __restrict__ part;  // near part of each particle: phi, grad
     const int4* __restrict__ units;  // (column, first cell, end cell); first cell -1: none
     int* grab;                       // per-XCD counters of units taken (zeroed by k_near_units)
+    const int* status;               // bit 4: some cell is not z-sorted (no bisection of the ranges)
+    float zcut;                      // r_c with a rounding margin: the z reach of the ranges
     int max_units;
     int nc[3];
     real ch[3];
@@ -452,6 +524,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near_mfma(NearArgs<float> a
     const int ibeg = (blockIdx.x & 7) * per, iend = min(a.max_units, ibeg + per);
     int* grab = a.grab + (blockIdx.x & 7) * kGrabStride;
     const float fh = (float)kNearFrameCells * a.ch[2];  // frame height
+    const bool trim = (__builtin_amdgcn_readfirstlane(*a.status) & 4) == 0;
     for (;;) {
     int g = 0;
     if (lane == 0) g = atomicAdd(grab, 1);
@@ -465,6 +538,9 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near_mfma(NearArgs<float> a
     const int za = max(z0 - 1, 0), zb = min(z1 + 1, a.nc[2]);
     const int bnd = (za / kNearFrameCells + 1) * kNearFrameCells;
     const float zmid = 0.5f * (float)(z0 + z1) * a.ch[2];
+    // the chunk's z extent (its targets are z-sorted): frame-relative z plus the frame base
+    const float tzlo = a.pos[tb].z + (float)(z0 / kNearFrameCells) * fh;
+    const float tzhi = a.pos[te - 1].z + (float)((z1 - 1) / kNearFrameCells) * fh;
     // lane k < 18: range k = column (dx, dy) = k / 2, piece k % 2 of the cells from below
     // the run to above it, cut at the frame boundary; its shift into the unit frame
     int rs = 0, len = 0;
@@ -481,6 +557,26 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near_mfma(NearArgs<float> a
         sk = vec4<float>{((float)dx - 0.5f) * a.ch[0], ((float)dy - 0.5f) * a.ch[1],
                          (float)(pa / kNearFrameCells) * fh - zmid, 0.f};
         shift[lane] = sk;
+        if (trim && len > 0) {
+            // the columns are z-sorted: keep the candidates within zcut of the chunk's z
+            // extent [z of the first target, z of the last], by bisection in the piece's
+            // frame coordinates
+            const float fo = (float)(pa / kNearFrameCells) * fh;
+            const float lo = tzlo - a.zcut - fo, hi = tzhi + a.zcut - fo;
+            int l = rs, h = rs + len;
+            while (l < h) {
+                const int mid = (l + h) >> 1;
+                if (a.pos[mid].z < lo) l = mid + 1; else h = mid;
+            }
+            const int nrs = l;
+            h = rs + len;
+            while (l < h) {
+                const int mid = (l + h) >> 1;
+                if (a.pos[mid].z <= hi) l = mid + 1; else h = mid;
+            }
+            len = l - nrs;
+            rs = nrs;
+        }
     }
     // the ranges as one sequence: range k holds positions [pre_k, pre_k + len_k), and
     // position v of it is particle base_k + v
@@ -677,9 +773,12 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
         k_near_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, (const int2*)ws.key, ws.cell_start,
                                                          (vec4<real>*)ws.near_pos, ws.near_orig);
         const int ncols = r.nc[0] * r.nc[1];
-        if (sizeof(real) == 4)
+        if (sizeof(real) == 4) {
+            k_near_zsort<<<(ncells + 3) / 4, 256, 0, p.stream>>>(ws.cell_start, ncells, (vec4<float>*)ws.near_pos,
+                                                                 ws.near_orig, ws.status);
             k_near_chunks<<<ncols, 64, 0, p.stream>>>(ws.cell_start, r.nc[2], near_chunk_extra(r.nc[2]),
                                                       (int4*)ws.near_units, near_grab(ws, near_unit_slots(r)));
+        }
         else
             k_near_units<<<ncols, 64, 0, p.stream>>>(ws.cell_start, r.nc[2], (int4*)ws.near_units,
                                                      near_grab(ws, near_unit_slots(r)));
@@ -691,6 +790,8 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
     a.orig = ws.near_orig;
     a.units = (const int4*)ws.near_units;
     a.grab = near_grab(ws, near_unit_slots(r));
+    a.status = ws.status;
+    a.zcut = (float)(r.rc * (1.0 + 1e-5) + 1e-4 * r.ch[2]);
     a.max_units = (int)near_unit_slots(r);
     a.cell_start = ws.cell_start;
     a.part = (vec4<real>*)ws.parts;
