@@ -184,7 +184,8 @@ __global__ __launch_bounds__(64) void k_near_chunks(const int* __restrict__ cell
 // so a chunk of consecutive targets spans the least z and the candidates of a neighbour
 // column within r_c of the chunk in z form one contiguous range, which the pair kernel
 // finds by bisection.  One wave per cell: a bitonic network over the cell's (z, index)
-// pairs in LDS, then the records written back in order.  A cell of more than
+// pairs, across the lanes for up to 64 particles, in LDS for more, then the records
+// written back in order.  A cell of more than
 // kZsortMax particles stays unsorted and sets status bit 4, which switches the
 // bisection off for the call.
 constexpr int kZsortMax = 256;
@@ -202,6 +203,37 @@ __global__ __launch_bounds__(256) void k_near_zsort(const int* __restrict__ cell
     if (n <= 1) return;
     if (n > kZsortMax) {
         if (lane == 0) atomicOr(status, 4);
+        return;
+    }
+    if (n <= 64) {
+        // in registers: lane i holds element i (padding +inf), the network by lane shuffles
+        const vec4<float> rv = lane < n ? pos[b + lane] : vec4<float>{0.f, 0.f, 0.f, 0.f};
+        const int ov = lane < n ? orig[b + lane] : 0;
+        float kk = lane < n ? rv.z : INFINITY;
+        int ii = lane;
+#pragma unroll
+        for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const float ko = __shfl_xor(kk, j, 64);
+                const int io = __shfl_xor(ii, j, 64);
+                const bool other_less = ko < kk || (ko == kk && io < ii);
+                const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+                if (keep_min == other_less) {
+                    kk = ko;
+                    ii = io;
+                }
+            }
+        vec4<float> w;
+        w.x = __shfl(rv.x, ii, 64);
+        w.y = __shfl(rv.y, ii, 64);
+        w.z = __shfl(rv.z, ii, 64);
+        w.w = __shfl(rv.w, ii, 64);
+        const int ow = __shfl(ov, ii, 64);
+        if (lane < n) {
+            pos[b + lane] = w;
+            orig[b + lane] = ow;
+        }
         return;
     }
     float* key = key_all[wv];
