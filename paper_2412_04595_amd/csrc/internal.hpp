@@ -20,13 +20,14 @@ static_assert((kMidSub & (kMidSub - 1)) == 0, "kMidSub is a power of two");
 constexpr int kQsumSlots = 64;    // slots of the charge sums (spreads the float64 atomics of the key pass)
 constexpr int kMaxPw = 15;        // widest mid-range window the gridding and gathering kernels take
 constexpr int kSpreadStage = 32;  // particles whose window weights the gridding kernel stages at a time
-// LDS of one gridding or gathering workgroup at most: for narrow windows (P_w <= 9) three
-// workgroups share the 160 KiB of a compute unit (more waves to hide the per-particle LDS
-// round trips: 0.55 -> 0.48 ms gridding and 0.20 -> 0.15 ms gathering at P_w = 7, N = 1e6),
-// for wider ones two (larger tiles waste less on the halo: at P_w = 11 the smaller budget
-// was 8% slower in all)
+// LDS of one gridding or gathering workgroup at most: for narrow float32 windows (P_w <=
+// 9) three workgroups share the 160 KiB of a compute unit (more waves to hide the
+// per-particle LDS round trips: 0.55 -> 0.48 ms gridding and 0.20 -> 0.15 ms gathering at
+// P_w = 7, N = 1e6), otherwise two (larger tiles waste less on the halo: at P_w = 11 the
+// smaller budget was 8% slower in all, and float64 tiles, with twice the bytes per node,
+// were 1.6x slower at P_w = 9)
 constexpr size_t kTileLdsBytes = 81920;  // the largest budget
-inline size_t tile_lds_budget(int Pw) { return Pw <= 9 ? 53248 : kTileLdsBytes; }
+inline size_t tile_lds_budget(int Pw, size_t real_bytes) { return (real_bytes == 4 && Pw <= 9) ? 53248 : kTileLdsBytes; }
 
 // LDS layout of the mid-range gridding kernel: the tile plus its (P_w - 1) halo, 64 sink
 // slots for masked lanes, and per staged particle its y and z window weights (2 P_w) and

@@ -502,7 +502,7 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         a.ntiles = ntiles;
         a.ws = shape;
         const size_t lds = spread_lds_bytes(sizeof(real), PW, r.B[0], r.B[1], r.B[2]);
-        if (lds > tile_lds_budget(PW)) return hipErrorInvalidConfiguration;
+        if (lds > tile_lds_budget(PW, sizeof(real))) return hipErrorInvalidConfiguration;
         const int nlines = r.I[0] * r.I[1];
         k_zero_band<real><<<std::min((nlines + 3) / 4, 16384), 256, 0, p.stream>>>(
             (real*)ws.grid, nlines, r.Izs, r.zband[0], (r.zband[1] - r.zband[0]) / 2);
@@ -531,7 +531,7 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         a.vol = (real)(r.h[0] * r.h[1] * r.h[2]);
         size_t lds = (size_t)(r.B[0] + PW - 1) * (r.B[1] + PW - 1) * (r.B[2] + PW - 1) * sizeof(real);
         // plus the static residue sort: 128 + kGatherChunk ints
-        if (lds + (128 + kGatherChunk) * sizeof(int) > tile_lds_budget(PW)) return hipErrorInvalidConfiguration;
+        if (lds + (128 + kGatherChunk) * sizeof(int) > tile_lds_budget(PW, sizeof(real))) return hipErrorInvalidConfiguration;
         k_gather<real, PW><<<xcd_grid(ntiles), kGatherChunk, lds, p.stream>>>(a);
     }
     return hipGetLastError();

@@ -100,7 +100,7 @@ int tile_edge(int prec, int Pw) {
     // within tile_lds_budget(P_w)
     const size_t rs = (prec == SOG_PREC_FP64) ? 8 : 4;
     for (int B = 16; B >= 1; --B)
-        if (spread_lds_bytes(rs, Pw, B, B, B) <= tile_lds_budget(Pw)) return B;
+        if (spread_lds_bytes(rs, Pw, B, B, B) <= tile_lds_budget(Pw, rs)) return B;
     return 1;
 }
 
@@ -130,8 +130,8 @@ void spread_tile(int prec, int Pw, int B[3]) {
         const int HZ = bz + Pw - 1;
         if (!spread_pitch_conflict_free(Pw, HZ)) continue;
         int bxy = 32;
-        while (bxy > 1 && spread_lds_bytes(4, Pw, bxy, bxy, bz) > tile_lds_budget(Pw)) --bxy;
-        if (spread_lds_bytes(4, Pw, bxy, bxy, bz) > tile_lds_budget(Pw)) continue;
+        while (bxy > 1 && spread_lds_bytes(4, Pw, bxy, bxy, bz) > tile_lds_budget(Pw, 4)) --bxy;
+        if (spread_lds_bytes(4, Pw, bxy, bxy, bz) > tile_lds_budget(Pw, 4)) continue;
         const double eff = (double)bxy * bxy * bz / ((double)(bxy + Pw - 1) * (bxy + Pw - 1) * HZ);
         if (eff >= 0.97 * best) {
             best = std::max(best, eff);

@@ -44,11 +44,11 @@ static void check_lane_nodes_and_addresses() {
         for (int Pw = 3; Pw <= 15; Pw += 2) {
             int B[3];
             spread_tile(prec, Pw, B);
-            CHECK(spread_lds_bytes(prec == SOG_PREC_FP64 ? 8 : 4, Pw, B[0], B[1], B[2]) <= tile_lds_budget(Pw),
+            CHECK(spread_lds_bytes(prec == SOG_PREC_FP64 ? 8 : 4, Pw, B[0], B[1], B[2]) <= tile_lds_budget(Pw, prec == SOG_PREC_FP64 ? 8 : 4),
                   "tile LDS over budget Pw %d", Pw);
             // the gathering kernel: the halo block plus its residue-sort scratch (128 + 256 ints)
             CHECK((size_t)(B[0] + Pw - 1) * (B[1] + Pw - 1) * (B[2] + Pw - 1) * (prec == SOG_PREC_FP64 ? 8 : 4) +
-                          (128 + 256) * 4 <= tile_lds_budget(Pw),
+                          (128 + 256) * 4 <= tile_lds_budget(Pw, prec == SOG_PREC_FP64 ? 8 : 4),
                   "gather LDS over budget Pw %d", Pw);
             for (int bz : {B[2], 2, 3, 5, 8}) {
                 if (bz > B[2]) continue;  // tiles are clipped to small grids, never grown
