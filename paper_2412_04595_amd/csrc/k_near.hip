@@ -180,7 +180,7 @@ __global__ __launch_bounds__(64) void k_near_chunks(const int* __restrict__ cell
     for (int64_t i = s0 + u + (int)threadIdx.x; i < s1; i += 64) units[i] = make_int4(0, -1, -1, 0);
 }
 
-// Particles of each cell sorted by z (float32 pair kernel).  The columns become z-ordered,
+// Particles of each cell sorted by z.  The columns become z-ordered,
 // so a chunk of consecutive targets spans the least z and the candidates of a neighbour
 // column within r_c of the chunk in z form one contiguous range, which the pair kernel
 // finds by bisection.  One wave per cell: a bitonic network over the cell's (z, index)
@@ -189,12 +189,13 @@ __global__ __launch_bounds__(64) void k_near_chunks(const int* __restrict__ cell
 // kZsortMax particles stays unsorted and sets status bit 4, which switches the
 // bisection off for the call.
 constexpr int kZsortMax = 256;
+template <typename real>
 __global__ __launch_bounds__(256) void k_near_zsort(const int* __restrict__ cell_start, int ncells,
-                                                     vec4<float>* __restrict__ pos, int* __restrict__ orig,
+                                                     vec4<real>* __restrict__ pos, int* __restrict__ orig,
                                                      int* __restrict__ status) {
-    __shared__ float key_all[4][kZsortMax];
+    __shared__ real key_all[4][kZsortMax];
     __shared__ int idx_all[4][kZsortMax];
-    __shared__ vec4<float> rec_all[4][kZsortMax];
+    __shared__ vec4<real> rec_all[4][kZsortMax];
     __shared__ int org_all[4][kZsortMax];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int c = blockIdx.x * 4 + wv;
@@ -207,15 +208,15 @@ __global__ __launch_bounds__(256) void k_near_zsort(const int* __restrict__ cell
     }
     if (n <= 64) {
         // in registers: lane i holds element i (padding +inf), the network by lane shuffles
-        const vec4<float> rv = lane < n ? pos[b + lane] : vec4<float>{0.f, 0.f, 0.f, 0.f};
+        const vec4<real> rv = lane < n ? pos[b + lane] : vec4<real>{0, 0, 0, 0};
         const int ov = lane < n ? orig[b + lane] : 0;
-        float kk = lane < n ? rv.z : INFINITY;
+        real kk = lane < n ? rv.z : (real)INFINITY;
         int ii = lane;
 #pragma unroll
         for (int k = 2; k <= 64; k <<= 1)
 #pragma unroll
             for (int j = k >> 1; j > 0; j >>= 1) {
-                const float ko = __shfl_xor(kk, j, 64);
+                const real ko = __shfl_xor(kk, j, 64);
                 const int io = __shfl_xor(ii, j, 64);
                 const bool other_less = ko < kk || (ko == kk && io < ii);
                 const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(256) void k_near_zsort(const int* __restrict__ cell
                     ii = io;
                 }
             }
-        vec4<float> w;
+        vec4<real> w;
         w.x = __shfl(rv.x, ii, 64);
         w.y = __shfl(rv.y, ii, 64);
         w.z = __shfl(rv.z, ii, 64);
@@ -236,9 +237,9 @@ __global__ __launch_bounds__(256) void k_near_zsort(const int* __restrict__ cell
         }
         return;
     }
-    float* key = key_all[wv];
+    real* key = key_all[wv];
     int* idx = idx_all[wv];
-    vec4<float>* rec = rec_all[wv];
+    vec4<real>* rec = rec_all[wv];
     int* org = org_all[wv];
     int S = 2;
     while (S < n) S <<= 1;
@@ -248,7 +249,7 @@ __global__ __launch_bounds__(256) void k_near_zsort(const int* __restrict__ cell
             org[i] = orig[b + i];
             key[i] = rec[i].z;
         } else {
-            key[i] = INFINITY;
+            key[i] = (real)INFINITY;
         }
         idx[i] = i;
     }
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(256) void k_near_zsort(const int* __restrict__ cell
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int pi = lane; pi < S / 2; pi += 64) {
                 const int i = 2 * j * (pi / j) + pi % j, q = i + j;
-                const float ki = key[i], kq = key[q];
+                const real ki = key[i], kq = key[q];
                 const int ii = idx[i], iq = idx[q];
                 const bool gt = ki > kq || (ki == kq && ii > iq);
                 if (gt == ((i & k) == 0)) {
@@ -375,6 +376,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
     const int per = (a.max_units + 7) >> 3;
     const int ibeg = (blockIdx.x & 7) * per, iend = min(a.max_units, ibeg + per);
     int* grab = a.grab + (blockIdx.x & 7) * kGrabStride;
+    const bool trim = (__builtin_amdgcn_readfirstlane(*a.status) & 4) == 0;
     for (;;) {
     int g = 0;
     if (lane == 0) g = atomicAdd(grab, 1);
@@ -400,6 +402,27 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
             re = a.cell_start[ncol * a.nc[2] + pb];
         }
         shift[lane] = vec4<real>{(real)dx * a.ch[0], (real)dy * a.ch[1], (real)(pa / kNearFrameCells), (real)0};
+        if (trim && rs < re) {
+            // the columns are z-sorted: keep the candidates within zcut of the run's targets
+            // in z (first and last target), by bisection in the piece's frame coordinates
+            const real fh = (real)kNearFrameCells * a.ch[2];
+            const real tzlo = a.pos[tb].z + (real)(z0 / kNearFrameCells) * fh;
+            const real tzhi = a.pos[te - 1].z + (real)((z1 - 1) / kNearFrameCells) * fh;
+            const real fo = (real)(pa / kNearFrameCells) * fh;
+            const real lo = tzlo - (real)a.zcut - fo, hi = tzhi + (real)a.zcut - fo;
+            int l = rs, h = re;
+            while (l < h) {
+                const int mid = (l + h) >> 1;
+                if (a.pos[mid].z < lo) l = mid + 1; else h = mid;
+            }
+            rs = l;
+            h = re;
+            while (l < h) {
+                const int mid = (l + h) >> 1;
+                if (a.pos[mid].z <= hi) l = mid + 1; else h = mid;
+            }
+            re = l;
+        }
     }
     constexpr int nranges = 18;
     const real fh = (real)kNearFrameCells * a.ch[2];  // frame height
@@ -805,9 +828,9 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
         k_near_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, (const int2*)ws.key, ws.cell_start,
                                                          (vec4<real>*)ws.near_pos, ws.near_orig);
         const int ncols = r.nc[0] * r.nc[1];
+        k_near_zsort<real><<<(ncells + 3) / 4, 256, 0, p.stream>>>(ws.cell_start, ncells, (vec4<real>*)ws.near_pos,
+                                                                   ws.near_orig, ws.status);
         if (sizeof(real) == 4) {
-            k_near_zsort<<<(ncells + 3) / 4, 256, 0, p.stream>>>(ws.cell_start, ncells, (vec4<float>*)ws.near_pos,
-                                                                 ws.near_orig, ws.status);
             k_near_chunks<<<ncols, 64, 0, p.stream>>>(ws.cell_start, r.nc[2], near_chunk_extra(r.nc[2]),
                                                       (int4*)ws.near_units, near_grab(ws, near_unit_slots(r)));
         }
