@@ -7,12 +7,15 @@
 // Gaussians M (Remark rmk::sum asks for that; a polynomial in r^2 is this library's way
 // of getting it).
 //
-// Work unit: a run of consecutive cells of one (x, y) column holding at most one wave of
-// targets (at most kNearUnitCells cells; a cell with more targets is a unit of its own,
-// walked in several passes).  The units are formed per column on the device after the
-// cell sort.  A unit's candidate sources are the cells of the 9 neighbouring columns from
-// the cell below the run to the cell above it: per column one contiguous range of the
-// cell-sorted array, cut where it crosses a z frame (below).
+// Pipeline: a counting sort of the particles by cell (cells z-fastest, so a column is one
+// contiguous range), then a sort by z inside each cell, so every column is z-ordered.
+// Work units are formed per column on the device: float32, chunks of at most 32
+// consecutive targets within at most kNearUnitCells cells (k_near_chunks; the pair kernel
+// tests candidates against them on the matrix cores, k_near_mfma); float64, runs of
+// whole cells with at most 64 targets (k_near_units, the vector-ALU kernel k_near).  A
+// unit's candidates are, per neighbouring column (9 of them), the cells from below the
+// unit to above it, cut where they cross a z frame (below) and narrowed by bisection to
+// the unit's z extent +- r_c.
 //
 // Coordinates enter the pair kernel as offsets from the corner of the particle's x, y
 // cell and of its z frame (kNearFrameCells cells), formed in float64, so the float32 form
