@@ -31,6 +31,11 @@ CASES = {
     # field's coordinates
     "clustered": dict(N=3000, box=(12.0, 12.0, 48.0), seed=15, row=3, rc=3.0, M=140, m=8, gen="clustered",
                       mid=dict(I=(24, 24, 96), Izs=200, Pw=9), long=dict(form="direct", P=20, nk=(1, 1))),
+    # one cell of 1149 particles (a cluster centred inside a cell): too many to sort by z,
+    # so the near field's range bisection is switched off for the call
+    "dense_cluster": dict(N=3000, box=(10.5, 10.5, 45.0), seed=16, row=3, rc=3.0, M=140, m=8, gen="clustered",
+                          gen_args=dict(frac=0.4, sd=0.7),
+                          mid=dict(I=(24, 24, 90), Izs=200, Pw=9), long=dict(form="direct", P=20, nk=(1, 1))),
     # the ES window (sog_window ES, oracle window="es"): the cube with P_w = 7 and a tall
     # box (z frames, long z lines) with P_w = 9
     "cube_es": dict(N=1000, box=(20.0, 20.0, 20.0), seed=1, row=3, rc=4.0, M=100, m=6,

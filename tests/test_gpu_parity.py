@@ -18,7 +18,7 @@ _ORACLE = {}
 
 def _inputs(name):
     c = CASES[name]
-    x, q = getattr(workloads, c.get("gen", "uniform"))(c["N"], c["box"], c["seed"])
+    x, q = getattr(workloads, c.get("gen", "uniform"))(c["N"], c["box"], c["seed"], **c.get("gen_args", {}))
     return c, x, q
 
 
