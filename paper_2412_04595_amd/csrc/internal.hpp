@@ -100,6 +100,10 @@ struct Resolved {
     int near_deg = 0;
     double near_cF[kMaxNearDeg + 1] = {0};  // F(r)
     double near_cG[kMaxNearDeg + 1] = {0};  // F'(r)/r
+    // the same polynomials in monomial form, F = sum_k near_mF[k] x^k (float32 plans, whose
+    // degree stays small enough for the conversion; evaluated by Horner)
+    double near_mF[kMaxNearDeg + 1] = {0};
+    double near_mG[kMaxNearDeg + 1] = {0};
 
     // mid range (Alg. al::mid)
     bool has_mid = false;

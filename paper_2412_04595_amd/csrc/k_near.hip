@@ -308,6 +308,8 @@ struct NearArgs {
     int deg;
     real cF[kMaxNearDeg + 1];
     real cG[kMaxNearDeg + 1];
+    real mF[kMaxNearDeg + 1];  // the same in monomial form (float32 kernel, Horner)
+    real mG[kMaxNearDeg + 1];
 };
 
 constexpr int kNearWaves = 4;   // independent waves per block
@@ -558,12 +560,29 @@ __device__ __forceinline__ float readlane_f(float v, int k) {
 }
 constexpr int kNearMfmaRows = 16;  // hit-list slots a block appends per lane
 
+// F(r) and F'(r)/r from their monomial form in x = 2 r^2/r_c^2 - 1 by Horner (2 FMAs per
+// degree against the Chebyshev recurrence's 3; in float32 no less accurate on [-1, 1],
+// which the planner's host checks compare), then as near_pair; the particle paired with
+// itself (r^2 == 0) adds nothing
 template <int DEG>
 __device__ __forceinline__ void near_pair_nz(const NearArgs<float>& a, float rx, float ry, float rz, float qj,
                                              float& phi, float& gx, float& gy, float& gz) {
     const float r2 = rx * rx + ry * ry + rz * rz;
     const bool nz = r2 > 0.f;
-    near_pair<float, DEG>(a, rx, ry, rz, nz ? qj : 0.f, phi, gx, gy, gz, nz ? r2 : 1.f);
+    const float q = nz ? qj : 0.f, r2s = nz ? r2 : 1.f;
+    const float xs = 2.f * r2s * a.inv_rc2 - 1.f;
+    float F = a.mF[DEG], G = a.mG[DEG];
+#pragma unroll
+    for (int k = DEG - 1; k >= 0; --k) {
+        F = fmaf(F, xs, a.mF[k]);
+        G = fmaf(G, xs, a.mG[k]);
+    }
+    const float ri = near_rsqrt(r2s);
+    phi += q * (ri - F);
+    const float c = q * (-ri * ri * ri - G);
+    gx += c * rx;
+    gy += c * ry;
+    gz += c * rz;
 }
 
 template <int DEG>
@@ -809,6 +828,8 @@ void launch_near_kernel(const NearArgs<real>& a, int blocks, hipStream_t st) {
 template <typename real>
 hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
     const Resolved& r = p.r;
+    // the float32 kernel evaluates the monomial form, which the planner gives up to degree 24
+    if (sizeof(real) == 4 && r.near_deg > 24) return hipErrorInvalidConfiguration;
     Workspace& ws = p.ws;
     const int n = (int)r.n;
     NearGeom g;
@@ -863,6 +884,8 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
     for (int k = 0; k <= kMaxNearDeg; ++k) {
         a.cF[k] = (real)r.near_cF[k];
         a.cG[k] = (real)r.near_cG[k];
+        a.mF[k] = (real)r.near_mF[k];
+        a.mG[k] = (real)r.near_mG[k];
     }
     const int t = timer_id(p, "near");
     timer_begin(p, t);

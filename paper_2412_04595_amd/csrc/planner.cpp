@@ -596,6 +596,26 @@ void near_chebyshev(Resolved& r) {
     while (deg > 1 && std::fabs(r.near_cF[deg]) < thr * cmaxF && std::fabs(r.near_cG[deg]) < thr * cmaxG) --deg;
     r.near_deg = deg;
     for (int k = deg + 1; k <= kMaxNearDeg; ++k) r.near_cF[k] = r.near_cG[k] = 0.0;
+    // monomial coefficients: T_{k+1} = 2 x T_k - T_{k-1} on coefficient vectors (float64;
+    // the float32 fits stay below degree 24, where the coefficients of T_k are below 2^23)
+    for (int k = 0; k <= kMaxNearDeg; ++k) r.near_mF[k] = r.near_mG[k] = 0.0;
+    if (deg <= 24) {
+        std::vector<double> t0(deg + 2, 0.0), t1(deg + 2, 0.0), t2(deg + 2, 0.0);
+        t0[0] = 1.0;
+        t1[1] = 1.0;
+        for (int k = 0; k <= deg; ++k) {
+            const std::vector<double>& tk = (k == 0) ? t0 : t1;
+            for (int j = 0; j <= k; ++j) {
+                r.near_mF[j] += r.near_cF[k] * tk[j];
+                r.near_mG[j] += r.near_cG[k] * tk[j];
+            }
+            if (k >= 1) {
+                for (int j = 0; j <= deg + 1; ++j) t2[j] = (j > 0 ? 2.0 * t1[j - 1] : 0.0) - t0[j];
+                t0 = t1;
+                t1 = t2;
+            }
+        }
+    }
 }
 
 sog_status resolve(const double box[3], int64_t n, double tol, const sog_options& opt, Resolved& r,

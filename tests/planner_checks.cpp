@@ -14,7 +14,8 @@
 //     exactly when it has no prime factor above 7, into compiled radices;
 //  4. the z band: for z in [0, L_z] the nearest node is never clamped, so every window
 //     lies inside the band of planes the z transforms read and write;
-//  5. the near-field chunks of the float32 pair kernel fit their slots (below).
+//  5. the near-field chunks of the float32 pair kernel fit their slots (below);
+//  6. the float32 near-field polynomials in monomial form (below).
 //
 // Prints one line per failure and "bad N"; exit status 0 when N == 0.
 #include <cmath>
@@ -197,7 +198,67 @@ static void check_near_chunks() {
     }
 }
 
+// 6. the float32 near-field polynomials in monomial form (evaluated by Horner in float32)
+//    agree with their Chebyshev form (float64) on [-1, 1] no worse than the float32 Chebyshev
+//    recurrence does, or within 2.5e-7 of the largest value, for the benchmark workloads' plans
+static void check_near_monomials() {
+    // the float32 fits stay within the degree the conversion takes, at every tolerance
+    for (double tol : {1e-3, 1e-4, 1e-5, 1e-6, 1e-8, 1e-10}) {
+        sog_options opt;
+        std::memset(&opt, 0, sizeof(opt));
+        opt.precision = SOG_PREC_FP32_BULK;
+        Resolved r;
+        std::string err;
+        const double box[3] = {50, 50, 50};
+        if (resolve(box, 100000, tol, opt, r, err) != SOG_OK) continue;
+        CHECK(r.near_deg <= 24, "monomials: tol %g float32 degree %d above 24", tol, r.near_deg);
+        std::printf("float32 near degree at tol %g: %d\n", tol, r.near_deg);
+    }
+    const double boxes[][3] = {{100, 100, 100}, {400, 400, 25}, {50, 50, 800}, {150, 150, 60}, {20, 20, 20}};
+    const int64_t ns[] = {1000000, 1000000, 1000000, 200000, 1000};
+    for (int b = 0; b < 5; ++b) {
+        sog_options opt;
+        std::memset(&opt, 0, sizeof(opt));
+        opt.precision = SOG_PREC_FP32_BULK;
+        Resolved r;
+        std::string err;
+        if (resolve(boxes[b], ns[b], 1e-4, opt, r, err) != SOG_OK) {
+            CHECK(false, "monomials: box %d does not plan: %s", b, err.c_str());
+            continue;
+        }
+        const int D = r.near_deg;
+        for (int which = 0; which < 2; ++which) {
+            const double* c = which ? r.near_cG : r.near_cF;
+            const double* m = which ? r.near_mG : r.near_mF;
+            double vmax = 0, ehorner = 0, erec = 0;
+            for (int i = 0; i <= 4000; ++i) {
+                const double x = -1.0 + 2.0 * i / 4000.0;
+                double ref = 0;
+                for (int k = 0; k <= D; ++k) ref += c[k] * std::cos(k * std::acos(x));
+                vmax = std::max(vmax, std::fabs(ref));
+                float h = (float)m[D];
+                for (int k = D - 1; k >= 0; --k) h = std::fmaf(h, (float)x, (float)m[k]);
+                ehorner = std::max(ehorner, std::fabs((double)h - ref));
+                const float xf = (float)x, x2 = xf + xf;
+                float t0 = 1.f, t1 = xf, acc = (float)c[0] + (float)c[1] * xf;
+                for (int k = 2; k <= D; ++k) {
+                    const float t2 = std::fmaf(x2, t1, -t0);
+                    acc = std::fmaf((float)c[k], t2, acc);
+                    t0 = t1;
+                    t1 = t2;
+                }
+                erec = std::max(erec, std::fabs((double)acc - ref));
+            }
+            CHECK(ehorner <= std::max(erec, 2.5e-7 * vmax), "monomials: box %d %s: Horner error %.2e of %.2e (recurrence %.2e)", b,
+                  which ? "G" : "F", ehorner, vmax, erec);
+            if (b == 0) std::printf("near polynomial %s degree %d: float32 Horner %.2e, recurrence %.2e of max %.3g\n",
+                                    which ? "G" : "F", D, ehorner / vmax, erec / vmax, vmax);
+        }
+    }
+}
+
 int main() {
+    check_near_monomials();
     check_near_chunks();
     check_lane_nodes_and_addresses();
     check_fft_factors();
