@@ -685,27 +685,28 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near_mfma(NearArgs<float> a
         float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
         int tp = 0, hd = 0;
         constexpr int kMask = kNearCap - 1;
+        constexpr int kEval = 4;  // list entries evaluated per lane per round
         auto chunk = [&]() {
             const int cnt = (tp - hd) & kMask;
-            vec4<float> o[4], sh[4];
+            vec4<float> o[kEval], sh[kEval];
             const uint32_t dummy = (uint32_t)tb | (8u << kNearCodeShift);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kEval; ++u) {
                 const uint32_t e = (cnt > 0) ? hits[((hd + min(u, cnt - 1)) & kMask) * 64 + lane] : dummy;
                 o[u] = a.pos[e & ((1u << kNearCodeShift) - 1)];
                 sh[u] = shift[e >> kNearCodeShift];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < kEval; ++u)
                 if (u < cnt)
                     near_pair_nz<DEG>(a, tx - (o[u].x + sh[u].x), ty - (o[u].y + sh[u].y), tz - (o[u].z + sh[u].z),
                                       o[u].w, phi, gx, gy, gz);
-            hd = (hd + min(cnt, 4)) & kMask;
+            hd = (hd + min(cnt, kEval)) & kMask;
         };
         auto drain_ready = [&]() {
             while (true) {
                 const int cnt = (tp - hd) & kMask;
-                if (__ballot(act && cnt < 4) != 0 && __ballot(cnt > kNearCap - 1 - kNearMfmaRows) == 0) break;
+                if (__ballot(act && cnt < kEval) != 0 && __ballot(cnt > kNearCap - 1 - kNearMfmaRows) == 0) break;
                 chunk();
             }
         };
