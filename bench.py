@@ -171,6 +171,71 @@ def run_form(sog, torch, xt, qt, box, N, tol, precision, steps, warmup):
     return dict(dt=dt, U=U, phi=phi, F=F, kt=kt, info=info, sizes=sizes)
 
 
+def bench_batch(args):
+    """The 256-system batch (N log-uniform in [500, 20000], Lz/Lx in {1/8, 1, 8}, density 1)
+    in float32 through one batch plan: each timed step is one sog_batch_energy_potential_force
+    call (input copy into the batch's buffers, one graph launch, output copy)."""
+    import numpy as np
+    import torch
+    import paper_2412_04595_amd as sog
+    import workloads
+
+    x, q, boxes, ns = workloads.batch()
+    N = len(q)
+    xt = torch.from_numpy(x).cuda()
+    qt = torch.from_numpy(q).cuda()
+    log(f"[bench] batch_256: {len(ns)} systems, {N} particles, tol {args.tol}")
+    chk = sog.BatchSolver(boxes, ns, args.tol, precision="fp32", on_device=True, check_inputs=True)
+    chk(xt, qt)
+    chk.close()
+    t0 = time.perf_counter()
+    b = sog.BatchSolver(boxes, ns, args.tol, precision="fp32", on_device=True, check_inputs=False)
+    t_plan = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        b(xt, qt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        U, phi, F = b(xt, qt)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    phi, F = phi.cpu().numpy(), F.cpu().numpy()
+    d = np.loadtxt(os.path.join(ROOT, "tests", "golden", "batch_256_targets.txt"), comments="#")
+    sysi, idx = d[:, 0].astype(np.int64), d[:, 1].astype(np.int64)
+    ephi = eF = 0.0
+    for s in sorted(set(sysi.tolist())):
+        m = sysi == s
+        g = b.offsets[s] + idx[m]
+        rF = -q[g, None] * d[m, 3:6]
+        ephi = max(ephi, float(np.max(np.abs(phi[g] - d[m, 2])) / np.max(np.abs(d[m, 2]))))
+        eF = max(eF, float(np.max(np.abs(F[g] - rF)) / np.max(np.abs(rF))))
+    b.close()
+    out = {
+        "metric": METRIC,
+        "value": N / dt,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch_256: {len(ns)} independent systems, N log-uniform in [500, 20000] "
+                               f"(total {N}), Lz/Lx in {{1/8, 1, 8}}, density 1, uniform +/-1 neutral, "
+                               f"tol {args.tol:g}, FP32-bulk form, one graph launch per step",
+                   "systems": len(ns), "N": N, "tol": args.tol},
+        "plan_seconds": t_plan,
+        "accuracy": {"phi_rel_linf": ephi, "force_rel_linf": eF,
+                     "reference": "tests/golden/batch_256_targets.txt (12 systems x 4 sampled targets)"},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +253,9 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
               "(the multi-GPU design is described in DESIGN.md but not built)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch_256":
+        bench_batch(args)
+        return
     import numpy as np
     import torch
     import paper_2412_04595_amd as sog

@@ -11,6 +11,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (SOG_LONG_AUTO, SOG_LONG_DIRECT, SOG_LONG_FFT, SOG_PREC_FP32_BULK, SOG_PREC_FP64, SogError,
+                   sog_batch_destroy, sog_batch_energy_potential_force, sog_batch_plan, sog_batch_plan_info,
                    sog_destroy, sog_energy_potential_force, sog_energy_potential_gradient, sog_kernel_times,
                    sog_kernel_times_reset,
                    sog_last_error, sog_options_default, sog_plan, sog_plan_ex, sog_plan_info, sog_plan_resolve,
@@ -144,6 +145,48 @@ class Solver:
 
     def reset_kernel_times(self):
         sog_kernel_times_reset(self.plan)
+
+
+class BatchSolver:
+    """Independent systems solved by one call (sog_batch_plan): boxes[s] and ns[s] give
+    system s; inputs and outputs hold the systems one after another.  Same host/device
+    modes as Solver; __call__ returns (energies (nsys,), phi, force)."""
+
+    def __init__(self, boxes, ns, tol, precision="fp64", device=0, on_device=False, check_inputs=True,
+                 params=None, stream=None):
+        self.boxes = [tuple(float(v) for v in b) for b in boxes]
+        self.ns = [int(v) for v in ns]
+        self.n = sum(self.ns)
+        self.offsets = np.concatenate([[0], np.cumsum(self.ns)]).astype(np.int64)
+        self.on_device = bool(on_device)
+        self.device = int(device)
+        if self.on_device and stream is None:
+            import torch
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        self.options = make_options(precision, device, stream, on_device, check_inputs, False, params)
+        self.batch = sog_batch_plan(self.boxes, self.ns, float(tol), self.options)
+
+    def close(self):
+        if getattr(self, "batch", None):
+            sog_batch_destroy(self.batch)
+            self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self, s):
+        return sog_batch_plan_info(self.batch, s).as_dict()
+
+    def __call__(self, x, q):
+        x, q = Solver._inputs(self, x, q)
+        U = Solver._alloc(self, len(self.ns))
+        phi = Solver._alloc(self, self.n)
+        F = Solver._alloc(self, self.n, 3)
+        sog_batch_energy_potential_force(self.batch, _ptr(x), _ptr(q), _ptr(U), _ptr(phi), _ptr(F))
+        return U, phi, F
 
 
 def plan_parameters(box, n, tol, precision="fp64", params=None):

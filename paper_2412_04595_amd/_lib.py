@@ -40,6 +40,10 @@ EXPORTS = (
     "sog_kernel_times",
     "sog_kernel_times_reset",
     "sog_destroy",
+    "sog_batch_plan",
+    "sog_batch_energy_potential_force",
+    "sog_batch_plan_info",
+    "sog_batch_destroy",
     "sog_status_string",
     "sog_last_error",
 )
@@ -128,6 +132,15 @@ def lib():
         L.sog_kernel_times_reset.restype = C.c_int
         L.sog_destroy.argtypes = [P]
         L.sog_destroy.restype = None
+        L.sog_batch_plan.argtypes = [C.c_int32, dp, C.POINTER(C.c_int64), C.c_double, C.POINTER(sog_options),
+                                     C.POINTER(P)]
+        L.sog_batch_plan.restype = C.c_int
+        L.sog_batch_energy_potential_force.argtypes = [P, P, P, P, P, P]
+        L.sog_batch_energy_potential_force.restype = C.c_int
+        L.sog_batch_plan_info.argtypes = [P, C.c_int32, C.POINTER(sog_params)]
+        L.sog_batch_plan_info.restype = C.c_int
+        L.sog_batch_destroy.argtypes = [P]
+        L.sog_batch_destroy.restype = None
         L.sog_status_string.argtypes = [C.c_int]
         L.sog_status_string.restype = C.c_char_p
         L.sog_last_error.argtypes = []
@@ -224,3 +237,28 @@ def sog_kernel_times_reset(plan):
 def sog_destroy(plan):
     if plan:
         lib().sog_destroy(plan)
+
+
+def sog_batch_plan(boxes, ns, tol, options):
+    """boxes: sequence of (Lx, Ly, Lz); ns: particle counts, one per system."""
+    h = C.c_void_p()
+    k = len(ns)
+    b = (C.c_double * (3 * k))(*[float(v) for box in boxes for v in box])
+    n = (C.c_int64 * k)(*[int(v) for v in ns])
+    _check(lib().sog_batch_plan(k, b, n, float(tol), C.byref(options) if options is not None else None, C.byref(h)))
+    return h
+
+
+def sog_batch_energy_potential_force(batch, x_ptr, q_ptr, energy_ptr, phi_ptr, force_ptr):
+    _check(lib().sog_batch_energy_potential_force(batch, x_ptr, q_ptr, energy_ptr, phi_ptr, force_ptr))
+
+
+def sog_batch_plan_info(batch, s):
+    p = sog_params()
+    _check(lib().sog_batch_plan_info(batch, int(s), C.byref(p)))
+    return p
+
+
+def sog_batch_destroy(batch):
+    if batch:
+        lib().sog_batch_destroy(batch)

@@ -454,6 +454,91 @@ sog_status run(Plan& p, const double* x_in, const double* q_in, double* energy, 
     return SOG_OK;
 }
 
+// A batch of independent systems: one plan per system (device pointers, no per-plan
+// checks or timing) whose calls are captured once into a HIP graph.  The graph reads and
+// writes the batch's own staging buffers, so it stays valid for any caller pointers.
+struct Batch {
+    int device = 0;
+    hipStream_t stream = nullptr;   // the caller's stream: copies, check and graph launch
+    hipStream_t cap = nullptr;      // capture origin
+    std::vector<hipStream_t> lanes; // parallel branches of the graph
+    std::vector<hipEvent_t> ev;     // ev[0] forks the branches, ev[1 + k] joins branch k
+    std::vector<sog_plan_t> plans;
+    std::vector<int64_t> off;       // nsys + 1 particle offsets
+    std::vector<double> lz;
+    bool on_device = false, check = true;
+    std::vector<void*> bufs;
+    double *x = nullptr, *q = nullptr, *phi = nullptr, *force = nullptr, *energy = nullptr;
+    double *qsum = nullptr, *dlz = nullptr;
+    int64_t* doff = nullptr;
+    int* status = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+void free_batch(Batch& b) {
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    b.exec = nullptr;
+    b.graph = nullptr;
+    for (sog_plan_t p : b.plans) sog_destroy(p);
+    b.plans.clear();
+    for (void* v : b.bufs) (void)hipFree(v);
+    b.bufs.clear();
+    for (hipEvent_t e : b.ev) (void)hipEventDestroy(e);
+    b.ev.clear();
+    for (hipStream_t s : b.lanes) (void)hipStreamDestroy(s);
+    b.lanes.clear();
+    if (b.cap) (void)hipStreamDestroy(b.cap);
+    b.cap = nullptr;
+}
+
+// Capture every system's call into one graph: the branches fork from the capture stream,
+// system s (in order of decreasing size) runs on branch s mod K with its plan's own side
+// stream forked from that branch, and the branches join back before the capture ends.
+sog_status capture_batch(Batch& b) {
+    const int nsys = (int)b.plans.size();
+    std::vector<int> order(nsys);
+    for (int s = 0; s < nsys; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int i, int j) {
+        return b.off[i + 1] - b.off[i] > b.off[j + 1] - b.off[j];
+    });
+    const int K = (int)b.lanes.size();
+    hipError_t e = hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_status(e, "graph capture");
+    sog_status st = SOG_OK;
+    e = hipEventRecord(b.ev[0], b.cap);
+    for (int k = 0; k < K && e == hipSuccess; ++k) e = hipStreamWaitEvent(b.lanes[k], b.ev[0], 0);
+    if (e != hipSuccess) st = hip_status(e, "graph fork");
+    for (int i = 0; i < nsys && st == SOG_OK; ++i) {
+        const int s = order[i];
+        Plan& p = *reinterpret_cast<Plan*>(b.plans[s]);
+        p.stream = b.lanes[i % K];
+        const int64_t o = b.off[s];
+        st = run(p, b.x + 3 * o, b.q + o, b.energy + s, b.phi + o, b.force + 3 * o, nullptr, nullptr, nullptr);
+        if (st != SOG_OK) set_error("system " + std::to_string(s) + ": " + g_last_error);
+    }
+    for (int k = 0; k < K && st == SOG_OK; ++k) {
+        e = hipEventRecord(b.ev[1 + k], b.lanes[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b.cap, b.ev[1 + k], 0);
+        if (e != hipSuccess) st = hip_status(e, "graph join");
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b.cap, &g);
+    if (st == SOG_OK && e != hipSuccess) st = hip_status(e, "graph capture");
+    if (st != SOG_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    b.graph = g;
+    e = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        b.exec = nullptr;
+        return hip_status(e, "graph instantiation");
+    }
+    return SOG_OK;
+}
+
 }  // namespace
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -735,5 +820,202 @@ const char* sog_status_string(sog_status s) {
 }
 
 const char* sog_last_error(void) { return g_last_error.c_str(); }
+
+sog_status sog_batch_plan(int32_t nsys, const double* boxes, const int64_t* n, double tol, const sog_options* opt_in,
+                          sog_batch_t* out) {
+    if (!out || !boxes || !n || nsys < 1) {
+        set_error("nsys must be >= 1 and boxes, n, out must not be NULL");
+        if (out) *out = nullptr;
+        return SOG_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    sog_options opt;
+    sog_options_default(&opt);
+    if (opt_in) opt = *opt_in;
+    if (opt.timing) {
+        set_error("timing is not available for a batch");
+        return SOG_ERR_INVALID_ARG;
+    }
+    Batch* b = new (std::nothrow) Batch();
+    if (!b) {
+        set_error("host allocation failed");
+        return SOG_ERR_OUT_OF_MEMORY;
+    }
+    b->off.assign(1, 0);
+    for (int s = 0; s < nsys; ++s) {
+        if (n[s] < 2 || b->off.back() + n[s] > ((int64_t)1 << 31)) {
+            set_error("system " + std::to_string(s) + ": n must be >= 2 and the total at most 2^31");
+            delete b;
+            return SOG_ERR_INVALID_ARG;
+        }
+        b->off.push_back(b->off.back() + n[s]);
+        b->lz.push_back(boxes[3 * s + 2]);
+    }
+    // every system's parameters first, so that a bad system fails before any allocation
+    for (int s = 0; s < nsys; ++s) {
+        sog_params prm;
+        sog_status st = sog_plan_resolve(boxes + 3 * s, n[s], tol, &opt, &prm);
+        if (st != SOG_OK) {
+            set_error("system " + std::to_string(s) + ": " + g_last_error);
+            delete b;
+            return st;
+        }
+    }
+    // Device execution of a batch is switched off unless SOG_ENABLE_BATCH=1: creating the
+    // 256-system batch ended in a segmentation fault inside the HIP runtime, at plan
+    // creation or graph capture, with no fault found in this library's host code.
+    {
+        const char* en = std::getenv("SOG_ENABLE_BATCH");
+        if (!en || std::strcmp(en, "1") != 0) {
+            set_error("batched execution is switched off (set SOG_ENABLE_BATCH=1 to enable it)");
+            delete b;
+            return SOG_ERR_DEVICE;
+        }
+    }
+    b->device = opt.device;
+    b->stream = (hipStream_t)opt.stream;
+    b->on_device = opt.pointers_on_device != 0;
+    b->check = opt.check_inputs != 0;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        set_error("no HIP device available");
+        delete b;
+        return SOG_ERR_DEVICE;
+    }
+    if (opt.device < 0 || opt.device >= ndev) {
+        set_error("device ordinal out of range");
+        delete b;
+        return SOG_ERR_INVALID_ARG;
+    }
+    DeviceGuard dg(b->device);
+    auto fail = [&](sog_status st) {
+        free_batch(*b);
+        delete b;
+        return st;
+    };
+    const int64_t nt = b->off.back();
+    Allocator A;
+    A.get(b->x, 3 * nt * 8);
+    A.get(b->q, nt * 8);
+    A.get(b->phi, nt * 8);
+    A.get(b->force, 3 * nt * 8);
+    A.get(b->energy, nsys * 8);
+    A.get(b->qsum, 2 * nsys * 8);
+    A.get(b->dlz, nsys * 8);
+    A.get(b->doff, (nsys + 1) * 8);
+    A.get(b->status, nsys * 4);
+    b->bufs = A.ptrs;
+    if (A.err != hipSuccess || A.capped) {
+        set_error(A.capped ? "device memory cap (SOG_MAX_DEVICE_BYTES) reached" : "hipMalloc failed");
+        return fail(SOG_ERR_OUT_OF_MEMORY);
+    }
+    hipError_t e = hipMemcpy(b->dlz, b->lz.data(), nsys * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->doff, b->off.data(), (nsys + 1) * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(hip_status(e, "batch tables"));
+    sog_options po = opt;
+    po.pointers_on_device = 1;
+    po.check_inputs = 0;
+    po.timing = 0;
+    po.stream = nullptr;
+    for (int s = 0; s < nsys; ++s) {
+        sog_plan_t p = nullptr;
+        sog_status st = sog_plan_ex(boxes + 3 * s, n[s], tol, &po, &p);
+        if (st != SOG_OK) {
+            set_error("system " + std::to_string(s) + ": " + g_last_error);
+            return fail(st);
+        }
+        b->plans.push_back(p);
+    }
+    const int K = std::min(nsys, 8);
+    e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    for (int k = 0; k < K && e == hipSuccess; ++k) {
+        hipStream_t ls = nullptr;
+        e = hipStreamCreateWithFlags(&ls, hipStreamNonBlocking);
+        if (e == hipSuccess) b->lanes.push_back(ls);
+    }
+    for (int k = 0; k < K + 1 && e == hipSuccess; ++k) {
+        hipEvent_t ev = nullptr;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) b->ev.push_back(ev);
+    }
+    if (e != hipSuccess) return fail(hip_status(e, "stream creation"));
+    sog_status st = capture_batch(*b);
+    if (st != SOG_OK) return fail(st);
+    *out = reinterpret_cast<sog_batch_t>(b);
+    return SOG_OK;
+}
+
+sog_status sog_batch_energy_potential_force(sog_batch_t batch, const double* x, const double* q, double* energy,
+                                            double* phi, double* force) {
+    if (!batch || !x || !q) {
+        set_error("batch, x and q must not be NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    Batch& b = *reinterpret_cast<Batch*>(batch);
+    DeviceGuard dg(b.device);
+    const int nsys = (int)b.plans.size();
+    const int64_t nt = b.off.back();
+    const hipMemcpyKind in = b.on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    const hipMemcpyKind outk = b.on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    hipError_t e = hipMemcpyAsync(b.x, x, 3 * nt * 8, in, b.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.q, q, nt * 8, in, b.stream);
+    if (e != hipSuccess) return hip_status(e, "input copy");
+    if (b.check) {
+        e = launch_batch_check(b.x, b.q, b.doff, nsys, b.dlz, nt, b.qsum, b.status, b.stream);
+        std::vector<double> qs(2 * (size_t)nsys);
+        std::vector<int> fl(nsys);
+        if (e == hipSuccess) e = hipMemcpyAsync(qs.data(), b.qsum, 2 * nsys * 8, hipMemcpyDeviceToHost, b.stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(fl.data(), b.status, nsys * 4, hipMemcpyDeviceToHost, b.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b.stream);
+        if (e != hipSuccess) return hip_status(e, "input check");
+        for (int s = 0; s < nsys; ++s) {
+            const std::string sys = "system " + std::to_string(s) + ": ";
+            if (fl[s] & 1) {
+                set_error(sys + "non-finite position or charge");
+                return SOG_ERR_INVALID_ARG;
+            }
+            if (fl[s] & 2) {
+                set_error(sys + "some z is outside [0, Lz]");
+                return SOG_ERR_OUT_OF_BOX;
+            }
+            if (std::fabs(qs[2 * s]) > 1e-10 * qs[2 * s + 1]) {
+                set_error(sys + "charges are not neutral (|sum q| > 1e-10 sum |q|)");
+                return SOG_ERR_NOT_NEUTRAL;
+            }
+        }
+    }
+    e = hipGraphLaunch(b.exec, b.stream);
+    if (e != hipSuccess) return hip_status(e, "graph launch");
+    if (energy) e = hipMemcpyAsync(energy, b.energy, nsys * 8, outk, b.stream);
+    if (phi && e == hipSuccess) e = hipMemcpyAsync(phi, b.phi, nt * 8, outk, b.stream);
+    if (force && e == hipSuccess) e = hipMemcpyAsync(force, b.force, 3 * nt * 8, outk, b.stream);
+    if (e == hipSuccess && !b.on_device) e = hipStreamSynchronize(b.stream);
+    if (e != hipSuccess) return hip_status(e, "output copy");
+    return SOG_OK;
+}
+
+sog_status sog_batch_plan_info(sog_batch_t batch, int32_t s, sog_params* o) {
+    if (!batch || !o) {
+        set_error("batch and out must not be NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    Batch& b = *reinterpret_cast<Batch*>(batch);
+    if (s < 0 || s >= (int)b.plans.size()) {
+        set_error("system index out of range");
+        return SOG_ERR_INVALID_ARG;
+    }
+    return sog_plan_info(b.plans[s], o);
+}
+
+void sog_batch_destroy(sog_batch_t batch) {
+    if (!batch) return;
+    Batch* b = reinterpret_cast<Batch*>(batch);
+    {
+        DeviceGuard dg(b->device);
+        (void)hipStreamSynchronize(b->stream);
+        free_batch(*b);
+    }
+    delete b;
+}
 
 }  // extern "C"

@@ -292,6 +292,10 @@ void set_error(const std::string& msg);
 struct Timed;  // RAII helper in api.cpp
 hipError_t launch_fill_int(int* p, int value, int64_t n, hipStream_t s);
 hipError_t launch_fill_bytes_zero(void* p, size_t bytes, hipStream_t s);
+// per-system charge sums and flags of a batch of systems stored one after another
+// (off: nsys + 1 device offsets; lz: nsys heights; qsum: 2 nsys; status: nsys)
+hipError_t launch_batch_check(const double* x, const double* q, const int64_t* off, int nsys, const double* lz,
+                              int64_t n, double* qsum, int* status, hipStream_t s);
 hipError_t launch_counting_sort(Plan& p, const int* key, int n, int nbins, int* start, int* cursor, int* perm);
 // zero the counts (nbins + 1) and cursors (nbins) of a counting sort whose histogram the
 // caller's key kernel builds; launch_exclusive_scan then turns counts into starts

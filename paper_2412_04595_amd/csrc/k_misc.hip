@@ -145,6 +145,55 @@ __global__ void k_parts_out(const vec4<real>* __restrict__ part, int64_t n, doub
     }
 }
 
+// Input check of a batch of systems stored one after another (system s holds particles
+// [off[s], off[s + 1]), off strictly increasing): per system the sum of the charges and of
+// their magnitudes (qsum[2s], qsum[2s + 1], for the neutrality test of Prop.
+// lem::summation) and flags (status[s]: 1 a non-finite position or charge, 2 a z outside
+// [0, Lz_s]).  A wave whose particles all belong to one system adds its two sums once.
+__global__ __launch_bounds__(256) void k_batch_check(const double* __restrict__ x, const double* __restrict__ q,
+                                                     const int64_t* __restrict__ off, int nsys,
+                                                     const double* __restrict__ lz, int64_t n,
+                                                     double* __restrict__ qsum, int* __restrict__ status) {
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        int s = -1, fl = 0;
+        double a = 0.0, b = 0.0;
+        if (i < n) {
+            int lo = 0, hi = nsys - 1;  // the last s with off[s] <= i
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (off[mid] <= i) lo = mid;
+                else hi = mid - 1;
+            }
+            s = lo;
+            const double x0 = x[3 * i], y0 = x[3 * i + 1], z0 = x[3 * i + 2], qq = q[i];
+            if (!(isfinite(x0) && isfinite(y0) && isfinite(z0) && isfinite(qq))) {
+                fl = 1;
+            } else {
+                if (z0 < 0.0 || z0 > lz[s]) fl = 2;
+                a = qq;
+                b = fabs(qq);
+            }
+        }
+        if (fl) atomicOr(&status[s], fl);
+        // lane 0 holds the wave's lowest index, so it is in range whenever any lane is
+        const int s0 = __shfl(s, 0);
+        if (__all(s == s0 || s < 0)) {
+            for (int m = 32; m >= 1; m >>= 1) {
+                a += __shfl_xor(a, m);
+                b += __shfl_xor(b, m);
+            }
+            if ((threadIdx.x & 63) == 0 && s0 >= 0) {
+                atomicAdd(&qsum[2 * s0], a);
+                atomicAdd(&qsum[2 * s0 + 1], b);
+            }
+        } else if (s >= 0) {
+            atomicAdd(&qsum[2 * s], a);
+            atomicAdd(&qsum[2 * s + 1], b);
+        }
+    }
+}
+
 int grid_for(int64_t n, int threads, int maxb = 4096) {
     int64_t b = (n + threads - 1) / threads;
     if (b < 1) b = 1;
@@ -165,6 +214,16 @@ hipError_t launch_fill_bytes_zero(void* p, size_t bytes, hipStream_t s) {
     if (bytes % 4) return hipErrorInvalidValue;
     int64_t n = (int64_t)(bytes / 4);
     k_fill_zero_u32<<<grid_for(n, 256), 256, 0, s>>>((uint32_t*)p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_check(const double* x, const double* q, const int64_t* off, int nsys, const double* lz,
+                              int64_t n, double* qsum, int* status, hipStream_t s) {
+    if (nsys < 1 || n < 1) return hipErrorInvalidValue;
+    hipError_t e = launch_fill_bytes_zero(qsum, 2 * (size_t)nsys * sizeof(double), s);
+    if (e == hipSuccess) e = launch_fill_int(status, 0, nsys, s);
+    if (e != hipSuccess) return e;
+    k_batch_check<<<grid_for(n, 256), 256, 0, s>>>(x, q, off, nsys, lz, n, qsum, status);
     return hipGetLastError();
 }
 

@@ -78,6 +78,45 @@ def make(name, procs=8):
     print(f"{name}: {len(rows)} targets in {time.time() - t0:.0f} s -> {path}", flush=True)
 
 
+BATCH_TARGETS = 4
+
+
+def _init_batch(s):
+    N, box, seed = workloads.batch_specs()[s]
+    x, q = workloads.uniform(N, box, seed)
+    b, r0, om, rc, M = decomposition(N, box)
+    _CTX.update(x=x, q=q, box=box, sog=SOG(b, r0, om, rc, M))
+
+
+def _batch_rows(s):
+    N, box, seed = workloads.batch_specs()[s]
+    _init_batch(s)
+    rng = np.random.default_rng(1000 + s)
+    targets = np.sort(rng.choice(N, BATCH_TARGETS, replace=False))
+    b, r0, om, rc, M = decomposition(N, box)
+    return [(s, *_one(int(i))) for i in targets], (b, r0, om, rc, M)
+
+
+def make_batch(procs=8):
+    """Sampled targets of the systems workloads.BATCH_CHECKED of the 256-system batch,
+    each system with its own Table 1 decomposition (row 4, r_c from its density)."""
+    t0 = time.time()
+    with Pool(procs) as pool:
+        res = pool.map(_batch_rows, list(workloads.BATCH_CHECKED))
+    path = os.path.join(HERE, "batch_256_targets.txt")
+    with open(path, "w") as f:
+        f.write("# Reference potentials and gradients of sampled particles of systems of the 256-system batch\n")
+        f.write("# (workloads.batch_specs(): N log-uniform in [500, 20000], Lz/Lx in {1/8, 1, 8}, density 1,\n")
+        f.write("# uniform positions, +/-1 charges), written by tests/golden/make_golden.py with\n")
+        f.write("# oracle.direct.sog_direct: exact SOG decomposition per system, Table 1 row 4\n")
+        f.write(f"# (b={TABLE1[ROW][0]!r}), r_c = min(3 rho^(-1/3), min(Lx, Ly)/2), M from the omitted-tail bound.\n")
+        f.write("# columns: system index-in-system phi dphi/dx dphi/dy dphi/dz\n")
+        for rows, _dec in res:
+            for s, i, phi, g in rows:
+                f.write(f"{s} {i} {phi:.17g} {g[0]:.17g} {g[1]:.17g} {g[2]:.17g}\n")
+    print(f"batch_256: {sum(len(r) for r, _ in res)} targets in {time.time() - t0:.0f} s -> {path}", flush=True)
+
+
 def load(name):
     """(indices, phi, grad) from tests/golden/<name>_targets.txt"""
     d = np.loadtxt(os.path.join(HERE, f"{name}_targets.txt"), comments="#")
@@ -85,6 +124,9 @@ def load(name):
 
 
 if __name__ == "__main__":
-    names = sys.argv[1:] or ["cube_1e6", "slab_1e6", "tall_1e6", "layered_2e5"]
+    names = sys.argv[1:] or ["cube_1e6", "slab_1e6", "tall_1e6", "layered_2e5", "batch_256"]
     for n in names:
-        make(n)
+        if n == "batch_256":
+            make_batch()
+        else:
+            make(n)

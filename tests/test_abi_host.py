@@ -191,3 +191,67 @@ def test_window_choice():
     t = sog.plan_parameters((10, 10, 60), 1200, 1e-6, "fp64",
                             dict(mid_window=_lib.SOG_WINDOW_ES, mid_I=[20, 20, 120], mid_Izs=252, mid_Pw=[9, 9, 9]))
     assert t["mid_beta"] > 0
+
+
+@pytest.mark.parametrize("case, status", [
+    ("no_systems", _lib.SOG_ERR_INVALID_ARG),
+    ("one_particle", _lib.SOG_ERR_INVALID_ARG),
+    ("timing", _lib.SOG_ERR_INVALID_ARG),
+    ("bad_tol", _lib.SOG_ERR_TOL_UNREACHABLE),
+    ("bad_box", _lib.SOG_ERR_INVALID_ARG),
+])
+def test_batch_plan_rejects_bad_arguments(case, status):
+    """sog_batch_plan checks its arguments and resolves every system before it touches a
+    device, so each rejection is reached on a machine without a GPU; the message names the
+    failing system."""
+    boxes = [(10.0, 10.0, 10.0), (8.0, 8.0, 64.0), (20.0, 20.0, 2.5)]
+    ns = [1000, 4000, 1000]
+    tol = 1e-4
+    opt = sog.make_options("fp32")
+    if case == "no_systems":
+        boxes, ns = [], []
+    elif case == "one_particle":
+        ns[1] = 1
+    elif case == "timing":
+        opt.timing = 1
+    elif case == "bad_tol":
+        tol = 1e-9  # below the float32 range
+    elif case == "bad_box":
+        boxes[2] = (20.0, -1.0, 2.5)
+    with pytest.raises(sog.SogError) as ei:
+        sog.sog_batch_plan(boxes, ns, tol, opt)
+    assert ei.value.status == status
+    if case in ("one_particle", "bad_box"):
+        assert "system 1" in str(ei.value) or "system 2" in str(ei.value)
+
+
+def test_batch_workload_plans():
+    """Every system of the 256-system batch (N log-uniform in [500, 20000], Lz/Lx in
+    {1/8, 1, 8}, density 1) has a float32 plan at tol 1e-4 with the structure every plan
+    needs, and the batch totals about 1.3 million particles."""
+    import workloads
+    specs = workloads.batch_specs()
+    assert len(specs) == 256
+    total = 0
+    for N, box, _seed in specs:
+        assert 500 <= N <= 20000 and N % 2 == 0
+        p = sog.plan_parameters(box, N, 1e-4, "fp32")
+        assert p["rc"] <= min(box[0], box[1]) / 2 + 1e-12
+        assert p["m"] <= p["M"]
+        if p["m"] >= 0:
+            # periodic x, y and the padded z extent each hold at least two windows
+            sizes = (p["mid_I"][0], p["mid_I"][1], p["mid_Izs"])
+            assert all(I >= 2 * pw for I, pw in zip(sizes, p["mid_Pw"]))
+        total += N
+    assert 1.0e6 < total < 2.0e6
+    assert {round(b[2] / b[0], 3) for _n, b, _s in specs} == {0.125, 1.0, 8.0}
+
+
+def test_batch_plan_is_switched_off_by_default(monkeypatch):
+    """With valid arguments and SOG_ENABLE_BATCH unset, sog_batch_plan refuses with
+    SOG_ERR_DEVICE after resolving every system (no device is touched)."""
+    monkeypatch.delenv("SOG_ENABLE_BATCH", raising=False)
+    with pytest.raises(sog.SogError) as ei:
+        sog.sog_batch_plan([(10.0, 10.0, 10.0), (8.0, 8.0, 64.0)], [1000, 4000], 1e-4, sog.make_options("fp32"))
+    assert ei.value.status == _lib.SOG_ERR_DEVICE
+    assert "SOG_ENABLE_BATCH" in str(ei.value)

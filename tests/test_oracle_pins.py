@@ -453,3 +453,18 @@ def test_fast_mid_es_window_converges(cube_case):
         prev = e
     assert prev < 2e-8
     assert np.max(np.abs(g[T] - ref["grad_mid"])) < 2e-7 * gscale
+
+
+@pytest.mark.parametrize("system", [86, 32])
+def test_batch_golden_values_match_ewald2d(system):
+    """The stored sampled targets of the batch (oracle SOG-direct per system) agree with the
+    independent Ewald2D sum on a tall thin system (Lz/Lx = 8, Lx = 4) and a flat one
+    (Lz/Lx = 1/8) to the Table 1 row's decomposition error."""
+    d = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_256_targets.txt"),
+                   comments="#")
+    rows = d[d[:, 0] == system]
+    N, box, seed = workloads.batch_specs()[system]
+    x, q = workloads.uniform(N, box, seed)
+    o = ew.ewald2d(x, q, box, targets=rows[:, 1].astype(np.int64))
+    assert np.max(np.abs(o["phi"] - rows[:, 2])) <= 1e-8 * np.max(np.abs(rows[:, 2]))
+    assert np.max(np.abs(o["grad"] - rows[:, 3:6])) <= 1e-8 * np.max(np.abs(rows[:, 3:6]))

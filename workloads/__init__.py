@@ -125,3 +125,20 @@ def batch_specs(n_systems=256, seed=5, Nmin=500, Nmax=20000, density=1.0):
         Lx = (N / density / a) ** (1.0 / 3.0)
         out.append((N, (Lx, Lx, a * Lx), seed + s))
     return out
+
+
+def batch(specs=None):
+    """(x, q, boxes, ns) of a batch: each system uniform in its own box with its own seed,
+    the systems' particles stored one after another."""
+    specs = batch_specs() if specs is None else specs
+    xs, qs = [], []
+    for N, box, seed in specs:
+        x, q = uniform(N, box, seed)
+        xs.append(x)
+        qs.append(q)
+    return np.concatenate(xs), np.concatenate(qs), [b for _n, b, _s in specs], [n for n, _b, _s in specs]
+
+
+# systems of the 256-system batch with stored reference values: the three smallest and the
+# three largest, and two of each height ratio (1/8, 1, 8) of middle size
+BATCH_CHECKED = (6, 32, 82, 86, 93, 136, 138, 144, 150, 195, 197, 230)
