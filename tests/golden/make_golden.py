@@ -61,7 +61,8 @@ def make(name, procs=8):
     x, q, box = workloads.named(name)
     N = len(q)
     rng = np.random.default_rng(12345)
-    targets = np.sort(rng.choice(N, NTARGETS, replace=False))
+    # fewer targets for the 8-million cube: each costs about four minutes of one core
+    targets = np.sort(rng.choice(N, 8 if N > 4_000_000 else NTARGETS, replace=False))
     b, r0, om, rc, M = decomposition(N, box)
     t0 = time.time()
     with Pool(procs, initializer=_init, initargs=(name,)) as pool:

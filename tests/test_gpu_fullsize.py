@@ -53,8 +53,10 @@ def _sample_errors(name, phi, F, q):
 
 # slab_1e6 in FP64 runs the x pass with the multiplier table in global memory (12 mid-range
 # Gaussians x 672 points do not fit in LDS beside the lines)
+# cube_8e6 (8 million particles in 200^3, the same density) checks a size well above the
+# benchmark's: 560^2 x 552 grids, 8 sampled targets
 CASES = [("cube_1e6", "fp32"), ("cube_1e6", "fp64"), ("slab_1e6", "fp32"), ("slab_1e6", "fp64"), ("tall_1e6", "fp32"),
-         ("layered_2e5", "fp32"), ("layered_2e5", "fp64")]
+         ("layered_2e5", "fp32"), ("layered_2e5", "fp64"), ("cube_8e6", "fp32"), ("cube_8e6", "fp64")]
 
 
 @pytest.mark.parametrize("name,precision", CASES)

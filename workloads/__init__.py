@@ -33,8 +33,9 @@ NAMED = {
     "slab_1e6": (1_000_000, (400.0, 400.0, 25.0)),
     "tall_1e6": (1_000_000, (50.0, 50.0, 800.0)),
     "layered_2e5": (200_000, (150.0, 150.0, 60.0)),
+    "cube_8e6": (8_000_000, (200.0, 200.0, 200.0)),
 }
-NAMED_SEED = {"cube_small": 1, "cube_1e6": 2, "slab_1e6": 3, "tall_1e6": 4, "layered_2e5": 6}
+NAMED_SEED = {"cube_small": 1, "cube_1e6": 2, "slab_1e6": 3, "tall_1e6": 4, "layered_2e5": 6, "cube_8e6": 7}
 
 
 def _charges(rng, N):
