@@ -62,6 +62,15 @@ struct FFTFactors {
 // Longest line the LDS line transforms take (a batch holds at most this many elements):
 // 4608 complex in the float32 form, 2304 in float64.
 constexpr int fft_max_line(int prec) { return prec == SOG_PREC_FP64 ? 2304 : 4608; }
+// lines of length n that the line kernels transform per batch: a power of two, at most
+// 16, with n W <= fft_max_line
+inline int fft_lines_per_batch(int prec, int n) {
+    int W = 16;
+    while (W > 1 && (int64_t)n * W > fft_max_line(prec)) W >>= 1;
+    return W;
+}
+// dynamic LDS of one FFT line block at most (above 64 KiB, as the gridding's 80 KiB tiles)
+constexpr size_t kFFTLdsBudget = 98304;
 
 // LDS of the mid-range x pass (forward FFT along x, multiplier, inverse) with W lines per
 // block: the lines (complex), the x multipliers of the nl mid-range Gaussians and the

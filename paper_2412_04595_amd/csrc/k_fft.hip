@@ -307,9 +307,7 @@ __device__ void lds_fft(cpx<T>* A, const cpx<T>* __restrict__ twl, int W, int P,
 // lines per block: a power of two, n W <= kFFTCap, at most 16
 template <typename T>
 int lines_per_block(int n) {
-    int W = 16;
-    while (W > 1 && (size_t)n * W > (size_t)kFFTCap<T>) W >>= 1;
-    return W;
+    return fft_lines_per_batch(sizeof(T) == 8 ? SOG_PREC_FP64 : SOG_PREC_FP32_BULK, n);
 }
 
 // 1. real-to-complex along z for W lines per block.  m = I_z*/2 packed pairs per line;
@@ -566,7 +564,7 @@ hipError_t run_fft_mid(Plan& p) {
     const int Ix = r.I[0], Iy = r.I[1], Izs = r.Izs, Kz = Izs / 2 + 1, m = Izs / 2, Kzs = cgrid_stride(Izs);
     const int nlines = Ix * Iy;
     const size_t ce = sizeof(cpx<T>);
-    const size_t budget = 65536;
+    const size_t budget = kFFTLdsBudget;
     const int nl = r.m + 1;
     hipError_t e;
     if ((size_t)m > (size_t)kFFTCap<T> || (size_t)Ix > (size_t)kFFTCap<T> || (size_t)Iy > (size_t)kFFTCap<T>)

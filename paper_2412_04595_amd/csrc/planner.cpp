@@ -367,7 +367,12 @@ MidChoice plan_mid(const double L[3], int64_t n, double s0, double sm, int nl, d
             // gridding: each wave updates ceil(P_w / 4) x planes times ceil(P_w^2 / 64)
             // passes of 64 (y, z) nodes per particle; gathering: P_w^3 points per particle
             const double slots = (double)((Pw + 3) / 4) * ((Pw * Pw + 63) / 64);
-            c.cost = (double)n * (kCostSpreadSlot * slots + kCostGatherPt * Pw * Pw * Pw) + kCostFFTPt * Ng;
+            // the x and y passes move batches of W lines (W n <= the line kernels' element
+            // cap, W <= 16); below 8 lines a batch reads row segments of under 64 bytes, and
+            // the passes slow down (8e6-particle cube: the y pass 1.7x per point at W = 4)
+            const int wmin = std::min(fft_lines_per_batch(prec, c.I[0]), fft_lines_per_batch(prec, c.I[1]));
+            const double fft_pen = wmin >= 8 ? 1.0 : 1.0 + 0.5 * std::log2(8.0 / wmin);
+            c.cost = (double)n * (kCostSpreadSlot * slots + kCostGatherPt * Pw * Pw * Pw) + kCostFFTPt * Ng * fft_pen;
             c.ok = true;
             if (c.cost < best.cost) best = c;
         }

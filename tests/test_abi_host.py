@@ -255,3 +255,15 @@ def test_batch_plan_is_switched_off_by_default(monkeypatch):
         sog.sog_batch_plan([(10.0, 10.0, 10.0), (8.0, 8.0, 64.0)], [1000, 4000], 1e-4, sog.make_options("fp32"))
     assert ei.value.status == _lib.SOG_ERR_DEVICE
     assert "SOG_ENABLE_BATCH" in str(ei.value)
+
+
+@pytest.mark.parametrize("name, prec, cap", [("cube_8e6", "fp32", 4608), ("cube_1e6", "fp64", 2304),
+                                             ("cube_1e6", "fp32", 4608)])
+def test_planner_keeps_fft_batches_wide(name, prec, cap):
+    """The planner charges x/y line lengths that leave the FFT line kernels fewer than 8
+    lines per batch (short row segments): on the cubes it picks grids whose x and y lines
+    allow at least 8 (I <= cap / 8; the kernels batch n W <= cap elements)."""
+    import workloads
+    N, box = workloads.NAMED[name]
+    p = sog.plan_parameters(box, N, 1e-4, prec)
+    assert max(p["mid_I"][0], p["mid_I"][1]) * 8 <= cap
