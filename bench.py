@@ -185,7 +185,11 @@ def bench_batch(args):
     xt = torch.from_numpy(x).cuda()
     qt = torch.from_numpy(q).cuda()
     log(f"[bench] batch_256: {len(ns)} systems, {N} particles, tol {args.tol}")
-    chk = sog.BatchSolver(boxes, ns, args.tol, precision="fp32", on_device=True, check_inputs=True)
+    try:
+        chk = sog.BatchSolver(boxes, ns, args.tol, precision="fp32", on_device=True, check_inputs=True)
+    except sog.SogError as e:
+        print(f"bench.py: the batch cannot run: {e}", file=sys.stderr)
+        sys.exit(2)
     chk(xt, qt)
     chk.close()
     t0 = time.perf_counter()
