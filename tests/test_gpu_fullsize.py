@@ -26,7 +26,7 @@ def _golden(name):
     return d[:, 0].astype(np.int64), d[:, 1], d[:, 2:5]
 
 
-def _device_solve(name, precision, x=None, q=None):
+def _device_solve(name, precision, x=None, q=None, params=None):
     import torch
     import paper_2412_04595_amd as sog
     if x is None:
@@ -35,7 +35,7 @@ def _device_solve(name, precision, x=None, q=None):
         box = workloads.NAMED[name][1]
     xt = torch.from_numpy(x).cuda()
     qt = torch.from_numpy(q).cuda()
-    s = sog.Solver(box, len(q), TOL, precision=precision, on_device=True, check_inputs=True)
+    s = sog.Solver(box, len(q), TOL, precision=precision, on_device=True, check_inputs=True, params=params)
     U, phi, F = s(xt, qt)
     torch.cuda.synchronize()
     info = s.info()
@@ -51,8 +51,6 @@ def _sample_errors(name, phi, F, q):
     return ephi, eF
 
 
-# slab_1e6 in FP64 runs the x pass with the multiplier table in global memory (12 mid-range
-# Gaussians x 672 points do not fit in LDS beside the lines)
 # cube_8e6 (8 million particles in 200^3, the same density) checks a size well above the
 # benchmark's: 560^2 x 552 grids, 8 sampled targets
 CASES = [("cube_1e6", "fp32"), ("cube_1e6", "fp64"), ("slab_1e6", "fp32"), ("slab_1e6", "fp64"), ("tall_1e6", "fp32"),
@@ -71,6 +69,21 @@ def test_sampled_targets_meet_tolerance(name, precision):
     assert abs(U - 0.5 * float(q @ phi)) <= 1e-10 * float(np.sum(np.abs(q * phi)))
     Ftot = np.abs(F.sum(axis=0))
     assert np.all(Ftot <= TOL * np.sum(np.abs(F), axis=0))
+
+
+def test_x_pass_with_multipliers_in_global_memory():
+    """slab_1e6 in FP64 on a plan whose x lines (672 points, 12 mid-range Gaussians) leave no
+    room for the x multiplier table in LDS even at one line per block: the x pass reads the
+    table from global memory.  Sampled targets within the tolerance."""
+    name = "slab_1e6"
+    print(f"[gpu] {name} fp64, x multipliers in global memory", flush=True)
+    x, q, box = workloads.named(name)
+    params = dict(rc=4.365352892912549, set_m=1, m=11, mid_I=[672, 672, 42], mid_Izs=240, mid_Pw=[9, 9, 9])
+    U, phi, F, info = _device_solve(name, "fp64", x, q, params=params)
+    assert info["mid_I"] == [672, 672, 42] and info["m"] == 11
+    ephi, eF = _sample_errors(name, phi, F, q)
+    print(f"    phi {ephi:.2e} F {eF:.2e}", flush=True)
+    assert ephi < TOL and eF < TOL
 
 
 def test_fp32_bulk_matches_fp64_at_full_size():
