@@ -35,7 +35,8 @@ def log(*a):
 
 def kernel_models(info, sizes, N, box, rs):
     """Algorithmic work of one launch of the main kernels (flops, HBM bytes); rs is the
-    working precision's bytes per real.  The per-unit figures are stated in the design doc."""
+    working precision's bytes per real: per ordered near-field pair, per particle and window
+    point, and per grid point of each FFT pass, times the units one launch processes."""
     Pw = info["mid_Pw"][0]
     # the z planes the gridding, the z transforms and the gathering touch
     Nb = info["mid_I"][0] * info["mid_I"][1] * (sizes["mid_zband"][1] - sizes["mid_zband"][0])
@@ -254,8 +255,8 @@ def main():
                          "HBM counters of a profiling run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU design is described in DESIGN.md but not built)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the solver has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch_256":
         bench_batch(args)
