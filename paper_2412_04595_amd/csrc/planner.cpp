@@ -448,7 +448,13 @@ LongChoice plan_long(const double L[3], int64_t n, double sl, double eps, int pr
     if (f.Pw2 > 0 && f.Pw2 <= 15 && long_fft_tile(prec, f.Pw2, P) > 0) {
         for (int a = 0; a < 2; ++a)
             if (f.I2[a] < 2 * f.Pw2) f.I2[a] = next_smooth(2 * f.Pw2, true);
-        f.cost = kCostWindow2Pt * (double)n * f.Pw2 * f.Pw2 * P + kCostFFT2Pt * P * (double)f.I2[0] * f.I2[1];
+        // the 2D gridding and gathering run one workgroup per tile: with fewer tiles than
+        // about two per compute unit the GPU idles in proportion (a 24 x 24 grid is 4 tiles
+        // of 16, and the 10^6-particle slab took a second per call on it)
+        const int B2 = long_fft_tile(prec, f.Pw2, P);
+        const double nt2 = std::ceil((double)f.I2[0] / B2) * std::ceil((double)f.I2[1] / B2);
+        const double par = std::max(1.0, 512.0 / nt2);
+        f.cost = kCostWindow2Pt * (double)n * f.Pw2 * f.Pw2 * P * par + kCostFFT2Pt * P * (double)f.I2[0] * f.I2[1];
         f.ok = true;
     }
     if (ov.long_form == SOG_LONG_DIRECT) return d;

@@ -267,3 +267,13 @@ def test_planner_keeps_fft_batches_wide(name, prec, cap):
     N, box = workloads.NAMED[name]
     p = sog.plan_parameters(box, N, 1e-4, prec)
     assert max(p["mid_I"][0], p["mid_I"][1]) * 8 <= cap
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_planner_avoids_long_fft_grids_with_few_tiles(prec):
+    """The long range's FFT form grids one 2D tile per workgroup; the 10^6-particle slab's
+    24 x 24 long grid would be 4 tiles, so the planner takes the direct form there."""
+    import workloads
+    N, box = workloads.NAMED["slab_1e6"]
+    p = sog.plan_parameters(box, N, 1e-4, prec)
+    assert p["long_form"] == _lib.SOG_LONG_DIRECT
