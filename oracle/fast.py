@@ -50,6 +50,7 @@ Totals: Phi = Phi_N + Phi_mid + Phi_long - q_i sum_l w_l;  U = 1/2 sum q_i Phi_i
 F_i = -q_i grad Phi_i.
 """
 import math
+import time
 
 import numpy as np
 from scipy.spatial import cKDTree
@@ -167,38 +168,42 @@ def mid_range(xc, q, box, sog: SOG, m, mid):
     iy, Wy, dWy = wfun(xc[:, 1], -Ly / 2, hy, Iy, py, S, True)
     iz, Wz, dWz = wfun(xc[:, 2], -Lzs / 2, hz, Izs, pz, S, False)
     N = xc.shape[0]
-    # 1. gridding
+    # 1. gridding: S(g) = sum_j q_j W(g - r_j), added node by node (one scatter-add per
+    #    (x, y) window node, over all particles and their P_w z nodes)
     grid = np.zeros(Ix * Iy * Izs)
     for a in range(px):
         for b in range(py):
             lin_xy = (ix[:, a] * Iy + iy[:, b]) * Izs
             wxy = q * Wx[:, a] * Wy[:, b]
-            for c in range(pz):
-                grid += np.bincount(lin_xy + iz[:, c], weights=wxy * Wz[:, c], minlength=grid.size)
+            np.add.at(grid, (lin_xy[:, None] + iz).ravel(), (wxy[:, None] * Wz).ravel())
     grid = grid.reshape(Ix, Iy, Izs)
-    # 2.-4. FFT, scaling, inverse FFT
+    # 2.-4. FFT, scaling, inverse FFT.  S is real and the multiplier is real and even in
+    #    k, so the product's spectrum is Hermitian and the half spectrum (rfftn / irfftn)
+    #    holds all of it: u = ifftn(G/What^2 fftn(S)), which is real.
     kx = 2 * np.pi * np.fft.fftfreq(Ix, d=hx)
     ky = 2 * np.pi * np.fft.fftfreq(Iy, d=hy)
-    kz = 2 * np.pi * np.fft.fftfreq(Izs, d=hz)
-    k2 = kx[:, None, None] ** 2 + ky[None, :, None] ** 2 + kz[None, None, :] ** 2
-    G = np.zeros_like(k2)
+    kz = 2 * np.pi * np.fft.rfftfreq(Izs, d=hz)
+    G = np.zeros((Ix, Iy, kz.size))
     for ell in range(m + 1):
-        G += math.pi ** 1.5 * sog.w[ell] * sog.s[ell] ** 3 * np.exp(-sog.s[ell] ** 2 * k2 / 4.0)
+        # exp(-s^2 |k|^2 / 4) as the product of its three directional factors
+        s2 = sog.s[ell] ** 2
+        ex, ey, ez = (np.exp(-s2 * k * k / 4.0) for k in (kx, ky, kz))
+        G += math.pi ** 1.5 * sog.w[ell] * sog.s[ell] ** 3 * (ex[:, None, None] * ey[None, :, None] * ez[None, None, :])
     What2 = (hfun(kx, hx, px, S)[:, None, None] ** 2 * hfun(ky, hy, py, S)[None, :, None] ** 2
              * hfun(kz, hz, pz, S)[None, None, :] ** 2)
-    u = np.real(np.fft.ifftn(G / What2 * np.fft.fftn(grid))).ravel()
+    G /= What2
+    del What2
+    u = np.fft.irfftn(G * np.fft.rfftn(grid), s=(Ix, Iy, Izs), axes=(0, 1, 2)).ravel()
+    del G, grid
     # 5. gathering
     phi = np.zeros(N)
     grad = np.zeros((N, 3))
     for a in range(px):
         for b in range(py):
             lin_xy = (ix[:, a] * Iy + iy[:, b]) * Izs
-            acc0 = np.zeros(N)
-            acc1 = np.zeros(N)
-            for c in range(pz):
-                uu = u[lin_xy + iz[:, c]]
-                acc0 += Wz[:, c] * uu
-                acc1 += dWz[:, c] * uu
+            uu = u[lin_xy[:, None] + iz]  # (N, P_w): u on the particle's z nodes
+            acc0 = np.sum(Wz * uu, axis=1)
+            acc1 = np.sum(dWz * uu, axis=1)
             phi += Wx[:, a] * Wy[:, b] * acc0
             grad[:, 0] += dWx[:, a] * Wy[:, b] * acc0
             grad[:, 1] += Wx[:, a] * dWy[:, b] * acc0
@@ -335,7 +340,7 @@ def long_range_fft(xc, q, box, sog: SOG, m, lp):
 
 # ----------------------------------------------------------------------------- near field
 
-def near_field(xc, q, box, sog: SOG, chunk=1 << 20):
+def near_field(xc, q, box, sog: SOG, chunk=1 << 18):
     """eq. phiNDR over all pairs within r_c (xy periodic, z free); returns (phi, grad)."""
     Lx, Ly, Lz = box
     rc = sog.rc
@@ -372,10 +377,12 @@ def near_field(xc, q, box, sog: SOG, chunk=1 << 20):
 
 # ----------------------------------------------------------------------------- totals
 
-def solve(x, q, box, params, parts=False):
+def solve(x, q, box, params, parts=False, times=None):
     """Energy, potentials and forces by the fast SOG method with explicit parameters.
 
-    Returns dict(U, phi (N,), force (N,3), grad (N,3)) plus the per-part arrays when parts=True."""
+    Returns dict(U, phi (N,), force (N,3), grad (N,3)) plus the per-part arrays when parts=True.
+    If times is a dict, the wall-clock seconds of the three parts are stored in it under
+    "short", "mid" and "long" (the split of the paper's timing tables)."""
     box = tuple(float(v) for v in box)
     q = np.asarray(q, dtype=np.float64)
     xc = centered(x, box)
@@ -383,17 +390,23 @@ def solve(x, q, box, params, parts=False):
     sog = SOG(sp["b"], sp["r0"], sp["omega"], sp["rc"], sp["M"])
     m = params["m"]
     N = q.size
+    t = [time.perf_counter()]
     phi_n, g_n = near_field(xc, q, box, sog)
+    t.append(time.perf_counter())
     if m >= 0:
         phi_m, g_m = mid_range(xc, q, box, sog, m, params["mid"])
     else:
         phi_m, g_m = np.zeros(N), np.zeros((N, 3))
+    t.append(time.perf_counter())
     if m < sog.M:
         lp = params["long"]
         fn = long_range_direct if lp["form"] == "direct" else long_range_fft
         phi_l, g_l = fn(xc, q, box, sog, m, lp)
     else:
         phi_l, g_l = np.zeros(N), np.zeros((N, 3))
+    t.append(time.perf_counter())
+    if times is not None:
+        times.update(short=t[1] - t[0], mid=t[2] - t[1], long=t[3] - t[2])
     phi_self = q * sog.self_coeff()
     phi = phi_n + phi_m + phi_l - phi_self
     grad = g_n + g_m + g_l

@@ -48,12 +48,14 @@ def _window_error(Pw, h, s):
     return best
 
 
-def plan(box, N, tol, eta=0.5):
+def plan(box, N, tol, eta=0.5, rc=None):
+    """Parameters (a dict for fast.solve) for N particles in box at relative tolerance tol;
+    eta sets the range split, rc (default 3 rho^{-1/3}) the near-field cutoff."""
     Lx, Ly, Lz = (float(v) for v in box)
     eps = tol / 20.0
     b, r0, om = table_row_for_tol(tol)[:3]
     rho = N / (Lx * Ly * Lz)
-    rc = min(3.0 * rho ** (-1.0 / 3.0), 0.5 * min(Lx, Ly))
+    rc = min(3.0 * rho ** (-1.0 / 3.0) if rc is None else float(rc), 0.5 * min(Lx, Ly))
     sigma = rc / r0
     wl1 = math.sqrt(2 / math.pi) * math.log(b) / sigma
     rhs = 1e-2 * eps * Lx * Ly / (math.pi * N * Lz * Lz) * (1 - 1 / b) / wl1

@@ -7,7 +7,9 @@ r_c = 3 rho^{-1/3}, M from the omitted-tail bound; the values are therefore the
 potentials and gradients of the quasi-2D Coulomb sum itself to ~1e-9 relative.
 
 Usage: python tests/golden/make_golden.py [name ...]   (default: every workload)
-Output: tests/golden/<name>_targets.txt
+Output: tests/golden/<name>_targets.txt.  Also, by name: cube_small_ewald2d (Ewald2D on
+every particle of the 1000-particle cube) and <workload>_energy (the workload's energy from
+the plain fast method at two tolerances, tests/golden/<workload>_energy.txt).
 """
 import math
 import os
@@ -118,6 +120,81 @@ def make_batch(procs=8):
     print(f"batch_256: {sum(len(r) for r, _ in res)} targets in {time.time() - t0:.0f} s -> {path}", flush=True)
 
 
+def make_cube_small_ewald2d():
+    """Ewald2D (oracle.ewald2d, alpha-independent, pinned against brute-force image sums)
+    on every particle of the 1000-particle cube of Sec. 5.1 (20^3, seed 1): the energy
+    and each particle's potential and gradient."""
+    from oracle import ewald2d as ew
+    x, q, box = workloads.named("cube_small")
+    t0 = time.time()
+    o = ew.ewald2d(x, q, box)
+    U = ew.energy(q, o["phi"])
+    path = os.path.join(HERE, "cube_small_ewald2d.txt")
+    with open(path, "w") as f:
+        f.write("# Ewald2D potentials and gradients of every particle of workload cube_small\n")
+        f.write(f"# (N={len(q)}, box={box}, seed={workloads.NAMED_SEED['cube_small']}), written by\n")
+        f.write("# tests/golden/make_golden.py cube_small_ewald2d with oracle.ewald2d.ewald2d (default alpha).\n")
+        f.write(f"# U {U:.17g}\n")
+        f.write("# columns: index phi dphi/dx dphi/dy dphi/dz\n")
+        for i in range(len(q)):
+            g = o["grad"][i]
+            f.write(f"{i} {o['phi'][i]:.17g} {g[0]:.17g} {g[1]:.17g} {g[2]:.17g}\n")
+    print(f"cube_small_ewald2d: U={U!r} in {time.time() - t0:.0f} s -> {path}", flush=True)
+
+
+# The energy reference of a full-size workload: the plain fast method of oracle.fast at two
+# tolerances, with the oracle's own parameter choice.  The energy's relative error is the
+# potentials' error amplified by the cancellation in U = 1/2 sum q_i phi_i (|U| is ~40x
+# below sum |q_i phi_i| for uniform +/-1 charges), so the two runs must agree to 1e-7; the
+# tighter run is kept as the reference.
+ENERGY_TOLS = (1e-8, 1e-10)
+ENERGY_AGREE = 1e-7
+
+
+def make_energy(name):
+    from oracle import fast, planner
+    x, q, box = workloads.named(name)
+    N = len(q)
+    res = []
+    for tol in ENERGY_TOLS:
+        p = planner.plan(box, N, tol)
+        tm = {}
+        t0 = time.time()
+        o = fast.solve(x, q, box, p, times=tm)
+        res.append((tol, o["U"], time.time() - t0, tm, p))
+        print(f"{name}: tol {tol:g} U={o['U']!r} in {time.time() - t0:.0f} s {tm}", flush=True)
+        del o
+    (t1, U1, s1, _, p1), (t2, U2, s2, _, p2) = res
+    agree = abs(U1 - U2) / abs(U2)
+    if agree > ENERGY_AGREE:
+        raise SystemExit(f"{name}: the two oracle runs disagree by {agree:.2e} > {ENERGY_AGREE:g}; nothing written")
+    path = os.path.join(HERE, f"{name}_energy.txt")
+    with open(path, "w") as f:
+        f.write(f"# Reference energy of workload {name} (N={N}, box={box}, seed={workloads.NAMED_SEED[name]}),\n")
+        f.write(f"# written by tests/golden/make_golden.py {name}_energy: oracle.fast.solve with\n")
+        f.write("# oracle.planner.plan parameters at two tolerances; the tighter run is the reference.\n")
+        for tol, U, sec, tm, p in res:
+            f.write(f"# tol {tol:g}: U={U!r}, {sec:.0f} s (near {tm['short']:.0f}, mid {tm['mid']:.0f}, "
+                    f"long {tm['long']:.0f}); b={p['sog']['b']!r} r_c={p['sog']['rc']!r} M={p['sog']['M']} "
+                    f"m={p['m']} mid={p['mid']} long={p['long']}\n")
+        f.write(f"# relative difference of the two energies: {agree:.3e}\n")
+        f.write(f"U {U2:.17g}\n")
+        f.write(f"U_loose {U1:.17g}\n")
+    print(f"{name}_energy: U={U2!r} (agreement {agree:.2e}) -> {path}", flush=True)
+
+
+def load_energy(name):
+    """The reference energy from tests/golden/<name>_energy.txt, or None."""
+    path = os.path.join(HERE, f"{name}_energy.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        f = line.split()
+        if f and f[0] == "U":
+            return float(f[1])
+    return None
+
+
 def load(name):
     """(indices, phi, grad) from tests/golden/<name>_targets.txt"""
     d = np.loadtxt(os.path.join(HERE, f"{name}_targets.txt"), comments="#")
@@ -129,5 +206,9 @@ if __name__ == "__main__":
     for n in names:
         if n == "batch_256":
             make_batch()
+        elif n == "cube_small_ewald2d":
+            make_cube_small_ewald2d()
+        elif n.endswith("_energy"):
+            make_energy(n[: -len("_energy")])
         else:
             make(n)
