@@ -21,11 +21,14 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X peaks.  HBM3E 8 TB/s.  The kernels are built without packed-FP32 instructions,
-# so the FP32 vector peak this code can reach is one FMA per lane per clock:
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s (the published 157.3
-# counts packed FP32); FP64 vector 78.6 TFLOP/s.
-PEAK = {"hbm_GBs": 8000.0, "fp32_alu_TFs": 78.6, "fp64_alu_TFs": 78.6}
+# MI355X published peaks: HBM3E 8 TB/s; FP32 vector 157.3 TFLOP/s; FP64 vector 78.6 TFLOP/s.
+# The kernels are built without packed-FP32 instructions, so the FP32 rate they can reach
+# is one FMA per lane per clock, 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz =
+# 78.6 TFLOP/s; that figure is reported beside the published one (frac_nonpacked).
+PEAK = {"hbm_GBs": 8000.0, "fp32_alu_TFs": 157.3, "fp32_nonpacked_TFs": 78.6, "fp64_alu_TFs": 78.6}
+# algorithmic work per unit of the method: ~30 flops per ordered near-field pair within r_c
+# (distance, the kernel N(r) and N'(r)/r, accumulation of the potential and gradient)
+NEAR_FLOPS_PER_PAIR = 30
 METRIC = "particles/s energy+forces at 1e-4 rel err, N=1e6; FP32-bulk vs FP64 plain"
 
 
@@ -45,9 +48,8 @@ def kernel_models(info, sizes, N, box, rs):
     rho = N / (box[0] * box[1] * box[2])
     pairs = N * (4.0 * math.pi / 3.0) * rc ** 3 * rho   # ordered pairs within r_c (uniform density)
     m = {}
-    # near: per pair 6 flops per Chebyshev degree above 1 (recurrence + two series) and 30
-    # for distance, rsqrt and accumulation; bytes: the packed particle in, 4 results out
-    m["near"] = dict(flops=pairs * (6 * (deg - 1) + 30), bytes=N * (4 * rs + 4 + 4 * rs), bound="alu")
+    # near: per ordered pair within r_c; bytes: the packed particle in, 4 results out
+    m["near"] = dict(flops=pairs * NEAR_FLOPS_PER_PAIR, bytes=N * (4 * rs + 4 + 4 * rs), bound="alu")
     # spread: one FMA per window node; particle records in, grid read and written once
     m["mid_spread"] = dict(flops=N * 2 * Pw ** 3, bytes=N * (16 + 4 * rs) + 2 * Nb * rs, bound="alu")
     # gather: two FMAs per window node (value and z derivative) plus the y and x sums
@@ -69,7 +71,29 @@ def roofline_of(mdl, t_s, fp64=False):
         return dict(bound="hbm", achieved=ach, peak=PEAK["hbm_GBs"], unit="GB/s", frac=ach / PEAK["hbm_GBs"])
     pk = PEAK["fp64_alu_TFs"] if fp64 else PEAK["fp32_alu_TFs"]
     ach = mdl["flops"] / t_s / 1e12
-    return dict(bound="alu", achieved=ach, peak=pk, unit="TFLOP/s", frac=ach / pk)
+    out = dict(bound="alu", achieved=ach, peak=pk, unit="TFLOP/s", frac=ach / pk)
+    if not fp64:
+        out["frac_nonpacked"] = ach / PEAK["fp32_nonpacked_TFs"]
+    return out
+
+
+def spread_gather_hbm(info, sizes, N, per_launch, rs):
+    """The gridding + gathering pair against the HBM roof, with the algorithmic bytes of
+    the method: particle records in and out (16 B in, 16 B out in float32; 32 + 32 in
+    float64) plus one write and one read of every mid-range grid point.  Also given for
+    the z band of planes that windows can reach (the only planes the kernels touch)."""
+    if "mid_spread" not in per_launch or "mid_gather" not in per_launch:
+        return None
+    Ng = info["mid_I"][0] * info["mid_I"][1] * info["mid_Izs"]
+    t = (per_launch["mid_spread"] + per_launch["mid_gather"]) * 1e-3
+    Nb = info["mid_I"][0] * info["mid_I"][1] * (sizes["mid_zband"][1] - sizes["mid_zband"][0])
+    b_full = N * 8 * rs + 2 * Ng * rs
+    b_band = N * 8 * rs + 2 * Nb * rs
+    ach = b_full / t / 1e9
+    return dict(bound="hbm", achieved=ach, peak=PEAK["hbm_GBs"], unit="GB/s", frac=ach / PEAK["hbm_GBs"],
+                algorithmic_bytes=b_full, ms=t * 1e3, per_particle_bytes=b_full / N,
+                band=dict(achieved=b_band / t / 1e9, frac=b_band / t / 1e9 / PEAK["hbm_GBs"],
+                          algorithmic_bytes=b_band))
 
 
 def source_digest():
@@ -97,7 +121,20 @@ def traffic_from_profiles(kernel, workload):
     return None
 
 
-def accuracy(workload, phi, F, q):
+def reference_energy(workload):
+    """The oracle's energy of the workload (plain fast method at two tolerances that
+    agree), from tests/golden/<workload>_energy.txt, or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_energy.txt")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        f = line.split()
+        if f and f[0] == "U":
+            return float(f[1])
+    return None
+
+
+def accuracy(workload, U, phi, F, q):
     import numpy as np
     path = os.path.join(ROOT, "tests", "golden", f"{workload}_targets.txt")
     if not os.path.exists(path):
@@ -106,12 +143,17 @@ def accuracy(workload, phi, F, q):
     idx = d[:, 0].astype(np.int64)
     rphi, rgrad = d[:, 1], d[:, 2:5]
     rF = -q[idx, None] * rgrad
+    Uref = reference_energy(workload)
     return dict(
         n_targets=int(idx.size),
+        energy_rel=None if Uref is None else abs(U - Uref) / abs(Uref),
         phi_rel_linf=float(np.max(np.abs(phi[idx] - rphi)) / np.max(np.abs(rphi))),
+        phi_rel_rms=float(np.sqrt(np.mean((phi[idx] - rphi) ** 2) / np.mean(rphi ** 2))),
         force_rel_linf=float(np.max(np.abs(F[idx] - rF)) / np.max(np.abs(rF))),
         force_rel_rms=float(np.sqrt(np.mean(np.sum((F[idx] - rF) ** 2, 1)) / np.mean(np.sum(rF ** 2, 1)))),
-        reference="oracle SOG-direct (exact decomposition, b=1.2181), tests/golden",
+        reference="potentials and forces: oracle SOG-direct on sampled particles (exact decomposition, "
+                  "b=1.2181), tests/golden/<workload>_targets.txt; energy: oracle fast method at tol 1e-10, "
+                  "tests/golden/<workload>_energy.txt",
     )
 
 
@@ -131,23 +173,28 @@ def cpu_baseline(tol):
         box = (float(L),) * 3
         x, q = workloads.uniform(Ns, box, 2)
         p = planner.plan(box, Ns, tol)
+        tm = {}
         with threadpool_limits(limits=1):
             t0 = time.perf_counter()
-            fast.solve(x, q, box, p)
-            return Ns, time.perf_counter() - t0
+            fast.solve(x, q, box, p, times=tm)
+            return Ns, time.perf_counter() - t0, tm
 
     L = 30
-    Ns, t = timed(L)
+    Ns, t, tm = timed(L)
     note = ""
     if t < 10.0:
         first = f"; a first sample of {Ns} took {t:.1f} s"
         # oracle time grows about as N^1.3 here; even side: even N
         L = min(100, max(L + 2, 2 * int(round(L * (15.0 / t) ** (1.0 / 3.9) / 2))))
-        Ns, t = timed(L)
+        Ns, t, tm = timed(L)
         note = first
     return dict(value=Ns / t, unit="particles/s", cores=1, kind="oracle",
+                host_cpu_count=os.cpu_count(),
+                threads_used="1 (NumPy, SciPy FFT and BLAS limited to one thread)",
+                stages_s={"t_short": tm["short"], "t_mid": tm["mid"], "t_long": tm["long"]},
                 sample=f"oracle.fast.solve, N={Ns} uniform in {L}^3 (density 1 as the workload), tol {tol:g}, "
-                       f"oracle.planner parameters, 1 thread: {t:.1f} s{note}")
+                       f"oracle.planner parameters, 1 thread of {os.cpu_count()} host cores: {t:.1f} s "
+                       f"(near {tm['short']:.1f}, mid {tm['mid']:.1f}, long {tm['long']:.1f}){note}")
 
 
 def run_form(sog, torch, xt, qt, box, N, tol, precision, steps, warmup):
@@ -288,8 +335,8 @@ def main():
         del src, dst
     phi32 = r32["phi"].cpu().numpy()
     F32 = r32["F"].cpu().numpy()
-    acc32 = accuracy(args.workload, phi32, F32, q)
-    acc64 = accuracy(args.workload, r64["phi"].cpu().numpy(), r64["F"].cpu().numpy(), q) if r64 else None
+    acc32 = accuracy(args.workload, r32["U"], phi32, F32, q)
+    acc64 = accuracy(args.workload, r64["U"], r64["phi"].cpu().numpy(), r64["F"].cpu().numpy(), q) if r64 else None
 
     # roofline of the dominant kernel (FP32-bulk run), from the library's HIP events on
     # the plan's stream during the timed calls
@@ -340,6 +387,7 @@ def main():
         "speedup_fp32_vs_fp64": None if r64 is None else r64["dt"] / r32["dt"],
         "accuracy": acc32,
         "roofline": roof,
+        "spread_gather_hbm": spread_gather_hbm(r32["info"], r32["sizes"], N, per_launch, 4),
         "roofline_kernels": others,
         "cpu_baseline": cpu,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},

@@ -47,6 +47,24 @@ CASES = {
     # window 13 and odd-radix FFT lengths (3, 5, 7)
     "radix_mix": dict(N=900, box=(21.0, 15.0, 10.0), seed=14, row=4, rc=3.5, M=200, m=5,
                       mid=dict(I=(42, 30, 20), Izs=70, Pw=13), long=dict(form="direct", P=14, nk=(3, 2))),
+    # every other window width the gridding and gathering kernels are built for: 3, 5, 11
+    # and 15 points, Gaussian and ES (11 with ES is the planner's choice for the Sec. 5.1
+    # box at tol 1e-6)
+    "pw3": dict(N=800, box=(16.0, 16.0, 12.0), seed=31, row=3, rc=3.5, M=100, m=5,
+                mid=dict(I=(40, 40, 30), Izs=80, Pw=3), long=dict(form="direct", P=12, nk=(3, 3))),
+    "pw5_es": dict(N=800, box=(16.0, 16.0, 12.0), seed=32, row=3, rc=3.5, M=100, m=5,
+                   mid=dict(I=(40, 40, 30), Izs=80, Pw=5, window="es", beta=11.5),
+                   long=dict(form="direct", P=12, nk=(3, 3))),
+    "pw11": dict(N=1000, box=(20.0, 20.0, 20.0), seed=1, row=4, rc=6.0, M=166, m=8,
+                 mid=dict(I=(36, 36, 36), Izs=108, Pw=11), long=dict(form="direct", P=16, nk=(2, 2))),
+    "pw11_es": dict(N=1000, box=(20.0, 20.0, 20.0), seed=1, row=4, rc=6.0, M=166, m=8,
+                    mid=dict(I=(36, 36, 36), Izs=108, Pw=11, window="es", beta=22.0),
+                    long=dict(form="direct", P=16, nk=(2, 2))),
+    "pw15": dict(N=1200, box=(18.0, 22.0, 14.0), seed=33, row=4, rc=5.0, M=170, m=8,
+                 mid=dict(I=(40, 48, 30), Izs=96, Pw=15), long=dict(form="direct", P=16, nk=(2, 3))),
+    "pw15_es": dict(N=1200, box=(18.0, 22.0, 14.0), seed=34, row=4, rc=5.0, M=170, m=8,
+                    mid=dict(I=(40, 48, 30), Izs=96, Pw=15, window="es", beta=33.0),
+                    long=dict(form="direct", P=16, nk=(2, 3))),
 }
 
 
@@ -87,3 +105,23 @@ def oracle_params(c):
     if lp and lp["form"] == "fft":
         lp = dict(form="fft", P=lp["P"], I=tuple(lp["I"]), Pw=(lp["Pw"], lp["Pw"]), S=_window_S(lp["Pw"]))
     return fast.make_params(b, r0, om, c["rc"], c["M"], c["m"], mid=mid, long=lp)
+
+
+def oracle_params_from_info(info):
+    """The oracle's parameter dict for a plan the library resolved (sog_params as a dict):
+    the same decomposition, split, grids, windows and long-range form."""
+    from oracle import fast
+    mid = None
+    if info["m"] >= 0:
+        Pw = info["mid_Pw"][0]
+        mid = dict(I=tuple(info["mid_I"]), Izs=info["mid_Izs"], Pw=(Pw, Pw, Pw), S=info["mid_S"])
+        if info["mid_window"] == 2:
+            mid.update(window="es", beta=info["mid_beta"])
+    lp = None
+    if info["m"] < info["M"]:
+        if info["long_form"] == 1:
+            lp = dict(form="direct", P=info["long_P"], nk=tuple(info["long_nk"]))
+        else:
+            lp = dict(form="fft", P=info["long_P"], I=tuple(info["long_I"]), Pw=tuple(info["long_Pw"]),
+                      S=info["long_S"])
+    return fast.make_params(info["b"], info["r0"], info["omega"], info["rc"], info["M"], info["m"], mid=mid, long=lp)

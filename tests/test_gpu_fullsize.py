@@ -4,6 +4,9 @@ configuration the benchmark times (device pointers, torch's current stream).
 * sampled targets against tests/golden/<workload>_targets.txt (the oracle's exact SOG
   sum at a 7e-10 decomposition, written by tests/golden/make_golden.py): relative L-inf
   of the potential and of the force over the samples within the requested tolerance;
+* the energy against tests/golden/<workload>_energy.txt where it exists (the oracle's
+  plain fast method at tol 1e-10, confirmed by a second run at 1e-8): |dU|/|U| within
+  the tolerance;
 * properties that hold at any size: U = 1/2 sum q phi, the float32-bulk and float64
   forms agree within the tolerance, sum_i F_i is small against sum_i |F_i|, and a
   periodic shift of all x, y coordinates leaves the result unchanged within tol.
@@ -43,6 +46,13 @@ def _device_solve(name, precision, x=None, q=None, params=None):
     return U, phi.cpu().numpy(), F.cpu().numpy(), info
 
 
+def _energy(name):
+    path = os.path.join(HERE, "golden", f"{name}_energy.txt")
+    if not os.path.exists(path):
+        return None
+    return next(float(l.split()[1]) for l in open(path) if l.startswith("U "))
+
+
 def _sample_errors(name, phi, F, q):
     idx, rphi, rgrad = _golden(name)
     rF = -q[idx, None] * rgrad
@@ -63,9 +73,12 @@ def test_sampled_targets_meet_tolerance(name, precision):
     x, q, box = workloads.named(name)
     U, phi, F, info = _device_solve(name, precision, x, q)
     ephi, eF = _sample_errors(name, phi, F, q)
+    Uref = _energy(name)
+    eU = None if Uref is None else abs(U - Uref) / abs(Uref)
     print(f"    rc={info['rc']:.3f} m={info['m']} M={info['M']} I={info['mid_I']} Pw={info['mid_Pw'][0]} "
-          f"long={info['long_form']} P={info['long_P']}: phi {ephi:.2e} F {eF:.2e}", flush=True)
+          f"long={info['long_form']} P={info['long_P']}: phi {ephi:.2e} F {eF:.2e} U {eU}", flush=True)
     assert ephi < TOL and eF < TOL
+    assert eU is None or eU < TOL
     assert abs(U - 0.5 * float(q @ phi)) <= 1e-10 * float(np.sum(np.abs(q * phi)))
     Ftot = np.abs(F.sum(axis=0))
     assert np.all(Ftot <= TOL * np.sum(np.abs(F), axis=0))
