@@ -66,7 +66,8 @@ def make_params(b, r0, omega, rc, M, m, mid=None, long=None):
     mid: dict(I=(Ix,Iy,Iz), Izs=I_z*, Pw=(px,py,pz), S=shape) or None (m < 0); with
          window='es' and beta=beta the ES window replaces the Gaussian (S unused).
     long: dict(form='direct', P=P, nk=(nkx,nky)) or
-          dict(form='fft', P=P, I=(Ix,Iy), Pw=(px,py), S=shape) or None (m == M)."""
+          dict(form='fft', P=P, I=(Ix,Iy), Pw=(px,py), S=shape) or None (m == M); with
+          Q=Q > 0 the FFT form takes the Taylor acceleration of App. C."""
     return dict(sog=dict(b=b, r0=r0, omega=omega, rc=rc, M=M), m=m, mid=mid, long=long)
 
 
@@ -338,6 +339,119 @@ def long_range_fft(xc, q, box, sog: SOG, m, lp):
     return hx * hy * phi, hx * hy * grad
 
 
+# ----------------------------------------------------------------------------- App. C Taylor form
+
+def taylor_gaussian(z, s, Q):
+    """The Q-term Taylor polynomial of exp(-z^2/s^2) in -z^2/s^2 (Lemma lemma::Taylor):
+    sum_{p<Q} (1/p!) (-z^2/s^2)^p."""
+    x = -(np.asarray(z, dtype=np.float64) / s) ** 2
+    out = np.zeros_like(x)
+    term = np.ones_like(x)
+    for p in range(Q):
+        out += term
+        term = term * x / (p + 1)
+    return out
+
+
+def taylor_coefficients(k2, sog: SOG, m, Lz, Q):
+    """A_p(k) without the window factor: ((-1)^p/p!) sum_{l>m} w_l Lz^{2p} s_l^{2-2p}
+    exp(-s_l^2 |k|^2/4), p < Q (App. C, with |k|^2 in the exponent).  Returns (nk, Q).
+    At k = 0 the p = 0 term, the constant sum_l w_l s_l^2, is left out: it multiplies
+    sum_j q_j = 0 (the same reading as the exact kernel's expm1)."""
+    A = np.zeros((k2.size, Q))
+    for ell in range(m + 1, sog.M + 1):
+        s2 = sog.s[ell] ** 2
+        ek = np.exp(-s2 * k2 / 4.0)
+        for p in range(Q):
+            A[:, p] += ((-1) ** p / math.factorial(p)) * sog.w[ell] * Lz ** (2 * p) * s2 ** (1 - p) * ek
+    A[k2 == 0.0, 0] = 0.0
+    return A
+
+
+def long_range_fft_taylor(xc, q, box, sog: SOG, m, lp):
+    """FFT form of the long range with the Taylor acceleration of App. C, in the paper's
+    order (the steps replace steps 1-3 of Alg. al::long):
+      1. S^p(g, c) = sum_j q_j W2(g - r_j) ((z_c - z_j)/Lz)^{2p}, p < Q, on the x,y grid
+         times the Chebyshev nodes z_c;
+      2. 2D FFT of every (p, c);
+      3. Chebyshev interpolation in c: Stilde^p(k, n) = sum_c (2 - delta_n0)/P T_n(t_c) Shat^p(k, c);
+      4. Shat_scal(k, n) = sum_p A_p(k) / What2(k)^2 Stilde^p(k, n);
+      5. inverse 2D FFTs;
+      6. Phi_long_i = pi h_x h_y sum_g W2(r_i - g) sum_n T_n(2 z_i/Lz) u(g, n)
+         (pi: the prefactor of eq. trun2; the gradient in z from T_n').
+    Returns (phi, grad)."""
+    Lx, Ly, Lz = box
+    P, Q = lp["P"], lp["Q"]
+    Ix, Iy = lp["I"]
+    px, py = lp["Pw"]
+    S = lp["S"]
+    hx, hy = Lx / Ix, Ly / Iy
+    N = xc.shape[0]
+    ix, Wx, dWx = window_1d(xc[:, 0], -Lx / 2, hx, Ix, px, S, True)
+    iy, Wy, dWy = window_1d(xc[:, 1], -Ly / 2, hy, Iy, py, S, True)
+    zc = 0.5 * Lz * cheb_nodes(P)
+    # 1. gridding of the Taylor moments on R^2 x C
+    mom = ((zc[None, :] - xc[:, 2][:, None]) / Lz) ** 2  # (N, P)
+    grid = np.zeros((Q, P, Ix * Iy))
+    for a in range(px):
+        for b in range(py):
+            lin = ix[:, a] * Iy + iy[:, b]
+            wxy = q * Wx[:, a] * Wy[:, b]
+            powp = np.ones_like(mom)
+            for p in range(Q):
+                for c in range(P):
+                    grid[p, c] += np.bincount(lin, weights=wxy * powp[:, c], minlength=Ix * Iy)
+                powp = powp * mom
+    # 2. 2D FFTs
+    Ghat = np.fft.fft2(grid.reshape(Q, P, Ix, Iy), axes=(2, 3)).reshape(Q, P, -1)
+    # 3. Chebyshev interpolation: values at the nodes -> coefficients of T_n
+    tc = cheb_nodes(P)
+    Tc = np.ones((P, P))  # Tc[n, c] = T_n(t_c)
+    if P > 1:
+        Tc[1] = tc
+    for n in range(2, P):
+        Tc[n] = 2 * tc * Tc[n - 1] - Tc[n - 2]
+    coef = np.full(P, 2.0 / P)
+    coef[0] = 1.0 / P
+    Stil = np.einsum("nc,pck->pnk", coef[:, None] * Tc, Ghat)  # (Q, P_n, nk)
+    # 4. combination with A_p(k) / What2(k)^2
+    kx = 2 * np.pi * np.fft.fftfreq(Ix, d=hx)
+    ky = 2 * np.pi * np.fft.fftfreq(Iy, d=hy)
+    k2 = (kx[:, None] ** 2 + ky[None, :] ** 2).ravel()
+    A = taylor_coefficients(k2, sog, m, Lz, Q)  # (nk, Q)
+    What2 = (window_hat(kx, hx, px, S)[:, None] ** 2 * window_hat(ky, hy, py, S)[None, :] ** 2).ravel()
+    Sscal = np.einsum("kp,pnk->nk", A / What2[:, None], Stil)
+    # 5. inverse 2D FFTs
+    u = np.real(np.fft.ifft2(Sscal.reshape(P, Ix, Iy), axes=(1, 2))).reshape(P, -1)
+    # 6. gathering with T_n(2 z_i / Lz)
+    t = 2.0 * xc[:, 2] / Lz
+    T = np.ones((N, P))
+    dT = np.zeros((N, P))
+    U = np.ones((N, P))  # U_n, for T_n' = n U_{n-1}
+    if P > 1:
+        T[:, 1] = t
+        U[:, 1] = 2 * t
+        dT[:, 1] = 1.0
+    for n in range(2, P):
+        T[:, n] = 2 * t * T[:, n - 1] - T[:, n - 2]
+        U[:, n] = 2 * t * U[:, n - 1] - U[:, n - 2]
+        dT[:, n] = n * U[:, n - 1]
+    phi = np.zeros(N)
+    grad = np.zeros((N, 3))
+    for a in range(px):
+        for b in range(py):
+            lin = ix[:, a] * Iy + iy[:, b]
+            uu = u[:, lin].T  # (N, P)
+            acc0 = np.sum(T * uu, axis=1)
+            acc1 = np.sum(dT * uu, axis=1)
+            phi += Wx[:, a] * Wy[:, b] * acc0
+            grad[:, 0] += dWx[:, a] * Wy[:, b] * acc0
+            grad[:, 1] += Wx[:, a] * dWy[:, b] * acc0
+            grad[:, 2] += Wx[:, a] * Wy[:, b] * acc1 * (2.0 / Lz)
+    c = math.pi * hx * hy
+    return c * phi, c * grad
+
+
 # ----------------------------------------------------------------------------- near field
 
 def near_field(xc, q, box, sog: SOG, chunk=1 << 18):
@@ -400,7 +514,12 @@ def solve(x, q, box, params, parts=False, times=None):
     t.append(time.perf_counter())
     if m < sog.M:
         lp = params["long"]
-        fn = long_range_direct if lp["form"] == "direct" else long_range_fft
+        if lp["form"] == "direct":
+            fn = long_range_direct
+        elif lp.get("Q", 0) > 0:
+            fn = long_range_fft_taylor
+        else:
+            fn = long_range_fft
         phi_l, g_l = fn(xc, q, box, sog, m, lp)
     else:
         phi_l, g_l = np.zeros(N), np.zeros((N, 3))

@@ -468,3 +468,79 @@ def test_batch_golden_values_match_ewald2d(system):
     o = ew.ewald2d(x, q, box, targets=rows[:, 1].astype(np.int64))
     assert np.max(np.abs(o["phi"] - rows[:, 2])) <= 1e-8 * np.max(np.abs(rows[:, 2]))
     assert np.max(np.abs(o["grad"] - rows[:, 3:6])) <= 1e-8 * np.max(np.abs(rows[:, 3:6]))
+
+
+# ---------------------------------------------------------------- App. C Taylor form (strongly confined boxes)
+
+def test_taylor_series_matches_lemma_digits():
+    """Lemma lemma::Taylor: the Q-term series of exp(-z^2/s^2) with s = eta Lz errs by at
+    most 1/(Q! (2 eta)^{2Q}) on [-Lz/2, Lz/2], which is the printed number of digits for
+    eta = 1 (tests/golden/taylor_digits.txt).  On [-Lz, Lz] (the range of z - z_j, the
+    reading the algorithm needs) the bound is 1/(Q! eta^{2Q})."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "taylor_digits.txt"), comments="#")
+    Lz = 1.0
+    for eta, Q, dig in rows:
+        Q = int(Q)
+        s = eta * Lz
+        z = np.linspace(-Lz / 2, Lz / 2, 2001)
+        err = np.max(np.abs(np.exp(-(z / s) ** 2) - fast.taylor_gaussian(z, s, Q)))
+        # 4e-16: the float64 rounding of exp and of the series near 1
+        assert err <= 1.0 / (math.factorial(Q) * (2 * eta) ** (2 * Q)) + 4e-16
+        assert 10.0 ** (-dig - 1) < err + 1e-16 <= 10.0 ** (-dig + 0.5)
+        z2 = np.linspace(-Lz, Lz, 4001)
+        err2 = np.max(np.abs(np.exp(-(z2 / s) ** 2) - fast.taylor_gaussian(z2, s, Q)))
+        assert err2 <= 1.0 / (math.factorial(Q) * eta ** (2 * Q)) + 4e-16
+
+
+def test_taylor_coefficients_rebuild_the_exact_kernel():
+    """sum_p A_p(k) (dz/Lz)^{2p} is the z kernel pi^{-1} K(k; dz) of eq. trun2 (oracle
+    long_kernel, which sums the Gaussians themselves) once Q is large; at k = 0 both leave
+    out the constant that multiplies the total charge."""
+    b, r0, om = _table1_fixture()[3][:3]
+    sog = SOG(b, r0, om, 3.0, 120)
+    Lz = 0.3
+    k2 = np.array([0.0, 0.04, 0.9, 7.5])
+    zc = np.array([-0.15, 0.0, 0.11])
+    K = fast.long_kernel(k2, sog, -1, zc)  # (nk, 3, 3), pi included
+    A = fast.taylor_coefficients(k2, sog, -1, Lz, 9)
+    dz = (zc[:, None] - zc[None, :]) / Lz
+    KT = np.einsum("kp,pab->kab", A, np.stack([dz ** (2 * p) for p in range(9)]))
+    assert np.max(np.abs(math.pi * KT - K)) < 1e-12 * np.max(np.abs(K))
+    assert np.all(A[0, 0] == 0.0)
+
+
+@pytest.fixture(scope="module")
+def thin_case():
+    """The paper's strongly confined setting at N ~ 1000: surface density 1.1, Lz = 0.3
+    (Sec. 5.3 and App. E), every Gaussian long range (s_0 > eta Lz)."""
+    box = (30.0, 30.0, 0.3)
+    x, q = workloads.uniform(990, box, 41)
+    b, r0, om = _table1_fixture()[3][:3]
+    sog = SOG(b, r0, om, 3.0, 120)
+    T = np.arange(0, 990, 45)
+    ref = sog_direct(x, q, box, sog, -1, T)
+    return x, q, box, sog, T, ref
+
+
+def test_fast_long_taylor_converges_at_lemma_rate(thin_case):
+    """Fig. 5(c): the Taylor form's error falls with Q within the bound of Lemma
+    lemma::Taylor (read on [-Lz, Lz]: 1/(Q! eta^{2Q}), eta = s_0/Lz), down to the floor
+    the 2D grid and P set, where it agrees with the exact-kernel FFT form."""
+    x, q, box, sog, T, ref = thin_case
+    xc = fast.centered(x, box)
+    scale = np.max(np.abs(ref["phi"]))
+    lp = dict(form="fft", P=8, I=(96, 96), Pw=(15, 15), S=0.455 * math.pi * 15)
+    pe, ge = fast.long_range_fft(xc, q, box, sog, -1, lp)
+    floor = np.max(np.abs(pe[T] - ref["phi_long"])) / scale
+    assert floor < 5e-8
+    eta = sog.s[0] / box[2]
+    errs = []
+    for Q in (1, 2, 3, 4):
+        p, g = fast.long_range_fft_taylor(xc, q, box, sog, -1, dict(lp, Q=Q))
+        e = np.max(np.abs(p[T] - ref["phi_long"])) / scale
+        errs.append(e)
+        assert e <= 1.0 / (math.factorial(Q) * eta ** (2 * Q)) + 2 * floor
+    assert errs[0] > 10 * errs[1] > 100 * errs[2]
+    p, g = fast.long_range_fft_taylor(xc, q, box, sog, -1, dict(lp, Q=6))
+    assert np.max(np.abs(p - pe)) < 2e-8 * scale
+    assert np.max(np.abs(g[T] - ref["grad_long"])) < 1e-7 * np.max(np.abs(ref["grad"]))
