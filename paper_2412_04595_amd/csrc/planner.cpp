@@ -15,21 +15,66 @@
 
 namespace sog {
 
+// Gauss-Legendre rule of n points on [-1, 1]: the roots of P_n by Newton's method from
+// the Chebyshev-like initial guesses cos(pi (i + 3/4) / (n + 1/2)), weights
+// 2 / ((1 - x^2) P_n'(x)^2).  Cached per n.
+const std::vector<double>& gauss_legendre(int n) {
+    static std::mutex mu;
+    static std::map<int, std::vector<double>> cache;  // n nodes, then n weights
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(n);
+    if (it != cache.end()) return it->second;
+    std::vector<double> xw(2 * (size_t)n);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double x = std::cos(3.14159265358979323846 * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it2 = 0; it2 < 100; ++it2) {
+            double p0 = 1.0, p1 = x;  // P_0, P_1, then the three-term recurrence up to P_n
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p0 = 1.0; p1 = x; }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);  // P_n'(x)
+            const double dx = p1 / dp;
+            x -= dx;
+            if (std::fabs(dx) < 1e-16) break;
+        }
+        {
+            double p0 = 1.0, p1 = x;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (x * p1 - p0) / (x * x - 1.0);
+        }
+        const double w = 2.0 / ((1.0 - x * x) * dp * dp);
+        xw[i] = -x;
+        xw[n - 1 - i] = x;
+        xw[n + i] = w;
+        xw[2 * n - 1 - i] = w;
+    }
+    return cache.emplace(n, std::move(xw)).first->second;
+}
+
 // The ES window psi(d) = exp(beta (sqrt(1 - (d/a)^2) - 1)), |d| < a = P_w/2 (grid units).
 // Its transform by x = a sin(theta): 2 a int_0^{pi/2} exp(beta (cos theta - 1))
-// cos(kappa a sin theta) cos theta dtheta, a smooth integrand; composite Simpson with
-// enough panels for the oscillation.
+// cos(kappa a sin theta) cos theta dtheta, an entire function of theta; Gauss-Legendre on
+// [0, pi/2] with enough points for the oscillation converges geometrically (a composite
+// Simpson rule of 96 panels had left 2e-11 of the transform at P_w = 5).
 double es_hat_grid(double kappa, int Pw, double beta) {
     const double a = 0.5 * Pw;
-    const int n = 2 * (48 + (int)std::ceil(2.0 * std::fabs(kappa) * a));
-    const double dth = 0.5 * 3.14159265358979323846 / n;
+    const int n = 64 + (int)std::ceil(2.0 * std::fabs(kappa) * a);
+    const std::vector<double>& xw = gauss_legendre(n);
+    const double hp = 0.25 * 3.14159265358979323846;  // [0, pi/2] = hp (t + 1)
     double sum = 0;
-    for (int i = 0; i <= n; ++i) {
-        const double th = i * dth;
-        const double f = std::exp(beta * (std::cos(th) - 1.0)) * std::cos(kappa * a * std::sin(th)) * std::cos(th);
-        sum += f * ((i == 0 || i == n) ? 1.0 : ((i & 1) ? 4.0 : 2.0));
+    for (int i = 0; i < n; ++i) {
+        const double th = hp * (xw[i] + 1.0);
+        sum += xw[n + i] * std::exp(beta * (std::cos(th) - 1.0)) * std::cos(kappa * a * std::sin(th)) * std::cos(th);
     }
-    return 2.0 * a * sum * dth / 3.0;
+    return 2.0 * a * hp * sum;
 }
 
 namespace {
@@ -224,8 +269,8 @@ const std::vector<double>& es_ratio(int Pw, double beta) {
     std::lock_guard<std::mutex> lock(mu);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
-    // es_hat_grid's rule with the panels its largest argument (5 pi) needs, the theta
-    // nodes shared by every argument
+    // a composite Simpson rule in theta with the panels the largest argument (5 pi) needs,
+    // the nodes shared by every argument (an estimate: its accuracy is ample)
     const double a = 0.5 * Pw;
     const int nq = 2 * (48 + (int)std::ceil(2.0 * 5.0 * kPi * a));
     const double dth = 0.5 * kPi / nq;

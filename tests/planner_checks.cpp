@@ -15,7 +15,9 @@
 //  4. the z band: for z in [0, L_z] the nearest node is never clamped, so every window
 //     lies inside the band of planes the z transforms read and write;
 //  5. the near-field chunks of the float32 pair kernel fit their slots (below);
-//  6. the float32 near-field polynomials in monomial form (below).
+//  6. the float32 near-field polynomials in monomial form (below);
+//  7. the ES window transform (Gauss-Legendre) against a fine composite Simpson sum in x
+//     itself (no change of variable), and the Gauss-Legendre rule against exact moments.
 //
 // Prints one line per failure and "bad N"; exit status 0 when N == 0.
 #include <cmath>
@@ -257,7 +259,45 @@ static void check_near_monomials() {
     }
 }
 
+// 7. es_hat_grid: the transform of psi(d) = exp(beta (sqrt(1 - (d/a)^2) - 1)) on |d| < a.
+//    Reference: composite Simpson directly in d with 2e5 panels on [0, a) (the integrand's
+//    square-root edge limits it to ~1e-10 relative; below the parity gates, above rounding).
+//    The rule itself: n-point Gauss-Legendre integrates x^k exactly for k < 2n.
+static void check_es_transform() {
+    for (int n : {1, 2, 5, 64, 97}) {
+        const std::vector<double>& xw = gauss_legendre(n);
+        for (int k = 0; k < 2 * n && k < 40; ++k) {
+            double s = 0;
+            for (int i = 0; i < n; ++i) s += xw[n + i] * std::pow(xw[i], k);
+            const double exact = (k % 2) ? 0.0 : 2.0 / (k + 1);
+            CHECK(std::fabs(s - exact) < 1e-14, "gauss-legendre n %d moment %d: %.17g vs %.17g", n, k, s, exact);
+        }
+    }
+    double emax = 0;
+    for (int Pw : {3, 5, 9, 15})
+        for (double bf : {1.6, 2.3, 2.6})
+            for (double kappa : {0.0, 0.7, 2.0, 3.14159, 6.0, 12.0}) {
+                const double beta = bf * Pw, a = 0.5 * Pw;
+                const int np = 200000;
+                const double dd = a / np;
+                double s = 0;
+                for (int i = 0; i <= np; ++i) {
+                    const double d = i * dd;
+                    const double u = 1.0 - (d / a) * (d / a);
+                    const double f = std::exp(beta * (std::sqrt(u > 0 ? u : 0.0) - 1.0)) * std::cos(kappa * d);
+                    s += f * ((i == 0 || i == np) ? 1.0 : ((i & 1) ? 4.0 : 2.0));
+                }
+                const double ref = 2.0 * s * dd / 3.0;
+                const double g = es_hat_grid(kappa, Pw, beta);
+                const double e = std::fabs(g - ref) / es_hat_grid(0.0, Pw, beta);
+                emax = std::max(emax, e);
+                CHECK(e < 1e-9, "es transform Pw %d beta %g kappa %g: %.17g vs %.17g", Pw, beta, kappa, g, ref);
+            }
+    std::printf("es transform: max relative difference to the direct Simpson sum %.2e\n", emax);
+}
+
 int main() {
+    check_es_transform();
     check_near_monomials();
     check_near_chunks();
     check_lane_nodes_and_addresses();
