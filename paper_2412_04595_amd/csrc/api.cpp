@@ -96,41 +96,63 @@ double inv_what2_log(double k, double H, double S, double* pref) {
     return k * k * H * H / (2.0 * S);
 }
 
+// Point the plan's per-call buffers into a region of at least p.region_bytes bytes (or
+// clear them for nullptr).
+void bind_region(Plan& p, void* base) {
+    for (auto& sl : p.region_slots) *sl.first = base ? (void*)((char*)base + sl.second) : nullptr;
+}
+
+// Offsets of the per-call buffers (everything a call overwrites before it reads it) inside
+// one region, 256-byte aligned: the plan's own allocation, or any other region of at least
+// `total` bytes (bind_region).
+struct Layout {
+    std::vector<std::pair<void**, size_t>> slots;
+    size_t total = 0;
+    template <typename T>
+    void get(T*& field, size_t bytes) {
+        field = nullptr;
+        bytes = (std::max<size_t>(bytes, 16) + 255) & ~(size_t)255;
+        slots.push_back({reinterpret_cast<void**>(&field), total});
+        total += bytes;
+    }
+};
+
 sog_status build_plan(Plan& p) {
     Resolved& r = p.r;
     Workspace& ws = p.ws;
     const bool f64 = r.prec == SOG_PREC_FP64;
     const size_t rs = real_size(r), cs = 2 * rs;
     const int64_t n = r.n;
-    Allocator A;
+    Allocator A;  // tables, written once here
+    Layout W;     // per-call buffers
     if (!p.on_device) {
-        A.get(ws.x, 3 * n * 8);
-        A.get(ws.q, n * 8);
-        A.get(ws.phi, n * 8);
-        A.get(ws.force, 3 * n * 8);
-        A.get(ws.energy, 8);
+        W.get(ws.x, 3 * n * 8);
+        W.get(ws.q, n * 8);
+        W.get(ws.phi, n * 8);
+        W.get(ws.force, 3 * n * 8);
+        W.get(ws.energy, 8);
     }
-    A.get(ws.qsum, kQsumSlots * 2 * 8);
-    A.get(ws.status, 4);
-    A.get(ws.parts, 12 * n * rs);
-    A.get(ws.key, n * 8);  // near-field (cell, rank) pairs; the long-range FFT form's keys
-    A.get(ws.perm, n * 4);
+    W.get(ws.qsum, kQsumSlots * 2 * 8);
+    W.get(ws.status, 4);
+    W.get(ws.parts, 12 * n * rs);
+    W.get(ws.key, n * 8);  // near-field (cell, rank) pairs; the long-range FFT form's keys
+    W.get(ws.perm, n * 4);
     const int ncells = r.nc[0] * r.nc[1] * r.nc[2];
     int64_t maxbins = ncells;
-    A.get(ws.cell_start, (ncells + 1) * 4);
-    A.get(ws.near_orig, n * 4);
-    A.get(ws.near_pos, n * 4 * rs);
-    A.get(ws.near_units, ((size_t)near_unit_slots(r) * 16 + 127) / 128 * 128 + 8 * 128);  // units, then 8 work counters
+    W.get(ws.cell_start, (ncells + 1) * 4);
+    W.get(ws.near_orig, n * 4);
+    W.get(ws.near_pos, n * 4 * rs);
+    W.get(ws.near_units, ((size_t)near_unit_slots(r) * 16 + 127) / 128 * 128 + 8 * 128);  // units, then 8 work counters
     if (r.has_mid) {
         const int ntiles = r.ntile[0] * r.ntile[1] * r.ntile[2];
         maxbins = std::max<int64_t>(maxbins, (int64_t)ntiles * kMidSub);
         const int Kz = r.Izs / 2 + 1;
-        A.get(ws.tile_start, ((int64_t)ntiles * kMidSub + 1) * 4);
+        W.get(ws.tile_start, ((int64_t)ntiles * kMidSub + 1) * 4);
         A.get(ws.spread_nodes, 2 * 4 * 64);
-        A.get(ws.mid_g, n * 16);
-        A.get(ws.mid_u, n * 4 * rs);
-        A.get(ws.grid, (size_t)r.I[0] * r.I[1] * r.Izs * rs);
-        A.get(ws.cgrid, (size_t)r.I[0] * r.I[1] * cgrid_stride(r.Izs) * cs);
+        W.get(ws.mid_g, n * 16);
+        W.get(ws.mid_u, n * 4 * rs);
+        W.get(ws.grid, (size_t)r.I[0] * r.I[1] * r.Izs * rs);
+        W.get(ws.cgrid, (size_t)r.I[0] * r.I[1] * cgrid_stride(r.Izs) * cs);
         A.get(ws.tw_x, r.I[0] * cs);
         A.get(ws.tw_y, r.I[1] * cs);
         A.get(ws.tw_z, (r.Izs / 2) * cs);
@@ -144,35 +166,39 @@ sog_status build_plan(Plan& p) {
         if (r.form == SOG_LONG_DIRECT) {
             ws.long_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 1023) / 1024));
             A.get(ws.long_kt, (size_t)r.nh * r.P * r.P * 8);
-            A.get(ws.long_mu, (size_t)ws.long_blocks * r.nh * r.P * 16);
-            A.get(ws.long_a, (size_t)r.nh * r.P * cs);
+            W.get(ws.long_mu, (size_t)ws.long_blocks * r.nh * r.P * 16);
+            W.get(ws.long_a, (size_t)r.nh * r.P * cs);
         } else {
             const int nt2 = r.ntile2[0] * r.ntile2[1];
             maxbins = std::max<int64_t>(maxbins, nt2);
-            A.get(ws.l2_tile_start, (nt2 + 1) * 4);
-            A.get(ws.l2_tile_cursor, nt2 * 4);
-            A.get(ws.l2_dup_start, (nt2 + 1) * 4);
-            A.get(ws.l2_dup_cursor, nt2 * 4);
-            A.get(ws.l2_dup_list, (size_t)n * r.max_dup2 * 4);
-            A.get(ws.l2_g, n * 16);
-            A.get(ws.l2_u, n * 4 * rs);
-            A.get(ws.l2_grid, (size_t)r.P * r.I2[0] * r.I2[1] * cs);
+            W.get(ws.l2_tile_start, (nt2 + 1) * 4);
+            W.get(ws.l2_tile_cursor, nt2 * 4);
+            W.get(ws.l2_dup_start, (nt2 + 1) * 4);
+            W.get(ws.l2_dup_cursor, nt2 * 4);
+            W.get(ws.l2_dup_list, (size_t)n * r.max_dup2 * 4);
+            W.get(ws.l2_g, n * 16);
+            W.get(ws.l2_u, n * 4 * rs);
+            W.get(ws.l2_grid, (size_t)r.P * r.I2[0] * r.I2[1] * cs);
             A.get(ws.l2_tw_x, r.I2[0] * cs);
             A.get(ws.l2_tw_y, r.I2[1] * cs);
             A.get(ws.l2_kt_r, (size_t)(r.I2[0] / 2 + 1) * (r.I2[1] / 2 + 1) * r.P * r.P * rs);
         }
     }
-    A.get(ws.scan_tmp, ((maxbins + 1) / 1024 + 2) * 4);
+    W.get(ws.scan_tmp, ((maxbins + 1) / 1024 + 2) * 4);
     if (r.has_mid) {
-        A.get(ws.key2, n * 8);  // mid-range (tile, rank) pairs
-        A.get(ws.scan_tmp2, ((maxbins + 1) / 1024 + 2) * 4);
+        W.get(ws.key2, n * 8);  // mid-range (tile, rank) pairs
+        W.get(ws.scan_tmp2, ((maxbins + 1) / 1024 + 2) * 4);
     }
     ws.red_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256));
-    A.get(ws.red, ws.red_blocks * 8);
+    W.get(ws.red, ws.red_blocks * 8);
+    p.region_slots = W.slots;
+    p.region_bytes = W.total;
+    if (!p.static_region) A.get(p.region, W.total);
     ws.bytes = A.total;
     auto release = [&]() {
         for (void* q : A.ptrs) (void)hipFree(q);
         ws = Workspace();
+        p.region = nullptr;
     };
     if (A.capped) {
         release();
@@ -184,6 +210,7 @@ sog_status build_plan(Plan& p) {
         release();
         return s;
     }
+    bind_region(p, p.region);
     // tables (float64 on the host)
     hipError_t e = hipSuccess;
     if (r.has_mid) {
@@ -285,15 +312,13 @@ sog_status build_plan(Plan& p) {
 
 void free_plan(Plan& p) {
     Workspace& ws = p.ws;
-    void* ptrs[] = {ws.x, ws.q, ws.phi, ws.force, ws.energy, ws.qsum, ws.status, ws.parts,
-                    ws.key, ws.perm, ws.scan_tmp, ws.key2, ws.scan_tmp2, ws.cell_start, ws.near_orig, ws.near_units,
-                    ws.near_pos, ws.tile_start, ws.spread_nodes, ws.mid_g,
-                    ws.mid_u, ws.grid, ws.cgrid, ws.tw_x, ws.tw_y, ws.tw_z, ws.tw_zpost, ws.mult_ax, ws.mult_ay,
-                    ws.mult_az, ws.mult_c, ws.long_modes, ws.long_kt, ws.long_mu, ws.long_a, ws.l2_tile_start,
-                    ws.l2_tile_cursor, ws.l2_dup_start, ws.l2_dup_cursor, ws.l2_dup_list, ws.l2_g, ws.l2_u,
-                    ws.l2_grid, ws.l2_tw_x, ws.l2_tw_y, ws.l2_kt, ws.l2_kt_r, ws.red};
+    // the tables (the per-call buffers live in p.region)
+    void* ptrs[] = {ws.spread_nodes, ws.tw_x, ws.tw_y, ws.tw_z, ws.tw_zpost, ws.mult_ax, ws.mult_ay,
+                    ws.mult_az, ws.mult_c, ws.long_modes, ws.long_kt, ws.l2_tw_x, ws.l2_tw_y, ws.l2_kt, ws.l2_kt_r,
+                    p.region};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
+    p.region = nullptr;
     ws = Workspace();
     for (hipEvent_t ev : p.ev_pool) (void)hipEventDestroy(ev);
     if (p.ev_fork) (void)hipEventDestroy(p.ev_fork);
@@ -646,30 +671,29 @@ sog_status sog_plan_ex(const double box[3], int64_t n, double tol, const sog_opt
     return SOG_OK;
 }
 
-sog_status sog_energy_potential_force(sog_plan_t plan, const double* x, const double* q, double* energy,
-                                      double* phi, double* force) {
+static sog_status own_region_plan(sog_plan_t plan) {
     if (!plan) {
         set_error("plan is NULL");
         return SOG_ERR_INVALID_ARG;
     }
+    return SOG_OK;
+}
+
+sog_status sog_energy_potential_force(sog_plan_t plan, const double* x, const double* q, double* energy,
+                                      double* phi, double* force) {
+    if (sog_status st = own_region_plan(plan)) return st;
     return run(*reinterpret_cast<Plan*>(plan), x, q, energy, phi, force, nullptr, nullptr, nullptr);
 }
 
 sog_status sog_energy_potential_gradient(sog_plan_t plan, const double* x, const double* q, double* energy,
                                          double* phi, double* grad) {
-    if (!plan) {
-        set_error("plan is NULL");
-        return SOG_ERR_INVALID_ARG;
-    }
+    if (sog_status st = own_region_plan(plan)) return st;
     return run(*reinterpret_cast<Plan*>(plan), x, q, energy, phi, nullptr, grad, nullptr, nullptr);
 }
 
 sog_status sog_potential_parts(sog_plan_t plan, const double* x, const double* q, double* phi_parts,
                                double* grad_parts) {
-    if (!plan) {
-        set_error("plan is NULL");
-        return SOG_ERR_INVALID_ARG;
-    }
+    if (sog_status st = own_region_plan(plan)) return st;
     if (!phi_parts && !grad_parts) {
         set_error("phi_parts and grad_parts are both NULL");
         return SOG_ERR_INVALID_ARG;

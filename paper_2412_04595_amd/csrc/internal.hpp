@@ -263,7 +263,7 @@ struct Workspace {
     // energy reduction
     double* red = nullptr;
     int red_blocks = 0;
-    size_t bytes = 0;
+    size_t bytes = 0;  // device bytes the plan holds: tables and its per-call region
 };
 
 struct Plan {
@@ -279,6 +279,12 @@ struct Plan {
     bool timing = false;
     FFTFactors fx, fy, fz;          // mid-range FFT lengths I_x, I_y, I_z*/2
     FFTFactors f2x, f2y;            // long-range FFT form
+    // per-call buffers: one region of region_bytes (offsets in region_slots) that the plan
+    // allocates, unless static_region (then every call binds a region of its own)
+    void* region = nullptr;
+    size_t region_bytes = 0;
+    bool static_region = false;
+    std::vector<std::pair<void**, size_t>> region_slots;
     std::vector<KernelTimer> timers;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
