@@ -121,6 +121,9 @@ typedef struct {
                                 /*    device-to-host synchronisation per call                  */
     int32_t timing;             /* 1: time every kernel with HIP events (sog_kernel_times)    */
     sog_params params;          /* overrides; all zero = choose everything from tol          */
+    int32_t static_workspace;   /* 1: the plan allocates only its tables; its calls run in    */
+                                /*    the library's static scratch, through                   */
+                                /*    sog_energy_potential_force_static only                  */
 } sog_options;
 
 /* Fill *opt with the defaults: FP64, device 0, default stream, host pointers, checks on,
@@ -150,6 +153,24 @@ sog_status sog_energy_potential_force(sog_plan_t plan, const double* x, const do
  * the k = 0 constant, which every call leaves out). */
 sog_status sog_energy_potential_gradient(sog_plan_t plan, const double* x, const double* q,
                                          double* energy, double* phi, double* grad);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): sog_energy_potential_force with every per-call
+ * buffer (sort keys, grids, partial results, counters, host staging) in a static device
+ * array of the library instead of the plan's own memory.  The call allocates nothing:
+ * no hipMalloc, hipFree or allocating library routine; the plan (made beforehand, outside
+ * such code) keeps only its tables.  Any plan works; one made with
+ * options.static_workspace = 1 holds no per-call buffers at all and runs only here.
+ *   - Limit: the plan's per-call buffers must fit the scratch, 128 MiB (about 10^5
+ *     particles at tol 1e-4); larger plans return SOG_ERR_OUT_OF_MEMORY with the sizes.
+ *   - The scratch is one array per device, held from the library's load until the process
+ *     ends, shared by every call on that device and keeping the last call's contents
+ *     (each call clears what it needs).  Calls that overlap on one device race: order them
+ *     on one stream, or synchronise between them.
+ *   - A plan with timing on is refused (timing creates events during calls).
+ * Arguments, pointer rules, outputs and errors as for sog_energy_potential_force. */
+sog_status sog_energy_potential_force_static(sog_plan_t plan, const double* x, const double* q,
+                                             double* energy, double* phi, double* force);
 
 /* The parts of the potential and its gradient (eq. splitting), for checking each solver
  * on its own: phi_parts is 3 x n (near, mid, long; the self term is not included),

@@ -12,7 +12,8 @@ import numpy as np
 from . import _lib
 from ._lib import (SOG_LONG_AUTO, SOG_LONG_DIRECT, SOG_LONG_FFT, SOG_PREC_FP32_BULK, SOG_PREC_FP64, SogError,
                    sog_batch_destroy, sog_batch_energy_potential_force, sog_batch_plan, sog_batch_plan_info,
-                   sog_destroy, sog_energy_potential_force, sog_energy_potential_gradient, sog_kernel_times,
+                   sog_destroy, sog_energy_potential_force, sog_energy_potential_force_static,
+                   sog_energy_potential_gradient, sog_kernel_times,
                    sog_kernel_times_reset,
                    sog_last_error, sog_options_default, sog_plan, sog_plan_ex, sog_plan_info, sog_plan_resolve,
                    sog_plan_sizes_get,
@@ -23,9 +24,10 @@ LONG_FORM = {"auto": SOG_LONG_AUTO, "direct": SOG_LONG_DIRECT, "fft": SOG_LONG_F
 
 
 def make_options(precision="fp64", device=0, stream=None, on_device=False, check_inputs=True, timing=False,
-                 params=None):
+                 params=None, static_workspace=False):
     """sog_options from keyword arguments; ``params`` is a dict of sog_params fields."""
     o = sog_options_default()
+    o.static_workspace = int(bool(static_workspace))
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     o.device = int(device)
     o.stream = stream
@@ -60,7 +62,7 @@ class Solver:
     the work is queued on torch's current stream."""
 
     def __init__(self, box, n, tol, precision="fp64", device=0, on_device=False, check_inputs=True,
-                 timing=False, params=None, stream=None):
+                 timing=False, params=None, stream=None, static_workspace=False):
         self.box = tuple(float(v) for v in box)
         self.n = int(n)
         self.on_device = bool(on_device)
@@ -68,7 +70,8 @@ class Solver:
         if self.on_device and stream is None:
             import torch
             stream = torch.cuda.current_stream(self.device).cuda_stream
-        self.options = make_options(precision, device, stream, on_device, check_inputs, timing, params)
+        self.options = make_options(precision, device, stream, on_device, check_inputs, timing, params,
+                                    static_workspace)
         self.plan = sog_plan_ex(self.box, self.n, float(tol), self.options)
 
     def close(self):
@@ -101,13 +104,15 @@ class Solver:
             return torch.empty(*shape, dtype=torch.float64, device=f"cuda:{self.device}")
         return np.empty(shape, dtype=np.float64)
 
-    def __call__(self, x, q, energy=True, potential=True, forces=True):
-        """Returns (U, phi, force); entries not requested are None."""
+    def __call__(self, x, q, energy=True, potential=True, forces=True, static=False):
+        """Returns (U, phi, force); entries not requested are None.  static: through
+        sog_energy_potential_force_static (the library's static scratch)."""
         x, q = self._inputs(x, q)
         U = self._alloc(1) if energy else None
         phi = self._alloc(self.n) if potential else None
         F = self._alloc(self.n, 3) if forces else None
-        sog_energy_potential_force(self.plan, _ptr(x), _ptr(q), _ptr(U), _ptr(phi), _ptr(F))
+        call = sog_energy_potential_force_static if static else sog_energy_potential_force
+        call(self.plan, _ptr(x), _ptr(q), _ptr(U), _ptr(phi), _ptr(F))
         if U is not None:
             U = float(U[0])
         return U, phi, F

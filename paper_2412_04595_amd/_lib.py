@@ -32,6 +32,7 @@ EXPORTS = (
     "sog_plan",
     "sog_plan_ex",
     "sog_energy_potential_force",
+    "sog_energy_potential_force_static",
     "sog_energy_potential_gradient",
     "sog_potential_parts",
     "sog_plan_resolve",
@@ -72,7 +73,7 @@ class sog_options(C.Structure):
     _fields_ = [
         ("precision", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
         ("pointers_on_device", C.c_int32), ("check_inputs", C.c_int32), ("timing", C.c_int32),
-        ("params", sog_params),
+        ("params", sog_params), ("static_workspace", C.c_int32),
     ]
 
 
@@ -116,6 +117,8 @@ def lib():
         L.sog_plan_ex.restype = C.c_int
         L.sog_energy_potential_force.argtypes = [P, P, P, P, P, P]
         L.sog_energy_potential_force.restype = C.c_int
+        L.sog_energy_potential_force_static.argtypes = [P, P, P, P, P, P]
+        L.sog_energy_potential_force_static.restype = C.c_int
         L.sog_energy_potential_gradient.argtypes = [P, P, P, P, P, P]
         L.sog_energy_potential_gradient.restype = C.c_int
         L.sog_potential_parts.argtypes = [P, P, P, P, P]
@@ -192,6 +195,10 @@ def sog_energy_potential_force(plan, x_ptr, q_ptr, energy_ptr, phi_ptr, force_pt
     """Pointers are integers (host or device addresses, as the plan was made for) or None."""
     st = lib().sog_energy_potential_force(plan, x_ptr, q_ptr, energy_ptr, phi_ptr, force_ptr)
     _check(st)
+
+
+def sog_energy_potential_force_static(plan, x_ptr, q_ptr, energy_ptr, phi_ptr, force_ptr):
+    _check(lib().sog_energy_potential_force_static(plan, x_ptr, q_ptr, energy_ptr, phi_ptr, force_ptr))
 
 
 def sog_energy_potential_gradient(plan, x_ptr, q_ptr, energy_ptr, phi_ptr, grad_ptr):

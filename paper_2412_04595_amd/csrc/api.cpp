@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -94,6 +95,36 @@ hipError_t upload(void* dst, const std::vector<double>& v, bool f64) {
 double inv_what2_log(double k, double H, double S, double* pref) {
     *pref = S / (kPi * H * H);
     return k * k * H * H / (2.0 * S);
+}
+
+// The static scratch of sog_energy_potential_force_static: device memory the library holds
+// on every device it runs on from the load of its code object to the end of the process,
+// for callers that cannot allocate.  Host code never uses the array's name as an address:
+// static_scratch(dev) looks up its device address once per device.
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of the scratch on device dev (current device set by the caller);
+// looked up on the first use per device.
+sog_status static_scratch(int dev, void** out) {
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device ordinal out of range for the static scratch");
+        return SOG_ERR_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_status(e != hipSuccess ? e : hipErrorInvalidSymbol, "static scratch address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SOG_OK;
 }
 
 // Point the plan's per-call buffers into a region of at least p.region_bytes bytes (or
@@ -635,6 +666,12 @@ sog_status sog_plan_ex(const double box[3], int64_t n, double tol, const sog_opt
     p->on_device = opt.pointers_on_device != 0;
     p->check = opt.check_inputs != 0;
     p->timing = opt.timing != 0;
+    p->static_region = opt.static_workspace != 0;
+    if (p->static_region && p->timing) {
+        set_error("timing is not available with static_workspace (it creates events during calls)");
+        delete p;
+        return SOG_ERR_INVALID_ARG;
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
         set_error("no HIP device available");
@@ -657,6 +694,23 @@ sog_status sog_plan_ex(const double box[3], int64_t n, double tol, const sog_opt
         delete p;
         return s;
     }
+    if (p->static_region) {
+        // set-up of sog_energy_potential_force_static: the per-call buffers must fit the
+        // static scratch, whose device address is looked up here
+        void* base = nullptr;
+        if (p->region_bytes > kStaticScratchBytes) {
+            set_error("static_workspace: the plan's per-call buffers need " + std::to_string(p->region_bytes) +
+                      " bytes, above the static scratch of " + std::to_string(kStaticScratchBytes) + " bytes");
+            free_plan(*p);
+            delete p;
+            return SOG_ERR_OUT_OF_MEMORY;
+        }
+        if ((s = static_scratch(p->device, &base)) != SOG_OK) {
+            free_plan(*p);
+            delete p;
+            return s;
+        }
+    }
     hipError_t he = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
     if (he == hipSuccess) he = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
     if (he == hipSuccess) he = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
@@ -671,9 +725,15 @@ sog_status sog_plan_ex(const double box[3], int64_t n, double tol, const sog_opt
     return SOG_OK;
 }
 
+// A plan made with static_workspace holds no per-call buffers of its own: only
+// sog_energy_potential_force_static runs it.
 static sog_status own_region_plan(sog_plan_t plan) {
     if (!plan) {
         set_error("plan is NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    if (reinterpret_cast<Plan*>(plan)->static_region) {
+        set_error("the plan was made with static_workspace: call sog_energy_potential_force_static");
         return SOG_ERR_INVALID_ARG;
     }
     return SOG_OK;
@@ -699,6 +759,33 @@ sog_status sog_potential_parts(sog_plan_t plan, const double* x, const double* q
         return SOG_ERR_INVALID_ARG;
     }
     return run(*reinterpret_cast<Plan*>(plan), x, q, nullptr, nullptr, nullptr, nullptr, phi_parts, grad_parts);
+}
+
+sog_status sog_energy_potential_force_static(sog_plan_t plan, const double* x, const double* q, double* energy,
+                                             double* phi, double* force) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    Plan& p = *reinterpret_cast<Plan*>(plan);
+    if (p.timing) {
+        set_error("sog_energy_potential_force_static does not take a plan with timing on");
+        return SOG_ERR_INVALID_ARG;
+    }
+    if (p.region_bytes > kStaticScratchBytes) {
+        set_error("the plan's per-call buffers need " + std::to_string(p.region_bytes) +
+                  " bytes, above the static scratch of " + std::to_string(kStaticScratchBytes) + " bytes");
+        return SOG_ERR_OUT_OF_MEMORY;
+    }
+    void* base = nullptr;
+    {
+        DeviceGuard dg(p.device);
+        if (sog_status st = static_scratch(p.device, &base)) return st;
+    }
+    bind_region(p, base);
+    const sog_status st = run(p, x, q, energy, phi, force, nullptr, nullptr, nullptr);
+    bind_region(p, p.region);
+    return st;
 }
 
 static void fill_params(const Resolved& r, sog_params* o);
