@@ -110,6 +110,10 @@ typedef struct {
     /* mid-range window (sog_window) and the ES shape beta (0: chosen)                 */
     int32_t mid_window;
     double mid_beta;
+    /* FFT form of the long range: the z kernel in App. C's Taylor form with long_Q    */
+    /* terms (Lemma lemma::Taylor; 2 long_Q - 1 source planes), or -1: the exact       */
+    /* kernel interpolated at the Chebyshev nodes (long_P source planes); 0: chosen.   */
+    int32_t long_Q;
 } sog_params;
 
 typedef struct {

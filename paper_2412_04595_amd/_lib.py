@@ -58,7 +58,7 @@ class sog_params(C.Structure):
         ("mid_I", C.c_int32 * 3), ("mid_Izs", C.c_int32), ("mid_Pw", C.c_int32 * 3), ("mid_S", C.c_double),
         ("long_form", C.c_int32), ("long_P", C.c_int32), ("long_nk", C.c_int32 * 2),
         ("long_I", C.c_int32 * 2), ("long_Pw", C.c_int32 * 2), ("long_S", C.c_double),
-        ("mid_window", C.c_int32), ("mid_beta", C.c_double),
+        ("mid_window", C.c_int32), ("mid_beta", C.c_double), ("long_Q", C.c_int32),
     ]
 
     def as_dict(self):

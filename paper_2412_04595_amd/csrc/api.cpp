@@ -201,18 +201,27 @@ sog_status build_plan(Plan& p) {
             W.get(ws.long_a, (size_t)r.nh * r.P * cs);
         } else {
             const int nt2 = r.ntile2[0] * r.ntile2[1];
-            maxbins = std::max<int64_t>(maxbins, nt2);
+            const int planes = std::max(r.P, r.Ps);
+            const int Ky = r.I2[1] / 2 + 1;
+            maxbins = std::max<int64_t>(maxbins, nt2 + 1);
             W.get(ws.l2_tile_start, (nt2 + 1) * 4);
             W.get(ws.l2_tile_cursor, nt2 * 4);
-            W.get(ws.l2_dup_start, (nt2 + 1) * 4);
-            W.get(ws.l2_dup_cursor, nt2 * 4);
-            W.get(ws.l2_dup_list, (size_t)n * r.max_dup2 * 4);
             W.get(ws.l2_g, n * 16);
             W.get(ws.l2_u, n * 4 * rs);
-            W.get(ws.l2_grid, (size_t)r.P * r.I2[0] * r.I2[1] * cs);
+            W.get(ws.l2_grid, (size_t)planes * r.I2[0] * r.I2[1] * rs);
+            W.get(ws.l2_cgrid, (size_t)planes * r.I2[0] * cgrid_stride(r.I2[1]) * cs);
             A.get(ws.l2_tw_x, r.I2[0] * cs);
-            A.get(ws.l2_tw_y, r.I2[1] * cs);
-            A.get(ws.l2_kt_r, (size_t)(r.I2[0] / 2 + 1) * (r.I2[1] / 2 + 1) * r.P * r.P * rs);
+            A.get(ws.l2_tw_y, (r.I2[1] / 2) * cs);
+            A.get(ws.l2_tw_ypost, Ky * cs);
+            if (r.Q > 0) {
+                A.get(ws.l2_el, (size_t)(r.M - r.m) * rs);
+                A.get(ws.l2_coef, (size_t)(r.M - r.m) * r.Q * rs);
+                A.get(ws.l2_bp, (size_t)r.Q * r.P * r.Ps * rs);
+                A.get(ws.l2_winv_x, r.I2[0] * rs);
+                A.get(ws.l2_winv_y, Ky * rs);
+            } else {
+                A.get(ws.l2_kt_r, (size_t)(r.I2[0] / 2 + 1) * Ky * r.P * r.Ps * rs);
+            }
         }
     }
     W.get(ws.scan_tmp, ((maxbins + 1) / 1024 + 2) * 4);
@@ -309,28 +318,86 @@ sog_status build_plan(Plan& p) {
             long_kernel_cheb_basis(r, k2.data(), r.nh, kt.data());
             if (e == hipSuccess) e = hipMemcpy(ws.long_kt, kt.data(), kt.size() * 8, hipMemcpyHostToDevice);
         } else {
-            if (!factor_fft(r.I2[0], p.f2x) || !factor_fft(r.I2[1], p.f2y)) {
+            if (!factor_fft(r.I2[0], p.f2x) || !factor_fft(r.I2[1] / 2, p.f2y)) {
                 release();
                 set_error("long-range FFT length is not 2,3,5,7-smooth");
                 return SOG_ERR_INVALID_ARG;
             }
+            const int Ky = r.I2[1] / 2 + 1;
             if (e == hipSuccess) e = upload(ws.l2_tw_x, twiddles(r.I2[0], r.I2[0]), f64);
-            if (e == hipSuccess) e = upload(ws.l2_tw_y, twiddles(r.I2[1], r.I2[1]), f64);
-            const int jx = r.I2[0] / 2 + 1, jy = r.I2[1] / 2 + 1;
-            std::vector<double> k2((size_t)jx * jy), scale((size_t)jx * jy);
-            for (int a = 0; a < jx; ++a)
-                for (int b = 0; b < jy; ++b) {
-                    double kx = 2.0 * kPi * a / r.L[0], ky = 2.0 * kPi * b / r.L[1];
-                    k2[(size_t)a * jy + b] = kx * kx + ky * ky;
-                    double px, py;
-                    double ex = inv_what2_log(kx, r.H2[0], r.S2, &px) + inv_what2_log(ky, r.H2[1], r.S2, &py);
-                    scale[(size_t)a * jy + b] = px * py * std::exp(std::min(ex, 80.0)) / ((double)r.I2[0] * r.I2[1]);
+            if (e == hipSuccess) e = upload(ws.l2_tw_y, twiddles(r.I2[1] / 2, r.I2[1] / 2), f64);
+            if (e == hipSuccess) e = upload(ws.l2_tw_ypost, twiddles(r.I2[1], Ky), f64);
+            const double norm = 1.0 / ((double)r.I2[0] * r.I2[1]);
+            // 1 / What2(k)^2 per direction (Gaussian window, eq. GS)
+            auto winv = [&](int d, int cnt) {
+                std::vector<double> v(cnt);
+                for (int i = 0; i < cnt; ++i) {
+                    const int N = r.I2[d];
+                    const int f = (cnt == N && i >= (N + 1) / 2) ? i - N : i;
+                    const double k = 2.0 * kPi * f / r.L[d];
+                    double pref;
+                    const double ex = inv_what2_log(k, r.H2[d], r.S2, &pref);
+                    v[i] = pref * std::exp(std::min(ex, 80.0));
                 }
-            std::vector<double> kt((size_t)jx * jy * r.P * r.P);
-            long_kernel_cheb_basis(r, k2.data(), jx * jy, kt.data());
-            for (size_t k = 0; k < (size_t)jx * jy; ++k)
-                for (int i = 0; i < r.P * r.P; ++i) kt[k * r.P * r.P + i] *= scale[k];
-            if (e == hipSuccess) e = upload(ws.l2_kt_r, kt, f64);
+                return v;
+            };
+            const std::vector<double> wx = winv(0, r.I2[0]), wy = winv(1, Ky);
+            if (r.Q > 0) {
+                // App. C: A_p(k) = sum_l coef[l][p] e^{-el[l] |k|^2}, with pi, the signs,
+                // factorials, L_z^{2p} s_l^{2-2p} and the unnormalised inverse folded in
+                const int nl = r.M - r.m;
+                std::vector<double> el(nl), coef((size_t)nl * r.Q);
+                for (int l = 0; l < nl; ++l) {
+                    const double sl = r.s[r.m + 1 + l], s2 = sl * sl;
+                    el[l] = s2 / 4.0;
+                    double c = kPi * r.w[r.m + 1 + l] * s2 * norm;  // p = 0
+                    for (int q = 0; q < r.Q; ++q) {
+                        coef[(size_t)l * r.Q + q] = c;
+                        c *= -(r.L[2] * r.L[2]) / (s2 * (q + 1));
+                    }
+                }
+                // B_p[n][a]: ((z - z')/L_z)^{2p} = ((t - t')/2)^{2p}, interpolated at the P
+                // Chebyshev nodes in the target t and expanded exactly in T_a(t'), a < P_s
+                // (P_s = 2Q - 1 nodes reproduce every polynomial of degree 2Q - 2)
+                std::vector<double> bp((size_t)r.Q * r.P * r.Ps, 0.0);
+                std::vector<double> tc(r.P), te(r.Ps);
+                for (int c = 0; c < r.P; ++c) tc[c] = std::cos((c + 0.5) * kPi / r.P);
+                for (int c = 0; c < r.Ps; ++c) te[c] = std::cos((c + 0.5) * kPi / r.Ps);
+                for (int q = 0; q < r.Q; ++q)
+                    for (int nn = 0; nn < r.P; ++nn)
+                        for (int a = 0; a < r.Ps; ++a) {
+                            double acc = 0;
+                            for (int c = 0; c < r.P; ++c)
+                                for (int g = 0; g < r.Ps; ++g) {
+                                    const double d = 0.5 * (tc[c] - te[g]);
+                                    acc += std::cos(nn * (c + 0.5) * kPi / r.P) * std::cos(a * (g + 0.5) * kPi / r.Ps) *
+                                           std::pow(d, 2 * q);
+                                }
+                            bp[((size_t)q * r.P + nn) * r.Ps + a] =
+                                acc * (nn ? 2.0 : 1.0) / r.P * (a ? 2.0 : 1.0) / r.Ps;
+                        }
+                if (e == hipSuccess) e = upload(ws.l2_el, el, f64);
+                if (e == hipSuccess) e = upload(ws.l2_coef, coef, f64);
+                if (e == hipSuccess) e = upload(ws.l2_bp, bp, f64);
+                if (e == hipSuccess) e = upload(ws.l2_winv_x, wx, f64);
+                if (e == hipSuccess) e = upload(ws.l2_winv_y, wy, f64);
+            } else {
+                const int jx = r.I2[0] / 2 + 1;
+                std::vector<double> k2((size_t)jx * Ky);
+                for (int a = 0; a < jx; ++a)
+                    for (int b = 0; b < Ky; ++b) {
+                        const double kx = 2.0 * kPi * a / r.L[0], ky = 2.0 * kPi * b / r.L[1];
+                        k2[(size_t)a * Ky + b] = kx * kx + ky * ky;
+                    }
+                std::vector<double> kt((size_t)jx * Ky * r.P * r.P);
+                long_kernel_cheb_basis(r, k2.data(), jx * Ky, kt.data());
+                for (int a = 0; a < jx; ++a)
+                    for (int b = 0; b < Ky; ++b) {
+                        const double sc = wx[a] * wy[b] * norm;
+                        for (int i = 0; i < r.P * r.P; ++i) kt[((size_t)a * Ky + b) * r.P * r.P + i] *= sc;
+                    }
+                if (e == hipSuccess) e = upload(ws.l2_kt_r, kt, f64);
+            }
         }
     }
     if (e != hipSuccess) {
@@ -345,7 +412,8 @@ void free_plan(Plan& p) {
     Workspace& ws = p.ws;
     // the tables (the per-call buffers live in p.region)
     void* ptrs[] = {ws.spread_nodes, ws.tw_x, ws.tw_y, ws.tw_z, ws.tw_zpost, ws.mult_ax, ws.mult_ay,
-                    ws.mult_az, ws.mult_c, ws.long_modes, ws.long_kt, ws.l2_tw_x, ws.l2_tw_y, ws.l2_kt, ws.l2_kt_r,
+                    ws.mult_az, ws.mult_c, ws.long_modes, ws.long_kt, ws.l2_tw_x, ws.l2_tw_y, ws.l2_tw_ypost,
+                    ws.l2_kt_r, ws.l2_el, ws.l2_coef, ws.l2_bp, ws.l2_winv_x, ws.l2_winv_y,
                     p.region};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -850,6 +918,7 @@ static void fill_params(const Resolved& r, sog_params* o) {
             o->long_I[1] = r.I2[1];
             o->long_Pw[0] = o->long_Pw[1] = r.Pw2;
             o->long_S = r.S2;
+            o->long_Q = r.Q > 0 ? r.Q : -1;
         }
     }
 }

@@ -147,10 +147,15 @@ struct Resolved {
     double S2 = 0;
     double h2[2] = {0, 0};
     double H2[2] = {0, 0};
-    int B2[2] = {0, 0};
-    int ntile2[2] = {0, 0};
-    int max_dup2 = 1;
+    int ntile2[2] = {0, 0};    // tiles of kLong2Tile x kLong2Tile nodes
+    int Q = 0;                 // FFT form: Taylor terms of the z kernel (App. C); 0: exact kernel
+    int Ps = 0;                // FFT form: source planes (P exact, 2Q - 1 Taylor); P target planes
 };
+
+// The long range's FFT form: gridding and gathering tiles of kLong2Tile^2 nodes; at most
+// kLong2MaxPlanes source or target planes (Chebyshev terms in z).
+constexpr int kLong2Tile = 16;
+constexpr int kLong2MaxPlanes = 32;
 
 // Near-field work units.  Float64: runs of at most kNearUnitCells cells of a column with at
 // most 64 targets, one slot per cell.  Float32: chunks of at most kNearChunk consecutive
@@ -248,18 +253,21 @@ struct Workspace {
     void* long_a = nullptr;     // nh x P complex coefficients a(k,n) (real type)
     int long_blocks = 0;
     // FFT form of the long range
-    int* l2_tile_start = nullptr;
-    int* l2_tile_cursor = nullptr;
-    int* l2_dup_start = nullptr;
-    int* l2_dup_cursor = nullptr;
-    int* l2_dup_list = nullptr;
-    int* l2_g = nullptr;        // n x int4 (gx, gy, -, orig)
+    int* l2_tile_start = nullptr;  // ntiles + 1
+    int* l2_tile_cursor = nullptr; // ntiles
+    int* l2_g = nullptr;        // n x int4 (gx, gy, -, orig), in tile order
     void* l2_u = nullptr;       // n x real4 (ux, uy, t = 2z/Lz, q)
-    void* l2_grid = nullptr;    // P x I2x x I2y complex
-    void* l2_tw_x = nullptr;
-    void* l2_tw_y = nullptr;
-    double* l2_kt = nullptr;    // (I2x/2+1) x (I2y/2+1) x P x P, divided by What2^2 and I2x I2y
-    void* l2_kt_r = nullptr;    // same in the working precision
+    void* l2_grid = nullptr;    // max(P_s, P) planes of I2x x I2y reals
+    void* l2_cgrid = nullptr;   // max(P_s, P) planes of I2x rows of cgrid_stride(I2y) complex
+    void* l2_tw_x = nullptr;    // e^{-2 pi i t / I2x}
+    void* l2_tw_y = nullptr;    // e^{-2 pi i t / (I2y/2)}
+    void* l2_tw_ypost = nullptr;  // e^{-2 pi i k / I2y}, k <= I2y/2
+    void* l2_kt_r = nullptr;    // exact kernel: (I2x/2+1) x (I2y/2+1) x P x P, divided by What2^2 and I2x I2y
+    void* l2_el = nullptr;      // Taylor: s_l^2/4 per long-range Gaussian
+    void* l2_coef = nullptr;    // Taylor: (M - m) x Q, pi ((-1)^p/p!) w_l L_z^{2p} s_l^{2-2p} / (I2x I2y)
+    void* l2_bp = nullptr;      // Taylor: Q x P x P_s
+    void* l2_winv_x = nullptr;  // Taylor: 1/What2_x(k_x)^2, I2x
+    void* l2_winv_y = nullptr;  // Taylor: 1/What2_y(k_y)^2, I2y/2 + 1
     // energy reduction
     double* red = nullptr;
     int red_blocks = 0;
@@ -278,7 +286,7 @@ struct Plan {
     bool check = true;
     bool timing = false;
     FFTFactors fx, fy, fz;          // mid-range FFT lengths I_x, I_y, I_z*/2
-    FFTFactors f2x, f2y;            // long-range FFT form
+    FFTFactors f2x, f2y;            // long-range FFT form: I2x and I2y/2 (real-to-complex along y)
     // per-call buffers: one region of region_bytes (offsets in region_slots) that the plan
     // allocates, unless static_region (then every call binds a region of its own)
     void* region = nullptr;
@@ -294,7 +302,6 @@ struct Plan {
 sog_status resolve(const double box[3], int64_t n, double tol, const sog_options& opt, Resolved& r,
                    std::string& err);
 bool factor_fft(int n, FFTFactors& f);
-int long_fft_tile(int prec, int Pw2, int P);
 int next_smooth(int n, bool even);
 void near_chebyshev(Resolved& r);
 void long_kernel_cheb_basis(const Resolved& r, const double* k2, int nk, double* out);

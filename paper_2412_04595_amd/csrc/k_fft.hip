@@ -527,36 +527,6 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_scale(cpx<T>* __restrict_
     }
 }
 
-// Generic batched line transform: W consecutive lines per block; line l starts at
-// (l / ncols) * outer_stride + (l % ncols) * col_stride, elements at elem_stride.
-// Lines adjacent in memory (col_stride == 1) load and store coalesced.
-template <typename T, int SIGN>
-__global__ __launch_bounds__(kFFTThreads) void k_fft_lines(cpx<T>* __restrict__ d, int nlines, int ncols,
-                                                           size_t outer_stride, size_t col_stride, size_t elem_stride,
-                                                           int W, FFTDev f, const cpx<T>* __restrict__ tw) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int n = f.n;
-    cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* twl = A + n * W;
-    const int line0 = blockIdx.x * W;
-    const int lw = __ffs(W) - 1;
-    stage_in<T>(A, n * W,
-                [&](int idx) {
-                    const int line = line0 + (idx & (W - 1));
-                    return (line < nlines) ? d[(size_t)(line / ncols) * outer_stride + (size_t)(line % ncols) * col_stride +
-                                               (size_t)(idx >> lw) * elem_stride]
-                                           : cpx<T>{0, 0};
-                },
-                [&](int idx) { return idx; }, [&] { copy_in<4>(twl, tw, n); });
-    __syncthreads();
-    lds_fft<T, SIGN>(A, twl, W, W, f);
-    for (int idx = threadIdx.x; idx < n * W; idx += kFFTThreads) {
-        const int w = idx & (W - 1), e = idx >> lw, line = line0 + w;
-        if (line < nlines)
-            d[(size_t)(line / ncols) * outer_stride + (size_t)(line % ncols) * col_stride + (size_t)e * elem_stride] = A[idx];
-    }
-}
-
 template <typename T>
 hipError_t run_fft_mid(Plan& p) {
     const Resolved& r = p.r;
@@ -656,33 +626,59 @@ hipError_t run_fft_mid(Plan& p) {
 
 }  // namespace
 
-hipError_t launch_fft_lines(Plan& p, void* data, const FFTFactors& f, const void* tw, int nlines, int ncols,
-                            size_t outer_stride, size_t col_stride, size_t elem_stride, int sign, int W) {
-    const bool f64 = p.r.prec == SOG_PREC_FP64;
-    const size_t ce = f64 ? 16 : 8;
-    const int cap = f64 ? kFFTCap<double> : kFFTCap<float>;
-    int Wp = 1;
-    while (Wp * 2 <= W) Wp *= 2;  // a power of two
-    while (Wp > 1 && ((size_t)f.n * Wp > (size_t)cap || (size_t)f.n * (Wp + 1) * ce > 65536)) Wp >>= 1;
-    const size_t lds = (size_t)f.n * (Wp + 1) * ce;
-    if (f.n > cap || lds > 65536 || nlines <= 0) return hipErrorInvalidConfiguration;
-    const int nb = (nlines + Wp - 1) / Wp;
-    if (f64) {
-        if (sign < 0)
-            k_fft_lines<double, -1><<<nb, kFFTThreads, lds, p.stream>>>((cpx<double>*)data, nlines, ncols, outer_stride,
-                                                                       col_stride, elem_stride, Wp, to_dev(f), (const cpx<double>*)tw);
-        else
-            k_fft_lines<double, +1><<<nb, kFFTThreads, lds, p.stream>>>((cpx<double>*)data, nlines, ncols, outer_stride,
-                                                                       col_stride, elem_stride, Wp, to_dev(f), (const cpx<double>*)tw);
+namespace {
+
+// The 2D transforms of the long range's FFT form on `planes` planes of I2x x I2y reals
+// (y fastest): forward (sign < 0) real-to-complex along y (the z pass's kernel on lines of
+// I2y reals, every pair nonzero), then complex along x (the y pass's kernel with the
+// planes as its outer index); inverse (sign > 0) the reverse, unnormalised.  Half
+// spectrum: planes of I2x rows of Ky = I2y/2 + 1 complex, row stride cgrid_stride(I2y).
+template <typename T>
+hipError_t run_fft_long2(Plan& p, int sign, int planes) {
+    const Resolved& r = p.r;
+    Workspace& ws = p.ws;
+    const int Ix = r.I2[0], Iy = r.I2[1], m = Iy / 2, Ky = m + 1, Kys = cgrid_stride(Iy);
+    const int nlines = planes * Ix;
+    const size_t ce = sizeof(cpx<T>);
+    const size_t budget = kFFTLdsBudget;
+    if (planes < 1 || (Iy & 1) || m < 2 || (size_t)m > (size_t)kFFTCap<T> || (size_t)Ix > (size_t)kFFTCap<T> ||
+        p.f2y.n != m || p.f2x.n != Ix)
+        return hipErrorInvalidConfiguration;
+    auto ldsz_of = [&](int w) { return ((size_t)(m + 1) * (w + 1) + 2 * (size_t)m + 1) * ce; };
+    int Wz = lines_per_block<T>(m + 1);
+    while (Wz > 1 && ldsz_of(Wz) > budget) Wz >>= 1;
+    const size_t ldsz = ldsz_of(Wz);
+    int Wx = lines_per_block<T>(Ix);
+    while (Wx > 1 && (size_t)Ix * (Wx + 1) * ce > budget) Wx >>= 1;
+    const size_t ldsx = (size_t)Ix * (Wx + 1) * ce;
+    if (ldsz > budget || ldsx > budget) return hipErrorInvalidConfiguration;
+    const int nbx = planes * ((Ky + Wx - 1) / Wx);
+    T* grid = (T*)ws.l2_grid;
+    cpx<T>* cg = (cpx<T>*)ws.l2_cgrid;
+    const cpx<T>* twy = (const cpx<T>*)ws.l2_tw_y;
+    const cpx<T>* twp = (const cpx<T>*)ws.l2_tw_ypost;
+    const cpx<T>* twx = (const cpx<T>*)ws.l2_tw_x;
+    if (sign < 0) {
+        k_fft_z_r2c<T><<<(nlines + Wz - 1) / Wz, kFFTThreads, ldsz, p.stream>>>(
+            grid, cg, nlines, Iy, Kys, Wz, 0, make_udiv(m), make_udiv(m + 1), to_dev(p.f2y), twy, twp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        k_fft_y<T, -1><<<nbx, kFFTThreads, ldsx, p.stream>>>(cg, planes, Ix, Ky, Kys, Wx, to_dev(p.f2x), twx);
     } else {
-        if (sign < 0)
-            k_fft_lines<float, -1><<<nb, kFFTThreads, lds, p.stream>>>((cpx<float>*)data, nlines, ncols, outer_stride,
-                                                                      col_stride, elem_stride, Wp, to_dev(f), (const cpx<float>*)tw);
-        else
-            k_fft_lines<float, +1><<<nb, kFFTThreads, lds, p.stream>>>((cpx<float>*)data, nlines, ncols, outer_stride,
-                                                                      col_stride, elem_stride, Wp, to_dev(f), (const cpx<float>*)tw);
+        k_fft_y<T, +1><<<nbx, kFFTThreads, ldsx, p.stream>>>(cg, planes, Ix, Ky, Kys, Wx, to_dev(p.f2x), twx);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        k_fft_z_c2r<T><<<(nlines + Wz - 1) / Wz, kFFTThreads, ldsz, p.stream>>>(
+            cg, grid, nlines, Iy, Kys, Wz, 0, make_udiv(m), make_udiv(m + 1), to_dev(p.f2y), twy, twp);
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fft_long2(Plan& p, int sign, int planes) {
+    if (p.r.prec == SOG_PREC_FP64) return run_fft_long2<double>(p, sign, planes);
+    return run_fft_long2<float>(p, sign, planes);
 }
 
 hipError_t launch_fft_mid(Plan& p) {

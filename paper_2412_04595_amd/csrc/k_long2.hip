@@ -1,31 +1,52 @@
-// Long range, Fourier-Chebyshev solver with FFTs (Alg. al::long, Sec. 3.3): for flat
-// boxes the direct form needs O(A / s_{m+1}^2) modes per particle, so the x,y Fourier
-// sums go through a 2D Gaussian-window grid (eq. Chebygrid) and 2D FFTs, exactly as the
-// mid range does in 3D, while z stays in the Chebyshev basis:
-//   S2(g, n)  = sum_j q_j W2(g - r_j) T_n(t_j)                       (gridding)
-//   Shat2     = fft2(S2(., n)) for each n
-//   uhat(k,n) = sum_n' Kt(k)[n][n'] / What2(k)^2 / (I2x I2y) Shat2(k, n')   (scaling)
-//   u(., n)   = ifft2(uhat(., n))                                      (unnormalised)
+// Long range, Fourier-Chebyshev solver with FFTs (Alg. al::long, Sec. 3.3), for boxes
+// where the direct form's O(A / s_{m+1}^2) modes per particle are too many (flat and
+// strongly confined boxes).  The x,y Fourier sums go through a 2D Gaussian-window grid
+// (eq. Chebygrid) and 2D FFTs, z stays polynomial:
+//   S2(g, a)  = sum_j q_j W2(g - r_j) T_a(t_j),  a < P_s               (gridding)
+//   Shat2     = fft2(S2(., a))                  (real-to-complex along y, then along x)
+//   uhat(k,n) = sum_a K(k)[n][a] Shat2(k, a),  n < P                  (scaling)
+//   u(., n)   = ifft2(uhat(., n))               (along x, then complex-to-real along y)
 //   Phi^long_i = h_x h_y sum_g W2(r_i - g) sum_n T_n(t_i) u(g, n)      (gathering)
-// Kt = C^T K C is the same Chebyshev-basis z kernel as the direct form.  Gridding is
-// output-stationary over 2D tiles that hold all P Chebyshev terms, gathering uses a
-// halo tile, as in the mid range.
+// with t = 2 z / L_z on the centred box.  Two forms of the z kernel K (both divided by
+// What2(k)^2 and by I2x I2y, the unnormalised inverse):
+//   * exact: P_s = P, K = C^T Kz C with Kz(k; c, c') = pi sum_{l>m} w_l s_l^2
+//     e^{-s_l^2 |k|^2/4} e^{-(z_c - z_c')^2/s_l^2} at the Chebyshev nodes (eq. trun2,
+//     interpolation in the target and anterpolation in the source z); a table per mode;
+//   * Taylor (App. C, Lemma lemma::Taylor): e^{-dz^2/s^2} = sum_{p<Q} (-dz^2/s^2)^p/p! + ...,
+//     so Kz(k; z, z') = sum_{p<Q} A_p(k) ((z - z')/L_z)^{2p} with
+//     A_p(k) = pi ((-1)^p/p!) sum_{l>m} w_l L_z^{2p} s_l^{2-2p} e^{-s_l^2 |k|^2/4}.  In the
+//     source z the polynomial is exact with P_s = 2Q - 1 Chebyshev terms, in the target z it
+//     is interpolated at the P Chebyshev nodes: K(k) = sum_p A_p(k) B_p with fixed matrices
+//     B_p (host, float64).  A_p is formed on the fly per mode (no table), so the scaling
+//     reads and writes only the grid.  This is the paper's Taylor form with its sum over the
+//     nodes' moments ((z_c - z_j)/L_z)^{2p} reordered through the Chebyshev basis of z_j
+//     (equal up to rounding).
+// At k = 0 the constant term (p = 0, or the expm1 of the exact form) multiplies
+// sum_j q_j and is left out.
+//
+// Gridding is output-stationary: a workgroup owns a 16 x 16 tile of nodes, one node per
+// thread, and sums in registers the windows of every particle whose nearest node lies in
+// a tile its windows can reach (particles counting-sorted by tile; at most three tiles per
+// direction), 8 planes per pass.  No atomics: each node is written once, in a fixed order
+// of the particles, so the grid is deterministic.  Gathering: one particle per lane,
+// the tile's halo of the u planes staged in LDS 8 planes at a time.
 #include "device_common.hpp"
 
 namespace sog {
 
-hipError_t launch_fft_lines(Plan& p, void* data, const FFTFactors& f, const void* tw, int nlines, int ncols,
-                            size_t outer_stride, size_t col_stride, size_t elem_stride, int sign, int W);
+hipError_t launch_fft_long2(Plan& p, int sign, int planes);  // k_fft.hip
 
 namespace {
+
+constexpr int kL2Tile = kLong2Tile;  // tile edge (nodes) in x and y
+constexpr int kL2Chunk = 8;          // planes per pass of the gridding and gathering
+constexpr int kL2Batch = 128;        // particles staged at a time by the gridding
 
 struct L2Geom {
     double L[3];
     double h[2];
     int I[2];
-    int B[2];
     int nt[2];
-    int HW;
 };
 
 __device__ __forceinline__ void grid_point2(const L2Geom& g, double x, double y, int a[2], double u[2]) {
@@ -38,20 +59,23 @@ __device__ __forceinline__ void grid_point2(const L2Geom& g, double x, double y,
     }
 }
 
-__global__ void k_l2_key(const double* __restrict__ x, int n, L2Geom g, int* __restrict__ key) {
+__global__ void k_l2_key(const double* __restrict__ x, int n, L2Geom g, int* __restrict__ key,
+                         int* __restrict__ count) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         int a[2];
         double u[2];
         grid_point2(g, x[3 * i], x[3 * i + 1], a, u);
-        key[i] = (a[0] / g.B[0]) * g.nt[1] + a[1] / g.B[1];
+        const int t = (a[0] / kL2Tile) * g.nt[1] + a[1] / kL2Tile;
+        key[i] = t;
+        atomicAdd(&count[t], 1);
     }
 }
 
 template <typename real>
 __global__ void k_l2_pack(const double* __restrict__ x, const double* __restrict__ q, int n, L2Geom g,
-                          const int* __restrict__ perm, int4* __restrict__ gp, vec4<real>* __restrict__ up) {
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-        int i = perm[p];
+                          const int* __restrict__ key, const int* __restrict__ start, int* __restrict__ cursor,
+                          int4* __restrict__ gp, vec4<real>* __restrict__ up) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         int a[2];
         double u[2];
         grid_point2(g, x[3 * i], x[3 * i + 1], a, u);
@@ -60,6 +84,8 @@ __global__ void k_l2_pack(const double* __restrict__ x, const double* __restrict
         if (!isfinite(qq)) qq = 0;
         double t = 2.0 * (zz - 0.5 * g.L[2]) / g.L[2];
         t = fmin(1.0, fmax(-1.0, t));
+        const int k = key[i];
+        const int p = start[k] + atomicAdd(&cursor[k], 1);
         gp[p] = make_int4(a[0], a[1], 0, i);
         vec4<real> v;
         v.x = (real)u[0];
@@ -70,38 +96,8 @@ __global__ void k_l2_pack(const double* __restrict__ x, const double* __restrict
     }
 }
 
-__device__ __forceinline__ int touched2(int a0, int HW, int I, int B, int* out) {
-    int cnt = 0;
-    for (int o = -HW; o <= HW; ++o) {
-        int t = imod(a0 + o, I) / B;
-        bool seen = false;
-        for (int k = 0; k < cnt; ++k) seen |= (out[k] == t);
-        if (!seen && cnt < 8) out[cnt++] = t;
-    }
-    return cnt;
-}
-
-__global__ void k_l2_dup(const int4* __restrict__ gp, int n, L2Geom g, int* __restrict__ count,
-                         const int* __restrict__ start, int* __restrict__ cursor, int* __restrict__ list, int cap,
-                         int fill) {
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
-        int4 a = gp[p];
-        int tx[8], ty[8];
-        int nx = touched2(a.x, g.HW, g.I[0], g.B[0], tx);
-        int ny = touched2(a.y, g.HW, g.I[1], g.B[1], ty);
-        for (int i = 0; i < nx; ++i)
-            for (int j = 0; j < ny; ++j) {
-                int t = tx[i] * g.nt[1] + ty[j];
-                if (!fill) {
-                    atomicAdd(&count[t], 1);
-                } else {
-                    int pos = start[t] + atomicAdd(&cursor[t], 1);
-                    if (pos < cap) list[pos] = p;
-                }
-            }
-    }
-}
-
+// The Gaussian window of eq. GS at node o of a P_w-point window, for a particle at offset
+// u in [-1/2, 1/2] (grid units) from its nearest node: exp(-S d^2 / HW^2), d = o - HW - u.
 template <typename real, int PW>
 __device__ __forceinline__ real win2(int o, real u, real S, real inv_hw2) {
     constexpr int HW = (PW - 1) / 2;
@@ -110,103 +106,187 @@ __device__ __forceinline__ real win2(int o, real u, real S, real inv_hw2) {
     return (r2 <= (real)1) ? dexp(-S * r2) : (real)0;
 }
 
+// The tiles (cyclic, first tile and count) holding the nearest nodes of particles whose
+// windows of half-width HW reach nodes [x0, x0 + e) of a periodic line of I nodes in
+// tiles of B.
+__device__ __forceinline__ int l2_tile_span(int x0, int e, int HW, int I, int nt, int* first) {
+    if (e + 2 * HW >= I) {
+        *first = 0;
+        return nt;
+    }
+    const int lo = imod(x0 - HW, I), hi = imod(x0 + e - 1 + HW, I);
+    const int tlo = lo / kL2Tile, thi = hi / kL2Tile;
+    int cnt = (lo <= hi) ? thi - tlo + 1 : (nt - tlo) + thi + 1;
+    *first = tlo;
+    return cnt < nt ? cnt : nt;
+}
+
 template <typename real>
 struct L2SpreadArgs {
     const int4* gp;
     const vec4<real>* up;
-    const int* dstart;
-    const int* dlist;
-    int cap;
-    cpx<real>* grid;  // P x I2x x I2y
-    int I[2], B[2], nt[2], ntiles, P;
+    const int* tstart;  // ntiles + 1
+    real* grid;         // P_s planes of I0 x I1 reals (y fastest)
+    int I[2], nt[2], ntiles, Ps;
     real S, inv_hw2;
 };
 
-constexpr int kL2Threads = 128;
-
 template <typename real, int PW>
-__global__ __launch_bounds__(kL2Threads) void k_l2_spread(L2SpreadArgs<real> a) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int P = a.P;
-    real* tile = reinterpret_cast<real*>(smem_raw);  // B0 x B1 x P
-    const int T = a.B[0] * a.B[1] * P;
-    real* tn = tile + T;                              // kL2Threads x P
+__global__ __launch_bounds__(256) void k_l2_spread(L2SpreadArgs<real> a) {
+    constexpr int HW = (PW - 1) / 2;
+    __shared__ int cxs[kL2Batch], cys[kL2Batch];
+    __shared__ real wxs[kL2Batch * PW], wys[kL2Batch * PW];
+    __shared__ real ts[kL2Batch * kL2Chunk];
     const int t = xcd_logical_block(a.ntiles);
     if (t < 0) return;
     const int tx = t / a.nt[1], ty = t % a.nt[1];
-    const int x0 = tx * a.B[0], y0 = ty * a.B[1];
-    const int ex = min(a.B[0], a.I[0] - x0), ey = min(a.B[1], a.I[1] - y0);
-    for (int k = threadIdx.x; k < T; k += blockDim.x) tile[k] = 0;
-    __syncthreads();
-    constexpr int HW = (PW - 1) / 2;
-    real* mt = tn + threadIdx.x * P;
-    const int beg = min(a.dstart[t], a.cap), end = min(a.dstart[t + 1], a.cap);
-    for (int e = beg + threadIdx.x; e < end; e += blockDim.x) {
-        const int p = a.dlist[e];
-        const int4 g = a.gp[p];
-        const vec4<real> u = a.up[p];
-        real wx[PW], wy[PW];
+    const int x0 = tx * kL2Tile, y0 = ty * kL2Tile;
+    const int ex = min(kL2Tile, a.I[0] - x0), ey = min(kL2Tile, a.I[1] - y0);
+    const int lx = threadIdx.x / kL2Tile, ly = threadIdx.x % kL2Tile;
+    const bool valid = lx < ex && ly < ey;
+    // a node outside the grid takes a far-away index that no window reaches
+    const int nx = valid ? x0 + lx : -(1 << 29), ny = valid ? y0 + ly : -(1 << 29);
+    int fx, fy;
+    const int cntx = l2_tile_span(x0, ex, HW, a.I[0], a.nt[0], &fx);
+    const int cnty = l2_tile_span(y0, ey, HW, a.I[1], a.nt[1], &fy);
+    // the y tiles as at most two runs of consecutive tiles
+    const int r1 = min(cnty, a.nt[1] - fy), r2 = cnty - r1;
+    for (int c0 = 0; c0 < a.Ps; c0 += kL2Chunk) {
+        real acc[kL2Chunk];
 #pragma unroll
-        for (int o = 0; o < PW; ++o) {
-            wx[o] = u.w * win2<real, PW>(o, u.x, a.S, a.inv_hw2);
-            wy[o] = win2<real, PW>(o, u.y, a.S, a.inv_hw2);
-        }
-        real T0 = 1, T1 = u.z;
-        mt[0] = 1;
-        if (P > 1) mt[1] = u.z;
-        for (int k = 2; k < P; ++k) {
-            const real T2 = (real)2 * u.z * T1 - T0;
-            mt[k] = T2;
-            T0 = T1;
-            T1 = T2;
-        }
-        for (int ix = -1; ix <= 1; ++ix) {
-            const int sx = g.x - HW + ix * a.I[0];
-            for (int iy = -1; iy <= 1; ++iy) {
-                const int sy = g.y - HW + iy * a.I[1];
+        for (int k = 0; k < kL2Chunk; ++k) acc[k] = 0;
+        for (int ix = 0; ix < cntx; ++ix) {
+            const int txx = (fx + ix) % a.nt[0];
+            for (int run = 0; run < 2; ++run) {
+                const int ty0 = run == 0 ? fy : 0, tn = run == 0 ? r1 : r2;
+                if (tn <= 0) continue;
+                const int beg = a.tstart[txx * a.nt[1] + ty0], end = a.tstart[txx * a.nt[1] + ty0 + tn];
+                for (int base = beg; base < end; base += kL2Batch) {
+                    const int nb = min(kL2Batch, end - base);
+                    __syncthreads();
+                    if ((int)threadIdx.x < nb) {
+                        const int j = threadIdx.x;
+                        const int4 g = a.gp[base + j];
+                        const vec4<real> u = a.up[base + j];
+                        cxs[j] = g.x - HW;
+                        cys[j] = g.y - HW;
 #pragma unroll
-                for (int ox = 0; ox < PW; ++ox) {
-                    const int gx = sx + ox;
-                    if (gx < x0 || gx >= x0 + ex) continue;
+                        for (int o = 0; o < PW; ++o) {
+                            wxs[j * PW + o] = u.w * win2<real, PW>(o, u.x, a.S, a.inv_hw2);
+                            wys[j * PW + o] = win2<real, PW>(o, u.y, a.S, a.inv_hw2);
+                        }
+                        // T_k(t) for k in [c0, c0 + 8)
+                        real T0 = 1, T1 = u.z;
+                        for (int k = 0; k < c0 + kL2Chunk; ++k) {
+                            const real Tk = k == 0 ? (real)1 : (k == 1 ? u.z : (real)2 * u.z * T1 - T0);
+                            if (k >= 2) {
+                                T0 = T1;
+                                T1 = Tk;
+                            }
+                            if (k >= c0) ts[j * kL2Chunk + (k - c0)] = Tk;
+                        }
+                    }
+                    __syncthreads();
+                    for (int j = 0; j < nb; ++j) {
+                        int dx = nx - cxs[j], dy = ny - cys[j];
+                        dx += dx < 0 ? a.I[0] : 0;
+                        dx -= dx >= a.I[0] ? a.I[0] : 0;
+                        dy += dy < 0 ? a.I[1] : 0;
+                        dy -= dy >= a.I[1] ? a.I[1] : 0;
+                        if ((unsigned)dx < (unsigned)PW && (unsigned)dy < (unsigned)PW) {
+                            const real w = wxs[j * PW + dx] * wys[j * PW + dy];
 #pragma unroll
-                    for (int oy = 0; oy < PW; ++oy) {
-                        const int gy = sy + oy;
-                        if (gy < y0 || gy >= y0 + ey) continue;
-                        const real w = wx[ox] * wy[oy];
-                        real* cell = tile + ((gx - x0) * a.B[1] + (gy - y0)) * P;
-                        for (int k = 0; k < P; ++k) atomicAdd(cell + k, w * mt[k]);
+                            for (int k = 0; k < kL2Chunk; ++k) acc[k] += w * ts[j * kL2Chunk + k];
+                        }
                     }
                 }
             }
         }
-    }
-    __syncthreads();
-    const size_t plane = (size_t)a.I[0] * a.I[1];
-    for (int k = threadIdx.x; k < T; k += blockDim.x) {
-        const int nn = k % P, ly = (k / P) % a.B[1], lx = k / (P * a.B[1]);
-        if (lx < ex && ly < ey)
-            a.grid[nn * plane + (size_t)(x0 + lx) * a.I[1] + (y0 + ly)] = cpx<real>{tile[k], 0};
+        if (valid) {
+            const size_t plane = (size_t)a.I[0] * a.I[1];
+            const size_t node = (size_t)nx * a.I[1] + ny;
+#pragma unroll
+            for (int k = 0; k < kL2Chunk; ++k)
+                if (c0 + k < a.Ps) a.grid[(size_t)(c0 + k) * plane + node] = acc[k];
+        }
     }
 }
 
+// Scaling of every mode of the half spectrum: uhat(k, n) = sum_a K(k)[n][a] Shat2(k, a),
+// n < P, a < P_s, in place (a thread reads all P_s planes of its mode before it writes).
 template <typename real>
-__global__ void k_l2_scale(cpx<real>* __restrict__ grid, int I0, int I1, int P, const real* __restrict__ kt) {
+struct L2ScaleArgs {
+    cpx<real>* cg;        // planes of I0 rows of Kys complex (k_y fastest)
+    int I0, Ky, Kys, P, Ps, Q;
+    // exact form: K per mode (j_x = min(i_x, I0 - i_x), k_y), P x P_s, scaled
+    const real* kt;
+    // Taylor form: per long-range Gaussian l, e_l = s_l^2/4 and coef[l][p] (p < Q), with
+    // A_p(k) = sum_l e^{-e_l |k|^2} coef[l][p]; B_p (Q x P x P_s); 1/What2^2 per direction
+    // (the 1/(I0 I1) and pi folded into coef)
+    const real* el;
+    const real* coef;
+    int nl;
+    const real* bp;
+    const real* winv_x;  // I0
+    const real* winv_y;  // Ky
+    real dkx, dky;       // 2 pi / L_x, 2 pi / L_y
+};
+
+constexpr int kL2ScaleThreads = 64;
+constexpr int kL2MaxQ = 16;
+
+template <typename real>
+__global__ __launch_bounds__(kL2ScaleThreads) void k_l2_scale(L2ScaleArgs<real> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    cpx<real>* v = reinterpret_cast<cpx<real>*>(smem_raw) + threadIdx.x * P;
-    const int kp = blockIdx.x * blockDim.x + threadIdx.x;
-    if (kp >= I0 * I1) return;
-    const int ix = kp / I1, iy = kp % I1;
-    const int jx = min(ix, I0 - ix), jy = min(iy, I1 - iy);
-    const real* K = kt + ((size_t)jx * (I1 / 2 + 1) + jy) * P * P;
-    const size_t plane = (size_t)I0 * I1;
-    for (int k = 0; k < P; ++k) v[k] = grid[k * plane + kp];
-    for (int nn = 0; nn < P; ++nn) {
-        real sr = 0, si = 0;
-        for (int e = 0; e < P; ++e) {
-            sr += K[nn * P + e] * v[e].x;
-            si += K[nn * P + e] * v[e].y;
+    cpx<real>* rho = reinterpret_cast<cpx<real>*>(smem_raw);  // Ps x kL2ScaleThreads
+    const int mode = blockIdx.x * kL2ScaleThreads + threadIdx.x;
+    if (mode >= a.I0 * a.Ky) return;  // no barrier below: each thread uses only its own LDS column
+    const int ix = mode / a.Ky, ky = mode - ix * a.Ky;
+    const size_t plane = (size_t)a.I0 * a.Kys;
+    cpx<real>* cell = a.cg + (size_t)ix * a.Kys + ky;
+    for (int s = 0; s < a.Ps; ++s) rho[s * kL2ScaleThreads + threadIdx.x] = cell[(size_t)s * plane];
+    if (a.Q > 0) {
+        const int fx = ix < (a.I0 + 1) / 2 ? ix : ix - a.I0;
+        const real kx = a.dkx * (real)fx, kyv = a.dky * (real)ky;
+        const real k2 = kx * kx + kyv * kyv;
+        real A[kL2MaxQ];
+#pragma unroll
+        for (int p = 0; p < kL2MaxQ; ++p) A[p] = 0;
+        for (int l = 0; l < a.nl; ++l) {
+            const real e = dexp(-a.el[l] * k2);
+            const real* c = a.coef + (size_t)l * a.Q;
+#pragma unroll
+            for (int p = 0; p < kL2MaxQ; ++p)
+                if (p < a.Q) A[p] += e * c[p];
         }
-        grid[nn * plane + kp] = cpx<real>{sr, si};
+        if (ix == 0 && ky == 0) A[0] = 0;  // the k = 0 constant multiplies sum_j q_j
+        const real wv = a.winv_x[ix] * a.winv_y[ky];
+        for (int n = 0; n < a.P; ++n) {
+            real sr = 0, si = 0;
+            for (int s = 0; s < a.Ps; ++s) {
+                real kk = 0;
+#pragma unroll
+                for (int p = 0; p < kL2MaxQ; ++p)
+                    if (p < a.Q) kk += A[p] * a.bp[((size_t)p * a.P + n) * a.Ps + s];
+                const cpx<real> v = rho[s * kL2ScaleThreads + threadIdx.x];
+                sr += kk * v.x;
+                si += kk * v.y;
+            }
+            cell[(size_t)n * plane] = cpx<real>{wv * sr, wv * si};
+        }
+    } else {
+        const int jx = min(ix, a.I0 - ix);
+        const real* K = a.kt + ((size_t)jx * a.Ky + ky) * a.P * a.Ps;
+        for (int n = 0; n < a.P; ++n) {
+            real sr = 0, si = 0;
+            for (int s = 0; s < a.Ps; ++s) {
+                const real kk = K[n * a.Ps + s];
+                const cpx<real> v = rho[s * kL2ScaleThreads + threadIdx.x];
+                sr += kk * v.x;
+                si += kk * v.y;
+            }
+            cell[(size_t)n * plane] = cpx<real>{sr, si};
+        }
     }
 }
 
@@ -215,83 +295,109 @@ struct L2GatherArgs {
     const int4* gp;
     const vec4<real>* up;
     const int* tstart;
-    const cpx<real>* grid;
+    const real* grid;  // P planes of I0 x I1 reals
     vec4<real>* part;  // long part of each particle: phi, grad
-    int I[2], B[2], nt[2], ntiles, P;
+    int I[2], nt[2], ntiles, P;
     real S, inv_hw2, dcoef[2], area, dzf;
 };
 
+constexpr int kL2GatherThreads = 64;
+
 template <typename real, int PW>
-__global__ __launch_bounds__(64) void k_l2_gather(L2GatherArgs<real> a) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int P = a.P;
+__global__ __launch_bounds__(kL2GatherThreads) void k_l2_gather(L2GatherArgs<real> a) {
     constexpr int HW = (PW - 1) / 2;
+    constexpr int HX = kL2Tile + PW - 1;
+    __shared__ real halo[HX * HX * kL2Chunk];  // (lx, ly, k), k fastest
     const int t = xcd_logical_block(a.ntiles);
     if (t < 0) return;
     const int beg = a.tstart[t], end = a.tstart[t + 1];
     if (beg == end) return;
     const int tx = t / a.nt[1], ty = t % a.nt[1];
-    const int x0 = tx * a.B[0], y0 = ty * a.B[1];
-    const int HX = a.B[0] + PW - 1, HY = a.B[1] + PW - 1;
-    real* halo = reinterpret_cast<real*>(smem_raw);  // HX x HY x P
-    real* tt = halo + HX * HY * P;                    // blockDim x 2P
+    const int x0 = tx * kL2Tile, y0 = ty * kL2Tile;
     const size_t plane = (size_t)a.I[0] * a.I[1];
-    for (int k = threadIdx.x; k < HX * HY * P; k += blockDim.x) {
-        const int nn = k % P, ly = (k / P) % HY, lx = k / (P * HY);
-        const int gx = imod(x0 - HW + lx, a.I[0]), gy = imod(y0 - HW + ly, a.I[1]);
-        halo[k] = a.grid[nn * plane + (size_t)gx * a.I[1] + gy].x;
-    }
-    __syncthreads();
-    real* Tt = tt + threadIdx.x * 2 * P;
-    real* Td = Tt + P;
-    for (int p = beg + threadIdx.x; p < end; p += blockDim.x) {
-        const int4 g = a.gp[p];
-        const vec4<real> u = a.up[p];
-        {
-            real T0 = 1, T1 = u.z, U0 = 1, U1 = 2 * u.z;
-            Tt[0] = 1;
-            Td[0] = 0;
-            if (P > 1) { Tt[1] = u.z; Td[1] = 1; }
-            for (int k = 2; k < P; ++k) {
-                const real T2 = (real)2 * u.z * T1 - T0;
-                Tt[k] = T2;
-                Td[k] = (real)k * U1;
-                const real U2 = (real)2 * u.z * U1 - U0;
-                T0 = T1; T1 = T2;
-                U0 = U1; U1 = U2;
-            }
+    const int nchunks = (a.P + kL2Chunk - 1) / kL2Chunk;
+    for (int pb = beg; pb < end; pb += kL2GatherThreads) {
+        const int p = pb + threadIdx.x;
+        const bool active = p < end;
+        int4 g = make_int4(x0, y0, 0, 0);
+        vec4<real> u = {0, 0, 0, 0};
+        if (active) {
+            g = a.gp[p];
+            u = a.up[p];
         }
-        real wy[PW], dwy[PW];
-#pragma unroll
-        for (int o = 0; o < PW; ++o) {
-            wy[o] = win2<real, PW>(o, u.y, a.S, a.inv_hw2);
-            dwy[o] = a.dcoef[1] * ((real)(o - HW) - u.y) * wy[o];
-        }
-        const int lx0 = g.x - x0, ly0 = g.y - y0;
         real phi = 0, gx = 0, gy = 0, gz = 0;
-        for (int ox = 0; ox < PW; ++ox) {
-            const real wx = win2<real, PW>(ox, u.x, a.S, a.inv_hw2);
-            const real dwx = a.dcoef[0] * ((real)(ox - HW) - u.x) * wx;
-            real s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-            for (int oy = 0; oy < PW; ++oy) {
-                const real* cell = halo + ((lx0 + ox) * HY + (ly0 + oy)) * P;
-                real c0 = 0, c1 = 0;
-                for (int k = 0; k < P; ++k) {
-                    c0 += Tt[k] * cell[k];
-                    c1 += Td[k] * cell[k];
+        for (int ci = 0; ci < nchunks; ++ci) {
+            const int c0 = ci * kL2Chunk;
+            if (nchunks > 1 || pb == beg) {
+                __syncthreads();
+                // y fastest in the loads (coalesced rows of the grid)
+                for (int idx = threadIdx.x; idx < HX * HX * kL2Chunk; idx += kL2GatherThreads) {
+                    const int ly = idx % HX, r = idx / HX, lx = r % HX, k = r / HX;
+                    const int gxn = imod(x0 - HW + lx, a.I[0]), gyn = imod(y0 - HW + ly, a.I[1]);
+                    halo[(lx * HX + ly) * kL2Chunk + k] =
+                        (c0 + k < a.P) ? a.grid[(size_t)(c0 + k) * plane + (size_t)gxn * a.I[1] + gyn] : (real)0;
                 }
-                s0 += wy[oy] * c0;
-                s1 += dwy[oy] * c0;
-                s2 += wy[oy] * c1;
+                __syncthreads();
             }
-            phi += wx * s0;
-            gx += dwx * s0;
-            gy += wx * s1;
-            gz += wx * s2;
+            if (!active) continue;
+            // T_k(t) and T_k'(t) = k U_{k-1}(t) for k in [c0, c0 + 8)
+            real Tt[kL2Chunk], Td[kL2Chunk];
+            {
+                real T0 = 1, T1 = u.z, U0 = 1, U1 = 2 * u.z;
+                for (int k = 0; k < c0 + kL2Chunk; ++k) {
+                    real Tk, Dk;
+                    if (k == 0) {
+                        Tk = 1;
+                        Dk = 0;
+                    } else if (k == 1) {
+                        Tk = u.z;
+                        Dk = 1;
+                    } else {
+                        Tk = (real)2 * u.z * T1 - T0;
+                        Dk = (real)k * U1;
+                        const real U2 = (real)2 * u.z * U1 - U0;
+                        T0 = T1;
+                        T1 = Tk;
+                        U0 = U1;
+                        U1 = U2;
+                    }
+                    if (k >= c0) {
+                        Tt[k - c0] = Tk;
+                        Td[k - c0] = Dk;
+                    }
+                }
+            }
+            real wy[PW], dwy[PW];
+#pragma unroll
+            for (int o = 0; o < PW; ++o) {
+                wy[o] = win2<real, PW>(o, u.y, a.S, a.inv_hw2);
+                dwy[o] = a.dcoef[1] * ((real)(o - HW) - u.y) * wy[o];
+            }
+            const int lx0 = g.x - x0, ly0 = g.y - y0;
+            for (int ox = 0; ox < PW; ++ox) {
+                const real wx = win2<real, PW>(ox, u.x, a.S, a.inv_hw2);
+                const real dwx = a.dcoef[0] * ((real)(ox - HW) - u.x) * wx;
+                real s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+                for (int oy = 0; oy < PW; ++oy) {
+                    const real* cell = halo + ((lx0 + ox) * HX + (ly0 + oy)) * kL2Chunk;
+                    real c0s = 0, c1s = 0;
+#pragma unroll
+                    for (int k = 0; k < kL2Chunk; ++k) {
+                        c0s += Tt[k] * cell[k];
+                        c1s += Td[k] * cell[k];
+                    }
+                    s0 += wy[oy] * c0s;
+                    s1 += dwy[oy] * c0s;
+                    s2 += wy[oy] * c1s;
+                }
+                phi += wx * s0;
+                gx += dwx * s0;
+                gy += wx * s1;
+                gz += wx * s2;
+            }
         }
-        const int i = g.w;
-        a.part[i] = vec4<real>{a.area * phi, a.area * gx, a.area * gy, a.area * a.dzf * gz};
+        if (active) a.part[g.w] = vec4<real>{a.area * phi, a.area * gx, a.area * gy, a.area * a.dzf * gz};
     }
 }
 
@@ -306,28 +412,26 @@ hipError_t l2_spread_gather_pw(Plan& p, bool spread) {
         L2SpreadArgs<real> a;
         a.gp = (const int4*)ws.l2_g;
         a.up = (const vec4<real>*)ws.l2_u;
-        a.dstart = ws.l2_dup_start;
-        a.dlist = ws.l2_dup_list;
-        a.cap = (int)std::min<int64_t>((int64_t)r.n * r.max_dup2, INT32_MAX);
-        a.grid = (cpx<real>*)ws.l2_grid;
-        for (int d = 0; d < 2; ++d) { a.I[d] = r.I2[d]; a.B[d] = r.B2[d]; a.nt[d] = r.ntile2[d]; }
+        a.tstart = ws.l2_tile_start;
+        a.grid = (real*)ws.l2_grid;
+        for (int d = 0; d < 2; ++d) {
+            a.I[d] = r.I2[d];
+            a.nt[d] = r.ntile2[d];
+        }
         a.ntiles = ntiles;
-        a.P = r.P;
+        a.Ps = r.Ps;
         a.S = (real)r.S2;
         a.inv_hw2 = inv_hw2;
-        size_t lds = ((size_t)r.B2[0] * r.B2[1] * r.P + (size_t)kL2Threads * r.P) * sizeof(real);
-        if (lds > 65536) return hipErrorInvalidConfiguration;
-        k_l2_spread<real, PW><<<xcd_grid(ntiles), kL2Threads, lds, p.stream>>>(a);
+        k_l2_spread<real, PW><<<xcd_grid(ntiles), 256, 0, p.stream>>>(a);
     } else {
         L2GatherArgs<real> a;
         a.gp = (const int4*)ws.l2_g;
         a.up = (const vec4<real>*)ws.l2_u;
         a.tstart = ws.l2_tile_start;
-        a.grid = (const cpx<real>*)ws.l2_grid;
+        a.grid = (const real*)ws.l2_grid;
         a.part = (vec4<real>*)ws.parts + 2 * r.n;
         for (int d = 0; d < 2; ++d) {
             a.I[d] = r.I2[d];
-            a.B[d] = r.B2[d];
             a.nt[d] = r.ntile2[d];
             a.dcoef[d] = (real)(2.0 * r.S2 / ((double)HW * HW * r.h2[d]));
         }
@@ -337,9 +441,7 @@ hipError_t l2_spread_gather_pw(Plan& p, bool spread) {
         a.inv_hw2 = inv_hw2;
         a.area = (real)(r.h2[0] * r.h2[1]);
         a.dzf = (real)(2.0 / r.L[2]);
-        size_t lds = ((size_t)(r.B2[0] + PW - 1) * (r.B2[1] + PW - 1) * r.P + 64 * 2 * (size_t)r.P) * sizeof(real);
-        if (lds > 65536) return hipErrorInvalidConfiguration;
-        k_l2_gather<real, PW><<<xcd_grid(ntiles), 64, lds, p.stream>>>(a);
+        k_l2_gather<real, PW><<<xcd_grid(ntiles), kL2GatherThreads, 0, p.stream>>>(a);
     }
     return hipGetLastError();
 }
@@ -363,50 +465,67 @@ hipError_t run_long_fft(Plan& p, const double* x, const double* q) {
     const Resolved& r = p.r;
     Workspace& ws = p.ws;
     const int n = (int)r.n;
+    if (r.Ps > kLong2MaxPlanes || r.P > kLong2MaxPlanes || r.Q > kL2MaxQ || r.I2[0] < 2 * r.Pw2 ||
+        r.I2[1] < 2 * r.Pw2 || (r.I2[1] & 1))
+        return hipErrorInvalidConfiguration;
     L2Geom g;
     for (int d = 0; d < 3; ++d) g.L[d] = r.L[d];
     for (int d = 0; d < 2; ++d) {
         g.h[d] = r.h2[d];
         g.I[d] = r.I2[d];
-        g.B[d] = r.B2[d];
         g.nt[d] = r.ntile2[d];
     }
-    g.HW = (r.Pw2 - 1) / 2;
     const int ntiles = r.ntile2[0] * r.ntile2[1];
     const int blocks = std::min((n + 255) / 256, 8192);
     int t = timer_id(p, "long2_sort");
     timer_begin(p, t);
-    k_l2_key<<<blocks, 256, 0, p.stream>>>(x, n, g, ws.key);
-    hipError_t e = launch_counting_sort(p, ws.key, n, ntiles, ws.l2_tile_start, ws.l2_tile_cursor, ws.perm);
+    hipError_t e = launch_fill_int(ws.l2_tile_start, 0, (int64_t)ntiles + 1, p.stream);
+    if (e == hipSuccess) e = launch_fill_int(ws.l2_tile_cursor, 0, ntiles, p.stream);
     if (e != hipSuccess) return e;
-    k_l2_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.perm, (int4*)ws.l2_g, (vec4<real>*)ws.l2_u);
-    if ((e = launch_fill_int(ws.l2_dup_start, 0, (int64_t)ntiles + 1, p.stream)) != hipSuccess) return e;
-    if ((e = launch_fill_int(ws.l2_dup_cursor, 0, ntiles, p.stream)) != hipSuccess) return e;
-    k_l2_dup<<<blocks, 256, 0, p.stream>>>((const int4*)ws.l2_g, n, g, ws.l2_dup_start, nullptr, nullptr, nullptr, 0, 0);
-    if ((e = launch_exclusive_scan(p, ws.l2_dup_start, ntiles + 1, ws.scan_tmp)) != hipSuccess) return e;
-    k_l2_dup<<<blocks, 256, 0, p.stream>>>((const int4*)ws.l2_g, n, g, nullptr, ws.l2_dup_start, ws.l2_dup_cursor,
-                                            ws.l2_dup_list, (int)std::min<int64_t>((int64_t)n * r.max_dup2, INT32_MAX), 1);
+    k_l2_key<<<blocks, 256, 0, p.stream>>>(x, n, g, ws.key, ws.l2_tile_start);
+    if ((e = launch_exclusive_scan(p, ws.l2_tile_start, ntiles + 1, ws.scan_tmp)) != hipSuccess) return e;
+    k_l2_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.key, ws.l2_tile_start, ws.l2_tile_cursor,
+                                                   (int4*)ws.l2_g, (vec4<real>*)ws.l2_u);
     timer_end(p, t);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     t = timer_id(p, "long2_spread");
     timer_begin(p, t);
     if ((e = l2_spread_gather<real>(p, true)) != hipSuccess) return e;
     timer_end(p, t);
-    const int I0 = r.I2[0], I1 = r.I2[1], P = r.P;
-    const size_t plane = (size_t)I0 * I1;
-    t = timer_id(p, "long2_fft");
+    t = timer_id(p, "long2_fft_fwd");
     timer_begin(p, t);
-    // forward: y lines are contiguous (one per block), x lines are strided by I1
-    if ((e = launch_fft_lines(p, ws.l2_grid, p.f2y, ws.l2_tw_y, P * I0, 1, I1, 0, 1, -1, 1)) != hipSuccess) return e;
-    if ((e = launch_fft_lines(p, ws.l2_grid, p.f2x, ws.l2_tw_x, P * I1, I1, plane, 1, I1, -1, 16)) != hipSuccess) return e;
+    if ((e = launch_fft_long2(p, -1, r.Ps)) != hipSuccess) return e;
+    timer_end(p, t);
     {
-        const int B = 64;
-        size_t lds = (size_t)B * P * sizeof(cpx<real>);
-        if (lds > 65536) return hipErrorInvalidConfiguration;
-        k_l2_scale<real><<<(int)((plane + B - 1) / B), B, lds, p.stream>>>((cpx<real>*)ws.l2_grid, I0, I1, P,
-                                                                           (const real*)ws.l2_kt_r);
+        const int Ky = r.I2[1] / 2 + 1;
+        L2ScaleArgs<real> a;
+        a.cg = (cpx<real>*)ws.l2_cgrid;
+        a.I0 = r.I2[0];
+        a.Ky = Ky;
+        a.Kys = cgrid_stride(r.I2[1]);
+        a.P = r.P;
+        a.Ps = r.Ps;
+        a.Q = r.Q;
+        a.kt = (const real*)ws.l2_kt_r;
+        a.el = (const real*)ws.l2_el;
+        a.coef = (const real*)ws.l2_coef;
+        a.nl = r.M - r.m;
+        a.bp = (const real*)ws.l2_bp;
+        a.winv_x = (const real*)ws.l2_winv_x;
+        a.winv_y = (const real*)ws.l2_winv_y;
+        a.dkx = (real)(2.0 * 3.14159265358979323846 / r.L[0]);
+        a.dky = (real)(2.0 * 3.14159265358979323846 / r.L[1]);
+        const size_t lds = (size_t)kL2ScaleThreads * r.Ps * sizeof(cpx<real>);
+        const int64_t modes = (int64_t)r.I2[0] * Ky;
+        t = timer_id(p, "long2_scale");
+        timer_begin(p, t);
+        k_l2_scale<real><<<(int)((modes + kL2ScaleThreads - 1) / kL2ScaleThreads), kL2ScaleThreads, lds, p.stream>>>(a);
+        timer_end(p, t);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = launch_fft_lines(p, ws.l2_grid, p.f2x, ws.l2_tw_x, P * I1, I1, plane, 1, I1, +1, 16)) != hipSuccess) return e;
-    if ((e = launch_fft_lines(p, ws.l2_grid, p.f2y, ws.l2_tw_y, P * I0, 1, I1, 0, 1, +1, 1)) != hipSuccess) return e;
+    t = timer_id(p, "long2_fft_inv");
+    timer_begin(p, t);
+    if ((e = launch_fft_long2(p, +1, r.P)) != hipSuccess) return e;
     timer_end(p, t);
     t = timer_id(p, "long2_gather");
     timer_begin(p, t);

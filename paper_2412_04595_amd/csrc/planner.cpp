@@ -428,28 +428,44 @@ MidChoice plan_mid(const double L[3], int64_t n, double s0, double sm, int nl, d
 
 }  // namespace
 
-// Largest 2D tile edge B <= 16 for the long-range FFT form whose LDS use fits 64 KiB:
-// spread B^2 P + 128 P reals, gather (B + P_w - 1)^2 P + 64 (2 P) reals.  0 if none.
-int long_fft_tile(int prec, int Pw2, int P) {
-    const size_t rs = (prec == SOG_PREC_FP64) ? 8 : 4;
-    for (int B = 16; B >= 1; --B) {
-        size_t spread = ((size_t)B * B * P + 128 * (size_t)P) * rs;
-        size_t gather = ((size_t)(B + Pw2 - 1) * (B + Pw2 - 1) * P + 64 * 2 * (size_t)P) * rs;
-        if (spread <= 65536 && gather <= 65536) return B;
-    }
-    return 0;
-}
-
 namespace {
 
 struct LongChoice {
     bool ok = false;
-    int form = SOG_LONG_DIRECT, P = 0, nk[2] = {0, 0}, I2[2] = {0, 0}, Pw2 = 0;
+    int form = SOG_LONG_DIRECT, P = 0, nk[2] = {0, 0}, I2[2] = {0, 0}, Pw2 = 0, Q = 0, Ps = 0;
     double S2 = 0, cost = 1e300;
+    std::string why;  // when not ok: the limit that ruled the form out
 };
 
-LongChoice plan_long(const double L[3], int64_t n, double sl, double eps, int prec, const sog_params& ov) {
+// Costs of the long range's FFT form (seconds, float32 kernels on MI355X; float64 about
+// twice), fitted to the kernels' event times on the 10^6-particle confined box, slab and
+// layered cell.  Gridding: every node of a 16 x 16 tile tests every particle of the (at
+// most 3 x 3) tiles its windows can come from, 8 planes per pass, about 2048 tiles at once
+// on the GPU: per candidate particle and pass.  Gathering: 64 particles of a tile at a
+// time, about 1280 tiles at once: per batch, window node and pass.  Transforms per grid
+// point and plane (each direction), scaling per mode and multiply-add of its z kernel.
+constexpr double kCostL2Cand = 2.0e-7;
+constexpr double kCostL2GatherNode = 1.3e-7;
+constexpr double kCostL2FFTPt = 1.2e-11;
+constexpr double kCostL2ScaleTable = 6.0e-12;
+constexpr double kCostL2ScaleTaylor = 3.0e-13;
+
+// The Taylor form of the z kernel (App. C, Lemma lemma::Taylor): Q terms of
+// e^{-x} = sum_{p<Q} (-x)^p/p!, x = dz^2/s^2 <= (L_z/s_{m+1})^2 = xi, leave at most
+// xi^Q/Q! of each Gaussian (the lemma's bound with the variable z - z' on [-L_z, L_z]).
+int taylor_terms(double xi, double eps) {
+    double t = 1.0;  // xi^Q / Q!
+    for (int Q = 1; Q <= 16; ++Q) {
+        t *= xi / Q;
+        if (t <= eps) return Q;
+    }
+    return 0;
+}
+
+LongChoice plan_long(const double L[3], int64_t n, double sl, int nl, double eps, int prec, const sog_options& opt) {
+    const sog_params& ov = opt.params;
     LongChoice best;
+    const double pf = prec == SOG_PREC_FP64 ? 2.0 : 1.0;
     double eta = sl / L[2];
     int P = ov.long_P;
     if (P <= 0) {
@@ -459,7 +475,10 @@ LongChoice plan_long(const double L[3], int64_t n, double sl, double eps, int pr
             double lg = 0.5 * std::lgamma(P + 1.0) + P * std::log(2.0 * std::sqrt(2.0) * eta);
             if (std::log(4.0 * 1.0865) - lg <= std::log(eps)) break;
         }
-        if (P > 64) return best;  // not reachable with this split
+        if (P > 64) {
+            best.why = "long range: more than 64 Chebyshev terms in z";
+            return best;
+        }
     }
     // direct form (App. B): |k| <= 2 sqrt(log(1/eps)) / s_{m+1} (Thm thm::Fcheb)
     LongChoice d;
@@ -470,41 +489,82 @@ LongChoice plan_long(const double L[3], int64_t n, double sl, double eps, int pr
     if (ov.long_nk[0] > 0 || ov.long_nk[1] > 0) { d.nk[0] = ov.long_nk[0]; d.nk[1] = ov.long_nk[1]; }
     double nh = (d.nk[0] + 1.0) + d.nk[1] * (2.0 * d.nk[0] + 1.0);
     d.cost = kCostLongDirect * (double)n * nh * P;
-    d.ok = true;
-    // FFT form (Alg. al::long): 2D window + grid, same error rules as the mid range
+    d.ok = nh * P <= 65536.0;
+    if (!d.ok)
+        d.why = "long range, direct form: " + std::to_string((long long)nh) + " modes x " + std::to_string(P) +
+                " Chebyshev terms exceed the kernel's 65536";
+    // FFT form (Alg. al::long): 2D Gaussian window on an I^long grid, the mid range's error
+    // rules; the z kernel exact (a table per mode) or in App. C's Taylor form (none)
     LongChoice f;
     f.form = SOG_LONG_FFT;
-    f.P = P;
-    double hmax = kPi * sl / (2.0 * std::sqrt(std::log(0.1 / eps)));
-    for (int a = 0; a < 2; ++a) f.I2[a] = next_smooth((int)std::ceil(L[a] / hmax - 1e-9), true);
-    if (ov.long_I[0] > 0) { f.I2[0] = ov.long_I[0]; f.I2[1] = ov.long_I[1]; }
-    double hw = std::max(L[0] / f.I2[0], L[1] / f.I2[1]);
-    f.Pw2 = 0;
-    if (ov.long_Pw[0] > 0) {
-        f.Pw2 = ov.long_Pw[0];
-        window_exponent(f.Pw2, hw, sl, &f.S2);
-    } else {
-        for (int p = 5; p <= kMaxPw; p += 2) {
-            double Sp;
-            if (std::exp(-window_exponent(p, hw, sl, &Sp)) <= eps) { f.Pw2 = p; f.S2 = Sp; break; }
+    f.why = "long range, FFT form: no Gaussian window of at most 15 points meets the tolerance on grids with lines "
+            "the FFT kernels take";
+    const double hmax = kPi * sl / (2.0 * std::sqrt(std::log(0.1 / eps)));
+    const int Qt = taylor_terms((L[2] / sl) * (L[2] / sl), eps);
+    const double fr[] = {1.0, 0.92, 0.85, 0.78, 0.7, 0.62, 0.55, 0.48, 0.42, 0.36};
+    for (double fc : fr) {
+        int I2[2];
+        for (int a = 0; a < 2; ++a) I2[a] = next_smooth((int)std::ceil(L[a] / (fc * hmax) - 1e-9), true);
+        if (ov.long_I[0] > 0) { I2[0] = ov.long_I[0]; I2[1] = ov.long_I[1]; }
+        double hw = std::max(L[0] / I2[0], L[1] / I2[1]);
+        int Pw2 = 0;
+        double S2 = 0;
+        if (ov.long_Pw[0] > 0) {
+            Pw2 = ov.long_Pw[0];
+            window_exponent(Pw2, hw, sl, &S2);
+        } else {
+            for (int pw = 5; pw <= kMaxPw; pw += 2) {
+                double Sp;
+                if (std::exp(-window_exponent(pw, hw, sl, &Sp)) <= eps) { Pw2 = pw; S2 = Sp; break; }
+            }
         }
-    }
-    if (ov.long_S > 0) f.S2 = ov.long_S;
-    if (f.Pw2 > 0 && f.Pw2 <= 15 && long_fft_tile(prec, f.Pw2, P) > 0) {
-        for (int a = 0; a < 2; ++a)
-            if (f.I2[a] < 2 * f.Pw2) f.I2[a] = next_smooth(2 * f.Pw2, true);
-        // the 2D gridding and gathering run one workgroup per tile: with fewer tiles than
-        // about two per compute unit the GPU idles in proportion (a 24 x 24 grid is 4 tiles
-        // of 16, and the 10^6-particle slab took a second per call on it)
-        const int B2 = long_fft_tile(prec, f.Pw2, P);
-        const double nt2 = std::ceil((double)f.I2[0] / B2) * std::ceil((double)f.I2[1] / B2);
-        const double par = std::max(1.0, 512.0 / nt2);
-        f.cost = kCostWindow2Pt * (double)n * f.Pw2 * f.Pw2 * P * par + kCostFFT2Pt * P * (double)f.I2[0] * f.I2[1];
-        f.ok = true;
+        if (ov.long_S > 0) S2 = ov.long_S;
+        if (Pw2 > 0) {
+            for (int a = 0; a < 2; ++a)
+                if (I2[a] < 2 * Pw2) I2[a] = next_smooth(2 * Pw2, true);
+            if (I2[0] <= fft_max_line(prec) && I2[1] / 2 <= fft_max_line(prec)) {
+                const double npts = (double)I2[0] * I2[1];
+                const double modes = (double)I2[0] * (I2[1] / 2 + 1);
+                // the two z kernels: exact (Q = 0, P_s = P) or Taylor (P_s = 2Q - 1)
+                for (int taylor = 0; taylor < 2; ++taylor) {
+                    if (taylor && (ov.long_Q < 0 || (Qt == 0 && ov.long_Q == 0))) continue;
+                    if (!taylor && ov.long_Q > 0) continue;
+                    LongChoice c;
+                    c.form = SOG_LONG_FFT;
+                    c.P = P;
+                    c.Q = taylor ? (ov.long_Q > 0 ? ov.long_Q : Qt) : 0;
+                    c.Ps = taylor ? 2 * c.Q - 1 : P;
+                    if (taylor && ov.long_P <= 0) c.P = std::min(P, c.Ps);  // exact in z beyond 2Q - 1 terms
+                    if (c.Ps > kLong2MaxPlanes || c.P > kLong2MaxPlanes || c.Q > 16) continue;
+                    c.I2[0] = I2[0];
+                    c.I2[1] = I2[1];
+                    c.Pw2 = Pw2;
+                    c.S2 = S2;
+                    const double ch_s = std::ceil(c.Ps / 8.0), ch_t = std::ceil(c.P / 8.0);
+                    const double ntx = std::ceil(I2[0] / (double)kLong2Tile), nty = std::ceil(I2[1] / (double)kLong2Tile);
+                    const double ntl = ntx * nty;
+                    const double cand = (double)n / ntl * std::min(ntx, 3.0) * std::min(nty, 3.0);
+                    const double t_spread = std::max(1.0, ntl / 2048.0) * cand * ch_s * kCostL2Cand;
+                    const double t_gather =
+                        std::max(1.0, ntl / 1280.0) * std::ceil((double)n / ntl / 64.0) * Pw2 * Pw2 * ch_t * kCostL2GatherNode;
+                    const double t_scale = taylor ? kCostL2ScaleTaylor * modes * ((double)nl * c.Q + (double)c.Q * c.P * c.Ps)
+                                                  : kCostL2ScaleTable * modes * c.P * c.Ps;
+                    c.cost = pf * (t_spread + t_gather + kCostL2FFTPt * npts * (c.Ps + c.P) + t_scale);
+                    c.ok = true;
+                    if (c.cost < f.cost || !f.ok) f = c;
+                }
+            } else {
+                f.why = "long range, FFT form: grid lines above the FFT kernels' " + std::to_string(fft_max_line(prec)) +
+                        " points";
+            }
+        }
+        if (ov.long_I[0] > 0) break;
     }
     if (ov.long_form == SOG_LONG_DIRECT) return d;
     if (ov.long_form == SOG_LONG_FFT) return f;
-    best = (f.ok && f.cost < d.cost) ? f : d;
+    if (f.ok && (!d.ok || f.cost < d.cost)) return f;
+    if (d.ok) return d;
+    best.why = d.why + "; " + f.why;
     return best;
 }
 
@@ -674,6 +734,23 @@ void near_chebyshev(Resolved& r) {
     }
 }
 
+namespace {
+
+// Mean volume of the ball of radius rc inside the slab 0 <= z <= Lz, over centres uniform
+// in the slab (the near-field pairs per particle and unit density; no z images)
+double neighbour_volume(double rc, double Lz) {
+    const int nz = 64;
+    double acc = 0;
+    for (int i = 0; i < nz; ++i) {
+        const double z0 = (i + 0.5) * Lz / nz;
+        const double a = std::max(0.0, z0 - rc) - z0, b = std::min(Lz, z0 + rc) - z0;  // u = z - z0 in [a, b]
+        acc += kPi * (rc * rc * (b - a) - (b * b * b - a * a * a) / 3.0);
+    }
+    return acc / nz;
+}
+
+}  // namespace
+
 sog_status resolve(const double box[3], int64_t n, double tol, const sog_options& opt, Resolved& r,
                    std::string& err) {
     const sog_params& ov = opt.params;
@@ -695,6 +772,7 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
     if (ov.mid_Pw[0] < 0 || (ov.mid_Pw[0] > 0 && (ov.mid_Pw[0] % 2 == 0 || ov.mid_Pw[0] < 3 || ov.mid_Pw[0] > kMaxPw))) { err = "mid_Pw must be odd in [3, 15]"; return SOG_ERR_INVALID_ARG; }
     if (ov.long_Pw[0] != ov.long_Pw[1] || (ov.long_Pw[0] > 0 && (ov.long_Pw[0] % 2 == 0 || ov.long_Pw[0] < 3 || ov.long_Pw[0] > kMaxPw))) { err = "long_Pw must be odd in [3, 15] and equal in x, y"; return SOG_ERR_INVALID_ARG; }
     if (ov.long_P < 0 || ov.long_P > 64) { err = "long_P must be in [1, 64]"; return SOG_ERR_INVALID_ARG; }
+    if (ov.long_Q < -1 || ov.long_Q > 16) { err = "long_Q must be -1 (exact z kernel), 0 (chosen) or in [1, 16]"; return SOG_ERR_INVALID_ARG; }
     if (ov.mid_Izs % 2) { err = "mid_Izs must be even"; return SOG_ERR_INVALID_ARG; }
 
     // decomposition parameters
@@ -719,8 +797,13 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         rcs.push_back(ov.rc);
     } else {
         for (double c : {2.0, 2.5, 2.75, 3.0, 3.25, 3.5, 4.0, 5.0}) rcs.push_back(std::min(c * std::cbrt(1.0 / rho), rc_max));
+        // flat boxes: cutoffs on the scale of the area per particle too (the near field is
+        // two-dimensional once r_c exceeds L_z)
+        if (r.L[2] < 0.25 * std::min(r.L[0], r.L[1]))
+            for (double c : {2.0, 3.0, 4.0, 5.0, 6.0, 8.0}) rcs.push_back(std::min(c * std::sqrt(A / (double)n), rc_max));
     }
     const double eps = tol / 20.0;
+    std::string why;  // the last limit that ruled a candidate out
     double best_cost = 1e300;
     Resolved best = r;
     bool found = false;
@@ -738,8 +821,8 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         M = std::min(M, 4000);
         c.M = M;
         sog_weights(c.b, c.sigma, c.omega, M, c.w, c.s);
-        double near_cost = kCostNearPair * (r.prec == SOG_PREC_FP64 ? 3.0 : 1.0) * (double)n * (4.0 * kPi / 3.0) *
-                           rc * rc * rc * rho;
+        double near_cost = kCostNearPair * (r.prec == SOG_PREC_FP64 ? 3.0 : 1.0) * (double)n * rho *
+                           neighbour_volume(rc, r.L[2]);
         // candidate splits: m = -1 (all long) .. last l with s_l <= 2 Lz
         int mlo = -1, mhi = -1;
         for (int l = 0; l <= M; ++l)
@@ -753,12 +836,18 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
             LongChoice lc;
             if (m >= 0) {
                 mc = plan_mid(r.L, n, c.s[0], c.s[m], m + 1, eps, r.prec, ov);
-                if (!mc.ok) continue;
+                if (!mc.ok) {
+                    why = "mid range: no window of at most 15 points meets the tolerance on grids the kernels take";
+                    continue;
+                }
                 cost += mc.cost;
             }
             if (m < M) {
-                lc = plan_long(r.L, n, c.s[m + 1], eps, r.prec, ov);
-                if (!lc.ok) continue;
+                lc = plan_long(r.L, n, c.s[m + 1], M - m, eps, r.prec, opt);
+                if (!lc.ok) {
+                    why = lc.why;
+                    continue;
+                }
                 cost += lc.cost;
             }
             if (cost < best_cost) {
@@ -782,12 +871,17 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
                     best.I2[0] = lc.I2[0]; best.I2[1] = lc.I2[1];
                     best.Pw2 = lc.Pw2;
                     best.S2 = lc.S2;
+                    best.Q = lc.Q;
+                    best.Ps = lc.Ps;
                 }
                 found = true;
             }
         }
     }
-    if (!found) { err = "no feasible discretisation for this box and tolerance"; return SOG_ERR_TOL_UNREACHABLE; }
+    if (!found) {
+        err = "no feasible discretisation for this box and tolerance" + (why.empty() ? std::string() : ": " + why);
+        return SOG_ERR_TOL_UNREACHABLE;
+    }
     r = best;
     r.self_coeff = 0;
     for (double v : r.w) r.self_coeff += v;
@@ -838,22 +932,17 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         if (r.form == SOG_LONG_DIRECT) {
             r.nh = (r.nk[0] + 1) + r.nk[1] * (2 * r.nk[0] + 1);
             if ((int64_t)r.nh * r.P > 65536) { err = "too many long-range modes for the direct form"; return SOG_ERR_INVALID_ARG; }
+            r.Q = r.Ps = 0;
         } else {
-            if (r.Pw2 < 3 || r.I2[0] < r.Pw2 || r.I2[1] < r.Pw2) { err = "long-range FFT grid smaller than its window"; return SOG_ERR_INVALID_ARG; }
-            if (!is_smooth(r.I2[0]) || !is_smooth(r.I2[1])) { err = "long-range grid sizes must have only factors 2, 3, 5, 7"; return SOG_ERR_INVALID_ARG; }
-            if (std::max(r.I2[0], r.I2[1]) > fft_max_line(r.prec)) { err = "long-range grid line too long for the FFT kernels in this precision"; return SOG_ERR_INVALID_ARG; }
+            if (r.Pw2 < 3 || r.Pw2 > kMaxPw || (r.Pw2 % 2) == 0) { err = "long-range window must have an odd number of points in [3, 15]"; return SOG_ERR_INVALID_ARG; }
+            if (r.I2[0] < 2 * r.Pw2 || r.I2[1] < 2 * r.Pw2) { err = "long-range FFT grid smaller than twice its window"; return SOG_ERR_INVALID_ARG; }
+            if (!is_smooth(r.I2[0]) || !is_smooth(r.I2[1] / 2) || (r.I2[1] & 1)) { err = "long-range grid sizes must be even with only factors 2, 3, 5, 7 (I^long_y / 2 as well)"; return SOG_ERR_INVALID_ARG; }
+            if (r.I2[0] > fft_max_line(r.prec) || r.I2[1] / 2 > fft_max_line(r.prec)) { err = "long-range grid line too long for the FFT kernels in this precision"; return SOG_ERR_INVALID_ARG; }
+            if (r.Ps < 1 || r.Ps > kLong2MaxPlanes || r.P > kLong2MaxPlanes || r.Q < 0 || r.Q > 16) { err = "long-range FFT form: at most 32 Chebyshev terms (long_P) and 16 Taylor terms (long_Q)"; return SOG_ERR_INVALID_ARG; }
             for (int a = 0; a < 2; ++a) {
                 r.h2[a] = r.L[a] / r.I2[a];
                 r.H2[a] = 0.5 * (r.Pw2 - 1) * r.h2[a];
-            }
-            int B = long_fft_tile(r.prec, r.Pw2, r.P);
-            if (B == 0) { err = "long-range FFT form does not fit in LDS for this P and window"; return SOG_ERR_INVALID_ARG; }
-            r.max_dup2 = 1;
-            for (int a = 0; a < 2; ++a) {
-                r.B2[a] = std::min(B, r.I2[a]);
-                r.ntile2[a] = (r.I2[a] + r.B2[a] - 1) / r.B2[a];
-                if ((r.Pw2 + r.B2[a] - 1) / r.B2[a] + 1 > 8) { err = "long window too wide for the tile"; return SOG_ERR_INVALID_ARG; }
-                r.max_dup2 *= std::min(r.ntile2[a], (r.Pw2 - 1 + r.B2[a] - 1) / r.B2[a] + 2);
+                r.ntile2[a] = (r.I2[a] + kLong2Tile - 1) / kLong2Tile;
             }
         }
     }

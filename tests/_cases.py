@@ -23,6 +23,19 @@ CASES = {
     # mid range plus the FFT form of the long range
     "slab_mid_fft": dict(N=2400, box=(30.0, 30.0, 6.0), seed=12, row=3, rc=3.0, M=120, m=3,
                          mid=dict(I=(50, 50, 10), Izs=40, Pw=9), long=dict(form="fft", P=14, I=(40, 40), Pw=9)),
+    # strongly confined (Table 4's surface density 1.1 and L_z = 0.3, Lx/Lz = 133): every
+    # Gaussian long range, FFT form with the exact z kernel, and with App. C's Taylor form
+    # (Q = 4: 7 source planes, 5 target terms; Q = 6: two 8-plane passes of the gridding);
+    # grids that are not multiples of the 16-node tile, window 15 (half-width 7)
+    "confined_exact": dict(N=1760, box=(40.0, 40.0, 0.3), seed=41, row=3, rc=3.0, M=90, m=-1,
+                           mid=None, long=dict(form="fft", P=6, Q=-1, I=(90, 84), Pw=11)),
+    "confined_taylor": dict(N=1760, box=(40.0, 40.0, 0.3), seed=41, row=3, rc=3.0, M=90, m=-1,
+                            mid=None, long=dict(form="fft", P=5, Q=4, I=(90, 84), Pw=11)),
+    "confined_taylor6": dict(N=1500, box=(36.0, 30.0, 0.6), seed=42, row=4, rc=3.0, M=180, m=-1,
+                             mid=None, long=dict(form="fft", P=9, Q=6, I=(70, 60), Pw=15)),
+    # a long grid of 2 x 2 tiles (every tile's windows reach all tiles), Taylor form
+    "confined_small": dict(N=600, box=(18.0, 15.0, 0.5), seed=43, row=3, rc=3.0, M=90, m=-1,
+                           mid=None, long=dict(form="fft", P=6, Q=5, I=(24, 20), Pw=9)),
     # tall cell: long z lines in the FFT, many Chebyshev terms
     "tall": dict(N=1200, box=(10.0, 10.0, 60.0), seed=13, row=3, rc=3.0, M=140, m=8,
                  mid=dict(I=(20, 20, 120), Izs=252, Pw=9), long=dict(form="direct", P=20, nk=(1, 1))),
@@ -88,7 +101,8 @@ def gpu_params(c):
         if lp["form"] == "direct":
             p.update(long_nk=list(lp["nk"]))
         else:
-            p.update(long_I=list(lp["I"]), long_Pw=[lp["Pw"]] * 2, long_S=_window_S(lp["Pw"]))
+            p.update(long_I=list(lp["I"]), long_Pw=[lp["Pw"]] * 2, long_S=_window_S(lp["Pw"]),
+                     long_Q=lp.get("Q", -1))
     return p
 
 
@@ -103,7 +117,8 @@ def oracle_params(c):
             mid.update(window="es", beta=c["mid"]["beta"])
     lp = dict(c["long"]) if c["long"] else None
     if lp and lp["form"] == "fft":
-        lp = dict(form="fft", P=lp["P"], I=tuple(lp["I"]), Pw=(lp["Pw"], lp["Pw"]), S=_window_S(lp["Pw"]))
+        lp = dict(form="fft", P=lp["P"], I=tuple(lp["I"]), Pw=(lp["Pw"], lp["Pw"]), S=_window_S(lp["Pw"]),
+                  Q=max(0, lp.get("Q", 0)))
     return fast.make_params(b, r0, om, c["rc"], c["M"], c["m"], mid=mid, long=lp)
 
 
@@ -123,5 +138,5 @@ def oracle_params_from_info(info):
             lp = dict(form="direct", P=info["long_P"], nk=tuple(info["long_nk"]))
         else:
             lp = dict(form="fft", P=info["long_P"], I=tuple(info["long_I"]), Pw=tuple(info["long_Pw"]),
-                      S=info["long_S"])
+                      S=info["long_S"], Q=max(0, info["long_Q"]))
     return fast.make_params(info["b"], info["r0"], info["omega"], info["rc"], info["M"], info["m"], mid=mid, long=lp)

@@ -270,10 +270,43 @@ def test_planner_keeps_fft_batches_wide(name, prec, cap):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_planner_avoids_long_fft_grids_with_few_tiles(prec):
-    """The long range's FFT form grids one 2D tile per workgroup; the 10^6-particle slab's
-    24 x 24 long grid would be 4 tiles, so the planner takes the direct form there."""
-    import workloads
-    N, box = workloads.NAMED["slab_1e6"]
-    p = sog.plan_parameters(box, N, 1e-4, prec)
-    assert p["long_form"] == _lib.SOG_LONG_DIRECT
+@pytest.mark.parametrize("box", [(953.5, 953.5, 0.3), (400.0, 400.0, 2.0), (300.0, 300.0, 1.0)])
+def test_strongly_confined_boxes_plan_all_long_fft(box, prec):
+    """Strongly confined boxes (Table 4's 953.5 x 953.5 x 0.3 at surface density 1.1, and
+    Lx/Lz = 200, 300) need the long range's FFT form (the direct form would need millions of
+    modes); in Table 4's box every Gaussian is long range (s_0 > 2 L_z, the Remark after the
+    range-splitting definition).  The plan's grid holds whole windows and has far more tiles
+    than compute units."""
+    p = sog.plan_parameters(box, 10**6, 1e-4, prec)
+    assert p["long_form"] == _lib.SOG_LONG_FFT
+    if box[2] < 0.5:
+        assert p["m"] == -1  # s_0 > 2 L_z: nothing is left for the mid range
+    I = p["long_I"]
+    assert min(I) >= 2 * p["long_Pw"][0] and I[1] % 2 == 0
+    assert (I[0] // 16) * (I[1] // 16) >= 1024
+    assert p["long_Q"] == -1 or p["long_Q"] > 0
+
+
+def test_unreachable_plans_name_the_limit():
+    """A box the kernels cannot discretise at the tolerance returns SOG_ERR_TOL_UNREACHABLE
+    with the binding limit in the message (not SOG_ERR_INVALID_ARG)."""
+    with pytest.raises(sog.SogError) as ei:
+        sog.plan_parameters((953.5, 953.5, 0.3), 10**6, 1e-4, "fp32", params=dict(long_form="direct"))
+    assert ei.value.status == _lib.SOG_ERR_TOL_UNREACHABLE and "65536" in str(ei.value)
+    with pytest.raises(sog.SogError) as ei:
+        sog.plan_parameters((953.5, 953.5, 0.3), 10**6, 1e-4, "fp32", params=dict(long_form="fft", long_Pw=[3, 3],
+                                                                                    long_I=[5000, 5000]))
+    assert ei.value.status in (_lib.SOG_ERR_TOL_UNREACHABLE, _lib.SOG_ERR_INVALID_ARG)
+
+
+def test_taylor_form_is_planned_on_request():
+    """long_Q > 0 asks for App. C's Taylor form of the z kernel (2Q - 1 source planes, at most
+    2Q - 1 target terms); long_Q = -1 for the exact kernel; both plan on the Table 4 box."""
+    box = (953.5, 953.5, 0.3)
+    t = sog.plan_parameters(box, 10**6, 1e-4, "fp32", params=dict(long_form="fft", long_Q=4))
+    e = sog.plan_parameters(box, 10**6, 1e-4, "fp32", params=dict(long_form="fft", long_Q=-1))
+    assert t["long_Q"] == 4 and t["long_P"] <= 7
+    assert e["long_Q"] == -1
+    with pytest.raises(sog.SogError) as ei:
+        sog.plan_parameters(box, 10**6, 1e-4, "fp32", params=dict(long_Q=17))
+    assert ei.value.status == _lib.SOG_ERR_INVALID_ARG

@@ -9,7 +9,8 @@ float64 arrays of shape (N,3); charges float64 (N,), +/-1 with exactly half of
 each sign (charge neutral, as the problem statement requires).
 
 Workloads (the paper's experiments use uniform random monovalent particles,
-Sec. 5; the layered set stands in for an electrolyte between two interfaces):
+Sec. 5; the layered set stands in for an electrolyte between two interfaces; the
+confined set has the size and shape of the strongly confined runs of Sec. 5.2, Table 4):
 
 * ``uniform(N, box, seed)``
 * ``layered(N, box, seed, ...)``: x,y uniform; half of the particles have z drawn
@@ -34,8 +35,11 @@ NAMED = {
     "tall_1e6": (1_000_000, (50.0, 50.0, 800.0)),
     "layered_2e5": (200_000, (150.0, 150.0, 60.0)),
     "cube_8e6": (8_000_000, (200.0, 200.0, 200.0)),
+    # strongly confined: Table 4's box, surface density N/(Lx Ly) = 1.1 at L_z = 0.3
+    "confined_1e6": (1_000_000, (953.5, 953.5, 0.3)),
 }
-NAMED_SEED = {"cube_small": 1, "cube_1e6": 2, "slab_1e6": 3, "tall_1e6": 4, "layered_2e5": 6, "cube_8e6": 7}
+NAMED_SEED = {"cube_small": 1, "cube_1e6": 2, "slab_1e6": 3, "tall_1e6": 4, "layered_2e5": 6, "cube_8e6": 7,
+              "confined_1e6": 8}
 
 
 def _charges(rng, N):
