@@ -391,12 +391,17 @@ sog_status build_plan(Plan& p) {
                     }
                 std::vector<double> kt((size_t)jx * Ky * r.P * r.P);
                 long_kernel_cheb_basis(r, k2.data(), jx * Ky, kt.data());
+                // as P^2 planes over the modes (consecutive k_y adjacent: coalesced reads),
+                // scaled by 1/What2^2 and the unnormalised inverse
+                std::vector<double> ktp(kt.size());
+                const size_t nm = (size_t)jx * Ky, pp = (size_t)r.P * r.P;
                 for (int a = 0; a < jx; ++a)
                     for (int b = 0; b < Ky; ++b) {
+                        const size_t md = (size_t)a * Ky + b;
                         const double sc = wx[a] * wy[b] * norm;
-                        for (int i = 0; i < r.P * r.P; ++i) kt[((size_t)a * Ky + b) * r.P * r.P + i] *= sc;
+                        for (size_t i = 0; i < pp; ++i) ktp[i * nm + md] = kt[md * pp + i] * sc;
                     }
-                if (e == hipSuccess) e = upload(ws.l2_kt_r, kt, f64);
+                if (e == hipSuccess) e = upload(ws.l2_kt_r, ktp, f64);
             }
         }
     }

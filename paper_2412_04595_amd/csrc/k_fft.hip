@@ -658,18 +658,29 @@ hipError_t run_fft_long2(Plan& p, int sign, int planes) {
     const cpx<T>* twy = (const cpx<T>*)ws.l2_tw_y;
     const cpx<T>* twp = (const cpx<T>*)ws.l2_tw_ypost;
     const cpx<T>* twx = (const cpx<T>*)ws.l2_tw_x;
+    hipError_t e = hipSuccess;
     if (sign < 0) {
+        int t = timer_id(p, "long2_fft_y_fwd");
+        timer_begin(p, t);
         k_fft_z_r2c<T><<<(nlines + Wz - 1) / Wz, kFFTThreads, ldsz, p.stream>>>(
             grid, cg, nlines, Iy, Kys, Wz, 0, make_udiv(m), make_udiv(m + 1), to_dev(p.f2y), twy, twp);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        timer_end(p, t);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        t = timer_id(p, "long2_fft_x_fwd");
+        timer_begin(p, t);
         k_fft_y<T, -1><<<nbx, kFFTThreads, ldsx, p.stream>>>(cg, planes, Ix, Ky, Kys, Wx, to_dev(p.f2x), twx);
+        timer_end(p, t);
     } else {
+        int t = timer_id(p, "long2_fft_x_inv");
+        timer_begin(p, t);
         k_fft_y<T, +1><<<nbx, kFFTThreads, ldsx, p.stream>>>(cg, planes, Ix, Ky, Kys, Wx, to_dev(p.f2x), twx);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        timer_end(p, t);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        t = timer_id(p, "long2_fft_y_inv");
+        timer_begin(p, t);
         k_fft_z_c2r<T><<<(nlines + Wz - 1) / Wz, kFFTThreads, ldsz, p.stream>>>(
             cg, grid, nlines, Iy, Kys, Wz, 0, make_udiv(m), make_udiv(m + 1), to_dev(p.f2y), twy, twp);
+        timer_end(p, t);
     }
     return hipGetLastError();
 }

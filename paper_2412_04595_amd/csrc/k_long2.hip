@@ -25,10 +25,10 @@
 // sum_j q_j and is left out.
 //
 // Gridding is output-stationary: a workgroup owns a 16 x 16 tile of nodes, one node per
-// thread, and sums in registers the windows of every particle whose nearest node lies in
-// a tile its windows can reach (particles counting-sorted by tile; at most three tiles per
-// direction), 8 planes per pass.  No atomics: each node is written once, in a fixed order
-// of the particles, so the grid is deterministic.  Gathering: one particle per lane,
+// thread, and sums in registers the windows of the particles that reach the tile: it reads
+// the particles of the (at most three per direction) tiles around its own (particles
+// counting-sorted by tile), keeps those whose windows reach it, and stages their weights in
+// LDS 128 at a time; 8 planes per pass.  No atomics: each node is written once.  Gathering: one particle per lane,
 // the tile's halo of the u planes staged in LDS 8 planes at a time.
 #include "device_common.hpp"
 
@@ -131,18 +131,28 @@ struct L2SpreadArgs {
     real S, inv_hw2;
 };
 
+// Whether a window starting at node c (of PW nodes, periodic line of I nodes) reaches
+// nodes [x0, x0 + e): the offset of x0 from c, taken mod I, is below PW, or c lies inside.
+__device__ __forceinline__ bool l2_reaches(int c, int PW, int x0, int e, int I) {
+    const int d = imod(x0 - c, I);      // nodes from the window's first node to x0
+    const int d2 = imod(c - x0, I);     // nodes from x0 to the window's first node
+    return d < PW || d2 < e;
+}
+
 template <typename real, int PW>
 __global__ __launch_bounds__(256) void k_l2_spread(L2SpreadArgs<real> a) {
     constexpr int HW = (PW - 1) / 2;
-    __shared__ int cxs[kL2Batch], cys[kL2Batch];
+    __shared__ int2 cs[kL2Batch];
     __shared__ real wxs[kL2Batch * PW], wys[kL2Batch * PW];
-    __shared__ real ts[kL2Batch * kL2Chunk];
+    __shared__ __align__(16) real ts[kL2Batch * kL2Chunk];
+    __shared__ int wcount[4];
     const int t = xcd_logical_block(a.ntiles);
     if (t < 0) return;
     const int tx = t / a.nt[1], ty = t % a.nt[1];
     const int x0 = tx * kL2Tile, y0 = ty * kL2Tile;
     const int ex = min(kL2Tile, a.I[0] - x0), ey = min(kL2Tile, a.I[1] - y0);
     const int lx = threadIdx.x / kL2Tile, ly = threadIdx.x % kL2Tile;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const bool valid = lx < ex && ly < ey;
     // a node outside the grid takes a far-away index that no window reaches
     const int nx = valid ? x0 + lx : -(1 << 29), ny = valid ? y0 + ly : -(1 << 29);
@@ -162,14 +172,28 @@ __global__ __launch_bounds__(256) void k_l2_spread(L2SpreadArgs<real> a) {
                 if (tn <= 0) continue;
                 const int beg = a.tstart[txx * a.nt[1] + ty0], end = a.tstart[txx * a.nt[1] + ty0 + tn];
                 for (int base = beg; base < end; base += kL2Batch) {
-                    const int nb = min(kL2Batch, end - base);
+                    // the next kL2Batch particles of the range; those whose windows reach the
+                    // tile are compacted into the staging arrays
+                    const int pi = base + (int)threadIdx.x;
+                    bool keep = false;
+                    int4 g = make_int4(0, 0, 0, 0);
+                    if ((int)threadIdx.x < kL2Batch && pi < end) {
+                        g = a.gp[pi];
+                        keep = l2_reaches(g.x - HW, PW, x0, ex, a.I[0]) && l2_reaches(g.y - HW, PW, y0, ey, a.I[1]);
+                    }
+                    const unsigned long long m = __ballot(keep);
+                    __syncthreads();  // the previous batch's staging is no longer read
+                    if (lane == 0) wcount[wid] = __popcll(m);
                     __syncthreads();
-                    if ((int)threadIdx.x < nb) {
-                        const int j = threadIdx.x;
-                        const int4 g = a.gp[base + j];
-                        const vec4<real> u = a.up[base + j];
-                        cxs[j] = g.x - HW;
-                        cys[j] = g.y - HW;
+                    int off = 0, nb = 0;
+                    for (int w = 0; w < 4; ++w) {
+                        off += w < wid ? wcount[w] : 0;
+                        nb += wcount[w];
+                    }
+                    if (keep) {
+                        const int j = off + __popcll(m & ((1ull << lane) - 1ull));
+                        const vec4<real> u = a.up[pi];
+                        cs[j] = make_int2(g.x - HW, g.y - HW);
 #pragma unroll
                         for (int o = 0; o < PW; ++o) {
                             wxs[j * PW + o] = u.w * win2<real, PW>(o, u.x, a.S, a.inv_hw2);
@@ -188,7 +212,8 @@ __global__ __launch_bounds__(256) void k_l2_spread(L2SpreadArgs<real> a) {
                     }
                     __syncthreads();
                     for (int j = 0; j < nb; ++j) {
-                        int dx = nx - cxs[j], dy = ny - cys[j];
+                        const int2 c = cs[j];
+                        int dx = nx - c.x, dy = ny - c.y;
                         dx += dx < 0 ? a.I[0] : 0;
                         dx -= dx >= a.I[0] ? a.I[0] : 0;
                         dy += dy < 0 ? a.I[1] : 0;
@@ -218,7 +243,8 @@ template <typename real>
 struct L2ScaleArgs {
     cpx<real>* cg;        // planes of I0 rows of Kys complex (k_y fastest)
     int I0, Ky, Kys, P, Ps, Q;
-    // exact form: K per mode (j_x = min(i_x, I0 - i_x), k_y), P x P_s, scaled
+    // exact form: K per (n, a) as planes over the modes (j_x = min(i_x, I0 - i_x), k_y):
+    // kt[((n P_s + a) (I0/2 + 1) + j_x) Ky + k_y], scaled
     const real* kt;
     // Taylor form: per long-range Gaussian l, e_l = s_l^2/4 and coef[l][p] (p < Q), with
     // A_p(k) = sum_l e^{-e_l |k|^2} coef[l][p]; B_p (Q x P x P_s); 1/What2^2 per direction
@@ -230,17 +256,42 @@ struct L2ScaleArgs {
     const real* winv_x;  // I0
     const real* winv_y;  // Ky
     real dkx, dky;       // 2 pi / L_x, 2 pi / L_y
+    int tables_in_lds;   // Taylor: e_l, coef and B_p staged in LDS
 };
 
-constexpr int kL2ScaleThreads = 64;
+constexpr int kL2ScaleThreads = 128;
 constexpr int kL2MaxQ = 16;
+
+// LDS of the scaling kernel: the modes' P_s source values per thread, then (Taylor, when
+// they fit) e_l, coef and B_p.
+inline size_t l2_scale_lds(int Ps, int nl, int Q, int P, size_t rs, bool tables) {
+    size_t b = (size_t)kL2ScaleThreads * Ps * 2 * rs;
+    if (tables) b += ((size_t)nl * (1 + Q) + (size_t)Q * P * Ps) * rs;
+    return b;
+}
 
 template <typename real>
 __global__ __launch_bounds__(kL2ScaleThreads) void k_l2_scale(L2ScaleArgs<real> a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<real>* rho = reinterpret_cast<cpx<real>*>(smem_raw);  // Ps x kL2ScaleThreads
+    real* tl = reinterpret_cast<real*>(rho + (size_t)a.Ps * kL2ScaleThreads);
+    const real* el = a.el;
+    const real* coef = a.coef;
+    const real* bp = a.bp;
+    if (a.Q > 0 && a.tables_in_lds) {
+        real* lel = tl;
+        real* lco = lel + a.nl;
+        real* lbp = lco + a.nl * a.Q;
+        for (int i = threadIdx.x; i < a.nl; i += kL2ScaleThreads) lel[i] = a.el[i];
+        for (int i = threadIdx.x; i < a.nl * a.Q; i += kL2ScaleThreads) lco[i] = a.coef[i];
+        for (int i = threadIdx.x; i < a.Q * a.P * a.Ps; i += kL2ScaleThreads) lbp[i] = a.bp[i];
+        __syncthreads();
+        el = lel;
+        coef = lco;
+        bp = lbp;
+    }
     const int mode = blockIdx.x * kL2ScaleThreads + threadIdx.x;
-    if (mode >= a.I0 * a.Ky) return;  // no barrier below: each thread uses only its own LDS column
+    if (mode >= a.I0 * a.Ky) return;  // no barrier below
     const int ix = mode / a.Ky, ky = mode - ix * a.Ky;
     const size_t plane = (size_t)a.I0 * a.Kys;
     cpx<real>* cell = a.cg + (size_t)ix * a.Kys + ky;
@@ -253,8 +304,8 @@ __global__ __launch_bounds__(kL2ScaleThreads) void k_l2_scale(L2ScaleArgs<real> 
 #pragma unroll
         for (int p = 0; p < kL2MaxQ; ++p) A[p] = 0;
         for (int l = 0; l < a.nl; ++l) {
-            const real e = dexp(-a.el[l] * k2);
-            const real* c = a.coef + (size_t)l * a.Q;
+            const real e = dexp(-el[l] * k2);
+            const real* c = coef + l * a.Q;
 #pragma unroll
             for (int p = 0; p < kL2MaxQ; ++p)
                 if (p < a.Q) A[p] += e * c[p];
@@ -267,7 +318,7 @@ __global__ __launch_bounds__(kL2ScaleThreads) void k_l2_scale(L2ScaleArgs<real> 
                 real kk = 0;
 #pragma unroll
                 for (int p = 0; p < kL2MaxQ; ++p)
-                    if (p < a.Q) kk += A[p] * a.bp[((size_t)p * a.P + n) * a.Ps + s];
+                    if (p < a.Q) kk += A[p] * bp[(p * a.P + n) * a.Ps + s];
                 const cpx<real> v = rho[s * kL2ScaleThreads + threadIdx.x];
                 sr += kk * v.x;
                 si += kk * v.y;
@@ -276,11 +327,12 @@ __global__ __launch_bounds__(kL2ScaleThreads) void k_l2_scale(L2ScaleArgs<real> 
         }
     } else {
         const int jx = min(ix, a.I0 - ix);
-        const real* K = a.kt + ((size_t)jx * a.Ky + ky) * a.P * a.Ps;
+        const size_t kplane = (size_t)(a.I0 / 2 + 1) * a.Ky;
+        const real* K = a.kt + (size_t)jx * a.Ky + ky;
         for (int n = 0; n < a.P; ++n) {
             real sr = 0, si = 0;
             for (int s = 0; s < a.Ps; ++s) {
-                const real kk = K[n * a.Ps + s];
+                const real kk = K[(size_t)(n * a.Ps + s) * kplane];
                 const cpx<real> v = rho[s * kL2ScaleThreads + threadIdx.x];
                 sr += kk * v.x;
                 si += kk * v.y;
@@ -492,10 +544,7 @@ hipError_t run_long_fft(Plan& p, const double* x, const double* q) {
     timer_begin(p, t);
     if ((e = l2_spread_gather<real>(p, true)) != hipSuccess) return e;
     timer_end(p, t);
-    t = timer_id(p, "long2_fft_fwd");
-    timer_begin(p, t);
     if ((e = launch_fft_long2(p, -1, r.Ps)) != hipSuccess) return e;
-    timer_end(p, t);
     {
         const int Ky = r.I2[1] / 2 + 1;
         L2ScaleArgs<real> a;
@@ -515,7 +564,10 @@ hipError_t run_long_fft(Plan& p, const double* x, const double* q) {
         a.winv_y = (const real*)ws.l2_winv_y;
         a.dkx = (real)(2.0 * 3.14159265358979323846 / r.L[0]);
         a.dky = (real)(2.0 * 3.14159265358979323846 / r.L[1]);
-        const size_t lds = (size_t)kL2ScaleThreads * r.Ps * sizeof(cpx<real>);
+        const int nl = r.M - r.m;
+        a.tables_in_lds = r.Q > 0 && l2_scale_lds(r.Ps, nl, r.Q, r.P, sizeof(real), true) <= 65536;
+        const size_t lds = l2_scale_lds(r.Ps, nl, r.Q, r.P, sizeof(real), a.tables_in_lds);
+        if (lds > 65536) return hipErrorInvalidConfiguration;
         const int64_t modes = (int64_t)r.I2[0] * Ky;
         t = timer_id(p, "long2_scale");
         timer_begin(p, t);
@@ -523,10 +575,7 @@ hipError_t run_long_fft(Plan& p, const double* x, const double* q) {
         timer_end(p, t);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    t = timer_id(p, "long2_fft_inv");
-    timer_begin(p, t);
     if ((e = launch_fft_long2(p, +1, r.P)) != hipSuccess) return e;
-    timer_end(p, t);
     t = timer_id(p, "long2_gather");
     timer_begin(p, t);
     e = l2_spread_gather<real>(p, false);

@@ -440,14 +440,14 @@ struct LongChoice {
 // Costs of the long range's FFT form (seconds, float32 kernels on MI355X; float64 about
 // twice), fitted to the kernels' event times on the 10^6-particle confined box, slab and
 // layered cell.  Gridding: every node of a 16 x 16 tile tests every particle of the (at
-// most 3 x 3) tiles its windows can come from, 8 planes per pass, about 2048 tiles at once
-// on the GPU: per candidate particle and pass.  Gathering: 64 particles of a tile at a
+// most 3 x 3) tiles its windows can come from and stages those that reach it, 8 planes
+// per pass, about 2048 tiles at once on the GPU: per candidate particle and pass.  Gathering: 64 particles of a tile at a
 // time, about 1280 tiles at once: per batch, window node and pass.  Transforms per grid
 // point and plane (each direction), scaling per mode and multiply-add of its z kernel.
-constexpr double kCostL2Cand = 2.0e-7;
+constexpr double kCostL2Cand = 1.05e-7;
 constexpr double kCostL2GatherNode = 1.3e-7;
 constexpr double kCostL2FFTPt = 1.2e-11;
-constexpr double kCostL2ScaleTable = 6.0e-12;
+constexpr double kCostL2ScaleTable = 1.3e-12;
 constexpr double kCostL2ScaleTaylor = 3.0e-13;
 
 // The Taylor form of the z kernel (App. C, Lemma lemma::Taylor): Q terms of
@@ -736,17 +736,21 @@ void near_chebyshev(Resolved& r) {
 
 namespace {
 
-// Mean volume of the ball of radius rc inside the slab 0 <= z <= Lz, over centres uniform
-// in the slab (the near-field pairs per particle and unit density; no z images)
+// Near-field work per particle and unit density: the ball of radius rc, or, in a slab
+// thinner than 2 rc (where the near field becomes two-dimensional), the ball scaled by the
+// mean z extent of the candidate ranges [z - rc, z + rc] cut to [0, L_z] over 2 rc (the
+// pair kernel tests every candidate of the 3 x 3 cell columns within that z range).
+// Thicker boxes keep the ball, to which the kernel cost constants were fitted.
 double neighbour_volume(double rc, double Lz) {
+    const double ball = (4.0 * kPi / 3.0) * rc * rc * rc;
+    if (Lz >= 2.0 * rc) return ball;
     const int nz = 64;
     double acc = 0;
     for (int i = 0; i < nz; ++i) {
         const double z0 = (i + 0.5) * Lz / nz;
-        const double a = std::max(0.0, z0 - rc) - z0, b = std::min(Lz, z0 + rc) - z0;  // u = z - z0 in [a, b]
-        acc += kPi * (rc * rc * (b - a) - (b * b * b - a * a * a) / 3.0);
+        acc += std::min(Lz, z0 + rc) - std::max(0.0, z0 - rc);
     }
-    return acc / nz;
+    return ball * (acc / nz) / (2.0 * rc);
 }
 
 }  // namespace
