@@ -64,7 +64,8 @@ def _sample_errors(name, phi, F, q):
 # cube_8e6 (8 million particles in 200^3, the same density) checks a size well above the
 # benchmark's: 560^2 x 552 grids, 8 sampled targets
 CASES = [("cube_1e6", "fp32"), ("cube_1e6", "fp64"), ("slab_1e6", "fp32"), ("slab_1e6", "fp64"), ("tall_1e6", "fp32"),
-         ("layered_2e5", "fp32"), ("layered_2e5", "fp64"), ("cube_8e6", "fp32"), ("cube_8e6", "fp64")]
+         ("layered_2e5", "fp32"), ("layered_2e5", "fp64"), ("cube_8e6", "fp32"), ("cube_8e6", "fp64"),
+         ("confined_1e6", "fp32"), ("confined_1e6", "fp64")]
 
 
 @pytest.mark.parametrize("name,precision", CASES)
@@ -82,6 +83,22 @@ def test_sampled_targets_meet_tolerance(name, precision):
     assert abs(U - 0.5 * float(q @ phi)) <= 1e-10 * float(np.sum(np.abs(q * phi)))
     Ftot = np.abs(F.sum(axis=0))
     assert np.all(Ftot <= TOL * np.sum(np.abs(F), axis=0))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_confined_taylor_form(precision):
+    """The 10^6-particle strongly confined box (Table 4's size and shape) with the long
+    range's z kernel in App. C's Taylor form (long_Q = 4: 7 source planes) instead of the
+    planner's choice: sampled targets within the tolerance."""
+    name = "confined_1e6"
+    print(f"[gpu] {name} {precision}, Taylor form of the z kernel", flush=True)
+    x, q, box = workloads.named(name)
+    U, phi, F, info = _device_solve(name, precision, x, q, params=dict(long_form="fft", long_Q=4))
+    assert info["long_Q"] == 4 and info["m"] == -1
+    ephi, eF = _sample_errors(name, phi, F, q)
+    print(f"    rc={info['rc']:.3f} I={info['long_I']} Pw={info['long_Pw'][0]} P={info['long_P']}: "
+          f"phi {ephi:.2e} F {eF:.2e}", flush=True)
+    assert ephi < TOL and eF < TOL
 
 
 def test_x_pass_with_multipliers_in_global_memory():
