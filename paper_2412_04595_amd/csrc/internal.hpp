@@ -201,6 +201,8 @@ inline int64_t near_unit_slots(const Resolved& r) {
     return r.n / kNearChunk + ncols * near_chunk_extra(r.nc[2]);
 }
 
+struct RecLaunch;  // launch.hpp
+
 struct KernelTimer {
     const char* name;
     double total_ms = 0;
@@ -293,6 +295,8 @@ struct Plan {
     size_t region_bytes = 0;
     bool static_region = false;
     std::vector<std::pair<void**, size_t>> region_slots;
+    // when set, kernel launches are recorded here instead of launched (batches, launch.hpp)
+    std::vector<RecLaunch>* rec = nullptr;
     std::vector<KernelTimer> timers;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
@@ -312,8 +316,8 @@ void set_error(const std::string& msg);
 
 // kernel launchers (k_*.hip); every launcher checks its own shapes on the host
 struct Timed;  // RAII helper in api.cpp
-hipError_t launch_fill_int(int* p, int value, int64_t n, hipStream_t s);
-hipError_t launch_fill_bytes_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_fill_int(Plan& p, int* ptr, int value, int64_t n);
+hipError_t launch_fill_bytes_zero(Plan& p, void* ptr, size_t bytes);
 // per-system charge sums and flags of a batch of systems stored one after another
 // (off: nsys + 1 device offsets; lz: nsys heights; qsum: 2 nsys; status: nsys)
 hipError_t launch_batch_check(const double* x, const double* q, const int64_t* off, int nsys, const double* lz,

@@ -19,7 +19,7 @@
 // thread holds its butterflies in registers across a stage; small DFTs with constant
 // coefficients; twiddles e^{-2 pi i t/n} from a float64-built table staged in LDS), and
 // stored.  Each pass reads and writes the grid once.
-#include "device_common.hpp"
+#include "launch.hpp"
 
 namespace sog {
 
@@ -315,16 +315,15 @@ int lines_per_block(int n) {
 // are zero rows of the batch.  LDS rows have pitch W + 1, so the line-to-row transpose of
 // the load and the k-ordered reads of the split hit distinct banks.
 template <typename T>
-__global__ __launch_bounds__(kFFTThreads) void k_fft_z_r2c(const T* __restrict__ grid, cpx<T>* __restrict__ cg,
-                                                           int nlines, int Izs, int Kzs, int W, int t0, UDiv span,
-                                                           UDiv m1, FFTDev f, const cpx<T>* __restrict__ tw,
-                                                           const cpx<T>* __restrict__ twpost) {
+struct FFTZr2cK {
+    static constexpr int kThreads = kFFTThreads;
+    __device__ static void run(GridPos gpos, const T* __restrict__ grid, cpx<T>* __restrict__ cg, int nlines, int Izs, int Kzs, int W, int t0, UDiv span, UDiv m1, const FFTDev& f, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twpost) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int m = f.n, P = W + 1, lw = __ffs(W) - 1;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);  // (m + 1) rows of pitch P
     cpx<T>* twl = A + (m + 1) * P;                     // m
     cpx<T>* tpl = twl + m;                             // m + 1
-    const int line0 = blockIdx.x * W;
+    const int line0 = gpos.bid * W;
     const size_t hz = (size_t)(Izs / 2);
     const cpx<T>* rows = reinterpret_cast<const cpx<T>*>(grid);
     for (int idx = threadIdx.x; idx < (m - span.d) * W; idx += kFFTThreads) {
@@ -359,6 +358,7 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_z_r2c(const T* __restrict__
         cg[(size_t)line * Kzs + k] = cadd(ev, cmul(tpl[k], od));
     }
 }
+};
 
 // Z_k of the packed inverse from X_k and conj X_{m-k}: (X_k + conj X_{m-k}) + i (X_k -
 // conj X_{m-k}) e^{+2 pi i k / I_z*}
@@ -372,16 +372,15 @@ __device__ __forceinline__ cpx<T> c2r_pre(cpx<T> xk, cpx<T> xmkc, cpx<T> tp) {
 // 5. complex-to-real along z (unnormalised inverse); only the pairs [t0, t0 + span) are
 // stored (the planes the gathering reads).
 template <typename T>
-__global__ __launch_bounds__(kFFTThreads) void k_fft_z_c2r(const cpx<T>* __restrict__ cg, T* __restrict__ grid,
-                                                           int nlines, int Izs, int Kzs, int W, int t0, UDiv span,
-                                                           UDiv m1, FFTDev f, const cpx<T>* __restrict__ tw,
-                                                           const cpx<T>* __restrict__ twpost) {
+struct FFTZc2rK {
+    static constexpr int kThreads = kFFTThreads;
+    __device__ static void run(GridPos gpos, const cpx<T>* __restrict__ cg, T* __restrict__ grid, int nlines, int Izs, int Kzs, int W, int t0, UDiv span, UDiv m1, const FFTDev& f, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twpost) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int m = f.n, P = W + 1, lw = __ffs(W) - 1;
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* twl = A + (m + 1) * P;
     cpx<T>* tpl = twl + m;
-    const int line0 = blockIdx.x * W;
+    const int line0 = gpos.bid * W;
     const size_t hz = (size_t)(Izs / 2);
     stage_in<T>(A, m1.d * W,
                 [&](int e) {
@@ -414,16 +413,18 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_z_c2r(const cpx<T>* __restr
         rows[(size_t)line * hz + t] = A[t * P + w];
     }
 }
+};
 
 // 2./4. complex FFT along y for (x, a batch of W consecutive k_z)
 template <typename T, int SIGN>
-__global__ __launch_bounds__(kFFTThreads) void k_fft_y(cpx<T>* __restrict__ cg, int Ix, int Iy, int Kz, int Kzs, int W,
-                                                       FFTDev f, const cpx<T>* __restrict__ tw) {
+struct FFTYK {
+    static constexpr int kThreads = kFFTThreads;
+    __device__ static void run(GridPos gpos, cpx<T>* __restrict__ cg, int Ix, int Iy, int Kz, int Kzs, int W, const FFTDev& f, const cpx<T>* __restrict__ tw) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* twl = A + Iy * W;
     const int nkb = (Kz + W - 1) / W;
-    const int ix = blockIdx.x / nkb, kz0 = (blockIdx.x % nkb) * W;
+    const int ix = gpos.bid / nkb, kz0 = (gpos.bid % nkb) * W;
     if (ix >= Ix) return;
     const int lw = __ffs(W) - 1;
     cpx<T>* base = cg + (size_t)ix * Iy * Kzs + kz0;
@@ -441,23 +442,22 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_y(cpx<T>* __restrict__ cg, 
         if (w < nw) base[(size_t)iy * Kzs + w] = A[idx];
     }
 }
+};
 
 // 3. forward FFT along x, the SOG multiplier, inverse FFT along x.  The multiplier is
 // sum_l c_l ax_l(k_x) ay_l(k_y) az_l(k_z): the block's (k_y, k_z) factors are staged in
 // LDS, and ax too when it fits (AXLDS); otherwise ax is read from global memory (L2).
 template <typename T, bool AXLDS>
-__global__ __launch_bounds__(kFFTThreads) void k_fft_x_scale(cpx<T>* __restrict__ cg, int Ix, int Iy, int Kz, int Kzs,
-                                                             int W,
-                                                             FFTDev f, const cpx<T>* __restrict__ tw, int nl,
-                                                             const T* __restrict__ ax, const T* __restrict__ ay,
-                                                             const T* __restrict__ az, const T* __restrict__ cl) {
+struct FFTXScaleK {
+    static constexpr int kThreads = kFFTThreads;
+    __device__ static void run(GridPos gpos, cpx<T>* __restrict__ cg, int Ix, int Iy, int Kz, int Kzs, int W, const FFTDev& f, const cpx<T>* __restrict__ tw, int nl, const T* __restrict__ ax, const T* __restrict__ ay, const T* __restrict__ az, const T* __restrict__ cl) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* twl = A + Ix * W;
     T* cyz = reinterpret_cast<T*>(twl + Ix);  // nl x W
     T* axl = cyz + nl * W;                    // AXLDS: nl x Ix, then kStageK (256 / W) - Ix zeros
     const int nkb = (Kz + W - 1) / W;
-    const int iy = blockIdx.x / nkb, kz0 = (blockIdx.x % nkb) * W;
+    const int iy = gpos.bid / nkb, kz0 = (gpos.bid % nkb) * W;
     if (iy >= Iy) return;
     const int lw = __ffs(W) - 1;
     const size_t stride = (size_t)Iy * Kzs;
@@ -526,6 +526,7 @@ __global__ __launch_bounds__(kFFTThreads) void k_fft_x_scale(cpx<T>* __restrict_
         if (w < nw) base[(size_t)ix * stride + w] = A[idx];
     }
 }
+};
 
 template <typename T>
 hipError_t run_fft_mid(Plan& p) {
@@ -551,11 +552,11 @@ hipError_t run_fft_mid(Plan& p) {
     {
         int t = timer_id(p, "fft_z_fwd");
         timer_begin(p, t);
-        k_fft_z_r2c<T><<<(nlines + Wz - 1) / Wz, kFFTThreads, ldsz, p.stream>>>(
-            (const T*)ws.grid, (cpx<T>*)ws.cgrid, nlines, Izs, Kzs, Wz, t0, make_udiv(span), make_udiv(m + 1),
-            to_dev(p.fz), (const cpx<T>*)ws.tw_z, (const cpx<T>*)ws.tw_zpost);
+        e = launch<FFTZr2cK<T>>(p, (nlines + Wz - 1) / Wz, ldsz, (const T*)ws.grid, (cpx<T>*)ws.cgrid, nlines, Izs, Kzs,
+                                Wz, t0, make_udiv(span), make_udiv(m + 1), to_dev(p.fz), (const cpx<T>*)ws.tw_z,
+                                (const cpx<T>*)ws.tw_zpost);
         timer_end(p, t);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (e != hipSuccess) return e;
     }
     // 2. y forward
     int Wy = lines_per_block<T>(Iy);
@@ -566,10 +567,10 @@ hipError_t run_fft_mid(Plan& p) {
     {
         int t = timer_id(p, "fft_y_fwd");
         timer_begin(p, t);
-        k_fft_y<T, -1><<<nby, kFFTThreads, ldsy, p.stream>>>((cpx<T>*)ws.cgrid, Ix, Iy, Kz, Kzs, Wy, to_dev(p.fy),
-                                                             (const cpx<T>*)ws.tw_y);
+        e = launch<FFTYK<T, -1>>(p, nby, ldsy, (cpx<T>*)ws.cgrid, Ix, Iy, Kz, Kzs, Wy, to_dev(p.fy),
+                                 (const cpx<T>*)ws.tw_y);
         timer_end(p, t);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (e != hipSuccess) return e;
     }
     // 3. x forward, scale, x inverse
     {
@@ -592,34 +593,34 @@ hipError_t run_fft_mid(Plan& p) {
         int t = timer_id(p, "fft_x_scale");
         timer_begin(p, t);
         if (axlds)
-            k_fft_x_scale<T, true><<<nb, kFFTThreads, lds, p.stream>>>(
-                (cpx<T>*)ws.cgrid, Ix, Iy, Kz, Kzs, W, to_dev(p.fx), (const cpx<T>*)ws.tw_x, nl, (const T*)ws.mult_ax,
-                (const T*)ws.mult_ay, (const T*)ws.mult_az, (const T*)ws.mult_c);
+            e = launch<FFTXScaleK<T, true>>(p, nb, lds, (cpx<T>*)ws.cgrid, Ix, Iy, Kz, Kzs, W, to_dev(p.fx),
+                                            (const cpx<T>*)ws.tw_x, nl, (const T*)ws.mult_ax, (const T*)ws.mult_ay,
+                                            (const T*)ws.mult_az, (const T*)ws.mult_c);
         else
-            k_fft_x_scale<T, false><<<nb, kFFTThreads, lds, p.stream>>>(
-                (cpx<T>*)ws.cgrid, Ix, Iy, Kz, Kzs, W, to_dev(p.fx), (const cpx<T>*)ws.tw_x, nl, (const T*)ws.mult_ax,
-                (const T*)ws.mult_ay, (const T*)ws.mult_az, (const T*)ws.mult_c);
+            e = launch<FFTXScaleK<T, false>>(p, nb, lds, (cpx<T>*)ws.cgrid, Ix, Iy, Kz, Kzs, W, to_dev(p.fx),
+                                             (const cpx<T>*)ws.tw_x, nl, (const T*)ws.mult_ax, (const T*)ws.mult_ay,
+                                             (const T*)ws.mult_az, (const T*)ws.mult_c);
         timer_end(p, t);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (e != hipSuccess) return e;
     }
     // 4. y inverse
     {
         int t = timer_id(p, "fft_y_inv");
         timer_begin(p, t);
-        k_fft_y<T, +1><<<nby, kFFTThreads, ldsy, p.stream>>>((cpx<T>*)ws.cgrid, Ix, Iy, Kz, Kzs, Wy, to_dev(p.fy),
-                                                             (const cpx<T>*)ws.tw_y);
+        e = launch<FFTYK<T, +1>>(p, nby, ldsy, (cpx<T>*)ws.cgrid, Ix, Iy, Kz, Kzs, Wy, to_dev(p.fy),
+                                 (const cpx<T>*)ws.tw_y);
         timer_end(p, t);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (e != hipSuccess) return e;
     }
     // 5. z inverse
     {
         int t = timer_id(p, "fft_z_inv");
         timer_begin(p, t);
-        k_fft_z_c2r<T><<<(nlines + Wz - 1) / Wz, kFFTThreads, ldsz, p.stream>>>(
-            (const cpx<T>*)ws.cgrid, (T*)ws.grid, nlines, Izs, Kzs, Wz, t0, make_udiv(span), make_udiv(m + 1),
-            to_dev(p.fz), (const cpx<T>*)ws.tw_z, (const cpx<T>*)ws.tw_zpost);
+        e = launch<FFTZc2rK<T>>(p, (nlines + Wz - 1) / Wz, ldsz, (const cpx<T>*)ws.cgrid, (T*)ws.grid, nlines, Izs, Kzs,
+                                Wz, t0, make_udiv(span), make_udiv(m + 1), to_dev(p.fz), (const cpx<T>*)ws.tw_z,
+                                (const cpx<T>*)ws.tw_zpost);
         timer_end(p, t);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
@@ -662,27 +663,27 @@ hipError_t run_fft_long2(Plan& p, int sign, int planes) {
     if (sign < 0) {
         int t = timer_id(p, "long2_fft_y_fwd");
         timer_begin(p, t);
-        k_fft_z_r2c<T><<<(nlines + Wz - 1) / Wz, kFFTThreads, ldsz, p.stream>>>(
-            grid, cg, nlines, Iy, Kys, Wz, 0, make_udiv(m), make_udiv(m + 1), to_dev(p.f2y), twy, twp);
+        e = launch<FFTZr2cK<T>>(p, (nlines + Wz - 1) / Wz, ldsz, (const T*)grid, cg, nlines, Iy, Kys, Wz, 0,
+                                make_udiv(m), make_udiv(m + 1), to_dev(p.f2y), twy, twp);
         timer_end(p, t);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (e != hipSuccess) return e;
         t = timer_id(p, "long2_fft_x_fwd");
         timer_begin(p, t);
-        k_fft_y<T, -1><<<nbx, kFFTThreads, ldsx, p.stream>>>(cg, planes, Ix, Ky, Kys, Wx, to_dev(p.f2x), twx);
+        e = launch<FFTYK<T, -1>>(p, nbx, ldsx, cg, planes, Ix, Ky, Kys, Wx, to_dev(p.f2x), twx);
         timer_end(p, t);
     } else {
         int t = timer_id(p, "long2_fft_x_inv");
         timer_begin(p, t);
-        k_fft_y<T, +1><<<nbx, kFFTThreads, ldsx, p.stream>>>(cg, planes, Ix, Ky, Kys, Wx, to_dev(p.f2x), twx);
+        e = launch<FFTYK<T, +1>>(p, nbx, ldsx, cg, planes, Ix, Ky, Kys, Wx, to_dev(p.f2x), twx);
         timer_end(p, t);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (e != hipSuccess) return e;
         t = timer_id(p, "long2_fft_y_inv");
         timer_begin(p, t);
-        k_fft_z_c2r<T><<<(nlines + Wz - 1) / Wz, kFFTThreads, ldsz, p.stream>>>(
-            cg, grid, nlines, Iy, Kys, Wz, 0, make_udiv(m), make_udiv(m + 1), to_dev(p.f2y), twy, twp);
+        e = launch<FFTZc2rK<T>>(p, (nlines + Wz - 1) / Wz, ldsz, (const cpx<T>*)cg, grid, nlines, Iy, Kys, Wz, 0,
+                                make_udiv(m), make_udiv(m + 1), to_dev(p.f2y), twy, twp);
         timer_end(p, t);
     }
-    return hipGetLastError();
+    return e;
 }
 
 }  // namespace

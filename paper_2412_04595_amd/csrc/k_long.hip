@@ -16,7 +16,7 @@
 //
 // Moments are summed per block in the working precision and across blocks in float64
 // in a fixed order.
-#include "device_common.hpp"
+#include "launch.hpp"
 
 namespace sog {
 
@@ -33,8 +33,7 @@ struct MomArgs {
     int nkx, nky, nh, P;
     int per_block;  // particles per block
     int chunk;      // particles per LDS batch (<= kMomThreads)
-    int item0, nitems;
-    int group;      // threads per item in this launch (they split the particles)
+    int nitems;
     double* mu;     // blocks x nh x P complex
 };
 
@@ -50,7 +49,17 @@ __device__ __forceinline__ void mode_of(int kk, int nkx, int* nx, int* ny) {
 }
 
 template <typename real>
-__global__ __launch_bounds__(kMomThreads) void k_long_moments(MomArgs<real> a) {
+struct MomentsK {
+    static constexpr int kThreads = kMomThreads;
+    // every item (mode, 4 degrees) in chunks of kMomThreads items, G = group(chunk) threads per item
+    __device__ static void run(GridPos gpos, const MomArgs<real>& a) {
+        for (int i0 = 0; i0 < a.nitems; i0 += kMomThreads) {
+            const int left = min(kMomThreads, a.nitems - i0);
+            __syncthreads();  // the previous chunk's reduction has read its LDS
+            chunk(gpos, a, i0, max(1, kMomThreads / left));
+        }
+    }
+    __device__ static void chunk(GridPos gpos, const MomArgs<real>& a, int item0, int G) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int CH = a.chunk, P = a.P;
     const int NX = 2 * a.nkx + 1, NY = a.nky + 1;
@@ -59,9 +68,8 @@ __global__ __launch_bounds__(kMomThreads) void k_long_moments(MomArgs<real> a) {
     cpx<real>* ey = ex + NX * CH;                                     // NY x CH
     cpx<real>* red = ey + NY * CH;                                    // kMomThreads x 4
     const int PB = (P + 3) / 4;
-    const int G = a.group;
     const int item_l = threadIdx.x / G, sub = threadIdx.x - item_l * G;
-    const int item = a.item0 + item_l;
+    const int item = item0 + item_l;
     const bool act = item_l * G + G <= kMomThreads && item < a.nitems;
     const int kk = act ? item / PB : 0;
     const int n0 = act ? (item % PB) * 4 : 0;
@@ -70,7 +78,7 @@ __global__ __launch_bounds__(kMomThreads) void k_long_moments(MomArgs<real> a) {
     cpx<real> acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = cpx<real>{0, 0};
-    const int pbeg = blockIdx.x * a.per_block;
+    const int pbeg = gpos.bid * a.per_block;
     const int pend = min(a.n, pbeg + a.per_block);
     const double kx0 = 2.0 * 3.14159265358979323846 / a.L[0], ky0 = 2.0 * 3.14159265358979323846 / a.L[1];
     for (int s = pbeg; s < pend; s += CH) {
@@ -149,23 +157,24 @@ __global__ __launch_bounds__(kMomThreads) void k_long_moments(MomArgs<real> a) {
                 sr += (double)v.x;
                 si += (double)v.y;
             }
-            double* o = a.mu + 2 * (((size_t)blockIdx.x * a.nh + kk) * P + nn);
+            double* o = a.mu + 2 * (((size_t)gpos.bid * a.nh + kk) * P + nn);
             o[0] = sr;
             o[1] = si;
         }
     }
 }
+};
 
 // one block per mode: float64 sum over blocks (each thread a strided subset, then a
 // fixed-order tree in LDS), then a = (w_k/A) Kt mu
 constexpr int kContractThreads = 256;
 template <typename real>
-__global__ __launch_bounds__(kContractThreads) void k_long_contract(const double* __restrict__ mu, int nblocks, int nh,
-                                                                   int P, const double* __restrict__ kt, double invA,
-                                                                   cpx<real>* __restrict__ aout) {
+struct ContractK {
+    static constexpr int kThreads = kContractThreads;
+    __device__ static void run(GridPos gpos, const double* __restrict__ mu, int nblocks, int nh, int P, const double* __restrict__ kt, double invA, cpx<real>* __restrict__ aout) {
     __shared__ double smu[2 * 64];
     __shared__ double tre[kContractThreads], tim[kContractThreads];
-    const int k = blockIdx.x;
+    const int k = gpos.bid;
     for (int nn = 0; nn < P; ++nn) {
         double sr = 0, si = 0;
         for (int b = threadIdx.x; b < nblocks; b += kContractThreads) {
@@ -200,6 +209,7 @@ __global__ __launch_bounds__(kContractThreads) void k_long_contract(const double
         aout[(size_t)k * P + nn] = cpx<real>{(real)(wk * sr), (real)(wk * si)};
     }
 }
+};
 
 template <typename real>
 struct EvalArgs {
@@ -213,22 +223,24 @@ struct EvalArgs {
 
 // STAGED: the coefficient table (nh x P) is copied to LDS; otherwise (a table larger than
 // LDS) it is read where it is, through scalar loads (every thread reads the same entry)
-template <typename real, bool STAGED>
-__global__ void k_long_eval(EvalArgs<real> a) {
+template <typename real, bool STAGED, int B>
+struct EvalK {
+    static constexpr int kThreads = B;
+    __device__ static void run(GridPos gpos, const EvalArgs<real>& a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int P = a.P, nh = a.nh;
     cpx<real>* sa = reinterpret_cast<cpx<real>*>(smem_raw);  // nh x P when staged
     real* Tt = reinterpret_cast<real*>(sa + (STAGED ? nh * P : 0));  // P x blockDim: T_n(t)
-    real* Td = Tt + P * blockDim.x;                           // P x blockDim: dT_n/dt
+    real* Td = Tt + P * kThreads;                           // P x blockDim: dT_n/dt
     using ctab = const __attribute__((address_space(4))) cpx<real>;
     ctab* ga = (ctab*)a.acoef;
     if (STAGED) {
-        for (int idx = threadIdx.x; idx < nh * P; idx += blockDim.x) sa[idx] = a.acoef[idx];
+        for (int idx = threadIdx.x; idx < nh * P; idx += kThreads) sa[idx] = a.acoef[idx];
     }
     __syncthreads();
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gpos.bid * kThreads + threadIdx.x;
     if (i >= a.n) return;
-    const int B = blockDim.x, t = threadIdx.x;
+    const int t = threadIdx.x;
     double xx = a.x[3 * i], yy = a.x[3 * i + 1], zz = a.x[3 * i + 2];
     if (!(isfinite(xx) && isfinite(yy) && isfinite(zz))) xx = yy = zz = 0;
     const double xc = wrap_periodic(xx, a.L[0]) - 0.5 * a.L[0];
@@ -297,6 +309,7 @@ __global__ void k_long_eval(EvalArgs<real> a) {
     }
     a.part[i] = vec4<real>{phi, gx, gy, gz * (real)(2.0 / a.L[2])};
 }
+};
 
 template <typename real>
 hipError_t run_long_direct(Plan& p, const double* x, const double* q) {
@@ -328,20 +341,15 @@ hipError_t run_long_direct(Plan& p, const double* x, const double* q) {
     const size_t lds = lds_of(CH);
     int t = timer_id(p, "long_moments");
     timer_begin(p, t);
-    for (int i0 = 0; i0 < nitems; i0 += kMomThreads) {
-        a.item0 = i0;
-        a.group = std::max(1, kMomThreads / std::min(kMomThreads, nitems - i0));
-        k_long_moments<real><<<nb, kMomThreads, lds, p.stream>>>(a);
-    }
+    hipError_t e = launch<MomentsK<real>>(p, nb, lds, a);
     timer_end(p, t);
-    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     t = timer_id(p, "long_contract");
     timer_begin(p, t);
-    k_long_contract<real><<<nh, kContractThreads, 0, p.stream>>>(ws.long_mu, nb, nh, P, ws.long_kt, 1.0 / (r.L[0] * r.L[1]),
-                                                   (cpx<real>*)ws.long_a);
+    e = launch<ContractK<real>>(p, nh, 0, (const double*)ws.long_mu, nb, nh, P, (const double*)ws.long_kt,
+                                1.0 / (r.L[0] * r.L[1]), (cpx<real>*)ws.long_a);
     timer_end(p, t);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (e != hipSuccess) return e;
     EvalArgs<real> ea;
     ea.x = x;
     ea.n = n;
@@ -364,12 +372,15 @@ hipError_t run_long_direct(Plan& p, const double* x, const double* q) {
     }
     t = timer_id(p, "long_eval");
     timer_begin(p, t);
+    const int nbl = (n + B - 1) / B;
     if (staged)
-        k_long_eval<real, true><<<(n + B - 1) / B, B, lds2, p.stream>>>(ea);
+        e = B == 256 ? launch<EvalK<real, true, 256>>(p, nbl, lds2, ea)
+                     : (B == 128 ? launch<EvalK<real, true, 128>>(p, nbl, lds2, ea) : launch<EvalK<real, true, 64>>(p, nbl, lds2, ea));
     else
-        k_long_eval<real, false><<<(n + B - 1) / B, B, lds2, p.stream>>>(ea);
+        e = B == 256 ? launch<EvalK<real, false, 256>>(p, nbl, lds2, ea)
+                     : (B == 128 ? launch<EvalK<real, false, 128>>(p, nbl, lds2, ea) : launch<EvalK<real, false, 64>>(p, nbl, lds2, ea));
     timer_end(p, t);
-    return hipGetLastError();
+    return e;
 }
 
 }  // namespace

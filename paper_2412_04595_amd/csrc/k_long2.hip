@@ -30,7 +30,7 @@
 // counting-sorted by tile), keeps those whose windows reach it, and stages their weights in
 // LDS 128 at a time; 8 planes per pass.  No atomics: each node is written once.  Gathering: one particle per lane,
 // the tile's halo of the u planes staged in LDS 8 planes at a time.
-#include "device_common.hpp"
+#include "launch.hpp"
 
 namespace sog {
 
@@ -59,9 +59,10 @@ __device__ __forceinline__ void grid_point2(const L2Geom& g, double x, double y,
     }
 }
 
-__global__ void k_l2_key(const double* __restrict__ x, int n, L2Geom g, int* __restrict__ key,
-                         int* __restrict__ count) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+struct L2KeyK {
+    static constexpr int kThreads = 256;
+    __device__ static void run(GridPos gpos, const double* __restrict__ x, int n, L2Geom g, int* __restrict__ key, int* __restrict__ count) {
+    for (int i = gpos.bid * kThreads + threadIdx.x; i < n; i += gpos.nb * kThreads) {
         int a[2];
         double u[2];
         grid_point2(g, x[3 * i], x[3 * i + 1], a, u);
@@ -70,12 +71,13 @@ __global__ void k_l2_key(const double* __restrict__ x, int n, L2Geom g, int* __r
         atomicAdd(&count[t], 1);
     }
 }
+};
 
 template <typename real>
-__global__ void k_l2_pack(const double* __restrict__ x, const double* __restrict__ q, int n, L2Geom g,
-                          const int* __restrict__ key, const int* __restrict__ start, int* __restrict__ cursor,
-                          int4* __restrict__ gp, vec4<real>* __restrict__ up) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+struct L2PackK {
+    static constexpr int kThreads = 256;
+    __device__ static void run(GridPos gpos, const double* __restrict__ x, const double* __restrict__ q, int n, L2Geom g, const int* __restrict__ key, const int* __restrict__ start, int* __restrict__ cursor, int4* __restrict__ gp, vec4<real>* __restrict__ up) {
+    for (int i = gpos.bid * kThreads + threadIdx.x; i < n; i += gpos.nb * kThreads) {
         int a[2];
         double u[2];
         grid_point2(g, x[3 * i], x[3 * i + 1], a, u);
@@ -95,6 +97,7 @@ __global__ void k_l2_pack(const double* __restrict__ x, const double* __restrict
         up[p] = v;
     }
 }
+};
 
 // The Gaussian window of eq. GS at node o of a P_w-point window, for a particle at offset
 // u in [-1/2, 1/2] (grid units) from its nearest node: exp(-S d^2 / HW^2), d = o - HW - u.
@@ -140,13 +143,15 @@ __device__ __forceinline__ bool l2_reaches(int c, int PW, int x0, int e, int I) 
 }
 
 template <typename real, int PW>
-__global__ __launch_bounds__(256) void k_l2_spread(L2SpreadArgs<real> a) {
+struct L2SpreadK {
+    static constexpr int kThreads = 256;
+    __device__ static void run(GridPos gpos, const L2SpreadArgs<real>& a) {
     constexpr int HW = (PW - 1) / 2;
     __shared__ int2 cs[kL2Batch];
     __shared__ real wxs[kL2Batch * PW], wys[kL2Batch * PW];
     __shared__ __align__(16) real ts[kL2Batch * kL2Chunk];
     __shared__ int wcount[4];
-    const int t = xcd_logical_block(a.ntiles);
+    const int t = xcd_logical(a.ntiles, gpos);
     if (t < 0) return;
     const int tx = t / a.nt[1], ty = t % a.nt[1];
     const int x0 = tx * kL2Tile, y0 = ty * kL2Tile;
@@ -236,6 +241,7 @@ __global__ __launch_bounds__(256) void k_l2_spread(L2SpreadArgs<real> a) {
         }
     }
 }
+};
 
 // Scaling of every mode of the half spectrum: uhat(k, n) = sum_a K(k)[n][a] Shat2(k, a),
 // n < P, a < P_s, in place (a thread reads all P_s planes of its mode before it writes).
@@ -271,7 +277,9 @@ inline size_t l2_scale_lds(int Ps, int nl, int Q, int P, size_t rs, bool tables)
 }
 
 template <typename real>
-__global__ __launch_bounds__(kL2ScaleThreads) void k_l2_scale(L2ScaleArgs<real> a) {
+struct L2ScaleK {
+    static constexpr int kThreads = kL2ScaleThreads;
+    __device__ static void run(GridPos gpos, const L2ScaleArgs<real>& a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cpx<real>* rho = reinterpret_cast<cpx<real>*>(smem_raw);  // Ps x kL2ScaleThreads
     real* tl = reinterpret_cast<real*>(rho + (size_t)a.Ps * kL2ScaleThreads);
@@ -290,7 +298,7 @@ __global__ __launch_bounds__(kL2ScaleThreads) void k_l2_scale(L2ScaleArgs<real> 
         coef = lco;
         bp = lbp;
     }
-    const int mode = blockIdx.x * kL2ScaleThreads + threadIdx.x;
+    const int mode = gpos.bid * kL2ScaleThreads + threadIdx.x;
     if (mode >= a.I0 * a.Ky) return;  // no barrier below
     const int ix = mode / a.Ky, ky = mode - ix * a.Ky;
     const size_t plane = (size_t)a.I0 * a.Kys;
@@ -341,6 +349,7 @@ __global__ __launch_bounds__(kL2ScaleThreads) void k_l2_scale(L2ScaleArgs<real> 
         }
     }
 }
+};
 
 template <typename real>
 struct L2GatherArgs {
@@ -356,11 +365,13 @@ struct L2GatherArgs {
 constexpr int kL2GatherThreads = 64;
 
 template <typename real, int PW>
-__global__ __launch_bounds__(kL2GatherThreads) void k_l2_gather(L2GatherArgs<real> a) {
+struct L2GatherK {
+    static constexpr int kThreads = kL2GatherThreads;
+    __device__ static void run(GridPos gpos, const L2GatherArgs<real>& a) {
     constexpr int HW = (PW - 1) / 2;
     constexpr int HX = kL2Tile + PW - 1;
     __shared__ real halo[HX * HX * kL2Chunk];  // (lx, ly, k), k fastest
-    const int t = xcd_logical_block(a.ntiles);
+    const int t = xcd_logical(a.ntiles, gpos);
     if (t < 0) return;
     const int beg = a.tstart[t], end = a.tstart[t + 1];
     if (beg == end) return;
@@ -452,6 +463,7 @@ __global__ __launch_bounds__(kL2GatherThreads) void k_l2_gather(L2GatherArgs<rea
         if (active) a.part[g.w] = vec4<real>{a.area * phi, a.area * gx, a.area * gy, a.area * a.dzf * gz};
     }
 }
+};
 
 template <typename real, int PW>
 hipError_t l2_spread_gather_pw(Plan& p, bool spread) {
@@ -474,7 +486,7 @@ hipError_t l2_spread_gather_pw(Plan& p, bool spread) {
         a.Ps = r.Ps;
         a.S = (real)r.S2;
         a.inv_hw2 = inv_hw2;
-        k_l2_spread<real, PW><<<xcd_grid(ntiles), 256, 0, p.stream>>>(a);
+        return launch<L2SpreadK<real, PW>>(p, xcd_grid(ntiles), 0, a);
     } else {
         L2GatherArgs<real> a;
         a.gp = (const int4*)ws.l2_g;
@@ -493,9 +505,8 @@ hipError_t l2_spread_gather_pw(Plan& p, bool spread) {
         a.inv_hw2 = inv_hw2;
         a.area = (real)(r.h2[0] * r.h2[1]);
         a.dzf = (real)(2.0 / r.L[2]);
-        k_l2_gather<real, PW><<<xcd_grid(ntiles), kL2GatherThreads, 0, p.stream>>>(a);
+        return launch<L2GatherK<real, PW>>(p, xcd_grid(ntiles), 0, a);
     }
-    return hipGetLastError();
 }
 
 template <typename real>
@@ -531,15 +542,15 @@ hipError_t run_long_fft(Plan& p, const double* x, const double* q) {
     const int blocks = std::min((n + 255) / 256, 8192);
     int t = timer_id(p, "long2_sort");
     timer_begin(p, t);
-    hipError_t e = launch_fill_int(ws.l2_tile_start, 0, (int64_t)ntiles + 1, p.stream);
-    if (e == hipSuccess) e = launch_fill_int(ws.l2_tile_cursor, 0, ntiles, p.stream);
-    if (e != hipSuccess) return e;
-    k_l2_key<<<blocks, 256, 0, p.stream>>>(x, n, g, ws.key, ws.l2_tile_start);
-    if ((e = launch_exclusive_scan(p, ws.l2_tile_start, ntiles + 1, ws.scan_tmp)) != hipSuccess) return e;
-    k_l2_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, ws.key, ws.l2_tile_start, ws.l2_tile_cursor,
-                                                   (int4*)ws.l2_g, (vec4<real>*)ws.l2_u);
+    hipError_t e = launch_fill_int(p, ws.l2_tile_start, 0, (int64_t)ntiles + 1);
+    if (e == hipSuccess) e = launch_fill_int(p, ws.l2_tile_cursor, 0, ntiles);
+    if (e == hipSuccess) e = launch<L2KeyK>(p, blocks, 0, x, n, g, ws.key, ws.l2_tile_start);
+    if (e == hipSuccess) e = launch_exclusive_scan(p, ws.l2_tile_start, ntiles + 1, ws.scan_tmp);
+    if (e == hipSuccess)
+        e = launch<L2PackK<real>>(p, blocks, 0, x, q, n, g, (const int*)ws.key, (const int*)ws.l2_tile_start,
+                                  ws.l2_tile_cursor, (int4*)ws.l2_g, (vec4<real>*)ws.l2_u);
     timer_end(p, t);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (e != hipSuccess) return e;
     t = timer_id(p, "long2_spread");
     timer_begin(p, t);
     if ((e = l2_spread_gather<real>(p, true)) != hipSuccess) return e;
@@ -571,9 +582,9 @@ hipError_t run_long_fft(Plan& p, const double* x, const double* q) {
         const int64_t modes = (int64_t)r.I2[0] * Ky;
         t = timer_id(p, "long2_scale");
         timer_begin(p, t);
-        k_l2_scale<real><<<(int)((modes + kL2ScaleThreads - 1) / kL2ScaleThreads), kL2ScaleThreads, lds, p.stream>>>(a);
+        e = launch<L2ScaleK<real>>(p, (unsigned)((modes + kL2ScaleThreads - 1) / kL2ScaleThreads), lds, a);
         timer_end(p, t);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (e != hipSuccess) return e;
     }
     if ((e = launch_fft_long2(p, +1, r.P)) != hipSuccess) return e;
     t = timer_id(p, "long2_gather");

@@ -12,7 +12,7 @@
 // the tiles into launches whose blocks never overlap).  Gathering: the workgroup of a
 // tile loads the tile plus halo into LDS and evaluates Phi and grad Phi for its
 // particles.
-#include "device_common.hpp"
+#include "launch.hpp"
 
 namespace sog {
 
@@ -50,9 +50,10 @@ __device__ __forceinline__ void grid_point(const MidGeom& g, double x, double y,
 
 // tile of every particle's nearest node and its rank within the tile (the counting sort's
 // histogram)
-__global__ void k_mid_key(const double* __restrict__ x, int n, MidGeom g, int2* __restrict__ key,
-                          int* __restrict__ count) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+struct MidKeyK {
+    static constexpr int kThreads = 256;
+    __device__ static void run(GridPos gpos, const double* __restrict__ x, int n, MidGeom g, int2* __restrict__ key, int* __restrict__ count) {
+    for (int i = gpos.bid * kThreads + threadIdx.x; i < n; i += gpos.nb * kThreads) {
         int a[3];
         double u[3];
         grid_point(g, x[3 * i], x[3 * i + 1], x[3 * i + 2], a, u);
@@ -63,15 +64,16 @@ __global__ void k_mid_key(const double* __restrict__ x, int n, MidGeom g, int2* 
         key[i] = make_int2(kb, atomicAdd(&count[kb], 1));
     }
 }
+};
 
 // Scatter of the counting sort: each particle's grid point and offset record written at
 // its place in tile order, tile start plus rank (particles read in their own order, no
 // atomics).
 template <typename real>
-__global__ void k_mid_pack(const double* __restrict__ x, const double* __restrict__ q, int n, MidGeom g,
-                           const int2* __restrict__ key, const int* __restrict__ start,
-                           int4* __restrict__ gp, vec4<real>* __restrict__ up) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+struct MidPackK {
+    static constexpr int kThreads = 256;
+    __device__ static void run(GridPos gpos, const double* __restrict__ x, const double* __restrict__ q, int n, MidGeom g, const int2* __restrict__ key, const int* __restrict__ start, int4* __restrict__ gp, vec4<real>* __restrict__ up) {
+    for (int i = gpos.bid * kThreads + threadIdx.x; i < n; i += gpos.nb * kThreads) {
         const int2 kr = key[i];
         const int p = start[kr.x] + kr.y;
         int a[3];
@@ -88,6 +90,7 @@ __global__ void k_mid_pack(const double* __restrict__ x, const double* __restric
         up[p] = v;
     }
 }
+};
 
 // The window on the P_w nodes nearest a particle, at offset d = node - particle (units of
 // h): the truncated Gaussian exp(-S d^2 / HW^2), |d| <= HW (eq. GS), or the ES window
@@ -175,7 +178,9 @@ struct SpreadArgs {
 // zero weight, a dummy node of the same plane that no window node uses (DUMMY) or its
 // private sink slot.
 template <typename real, int PW, bool DUMMY>
-__global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
+struct SpreadK {
+    static constexpr int kThreads = kSpreadThreads;
+    __device__ static void run(GridPos gpos, const SpreadArgs<real>& a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int HW = (PW - 1) / 2;
     constexpr int NPASS = (PW * PW + 63) / 64;   // groups of 64 (y, z) window nodes
@@ -183,7 +188,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
     constexpr int NPAD = 4 * NPL - PW;           // padding planes after the block
     constexpr int NW = 2 * PW + 1;               // staged y, z weights and a zero per particle
     static_assert(NPL <= 4, "window too wide for four plane groups");
-    const int t = xcd_logical_block(a.ntiles);
+    const int t = xcd_logical(a.ntiles, gpos);
     if (t < 0) return;
     const int tz = t % a.nt[2], ty = (t / a.nt[2]) % a.nt[1], tx = t / (a.nt[2] * a.nt[1]);
     const int beg = a.tstart[t * kMidSub], end = a.tstart[(t + 1) * kMidSub];
@@ -335,18 +340,22 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread(SpreadArgs<real> a) {
             if (v[j] != (real)0) atomicAdd(a.grid + at[j], v[j]);
     }
 }
+};
 
 // zero planes [zlo, zlo + 2 span2) of every (x, y) line of the real grid, one wave per
 // line (the other planes are never read or written)
 template <typename real>
-__global__ __launch_bounds__(256) void k_zero_band(real* __restrict__ grid, int nlines, int Izs, int zlo, int span2) {
+struct ZeroBandK {
+    static constexpr int kThreads = 256;
+    __device__ static void run(GridPos gpos, real* __restrict__ grid, int nlines, int Izs, int zlo, int span2) {
     struct alignas(2 * sizeof(real)) pair { real a, b; };
     const int lane = threadIdx.x & 63;
-    for (int line = blockIdx.x * 4 + (threadIdx.x >> 6); line < nlines; line += gridDim.x * 4) {
+    for (int line = gpos.bid * 4 + (threadIdx.x >> 6); line < nlines; line += gpos.nb * 4) {
         pair* row = reinterpret_cast<pair*>(grid + (size_t)line * Izs + zlo);
         for (int c = lane; c < span2; c += 64) row[c] = pair{0, 0};
     }
 }
+};
 
 template <typename real>
 struct GatherArgs {
@@ -367,10 +376,12 @@ struct GatherArgs {
 constexpr int kGatherChunk = 256;  // particles sorted and dealt to the lanes at a time (the block size)
 
 template <typename real, int PW>
-__global__ __launch_bounds__(kGatherChunk) void k_gather(GatherArgs<real> a) {
+struct GatherK {
+    static constexpr int kThreads = kGatherChunk;
+    __device__ static void run(GridPos gpos, const GatherArgs<real>& a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     real* halo = reinterpret_cast<real*>(smem_raw);
-    const int t = xcd_logical_block(a.ntiles);
+    const int t = xcd_logical(a.ntiles, gpos);
     if (t < 0) return;
     const int beg = a.tstart[t * kMidSub], end = a.tstart[(t + 1) * kMidSub];
     if (beg == end) return;
@@ -383,7 +394,7 @@ __global__ __launch_bounds__(kGatherChunk) void k_gather(GatherArgs<real> a) {
     // up to kHaloILP x planes, whose loads are all in flight together
     const int nch = (HX + kHaloILP - 1) / kHaloILP;
     const size_t plane = (size_t)a.I[1] * a.I[2];
-    for (int it = threadIdx.x; it < HYZ * nch; it += blockDim.x) {
+    for (int it = threadIdx.x; it < HYZ * nch; it += kThreads) {
         const int c = it / HYZ, k = it - c * HYZ;
         const int ly = k / HZ, lz = k - ly * HZ;
         const int gz = z0 - HW + lz;
@@ -476,6 +487,7 @@ __global__ __launch_bounds__(kGatherChunk) void k_gather(GatherArgs<real> a) {
         __syncthreads();  // the next chunk reuses rcount and order
     }
 }
+};
 
 template <typename real, int PW>
 hipError_t spread_gather_pw(Plan& p, bool spread) {
@@ -504,14 +516,11 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         const size_t lds = spread_lds_bytes(sizeof(real), PW, r.B[0], r.B[1], r.B[2]);
         if (lds > tile_lds_budget(PW, sizeof(real))) return hipErrorInvalidConfiguration;
         const int nlines = r.I[0] * r.I[1];
-        k_zero_band<real><<<std::min((nlines + 3) / 4, 16384), 256, 0, p.stream>>>(
-            (real*)ws.grid, nlines, r.Izs, r.zband[0], (r.zband[1] - r.zband[0]) / 2);
-        hipError_t e = hipGetLastError();
+        hipError_t e = launch<ZeroBandK<real>>(p, std::min((nlines + 3) / 4, 16384), 0, (real*)ws.grid, nlines, r.Izs,
+                                               r.zband[0], (r.zband[1] - r.zband[0]) / 2);
         if (e != hipSuccess) return e;
-        if (r.spread_dummy)
-            k_spread<real, PW, true><<<xcd_grid(ntiles), kSpreadThreads, lds, p.stream>>>(a);
-        else
-            k_spread<real, PW, false><<<xcd_grid(ntiles), kSpreadThreads, lds, p.stream>>>(a);
+        if (r.spread_dummy) return launch<SpreadK<real, PW, true>>(p, xcd_grid(ntiles), lds, a);
+        return launch<SpreadK<real, PW, false>>(p, xcd_grid(ntiles), lds, a);
     } else {
         GatherArgs<real> a;
         a.gp = (const int4*)ws.mid_g;
@@ -532,9 +541,8 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         size_t lds = (size_t)(r.B[0] + PW - 1) * (r.B[1] + PW - 1) * (r.B[2] + PW - 1) * sizeof(real);
         // plus the static residue sort: 128 + kGatherChunk ints
         if (lds + (128 + kGatherChunk) * sizeof(int) > tile_lds_budget(PW, sizeof(real))) return hipErrorInvalidConfiguration;
-        k_gather<real, PW><<<xcd_grid(ntiles), kGatherChunk, lds, p.stream>>>(a);
+        return launch<GatherK<real, PW>>(p, xcd_grid(ntiles), lds, a);
     }
-    return hipGetLastError();
 }
 
 template <typename real>
@@ -578,13 +586,13 @@ hipError_t run_mid_prepare(Plan& p, const double* x, const double* q) {
     const int ntiles = r.ntile[0] * r.ntile[1] * r.ntile[2];
     const int blocks = std::min((n + 255) / 256, 8192);
     const int nbins = ntiles * kMidSub;
-    hipError_t e = launch_fill_int(ws.tile_start, 0, (int64_t)nbins + 1, p.stream);
-    if (e != hipSuccess) return e;
-    k_mid_key<<<blocks, 256, 0, p.stream>>>(x, n, g, (int2*)ws.key2, ws.tile_start);
-    if ((e = launch_exclusive_scan(p, ws.tile_start, nbins + 1, ws.scan_tmp2)) != hipSuccess) return e;
-    k_mid_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, (const int2*)ws.key2, ws.tile_start,
-                                                    (int4*)ws.mid_g, (vec4<real>*)ws.mid_u);
-    return hipGetLastError();
+    hipError_t e = launch_fill_int(p, ws.tile_start, 0, (int64_t)nbins + 1);
+    if (e == hipSuccess) e = launch<MidKeyK>(p, blocks, 0, x, n, g, (int2*)ws.key2, ws.tile_start);
+    if (e == hipSuccess) e = launch_exclusive_scan(p, ws.tile_start, nbins + 1, ws.scan_tmp2);
+    if (e == hipSuccess)
+        e = launch<MidPackK<real>>(p, blocks, 0, x, q, n, g, (const int2*)ws.key2, (const int*)ws.tile_start,
+                                   (int4*)ws.mid_g, (vec4<real>*)ws.mid_u);
+    return e;
 }
 
 }  // namespace

@@ -23,7 +23,7 @@
 // box would.  A candidate is seen from a target shifted by the geometric offset of their
 // columns and frames; that shift is an exact zero for the target's own column and frame,
 // so the pair of a particle with itself has r^2 == 0 exactly.
-#include "device_common.hpp"
+#include "launch.hpp"
 
 namespace sog {
 
@@ -54,13 +54,13 @@ __device__ __forceinline__ void cell_of(const NearGeom& g, double xw, double yw,
 // (status bits 1 and 2), and the charge sums sum q, sum |q| for the neutrality test of
 // Prop. lem::summation (block b adds into slot b mod kQsumSlots; the host adds the
 // slots).  Block sums need blockDim.x a multiple of 64.
-__global__ __launch_bounds__(256) void k_near_key(const double* __restrict__ x, const double* __restrict__ q, int n,
-                                                  NearGeom g, int2* __restrict__ key, int* __restrict__ count,
-                                                  double* __restrict__ qsum, int* __restrict__ status) {
+struct NearKeyK {
+    static constexpr int kThreads = 256;
+    __device__ static void run(GridPos gpos, const double* __restrict__ x, const double* __restrict__ q, int n, NearGeom g, int2* __restrict__ key, int* __restrict__ count, double* __restrict__ qsum, int* __restrict__ status) {
     __shared__ double red[16];
     double s = 0, sa = 0;
     int flags = 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (int i = gpos.bid * kThreads + threadIdx.x; i < n; i += gpos.nb * kThreads) {
         const double x0 = x[3 * i], y0 = x[3 * i + 1], z0 = x[3 * i + 2], qq = q[i];
         if (!(isfinite(x0) && isfinite(y0) && isfinite(z0) && isfinite(qq))) {
             flags |= 1;
@@ -80,21 +80,22 @@ __global__ __launch_bounds__(256) void k_near_key(const double* __restrict__ x, 
         key[i] = make_int2(k, atomicAdd(&count[k], 1));  // cell and rank within it
     }
     if (flags) atomicOr(status, flags);
-    double* slot = qsum + 2 * (blockIdx.x % kQsumSlots);  // spread over slots: few adds per address
+    double* slot = qsum + 2 * (gpos.bid % kQsumSlots);  // spread over slots: few adds per address
     double t = block_sum_double(s, red);
     if (threadIdx.x == 0) atomicAdd(&slot[0], t);
     t = block_sum_double(sa, red);
     if (threadIdx.x == 0) atomicAdd(&slot[1], t);
 }
+};
 
 // Scatter of the counting sort, writing each particle's packed record at its place in
 // cell order, cell start plus the rank the histogram pass gave it (particles read in their
 // own order, records written once, no atomics).
 template <typename real>
-__global__ void k_near_pack(const double* __restrict__ x, const double* __restrict__ q, int n, NearGeom g,
-                            const int2* __restrict__ key, const int* __restrict__ start,
-                            vec4<real>* __restrict__ pos, int* __restrict__ orig) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+struct NearPackK {
+    static constexpr int kThreads = 256;
+    __device__ static void run(GridPos gpos, const double* __restrict__ x, const double* __restrict__ q, int n, NearGeom g, const int2* __restrict__ key, const int* __restrict__ start, vec4<real>* __restrict__ pos, int* __restrict__ orig) {
+    for (int i = gpos.bid * kThreads + threadIdx.x; i < n; i += gpos.nb * kThreads) {
         const int2 kr = key[i];
         const int p = start[kr.x] + kr.y;
         double xw = wrap_periodic(x[3 * i], g.L[0]), yw = wrap_periodic(x[3 * i + 1], g.L[1]);
@@ -115,6 +116,7 @@ __global__ void k_near_pack(const double* __restrict__ x, const double* __restri
         orig[p] = i;
     }
 }
+};
 
 // Work units: each column's cells grouped greedily into runs of at most kNearUnitCells
 // cells and kNearUnitTargets particles; unit = (column, first cell, end cell), stored in
@@ -123,10 +125,11 @@ __global__ void k_near_pack(const double* __restrict__ x, const double* __restri
 // starts are read in parallel into LDS, then lane 0 walks them.
 constexpr int kUnitsLds = 4096;  // cells of a column staged in LDS at a time
 constexpr int kGrabStride = 32;  // ints between the per-XCD work counters (own 128-byte lines)
-__global__ __launch_bounds__(64) void k_near_units(const int* __restrict__ cell_start, int ncz,
-                                                    int4* __restrict__ units, int* __restrict__ grab) {
+struct NearUnitsK {
+    static constexpr int kThreads = 64;
+    __device__ static void run(GridPos gpos, const int* __restrict__ cell_start, int ncz, int4* __restrict__ units, int* __restrict__ grab) {
     __shared__ int cs[kUnitsLds + 1];
-    const int col = blockIdx.x;
+    const int col = gpos.bid;
     if (col == 0 && threadIdx.x < 8) grab[threadIdx.x * kGrabStride] = 0;  // the pair kernel's work counters
     const int* gcs = cell_start + (size_t)col * ncz;
     int4* us = units + (size_t)col * ncz;
@@ -154,16 +157,18 @@ __global__ __launch_bounds__(64) void k_near_units(const int* __restrict__ cell_
     u = __shfl(u, 0, 64);
     for (int i = u + (int)threadIdx.x; i < ncz; i += 64) us[i] = make_int4(col, -1, -1, 0);
 }
+};
 
 // Work units of the float32 pair kernel: chunks of at most kNearChunk consecutive targets
 // of a column, cut where a chunk would span more than kNearUnitCells cells; unit =
 // (cell of the first target, first target, end target, end cell), in the column's slots
 // (see near_unit_slots), unused slots marked by -1.  One wave per column: the column's
 // cell starts are staged in LDS when they fit, and lane 0 walks them.
-__global__ __launch_bounds__(64) void k_near_chunks(const int* __restrict__ cell_start, int ncz, int extra,
-                                                     int4* __restrict__ units, int* __restrict__ grab) {
+struct NearChunksK {
+    static constexpr int kThreads = 64;
+    __device__ static void run(GridPos gpos, const int* __restrict__ cell_start, int ncz, int extra, int4* __restrict__ units, int* __restrict__ grab) {
     __shared__ int cs_lds[kUnitsLds + 1];
-    const int col = blockIdx.x;
+    const int col = gpos.bid;
     if (col == 0 && threadIdx.x < 8) grab[threadIdx.x * kGrabStride] = 0;  // the pair kernel's work counters
     const int* gcs = cell_start + (size_t)col * ncz;
     const int* cs = gcs;
@@ -182,6 +187,7 @@ __global__ __launch_bounds__(64) void k_near_chunks(const int* __restrict__ cell
     u = __shfl(u, 0, 64);
     for (int64_t i = s0 + u + (int)threadIdx.x; i < s1; i += 64) units[i] = make_int4(0, -1, -1, 0);
 }
+};
 
 // Particles of each cell sorted by z.  The columns become z-ordered,
 // so a chunk of consecutive targets spans the least z and the candidates of a neighbour
@@ -193,15 +199,15 @@ __global__ __launch_bounds__(64) void k_near_chunks(const int* __restrict__ cell
 // bisection off for the call.
 constexpr int kZsortMax = 256;
 template <typename real>
-__global__ __launch_bounds__(256) void k_near_zsort(const int* __restrict__ cell_start, int ncells,
-                                                     vec4<real>* __restrict__ pos, int* __restrict__ orig,
-                                                     int* __restrict__ status) {
+struct NearZsortK {
+    static constexpr int kThreads = 256;
+    __device__ static void run(GridPos gpos, const int* __restrict__ cell_start, int ncells, vec4<real>* __restrict__ pos, int* __restrict__ orig, int* __restrict__ status) {
     __shared__ real key_all[4][kZsortMax];
     __shared__ int idx_all[4][kZsortMax];
     __shared__ vec4<real> rec_all[4][kZsortMax];
     __shared__ int org_all[4][kZsortMax];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int c = blockIdx.x * 4 + wv;
+    const int c = gpos.bid * 4 + wv;
     if (c >= ncells) return;
     const int b = cell_start[c], n = cell_start[c + 1] - b;
     if (n <= 1) return;
@@ -285,6 +291,7 @@ __global__ __launch_bounds__(256) void k_near_zsort(const int* __restrict__ cell
         orig[b + i] = org[src];
     }
 }
+};
 
 // the 8 work counters live after the units, on 128-byte boundaries
 inline int* near_grab(const Workspace& ws, int64_t slots) {
@@ -365,7 +372,9 @@ __device__ __forceinline__ void near_pair(const NearArgs<real>& a, real rx, real
 // have similar lengths.  A pair is the particle with itself exactly when r^2 == 0 (same
 // stored coordinates, zero shift); that pair is skipped.
 template <typename real, int DEG>
-__global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
+struct NearK {
+    static constexpr int kThreads = 64 * kNearWaves;
+    __device__ static void run(GridPos gpos, const NearArgs<real>& a) {
     __shared__ uint32_t hits_all[kNearWaves][kNearCap * 64];
     __shared__ vec4<real> shift_all[kNearWaves][18];
     // the candidates' addresses are the same in every lane: read them through the
@@ -379,8 +388,8 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
     // time from that eighth's counter, so that neighbouring columns share an L2 and the
     // waves finish together
     const int per = (a.max_units + 7) >> 3;
-    const int ibeg = (blockIdx.x & 7) * per, iend = min(a.max_units, ibeg + per);
-    int* grab = a.grab + (blockIdx.x & 7) * kGrabStride;
+    const int ibeg = (gpos.bid & 7) * per, iend = min(a.max_units, ibeg + per);
+    int* grab = a.grab + (gpos.bid & 7) * kGrabStride;
     const bool trim = (__builtin_amdgcn_readfirstlane(*a.status) & 4) == 0;
     for (;;) {
     int g = 0;
@@ -535,6 +544,7 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near(NearArgs<real> a) {
     }
     }
 }
+};
 
 // The float32 pair kernel with the candidate test on the matrix cores.  A pass takes 32
 // targets; lanes l and l + 32 share target l % 32 and split its candidates between their
@@ -586,7 +596,9 @@ __device__ __forceinline__ void near_pair_nz(const NearArgs<float>& a, float rx,
 }
 
 template <int DEG>
-__global__ __launch_bounds__(64 * kNearWaves) void k_near_mfma(NearArgs<float> a) {
+struct NearMfmaK {
+    static constexpr int kThreads = 64 * kNearWaves;
+    __device__ static void run(GridPos gpos, const NearArgs<float>& a) {
     __shared__ uint32_t hits_all[kNearWaves][kNearCap * 64];
     __shared__ vec4<float> shift_all[kNearWaves][18];
     __shared__ alignas(16) uint32_t codes_all[kNearWaves][32];
@@ -598,8 +610,8 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near_mfma(NearArgs<float> a
     static_assert(kNearCap * 256 == 8192, "list slot bits 8..12 between the lane and wave bits");
     const uint32_t lb = (uint32_t)wv * (kNearCap * 256) | (uint32_t)lane * 4;
     const int per = (a.max_units + 7) >> 3;
-    const int ibeg = (blockIdx.x & 7) * per, iend = min(a.max_units, ibeg + per);
-    int* grab = a.grab + (blockIdx.x & 7) * kGrabStride;
+    const int ibeg = (gpos.bid & 7) * per, iend = min(a.max_units, ibeg + per);
+    int* grab = a.grab + (gpos.bid & 7) * kGrabStride;
     const float fh = (float)kNearFrameCells * a.ch[2];  // frame height
     const bool trim = (__builtin_amdgcn_readfirstlane(*a.status) & 4) == 0;
     for (;;) {
@@ -802,28 +814,29 @@ __global__ __launch_bounds__(64 * kNearWaves) void k_near_mfma(NearArgs<float> a
     }
     }
 }
+};
 
 // polynomial degrees compiled; the fitted degree is rounded up to one of these
 template <typename real, int DEG>
-void launch_near_deg(const NearArgs<real>& a, int blocks, hipStream_t st) {
+hipError_t launch_near_deg(Plan& p, const NearArgs<real>& a, int blocks) {
     if constexpr (sizeof(real) == 4)
-        k_near_mfma<DEG><<<blocks, 64 * kNearWaves, 0, st>>>(a);
+        return launch<NearMfmaK<DEG>>(p, blocks, 0, a);
     else
-        k_near<real, DEG><<<blocks, 64 * kNearWaves, 0, st>>>(a);
+        return launch<NearK<real, DEG>>(p, blocks, 0, a);
 }
 
 template <typename real>
-void launch_near_kernel(const NearArgs<real>& a, int blocks, hipStream_t st) {
-    if (a.deg <= 8) launch_near_deg<real, 8>(a, blocks, st);
-    else if (a.deg <= 10) launch_near_deg<real, 10>(a, blocks, st);
-    else if (a.deg <= 12) launch_near_deg<real, 12>(a, blocks, st);
-    else if (a.deg <= 14) launch_near_deg<real, 14>(a, blocks, st);
-    else if (a.deg <= 16) launch_near_deg<real, 16>(a, blocks, st);
-    else if (a.deg <= 20) launch_near_deg<real, 20>(a, blocks, st);
-    else if (a.deg <= 24) launch_near_deg<real, 24>(a, blocks, st);
-    else if (a.deg <= 32) launch_near_deg<real, 32>(a, blocks, st);
-    else if (a.deg <= 48) launch_near_deg<real, 48>(a, blocks, st);
-    else launch_near_deg<real, kMaxNearDeg>(a, blocks, st);
+hipError_t launch_near_kernel(Plan& p, const NearArgs<real>& a, int blocks) {
+    if (a.deg <= 8) return launch_near_deg<real, 8>(p, a, blocks);
+    if (a.deg <= 10) return launch_near_deg<real, 10>(p, a, blocks);
+    if (a.deg <= 12) return launch_near_deg<real, 12>(p, a, blocks);
+    if (a.deg <= 14) return launch_near_deg<real, 14>(p, a, blocks);
+    if (a.deg <= 16) return launch_near_deg<real, 16>(p, a, blocks);
+    if (a.deg <= 20) return launch_near_deg<real, 20>(p, a, blocks);
+    if (a.deg <= 24) return launch_near_deg<real, 24>(p, a, blocks);
+    if (a.deg <= 32) return launch_near_deg<real, 32>(p, a, blocks);
+    if (a.deg <= 48) return launch_near_deg<real, 48>(p, a, blocks);
+    return launch_near_deg<real, kMaxNearDeg>(p, a, blocks);
 }
 
 template <typename real>
@@ -844,26 +857,29 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
         const int t = timer_id(p, "near_sort");
         timer_begin(p, t);
         const int blocks = std::min((n + 255) / 256, 8192);
-        hipError_t e = launch_fill_int(ws.cell_start, 0, (int64_t)ncells + 1, p.stream);
-        if (e == hipSuccess) e = launch_fill_bytes_zero(ws.qsum, 2 * kQsumSlots * sizeof(double), p.stream);
-        if (e == hipSuccess) e = launch_fill_int(ws.status, 0, 1, p.stream);
-        if (e != hipSuccess) return e;
-        k_near_key<<<blocks, 256, 0, p.stream>>>(x, q, n, g, (int2*)ws.key, ws.cell_start, ws.qsum, ws.status);
-        if ((e = launch_exclusive_scan(p, ws.cell_start, ncells + 1, ws.scan_tmp)) != hipSuccess) return e;
-        k_near_pack<real><<<blocks, 256, 0, p.stream>>>(x, q, n, g, (const int2*)ws.key, ws.cell_start,
-                                                         (vec4<real>*)ws.near_pos, ws.near_orig);
+        hipError_t e = launch_fill_int(p, ws.cell_start, 0, (int64_t)ncells + 1);
+        if (e == hipSuccess) e = launch_fill_bytes_zero(p, ws.qsum, 2 * kQsumSlots * sizeof(double));
+        if (e == hipSuccess) e = launch_fill_int(p, ws.status, 0, 1);
+        if (e == hipSuccess)
+            e = launch<NearKeyK>(p, blocks, 0, x, q, n, g, (int2*)ws.key, ws.cell_start, ws.qsum, ws.status);
+        if (e == hipSuccess) e = launch_exclusive_scan(p, ws.cell_start, ncells + 1, ws.scan_tmp);
+        if (e == hipSuccess)
+            e = launch<NearPackK<real>>(p, blocks, 0, x, q, n, g, (const int2*)ws.key, (const int*)ws.cell_start,
+                                        (vec4<real>*)ws.near_pos, ws.near_orig);
         const int ncols = r.nc[0] * r.nc[1];
-        k_near_zsort<real><<<(ncells + 3) / 4, 256, 0, p.stream>>>(ws.cell_start, ncells, (vec4<real>*)ws.near_pos,
-                                                                   ws.near_orig, ws.status);
-        if (sizeof(real) == 4) {
-            k_near_chunks<<<ncols, 64, 0, p.stream>>>(ws.cell_start, r.nc[2], near_chunk_extra(r.nc[2]),
-                                                      (int4*)ws.near_units, near_grab(ws, near_unit_slots(r)));
+        if (e == hipSuccess)
+            e = launch<NearZsortK<real>>(p, (ncells + 3) / 4, 0, (const int*)ws.cell_start, ncells,
+                                         (vec4<real>*)ws.near_pos, ws.near_orig, ws.status);
+        if (e == hipSuccess) {
+            if (sizeof(real) == 4)
+                e = launch<NearChunksK>(p, ncols, 0, (const int*)ws.cell_start, r.nc[2], near_chunk_extra(r.nc[2]),
+                                        (int4*)ws.near_units, near_grab(ws, near_unit_slots(r)));
+            else
+                e = launch<NearUnitsK>(p, ncols, 0, (const int*)ws.cell_start, r.nc[2], (int4*)ws.near_units,
+                                       near_grab(ws, near_unit_slots(r)));
         }
-        else
-            k_near_units<<<ncols, 64, 0, p.stream>>>(ws.cell_start, r.nc[2], (int4*)ws.near_units,
-                                                     near_grab(ws, near_unit_slots(r)));
         timer_end(p, t);
-        if (!(stages & 2)) return hipGetLastError();
+        if (e != hipSuccess || !(stages & 2)) return e;
     }
     NearArgs<real> a;
     a.pos = (const vec4<real>*)ws.near_pos;
@@ -890,10 +906,11 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
     }
     const int t = timer_id(p, "near");
     timer_begin(p, t);
+    // persistent blocks in groups of 8 (one per XCD's share of the units)
     const int want = std::min(p.num_cus * kNearBlocksPerCU, (a.max_units + kNearWaves - 1) / kNearWaves);
-    launch_near_kernel<real>(a, std::max(8, (want + 7) / 8 * 8), p.stream);
+    const hipError_t e = launch_near_kernel<real>(p, a, std::max(8, (want + 7) / 8 * 8));
     timer_end(p, t);
-    return hipGetLastError();
+    return e;
 }
 
 }  // namespace
