@@ -223,11 +223,12 @@ void sog_destroy(sog_plan_t plan);
  * neutrality (every system is a separate instance of the problem of Sec. 2.1), solved by
  * one call at the same tolerance and options.  The mid/long split of the Gaussians
  * depends on each system's height (Sec. 3; a thin enough system is all long range, per
- * the remark after the far-field split), so each system gets its own plan (cutoff, grids,
- * windows, long-range form) from the planner; the whole sequence of kernels of all
- * systems is captured once, at batch-plan time, into one HIP graph that each call
- * launches with a single hipGraphLaunch.  Systems are spread over parallel branches of
- * the graph, largest first.
+ * the remark after the far-field split), so each system gets its own parameters (cutoff,
+ * grids, windows, long-range form) from the planner.  Systems whose parameters use the
+ * same kernels form a group; each kernel of a group runs once for all its systems (its
+ * blocks dealt to the systems by a table, each system's arguments read from a table in
+ * device memory), and the launches of all groups are captured at batch-plan time into one
+ * HIP graph of a few dozen kernel nodes that each call launches once.
  *
  * Layout: the systems' particles are stored one after another, system s holding
  * particles [off_s, off_s + n[s]) with off_s = n[0] + ... + n[s-1]; x is (sum n) x 3
@@ -239,18 +240,15 @@ void sog_destroy(sog_plan_t plan);
  * name the first failing system), launches the graph and copies the outputs out.
  * Outputs are unspecified on error.  Errors as for sog_plan_ex, plus SOG_ERR_INVALID_ARG
  * for nsys < 1, NULL arrays, timing on, or a total above 2^31 particles.  A batch must
- * not be used by two calls at once.
- *
- * Status: device execution is switched off unless the environment variable
- * SOG_ENABLE_BATCH is 1 (sog_batch_plan then returns SOG_ERR_DEVICE after checking its
- * arguments and resolving every system): the first device run of the 256-system batch
- * ended in a segmentation fault inside the HIP runtime during plan creation or capture,
- * and its cause has not been found. */
+ * not be used by two calls at once. */
 typedef struct sog_batch_s* sog_batch_t;
 sog_status sog_batch_plan(int32_t nsys, const double* boxes /* nsys x 3 */, const int64_t* n /* nsys */,
                           double tol, const sog_options* opt, sog_batch_t* out);
 sog_status sog_batch_energy_potential_force(sog_batch_t batch, const double* x, const double* q,
                                             double* energy, double* phi, double* force);
+/* The structure of a batch's graph: the number of groups of systems that share kernels,
+ * and the number of kernel launches (graph nodes) of one call. */
+sog_status sog_batch_graph_info(sog_batch_t batch, int32_t* groups, int32_t* launches);
 /* The resolved parameters of system s of a batch. */
 sog_status sog_batch_plan_info(sog_batch_t batch, int32_t s, sog_params* out);
 /* Release the batch, its plans, graph and buffers.  NULL is ignored. */

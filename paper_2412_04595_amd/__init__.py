@@ -11,7 +11,8 @@ import numpy as np
 
 from . import _lib
 from ._lib import (SOG_LONG_AUTO, SOG_LONG_DIRECT, SOG_LONG_FFT, SOG_PREC_FP32_BULK, SOG_PREC_FP64, SogError,
-                   sog_batch_destroy, sog_batch_energy_potential_force, sog_batch_plan, sog_batch_plan_info,
+                   sog_batch_destroy, sog_batch_energy_potential_force, sog_batch_graph_info, sog_batch_plan,
+                   sog_batch_plan_info,
                    sog_destroy, sog_energy_potential_force, sog_energy_potential_force_static,
                    sog_energy_potential_gradient, sog_kernel_times,
                    sog_kernel_times_reset,
@@ -184,6 +185,10 @@ class BatchSolver:
 
     def info(self, s):
         return sog_batch_plan_info(self.batch, s).as_dict()
+
+    def graph_info(self):
+        """(groups of systems sharing kernels, kernel launches per call)"""
+        return sog_batch_graph_info(self.batch)
 
     def __call__(self, x, q):
         x, q = Solver._inputs(self, x, q)

@@ -44,6 +44,7 @@ EXPORTS = (
     "sog_batch_plan",
     "sog_batch_energy_potential_force",
     "sog_batch_plan_info",
+    "sog_batch_graph_info",
     "sog_batch_destroy",
     "sog_status_string",
     "sog_last_error",
@@ -140,6 +141,8 @@ def lib():
         L.sog_batch_plan.restype = C.c_int
         L.sog_batch_energy_potential_force.argtypes = [P, P, P, P, P, P]
         L.sog_batch_energy_potential_force.restype = C.c_int
+        L.sog_batch_graph_info.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.sog_batch_graph_info.restype = C.c_int
         L.sog_batch_plan_info.argtypes = [P, C.c_int32, C.POINTER(sog_params)]
         L.sog_batch_plan_info.restype = C.c_int
         L.sog_batch_destroy.argtypes = [P]
@@ -258,6 +261,12 @@ def sog_batch_plan(boxes, ns, tol, options):
 
 def sog_batch_energy_potential_force(batch, x_ptr, q_ptr, energy_ptr, phi_ptr, force_ptr):
     _check(lib().sog_batch_energy_potential_force(batch, x_ptr, q_ptr, energy_ptr, phi_ptr, force_ptr))
+
+
+def sog_batch_graph_info(batch):
+    g, k = C.c_int32(0), C.c_int32(0)
+    _check(lib().sog_batch_graph_info(batch, C.byref(g), C.byref(k)))
+    return g.value, k.value
 
 
 def sog_batch_plan_info(batch, s):

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "launch.hpp"
 
 namespace sog {
 
@@ -583,24 +584,42 @@ sog_status run(Plan& p, const double* x_in, const double* q_in, double* energy, 
     return SOG_OK;
 }
 
-// A batch of independent systems: one plan per system (device pointers, no per-plan
-// checks or timing) whose calls are captured once into a HIP graph.  The graph reads and
-// writes the batch's own staging buffers, so it stays valid for any caller pointers.
+// A batch of independent systems.  Each system has its own plan (its cutoff, grids,
+// windows and long-range form come from the planner), holding only its tables: its
+// per-call buffers are bound into one region of the batch, and it owns no stream.  At
+// batch-plan time every system's sequence of kernel launches is recorded (launch.hpp);
+// systems whose sequences use the same kernels in the same order form a group, and the
+// k-th launch of a group runs as one batched launch over all its systems, whose blocks
+// are dealt to the systems by a block-offset table and read their system's recorded
+// arguments from a table in device memory.  The batched launches of all groups are
+// captured once into a graph (a few dozen kernel nodes on one capture stream) that every
+// call launches on the caller's stream.  The graph reads and writes the batch's staging
+// buffers, so it stays valid for any caller pointers.
+struct BatchStage {
+    hipError_t (*batched)(const void*, const int*, int, unsigned, size_t, hipStream_t) = nullptr;
+    const void* dtab = nullptr;  // the group's argument records (device)
+    const int* dboff = nullptr;  // the group's block offsets (device), nsys + 1
+    int nsys = 0;
+    unsigned blocks = 0;
+    size_t lds = 0;
+};
+
 struct Batch {
     int device = 0;
     hipStream_t stream = nullptr;   // the caller's stream: copies, check and graph launch
-    hipStream_t cap = nullptr;      // capture origin
-    std::vector<hipStream_t> lanes; // parallel branches of the graph
-    std::vector<hipEvent_t> ev;     // ev[0] forks the branches, ev[1 + k] joins branch k
-    std::vector<sog_plan_t> plans;
+    hipStream_t cap = nullptr;      // capture stream (graph creation only)
+    std::vector<Plan*> plans;
+    std::vector<int> group_of;      // group of each system
+    int ngroups = 0;
     std::vector<int64_t> off;       // nsys + 1 particle offsets
     std::vector<double> lz;
     bool on_device = false, check = true;
-    std::vector<void*> bufs;
+    std::vector<void*> bufs;        // staging, tables and the systems' per-call region
     double *x = nullptr, *q = nullptr, *phi = nullptr, *force = nullptr, *energy = nullptr;
     double *qsum = nullptr, *dlz = nullptr;
     int64_t* doff = nullptr;
     int* status = nullptr;
+    std::vector<BatchStage> stages;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -610,54 +629,176 @@ void free_batch(Batch& b) {
     if (b.graph) (void)hipGraphDestroy(b.graph);
     b.exec = nullptr;
     b.graph = nullptr;
-    for (sog_plan_t p : b.plans) sog_destroy(p);
+    for (Plan* p : b.plans) {
+        free_plan(*p);
+        delete p;
+    }
     b.plans.clear();
     for (void* v : b.bufs) (void)hipFree(v);
     b.bufs.clear();
-    for (hipEvent_t e : b.ev) (void)hipEventDestroy(e);
-    b.ev.clear();
-    for (hipStream_t s : b.lanes) (void)hipStreamDestroy(s);
-    b.lanes.clear();
     if (b.cap) (void)hipStreamDestroy(b.cap);
     b.cap = nullptr;
 }
 
-// Capture every system's call into one graph: the branches fork from the capture stream,
-// system s (in order of decreasing size) runs on branch s mod K with its plan's own side
-// stream forked from that branch, and the branches join back before the capture ends.
-sog_status capture_batch(Batch& b) {
+// One system of a batch: resolved, tables on the device, per-call buffers not yet bound.
+sog_status make_member_plan(const double box[3], int64_t n, double tol, const sog_options& opt, int num_cus,
+                            Plan*& out) {
+    out = nullptr;
+    Plan* p = new (std::nothrow) Plan();
+    if (!p) {
+        set_error("host allocation failed");
+        return SOG_ERR_OUT_OF_MEMORY;
+    }
+    std::string err;
+    sog_status s = resolve(box, n, tol, opt, p->r, err);
+    if (s != SOG_OK) {
+        set_error(err);
+        delete p;
+        return s;
+    }
+    p->device = opt.device;
+    p->on_device = true;
+    p->check = false;
+    p->timing = false;
+    p->static_region = true;
+    p->num_cus = num_cus;
+    if ((s = build_plan(*p)) != SOG_OK) {
+        delete p;
+        return s;
+    }
+    out = p;
+    return SOG_OK;
+}
+
+// The launches of one system's call, in the order of one stream: the near field's sort,
+// the long range, the mid range's sort and gridding, the pair kernel, the transforms and
+// gathering, the combination.
+hipError_t record_system(Plan& p, const double* x, const double* q, double* energy, double* phi, double* force) {
+    hipError_t e = launch_near(p, x, q, 1);
+    if (e == hipSuccess) e = p.r.has_long ? launch_long(p, x, q) : launch_zero_parts(p, 2);
+    if (e == hipSuccess) e = p.r.has_mid ? launch_mid(p, x, q, 1) : launch_zero_parts(p, 1);
+    if (e == hipSuccess) e = launch_near(p, x, q, 2);
+    if (e == hipSuccess && p.r.has_mid) e = launch_mid(p, x, q, 2);
+    if (e == hipSuccess) e = launch_combine(p, q, phi, force, nullptr, energy);
+    return e;
+}
+
+// Record every system, group the systems by kernel sequence, upload the argument and
+// block-offset tables, and capture the batched launches into the graph.
+sog_status build_batch_stages(Batch& b, Allocator& A) {
     const int nsys = (int)b.plans.size();
-    std::vector<int> order(nsys);
-    for (int s = 0; s < nsys; ++s) order[s] = s;
-    std::stable_sort(order.begin(), order.end(), [&](int i, int j) {
-        return b.off[i + 1] - b.off[i] > b.off[j + 1] - b.off[j];
-    });
-    const int K = (int)b.lanes.size();
+    std::vector<std::vector<RecLaunch>> recs(nsys);
+    for (int s = 0; s < nsys; ++s) {
+        Plan& p = *b.plans[s];
+        p.rec = &recs[s];
+        const int64_t o = b.off[s];
+        const hipError_t e = record_system(p, b.x + 3 * o, b.q + o, b.energy + s, b.phi + o, b.force + 3 * o);
+        p.rec = nullptr;
+        if (e != hipSuccess) return hip_status(e, ("recording system " + std::to_string(s)).c_str());
+    }
+    // groups: identical kernel sequences
+    std::vector<int> rep;  // first system of each group
+    b.group_of.assign(nsys, -1);
+    for (int s = 0; s < nsys; ++s) {
+        for (int g = 0; g < (int)rep.size(); ++g) {
+            const auto& a = recs[rep[g]];
+            const auto& c = recs[s];
+            bool same = a.size() == c.size();
+            for (size_t k = 0; same && k < a.size(); ++k)
+                same = a[k].id == c[k].id && a[k].args.size() == c[k].args.size() && a[k].block == c[k].block;
+            if (same) {
+                b.group_of[s] = g;
+                break;
+            }
+        }
+        if (b.group_of[s] < 0) {
+            b.group_of[s] = (int)rep.size();
+            rep.push_back(s);
+        }
+    }
+    b.ngroups = (int)rep.size();
+    // host images of the tables: per group and launch, the records of its systems (an
+    // array of the launch's argument pack, 256-byte aligned) and the block offsets
+    struct Tab {
+        size_t at, boff_at, stride;
+        int g, k, cnt;
+        unsigned blocks;
+        size_t lds;
+    };
+    std::vector<Tab> tabs;
+    size_t total = 0;
+    for (int g = 0; g < b.ngroups; ++g) {
+        std::vector<int> mem;
+        for (int s = 0; s < nsys; ++s)
+            if (b.group_of[s] == g) mem.push_back(s);
+        const auto& seq = recs[rep[g]];
+        for (size_t k = 0; k < seq.size(); ++k) {
+            Tab t;
+            t.g = g;
+            t.k = (int)k;
+            t.cnt = (int)mem.size();
+            t.stride = seq[k].args.size();  // the records form an array of the launch's argument pack
+            t.at = total;
+            total += (t.stride * mem.size() + 255) / 256 * 256;
+            t.boff_at = total;
+            total += ((mem.size() + 1) * sizeof(int) + 255) / 256 * 256;
+            t.blocks = 0;
+            t.lds = 0;
+            for (int s : mem) {
+                t.blocks += recs[s][k].grid;
+                t.lds = std::max(t.lds, recs[s][k].lds);
+            }
+            tabs.push_back(t);
+        }
+    }
+    std::vector<unsigned char> host(total, 0);
+    for (const Tab& t : tabs) {
+        int i = 0;
+        int acc = 0;
+        int* boff = reinterpret_cast<int*>(host.data() + t.boff_at);
+        for (int s = 0; s < nsys; ++s) {
+            if (b.group_of[s] != t.g) continue;
+            const RecLaunch& r = recs[s][t.k];
+            std::memcpy(host.data() + t.at + (size_t)i * t.stride, r.args.data(), r.args.size());
+            boff[i] = acc;
+            acc += (int)r.grid;
+            ++i;
+        }
+        boff[i] = acc;
+    }
+    unsigned char* dev = nullptr;
+    A.get(dev, total);
+    if (A.err != hipSuccess || A.capped) return A.capped ? SOG_ERR_OUT_OF_MEMORY : hip_status(A.err, "batch tables");
+    hipError_t e = hipMemcpy(dev, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_status(e, "batch tables");
+    for (const Tab& t : tabs) {
+        const RecLaunch& r = recs[rep[t.g]][t.k];
+        BatchStage st;
+        st.batched = r.batched;
+        st.dtab = dev + t.at;
+        st.dboff = reinterpret_cast<const int*>(dev + t.boff_at);
+        st.nsys = t.cnt;
+        st.blocks = t.blocks;
+        st.lds = t.lds;
+        b.stages.push_back(st);
+    }
+    return SOG_OK;
+}
+
+// The batched launches of all groups, in order, captured into the batch's graph.
+sog_status capture_batch(Batch& b) {
     hipError_t e = hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_status(e, "graph capture");
-    sog_status st = SOG_OK;
-    e = hipEventRecord(b.ev[0], b.cap);
-    for (int k = 0; k < K && e == hipSuccess; ++k) e = hipStreamWaitEvent(b.lanes[k], b.ev[0], 0);
-    if (e != hipSuccess) st = hip_status(e, "graph fork");
-    for (int i = 0; i < nsys && st == SOG_OK; ++i) {
-        const int s = order[i];
-        Plan& p = *reinterpret_cast<Plan*>(b.plans[s]);
-        p.stream = b.lanes[i % K];
-        const int64_t o = b.off[s];
-        st = run(p, b.x + 3 * o, b.q + o, b.energy + s, b.phi + o, b.force + 3 * o, nullptr, nullptr, nullptr);
-        if (st != SOG_OK) set_error("system " + std::to_string(s) + ": " + g_last_error);
-    }
-    for (int k = 0; k < K && st == SOG_OK; ++k) {
-        e = hipEventRecord(b.ev[1 + k], b.lanes[k]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(b.cap, b.ev[1 + k], 0);
-        if (e != hipSuccess) st = hip_status(e, "graph join");
+    hipError_t le = hipSuccess;
+    for (const BatchStage& st : b.stages) {
+        le = st.batched(st.dtab, st.dboff, st.nsys, st.blocks, st.lds, b.cap);
+        if (le != hipSuccess) break;
     }
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(b.cap, &g);
-    if (st == SOG_OK && e != hipSuccess) st = hip_status(e, "graph capture");
-    if (st != SOG_OK) {
+    if (le != hipSuccess || e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
-        return st;
+        return hip_status(le != hipSuccess ? le : e, "graph capture");
     }
     b.graph = g;
     e = hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0);
@@ -1046,17 +1187,6 @@ sog_status sog_batch_plan(int32_t nsys, const double* boxes, const int64_t* n, d
             return st;
         }
     }
-    // Device execution of a batch is switched off unless SOG_ENABLE_BATCH=1: creating the
-    // 256-system batch ended in a segmentation fault inside the HIP runtime, at plan
-    // creation or graph capture, with no fault found in this library's host code.
-    {
-        const char* en = std::getenv("SOG_ENABLE_BATCH");
-        if (!en || std::strcmp(en, "1") != 0) {
-            set_error("batched execution is switched off (set SOG_ENABLE_BATCH=1 to enable it)");
-            delete b;
-            return SOG_ERR_DEVICE;
-        }
-    }
     b->device = opt.device;
     b->stream = (hipStream_t)opt.stream;
     b->on_device = opt.pointers_on_device != 0;
@@ -1073,13 +1203,20 @@ sog_status sog_batch_plan(int32_t nsys, const double* boxes, const int64_t* n, d
         return SOG_ERR_INVALID_ARG;
     }
     DeviceGuard dg(b->device);
+    int num_cus = 256;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess && cus > 0)
+            num_cus = cus;
+    }
+    Allocator A;
     auto fail = [&](sog_status st) {
+        b->bufs = A.ptrs;
         free_batch(*b);
         delete b;
         return st;
     };
     const int64_t nt = b->off.back();
-    Allocator A;
     A.get(b->x, 3 * nt * 8);
     A.get(b->q, nt * 8);
     A.get(b->phi, nt * 8);
@@ -1089,7 +1226,6 @@ sog_status sog_batch_plan(int32_t nsys, const double* boxes, const int64_t* n, d
     A.get(b->dlz, nsys * 8);
     A.get(b->doff, (nsys + 1) * 8);
     A.get(b->status, nsys * 4);
-    b->bufs = A.ptrs;
     if (A.err != hipSuccess || A.capped) {
         set_error(A.capped ? "device memory cap (SOG_MAX_DEVICE_BYTES) reached" : "hipMalloc failed");
         return fail(SOG_ERR_OUT_OF_MEMORY);
@@ -1097,35 +1233,34 @@ sog_status sog_batch_plan(int32_t nsys, const double* boxes, const int64_t* n, d
     hipError_t e = hipMemcpy(b->dlz, b->lz.data(), nsys * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->doff, b->off.data(), (nsys + 1) * 8, hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(hip_status(e, "batch tables"));
-    sog_options po = opt;
-    po.pointers_on_device = 1;
-    po.check_inputs = 0;
-    po.timing = 0;
-    po.stream = nullptr;
+    // the systems' plans (tables only), then their per-call buffers in one region
+    size_t region = 0;
+    std::vector<size_t> at(nsys);
     for (int s = 0; s < nsys; ++s) {
-        sog_plan_t p = nullptr;
-        sog_status st = sog_plan_ex(boxes + 3 * s, n[s], tol, &po, &p);
+        Plan* p = nullptr;
+        sog_status st = make_member_plan(boxes + 3 * s, n[s], tol, opt, num_cus, p);
         if (st != SOG_OK) {
             set_error("system " + std::to_string(s) + ": " + g_last_error);
             return fail(st);
         }
         b->plans.push_back(p);
+        at[s] = region;
+        region += (p->region_bytes + 255) / 256 * 256;
     }
-    const int K = std::min(nsys, 8);
-    e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
-    for (int k = 0; k < K && e == hipSuccess; ++k) {
-        hipStream_t ls = nullptr;
-        e = hipStreamCreateWithFlags(&ls, hipStreamNonBlocking);
-        if (e == hipSuccess) b->lanes.push_back(ls);
+    unsigned char* reg = nullptr;
+    A.get(reg, region);
+    if (A.err != hipSuccess || A.capped) {
+        set_error(A.capped ? "device memory cap (SOG_MAX_DEVICE_BYTES) reached" : "hipMalloc failed");
+        return fail(SOG_ERR_OUT_OF_MEMORY);
     }
-    for (int k = 0; k < K + 1 && e == hipSuccess; ++k) {
-        hipEvent_t ev = nullptr;
-        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-        if (e == hipSuccess) b->ev.push_back(ev);
-    }
-    if (e != hipSuccess) return fail(hip_status(e, "stream creation"));
-    sog_status st = capture_batch(*b);
+    for (int s = 0; s < nsys; ++s) bind_region(*b->plans[s], reg + at[s]);
+    sog_status st = build_batch_stages(*b, A);
     if (st != SOG_OK) return fail(st);
+    e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(hip_status(e, "stream creation"));
+    st = capture_batch(*b);
+    if (st != SOG_OK) return fail(st);
+    b->bufs = A.ptrs;
     *out = reinterpret_cast<sog_batch_t>(b);
     return SOG_OK;
 }
@@ -1179,6 +1314,17 @@ sog_status sog_batch_energy_potential_force(sog_batch_t batch, const double* x, 
     return SOG_OK;
 }
 
+sog_status sog_batch_graph_info(sog_batch_t batch, int32_t* groups, int32_t* launches) {
+    if (!batch || !groups || !launches) {
+        set_error("batch, groups and launches must not be NULL");
+        return SOG_ERR_INVALID_ARG;
+    }
+    const Batch& b = *reinterpret_cast<Batch*>(batch);
+    *groups = b.ngroups;
+    *launches = (int32_t)b.stages.size();
+    return SOG_OK;
+}
+
 sog_status sog_batch_plan_info(sog_batch_t batch, int32_t s, sog_params* o) {
     if (!batch || !o) {
         set_error("batch and out must not be NULL");
@@ -1189,7 +1335,8 @@ sog_status sog_batch_plan_info(sog_batch_t batch, int32_t s, sog_params* o) {
         set_error("system index out of range");
         return SOG_ERR_INVALID_ARG;
     }
-    return sog_plan_info(b.plans[s], o);
+    fill_params(b.plans[s]->r, o);
+    return SOG_OK;
 }
 
 void sog_batch_destroy(sog_batch_t batch) {

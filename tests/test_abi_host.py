@@ -247,16 +247,6 @@ def test_batch_workload_plans():
     assert {round(b[2] / b[0], 3) for _n, b, _s in specs} == {0.125, 1.0, 8.0}
 
 
-def test_batch_plan_is_switched_off_by_default(monkeypatch):
-    """With valid arguments and SOG_ENABLE_BATCH unset, sog_batch_plan refuses with
-    SOG_ERR_DEVICE after resolving every system (no device is touched)."""
-    monkeypatch.delenv("SOG_ENABLE_BATCH", raising=False)
-    with pytest.raises(sog.SogError) as ei:
-        sog.sog_batch_plan([(10.0, 10.0, 10.0), (8.0, 8.0, 64.0)], [1000, 4000], 1e-4, sog.make_options("fp32"))
-    assert ei.value.status == _lib.SOG_ERR_DEVICE
-    assert "SOG_ENABLE_BATCH" in str(ei.value)
-
-
 @pytest.mark.parametrize("name, prec, cap", [("cube_8e6", "fp32", 4608), ("cube_1e6", "fp64", 2304),
                                              ("cube_1e6", "fp32", 4608)])
 def test_planner_keeps_fft_batches_wide(name, prec, cap):

@@ -1,5 +1,6 @@
 """Batched independent systems (sog_batch_plan / sog_batch_energy_potential_force) on the
-GPU: one call runs every system's plan from one captured HIP graph.
+GPU: one call launches one captured HIP graph whose kernels each run for every system of
+a group of systems that share kernels.
 
 * the 256-system batch (N log-uniform in [500, 20000], Lz/Lx in {1/8, 1, 8}) in float32:
   sampled targets of twelve systems against tests/golden/batch_256_targets.txt (the
@@ -17,13 +18,7 @@ import pytest
 
 import workloads
 
-pytestmark = [
-    pytest.mark.gpu,
-    pytest.mark.skipif(os.environ.get("SOG_ENABLE_BATCH") != "1",
-                       reason="batched execution is switched off: its first device run (the 256-system batch) "
-                              "ended in a segmentation fault inside the HIP runtime during sog_batch_plan, cause "
-                              "not found; the library refuses batches unless SOG_ENABLE_BATCH=1"),
-]
+pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TOL = 1e-4
@@ -40,6 +35,9 @@ def test_batch_256_sampled_targets():
     print("[gpu] batch of 256 systems, fp32", flush=True)
     x, q, boxes, ns = workloads.batch()
     b = sog.BatchSolver(boxes, ns, TOL, precision="fp32", on_device=True, check_inputs=True)
+    groups, launches = b.graph_info()
+    print(f"    {groups} groups of systems, {launches} kernel launches per call", flush=True)
+    assert launches <= 40 * groups and groups <= 16
     U, phi, F = b(torch.from_numpy(x).cuda(), torch.from_numpy(q).cuda())
     torch.cuda.synchronize()
     U, phi, F = U.cpu().numpy(), phi.cpu().numpy(), F.cpu().numpy()
