@@ -241,7 +241,7 @@ def secondary(sog, torch, name, tol, steps):
     return out
 
 
-def bench_batch(args):
+def batch_run(steps, warmup, tol):
     """The 256-system batch (N log-uniform in [500, 20000], Lz/Lx in {1/8, 1, 8}, density 1)
     in float32 through one batch plan: each timed step is one sog_batch_energy_potential_force
     call (input copy into the batch's buffers, one graph launch, output copy)."""
@@ -254,25 +254,22 @@ def bench_batch(args):
     N = len(q)
     xt = torch.from_numpy(x).cuda()
     qt = torch.from_numpy(q).cuda()
-    log(f"[bench] batch_256: {len(ns)} systems, {N} particles, tol {args.tol}")
-    try:
-        chk = sog.BatchSolver(boxes, ns, args.tol, precision="fp32", on_device=True, check_inputs=True)
-    except sog.SogError as e:
-        print(f"bench.py: the batch cannot run: {e}", file=sys.stderr)
-        sys.exit(2)
+    log(f"[bench] batch_256: {len(ns)} systems, {N} particles, tol {tol}")
+    chk = sog.BatchSolver(boxes, ns, tol, precision="fp32", on_device=True, check_inputs=True)
     chk(xt, qt)
     chk.close()
     t0 = time.perf_counter()
-    b = sog.BatchSolver(boxes, ns, args.tol, precision="fp32", on_device=True, check_inputs=False)
+    b = sog.BatchSolver(boxes, ns, tol, precision="fp32", on_device=True, check_inputs=False)
     t_plan = time.perf_counter() - t0
-    for _ in range(args.warmup):
+    groups, launches = b.graph_info()
+    for _ in range(warmup):
         b(xt, qt)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         U, phi, F = b(xt, qt)
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = (time.perf_counter() - t0) / steps
     phi, F = phi.cpu().numpy(), F.cpu().numpy()
     d = np.loadtxt(os.path.join(ROOT, "tests", "golden", "batch_256_targets.txt"), comments="#")
     sysi, idx = d[:, 0].astype(np.int64), d[:, 1].astype(np.int64)
@@ -284,26 +281,34 @@ def bench_batch(args):
         ephi = max(ephi, float(np.max(np.abs(phi[g] - d[m, 2])) / np.max(np.abs(d[m, 2]))))
         eF = max(eF, float(np.max(np.abs(F[g] - rF)) / np.max(np.abs(rF))))
     b.close()
+    log(f"[bench] batch_256 {dt * 1e3:.3f} ms/step ({groups} groups, {launches} launches)")
+    return dict(N=N, systems=len(ns), dt=dt, plan_seconds=t_plan, groups=groups, launches=launches,
+                accuracy={"phi_rel_linf": ephi, "force_rel_linf": eF,
+                          "reference": "tests/golden/batch_256_targets.txt (12 systems x 4 sampled targets)"})
+
+
+def bench_batch(args):
+    r = batch_run(args.steps, args.warmup, args.tol)
     out = {
         "metric": METRIC,
-        "value": N / dt,
+        "value": r["N"] / r["dt"],
         "unit": "particles/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt * 1e3,
+        "ms_per_step": r["dt"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"batch_256: {len(ns)} independent systems, N log-uniform in [500, 20000] "
-                               f"(total {N}), Lz/Lx in {{1/8, 1, 8}}, density 1, uniform +/-1 neutral, "
+        "config": {"workload": f"batch_256: {r['systems']} independent systems, N log-uniform in [500, 20000] "
+                               f"(total {r['N']}), Lz/Lx in {{1/8, 1, 8}}, density 1, uniform +/-1 neutral, "
                                f"tol {args.tol:g}, FP32-bulk form, one graph launch per step",
-                   "systems": len(ns), "N": N, "tol": args.tol},
-        "plan_seconds": t_plan,
-        "accuracy": {"phi_rel_linf": ephi, "force_rel_linf": eF,
-                     "reference": "tests/golden/batch_256_targets.txt (12 systems x 4 sampled targets)"},
+                   "systems": r["systems"], "N": r["N"], "tol": args.tol},
+        "plan_seconds": r["plan_seconds"],
+        "graph": {"groups": r["groups"], "kernel_launches": r["launches"]},
+        "accuracy": r["accuracy"],
         "roofline": None,
         "cpu_baseline": None,
     }
@@ -320,6 +325,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-confined", action="store_true", help="skip the strongly confined box")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-system batch")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three 256 MiB device-to-device copies (the known-size copy that scales the "
                          "HBM counters of a profiling run)")
@@ -391,6 +397,15 @@ def main():
                                 "the strongly confined box of the paper's Table 4), tol %g" % args.tol)
         confined["paper_context"] = ("Table 4, same N and box: 11.5 s at eps_r 1e-3, 55.0 s at 1e-6, potentials only, one "
                                      "core of a Threadripper PRO 3995WX (Julia)")
+    batched = None
+    if not args.no_batch:
+        r = batch_run(max(5, args.steps // 2), 2, args.tol)
+        batched = {"value": r["N"] / r["dt"], "unit": "particles/s", "ms_per_step": r["dt"] * 1e3,
+                   "workload": f"batch_256: {r['systems']} independent systems (total {r['N']} particles), N "
+                               f"log-uniform in [500, 20000], Lz/Lx in {{1/8, 1, 8}}, density 1, FP32-bulk, tol "
+                               f"{args.tol:g}, one graph launch per step",
+                   "plan_seconds": r["plan_seconds"], "graph": {"groups": r["groups"], "kernel_launches": r["launches"]},
+                   "accuracy": r["accuracy"]}
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a bounded sample)")
@@ -420,6 +435,7 @@ def main():
         "spread_gather_hbm": spread_gather_hbm(r32["info"], r32["sizes"], N, per_launch, 4),
         "roofline_kernels": others,
         "strongly_confined": confined,
+        "batched": batched,
         "cpu_baseline": cpu,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "plan": {k: r32["info"][k] for k in ("rc", "M", "m", "mid_I", "mid_Izs", "mid_Pw", "long_form", "long_P",

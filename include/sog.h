@@ -239,7 +239,8 @@ void sog_destroy(sog_plan_t plan);
  * (opt->check_inputs: one validation kernel for all systems and one read-back; errors
  * name the first failing system), launches the graph and copies the outputs out.
  * Outputs are unspecified on error.  Errors as for sog_plan_ex, plus SOG_ERR_INVALID_ARG
- * for nsys < 1, NULL arrays, timing on, or a total above 2^31 particles.  A batch must
+ * for nsys < 1, NULL arrays, timing on, a total above 2^31 particles, or a system whose
+ * plan takes the long range's FFT form (batches run the direct form only).  A batch must
  * not be used by two calls at once. */
 typedef struct sog_batch_s* sog_batch_t;
 sog_status sog_batch_plan(int32_t nsys, const double* boxes /* nsys x 3 */, const int64_t* n /* nsys */,

@@ -1244,6 +1244,12 @@ sog_status sog_batch_plan(int32_t nsys, const double* boxes, const int64_t* n, d
             return fail(st);
         }
         b->plans.push_back(p);
+        if (p->r.has_long && p->r.form == SOG_LONG_FFT) {
+            set_error("system " + std::to_string(s) +
+                      ": its plan takes the long range's FFT form, which batches do not run (a flat system with too "
+                      "many long-range modes for the direct form); solve it with its own plan");
+            return fail(SOG_ERR_INVALID_ARG);
+        }
         at[s] = region;
         region += (p->region_bytes + 255) / 256 * 256;
     }

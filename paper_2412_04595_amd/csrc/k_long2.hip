@@ -24,6 +24,9 @@
 // At k = 0 the constant term (p = 0, or the expm1 of the exact form) multiplies
 // sum_j q_j and is left out.
 //
+// Batches do not run this form (its launches are not recorded; a batch whose system needs it
+// is refused).
+//
 // Gridding is output-stationary: a workgroup owns a 16 x 16 tile of nodes, one node per
 // thread, and sums in registers the windows of the particles that reach the tile: it reads
 // the particles of the (at most three per direction) tiles around its own (particles
@@ -486,7 +489,7 @@ hipError_t l2_spread_gather_pw(Plan& p, bool spread) {
         a.Ps = r.Ps;
         a.S = (real)r.S2;
         a.inv_hw2 = inv_hw2;
-        return launch<L2SpreadK<real, PW>>(p, xcd_grid(ntiles), 0, a);
+        return launch<L2SpreadK<real, PW>, false>(p, xcd_grid(ntiles), 0, a);
     } else {
         L2GatherArgs<real> a;
         a.gp = (const int4*)ws.l2_g;
@@ -505,7 +508,7 @@ hipError_t l2_spread_gather_pw(Plan& p, bool spread) {
         a.inv_hw2 = inv_hw2;
         a.area = (real)(r.h2[0] * r.h2[1]);
         a.dzf = (real)(2.0 / r.L[2]);
-        return launch<L2GatherK<real, PW>>(p, xcd_grid(ntiles), 0, a);
+        return launch<L2GatherK<real, PW>, false>(p, xcd_grid(ntiles), 0, a);
     }
 }
 
@@ -544,10 +547,10 @@ hipError_t run_long_fft(Plan& p, const double* x, const double* q) {
     timer_begin(p, t);
     hipError_t e = launch_fill_int(p, ws.l2_tile_start, 0, (int64_t)ntiles + 1);
     if (e == hipSuccess) e = launch_fill_int(p, ws.l2_tile_cursor, 0, ntiles);
-    if (e == hipSuccess) e = launch<L2KeyK>(p, blocks, 0, x, n, g, ws.key, ws.l2_tile_start);
+    if (e == hipSuccess) e = launch<L2KeyK, false>(p, blocks, 0, x, n, g, ws.key, ws.l2_tile_start);
     if (e == hipSuccess) e = launch_exclusive_scan(p, ws.l2_tile_start, ntiles + 1, ws.scan_tmp);
     if (e == hipSuccess)
-        e = launch<L2PackK<real>>(p, blocks, 0, x, q, n, g, (const int*)ws.key, (const int*)ws.l2_tile_start,
+        e = launch<L2PackK<real>, false>(p, blocks, 0, x, q, n, g, (const int*)ws.key, (const int*)ws.l2_tile_start,
                                   ws.l2_tile_cursor, (int4*)ws.l2_g, (vec4<real>*)ws.l2_u);
     timer_end(p, t);
     if (e != hipSuccess) return e;
@@ -582,7 +585,7 @@ hipError_t run_long_fft(Plan& p, const double* x, const double* q) {
         const int64_t modes = (int64_t)r.I2[0] * Ky;
         t = timer_id(p, "long2_scale");
         timer_begin(p, t);
-        e = launch<L2ScaleK<real>>(p, (unsigned)((modes + kL2ScaleThreads - 1) / kL2ScaleThreads), lds, a);
+        e = launch<L2ScaleK<real>, false>(p, (unsigned)((modes + kL2ScaleThreads - 1) / kL2ScaleThreads), lds, a);
         timer_end(p, t);
         if (e != hipSuccess) return e;
     }

@@ -71,12 +71,20 @@ __device__ __forceinline__ int batch_system(const int* __restrict__ boff, int ns
     return lo;
 }
 
+// A block copies its system's argument record into LDS and runs the body on that copy
+// (reading the record from global memory where it is used made the compiler hold whole
+// argument structs in vector registers: 2x the registers of the single-plan kernels).
 template <class B, class... A>
 __global__ __launch_bounds__(B::kThreads) void k_batched(const KArgs<A...>* __restrict__ tab,
                                                          const int* __restrict__ boff, int nsys) {
+    __shared__ __align__(16) uint32_t rec_lds[(sizeof(KArgs<A...>) + 3) / 4];
     const int s = batch_system(boff, nsys);
     const GridPos g{(int)blockIdx.x - boff[s], boff[s + 1] - boff[s]};
-    tab[s].call([&](const A&... a) { B::run(g, a...); });
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(tab + s);
+    for (int i = threadIdx.x; i < (int)(sizeof(KArgs<A...>) / 4); i += B::kThreads) rec_lds[i] = src[i];
+    __syncthreads();
+    const KArgs<A...>& rec = *reinterpret_cast<const KArgs<A...>*>(rec_lds);
+    rec.call([&](const A&... a) { B::run(g, a...); });
 }
 
 // One recorded launch.
@@ -99,22 +107,28 @@ hipError_t launch_batched_thunk(const void* dtab, const int* boff, int nsys, uns
 }
 
 // Launch body B on the plan's stream, or record the launch when the plan records.
-template <class B, class... A>
+// BATCH = false: a kernel that no batch runs (recording it is an error), and k_batched
+// is not instantiated for it.
+template <class B, bool BATCH = true, class... A>
 hipError_t launch(Plan& p, unsigned grid, size_t lds, const A&... a) {
     if (grid == 0) return hipSuccess;
     if (p.rec) {
-        RecLaunch r;
-        const KArgs<A...> k = make_kargs(a...);
-        r.id = reinterpret_cast<const void*>(&k_batched<B, A...>);
-        r.args.resize(sizeof(k));
-        std::memcpy(r.args.data(), &k, sizeof(k));
-        r.align = alignof(KArgs<A...>);
-        r.grid = grid;
-        r.block = B::kThreads;
-        r.lds = lds;
-        r.batched = &launch_batched_thunk<B, A...>;
-        p.rec->push_back(std::move(r));
-        return hipSuccess;
+        if constexpr (!BATCH) {
+            return hipErrorNotSupported;
+        } else {
+            RecLaunch r;
+            const KArgs<A...> k = make_kargs(a...);
+            r.id = reinterpret_cast<const void*>(&k_batched<B, A...>);
+            r.args.resize(sizeof(k));
+            std::memcpy(r.args.data(), &k, sizeof(k));
+            r.align = alignof(KArgs<A...>);
+            r.grid = grid;
+            r.block = B::kThreads;
+            r.lds = lds;
+            r.batched = &launch_batched_thunk<B, A...>;
+            p.rec->push_back(std::move(r));
+            return hipSuccess;
+        }
     }
     k_single<B, A...><<<grid, B::kThreads, lds, p.stream>>>(a...);
     return hipGetLastError();
