@@ -20,7 +20,9 @@ period L_z*, Sec. 3.4):
   3. multiply by Ghat_mid(k) / What(k)^2   (k = 2 pi fftfreq)
   4. u = ifftn(.)
   5. Phi_mid_i = h_x h_y h_z sum_g W(r_i - g) u(g), grad with dW.
-  Optionally the ES window (window_1d_es) with its transform by quadrature.
+  Optionally the ES window (window_1d_es) with its transform by quadrature, or the
+  Kaiser-Bessel window (window_1d_kb, closed-form transform), exact or replaced by its
+  degree-nu Chebyshev interpolants per node (window_poly_1d, Remark rmk::PWindow).
 
 Long range, direct form (App. B, Alg. al::long_nonfft), with Chebyshev
 interpolation in the target z and anterpolation in the source z (the
@@ -152,6 +154,96 @@ def window_hat_es(k, h, Pw, beta):
     return out.reshape(k.shape)
 
 
+# The Kaiser-Bessel window, the window of the paper's experiments (Sec. 5, Remark
+# rmk::PWindow; the paper prints no formula):
+#   W(x) = I_0(beta sqrt(1 - (x/a)^2)) / I_0(beta) for |x| <= a,  0 otherwise,  a = P_w h / 2,
+# with the closed-form transform of the truncated window (the standard Kaiser-Bessel pair)
+#   What(k) = (2 a / I_0(beta)) sinh(sqrt(beta^2 - (k a)^2)) / sqrt(beta^2 - (k a)^2),
+# continued by sin(sqrt((k a)^2 - beta^2)) / sqrt((k a)^2 - beta^2) for |k a| > beta.
+
+def window_1d_kb(xc, origin, h, n, Pw, beta, periodic, nu=None):
+    """KB-window weights of every particle on its Pw nearest grid points; same returns as
+    window_1d (d/dx_particle of W(x_p - x_g) in dW: W' = I_1(beta r) beta (-x/a^2)/r / I_0(beta),
+    r = sqrt(1 - (x/a)^2)).  With nu, the weights are those of the window's polynomial
+    approximation of degree nu (window_poly_1d)."""
+    from scipy.special import i0, i1
+    a = 0.5 * Pw * h
+    a0 = np.round((xc - origin) / h).astype(np.int64)
+    off = np.arange(Pw) - (Pw - 1) // 2
+    idx = a0[:, None] + off[None, :]
+    if nu is not None:
+        W, dW = window_poly_1d(lambda d: kb_value(d, a, beta), (xc - origin) / h - a0, h, Pw, nu)
+        return _wrap_idx(idx, n, periodic), W, dW
+    dx = xc[:, None] - (origin + idx * h)  # x_p - x_g
+    t2 = (dx / a) ** 2
+    inside = t2 <= 1.0
+    r = np.sqrt(np.where(inside, 1.0 - t2, 1.0))
+    norm = 1.0 / i0(beta)
+    W = np.where(inside, i0(beta * r) * norm, 0.0)
+    # I_1(beta r)/r -> beta/2 as r -> 0 (the support edge)
+    ratio = np.where(r > 1e-8, i1(beta * r) / np.where(r > 1e-8, r, 1.0), 0.5 * beta)
+    dW = np.where(inside, -beta * dx / (a * a) * ratio * norm, 0.0)
+    if periodic:
+        idx = np.mod(idx, n)
+    else:
+        if np.any(idx < 0) or np.any(idx >= n):
+            raise ValueError("window support leaves the padded z grid")
+    return idx, W, dW
+
+
+def kb_value(x, a, beta):
+    """The KB window at x (array), zero outside [-a, a]."""
+    from scipy.special import i0
+    t2 = (np.asarray(x, dtype=np.float64) / a) ** 2
+    return np.where(t2 <= 1.0, i0(beta * np.sqrt(np.where(t2 <= 1.0, 1.0 - t2, 0.0))) / i0(beta), 0.0)
+
+
+def window_poly_1d(wexact, u, h, Pw, nu):
+    """Remark rmk::PWindow: a window replaced by polynomials of degree nu built by
+    Chebyshev interpolation.  A particle at offset u in [-1/2, 1/2] (grid units) from its
+    nearest node puts weight W(h (node - particle)) on node o = -(Pw-1)/2 .. (Pw-1)/2;
+    for each o this weight is a smooth function of u on [-1/2, 1/2] (the window's support
+    ends at u = +-1/2 for the outermost nodes), interpolated at the nu + 1 Chebyshev
+    points of that interval.  wexact(x) evaluates the window at distances x.  Returns
+    (W, dW) of shape (N, Pw); dW = d W / d x_particle = -(1/h) d/d(node - particle)."""
+    from numpy.polynomial import chebyshev as C
+    off = np.arange(Pw) - (Pw - 1) // 2
+    u = np.asarray(u, dtype=np.float64)
+    W = np.empty((u.size, Pw))
+    dW = np.empty((u.size, Pw))
+    for j, o in enumerate(off):
+        # weight on node o as a function of t = 2u in [-1, 1]
+        c = C.chebinterpolate(lambda t, o=o: wexact(h * (o - 0.5 * t)), nu)
+        W[:, j] = C.chebval(2.0 * u, c)
+        # d/dx_p = (1/h) d/du = (2/h) d/dt
+        dW[:, j] = (2.0 / h) * C.chebval(2.0 * u, C.chebder(c))
+    return W, dW
+
+
+def _wrap_idx(idx, n, periodic):
+    if periodic:
+        return np.mod(idx, n)
+    if np.any(idx < 0) or np.any(idx >= n):
+        raise ValueError("window support leaves the padded z grid")
+    return idx
+
+
+def window_hat_kb(k, h, Pw, beta):
+    """Closed-form Fourier transform of the KB window (see above)."""
+    from scipy.special import i0
+    a = 0.5 * Pw * h
+    k = np.asarray(k, dtype=np.float64)
+    z2 = beta * beta - (k * a) ** 2
+    out = np.empty_like(k)
+    pos, neg = z2 > 1e-12, z2 < -1e-12
+    zp = np.sqrt(z2[pos])
+    out[pos] = np.sinh(zp) / zp
+    zn = np.sqrt(-z2[neg])
+    out[neg] = np.sin(zn) / zn
+    out[~(pos | neg)] = 1.0
+    return 2.0 * a * out / i0(beta)
+
+
 # ----------------------------------------------------------------------------- mid range
 
 def mid_range(xc, q, box, sog: SOG, m, mid):
@@ -160,9 +252,15 @@ def mid_range(xc, q, box, sog: SOG, m, mid):
     Ix, Iy, Iz = mid["I"]
     Izs = mid["Izs"]
     px, py, pz = mid["Pw"]
-    es = mid.get("window", "gaussian") == "es"
-    S = mid["beta"] if es else mid["S"]
-    wfun, hfun = (window_1d_es, window_hat_es) if es else (window_1d, window_hat)
+    kind = mid.get("window", "gaussian")
+    S = mid["beta"] if kind in ("es", "kb") else mid["S"]
+    wfun, hfun = {"es": (window_1d_es, window_hat_es), "kb": (window_1d_kb, window_hat_kb)}.get(
+        kind, (window_1d, window_hat))
+    if kind == "kb" and mid.get("nu"):
+        # the KB window by its degree-nu polynomials (Remark rmk::PWindow); the multiplier
+        # keeps the exact window's transform
+        nu = mid["nu"]
+        wfun = lambda xc_, o_, h_, n_, p_, s_, per_: window_1d_kb(xc_, o_, h_, n_, p_, s_, per_, nu=nu)
     hx, hy, hz = Lx / Ix, Ly / Iy, Lz / Iz
     Lzs = Izs * hz
     ix, Wx, dWx = wfun(xc[:, 0], -Lx / 2, hx, Ix, px, S, True)

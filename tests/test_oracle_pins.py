@@ -455,6 +455,93 @@ def test_fast_mid_es_window_converges(cube_case):
     assert np.max(np.abs(g[T] - ref["grad_mid"])) < 2e-7 * gscale
 
 
+# ---------------------------------------------------------------- KB window, polynomial windows
+
+def test_kb_window_transform_pins():
+    """The closed-form KB transform: beta = 0 is the box window (2 sin(k a)/k); for
+    beta = 2.3 P_w it agrees with a fine midpoint sum of the definition, on both sides of
+    k a = beta (the sinh and sin branches) and at the branch point itself."""
+    from scipy.special import i0
+    h, Pw = 0.4, 7
+    a = 0.5 * Pw * h
+    k = np.array([0.1, 1.0, 3.0, 7.7, 15.0])
+    assert np.max(np.abs(fast.window_hat_kb(k, h, Pw, 0.0) - 2 * np.sin(k * a) / k)) < 1e-12
+    beta = 2.3 * Pw
+    M = 400_000
+    xm = (np.arange(M) + 0.5) / M * 2 * a - a
+    W = i0(beta * np.sqrt(1 - (xm / a) ** 2)) / i0(beta)
+    for kk in (0.0, 2.0, beta / a, 15.0, 25.0):
+        bf = np.sum(W * np.cos(kk * xm)) * (2 * a / M)
+        assert abs(fast.window_hat_kb(np.array([kk]), h, Pw, beta)[0] - bf) < 1e-8 * abs(fast.window_hat_kb(np.array([0.0]), h, Pw, beta)[0])
+
+
+def test_kb_window_weights_and_derivative():
+    """Weights: the P_w nodes nearest x are inside the support, W is 1 at the centre and
+    1/I_0(beta) at the support's edge; dW agrees with central differences of W."""
+    from scipy.special import i0
+    h, Pw, beta = 0.5, 7, 16.0
+    xs = np.array([0.013, 1.2345, -0.74, 3.0 - 1e-3])
+    idx, W, dW = fast.window_1d_kb(xs, 0.0, h, 100, Pw, beta, True)
+    dx = xs[:, None] - idx * h
+    dx = dx - 100 * h * np.round(dx / (100 * h))
+    assert np.all(np.abs(dx) <= 0.5 * Pw * h)
+    _, W0, _ = fast.window_1d_kb(np.array([0.0]), 0.0, h, 100, Pw, beta, True)
+    assert abs(W0[0, (Pw - 1) // 2] - 1.0) < 1e-15
+    assert abs(fast.kb_value(np.array([0.5 * Pw * h]), 0.5 * Pw * h, beta)[0] - 1 / i0(beta)) < 1e-15
+    e = 1e-6
+    _, Wp, _ = fast.window_1d_kb(xs + e, 0.0, h, 100, Pw, beta, True)
+    _, Wm, _ = fast.window_1d_kb(xs - e, 0.0, h, 100, Pw, beta, True)
+    assert np.max(np.abs((Wp - Wm) / (2 * e) - dW)) < 1e-6 * np.max(np.abs(dW))
+
+
+def test_polynomial_window_exact_on_polynomials_and_converges():
+    """Remark rmk::PWindow's polynomial windows: a window that is itself a polynomial of
+    degree <= nu in the offset is reproduced to rounding (with its derivative), and the KB
+    window's approximation error falls geometrically with nu (below 1e-11 at nu = 10 and
+    P_w = 9, the Sec. 5.1 setting)."""
+    h, Pw = 0.5, 5
+    u = np.linspace(-0.5, 0.5, 41)
+    poly = lambda x: 1.0 + 0.3 * x - 0.7 * x ** 3 + 0.05 * x ** 4  # degree 4 in x = h (o - u)
+    dpoly = lambda x: 0.3 - 2.1 * x ** 2 + 0.2 * x ** 3
+    W, dW = fast.window_poly_1d(poly, u, h, Pw, 4)
+    off = np.arange(Pw) - (Pw - 1) // 2
+    X = h * (off[None, :] - u[:, None])
+    assert np.max(np.abs(W - poly(X))) < 1e-13
+    assert np.max(np.abs(dW + dpoly(X))) < 1e-12  # d/dx_particle = -d/dX
+    Pw, beta = 9, 2.3 * 9
+    xs = np.random.default_rng(0).uniform(-10, 10, 500)
+    _, W1, d1 = fast.window_1d_kb(xs, 0.0, h, 100, Pw, beta, True)
+    errs = []
+    for nu in (4, 6, 8, 10):
+        _, W2, d2 = fast.window_1d_kb(xs, 0.0, h, 100, Pw, beta, True, nu=nu)
+        errs.append(np.max(np.abs(W2 - W1)))
+    assert all(errs[i + 1] < 0.02 * errs[i] for i in range(3))
+    assert errs[-1] < 1e-11
+
+
+def test_fast_mid_kb_window_converges(cube_case):
+    """With the KB window the mid range converges to SOG-direct as the support grows (as
+    fast as ES: P_w = 9 at I = 48 within 1e-8), and the degree-10 polynomial form gives the
+    same potentials as the exact window to 1e-10."""
+    x, q, box, sog, m, T, ref = cube_case
+    xc = fast.centered(x, box)
+    scale = np.max(np.abs(ref["phi"]))
+    gscale = np.max(np.abs(ref["grad"]))
+    prev = 1.0
+    for Pw in (5, 7, 9):
+        mid = dict(I=(48, 48, 48), Izs=144, Pw=(Pw, Pw, Pw), window="kb", beta=2.3 * Pw)
+        p, g = fast.mid_range(xc, q, box, sog, m, mid)
+        e = np.max(np.abs(p[T] - ref["phi_mid"])) / scale
+        assert e < 0.05 * prev
+        prev = e
+    assert prev < 1e-8
+    assert np.max(np.abs(g[T] - ref["grad_mid"])) < 5e-7 * gscale
+    mid["nu"] = 10
+    p2, g2 = fast.mid_range(xc, q, box, sog, m, mid)
+    assert np.max(np.abs(p2 - p)) < 1e-10 * scale
+    assert np.max(np.abs(g2 - g)) < 1e-9 * gscale
+
+
 @pytest.mark.parametrize("system", [86, 32])
 def test_batch_golden_values_match_ewald2d(system):
     """The stored sampled targets of the batch (oracle SOG-direct per system) agree with the
