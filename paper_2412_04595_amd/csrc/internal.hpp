@@ -251,7 +251,7 @@ struct Workspace {
     // long range
     int* long_modes = nullptr;  // nh x int2 (direct form)
     double* long_kt = nullptr;  // per mode P x P kernel in the Chebyshev basis (float64)
-    double* long_mu = nullptr;  // blocks x nh x P complex partial moments (float64)
+    double* long_mu = nullptr;  // nh x P x blocks complex partial moments (float64)
     void* long_a = nullptr;     // nh x P complex coefficients a(k,n) (real type)
     int long_blocks = 0;
     // FFT form of the long range

@@ -157,7 +157,8 @@ struct MomentsK {
                 sr += (double)v.x;
                 si += (double)v.y;
             }
-            double* o = a.mu + 2 * (((size_t)gpos.bid * a.nh + kk) * P + nn);
+            // partial sums as rows (mode, n) over the blocks, so the contraction reads them coalesced
+            double* o = a.mu + 2 * (((size_t)kk * P + nn) * gpos.nb + gpos.bid);
             o[0] = sr;
             o[1] = si;
         }
@@ -165,50 +166,47 @@ struct MomentsK {
 }
 };
 
-// one block per mode: float64 sum over blocks (each thread a strided subset, then a
-// fixed-order tree in LDS), then a = (w_k/A) Kt mu
+// one block per mode: for each n (a wave per n) the float64 sum of the blocks' partial
+// moments (each lane a strided subset, then a fixed-order butterfly across the wave), then
+// a = (w_k/A) Kt mu
 constexpr int kContractThreads = 256;
 template <typename real>
 struct ContractK {
     static constexpr int kThreads = kContractThreads;
-    __device__ static void run(GridPos gpos, const double* __restrict__ mu, int nblocks, int nh, int P, const double* __restrict__ kt, double invA, cpx<real>* __restrict__ aout) {
-    __shared__ double smu[2 * 64];
-    __shared__ double tre[kContractThreads], tim[kContractThreads];
-    const int k = gpos.bid;
-    for (int nn = 0; nn < P; ++nn) {
-        double sr = 0, si = 0;
-        for (int b = threadIdx.x; b < nblocks; b += kContractThreads) {
-            const double* o = mu + 2 * (((size_t)b * nh + k) * P + nn);
-            sr += o[0];
-            si += o[1];
-        }
-        tre[threadIdx.x] = sr;
-        tim[threadIdx.x] = si;
-        __syncthreads();
-        for (int h = kContractThreads / 2; h > 0; h >>= 1) {
-            if ((int)threadIdx.x < h) {
-                tre[threadIdx.x] += tre[threadIdx.x + h];
-                tim[threadIdx.x] += tim[threadIdx.x + h];
+    __device__ static void run(GridPos gpos, const double* __restrict__ mu, int nblocks, int nh, int P,
+                               const double* __restrict__ kt, double invA, cpx<real>* __restrict__ aout) {
+        __shared__ double smu[2 * 64];
+        const int k = gpos.bid;
+        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int nn = wv; nn < P; nn += kContractThreads / 64) {
+            const double2* o = reinterpret_cast<const double2*>(mu) + ((size_t)k * P + nn) * nblocks;
+            double sr = 0, si = 0;
+            for (int b = lane; b < nblocks; b += 64) {
+                const double2 v = o[b];
+                sr += v.x;
+                si += v.y;
             }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            smu[2 * nn] = tre[0];
-            smu[2 * nn + 1] = tim[0];
+            for (int off = 32; off > 0; off >>= 1) {
+                sr += __shfl_xor(sr, off, 64);
+                si += __shfl_xor(si, off, 64);
+            }
+            if (lane == 0) {
+                smu[2 * nn] = sr;
+                smu[2 * nn + 1] = si;
+            }
         }
         __syncthreads();
-    }
-    const double wk = (k == 0 ? 1.0 : 2.0) * invA;
-    for (int nn = threadIdx.x; nn < P; nn += kContractThreads) {
-        const double* row = kt + ((size_t)k * P + nn) * P;
-        double sr = 0, si = 0;
-        for (int e = 0; e < P; ++e) {
-            sr += row[e] * smu[2 * e];
-            si += row[e] * smu[2 * e + 1];
+        const double wk = (k == 0 ? 1.0 : 2.0) * invA;
+        for (int nn = threadIdx.x; nn < P; nn += kContractThreads) {
+            const double* row = kt + ((size_t)k * P + nn) * P;
+            double sr = 0, si = 0;
+            for (int e = 0; e < P; ++e) {
+                sr += row[e] * smu[2 * e];
+                si += row[e] * smu[2 * e + 1];
+            }
+            aout[(size_t)k * P + nn] = cpx<real>{(real)(wk * sr), (real)(wk * si)};
         }
-        aout[(size_t)k * P + nn] = cpx<real>{(real)(wk * sr), (real)(wk * si)};
     }
-}
 };
 
 template <typename real>
