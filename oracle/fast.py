@@ -172,7 +172,7 @@ def window_1d_kb(xc, origin, h, n, Pw, beta, periodic, nu=None):
     off = np.arange(Pw) - (Pw - 1) // 2
     idx = a0[:, None] + off[None, :]
     if nu is not None:
-        W, dW = window_poly_1d(lambda d: kb_value(d, a, beta), (xc - origin) / h - a0, h, Pw, nu)
+        W, dW = window_poly_1d(lambda d: kb_value_mp(d, a, beta), (xc - origin) / h - a0, h, Pw, nu)
         return _wrap_idx(idx, n, periodic), W, dW
     dx = xc[:, None] - (origin + idx * h)  # x_p - x_g
     t2 = (dx / a) ** 2
@@ -198,25 +198,50 @@ def kb_value(x, a, beta):
     return np.where(t2 <= 1.0, i0(beta * np.sqrt(np.where(t2 <= 1.0, 1.0 - t2, 0.0))) / i0(beta), 0.0)
 
 
+def kb_value_mp(x, a, beta):
+    """The KB window at one distance x, in mpmath's working precision."""
+    import mpmath as mp
+    t = mp.mpf(x) / a
+    if abs(t) > 1:
+        return mp.mpf(0)
+    return mp.besseli(0, beta * mp.sqrt(1 - t * t)) / mp.besseli(0, beta)
+
+
 def window_poly_1d(wexact, u, h, Pw, nu):
     """Remark rmk::PWindow: a window replaced by polynomials of degree nu built by
     Chebyshev interpolation.  A particle at offset u in [-1/2, 1/2] (grid units) from its
     nearest node puts weight W(h (node - particle)) on node o = -(Pw-1)/2 .. (Pw-1)/2;
     for each o this weight is a smooth function of u on [-1/2, 1/2] (the window's support
     ends at u = +-1/2 for the outermost nodes), interpolated at the nu + 1 Chebyshev
-    points of that interval.  wexact(x) evaluates the window at distances x.  Returns
+    points of that interval.  wexact(x) evaluates the window at one distance x in mpmath
+    precision: the interpolant's derivative magnifies errors of its samples up to 2 nu^2
+    times at the interval's ends, so the samples and the Chebyshev coefficients are
+    formed at 30 digits and only the coefficients are rounded to float64.  Returns
     (W, dW) of shape (N, Pw); dW = d W / d x_particle = -(1/h) d/d(node - particle)."""
+    import mpmath as mp
     from numpy.polynomial import chebyshev as C
     off = np.arange(Pw) - (Pw - 1) // 2
     u = np.asarray(u, dtype=np.float64)
     W = np.empty((u.size, Pw))
     dW = np.empty((u.size, Pw))
-    for j, o in enumerate(off):
-        # weight on node o as a function of t = 2u in [-1, 1]
-        c = C.chebinterpolate(lambda t, o=o: wexact(h * (o - 0.5 * t)), nu)
-        W[:, j] = C.chebval(2.0 * u, c)
-        # d/dx_p = (1/h) d/du = (2/h) d/dt
-        dW[:, j] = (2.0 / h) * C.chebval(2.0 * u, C.chebder(c))
+    n1 = nu + 1
+    with mp.workdps(30):
+        th = [(j + mp.mpf(1) / 2) * mp.pi / n1 for j in range(n1)]
+        for col, o in enumerate(off):
+            # weight on node o as a function of t = 2u in [-1, 1], sampled at t_j = cos(th_j)
+            f = [wexact(mp.mpf(h) * (o - mp.cos(t) / 2)) for t in th]
+            c = [2 * mp.fsum(f[j] * mp.cos(k * th[j]) for j in range(n1)) / n1 for k in range(n1)]
+            c[0] /= 2
+            # derivative series: c'_{k-1} = c'_{k+1} + 2 k c_k (the usual recurrence)
+            cd = [mp.mpf(0)] * (n1 + 1)
+            for k in range(nu, 0, -1):
+                cd[k - 1] = cd[k + 1] + 2 * k * c[k]
+            cd[0] /= 2
+            c64 = np.array([float(v) for v in c])
+            cd64 = np.array([float(v) for v in cd[:nu]]) if nu > 0 else np.zeros(1)
+            W[:, col] = C.chebval(2.0 * u, c64)
+            # d/dx_p = (1/h) d/du = (2/h) d/dt
+            dW[:, col] = (2.0 / h) * C.chebval(2.0 * u, cd64)
     return W, dW
 
 
