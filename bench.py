@@ -197,10 +197,11 @@ def cpu_baseline(tol):
                        f"(near {tm['short']:.1f}, mid {tm['mid']:.1f}, long {tm['long']:.1f}){note}")
 
 
-def run_form(sog, torch, xt, qt, box, N, tol, precision, steps, warmup):
-    s = sog.Solver(box, N, tol, precision=precision, on_device=True, check_inputs=False, timing=True)
+def run_form(sog, torch, xt, qt, box, N, tol, precision, steps, warmup, params=None):
+    s = sog.Solver(box, N, tol, precision=precision, on_device=True, check_inputs=False, timing=True, params=params)
     # one checked call first: inputs valid, neutral, z in range
-    chk = sog.Solver(box, N, tol, precision=precision, on_device=True, check_inputs=True, timing=False)
+    chk = sog.Solver(box, N, tol, precision=precision, on_device=True, check_inputs=True, timing=False,
+                     params=params)
     chk(xt, qt)
     chk.close()
     for _ in range(warmup):
@@ -326,6 +327,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-confined", action="store_true", help="skip the strongly confined box")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-system batch")
+    ap.add_argument("--no-kb", action="store_true", help="skip the KB-window run of the headline workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three 256 MiB device-to-device copies (the known-size copy that scales the "
                          "HBM counters of a profiling run)")
@@ -390,6 +392,19 @@ def main():
             rf = roofline_of(mdl, per_launch[k] * 1e-3)
             others[k] = {"bound": rf["bound"], "frac": round(rf["frac"], 4), "achieved": round(rf["achieved"], 3),
                          "unit": rf["unit"], "ms": round(per_launch[k], 4)}
+    # the same workload with the KB window by its polynomials (Remark rmk::PWindow) in place
+    # of the planner's window
+    kb = None
+    if not args.no_kb:
+        rk = run_form(sog, torch, xt, qt, box, N, args.tol, "fp32", max(5, args.steps // 2), 2,
+                      params=dict(mid_window=sog._lib.SOG_WINDOW_KB))
+        info = rk["info"]
+        kb = {"value": N / rk["dt"], "unit": "particles/s", "ms_per_step": rk["dt"] * 1e3,
+              "accuracy": accuracy(args.workload, rk["U"], rk["phi"].cpu().numpy(), rk["F"].cpu().numpy(), q),
+              "plan": {k: info[k] for k in ("rc", "m", "mid_I", "mid_Izs", "mid_Pw", "mid_beta", "mid_nu")},
+              "kernels_ms_per_step": {k: round(v[0] / max(5, args.steps // 2), 4) for k, v in
+                                      sorted(rk["kt"].items(), key=lambda kv: -kv[1][0]) if k in ("mid_spread", "mid_gather")}}
+        log(f"[bench] {args.workload} fp32 KB window {rk['dt'] * 1e3:.3f} ms/step")
     confined = None
     if not args.no_confined:
         confined = secondary(sog, torch, "confined_1e6", args.tol, max(5, args.steps // 2))
@@ -434,6 +449,7 @@ def main():
         "roofline": roof,
         "spread_gather_hbm": spread_gather_hbm(r32["info"], r32["sizes"], N, per_launch, 4),
         "roofline_kernels": others,
+        "kb_window": kb,
         "strongly_confined": confined,
         "batched": batched,
         "cpu_baseline": cpu,

@@ -76,9 +76,12 @@ typedef enum { SOG_LONG_AUTO = 0, SOG_LONG_DIRECT = 1, SOG_LONG_FFT = 2 } sog_lo
  * "exponential of semicircle" W(x) = exp(beta (sqrt(1 - (x/a)^2) - 1)), |x| < a = P_w h/2,
  * a compactly supported window of the Kaiser-Bessel family the paper's experiments use
  * (Sec. 5; the paper prints no formula for it), shape mid_beta; its transform is computed
- * by quadrature.  AUTO: the cheaper of the two that meets the tolerance (the Gaussian when
- * mid_S is given). */
-typedef enum { SOG_WINDOW_AUTO = 0, SOG_WINDOW_GAUSSIAN = 1, SOG_WINDOW_ES = 2 } sog_window;
+ * by quadrature.  KB: the Kaiser-Bessel window W(x) = I_0(beta sqrt(1 - (x/a)^2)) / I_0(beta),
+ * |x| <= a, shape mid_beta, with its closed-form transform; the kernels evaluate it as in
+ * Remark rmk::PWindow, by polynomials of degree mid_nu (Chebyshev interpolation of each
+ * node's weight over the particle's offset from its nearest node).  AUTO: the cheapest
+ * that meets the tolerance (the Gaussian when mid_S is given; ES over KB on a tie). */
+typedef enum { SOG_WINDOW_AUTO = 0, SOG_WINDOW_GAUSSIAN = 1, SOG_WINDOW_ES = 2, SOG_WINDOW_KB = 3 } sog_window;
 
 /*
  * Discretisation parameters.  In options, a zero field means "choose it from tol";
@@ -107,13 +110,16 @@ typedef struct {
     int32_t long_I[2];
     int32_t long_Pw[2];
     double long_S;
-    /* mid-range window (sog_window) and the ES shape beta (0: chosen)                 */
+    /* mid-range window (sog_window) and the ES / KB shape beta (0: chosen)            */
     int32_t mid_window;
     double mid_beta;
     /* FFT form of the long range: the z kernel in App. C's Taylor form with long_Q    */
     /* terms (Lemma lemma::Taylor; 2 long_Q - 1 source planes), or -1: the exact       */
     /* kernel interpolated at the Chebyshev nodes (long_P source planes); 0: chosen.   */
     int32_t long_Q;
+    /* KB window: degree nu of its polynomials, in [2, 16] (0: chosen, Sec. 4: the     */
+    /* smallest whose weights are within tol/20 of the window)                         */
+    int32_t mid_nu;
 } sog_params;
 
 typedef struct {

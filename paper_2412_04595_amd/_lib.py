@@ -25,7 +25,7 @@ STATUS = {
 }
 SOG_PREC_FP64, SOG_PREC_FP32_BULK = 0, 1
 SOG_LONG_AUTO, SOG_LONG_DIRECT, SOG_LONG_FFT = 0, 1, 2
-SOG_WINDOW_AUTO, SOG_WINDOW_GAUSSIAN, SOG_WINDOW_ES = 0, 1, 2
+SOG_WINDOW_AUTO, SOG_WINDOW_GAUSSIAN, SOG_WINDOW_ES, SOG_WINDOW_KB = 0, 1, 2, 3
 
 EXPORTS = (
     "sog_options_default",
@@ -60,6 +60,7 @@ class sog_params(C.Structure):
         ("long_form", C.c_int32), ("long_P", C.c_int32), ("long_nk", C.c_int32 * 2),
         ("long_I", C.c_int32 * 2), ("long_Pw", C.c_int32 * 2), ("long_S", C.c_double),
         ("mid_window", C.c_int32), ("mid_beta", C.c_double), ("long_Q", C.c_int32),
+        ("mid_nu", C.c_int32),
     ]
 
     def as_dict(self):

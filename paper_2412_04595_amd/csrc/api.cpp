@@ -193,6 +193,7 @@ sog_status build_plan(Plan& p) {
         A.get(ws.mult_ay, (size_t)(r.m + 1) * r.I[1] * rs);
         A.get(ws.mult_az, (size_t)(r.m + 1) * Kz * rs);
         A.get(ws.mult_c, (size_t)(r.m + 1) * rs);
+        if (r.window == SOG_WINDOW_KB) A.get(ws.wpoly, (size_t)r.Pw * (r.nu + 1) * rs);
     }
     if (r.has_long) {
         if (r.form == SOG_LONG_DIRECT) {
@@ -270,13 +271,17 @@ sog_status build_plan(Plan& p) {
         std::vector<double> ax((size_t)nl * r.I[0]), ay((size_t)nl * r.I[1]), az((size_t)nl * Kz), cl(nl);
         const double Ng = (double)r.I[0] * r.I[1] * r.Izs;
         auto fill = [&](std::vector<double>& t, int cnt, int N, double Ld, double H, double hd) {
-            // 1 / What(k)^2 of the ES window: h What_g(k h), What_g by quadrature
+            // 1 / What(k)^2 of the ES and KB windows: h What_g(k h), What_g by quadrature (ES)
+            // or in closed form (KB)
+            const bool shaped = r.window == SOG_WINDOW_ES || r.window == SOG_WINDOW_KB;
             std::vector<double> inv_es2;
-            if (r.window == SOG_WINDOW_ES) {
+            if (shaped) {
                 inv_es2.resize(cnt);
                 for (int i = 0; i < cnt; ++i) {
                     const int f = (cnt == N && i >= (N + 1) / 2) ? i - N : i;
-                    const double w = hd * es_hat_grid(2.0 * kPi * f / Ld * hd, r.Pw, r.beta);
+                    const double kap = 2.0 * kPi * f / Ld * hd;
+                    const double w = hd * (r.window == SOG_WINDOW_ES ? es_hat_grid(kap, r.Pw, r.beta)
+                                                                     : kb_hat_grid(kap, r.Pw, r.beta));
                     inv_es2[i] = 1.0 / (w * w);
                 }
             }
@@ -286,7 +291,7 @@ sog_status build_plan(Plan& p) {
                     // over the half spectrum (z)
                     const int f = (cnt == N && i >= (N + 1) / 2) ? i - N : i;
                     double k = 2.0 * kPi * f / Ld;
-                    if (r.window == SOG_WINDOW_ES) {
+                    if (shaped) {
                         t[(size_t)l * cnt + i] = inv_es2[i] * std::exp(-r.s[l] * r.s[l] * k * k / 4.0);
                         continue;
                     }
@@ -303,6 +308,11 @@ sog_status build_plan(Plan& p) {
         if (e == hipSuccess) e = upload(ws.mult_ay, ay, f64);
         if (e == hipSuccess) e = upload(ws.mult_az, az, f64);
         if (e == hipSuccess) e = upload(ws.mult_c, cl, f64);
+        if (e == hipSuccess && r.window == SOG_WINDOW_KB) {
+            std::vector<double> coef;
+            window_poly_fit(r.Pw, r.beta, r.nu, coef);
+            e = upload(ws.wpoly, coef, f64);
+        }
         if (e == hipSuccess) e = hipMemcpy(ws.spread_nodes, r.node_oy, 4 * 64, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(ws.spread_nodes + 4 * 64, r.node_oz, 4 * 64, hipMemcpyHostToDevice);
     }
@@ -420,7 +430,7 @@ void free_plan(Plan& p) {
     void* ptrs[] = {ws.spread_nodes, ws.tw_x, ws.tw_y, ws.tw_z, ws.tw_zpost, ws.mult_ax, ws.mult_ay,
                     ws.mult_az, ws.mult_c, ws.long_modes, ws.long_kt, ws.l2_tw_x, ws.l2_tw_y, ws.l2_tw_ypost,
                     ws.l2_kt_r, ws.l2_el, ws.l2_coef, ws.l2_bp, ws.l2_winv_x, ws.l2_winv_y,
-                    p.region};
+                    ws.wpoly, p.region};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     p.region = nullptr;
@@ -1048,10 +1058,11 @@ static void fill_params(const Resolved& r, sog_params* o) {
         }
         o->mid_Izs = r.Izs;
         o->mid_window = r.window;
-        if (r.window == SOG_WINDOW_ES)
+        if (r.window == SOG_WINDOW_ES || r.window == SOG_WINDOW_KB)
             o->mid_beta = r.beta;
         else
             o->mid_S = r.S;
+        if (r.window == SOG_WINDOW_KB) o->mid_nu = r.nu;
     }
     if (r.has_long) {
         o->long_form = r.form;

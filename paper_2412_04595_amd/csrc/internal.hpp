@@ -18,6 +18,7 @@ constexpr int kMaxMid = 96;       // max number of mid-range Gaussians (m + 1)
 constexpr int kMidSub = 8;        // rank counters per mid-range tile in the counting sort (fewer atomics per address)
 static_assert((kMidSub & (kMidSub - 1)) == 0, "kMidSub is a power of two");
 constexpr int kQsumSlots = 64;    // slots of the charge sums (spreads the float64 atomics of the key pass)
+constexpr int kMaxWinPoly = 16;   // highest degree of a polynomial window
 constexpr int kMaxPw = 15;        // widest mid-range window the gridding and gathering kernels take
 constexpr int kSpreadStage = 32;  // particles whose window weights the gridding kernel stages at a time
 // LDS of one gridding or gathering workgroup at most: for narrow float32 windows (P_w <=
@@ -90,6 +91,11 @@ inline size_t fft_x_lds_min_bytes(int prec, int Ix, int nl, int W) {
 // Transform of the ES window in grid units, What_g(kappa) = int psi(d) cos(kappa d) dd
 // over |d| < P_w/2 (planner.cpp); the physical transform is h What_g(k h).
 double es_hat_grid(double kappa, int Pw, double beta);
+double kb_value_grid(double d, int Pw, double beta);
+double kb_hat_grid(double kappa, int Pw, double beta);
+void window_poly_fit(int Pw, double beta, int nu, std::vector<double>& coef);
+double window_poly_error(int Pw, double beta, int nu, const std::vector<double>& coef, double* derr);
+int window_poly_degree(int Pw, double beta, double eps);
 
 struct Resolved {
     double L[3] = {0, 0, 0};
@@ -120,8 +126,9 @@ struct Resolved {
     int Izs = 0;           // padded z points I_z*
     int Pw = 0;            // window points (same in every direction)
     double S = 0;          // Gaussian window shape
-    int window = SOG_WINDOW_GAUSSIAN;  // SOG_WINDOW_GAUSSIAN or SOG_WINDOW_ES
-    double beta = 0;       // ES window shape
+    int window = SOG_WINDOW_GAUSSIAN;  // SOG_WINDOW_GAUSSIAN, SOG_WINDOW_ES or SOG_WINDOW_KB
+    double beta = 0;       // ES / KB window shape
+    int nu = 0;            // KB: degree of the window's polynomials
     double h[3] = {0, 0, 0};
     double H[3] = {0, 0, 0};
     double Lzs = 0;
@@ -248,6 +255,7 @@ struct Workspace {
     void* mult_ay = nullptr;    // (m+1) x I_y
     void* mult_az = nullptr;    // (m+1) x (I_z*/2+1)
     void* mult_c = nullptr;     // (m+1): pi^{3/2} w_l s_l^3 / (I_x I_y I_z*)
+    void* wpoly = nullptr;      // KB window: P_w x (nu+1) monomial coefficients per node (real)
     // long range
     int* long_modes = nullptr;  // nh x int2 (direct form)
     double* long_kt = nullptr;  // per mode P x P kernel in the Chebyshev basis (float64)

@@ -93,21 +93,46 @@ struct MidPackK {
 };
 
 // The window on the P_w nodes nearest a particle, at offset d = node - particle (units of
-// h): the truncated Gaussian exp(-S d^2 / HW^2), |d| <= HW (eq. GS), or the ES window
-// exp(beta (sqrt(1 - (d/a)^2) - 1)), |d| < a = P_w / 2 (the planner's option; its
-// transform enters the multiplier tables).
+// h): the truncated Gaussian exp(-S d^2 / HW^2), |d| <= HW (eq. GS), the ES window
+// exp(beta (sqrt(1 - (d/a)^2) - 1)), |d| < a = P_w / 2, or a polynomial window (Remark
+// rmk::PWindow: node o's weight as a polynomial in the particle's offset u from its nearest
+// node, |u| <= 1/2; the KB window's, fitted by the planner).  The transforms of the windows
+// enter the multiplier tables.
+enum { kWinGauss = 0, kWinES = 1, kWinPoly = 2 };
 template <typename real>
 struct WinShape {
-    real S, inv_hw2;  // Gaussian
-    real beta, inv_a; // ES
-    int es;
+    real S, inv_hw2;     // Gaussian
+    real beta, inv_a;    // ES
+    const real* poly;    // polynomial: per node nu + 1 monomial coefficients in u, highest first
+    int kind, nu;
 };
+
+// node o's polynomial weight at offset u, and its derivative in u (Horner)
+template <typename real>
+__device__ __forceinline__ real win_poly(int o, real u, const WinShape<real>& s) {
+    const real* c = s.poly + o * (s.nu + 1);
+    real w = c[0];
+    for (int j = 1; j <= s.nu; ++j) w = fma(w, u, c[j]);
+    return w;
+}
+template <typename real>
+__device__ __forceinline__ void win_poly_d(int o, real u, const WinShape<real>& s, real& w, real& dw) {
+    const real* c = s.poly + o * (s.nu + 1);
+    real v = c[0], d = 0;
+    for (int j = 1; j <= s.nu; ++j) {
+        d = fma(d, u, v);
+        v = fma(v, u, c[j]);
+    }
+    w = v;
+    dw = d;
+}
 
 template <typename real, int PW>
 __device__ __forceinline__ real win(int o, real u, const WinShape<real>& s) {
     constexpr int HW = (PW - 1) / 2;
+    if (s.kind == kWinPoly) return win_poly(o, u, s);
     const real d = (real)(o - HW) - u;
-    if (s.es) {
+    if (s.kind == kWinES) {
         const real t = fabs(d) * s.inv_a;
         const real r1 = ((real)1 - t) * ((real)1 + t);
         return (r1 > (real)0) ? dexp(s.beta * (sqrt(r1) - (real)1)) : (real)0;
@@ -117,12 +142,19 @@ __device__ __forceinline__ real win(int o, real u, const WinShape<real>& s) {
 }
 
 // the weight and its derivative in the particle coordinate, dcoef d W (Gaussian, dcoef =
-// 2 S / (HW^2 h)) or dcoef d W / sqrt(1 - (d/a)^2) (ES, dcoef = beta / (a^2 h))
+// 2 S / (HW^2 h)), dcoef d W / sqrt(1 - (d/a)^2) (ES, dcoef = beta / (a^2 h)) or
+// dcoef p'(u) (polynomial, dcoef = 1 / h)
 template <typename real, int PW>
 __device__ __forceinline__ void win_d(int o, real u, const WinShape<real>& s, real dcoef, real& w, real& dw) {
     constexpr int HW = (PW - 1) / 2;
+    if (s.kind == kWinPoly) {
+        real dp;
+        win_poly_d(o, u, s, w, dp);
+        dw = dcoef * dp;
+        return;
+    }
     const real d = (real)(o - HW) - u;
-    if (s.es) {
+    if (s.kind == kWinES) {
         const real t = fabs(d) * s.inv_a;
         const real r1 = ((real)1 - t) * ((real)1 + t);
         const real sq = sqrt(r1 > (real)0 ? r1 : (real)1);
@@ -496,12 +528,15 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
     const int ntiles = r.ntile[0] * r.ntile[1] * r.ntile[2];
     const int HW = (PW - 1) / 2;
     const bool es = r.window == SOG_WINDOW_ES;
+    const bool poly = r.window == SOG_WINDOW_KB;
     WinShape<real> shape;
     shape.S = (real)r.S;
     shape.inv_hw2 = (real)(HW > 0 ? 1.0 / ((double)HW * HW) : 0.0);
     shape.beta = (real)r.beta;
     shape.inv_a = (real)(2.0 / PW);
-    shape.es = es ? 1 : 0;
+    shape.poly = (const real*)ws.wpoly;
+    shape.kind = poly ? kWinPoly : (es ? kWinES : kWinGauss);
+    shape.nu = r.nu;
     if (spread) {
         SpreadArgs<real> a;
         a.gp = (const int4*)ws.mid_g;
@@ -532,8 +567,9 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         for (int d = 0; d < 3; ++d) {
             a.B[d] = r.B[d];
             a.nt[d] = r.ntile[d];
-            a.dcoef[d] = es ? (real)(4.0 * r.beta / ((double)PW * PW * r.h[d]))
-                            : (real)(2.0 * r.S / ((double)HW * HW * r.h[d]));
+            a.dcoef[d] = poly ? (real)(1.0 / r.h[d])
+                              : es ? (real)(4.0 * r.beta / ((double)PW * PW * r.h[d]))
+                                   : (real)(2.0 * r.S / ((double)HW * HW * r.h[d]));
         }
         a.ntiles = ntiles;
         a.ws = shape;

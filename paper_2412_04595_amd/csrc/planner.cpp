@@ -77,6 +77,143 @@ double es_hat_grid(double kappa, int Pw, double beta) {
     return 2.0 * a * hp * sum;
 }
 
+// The Kaiser-Bessel window W(d) = I_0(beta sqrt(1 - (d/a)^2)) / I_0(beta), |d| <= a = P_w/2
+// (grid units; one of the windows of Remark rmk::PWindow, no formula printed), and its
+// transform: the truncated window's standard closed form
+//   What_g(kappa) = (2 a / I_0(beta)) sinh(z) / z,  z = sqrt(beta^2 - (kappa a)^2),
+// continued as sin(z') / z', z' = sqrt((kappa a)^2 - beta^2), beyond kappa a = beta.
+// I_0 and I_1 by their power series, summed in long double: every term is positive, so
+// the sum keeps its relative accuracy for any argument (the window's beta stays below 60).
+long double bessel_i0_ld(long double x) {
+    const long double t = 0.25L * x * x;
+    long double term = 1.0L, sum = 1.0L;
+    for (int k = 1; k < 400; ++k) {
+        term *= t / ((long double)k * k);
+        sum += term;
+        if (term < 1e-21L * sum) break;
+    }
+    return sum;
+}
+
+double bessel_i0(double x) { return (double)bessel_i0_ld(x); }
+
+double bessel_i1(double x) {
+    const long double t = 0.25L * (long double)x * x;
+    long double term = 0.5L * x, sum = term;
+    for (int k = 1; k < 400; ++k) {
+        term *= t / ((long double)k * (k + 1));
+        sum += term;
+        if (std::fabs(term) < 1e-21L * std::fabs(sum)) break;
+    }
+    return (double)sum;
+}
+
+// the window in long double: the polynomial fit interpolates these samples, and the
+// derivative of an interpolant of degree nu magnifies sample errors up to 2 nu^2-fold at
+// the ends of its interval (Markov's inequality), 4e-13 from samples rounded to double
+long double kb_value_ld(long double d, int Pw, long double beta) {
+    const long double a = 0.5L * Pw;
+    const long double t = d / a;
+    if (!(std::fabs(t) <= 1.0L)) return 0.0L;
+    return bessel_i0_ld(beta * std::sqrt((1.0L - t) * (1.0L + t))) / bessel_i0_ld(beta);
+}
+
+double kb_value_grid(double d, int Pw, double beta) { return (double)kb_value_ld(d, Pw, beta); }
+
+double kb_hat_grid(double kappa, int Pw, double beta) {
+    const double a = 0.5 * Pw;
+    const double z2 = beta * beta - kappa * kappa * a * a;
+    double f = 1.0;
+    if (z2 > 1e-12) {
+        const double z = std::sqrt(z2);
+        f = std::sinh(z) / z;
+    } else if (z2 < -1e-12) {
+        const double z = std::sqrt(-z2);
+        f = std::sin(z) / z;
+    }
+    return 2.0 * a * f / bessel_i0(beta);
+}
+
+// Remark rmk::PWindow: the weight a particle at offset u in [-1/2, 1/2] (grid units) from
+// its nearest node puts on node o (o = 0 .. P_w - 1, at o - (P_w-1)/2 from that node),
+// W(o - (P_w-1)/2 - u), replaced by its Chebyshev interpolant of degree nu on that
+// interval (the nu + 1 first-kind points), written in monomials of u, highest degree first
+// (the order Horner's rule takes): coef[o (nu + 1) + j] multiplies u^(nu - j).
+void window_poly_fit(int Pw, double beta, int nu, std::vector<double>& coef) {
+    const long double pi = 3.14159265358979323846264338327950288L;
+    coef.assign((size_t)Pw * (nu + 1), 0.0);
+    const int hw = (Pw - 1) / 2;
+    const int np = nu + 1;
+    // T_k(2u) in monomials of u: T_0 = 1, T_1 = 2u, T_{k+1} = 4u T_k - T_{k-1}
+    std::vector<std::vector<long double>> T(np, std::vector<long double>(np, 0.0L));
+    T[0][0] = 1.0L;
+    if (np > 1) T[1][1] = 2.0L;
+    for (int k = 1; k + 1 < np; ++k)
+        for (int j = 0; j < np; ++j)
+            T[k + 1][j] = (j > 0 ? 4.0L * T[k][j - 1] : 0.0L) - T[k - 1][j];
+    std::vector<long double> f(np);
+    for (int o = 0; o < Pw; ++o) {
+        for (int j = 0; j < np; ++j) {
+            const long double t = std::cos((j + 0.5L) * pi / np);
+            f[j] = kb_value_ld((long double)(o - hw) - 0.5L * t, Pw, beta);
+        }
+        std::vector<long double> mono(np, 0.0L);
+        for (int k = 0; k < np; ++k) {
+            long double c = 0.0L;
+            for (int j = 0; j < np; ++j) c += f[j] * std::cos((long double)k * (j + 0.5L) * pi / np);
+            c *= 2.0L / np;
+            if (k == 0) c *= 0.5L;
+            for (int j = 0; j < np; ++j) mono[j] += c * T[k][j];
+        }
+        for (int j = 0; j <= nu; ++j) coef[(size_t)o * np + j] = (double)mono[nu - j];
+    }
+}
+
+// Largest deviation of the fitted weights from the window, and (derr) of their derivative
+// in u from the window's, over 201 offsets per node; the derivative relative to its
+// largest value.
+double window_poly_error(int Pw, double beta, int nu, const std::vector<double>& coef, double* derr) {
+    const int hw = (Pw - 1) / 2;
+    double ew = 0, ed = 0, dmax = 0;
+    const double inv_i0 = 1.0 / bessel_i0(beta);
+    for (int o = 0; o < Pw; ++o)
+        for (int i = 0; i <= 200; ++i) {
+            const double u = -0.5 + i / 200.0;
+            const double* c = coef.data() + (size_t)o * (nu + 1);
+            double w = c[0], dw = 0;
+            for (int j = 1; j <= nu; ++j) {
+                dw = dw * u + w;
+                w = w * u + c[j];
+            }
+            const double d = (double)(o - hw) - u;
+            const double t = std::min(1.0, std::fabs(d) / (0.5 * Pw));
+            const double r = std::sqrt((1.0 - t) * (1.0 + t));
+            ew = std::max(ew, std::fabs(w - bessel_i0(beta * r) * inv_i0));
+            if (derr) {
+                // d/du W(d(u)) = -W'(d) = beta (d / a^2) I_1(beta r) / (r I_0(beta)), -> beta^2 d / (2 a^2 I_0) at r = 0
+                const double a2 = 0.25 * Pw * Pw;
+                const double ex = r > 1e-12 ? beta * d / a2 * bessel_i1(beta * r) / r * inv_i0
+                                            : 0.5 * beta * beta * d / a2 * inv_i0;
+                ed = std::max(ed, std::fabs(dw - ex));
+                dmax = std::max(dmax, std::fabs(ex));
+            }
+        }
+    if (derr) *derr = dmax > 0 ? ed / dmax : ed;
+    return ew;
+}
+
+// The polynomial degree (Sec. 4: chosen adaptively): the smallest nu in [4, kMaxWinPoly]
+// whose weights are within eps / 20 of the window (the window's own aliasing is held to
+// eps / 4), or kMaxWinPoly.
+int window_poly_degree(int Pw, double beta, double eps) {
+    std::vector<double> c;
+    for (int nu = 4; nu < kMaxWinPoly; ++nu) {
+        window_poly_fit(Pw, beta, nu, c);
+        if (window_poly_error(Pw, beta, nu, c, nullptr) <= eps / 20.0) return nu;
+    }
+    return kMaxWinPoly;
+}
+
 namespace {
 
 struct Row {
@@ -247,9 +384,10 @@ struct MidChoice {
     double S = 0, cost = 1e300;
     int window = SOG_WINDOW_GAUSSIAN;
     double beta = 0;
+    int nu = 0;
 };
 
-// Aliasing estimate of the ES window.  Gridding and gathering each fold the spectrum of
+// Aliasing estimate of the ES and KB windows.  Gridding and gathering each fold the spectrum of
 // the spread charge onto the grid's band; for the narrowest mid-range Gaussian s (1D,
 // normalised to G(0) = 1) the error is about
 //   (1/pi) int_0^pi sqrt(pi) (s/h) exp(-(s/h)^2 kappa^2 / 4) R(kappa) dkappa,
@@ -261,11 +399,12 @@ constexpr int kEsK = 65;                                   // kappa points on [0
 constexpr double kEsShape[] = {1.6, 1.8, 2.0, 2.2, 2.4, 2.6};  // beta / P_w candidates
 constexpr int kEsNShape = sizeof(kEsShape) / sizeof(kEsShape[0]);
 
-// Per (P_w, beta): R(kappa_i) in [0, kEsK) and What_g(kappa_i) / What_g(0) in [kEsK, 2 kEsK).
-const std::vector<double>& es_ratio(int Pw, double beta) {
+// Per (window, P_w, beta): R(kappa_i) in [0, kEsK) and What_g(kappa_i) / What_g(0) in
+// [kEsK, 2 kEsK).
+const std::vector<double>& es_ratio(int window, int Pw, double beta) {
     static std::mutex mu;
     static std::map<std::pair<int, long long>, std::vector<double>> cache;
-    const std::pair<int, long long> key(Pw, std::llround(beta * 1e9));
+    const std::pair<int, long long> key(Pw * 4 + window, std::llround(beta * 1e9));
     std::lock_guard<std::mutex> lock(mu);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
@@ -281,6 +420,7 @@ const std::vector<double>& es_ratio(int Pw, double beta) {
         x[i] = a * std::sin(th);
     }
     auto hat = [&](double kappa) {
+        if (window == SOG_WINDOW_KB) return kb_hat_grid(kappa, Pw, beta);
         double sum = 0;
         for (int i = 0; i <= nq; ++i) sum += f[i] * std::cos(kappa * x[i]);
         return 2.0 * a * sum * dth / 3.0;
@@ -305,8 +445,8 @@ const std::vector<double>& es_ratio(int Pw, double beta) {
 // growth stays below kEsAmpMax in every direction, as the Gaussian's does (it never grows).
 constexpr double kEsAmpMax = 4.0;
 
-double es_alias_estimate(int Pw, double beta, double s_over_h) {
-    const std::vector<double>& R = es_ratio(Pw, beta);
+double es_alias_estimate(int window, int Pw, double beta, double s_over_h) {
+    const std::vector<double>& R = es_ratio(window, Pw, beta);
     double acc = 0;
     for (int i = 0; i < kEsK; ++i) {
         const double k = kPi * i / (kEsK - 1);
@@ -318,20 +458,20 @@ double es_alias_estimate(int Pw, double beta, double s_over_h) {
     return acc * (kPi / (kEsK - 1)) / kPi;
 }
 
-// The ES window for spacing h: the smallest P_w (odd, at most kMaxPw) whose estimate
+// The ES or KB window for spacing h: the smallest P_w (odd, at most kMaxPw) whose estimate
 // meets eps / kEsMargin with the best beta of kEsShape (or the given P_w / beta); false if
 // none.  The margin covers the estimate's shortfall on coarse grids (up to 2.5x against the
 // 1D simulation at s/h = 2) and the forces, whose error is about 8x the potential's in the
 // same simulation for either window.
 constexpr double kEsMargin = 4.0;
-bool es_window(double h, double s0, double eps, const sog_params& ov, int* Pw_out, double* beta_out) {
+bool es_window(int window, double h, double s0, double eps, const sog_params& ov, int* Pw_out, double* beta_out) {
     eps /= kEsMargin;
     for (int p = 3; p <= kMaxPw; p += 2) {
         if (ov.mid_Pw[0] > 0 && p != ov.mid_Pw[0]) continue;
         double best = 1e300, bbest = 0;
         for (int ci = 0; ci < kEsNShape; ++ci) {
             const double beta = ov.mid_beta > 0 ? ov.mid_beta : kEsShape[ci] * p;
-            const double e = es_alias_estimate(p, beta, s0 / h);
+            const double e = es_alias_estimate(window, p, beta, s0 / h);
             if (bbest == 0 || e < best) { best = e; bbest = beta; }
             if (ov.mid_beta > 0) break;
         }
@@ -361,15 +501,17 @@ MidChoice plan_mid(const double L[3], int64_t n, double s0, double sm, int nl, d
         double hd[3] = {L[0] / c.I[0], L[1] / c.I[1], L[2] / c.I[2]};
         double hw = std::max(hd[0], std::max(hd[1], hd[2]));
         const MidChoice grid = c;
-        // the Gaussian window (eq. GS) and the ES window, each where allowed
-        const bool try_gauss = ov.mid_window != SOG_WINDOW_ES;
-        const bool try_es = ov.mid_window == SOG_WINDOW_ES || (ov.mid_window == SOG_WINDOW_AUTO && !(ov.mid_S > 0));
-        for (int win = 0; win < 2; ++win) {
+        // the Gaussian window (eq. GS), the ES and the KB window, each where allowed
+        const bool auto_shaped = ov.mid_window == SOG_WINDOW_AUTO && !(ov.mid_S > 0);
+        const bool try_win[3] = {ov.mid_window == SOG_WINDOW_AUTO || ov.mid_window == SOG_WINDOW_GAUSSIAN,
+                                 ov.mid_window == SOG_WINDOW_ES || auto_shaped,
+                                 ov.mid_window == SOG_WINDOW_KB || auto_shaped};
+        for (int win = 0; win < 3; ++win) {
             c = grid;
-            int Pw = 0;
+            int Pw = 0, nu = 0;
             double S = 0, beta = 0;
+            if (!try_win[win]) continue;
             if (win == 0) {
-                if (!try_gauss) continue;
                 if (ov.mid_Pw[0] > 0) {
                     Pw = ov.mid_Pw[0];
                     window_exponent(Pw, hw, s0, &S);
@@ -383,7 +525,9 @@ MidChoice plan_mid(const double L[3], int64_t n, double s0, double sm, int nl, d
                 }
                 if (ov.mid_S > 0) S = ov.mid_S;
             } else {
-                if (!try_es || !es_window(hw, s0, eps_w, ov, &Pw, &beta)) continue;
+                const int kind = win == 1 ? SOG_WINDOW_ES : SOG_WINDOW_KB;
+                if (!es_window(kind, hw, s0, eps_w, ov, &Pw, &beta)) continue;
+                if (kind == SOG_WINDOW_KB) nu = ov.mid_nu;  // 0: chosen once the plan is (below)
             }
             for (int d = 0; d < 2; ++d)
                 if (c.I[d] < 2 * Pw) c.I[d] = next_smooth(2 * Pw, true);
@@ -406,8 +550,9 @@ MidChoice plan_mid(const double L[3], int64_t n, double s0, double sm, int nl, d
             if (ov.mid_Izs > 0) c.Izs = ov.mid_Izs;
             c.Pw = Pw;
             c.S = S;
-            c.window = win == 0 ? SOG_WINDOW_GAUSSIAN : SOG_WINDOW_ES;
+            c.window = win == 0 ? SOG_WINDOW_GAUSSIAN : (win == 1 ? SOG_WINDOW_ES : SOG_WINDOW_KB);
             c.beta = beta;
+            c.nu = nu;
             double Ng = (double)c.I[0] * c.I[1] * c.Izs;
             // gridding: each wave updates ceil(P_w / 4) x planes times ceil(P_w^2 / 64)
             // passes of 64 (y, z) nodes per particle; gathering: P_w^3 points per particle
@@ -418,6 +563,8 @@ MidChoice plan_mid(const double L[3], int64_t n, double s0, double sm, int nl, d
             const int wmin = std::min(fft_lines_per_batch(prec, c.I[0]), fft_lines_per_batch(prec, c.I[1]));
             const double fft_pen = wmin >= 8 ? 1.0 : 1.0 + 0.5 * std::log2(8.0 / wmin);
             c.cost = (double)n * (kCostSpreadSlot * slots + kCostGatherPt * Pw * Pw * Pw) + kCostFFTPt * Ng * fft_pen;
+            // the KB window's weights by polynomials: charged 1% so that ES keeps the ties
+            if (win == 2) c.cost *= 1.01;
             c.ok = true;
             if (c.cost < best.cost) best = c;
         }
@@ -770,9 +917,10 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
     if (!(tol >= tmin && tol <= 1e-2)) { err = "tol outside the reachable range for this precision"; return SOG_ERR_TOL_UNREACHABLE; }
     r.tol = tol;
     if (ov.mid_Pw[0] != ov.mid_Pw[1] || ov.mid_Pw[0] != ov.mid_Pw[2]) { err = "mid_Pw must be equal in x, y, z"; return SOG_ERR_INVALID_ARG; }
-    if (ov.mid_window < SOG_WINDOW_AUTO || ov.mid_window > SOG_WINDOW_ES) { err = "mid_window must be 0, 1 or 2"; return SOG_ERR_INVALID_ARG; }
+    if (ov.mid_window < SOG_WINDOW_AUTO || ov.mid_window > SOG_WINDOW_KB) { err = "mid_window must be 0, 1, 2 or 3"; return SOG_ERR_INVALID_ARG; }
     if (ov.mid_beta < 0 || !std::isfinite(ov.mid_beta)) { err = "mid_beta must be finite and >= 0"; return SOG_ERR_INVALID_ARG; }
-    if (ov.mid_window == SOG_WINDOW_ES && ov.mid_S > 0) { err = "mid_S is the Gaussian window's shape; use mid_beta with the ES window"; return SOG_ERR_INVALID_ARG; }
+    if ((ov.mid_window == SOG_WINDOW_ES || ov.mid_window == SOG_WINDOW_KB) && ov.mid_S > 0) { err = "mid_S is the Gaussian window's shape; use mid_beta with the ES and KB windows"; return SOG_ERR_INVALID_ARG; }
+    if (ov.mid_nu != 0 && (ov.mid_window != SOG_WINDOW_KB || ov.mid_nu < 2 || ov.mid_nu > kMaxWinPoly)) { err = "mid_nu is the KB window's polynomial degree, in [2, 16]"; return SOG_ERR_INVALID_ARG; }
     if (ov.mid_Pw[0] < 0 || (ov.mid_Pw[0] > 0 && (ov.mid_Pw[0] % 2 == 0 || ov.mid_Pw[0] < 3 || ov.mid_Pw[0] > kMaxPw))) { err = "mid_Pw must be odd in [3, 15]"; return SOG_ERR_INVALID_ARG; }
     if (ov.long_Pw[0] != ov.long_Pw[1] || (ov.long_Pw[0] > 0 && (ov.long_Pw[0] % 2 == 0 || ov.long_Pw[0] < 3 || ov.long_Pw[0] > kMaxPw))) { err = "long_Pw must be odd in [3, 15] and equal in x, y"; return SOG_ERR_INVALID_ARG; }
     if (ov.long_P < 0 || ov.long_P > 64) { err = "long_P must be in [1, 64]"; return SOG_ERR_INVALID_ARG; }
@@ -867,6 +1015,7 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
                     best.S = mc.S;
                     best.window = mc.window;
                     best.beta = mc.beta;
+                    best.nu = mc.nu;
                 }
                 if (best.has_long) {
                     best.form = lc.form;
@@ -887,6 +1036,7 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         return SOG_ERR_TOL_UNREACHABLE;
     }
     r = best;
+    if (r.has_mid && r.window == SOG_WINDOW_KB && r.nu == 0) r.nu = window_poly_degree(r.Pw, r.beta, eps);
     r.self_coeff = 0;
     for (double v : r.w) r.self_coeff += v;
 

@@ -57,6 +57,18 @@ CASES = {
     "tall_es": dict(N=1200, box=(10.0, 10.0, 60.0), seed=13, row=3, rc=3.0, M=140, m=8,
                     mid=dict(I=(20, 20, 120), Izs=252, Pw=9, window="es", beta=19.8),
                     long=dict(form="direct", P=20, nk=(1, 1))),
+    # the KB window by its polynomials (sog_window KB, oracle window="kb" with nu): the
+    # cube with P_w = 7 and the Sec. 5.1 degree nu = 10, the tall box with P_w = 9 and
+    # nu = 8, and the widest window with nu = 12
+    "cube_kb": dict(N=1000, box=(20.0, 20.0, 20.0), seed=1, row=3, rc=4.0, M=100, m=6,
+                    mid=dict(I=(32, 32, 32), Izs=80, Pw=7, window="kb", beta=16.1, nu=10),
+                    long=dict(form="direct", P=12, nk=(4, 4))),
+    "tall_kb": dict(N=1200, box=(10.0, 10.0, 60.0), seed=13, row=3, rc=3.0, M=140, m=8,
+                    mid=dict(I=(20, 20, 120), Izs=252, Pw=9, window="kb", beta=20.7, nu=8),
+                    long=dict(form="direct", P=20, nk=(1, 1))),
+    "pw15_kb": dict(N=1200, box=(18.0, 22.0, 14.0), seed=35, row=4, rc=5.0, M=170, m=8,
+                    mid=dict(I=(40, 48, 30), Izs=96, Pw=15, window="kb", beta=34.5, nu=12),
+                    long=dict(form="direct", P=16, nk=(2, 3))),
     # window 13 and odd-radix FFT lengths (3, 5, 7)
     "radix_mix": dict(N=900, box=(21.0, 15.0, 10.0), seed=14, row=4, rc=3.5, M=200, m=5,
                       mid=dict(I=(42, 30, 20), Izs=70, Pw=13), long=dict(form="direct", P=14, nk=(3, 2))),
@@ -93,6 +105,8 @@ def gpu_params(c):
         p.update(mid_I=list(c["mid"]["I"]), mid_Izs=c["mid"]["Izs"], mid_Pw=[c["mid"]["Pw"]] * 3)
         if c["mid"].get("window") == "es":
             p.update(mid_window=2, mid_beta=c["mid"]["beta"])
+        elif c["mid"].get("window") == "kb":
+            p.update(mid_window=3, mid_beta=c["mid"]["beta"], mid_nu=c["mid"]["nu"])
         else:
             p.update(mid_window=1, mid_S=_window_S(c["mid"]["Pw"]))
     lp = c["long"]
@@ -115,6 +129,8 @@ def oracle_params(c):
         mid = dict(I=tuple(c["mid"]["I"]), Izs=c["mid"]["Izs"], Pw=(Pw, Pw, Pw), S=_window_S(Pw))
         if c["mid"].get("window") == "es":
             mid.update(window="es", beta=c["mid"]["beta"])
+        elif c["mid"].get("window") == "kb":
+            mid.update(window="kb", beta=c["mid"]["beta"], nu=c["mid"]["nu"])
     lp = dict(c["long"]) if c["long"] else None
     if lp and lp["form"] == "fft":
         lp = dict(form="fft", P=lp["P"], I=tuple(lp["I"]), Pw=(lp["Pw"], lp["Pw"]), S=_window_S(lp["Pw"]),
@@ -132,6 +148,8 @@ def oracle_params_from_info(info):
         mid = dict(I=tuple(info["mid_I"]), Izs=info["mid_Izs"], Pw=(Pw, Pw, Pw), S=info["mid_S"])
         if info["mid_window"] == 2:
             mid.update(window="es", beta=info["mid_beta"])
+        elif info["mid_window"] == 3:
+            mid.update(window="kb", beta=info["mid_beta"], nu=info["mid_nu"])
     lp = None
     if info["m"] < info["M"]:
         if info["long_form"] == 1:

@@ -17,7 +17,8 @@
 //  5. the near-field chunks of the float32 pair kernel fit their slots (below);
 //  6. the float32 near-field polynomials in monomial form (below);
 //  7. the ES window transform (Gauss-Legendre) against a fine composite Simpson sum in x
-//     itself (no change of variable), and the Gauss-Legendre rule against exact moments.
+//     itself (no change of variable), and the Gauss-Legendre rule against exact moments;
+//  8. the KB window's transform and its polynomial form (below).
 //
 // Prints one line per failure and "bad N"; exit status 0 when N == 0.
 #include <cmath>
@@ -296,8 +297,78 @@ static void check_es_transform() {
     std::printf("es transform: max relative difference to the direct Simpson sum %.2e\n", emax);
 }
 
+// 8. The KB window: kb_hat_grid (closed form) against a composite Simpson sum of
+//    kb_value_grid in d (the same edge limit as 7); kb_value_grid is 1 at the centre and
+//    1 / I_0(beta) at the support's edge.  The polynomial window (window_poly_fit): every
+//    node's polynomial reproduces the window at its nu + 1 interpolation points to
+//    rounding (its defining property, checked by Horner on the monomials), the deviation
+//    falls geometrically with nu, the degree window_poly_degree picks meets eps / 20, and
+//    the polynomials of neighbouring nodes join: node o at u = +1/2 and node o - 1 at
+//    u = -1/2 (the same particle seen from the next nearest node) are the same point of
+//    the window.
+static void check_kb_window() {
+    for (int Pw : {3, 7, 9, 15})
+        for (double bf : {1.6, 2.3, 2.6}) {
+            const double beta = bf * Pw, a = 0.5 * Pw;
+            const int np = 200000;
+            const double dd = a / np;
+            std::vector<double> fw(np + 1);
+            for (int i = 0; i <= np; ++i)
+                fw[i] = kb_value_grid(i * dd, Pw, beta) * ((i == 0 || i == np) ? 1.0 : ((i & 1) ? 4.0 : 2.0));
+            for (double kappa : {0.0, 0.7, 2.0, 3.14159, 6.0, 12.0}) {
+                double s = 0;
+                for (int i = 0; i <= np; ++i) s += fw[i] * std::cos(kappa * i * dd);
+                const double ref = 2.0 * s * dd / 3.0;
+                const double g = kb_hat_grid(kappa, Pw, beta);
+                CHECK(std::fabs(g - ref) < 1e-9 * kb_hat_grid(0.0, Pw, beta), "kb transform Pw %d beta %g kappa %g: %.17g vs %.17g",
+                      Pw, beta, kappa, g, ref);
+            }
+        }
+    CHECK(std::fabs(kb_value_grid(0.0, 9, 20.0) - 1.0) < 1e-15, "kb centre");
+    CHECK(std::fabs(kb_value_grid(4.5, 9, 20.0) * std::cyl_bessel_i(0.0, 20.0) - 1.0) < 1e-14, "kb edge");
+    CHECK(kb_value_grid(4.5 + 1e-9, 9, 20.0) == 0.0, "kb outside");
+    const double pi = 3.14159265358979323846;
+    for (int Pw : {3, 9, 15}) {
+        const double beta = 2.3 * Pw;
+        double prev = 1.0;
+        for (int nu : {4, 6, 8, 10, 12}) {
+            std::vector<double> c;
+            window_poly_fit(Pw, beta, nu, c);
+            const int hw = (Pw - 1) / 2;
+            auto horner = [&](int o, double u) {
+                double w = c[(size_t)o * (nu + 1)];
+                for (int j = 1; j <= nu; ++j) w = w * u + c[(size_t)o * (nu + 1) + j];
+                return w;
+            };
+            const double e = window_poly_error(Pw, beta, nu, c, nullptr);
+            for (int o = 0; o < Pw; ++o) {
+                for (int j = 0; j <= nu; ++j) {
+                    const double u = 0.5 * std::cos((j + 0.5) * pi / (nu + 1));
+                    const double ex = kb_value_grid((double)(o - hw) - u, Pw, beta);
+                    CHECK(std::fabs(horner(o, u) - ex) < 1e-13, "poly window Pw %d nu %d node %d point %d: %.17g vs %.17g",
+                          Pw, nu, o, j, horner(o, u), ex);
+                }
+                if (o > 0)
+                    CHECK(std::fabs(horner(o, 0.5) - horner(o - 1, -0.5)) <= 2.0 * e + 1e-13,
+                          "poly window Pw %d nu %d: nodes %d and %d do not join", Pw, nu, o - 1, o);
+            }
+            if (nu > 4) CHECK(e < 0.1 * prev || e < 1e-13, "poly window Pw %d nu %d: error %.3e after %.3e", Pw, nu, e, prev);
+            prev = e;
+        }
+        for (double eps : {1e-4, 1e-8, 1e-12}) {
+            const int nu = window_poly_degree(Pw, beta, eps);
+            std::vector<double> c;
+            window_poly_fit(Pw, beta, nu, c);
+            const double e = window_poly_error(Pw, beta, nu, c, nullptr);
+            CHECK(e <= eps / 20.0 || nu == kMaxWinPoly, "poly window degree Pw %d eps %g: nu %d error %.3e", Pw, eps, nu, e);
+            std::printf("kb window Pw %d eps %g: nu %d, weights within %.2e\n", Pw, eps, nu, e);
+        }
+    }
+}
+
 int main() {
     check_es_transform();
+    check_kb_window();
     check_near_monomials();
     check_near_chunks();
     check_lane_nodes_and_addresses();

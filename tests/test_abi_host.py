@@ -82,9 +82,13 @@ def test_resolve_rejects_bad_arguments(box, n, tol, prec, status):
     dict(long_P=65),
     dict(mid_Izs=81),              # odd padded z grid
     dict(mid_Pw=[17, 17, 17]),     # wider than the kernels are built for
-    dict(mid_window=3),            # no such window
+    dict(mid_window=4),            # no such window
     dict(mid_window=2, mid_S=12.0),  # the Gaussian's shape given for the ES window
+    dict(mid_window=3, mid_S=12.0),  # ... or for the KB window
     dict(mid_beta=-1.0),
+    dict(mid_nu=8),                # a polynomial degree for a window that takes none
+    dict(mid_window=3, mid_nu=1),  # degree out of [2, 16]
+    dict(mid_window=3, mid_nu=17),
 ])
 def test_resolve_rejects_bad_overrides(params):
     assert _resolve_status((20, 20, 20), 1000, 1e-4, "fp64", params) == _lib.SOG_ERR_INVALID_ARG
@@ -191,6 +195,23 @@ def test_window_choice():
     t = sog.plan_parameters((10, 10, 60), 1200, 1e-6, "fp64",
                             dict(mid_window=_lib.SOG_WINDOW_ES, mid_I=[20, 20, 120], mid_Izs=252, mid_Pw=[9, 9, 9]))
     assert t["mid_beta"] > 0
+
+
+def test_kb_window_plans():
+    """The KB window on request: the same support as ES on the 10^6 cube (their aliasing
+    is alike), the polynomial degree chosen from the tolerance (higher for a tighter one)
+    or taken as given; AUTO keeps ES on a tie."""
+    box, n = (100.0, 100.0, 100.0), 1000000
+    es = sog.plan_parameters(box, n, 1e-4, "fp32")
+    kb = sog.plan_parameters(box, n, 1e-4, "fp32", dict(mid_window=_lib.SOG_WINDOW_KB))
+    assert kb["mid_window"] == _lib.SOG_WINDOW_KB and kb["mid_beta"] > 0 and kb["mid_S"] == 0
+    assert abs(kb["mid_Pw"][0] - es["mid_Pw"][0]) <= 2 and 4 <= kb["mid_nu"] <= 16
+    assert es["mid_window"] == _lib.SOG_WINDOW_ES and es["mid_nu"] == 0
+    tight = sog.plan_parameters((20, 20, 20), 1000, 1e-10, "fp64", dict(mid_window=_lib.SOG_WINDOW_KB))
+    assert tight["mid_window"] == _lib.SOG_WINDOW_KB and tight["mid_nu"] > kb["mid_nu"]
+    given = sog.plan_parameters((20, 20, 20), 1000, 1e-6, "fp64",
+                                dict(mid_window=_lib.SOG_WINDOW_KB, mid_Pw=[9, 9, 9], mid_beta=20.0, mid_nu=10))
+    assert (given["mid_Pw"], given["mid_beta"], given["mid_nu"]) == ([9, 9, 9], 20.0, 10)
 
 
 @pytest.mark.parametrize("case, status", [

@@ -101,6 +101,24 @@ def test_confined_taylor_form(precision):
     assert ephi < TOL and eF < TOL
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_kb_window_at_full_size(precision):
+    """The 10^6-particle cube with the KB window (its polynomial form, degree chosen from
+    the tolerance) instead of the planner's ES window: sampled targets and the energy
+    within the tolerance."""
+    import paper_2412_04595_amd._lib as L
+    name = "cube_1e6"
+    print(f"[gpu] {name} {precision}, KB window", flush=True)
+    x, q, box = workloads.named(name)
+    U, phi, F, info = _device_solve(name, precision, x, q, params=dict(mid_window=L.SOG_WINDOW_KB))
+    assert info["mid_window"] == L.SOG_WINDOW_KB and info["mid_nu"] >= 4
+    ephi, eF = _sample_errors(name, phi, F, q)
+    eU = abs(U - _energy(name)) / abs(_energy(name))
+    print(f"    Pw={info['mid_Pw'][0]} beta={info['mid_beta']:.2f} nu={info['mid_nu']}: "
+          f"phi {ephi:.2e} F {eF:.2e} U {eU:.2e}", flush=True)
+    assert ephi < TOL and eF < TOL and eU < TOL
+
+
 def test_x_pass_with_multipliers_in_global_memory():
     """slab_1e6 in FP64 on a plan whose x lines (672 points, 12 mid-range Gaussians) leave no
     room for the x multiplier table in LDS even at one line per block: the x pass reads the
