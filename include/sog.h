@@ -120,6 +120,11 @@ typedef struct {
     /* KB window: degree nu of its polynomials, in [2, 16] (0: chosen, Sec. 4: the     */
     /* smallest whose weights are within tol/20 of the window)                         */
     int32_t mid_nu;
+    /* range-splitting factor eta (Sec. 3.1, the range-splitting definition): the     */
+    /* Gaussians with s_l <= eta L_z are mid range, the rest long range, so            */
+    /* m = max{l : s_l <= eta L_z} (-1 if none); 0: m chosen by cost; ignored when     */
+    /* set_m is 1.  Resolved: the given eta, or s_m / L_z of the split (0 if m = -1).  */
+    double eta;
 } sog_params;
 
 typedef struct {
@@ -134,6 +139,12 @@ typedef struct {
     int32_t static_workspace;   /* 1: the plan allocates only its tables; its calls run in    */
                                 /*    the library's static scratch, through                   */
                                 /*    sog_energy_potential_force_static only                  */
+    int32_t deterministic;      /* 1: bitwise reproducible results for the same inputs: every */
+                                /*    counting sort orders each bin by particle index, and    */
+                                /*    the mid-range gridding adds the tiles' blocks into the  */
+                                /*    grid in a fixed order of tile colours (no atomics)      */
+                                /*    instead of with atomics; 0: the faster atomic form,     */
+                                /*    whose sums may differ in the last bits between calls   */
 } sog_options;
 
 /* Fill *opt with the defaults: FP64, device 0, default stream, host pointers, checks on,

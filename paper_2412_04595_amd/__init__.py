@@ -25,10 +25,11 @@ LONG_FORM = {"auto": SOG_LONG_AUTO, "direct": SOG_LONG_DIRECT, "fft": SOG_LONG_F
 
 
 def make_options(precision="fp64", device=0, stream=None, on_device=False, check_inputs=True, timing=False,
-                 params=None, static_workspace=False):
+                 params=None, static_workspace=False, deterministic=False):
     """sog_options from keyword arguments; ``params`` is a dict of sog_params fields."""
     o = sog_options_default()
     o.static_workspace = int(bool(static_workspace))
+    o.deterministic = int(bool(deterministic))
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     o.device = int(device)
     o.stream = stream
@@ -63,7 +64,7 @@ class Solver:
     the work is queued on torch's current stream."""
 
     def __init__(self, box, n, tol, precision="fp64", device=0, on_device=False, check_inputs=True,
-                 timing=False, params=None, stream=None, static_workspace=False):
+                 timing=False, params=None, stream=None, static_workspace=False, deterministic=False):
         self.box = tuple(float(v) for v in box)
         self.n = int(n)
         self.on_device = bool(on_device)
@@ -72,7 +73,7 @@ class Solver:
             import torch
             stream = torch.cuda.current_stream(self.device).cuda_stream
         self.options = make_options(precision, device, stream, on_device, check_inputs, timing, params,
-                                    static_workspace)
+                                    static_workspace, deterministic)
         self.plan = sog_plan_ex(self.box, self.n, float(tol), self.options)
 
     def close(self):
@@ -159,7 +160,7 @@ class BatchSolver:
     modes as Solver; __call__ returns (energies (nsys,), phi, force)."""
 
     def __init__(self, boxes, ns, tol, precision="fp64", device=0, on_device=False, check_inputs=True,
-                 params=None, stream=None):
+                 params=None, stream=None, deterministic=False):
         self.boxes = [tuple(float(v) for v in b) for b in boxes]
         self.ns = [int(v) for v in ns]
         self.n = sum(self.ns)
@@ -169,7 +170,8 @@ class BatchSolver:
         if self.on_device and stream is None:
             import torch
             stream = torch.cuda.current_stream(self.device).cuda_stream
-        self.options = make_options(precision, device, stream, on_device, check_inputs, False, params)
+        self.options = make_options(precision, device, stream, on_device, check_inputs, False, params,
+                                    deterministic=deterministic)
         self.batch = sog_batch_plan(self.boxes, self.ns, float(tol), self.options)
 
     def close(self):
@@ -199,9 +201,10 @@ class BatchSolver:
         return U, phi, F
 
 
-def plan_parameters(box, n, tol, precision="fp64", params=None):
+def plan_parameters(box, n, tol, precision="fp64", params=None, deterministic=False):
     """The parameters the planner picks (host only, no GPU needed)."""
-    return sog_plan_resolve(box, n, tol, make_options(precision, params=params)).as_dict()
+    return sog_plan_resolve(box, n, tol, make_options(precision, params=params,
+                                                      deterministic=deterministic)).as_dict()
 
 
 def device_count():

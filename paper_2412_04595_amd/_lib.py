@@ -60,7 +60,7 @@ class sog_params(C.Structure):
         ("long_form", C.c_int32), ("long_P", C.c_int32), ("long_nk", C.c_int32 * 2),
         ("long_I", C.c_int32 * 2), ("long_Pw", C.c_int32 * 2), ("long_S", C.c_double),
         ("mid_window", C.c_int32), ("mid_beta", C.c_double), ("long_Q", C.c_int32),
-        ("mid_nu", C.c_int32),
+        ("mid_nu", C.c_int32), ("eta", C.c_double),
     ]
 
     def as_dict(self):
@@ -75,7 +75,7 @@ class sog_options(C.Structure):
     _fields_ = [
         ("precision", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
         ("pointers_on_device", C.c_int32), ("check_inputs", C.c_int32), ("timing", C.c_int32),
-        ("params", sog_params), ("static_workspace", C.c_int32),
+        ("params", sog_params), ("static_workspace", C.c_int32), ("deterministic", C.c_int32),
     ]
 
 

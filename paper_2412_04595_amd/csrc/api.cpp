@@ -231,6 +231,13 @@ sog_status build_plan(Plan& p) {
         W.get(ws.key2, n * 8);  // mid-range (tile, rank) pairs
         W.get(ws.scan_tmp2, ((maxbins + 1) / 1024 + 2) * 4);
     }
+    if (r.deterministic) {
+        // bin member lists of the canonical order: the near-field and long-range sorts run
+        // one after the other, the mid range's beside them
+        W.get(ws.det_idx, n * 4);
+        if (r.has_mid) W.get(ws.det_idx2, n * 4);
+        if (r.has_long && r.form == SOG_LONG_FFT) W.get(ws.det_rank, n * 4);
+    }
     ws.red_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256));
     W.get(ws.red, ws.red_blocks * 8);
     p.region_slots = W.slots;
@@ -1051,6 +1058,7 @@ static void fill_params(const Resolved& r, sog_params* o) {
     o->M = r.M;
     o->m = r.m;
     o->set_m = 1;
+    o->eta = r.eta > 0 ? r.eta : (r.m >= 0 ? r.s[r.m] / r.L[2] : 0.0);
     if (r.has_mid) {
         for (int d = 0; d < 3; ++d) {
             o->mid_I[d] = r.I[d];

@@ -18,6 +18,17 @@ constexpr int kMaxMid = 96;       // max number of mid-range Gaussians (m + 1)
 constexpr int kMidSub = 8;        // rank counters per mid-range tile in the counting sort (fewer atomics per address)
 static_assert((kMidSub & (kMidSub - 1)) == 0, "kMidSub is a power of two");
 constexpr int kQsumSlots = 64;    // slots of the charge sums (spreads the float64 atomics of the key pass)
+// Colour of tile t in one direction for the deterministic gridding, which adds the tiles'
+// blocks (tile plus (P_w - 1)/2 nodes each side) into the grid one colour at a time with
+// plain read-add-writes.  Two tiles of one colour must be at least m tiles apart, m - 1
+// full tiles covering the P_w - 1 nodes of the two half-widths; so t mod m, except in a
+// periodic direction (x, y), where the first q m tiles take t mod m and every tile after
+// them (the short last tile among them) a colour of its own, m, m + 1, ...; the planner
+// picks m and q (Resolved::dcol_m, dcol_q).
+constexpr int tile_colour(int t, bool periodic, int m, int q) {
+    return (!periodic || t < q * m) ? t % m : m + (t - q * m);
+}
+
 constexpr int kMaxWinPoly = 16;   // highest degree of a polynomial window
 constexpr int kMaxPw = 15;        // widest mid-range window the gridding and gathering kernels take
 constexpr int kSpreadStage = 32;  // particles whose window weights the gridding kernel stages at a time
@@ -102,6 +113,11 @@ struct Resolved {
     int64_t n = 0;
     double tol = 0;
     int prec = SOG_PREC_FP64;
+    bool deterministic = false;  // canonical bin orders and coloured gridding (no float atomics)
+    int dcol_m[3] = {1, 1, 1};   // deterministic gridding: tile_colour's m, q and the colours
+    int dcol_q[3] = {0, 0, 0};   // per direction
+    int dcol_n[3] = {1, 1, 1};
+    double eta = 0;              // range-splitting factor as given (0: m chosen by cost)
 
     // decomposition (Sec. 2.2)
     double b = 0, r0 = 0, omega = 0, rc = 0, sigma = 0;
@@ -265,6 +281,11 @@ struct Workspace {
     // FFT form of the long range
     int* l2_tile_start = nullptr;  // ntiles + 1
     int* l2_tile_cursor = nullptr; // ntiles
+    // deterministic mode: bin member lists (near field / long range, mid range) and the
+    // long range's canonical ranks (n ints each)
+    int* det_idx = nullptr;
+    int* det_idx2 = nullptr;
+    int* det_rank = nullptr;
     int* l2_g = nullptr;        // n x int4 (gx, gy, -, orig), in tile order
     void* l2_u = nullptr;       // n x real4 (ux, uy, t = 2z/Lz, q)
     void* l2_grid = nullptr;    // max(P_s, P) planes of I2x x I2y reals
@@ -334,6 +355,12 @@ hipError_t launch_counting_sort(Plan& p, const int* key, int n, int nbins, int* 
 // zero the counts (nbins + 1) and cursors (nbins) of a counting sort whose histogram the
 // caller's key kernel builds; launch_exclusive_scan then turns counts into starts
 hipError_t launch_exclusive_scan(Plan& p, int* data, int nbins, int* tmp);  // in place; tmp: block sums
+// deterministic mode: after a counting sort's scan (start: nbins + 1 bin starts), rank the
+// members of every bin by particle index.  pairs: key holds (bin, rank) int2 records and
+// the ranks are replaced in place; else key holds bins (int), the ranks go to rank[i], and
+// cursor (nbins ints) is scratch.  idx: n ints of scratch.
+hipError_t launch_canonical_ranks(Plan& p, int* key, bool pairs, int n, const int* start, int nbins, int* cursor,
+                                  int* idx, int* rank);
 // stages (bit mask): near 1 = cell sort, 2 = pair kernel; mid 1 = tile sort and gridding,
 // 2 = FFT chain and gathering
 hipError_t launch_near(Plan& p, const double* x, const double* q, int stages = 3);

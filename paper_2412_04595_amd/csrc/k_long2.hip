@@ -79,7 +79,8 @@ struct L2KeyK {
 template <typename real>
 struct L2PackK {
     static constexpr int kThreads = 256;
-    __device__ static void run(GridPos gpos, const double* __restrict__ x, const double* __restrict__ q, int n, L2Geom g, const int* __restrict__ key, const int* __restrict__ start, int* __restrict__ cursor, int4* __restrict__ gp, vec4<real>* __restrict__ up) {
+    // rank: the canonical ranks of the deterministic mode, or null (ranks from the cursors)
+    __device__ static void run(GridPos gpos, const double* __restrict__ x, const double* __restrict__ q, int n, L2Geom g, const int* __restrict__ key, const int* __restrict__ start, int* __restrict__ cursor, const int* __restrict__ rank, int4* __restrict__ gp, vec4<real>* __restrict__ up) {
     for (int i = gpos.bid * kThreads + threadIdx.x; i < n; i += gpos.nb * kThreads) {
         int a[2];
         double u[2];
@@ -90,7 +91,7 @@ struct L2PackK {
         double t = 2.0 * (zz - 0.5 * g.L[2]) / g.L[2];
         t = fmin(1.0, fmax(-1.0, t));
         const int k = key[i];
-        const int p = start[k] + atomicAdd(&cursor[k], 1);
+        const int p = start[k] + (rank ? rank[i] : atomicAdd(&cursor[k], 1));
         gp[p] = make_int4(a[0], a[1], 0, i);
         vec4<real> v;
         v.x = (real)u[0];
@@ -549,9 +550,13 @@ hipError_t run_long_fft(Plan& p, const double* x, const double* q) {
     if (e == hipSuccess) e = launch_fill_int(p, ws.l2_tile_cursor, 0, ntiles);
     if (e == hipSuccess) e = launch<L2KeyK, false>(p, blocks, 0, x, n, g, ws.key, ws.l2_tile_start);
     if (e == hipSuccess) e = launch_exclusive_scan(p, ws.l2_tile_start, ntiles + 1, ws.scan_tmp);
+    if (e == hipSuccess && r.deterministic)
+        e = launch_canonical_ranks(p, ws.key, false, n, ws.l2_tile_start, ntiles, ws.l2_tile_cursor, ws.det_idx,
+                                   ws.det_rank);
     if (e == hipSuccess)
         e = launch<L2PackK<real>, false>(p, blocks, 0, x, q, n, g, (const int*)ws.key, (const int*)ws.l2_tile_start,
-                                  ws.l2_tile_cursor, (int4*)ws.l2_g, (vec4<real>*)ws.l2_u);
+                                         ws.l2_tile_cursor, (const int*)(r.deterministic ? ws.det_rank : nullptr),
+                                         (int4*)ws.l2_g, (vec4<real>*)ws.l2_u);
     timer_end(p, t);
     if (e != hipSuccess) return e;
     t = timer_id(p, "long2_spread");

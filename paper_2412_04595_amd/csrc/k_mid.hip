@@ -191,6 +191,11 @@ struct SpreadArgs {
     int nt[3];
     int ntiles;
     WinShape<real> ws;
+    // phase < 0: every tile, blocks added with atomics.  Else (deterministic mode, see
+    // tile_colour) only the tiles of one colour, pfirst[d] + pstep[d] j, j < pcount[d] per
+    // direction, blocks added with plain read-add-writes.
+    int phase;
+    int pfirst[3], pstep[3], pcount[3];
 };
 
 // Owner-tile gridding: the workgroup of a tile spreads the particles whose nearest node
@@ -220,9 +225,19 @@ struct SpreadK {
     constexpr int NPAD = 4 * NPL - PW;           // padding planes after the block
     constexpr int NW = 2 * PW + 1;               // staged y, z weights and a zero per particle
     static_assert(NPL <= 4, "window too wide for four plane groups");
-    const int t = xcd_logical(a.ntiles, gpos);
-    if (t < 0) return;
-    const int tz = t % a.nt[2], ty = (t / a.nt[2]) % a.nt[1], tx = t / (a.nt[2] * a.nt[1]);
+    int t, tx, ty, tz;
+    if (a.phase < 0) {
+        t = xcd_logical(a.ntiles, gpos);
+        if (t < 0) return;
+        tz = t % a.nt[2], ty = (t / a.nt[2]) % a.nt[1], tx = t / (a.nt[2] * a.nt[1]);
+    } else {
+        const int l = xcd_logical(a.pcount[0] * a.pcount[1] * a.pcount[2], gpos);
+        if (l < 0) return;
+        tz = a.pfirst[2] + a.pstep[2] * (l % a.pcount[2]);
+        ty = a.pfirst[1] + a.pstep[1] * ((l / a.pcount[2]) % a.pcount[1]);
+        tx = a.pfirst[0] + a.pstep[0] * (l / (a.pcount[2] * a.pcount[1]));
+        t = (tx * a.nt[1] + ty) * a.nt[2] + tz;
+    }
     const int beg = a.tstart[t * kMidSub], end = a.tstart[(t + 1) * kMidSub];
     if (beg == end) return;
     const int x0 = tx * a.B[0], y0 = ty * a.B[1], z0 = tz * a.B[2];
@@ -367,9 +382,20 @@ struct SpreadK {
             v[j] = (lx < HX) ? halo[lx * HYZ + k] : (real)0;
             at[j] = (size_t)wrap_once(x0 - HW + lx, a.I[0]) * plane + colyz;
         }
+        if (a.phase < 0) {
 #pragma unroll
-        for (int j = 0; j < kHaloILP; ++j)
-            if (v[j] != (real)0) atomicAdd(a.grid + at[j], v[j]);
+            for (int j = 0; j < kHaloILP; ++j)
+                if (v[j] != (real)0) atomicAdd(a.grid + at[j], v[j]);
+        } else {
+            // no other block of this colour touches these nodes, and within the block each
+            // node has one (y, z) column and one x plane
+            real old[kHaloILP];
+#pragma unroll
+            for (int j = 0; j < kHaloILP; ++j) old[j] = v[j] != (real)0 ? a.grid[at[j]] : (real)0;
+#pragma unroll
+            for (int j = 0; j < kHaloILP; ++j)
+                if (v[j] != (real)0) a.grid[at[j]] = old[j] + v[j];
+        }
     }
 }
 };
@@ -554,8 +580,35 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
         hipError_t e = launch<ZeroBandK<real>>(p, std::min((nlines + 3) / 4, 16384), 0, (real*)ws.grid, nlines, r.Izs,
                                                r.zband[0], (r.zband[1] - r.zband[0]) / 2);
         if (e != hipSuccess) return e;
-        if (r.spread_dummy) return launch<SpreadK<real, PW, true>>(p, xcd_grid(ntiles), lds, a);
-        return launch<SpreadK<real, PW, false>>(p, xcd_grid(ntiles), lds, a);
+        a.phase = -1;
+        for (int d = 0; d < 3; ++d) a.pfirst[d] = a.pstep[d] = a.pcount[d] = 0;
+        if (!r.deterministic)
+            return r.spread_dummy ? launch<SpreadK<real, PW, true>>(p, xcd_grid(ntiles), lds, a)
+                                  : launch<SpreadK<real, PW, false>>(p, xcd_grid(ntiles), lds, a);
+        // colour by colour (tile_colour), in a fixed order; one launch over each colour's tiles
+        const int nphase = r.dcol_n[0] * r.dcol_n[1] * r.dcol_n[2];
+        for (int ph = 0; ph < nphase; ++ph) {
+            const int col[3] = {ph / (r.dcol_n[1] * r.dcol_n[2]), (ph / r.dcol_n[2]) % r.dcol_n[1], ph % r.dcol_n[2]};
+            for (int d = 0; d < 3; ++d) {
+                const int m = r.dcol_m[d], qq = r.dcol_q[d], c = col[d];
+                if (d < 2 && c >= m) {  // a tile after the whole runs: a colour of its own
+                    a.pfirst[d] = qq * m + (c - m);
+                    a.pstep[d] = 1;
+                    a.pcount[d] = 1;
+                } else {
+                    a.pfirst[d] = c;
+                    a.pstep[d] = m;
+                    a.pcount[d] = d < 2 ? qq : (r.ntile[d] - c + m - 1) / m;
+                }
+            }
+            const int cnt = a.pcount[0] * a.pcount[1] * a.pcount[2];
+            if (cnt == 0) continue;
+            a.phase = ph;
+            e = r.spread_dummy ? launch<SpreadK<real, PW, true>>(p, xcd_grid(cnt), lds, a)
+                               : launch<SpreadK<real, PW, false>>(p, xcd_grid(cnt), lds, a);
+            if (e != hipSuccess) return e;
+        }
+        return e;
     } else {
         GatherArgs<real> a;
         a.gp = (const int4*)ws.mid_g;
@@ -625,6 +678,8 @@ hipError_t run_mid_prepare(Plan& p, const double* x, const double* q) {
     hipError_t e = launch_fill_int(p, ws.tile_start, 0, (int64_t)nbins + 1);
     if (e == hipSuccess) e = launch<MidKeyK>(p, blocks, 0, x, n, g, (int2*)ws.key2, ws.tile_start);
     if (e == hipSuccess) e = launch_exclusive_scan(p, ws.tile_start, nbins + 1, ws.scan_tmp2);
+    if (e == hipSuccess && r.deterministic)
+        e = launch_canonical_ranks(p, ws.key2, true, n, ws.tile_start, nbins, nullptr, ws.det_idx2, nullptr);
     if (e == hipSuccess)
         e = launch<MidPackK<real>>(p, blocks, 0, x, q, n, g, (const int2*)ws.key2, (const int*)ws.tile_start,
                                    (int4*)ws.mid_g, (vec4<real>*)ws.mid_u);

@@ -41,6 +41,53 @@ struct ScatterK {
     }
 };
 
+// Canonical order of a counting sort (the deterministic mode): the sort's atomic ranks put
+// the members of a bin in an arbitrary order; CanonScatterK lists each bin's members (by
+// particle index) at the ranks they got, and CanonRankK replaces every member's rank by
+// its rank by particle index within the bin, so the packing that follows puts each bin in
+// index order whatever order the atomics took.
+struct CanonScatterK {
+    static constexpr int kThreads = 256;
+    // key[i] = (bin, rank) (int2) when cursor is null, else key[i] = bin (int) and the rank
+    // is taken from cursor[bin] here
+    __device__ static void run(GridPos g, const int* const& key, const int& n, const int* const& start,
+                               int* const& cursor, int* const& idx) {
+        for (int i = g.bid * kThreads + threadIdx.x; i < n; i += g.nb * kThreads) {
+            int pos;
+            if (cursor) {
+                const int k = key[i];
+                pos = start[k] + atomicAdd(&cursor[k], 1);
+            } else {
+                pos = start[key[2 * i]] + key[2 * i + 1];
+            }
+            idx[pos] = i;
+        }
+    }
+};
+
+// One wave per bin (four per block, bins strided over the grid): each lane takes members
+// of the bin, 64 at a time, and counts the members with a smaller particle index (all
+// lanes read the same member at once); rank[stride * i] = that count.  Work grows with
+// the square of a bin's size: about 30 per near-field cell and a few hundred per gridding
+// tile on uniform input.
+struct CanonRankK {
+    static constexpr int kThreads = 256;
+    __device__ static void run(GridPos g, const int* const& start, const int& nbins, const int* const& idx,
+                               int* const& rank, const int& stride) {
+        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int b = g.bid * 4 + wv; b < nbins; b += g.nb * 4) {
+            const int s = start[b], e = start[b + 1];
+            for (int base = s; base < e; base += 64) {
+                const int p = base + lane;
+                const int mine = p < e ? idx[p] : 0x7fffffff;
+                int cnt = 0;
+                for (int q = s; q < e; ++q) cnt += idx[q] < mine ? 1 : 0;
+                if (p < e) rank[(size_t)stride * mine] = cnt;
+            }
+        }
+    }
+};
+
 constexpr int kScanPer = 4;
 constexpr int kScanThreads = 256;
 constexpr int kScanChunk = kScanPer * kScanThreads;
@@ -295,6 +342,20 @@ hipError_t launch_parts_out(Plan& p, double* phi_parts, double* grad_parts) {
                                          phi_parts, grad_parts);
     return launch<PartsOutK<float>>(p, grid_for(3 * p.r.n, 256), 0, (const vec4<float>*)p.ws.parts, p.r.n, phi_parts,
                                     grad_parts);
+}
+
+hipError_t launch_canonical_ranks(Plan& p, int* key, bool pairs, int n, const int* start, int nbins, int* cursor,
+                                  int* idx, int* rank) {
+    if (n <= 0 || nbins <= 0) return hipSuccess;
+    hipError_t e = hipSuccess;
+    if (!pairs) e = launch_fill_int(p, cursor, 0, nbins);
+    if (e == hipSuccess)
+        e = launch<CanonScatterK>(p, grid_for(n, 256), 0, (const int*)key, n, start, pairs ? (int*)nullptr : cursor,
+                                  idx);
+    if (e == hipSuccess)
+        e = launch<CanonRankK>(p, std::min((nbins + 3) / 4, 16384), 0, start, nbins, (const int*)idx,
+                               pairs ? key + 1 : rank, pairs ? 2 : 1);
+    return e;
 }
 
 hipError_t launch_zero_parts(Plan& p, int part) {

@@ -863,6 +863,8 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
         if (e == hipSuccess)
             e = launch<NearKeyK>(p, blocks, 0, x, q, n, g, (int2*)ws.key, ws.cell_start, ws.qsum, ws.status);
         if (e == hipSuccess) e = launch_exclusive_scan(p, ws.cell_start, ncells + 1, ws.scan_tmp);
+        if (e == hipSuccess && r.deterministic)
+            e = launch_canonical_ranks(p, ws.key, true, n, ws.cell_start, ncells, nullptr, ws.det_idx, nullptr);
         if (e == hipSuccess)
             e = launch<NearPackK<real>>(p, blocks, 0, x, q, n, g, (const int2*)ws.key, (const int*)ws.cell_start,
                                         (vec4<real>*)ws.near_pos, ws.near_orig);

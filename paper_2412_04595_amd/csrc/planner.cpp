@@ -323,6 +323,34 @@ void spread_tile(int prec, int Pw, int B[3]) {
     }
 }
 
+// Deterministic gridding (see tile_colour): per direction, m = 1 + ceil((P_w - 1) / B)
+// colours repeat so that two tiles of one colour have m - 1 full tiles between them; in x
+// and y (periodic) the tiles after the last whole run of m, the short last tile among
+// them, get colours of their own, so no run of m crosses the short tile or the wrap.  A
+// block must not wrap onto itself either: B + P_w - 1 <= I (the edge shrinks until it
+// holds).  z is not periodic: t mod m with m at most the tile count.  False if a periodic
+// direction has fewer than two tiles' room.
+bool deterministic_tiles(int Pw, const int gI[3], int B[3], int nt[3], int m[3], int q[3], int ncol[3]) {
+    for (int d = 0; d < 3; ++d) {
+        const bool periodic = d < 2;
+        if (periodic)
+            while (B[d] > 1 && B[d] + Pw - 1 > gI[d]) --B[d];
+        if (periodic && B[d] + Pw - 1 > gI[d]) return false;
+        nt[d] = (gI[d] + B[d] - 1) / B[d];
+        m[d] = 1 + (Pw - 1 + B[d] - 1) / B[d];
+        if (!periodic) {
+            m[d] = std::min(m[d], nt[d]);
+            q[d] = 0;
+            ncol[d] = m[d];
+            continue;
+        }
+        const int full = gI[d] % B[d] == 0 ? nt[d] : nt[d] - 1;
+        q[d] = full / m[d];
+        ncol[d] = m[d] + (nt[d] - q[d] * m[d]);
+    }
+    return true;
+}
+
 // Lane of each window node per pass (see spread_pitch_conflict_free); when the pitch is
 // not conflict-free, nodes in row order.  A lane left without a node in a pass gets, where
 // possible, a dummy node that the kernel updates with zero weight: an offset from the
@@ -912,6 +940,8 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
     if (n <= 1 || n > (int64_t)1 << 26) { err = "n must be in [2, 2^26]"; return SOG_ERR_INVALID_ARG; }
     r.n = n;
     r.prec = opt.precision;
+    r.deterministic = opt.deterministic != 0;
+    r.eta = opt.params.set_m ? 0.0 : opt.params.eta;
     if (r.prec != SOG_PREC_FP64 && r.prec != SOG_PREC_FP32_BULK) { err = "unknown precision"; return SOG_ERR_INVALID_ARG; }
     double tmin = (r.prec == SOG_PREC_FP64) ? 1e-12 : 1e-5;
     if (!(tol >= tmin && tol <= 1e-2)) { err = "tol outside the reachable range for this precision"; return SOG_ERR_TOL_UNREACHABLE; }
@@ -926,6 +956,8 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
     if (ov.long_P < 0 || ov.long_P > 64) { err = "long_P must be in [1, 64]"; return SOG_ERR_INVALID_ARG; }
     if (ov.long_Q < -1 || ov.long_Q > 16) { err = "long_Q must be -1 (exact z kernel), 0 (chosen) or in [1, 16]"; return SOG_ERR_INVALID_ARG; }
     if (ov.mid_Izs % 2) { err = "mid_Izs must be even"; return SOG_ERR_INVALID_ARG; }
+    if (!(ov.eta >= 0) || !std::isfinite(ov.eta)) { err = "eta must be finite and >= 0"; return SOG_ERR_INVALID_ARG; }
+    if (opt.deterministic != 0 && opt.deterministic != 1) { err = "deterministic must be 0 or 1"; return SOG_ERR_INVALID_ARG; }
 
     // decomposition parameters
     bool custom = ov.b > 0 || ov.r0 > 0 || ov.omega > 0;
@@ -981,6 +1013,18 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
             if (c.s[l] <= 2.0 * r.L[2]) mhi = l;
         mhi = std::min(mhi, std::min(M - 1, kMaxMid - 1));
         if (ov.set_m) { mlo = mhi = ov.m; }
+        if (ov.eta > 0 && !ov.set_m) {
+            // the range-splitting definition (Sec. 3.1): mid range are the Gaussians with
+            // s_l <= eta L_z
+            int me = -1;
+            for (int l = 0; l <= M; ++l)
+                if (c.s[l] <= ov.eta * r.L[2]) me = l;
+            if (me >= kMaxMid || me >= M) {
+                why = "eta puts more Gaussians in the mid range than the kernels take";
+                continue;
+            }
+            mlo = mhi = me;
+        }
         if (ov.set_m && (ov.m < -1 || ov.m > M || ov.m >= kMaxMid)) { err = "m out of range"; return SOG_ERR_INVALID_ARG; }
         for (int m = mlo; m <= mhi; ++m) {
             double cost = near_cost;
@@ -1071,6 +1115,10 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         for (int d = 0; d < 3; ++d) {
             r.B[d] = std::min(Bt[d], gI[d]);
             r.ntile[d] = (gI[d] + r.B[d] - 1) / r.B[d];
+        }
+        if (r.deterministic && !deterministic_tiles(r.Pw, gI, r.B, r.ntile, r.dcol_m, r.dcol_q, r.dcol_n)) {
+            err = "deterministic gridding: the mid grid is too small for the window";
+            return SOG_ERR_INVALID_ARG;
         }
         r.spread_dummy = spread_lane_nodes(r.Pw, r.B[2] + r.Pw - 1, r.B[2], r.node_oy, r.node_oz);
         if (!is_smooth(r.I[0]) || !is_smooth(r.I[1]) || !is_smooth(r.Izs / 2)) { err = "mid grid sizes must have only factors 2, 3, 5, 7 (and I_z*/2 as well)"; return SOG_ERR_INVALID_ARG; }

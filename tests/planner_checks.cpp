@@ -18,7 +18,8 @@
 //  6. the float32 near-field polynomials in monomial form (below);
 //  7. the ES window transform (Gauss-Legendre) against a fine composite Simpson sum in x
 //     itself (no change of variable), and the Gauss-Legendre rule against exact moments;
-//  8. the KB window's transform and its polynomial form (below).
+//  8. the KB window's transform and its polynomial form (below);
+//  9. the deterministic gridding's tiling (below).
 //
 // Prints one line per failure and "bad N"; exit status 0 when N == 0.
 #include <cmath>
@@ -366,8 +367,70 @@ static void check_kb_window() {
     }
 }
 
+// 9. Deterministic gridding: for grids of every size class, every window and the tile
+//    edges the planner uses (and smaller), the tiling deterministic_tiles returns puts no
+//    two blocks (tile plus (P_w - 1)/2 nodes each side, wrapped in x and y, clipped in z)
+//    of one tile_colour on a common node, and no block on a node twice (no self-wrap);
+//    the colour count matches, and the colour lists the spread launcher forms
+//    (first + m j, j < q or the tail tile) are exactly the tiles of that colour.  Checked
+//    per direction, which suffices: two tiles of one 3D colour have the same colour in
+//    every direction, and blocks that are apart in one direction do not meet.
+static void check_deterministic_tiles() {
+    long tried = 0;
+    for (int Pw = 3; Pw <= 15; Pw += 2)
+        for (int I = 2 * Pw; I <= 700; I += (I < 80 ? 1 : 7))
+            for (int B0 : {4, 6, 7, 10, 11, 14, 16, 24, 37}) {
+                ++tried;
+                const int gI[3] = {I, I, I + 6};
+                int B[3] = {B0, B0, B0}, nt[3], m[3], q[3], nc[3];
+                if (!deterministic_tiles(Pw, gI, B, nt, m, q, nc)) {
+                    CHECK(false, "deterministic tiles: none for P_w %d I %d B %d", Pw, I, B0);
+                    continue;
+                }
+                const int hw = (Pw - 1) / 2;
+                for (int d = 0; d < 3; ++d) {
+                    const bool periodic = d < 2;
+                    const int n = gI[d];
+                    CHECK(B[d] <= B0 && nt[d] == (n + B[d] - 1) / B[d], "tile count");
+                    std::vector<int> owner(n);
+                    int maxcol = 0;
+                    for (int t = 0; t < nt[d]; ++t) maxcol = std::max(maxcol, tile_colour(t, periodic, m[d], q[d]));
+                    CHECK(maxcol + 1 == nc[d], "deterministic tiles: P_w %d I %d dir %d: %d colours used, %d counted",
+                          Pw, n, d, maxcol + 1, nc[d]);
+                    for (int col = 0; col < nc[d]; ++col) {
+                        // the launcher's list of this colour's tiles
+                        std::vector<int> listed;
+                        if (periodic && col >= m[d]) listed.push_back(q[d] * m[d] + (col - m[d]));
+                        else {
+                            const int cnt = periodic ? q[d] : (nt[d] - col + m[d] - 1) / m[d];
+                            for (int j = 0; j < cnt; ++j) listed.push_back(col + m[d] * j);
+                        }
+                        std::vector<int> expect;
+                        for (int t = 0; t < nt[d]; ++t)
+                            if (tile_colour(t, periodic, m[d], q[d]) == col) expect.push_back(t);
+                        CHECK(listed == expect, "deterministic tiles: P_w %d I %d dir %d colour %d: launcher lists "
+                              "%zu tiles, %zu have the colour", Pw, n, d, col, listed.size(), expect.size());
+                        std::fill(owner.begin(), owner.end(), -1);
+                        for (int t : expect) {
+                            const int lo = t * B[d] - hw, hi = std::min(n, (t + 1) * B[d]) + hw;
+                            for (int g = lo; g < hi; ++g) {
+                                int gg = g;
+                                if (periodic) gg = ((g % n) + n) % n;
+                                else if (g < 0 || g >= n) continue;
+                                CHECK(owner[gg] == -1, "deterministic tiles: P_w %d I %d B %d dir %d: tiles %d and %d "
+                                      "of colour %d share node %d", Pw, n, B[d], d, owner[gg], t, col, gg);
+                                owner[gg] = t;
+                            }
+                        }
+                    }
+                }
+            }
+    std::printf("deterministic tiles: %ld grids\n", tried);
+}
+
 int main() {
     check_es_transform();
+    check_deterministic_tiles();
     check_kb_window();
     check_near_monomials();
     check_near_chunks();

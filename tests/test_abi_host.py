@@ -154,6 +154,45 @@ def test_resolve_is_deterministic_and_respects_overrides():
     assert c["mid_I"] == [32, 32, 32] and c["mid_Izs"] == 80 and c["mid_Pw"] == [9, 9, 9]
 
 
+def test_eta_sets_the_range_split():
+    """eta (the range-splitting definition, Sec. 3.1): m is the last Gaussian with
+    s_l <= eta L_z, so a larger eta moves Gaussians into the mid range; the resolved eta
+    is the given one, or s_m / L_z of the split the cost model chose; set_m wins over eta."""
+    import numpy as np
+    from oracle.sog import SOG
+    box, n, tol = (50.0, 50.0, 200.0), 100000, 1e-4
+    auto = sog.plan_parameters(box, n, tol, "fp32")
+    s = SOG(auto["b"], auto["r0"], auto["omega"], auto["rc"], auto["M"]).s
+    assert auto["m"] >= 0 and abs(auto["eta"] - s[auto["m"]] / box[2]) < 1e-12
+    for eta in (0.1, 0.3, 1.0):
+        p = sog.plan_parameters(box, n, tol, "fp32", dict(eta=eta))
+        s = SOG(p["b"], p["r0"], p["omega"], p["rc"], p["M"]).s
+        want = int(np.max(np.nonzero(s[: p["M"] + 1] <= eta * box[2])[0], initial=-1))
+        assert p["m"] == want and p["eta"] == eta
+    lo = sog.plan_parameters(box, n, tol, "fp32", dict(eta=0.1))
+    hi = sog.plan_parameters(box, n, tol, "fp32", dict(eta=1.0))
+    # a wider long range needs fewer Chebyshev terms in z (Thm thm::Che)
+    assert lo["m"] < hi["m"] and lo["long_P"] > hi["long_P"]
+    forced = sog.plan_parameters(box, n, tol, "fp32", dict(eta=1.0, set_m=1, m=lo["m"]))
+    assert forced["m"] == lo["m"]
+    assert _resolve_status(box, n, tol, "fp32", dict(eta=-1.0)) == _lib.SOG_ERR_INVALID_ARG
+
+
+def test_deterministic_plans():
+    """The deterministic option keeps every parameter of the plan (only the gridding tiles
+    may shrink, which the parameters do not show) and is refused for values other than 0
+    and 1."""
+    for box, n, tol, prec in [((100, 100, 100), 1000000, 1e-4, "fp32"), ((20, 20, 20), 1000, 1e-8, "fp64"),
+                              ((953.5, 953.5, 0.3), 1000000, 1e-4, "fp32")]:
+        a = sog.plan_parameters(box, n, tol, prec)
+        b = sog.plan_parameters(box, n, tol, prec, deterministic=True)
+        assert a == b
+    o = sog.make_options("fp64")
+    o.deterministic = 2
+    with pytest.raises(sog.SogError):
+        _lib.sog_plan_resolve((20, 20, 20), 1000, 1e-6, o)
+
+
 def test_tighter_tolerance_refines():
     lo = sog.plan_parameters((100, 100, 100), 1000000, 1e-4, "fp64")
     hi = sog.plan_parameters((100, 100, 100), 1000000, 1e-8, "fp64")
