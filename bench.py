@@ -121,6 +121,27 @@ def traffic_from_profiles(kernel, workload):
     return None
 
 
+def counters_from_profiles(kernel, workload):
+    """The committed rocprofv3 counter summary's line for the kernel (VALU issue, MFMA busy,
+    LDS activity and bank conflicts, resident waves per CU), if taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    digest = None
+    for line in open(path):
+        if line.startswith("# sources digest"):
+            digest = line.split()[-1]
+    if digest != source_digest():
+        return None
+    for line in open(path):
+        f = line.split()
+        if f and not line.startswith("#") and f[0] == kernel and len(f) >= 9:
+            return {"valu_issue": float(f[3]), "mfma_busy": float(f[4]), "lds_active": float(f[5]),
+                    "lds_bank_conflict": float(f[6]), "waves_per_cu": float(f[7]),
+                    "source": f"profiles/counters_{workload}.txt"}
+    return None
+
+
 def reference_energy(workload):
     """The oracle's energy of the workload (plain fast method at two tolerances that
     agree), from tests/golden/<workload>_energy.txt, or None."""
@@ -197,8 +218,9 @@ def cpu_baseline(tol):
                        f"(near {tm['short']:.1f}, mid {tm['mid']:.1f}, long {tm['long']:.1f}){note}")
 
 
-def run_form(sog, torch, xt, qt, box, N, tol, precision, steps, warmup, params=None):
-    s = sog.Solver(box, N, tol, precision=precision, on_device=True, check_inputs=False, timing=True, params=params)
+def run_form(sog, torch, xt, qt, box, N, tol, precision, steps, warmup, params=None, deterministic=False):
+    s = sog.Solver(box, N, tol, precision=precision, on_device=True, check_inputs=False, timing=True, params=params,
+                   deterministic=deterministic)
     # one checked call first: inputs valid, neutral, z in range
     chk = sog.Solver(box, N, tol, precision=precision, on_device=True, check_inputs=True, timing=False,
                      params=params)
@@ -328,6 +350,8 @@ def main():
     ap.add_argument("--no-confined", action="store_true", help="skip the strongly confined box")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-system batch")
     ap.add_argument("--no-kb", action="store_true", help="skip the KB-window run of the headline workload")
+    ap.add_argument("--no-deterministic", action="store_true",
+                    help="skip the deterministic-mode run of the headline workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three 256 MiB device-to-device copies (the known-size copy that scales the "
                          "HBM counters of a profiling run)")
@@ -381,6 +405,7 @@ def main():
         mdl = models[dom]
         roof = roofline_of(mdl, per_launch[dom] * 1e-3)
         roof["traffic"] = traffic_from_profiles(dom, args.workload)
+        roof["counters"] = counters_from_profiles(dom, args.workload)
         roof["kernel"] = dom
         roof["kernel_ms"] = per_launch[dom]
         roof["algorithmic_bytes"] = mdl["bytes"]
@@ -405,6 +430,16 @@ def main():
               "kernels_ms_per_step": {k: round(v[0] / max(5, args.steps // 2), 4) for k, v in
                                       sorted(rk["kt"].items(), key=lambda kv: -kv[1][0]) if k in ("mid_spread", "mid_gather")}}
         log(f"[bench] {args.workload} fp32 KB window {rk['dt'] * 1e3:.3f} ms/step")
+    # the same workload in the deterministic mode (canonical bin orders, coloured gridding)
+    det = None
+    if not args.no_deterministic:
+        steps_d = max(5, args.steps // 2)
+        rd = run_form(sog, torch, xt, qt, box, N, args.tol, "fp32", steps_d, 2, deterministic=True)
+        det = {"value": N / rd["dt"], "unit": "particles/s", "ms_per_step": rd["dt"] * 1e3,
+               "kernels_ms_per_step": {k: round(v[0] / steps_d, 4) for k, v in
+                                       sorted(rd["kt"].items(), key=lambda kv: -kv[1][0]) if k.endswith("sort")
+                                       or k in ("mid_spread", "near", "long2_spread")}}
+        log(f"[bench] {args.workload} fp32 deterministic {rd['dt'] * 1e3:.3f} ms/step")
     confined = None
     if not args.no_confined:
         confined = secondary(sog, torch, "confined_1e6", args.tol, max(5, args.steps // 2))
@@ -450,6 +485,7 @@ def main():
         "spread_gather_hbm": spread_gather_hbm(r32["info"], r32["sizes"], N, per_launch, 4),
         "roofline_kernels": others,
         "kb_window": kb,
+        "deterministic": det,
         "strongly_confined": confined,
         "batched": batched,
         "cpu_baseline": cpu,

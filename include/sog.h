@@ -80,7 +80,8 @@ typedef enum { SOG_LONG_AUTO = 0, SOG_LONG_DIRECT = 1, SOG_LONG_FFT = 2 } sog_lo
  * |x| <= a, shape mid_beta, with its closed-form transform; the kernels evaluate it as in
  * Remark rmk::PWindow, by polynomials of degree mid_nu (Chebyshev interpolation of each
  * node's weight over the particle's offset from its nearest node).  AUTO: the cheapest
- * that meets the tolerance (the Gaussian when mid_S is given; ES over KB on a tie). */
+ * that meets the tolerance (the Gaussian when mid_S is given; KB over ES on a tie: the ES
+ * window's derivative is unbounded at its support's edge, which costs float32 gradients). */
 typedef enum { SOG_WINDOW_AUTO = 0, SOG_WINDOW_GAUSSIAN = 1, SOG_WINDOW_ES = 2, SOG_WINDOW_KB = 3 } sog_window;
 
 /*

@@ -193,7 +193,7 @@ sog_status build_plan(Plan& p) {
         A.get(ws.mult_ay, (size_t)(r.m + 1) * r.I[1] * rs);
         A.get(ws.mult_az, (size_t)(r.m + 1) * Kz * rs);
         A.get(ws.mult_c, (size_t)(r.m + 1) * rs);
-        if (r.window == SOG_WINDOW_KB) A.get(ws.wpoly, (size_t)r.Pw * (r.nu + 1) * rs);
+        if (r.window == SOG_WINDOW_KB) A.get(ws.wpoly, (size_t)r.Pw * window_poly_row(r.nu) * rs);
     }
     if (r.has_long) {
         if (r.form == SOG_LONG_DIRECT) {
@@ -316,9 +316,14 @@ sog_status build_plan(Plan& p) {
         if (e == hipSuccess) e = upload(ws.mult_az, az, f64);
         if (e == hipSuccess) e = upload(ws.mult_c, cl, f64);
         if (e == hipSuccess && r.window == SOG_WINDOW_KB) {
-            std::vector<double> coef;
+            std::vector<double> coef, padded;
             window_poly_fit(r.Pw, r.beta, r.nu, coef);
-            e = upload(ws.wpoly, coef, f64);
+            // rows of window_poly_row(nu) coefficients, highest degree first: leading zeros
+            const int row = window_poly_row(r.nu), pad = row - (r.nu + 1);
+            padded.assign((size_t)r.Pw * row, 0.0);
+            for (int o = 0; o < r.Pw; ++o)
+                for (int j = 0; j <= r.nu; ++j) padded[(size_t)o * row + pad + j] = coef[(size_t)o * (r.nu + 1) + j];
+            e = upload(ws.wpoly, padded, f64);
         }
         if (e == hipSuccess) e = hipMemcpy(ws.spread_nodes, r.node_oy, 4 * 64, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(ws.spread_nodes + 4 * 64, r.node_oz, 4 * 64, hipMemcpyHostToDevice);

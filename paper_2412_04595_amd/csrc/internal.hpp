@@ -30,6 +30,9 @@ constexpr int tile_colour(int t, bool periodic, int m, int q) {
 }
 
 constexpr int kMaxWinPoly = 16;   // highest degree of a polynomial window
+// coefficients per node in the device table of a polynomial window of degree nu: nu + 1
+// rounded up to a multiple of 4 (leading zeros)
+constexpr int window_poly_row(int nu) { return (nu + 1 + 3) / 4 * 4; }
 constexpr int kMaxPw = 15;        // widest mid-range window the gridding and gathering kernels take
 constexpr int kSpreadStage = 32;  // particles whose window weights the gridding kernel stages at a time
 // LDS of one gridding or gathering workgroup at most: for narrow float32 windows (P_w <=

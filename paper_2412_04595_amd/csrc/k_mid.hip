@@ -107,24 +107,55 @@ struct WinShape {
     int kind, nu;
 };
 
-// node o's polynomial weight at offset u, and its derivative in u (Horner)
+// node o's polynomial weight at offset u, and its derivative in u (Horner).  Each node's
+// row holds nu + 1 coefficients, a multiple of 4 (leading zeros, which leave Horner's
+// rule exact), taken 4 at a time.
 template <typename real>
 __device__ __forceinline__ real win_poly(int o, real u, const WinShape<real>& s) {
-    const real* c = s.poly + o * (s.nu + 1);
-    real w = c[0];
-    for (int j = 1; j <= s.nu; ++j) w = fma(w, u, c[j]);
+    typedef const __attribute__((address_space(1))) real* gptr;  // the table is in global memory
+    const gptr c = (gptr)s.poly + o * (s.nu + 1);
+    real w = 0;
+    for (int j = 0; j <= s.nu; j += 4) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w = fma(w, u, c[j + i]);
+    }
     return w;
 }
 template <typename real>
 __device__ __forceinline__ void win_poly_d(int o, real u, const WinShape<real>& s, real& w, real& dw) {
-    const real* c = s.poly + o * (s.nu + 1);
-    real v = c[0], d = 0;
-    for (int j = 1; j <= s.nu; ++j) {
-        d = fma(d, u, v);
-        v = fma(v, u, c[j]);
+    typedef const __attribute__((address_space(1))) real* gptr;
+    const gptr c = (gptr)s.poly + o * (s.nu + 1);
+    real v = 0, d = 0;
+    for (int j = 0; j <= s.nu; j += 4) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            d = fma(d, u, v);
+            v = fma(v, u, c[j + i]);
+        }
     }
     w = v;
     dw = d;
+}
+// all P_w nodes' weights and derivatives (dcoef d/du) at once, the nodes' Horner chains
+// side by side
+template <typename real, int PW>
+__device__ __forceinline__ void win_poly_all(real u, const WinShape<real>& s, real dcoef, real* w, real* dw) {
+    const int n1 = s.nu + 1;
+    // the table is in global memory (read through a flat pointer taken from the LDS copy
+    // of a batched launch's arguments, the compiler emitted an invalid aperture test)
+    typedef const __attribute__((address_space(1))) real* gptr;
+    const gptr c = (gptr)s.poly;
+#pragma unroll
+    for (int o = 0; o < PW; ++o) w[o] = dw[o] = 0;
+    for (int j = 0; j < n1; ++j) {
+#pragma unroll
+        for (int o = 0; o < PW; ++o) {
+            dw[o] = fma(dw[o], u, w[o]);
+            w[o] = fma(w[o], u, c[o * n1 + j]);
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < PW; ++o) dw[o] *= dcoef;
 }
 
 template <typename real, int PW>
@@ -509,10 +540,15 @@ struct GatherK {
         const int4 g = a.gp[p];
         const vec4<real> u = a.up[p];
         real wy[PW], dwy[PW], wz[PW], dwz[PW];
+        if (a.ws.kind == kWinPoly) {
+            win_poly_all<real, PW>(u.y, a.ws, a.dcoef[1], wy, dwy);
+            win_poly_all<real, PW>(u.z, a.ws, a.dcoef[2], wz, dwz);
+        } else {
 #pragma unroll
-        for (int o = 0; o < PW; ++o) {
-            win_d<real, PW>(o, u.y, a.ws, a.dcoef[1], wy[o], dwy[o]);
-            win_d<real, PW>(o, u.z, a.ws, a.dcoef[2], wz[o], dwz[o]);
+            for (int o = 0; o < PW; ++o) {
+                win_d<real, PW>(o, u.y, a.ws, a.dcoef[1], wy[o], dwy[o]);
+                win_d<real, PW>(o, u.z, a.ws, a.dcoef[2], wz[o], dwz[o]);
+            }
         }
         const int lx0 = g.x - x0, ly0 = g.y - y0, lz0 = g.z - z0;
         real phi = 0, gx = 0, gy = 0, gz = 0;
@@ -562,7 +598,7 @@ hipError_t spread_gather_pw(Plan& p, bool spread) {
     shape.inv_a = (real)(2.0 / PW);
     shape.poly = (const real*)ws.wpoly;
     shape.kind = poly ? kWinPoly : (es ? kWinES : kWinGauss);
-    shape.nu = r.nu;
+    shape.nu = window_poly_row(r.nu) - 1;  // the padded degree of the table
     if (spread) {
         SpreadArgs<real> a;
         a.gp = (const int4*)ws.mid_g;

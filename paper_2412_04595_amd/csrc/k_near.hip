@@ -317,6 +317,12 @@ struct NearArgs {
     real cG[kMaxNearDeg + 1];
     real mF[kMaxNearDeg + 1];  // the same in monomial form (float32 kernel, Horner)
     real mG[kMaxNearDeg + 1];
+    // float32 kernel: pairs closer than sqrt(rclose2) take their separation from the
+    // float64 input coordinates x (minimum image over L in x, y) instead of from the
+    // float32 offsets, whose rounding (~5e-7 of a cell) would cost 5e-7 / r of 1/r
+    const double* __restrict__ x;
+    double L[2];
+    real rclose2;
 };
 
 constexpr int kNearWaves = 4;   // independent waves per block
@@ -595,6 +601,24 @@ __device__ __forceinline__ void near_pair_nz(const NearArgs<float>& a, float rx,
     gz += c * rz;
 }
 
+// The separation x_i - x_j of a close pair (packed positions pi, pj) from the float64
+// input coordinates: minimum image in x and y (the near field reaches at most L/2), none
+// in z.  Left unchanged for non-finite input (whose records hold zeros).
+__device__ __forceinline__ void near_close_separation(const NearArgs<float>& a, int pi, int pj, float& rx, float& ry,
+                                                   float& rz) {
+    const int i = a.orig[pi], j = a.orig[pj];
+    double d[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d[k] = a.x[3 * (size_t)i + k] - a.x[3 * (size_t)j + k];
+    d[0] -= a.L[0] * rint(d[0] / a.L[0]);
+    d[1] -= a.L[1] * rint(d[1] / a.L[1]);
+    if (isfinite(d[0]) && isfinite(d[1]) && isfinite(d[2])) {
+        rx = (float)d[0];
+        ry = (float)d[1];
+        rz = (float)d[2];
+    }
+}
+
 template <int DEG>
 struct NearMfmaK {
     static constexpr int kThreads = 64 * kNearWaves;
@@ -701,18 +725,22 @@ struct NearMfmaK {
         auto chunk = [&]() {
             const int cnt = (tp - hd) & kMask;
             vec4<float> o[kEval], sh[kEval];
+            int src[kEval];
             const uint32_t dummy = (uint32_t)tb | (8u << kNearCodeShift);
 #pragma unroll
             for (int u = 0; u < kEval; ++u) {
                 const uint32_t e = (cnt > 0) ? hits[((hd + min(u, cnt - 1)) & kMask) * 64 + lane] : dummy;
-                o[u] = a.pos[e & ((1u << kNearCodeShift) - 1)];
+                src[u] = (int)(e & ((1u << kNearCodeShift) - 1));
+                o[u] = a.pos[src[u]];
                 sh[u] = shift[e >> kNearCodeShift];
             }
 #pragma unroll
             for (int u = 0; u < kEval; ++u)
-                if (u < cnt)
-                    near_pair_nz<DEG>(a, tx - (o[u].x + sh[u].x), ty - (o[u].y + sh[u].y), tz - (o[u].z + sh[u].z),
-                                      o[u].w, phi, gx, gy, gz);
+                if (u < cnt) {
+                    float rx = tx - (o[u].x + sh[u].x), ry = ty - (o[u].y + sh[u].y), rz = tz - (o[u].z + sh[u].z);
+                    if (rx * rx + ry * ry + rz * rz < a.rclose2) near_close_separation(a, p, src[u], rx, ry, rz);
+                    near_pair_nz<DEG>(a, rx, ry, rz, o[u].w, phi, gx, gy, gz);
+                }
             hd = (hd + min(cnt, kEval)) & kMask;
         };
         auto drain_ready = [&]() {
@@ -899,6 +927,10 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
     }
     a.rc2 = (real)(r.rc * r.rc);
     a.inv_rc2 = (real)(1.0 / (r.rc * r.rc));
+    a.x = x;
+    a.L[0] = r.L[0];
+    a.L[1] = r.L[1];
+    a.rclose2 = (real)(r.rc * r.rc / (32.0 * 32.0));
     a.deg = r.near_deg;
     for (int k = 0; k <= kMaxNearDeg; ++k) {
         a.cF[k] = (real)r.near_cF[k];

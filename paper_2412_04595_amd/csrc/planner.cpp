@@ -591,8 +591,11 @@ MidChoice plan_mid(const double L[3], int64_t n, double s0, double sm, int nl, d
             const int wmin = std::min(fft_lines_per_batch(prec, c.I[0]), fft_lines_per_batch(prec, c.I[1]));
             const double fft_pen = wmin >= 8 ? 1.0 : 1.0 + 0.5 * std::log2(8.0 / wmin);
             c.cost = (double)n * (kCostSpreadSlot * slots + kCostGatherPt * Pw * Pw * Pw) + kCostFFTPt * Ng * fft_pen;
-            // the KB window's weights by polynomials: charged 1% so that ES keeps the ties
-            if (win == 2) c.cost *= 1.01;
+            // ES is charged 1% so that KB takes the ties: the ES window's derivative is
+            // infinite at the edge of its support, and in float32 its gradients near the
+            // edge lost up to 5e-3 of the mid range's largest (10^6 and 8e6 cubes; KB's
+            // polynomials 2e-6, the same support and cost within 4%)
+            if (win == 1) c.cost *= 1.01;
             c.ok = true;
             if (c.cost < best.cost) best = c;
         }

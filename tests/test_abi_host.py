@@ -212,11 +212,12 @@ def test_tight_tolerance_small_box_plans(tol):
 
 
 def test_window_choice():
-    """AUTO takes the ES window where it is cheaper (the 10^6 cube), the Gaussian when its
-    shape is given; each explicit choice is honoured and reported with its shape."""
+    """AUTO takes a compact window where it is cheaper (the 10^6 cube: KB, which wins the
+    tie with ES), the Gaussian when its shape is given; each explicit choice is honoured and
+    reported with its shape."""
     box, n = (100.0, 100.0, 100.0), 1000000
     auto = sog.plan_parameters(box, n, 1e-4, "fp32")
-    assert auto["mid_window"] == _lib.SOG_WINDOW_ES and auto["mid_beta"] > 0 and auto["mid_S"] == 0
+    assert auto["mid_window"] == _lib.SOG_WINDOW_KB and auto["mid_beta"] > 0 and auto["mid_S"] == 0
     g = sog.plan_parameters(box, n, 1e-4, "fp32", dict(mid_window=_lib.SOG_WINDOW_GAUSSIAN))
     assert g["mid_window"] == _lib.SOG_WINDOW_GAUSSIAN and g["mid_S"] > 0 and g["mid_beta"] == 0
     assert auto["mid_Pw"][0] < g["mid_Pw"][0]  # the compact window needs fewer points
@@ -237,15 +238,16 @@ def test_window_choice():
 
 
 def test_kb_window_plans():
-    """The KB window on request: the same support as ES on the 10^6 cube (their aliasing
-    is alike), the polynomial degree chosen from the tolerance (higher for a tighter one)
-    or taken as given; AUTO keeps ES on a tie."""
+    """The KB window: the same support as ES on the 10^6 cube (their aliasing is alike),
+    the polynomial degree chosen from the tolerance (higher for a tighter one) or taken as
+    given; AUTO takes KB on the tie."""
     box, n = (100.0, 100.0, 100.0), 1000000
-    es = sog.plan_parameters(box, n, 1e-4, "fp32")
+    es = sog.plan_parameters(box, n, 1e-4, "fp32", dict(mid_window=_lib.SOG_WINDOW_ES))
     kb = sog.plan_parameters(box, n, 1e-4, "fp32", dict(mid_window=_lib.SOG_WINDOW_KB))
     assert kb["mid_window"] == _lib.SOG_WINDOW_KB and kb["mid_beta"] > 0 and kb["mid_S"] == 0
     assert abs(kb["mid_Pw"][0] - es["mid_Pw"][0]) <= 2 and 4 <= kb["mid_nu"] <= 16
     assert es["mid_window"] == _lib.SOG_WINDOW_ES and es["mid_nu"] == 0
+    assert sog.plan_parameters(box, n, 1e-4, "fp32") == kb
     tight = sog.plan_parameters((20, 20, 20), 1000, 1e-10, "fp64", dict(mid_window=_lib.SOG_WINDOW_KB))
     assert tight["mid_window"] == _lib.SOG_WINDOW_KB and tight["mid_nu"] > kb["mid_nu"]
     given = sog.plan_parameters((20, 20, 20), 1000, 1e-6, "fp64",
