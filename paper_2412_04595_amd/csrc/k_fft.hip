@@ -284,9 +284,10 @@ __device__ __forceinline__ void fft_stage(cpx<T>* A, const cpx<T>* __restrict__ 
 
 // In-LDS transform of W interleaved lines (W a power of two, n W <= kFFTCap; element i
 // of line w at A[i P + w]).  The caller synchronises before (data in A) and may read A
-// after the return.
+// after the return.  Inlined (called, it costs its caller the calling convention's
+// registers).
 template <typename T, int SIGN>
-__device__ void lds_fft(cpx<T>* A, const cpx<T>* __restrict__ twl, int W, int P, const FFTDev& f) {
+__device__ __forceinline__ void lds_fft(cpx<T>* A, const cpx<T>* __restrict__ twl, int W, int P, const FFTDev& f) {
     const int lw = __ffs(W) - 1;
     for (int s = 0; s < f.nstages; ++s) {
         switch (f.radix[s]) {

@@ -71,20 +71,22 @@ __device__ __forceinline__ int batch_system(const int* __restrict__ boff, int ns
     return lo;
 }
 
-// A block copies its system's argument record into LDS and runs the body on that copy
-// (reading the record from global memory where it is used made the compiler hold whole
-// argument structs in vector registers: 2x the registers of the single-plan kernels).
+// A block finds its system (a uniform value) and runs the body on that system's argument
+// record, read through the constant address space (scalar loads, as kernel arguments
+// are).  The body is forced inline: as a called function it took the calling
+// convention's registers (248 VGPRs and one wave per SIMD where the single-plan kernel
+// has 124 and four).
 template <class B, class... A>
 __global__ __launch_bounds__(B::kThreads) void k_batched(const KArgs<A...>* __restrict__ tab,
                                                          const int* __restrict__ boff, int nsys) {
-    __shared__ __align__(16) uint32_t rec_lds[(sizeof(KArgs<A...>) + 3) / 4];
-    const int s = batch_system(boff, nsys);
-    const GridPos g{(int)blockIdx.x - boff[s], boff[s + 1] - boff[s]};
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(tab + s);
-    for (int i = threadIdx.x; i < (int)(sizeof(KArgs<A...>) / 4); i += B::kThreads) rec_lds[i] = src[i];
-    __syncthreads();
-    const KArgs<A...>& rec = *reinterpret_cast<const KArgs<A...>*>(rec_lds);
-    rec.call([&](const A&... a) { B::run(g, a...); });
+    const int s = __builtin_amdgcn_readfirstlane(batch_system(boff, nsys));
+    const int b0 = __builtin_amdgcn_readfirstlane(boff[s]), b1 = __builtin_amdgcn_readfirstlane(boff[s + 1]);
+    const GridPos g{(int)blockIdx.x - b0, b1 - b0};
+    typedef const __attribute__((address_space(4))) KArgs<A...>* cptr;
+    const cptr rec = (cptr)tab + s;
+    ((const KArgs<A...>*)rec)->call([&](const A&... a) __attribute__((always_inline)) {
+        [[clang::always_inline]] B::run(g, a...);
+    });
 }
 
 // One recorded launch.
