@@ -174,6 +174,7 @@ sog_status build_plan(Plan& p) {
     W.get(ws.cell_start, (ncells + 1) * 4);
     W.get(ws.near_orig, n * 4);
     W.get(ws.near_pos, n * 4 * rs);
+    if (f64) W.get(ws.near_pos32, n * 16);  // the float32 candidate test's copy
     W.get(ws.near_units, ((size_t)near_unit_slots(r) * 16 + 127) / 128 * 128 + 8 * 128);  // units, then 8 work counters
     if (r.has_mid) {
         const int ntiles = r.ntile[0] * r.ntile[1] * r.ntile[2];

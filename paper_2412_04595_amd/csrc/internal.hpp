@@ -183,9 +183,8 @@ struct Resolved {
 constexpr int kLong2Tile = 16;
 constexpr int kLong2MaxPlanes = 32;
 
-// Near-field work units.  Float64: runs of at most kNearUnitCells cells of a column with at
-// most 64 targets, one slot per cell.  Float32: chunks of at most kNearChunk consecutive
-// targets of a column within at most kNearUnitCells cells, formed greedily; a column of
+// Near-field work units: chunks of at most kNearChunk consecutive targets of a column
+// within at most kNearUnitCells cells, formed greedily; a column of
 // ncz cells needs at most floor(count / kNearChunk) full chunks, one last chunk and
 // ceil(ncz / kNearUnitCells) - 1 chunks cut short (their first cells lie below
 // ncz - kNearUnitCells, kNearUnitCells apart), so column c's slots start at
@@ -223,7 +222,6 @@ SOG_HOST_DEVICE inline int near_chunk_walk(const int* cs, int ncz, Emit&& emit) 
 }
 inline int64_t near_unit_slots(const Resolved& r) {
     const int64_t ncols = (int64_t)r.nc[0] * r.nc[1];
-    if (r.prec == SOG_PREC_FP64) return ncols * r.nc[2];
     return r.n / kNearChunk + ncols * near_chunk_extra(r.nc[2]);
 }
 
@@ -258,6 +256,7 @@ struct Workspace {
     int* cell_start = nullptr;  // ncells + 1
     int* near_orig = nullptr;   // n
     void* near_pos = nullptr;   // n x real4 (x, y, z relative to the cell corner; q)
+    void* near_pos32 = nullptr; // float64 plans: n x float4, the same records in float32
     void* near_units = nullptr; // near_unit_slots() int4 work units, then 8 work counters
     // mid range
     int* tile_start = nullptr;  // ntiles * kMidSub + 1: tile t owns [tile_start[t kMidSub], tile_start[(t+1) kMidSub])

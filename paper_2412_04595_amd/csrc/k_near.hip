@@ -9,13 +9,12 @@
 //
 // Pipeline: a counting sort of the particles by cell (cells z-fastest, so a column is one
 // contiguous range), then a sort by z inside each cell, so every column is z-ordered.
-// Work units are formed per column on the device: float32, chunks of at most 32
-// consecutive targets within at most kNearUnitCells cells (k_near_chunks; the pair kernel
-// tests candidates against them on the matrix cores, k_near_mfma); float64, runs of
-// whole cells with at most 64 targets (k_near_units, the vector-ALU kernel k_near).  A
-// unit's candidates are, per neighbouring column (9 of them), the cells from below the
-// unit to above it, cut where they cross a z frame (below) and narrowed by bisection to
-// the unit's z extent +- r_c.
+// Work units are formed per column on the device: chunks of at most 32 consecutive
+// targets within at most kNearUnitCells cells (NearChunksK); the pair kernel (NearMfmaK)
+// tests candidates against them on the matrix cores in float32 and evaluates the hits in
+// the plan's precision.  A unit's candidates are, per neighbouring column (9 of them),
+// the cells from below the unit to above it, cut where they cross a z frame (below) and
+// narrowed by bisection to the unit's z extent +- r_c.
 //
 // Coordinates enter the pair kernel as offsets from the corner of the particle's x, y
 // cell and of its z frame (kNearFrameCells cells), formed in float64, so the float32 form
@@ -39,7 +38,6 @@ constexpr int kNearFrameCells = 8;  // z cells per coordinate frame; a work unit
                                     // kNearUnitCells = 7 cells, so its candidate z range
                                     // (<= 9 cells) crosses at most one frame boundary
 static_assert(kNearUnitCells + 2 <= kNearFrameCells + 1, "candidate range crosses two frame boundaries");
-constexpr int kNearUnitTargets = 64;
 
 __device__ __forceinline__ void cell_of(const NearGeom& g, double xw, double yw, double z, int c[3]) {
     double v[3] = {xw, yw, z};
@@ -118,47 +116,8 @@ struct NearPackK {
 }
 };
 
-// Work units: each column's cells grouped greedily into runs of at most kNearUnitCells
-// cells and kNearUnitTargets particles; unit = (column, first cell, end cell), stored in
-// the column's own slots (column x cells) in z order, unused slots marked by -1, so that
-// consecutive units are neighbours in space.  One wave per column: the column's cell
-// starts are read in parallel into LDS, then lane 0 walks them.
 constexpr int kUnitsLds = 4096;  // cells of a column staged in LDS at a time
 constexpr int kGrabStride = 32;  // ints between the per-XCD work counters (own 128-byte lines)
-struct NearUnitsK {
-    static constexpr int kThreads = 64;
-    __device__ static void run(GridPos gpos, const int* __restrict__ cell_start, int ncz, int4* __restrict__ units, int* __restrict__ grab) {
-    __shared__ int cs[kUnitsLds + 1];
-    const int col = gpos.bid;
-    if (col == 0 && threadIdx.x < 8) grab[threadIdx.x * kGrabStride] = 0;  // the pair kernel's work counters
-    const int* gcs = cell_start + (size_t)col * ncz;
-    int4* us = units + (size_t)col * ncz;
-    int z0 = 0, u = 0;
-    for (int c0 = 0; c0 < ncz; c0 += kUnitsLds) {
-        const int cnt = min(kUnitsLds, ncz - c0);
-        __syncthreads();
-        for (int i = threadIdx.x; i <= cnt; i += 64) cs[i] = gcs[c0 + i];
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            // runs end within this chunk of cells (a run may not cross it)
-            while (z0 < c0 + cnt) {
-                int z1 = z0 + 1, n = cs[z0 + 1 - c0] - cs[z0 - c0];
-                while (z1 < c0 + cnt && z1 - z0 < kNearUnitCells &&
-                       n + (cs[z1 + 1 - c0] - cs[z1 - c0]) <= kNearUnitTargets) {
-                    n += cs[z1 + 1 - c0] - cs[z1 - c0];
-                    ++z1;
-                }
-                if (n > 0) us[u++] = make_int4(col, z0, z1, 0);
-                z0 = z1;
-            }
-        }
-    }
-    __syncthreads();
-    u = __shfl(u, 0, 64);
-    for (int i = u + (int)threadIdx.x; i < ncz; i += 64) us[i] = make_int4(col, -1, -1, 0);
-}
-};
-
 // Work units of the float32 pair kernel: chunks of at most kNearChunk consecutive targets
 // of a column, cut where a chunk would span more than kNearUnitCells cells; unit =
 // (cell of the first target, first target, end target, end cell), in the column's slots
@@ -305,7 +264,7 @@ struct NearArgs {
     const int* __restrict__ cell_start;
     vec4<real>* __restrict__ part;  // near part of each particle: phi, grad
     const int4* __restrict__ units;  // (column, first cell, end cell); first cell -1: none
-    int* grab;                       // per-XCD counters of units taken (zeroed by k_near_units)
+    int* grab;                       // per-XCD counters of units taken (zeroed by NearChunksK)
     const int* status;               // bit 4: some cell is not z-sorted (no bisection of the ranges)
     float zcut;                      // r_c with a rounding margin: the z reach of the ranges
     int max_units;
@@ -323,6 +282,11 @@ struct NearArgs {
     const double* __restrict__ x;
     double L[2];
     real rclose2;
+    // the candidate test's float32 positions (the records themselves in float32 plans) and
+    // the margin added to r_c^2 in that test (float64 plans: the float32 test must not
+    // lose a pair inside r_c; the evaluation cuts at r_c exactly)
+    const vec4<float>* __restrict__ pos32;
+    float test_margin;
 };
 
 constexpr int kNearWaves = 4;   // independent waves per block
@@ -331,8 +295,6 @@ constexpr int kNearWaves = 4;   // independent waves per block
 // (LDS and waves) on every compute unit beside it
 constexpr int kNearBlocksPerCU = 4;
 constexpr int kNearCap = 32;    // hit-list entries per lane (a ring; power of two)
-template <typename real>
-constexpr int kNearBatch = sizeof(real) == 4 ? 8 : 4;  // candidates tested between checks of the list's room
 constexpr int kNearCodeShift = 26;  // hit entry: source index | (neighbour range << 26)
 
 // 1/sqrt: the hardware reciprocal square root in float32 (r^2 is far from denormal here)
@@ -364,195 +326,8 @@ __device__ __forceinline__ void near_pair(const NearArgs<real>& a, real rx, real
     gz += c * rz;
 }
 
-template <typename real, int DEG>
-__device__ __forceinline__ void near_pair(const NearArgs<real>& a, real rx, real ry, real rz, real qj, real& phi,
-                                          real& gx, real& gy, real& gz) {
-    near_pair<real, DEG>(a, rx, ry, rz, qj, phi, gx, gy, gz, rx * rx + ry * ry + rz * rz);
-}
-
-// Each wave takes one z-block.  Its lanes hold up to 64 targets; the candidate sources
-// are walked in uniform order (so their loads are the same address in every lane), each
-// lane tests every candidate and appends the ones within r_c to its own hit list in LDS;
-// the lists are evaluated when one is nearly full and at the end, so the polynomial runs
-// only for pairs inside r_c (about 15% of the candidates) and the lanes' evaluation loops
-// have similar lengths.  A pair is the particle with itself exactly when r^2 == 0 (same
-// stored coordinates, zero shift); that pair is skipped.
-template <typename real, int DEG>
-struct NearK {
-    static constexpr int kThreads = 64 * kNearWaves;
-    __device__ static void run(GridPos gpos, const NearArgs<real>& a) {
-    __shared__ uint32_t hits_all[kNearWaves][kNearCap * 64];
-    __shared__ vec4<real> shift_all[kNearWaves][18];
-    // the candidates' addresses are the same in every lane: read them through the
-    // constant address space, which gives scalar loads (the array is not written here)
-    const __attribute__((address_space(4))) vec4<real>* cpos = (const __attribute__((address_space(4))) vec4<real>*)a.pos;
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint32_t* hits = hits_all[wv];
-    vec4<real>* shift = shift_all[wv];
-    // persistent waves (no block-wide barrier below: waves are independent): the blocks
-    // of XCD x (block b runs on XCD b % 8) take the units of the x-th eighth one at a
-    // time from that eighth's counter, so that neighbouring columns share an L2 and the
-    // waves finish together
-    const int per = (a.max_units + 7) >> 3;
-    const int ibeg = (gpos.bid & 7) * per, iend = min(a.max_units, ibeg + per);
-    int* grab = a.grab + (gpos.bid & 7) * kGrabStride;
-    const bool trim = (__builtin_amdgcn_readfirstlane(*a.status) & 4) == 0;
-    for (;;) {
-    int g = 0;
-    if (lane == 0) g = atomicAdd(grab, 1);
-    const int item = ibeg + __builtin_amdgcn_readfirstlane(g);
-    if (item >= iend) break;
-    const int4 unit = a.units[item];
-    if (unit.y < 0) continue;
-    const int col = unit.x, z0 = unit.y, z1 = unit.z;
-    const int cy = col % a.nc[1], cx = col / a.nc[1];
-    const int tb = a.cell_start[col * a.nc[2] + z0], te = a.cell_start[col * a.nc[2] + z1];
-    // lane k < 18: neighbour range k = column (dx, dy) = k / 2, piece k % 2 of the cells
-    // from below the run to above it, cut at the z frame boundary; shift.z holds the frame
-    int rs = 0, re = 0;
-    if (lane < 18) {
-        const int c9 = lane >> 1, piece = lane & 1;
-        const int dx = c9 % 3 - 1, dy = c9 / 3 - 1;
-        const int ncol = imod(cx + dx, a.nc[0]) * a.nc[1] + imod(cy + dy, a.nc[1]);
-        const int za = max(z0 - 1, 0), zb = min(z1 + 1, a.nc[2]);
-        const int bnd = (za / kNearFrameCells + 1) * kNearFrameCells;
-        const int pa = piece ? bnd : za, pb = piece ? zb : min(zb, bnd);
-        if (pa < pb) {
-            rs = a.cell_start[ncol * a.nc[2] + pa];
-            re = a.cell_start[ncol * a.nc[2] + pb];
-        }
-        shift[lane] = vec4<real>{(real)dx * a.ch[0], (real)dy * a.ch[1], (real)(pa / kNearFrameCells), (real)0};
-        if (trim && rs < re) {
-            // the columns are z-sorted: keep the candidates within zcut of the run's targets
-            // in z (first and last target), by bisection in the piece's frame coordinates
-            const real fh = (real)kNearFrameCells * a.ch[2];
-            const real tzlo = a.pos[tb].z + (real)(z0 / kNearFrameCells) * fh;
-            const real tzhi = a.pos[te - 1].z + (real)((z1 - 1) / kNearFrameCells) * fh;
-            const real fo = (real)(pa / kNearFrameCells) * fh;
-            const real lo = tzlo - (real)a.zcut - fo, hi = tzhi + (real)a.zcut - fo;
-            int l = rs, h = re;
-            while (l < h) {
-                const int mid = (l + h) >> 1;
-                if (a.pos[mid].z < lo) l = mid + 1; else h = mid;
-            }
-            rs = l;
-            h = re;
-            while (l < h) {
-                const int mid = (l + h) >> 1;
-                if (a.pos[mid].z <= hi) l = mid + 1; else h = mid;
-            }
-            re = l;
-        }
-    }
-    constexpr int nranges = 18;
-    const real fh = (real)kNearFrameCells * a.ch[2];  // frame height
-    // longest of the ranges
-    int maxlen = re - rs;
-    for (int o = 32; o > 0; o >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, o, 64));
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int t0 = tb; t0 < te; t0 += 64) {
-        const int p = t0 + lane;
-        const bool act = p < te;
-        const vec4<real> me = act ? a.pos[p] : vec4<real>{(real)1e30, (real)1e30, (real)1e30, (real)0};
-        // the target's z frame (the run's cells are consecutive in p)
-        int tcz = z0;
-        for (int c = z0 + 1; c < z1; ++c)
-            if (p >= a.cell_start[col * a.nc[2] + c]) tcz = c;
-        const real tczr = (real)(tcz / kNearFrameCells);
-        real phi = 0, gx = 0, gy = 0, gz = 0;
-        // each lane's hit list is a ring of kNearCap entries: tail tp, head hd
-        int tp = 0, hd = 0;
-        constexpr int kMask = kNearCap - 1;
-        // evaluate up to four entries of every lane's list, their loads issued first
-        auto chunk = [&]() {
-            const int cnt = (tp - hd) & kMask;
-            vec4<real> o[4], sh[4];
-            // a lane with an empty list loads a valid dummy (the block's first particle)
-            const uint32_t dummy = (uint32_t)tb;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t e = (cnt > 0) ? hits[((hd + min(u, cnt - 1)) & kMask) * 64 + lane] : dummy;
-                o[u] = a.pos[e & ((1u << kNearCodeShift) - 1)];
-                sh[u] = shift[e >> kNearCodeShift];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (u < cnt)
-                    near_pair<real, DEG>(a, me.x - (o[u].x + sh[u].x), me.y - (o[u].y + sh[u].y),
-                                         me.z - (o[u].z + (sh[u].z - tczr) * fh), o[u].w, phi, gx, gy, gz);
-            hd = (hd + min(cnt, 4)) & kMask;
-        };
-        // a chunk is evaluated as soon as every active lane has four entries waiting (all
-        // lanes busy), or when some list is too full for the next batch of candidates
-        auto drain_ready = [&]() {
-            while (true) {
-                const int cnt = (tp - hd) & kMask;
-                if (__ballot(act && cnt < 4) != 0 && __ballot(cnt > kNearCap - 1 - kNearBatch<real>) == 0) break;
-                chunk();
-            }
-        };
-        // the ranges are walked round-robin, one batch of each in turn, so that every
-        // lane's list grows at about the same rate and a list that fills up finds the
-        // others nearly as full (the evaluation runs as long as the longest list)
-        for (int off = 0; off < maxlen; off += kNearBatch<real>) {
-            for (int k = 0; k < nranges; ++k) {
-                const int js = __builtin_amdgcn_readlane(rs, k) + off, je = __builtin_amdgcn_readlane(re, k);
-                if (js >= je) continue;
-                const vec4<real> sh = shift[k];
-                const real mx = me.x - sh.x, my = me.y - sh.y, mz = me.z - (sh.z - tczr) * fh;
-                const uint32_t code = (uint32_t)k << kNearCodeShift;
-                // the particle itself is among the candidates only in the centre column
-                // (zero x, y shift), in its own frame, where the pair has r^2 == 0
-                const real r2min = ((k >> 1) == 4) ? (real)0 : (real)-1;
-                drain_ready();
-                vec4<real> o[kNearBatch<real>];
-                if (js + kNearBatch<real> <= je) {
-#pragma unroll
-                    for (int u = 0; u < kNearBatch<real>; ++u) {
-                        o[u].x = cpos[js + u].x;
-                        o[u].y = cpos[js + u].y;
-                        o[u].z = cpos[js + u].z;
-                    }
-#pragma unroll
-                    for (int u = 0; u < kNearBatch<real>; ++u) {
-                        const real rx = mx - o[u].x, ry = my - o[u].y, rz = mz - o[u].z;
-                        const real r2 = rx * rx + ry * ry + rz * rz;
-                        hits[tp * 64 + lane] = (uint32_t)(js + u) | code;
-                        tp = (tp + ((r2 < a.rc2 && r2 > r2min) ? 1 : 0)) & kMask;
-                    }
-                } else {
-                    // the range's last partial batch; indices past it re-read its last
-                    // element and are masked out of the count
-#pragma unroll
-                    for (int u = 0; u < kNearBatch<real>; ++u) {
-                        const int jj = min(js + u, je - 1);
-                        o[u].x = cpos[jj].x;
-                        o[u].y = cpos[jj].y;
-                        o[u].z = cpos[jj].z;
-                    }
-#pragma unroll
-                    for (int u = 0; u < kNearBatch<real>; ++u) {
-                        const real rx = mx - o[u].x, ry = my - o[u].y, rz = mz - o[u].z;
-                        const real r2 = rx * rx + ry * ry + rz * rz;
-                        hits[tp * 64 + lane] = (uint32_t)(js + u) | code;
-                        tp = (tp + ((r2 < a.rc2 && r2 > r2min && js + u < je) ? 1 : 0)) & kMask;
-                    }
-                }
-            }
-        }
-        while (__ballot(tp != hd)) chunk();
-        if (act) {
-            const int i = a.orig[p];
-            a.part[i] = vec4<real>{phi, gx, gy, gz};
-        }
-    }
-    }
-}
-};
-
-// The float32 pair kernel with the candidate test on the matrix cores.  A pass takes 32
+// The pair kernel with the candidate test on the matrix cores (float32 test; evaluation in
+// float32 or, for float64 plans, float64: see NearMfmaK).  A pass takes 32
 // targets; lanes l and l + 32 share target l % 32 and split its candidates between their
 // hit lists.  The unit's 18 candidate ranges are walked as one sequence in blocks of 32,
 // and one block against the pass's targets is a 32 x 32 matrix
@@ -619,16 +394,22 @@ __device__ __forceinline__ void near_close_separation(const NearArgs<float>& a, 
     }
 }
 
-template <int DEG>
+// E: the evaluation precision.  The candidate test always runs in float32 on the matrix
+// cores (positions a.pos32); with E = double the hits are tested with a margin of
+// a.test_margin and then evaluated, and cut at r_c exactly, in float64 (positions a.pos).
+template <int DEG, typename E = float>
 struct NearMfmaK {
     static constexpr int kThreads = 64 * kNearWaves;
-    __device__ static void run(GridPos gpos, const NearArgs<float>& a) {
+    static constexpr bool kF64 = sizeof(E) == 8;
+    __device__ static void run(GridPos gpos, const NearArgs<E>& a) {
     __shared__ uint32_t hits_all[kNearWaves][kNearCap * 64];
     __shared__ vec4<float> shift_all[kNearWaves][18];
+    __shared__ vec4<E> shiftE_all[kNearWaves][kF64 ? 18 : 1];  // float64 shifts (E = double)
     __shared__ alignas(16) uint32_t codes_all[kNearWaves][32];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, half = lane >> 5, jl = lane & 31;
     uint32_t* hits = hits_all[wv];
     vec4<float>* shift = shift_all[wv];
+    vec4<E>* shiftE = kF64 ? shiftE_all[wv] : reinterpret_cast<vec4<E>*>(shift_all[wv]);
     uint32_t* codes = codes_all[wv];
     char* hits_bytes = reinterpret_cast<char*>(&hits_all[0][0]);
     static_assert(kNearCap * 256 == 8192, "list slot bits 8..12 between the lane and wave bits");
@@ -636,7 +417,9 @@ struct NearMfmaK {
     const int per = (a.max_units + 7) >> 3;
     const int ibeg = (gpos.bid & 7) * per, iend = min(a.max_units, ibeg + per);
     int* grab = a.grab + (gpos.bid & 7) * kGrabStride;
-    const float fh = (float)kNearFrameCells * a.ch[2];  // frame height
+    const float fh = (float)kNearFrameCells * (float)a.ch[2];  // frame height
+    const E fhE = (E)kNearFrameCells * a.ch[2];
+    const vec4<float>* __restrict__ pos32 = a.pos32;  // the test's positions
     const bool trim = (__builtin_amdgcn_readfirstlane(*a.status) & 4) == 0;
     for (;;) {
     int g = 0;
@@ -650,10 +433,11 @@ struct NearMfmaK {
     const int tb = unit.y, te = unit.z;
     const int za = max(z0 - 1, 0), zb = min(z1 + 1, a.nc[2]);
     const int bnd = (za / kNearFrameCells + 1) * kNearFrameCells;
-    const float zmid = 0.5f * (float)(z0 + z1) * a.ch[2];
+    const float zmid = 0.5f * (float)(z0 + z1) * (float)a.ch[2];
+    const E zmidE = (E)0.5 * (E)(z0 + z1) * a.ch[2];
     // the chunk's z extent (its targets are z-sorted): frame-relative z plus the frame base
-    const float tzlo = a.pos[tb].z + (float)(z0 / kNearFrameCells) * fh;
-    const float tzhi = a.pos[te - 1].z + (float)((z1 - 1) / kNearFrameCells) * fh;
+    const float tzlo = pos32[tb].z + (float)(z0 / kNearFrameCells) * fh;
+    const float tzhi = pos32[te - 1].z + (float)((z1 - 1) / kNearFrameCells) * fh;
     // lane k < 18: range k = column (dx, dy) = k / 2, piece k % 2 of the cells from below
     // the run to above it, cut at the frame boundary; its shift into the unit frame
     int rs = 0, len = 0;
@@ -667,9 +451,12 @@ struct NearMfmaK {
             rs = a.cell_start[ncol * a.nc[2] + pa];
             len = a.cell_start[ncol * a.nc[2] + pb] - rs;
         }
-        sk = vec4<float>{((float)dx - 0.5f) * a.ch[0], ((float)dy - 0.5f) * a.ch[1],
+        sk = vec4<float>{((float)dx - 0.5f) * (float)a.ch[0], ((float)dy - 0.5f) * (float)a.ch[1],
                          (float)(pa / kNearFrameCells) * fh - zmid, 0.f};
         shift[lane] = sk;
+        if constexpr (kF64)
+            shiftE[lane] = vec4<E>{((E)dx - (E)0.5) * a.ch[0], ((E)dy - (E)0.5) * a.ch[1],
+                                   (E)(pa / kNearFrameCells) * fhE - zmidE, (E)0};
         if (trim && len > 0) {
             // the columns are z-sorted: keep the candidates within zcut of the chunk's z
             // extent [z of the first target, z of the last], by bisection in the piece's
@@ -679,13 +466,13 @@ struct NearMfmaK {
             int l = rs, h = rs + len;
             while (l < h) {
                 const int mid = (l + h) >> 1;
-                if (a.pos[mid].z < lo) l = mid + 1; else h = mid;
+                if (pos32[mid].z < lo) l = mid + 1; else h = mid;
             }
             const int nrs = l;
             h = rs + len;
             while (l < h) {
                 const int mid = (l + h) >> 1;
-                if (a.pos[mid].z <= hi) l = mid + 1; else h = mid;
+                if (pos32[mid].z <= hi) l = mid + 1; else h = mid;
             }
             len = l - nrs;
             rs = nrs;
@@ -707,24 +494,34 @@ struct NearMfmaK {
     for (int t0 = tb; t0 < te; t0 += 32) {
         const int p = t0 + jl;
         const bool act = p < te;
-        const vec4<float> me = act ? a.pos[p] : vec4<float>{0.f, 0.f, 0.f, 0.f};
+        const vec4<float> me = act ? pos32[p] : vec4<float>{0.f, 0.f, 0.f, 0.f};
         int tcz = z0;
         for (int c = z0 + 1; c < z1; ++c)
             if (p >= a.cell_start[col * a.nc[2] + c]) tcz = c;
         // the target in the unit frame: the shift of its own column (dx = dy = 0, ranges
         // 8 and 9) in its own frame
-        const vec4<float> st = shift[8 + ((tcz / kNearFrameCells) != (za / kNearFrameCells) ? 1 : 0)];
+        const int sti = 8 + ((tcz / kNearFrameCells) != (za / kNearFrameCells) ? 1 : 0);
+        const vec4<float> st = shift[sti];
         const float tx = me.x + st.x, ty = me.y + st.y, tz = me.z + st.z;
-        const float thr = act ? a.rc2 - (tx * tx + ty * ty + tz * tz) : -INFINITY;
+        const float thr = act ? (float)a.rc2 + a.test_margin - (tx * tx + ty * ty + tz * tz) : -INFINITY;
+        // the target in the evaluation precision
+        E txE = tx, tyE = ty, tzE = tz;
+        if constexpr (kF64) {
+            const vec4<E> meE = act ? a.pos[p] : vec4<E>{0, 0, 0, 0};
+            const vec4<E> stE = shiftE[sti];
+            txE = meE.x + stE.x;
+            tyE = meE.y + stE.y;
+            tzE = meE.z + stE.z;
+        }
         const float b1 = half ? -2.f * ty : -2.f * tx;
         const float b2 = half ? 1.f : -2.f * tz;
-        float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
+        E phi = 0, gx = 0, gy = 0, gz = 0;
         int tp = 0, hd = 0;
         constexpr int kMask = kNearCap - 1;
-        constexpr int kEval = 4;  // list entries evaluated per lane per round
+        constexpr int kEval = kF64 ? 2 : 4;  // list entries evaluated per lane per round
         auto chunk = [&]() {
             const int cnt = (tp - hd) & kMask;
-            vec4<float> o[kEval], sh[kEval];
+            vec4<E> o[kEval], sh[kEval];
             int src[kEval];
             const uint32_t dummy = (uint32_t)tb | (8u << kNearCodeShift);
 #pragma unroll
@@ -732,14 +529,21 @@ struct NearMfmaK {
                 const uint32_t e = (cnt > 0) ? hits[((hd + min(u, cnt - 1)) & kMask) * 64 + lane] : dummy;
                 src[u] = (int)(e & ((1u << kNearCodeShift) - 1));
                 o[u] = a.pos[src[u]];
-                sh[u] = shift[e >> kNearCodeShift];
+                sh[u] = shiftE[e >> kNearCodeShift];
             }
 #pragma unroll
             for (int u = 0; u < kEval; ++u)
                 if (u < cnt) {
-                    float rx = tx - (o[u].x + sh[u].x), ry = ty - (o[u].y + sh[u].y), rz = tz - (o[u].z + sh[u].z);
-                    if (rx * rx + ry * ry + rz * rz < a.rclose2) near_close_separation(a, p, src[u], rx, ry, rz);
-                    near_pair_nz<DEG>(a, rx, ry, rz, o[u].w, phi, gx, gy, gz);
+                    E rx = txE - (o[u].x + sh[u].x), ry = tyE - (o[u].y + sh[u].y), rz = tzE - (o[u].z + sh[u].z);
+                    if constexpr (kF64) {
+                        // the float32 test admits pairs up to the margin beyond r_c: the cut
+                        // at r_c is made here; the particle itself has r^2 = 0
+                        const E r2 = rx * rx + ry * ry + rz * rz;
+                        if (r2 < a.rc2 && r2 > (E)0) near_pair<E, DEG>(a, rx, ry, rz, o[u].w, phi, gx, gy, gz, r2);
+                    } else {
+                        if (rx * rx + ry * ry + rz * rz < a.rclose2) near_close_separation(a, p, src[u], rx, ry, rz);
+                        near_pair_nz<DEG>(a, rx, ry, rz, o[u].w, phi, gx, gy, gz);
+                    }
                 }
             hd = (hd + min(cnt, kEval)) & kMask;
         };
@@ -781,7 +585,7 @@ struct NearMfmaK {
         advance(0);
         bool vn = jl < total;
         uint32_t cn = (uint32_t)(vn ? bl + jl : tb) | ((uint32_t)kl << kNearCodeShift);
-        vec4<float> on = a.pos[cn & ((1u << kNearCodeShift) - 1)];
+        vec4<float> on = pos32[cn & ((1u << kNearCodeShift) - 1)];
         float sxn = sx, syn = sy, szn = sz;
         for (int v0 = 0; v0 < total; v0 += 32) {
             const bool valid = vn;
@@ -803,7 +607,7 @@ struct NearMfmaK {
                 advance(v0 + 32);
                 vn = v0 + 32 + jl < total;
                 cn = (uint32_t)(vn ? bl + v0 + 32 + jl : tb) | ((uint32_t)kl << kNearCodeShift);
-                on = a.pos[cn & ((1u << kNearCodeShift) - 1)];
+                on = pos32[cn & ((1u << kNearCodeShift) - 1)];
                 sxn = sx;
                 syn = sy;
                 szn = sz;
@@ -837,20 +641,29 @@ struct NearMfmaK {
         gz += __shfl_xor(gz, 32, 64);
         if (act && half == 0) {
             const int i = a.orig[p];
-            a.part[i] = vec4<float>{phi, gx, gy, gz};
+            a.part[i] = vec4<E>{phi, gx, gy, gz};
         }
     }
     }
 }
 };
 
+// The float32 copy of the float64 records (after the per-cell z sort) for the float32
+// candidate test of float64 plans.
+struct NearPos32K {
+    static constexpr int kThreads = 256;
+    __device__ static void run(GridPos g, const vec4<double>* __restrict__ pos, int n, vec4<float>* __restrict__ pos32) {
+        for (int i = g.bid * kThreads + threadIdx.x; i < n; i += g.nb * kThreads) {
+            const vec4<double> v = pos[i];
+            pos32[i] = vec4<float>{(float)v.x, (float)v.y, (float)v.z, (float)v.w};
+        }
+    }
+};
+
 // polynomial degrees compiled; the fitted degree is rounded up to one of these
 template <typename real, int DEG>
 hipError_t launch_near_deg(Plan& p, const NearArgs<real>& a, int blocks) {
-    if constexpr (sizeof(real) == 4)
-        return launch<NearMfmaK<DEG>>(p, blocks, 0, a);
-    else
-        return launch<NearK<real, DEG>>(p, blocks, 0, a);
+    return launch<NearMfmaK<DEG, real>>(p, blocks, 0, a);
 }
 
 template <typename real>
@@ -900,14 +713,12 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
         if (e == hipSuccess)
             e = launch<NearZsortK<real>>(p, (ncells + 3) / 4, 0, (const int*)ws.cell_start, ncells,
                                          (vec4<real>*)ws.near_pos, ws.near_orig, ws.status);
-        if (e == hipSuccess) {
-            if (sizeof(real) == 4)
-                e = launch<NearChunksK>(p, ncols, 0, (const int*)ws.cell_start, r.nc[2], near_chunk_extra(r.nc[2]),
-                                        (int4*)ws.near_units, near_grab(ws, near_unit_slots(r)));
-            else
-                e = launch<NearUnitsK>(p, ncols, 0, (const int*)ws.cell_start, r.nc[2], (int4*)ws.near_units,
-                                       near_grab(ws, near_unit_slots(r)));
-        }
+        if (e == hipSuccess && sizeof(real) == 8)
+            e = launch<NearPos32K>(p, std::min((n + 255) / 256, 4096), 0, (const vec4<double>*)ws.near_pos, n,
+                                   (vec4<float>*)ws.near_pos32);
+        if (e == hipSuccess)
+            e = launch<NearChunksK>(p, ncols, 0, (const int*)ws.cell_start, r.nc[2], near_chunk_extra(r.nc[2]),
+                                    (int4*)ws.near_units, near_grab(ws, near_unit_slots(r)));
         timer_end(p, t);
         if (e != hipSuccess || !(stages & 2)) return e;
     }
@@ -931,6 +742,10 @@ hipError_t run_near(Plan& p, const double* x, const double* q, int stages) {
     a.L[0] = r.L[0];
     a.L[1] = r.L[1];
     a.rclose2 = (real)(r.rc * r.rc / (32.0 * 32.0));
+    a.pos32 = sizeof(real) == 4 ? (const vec4<float>*)ws.near_pos : (const vec4<float>*)ws.near_pos32;
+    // the float32 test's rounding stays below 1e-5 r_c^2 (coordinates within a few cells of
+    // the unit's centre); float64 plans admit 4e-5 r_c^2 more and cut exactly
+    a.test_margin = sizeof(real) == 4 ? 0.f : (float)(4e-5 * r.rc * r.rc);
     a.deg = r.near_deg;
     for (int k = 0; k <= kMaxNearDeg; ++k) {
         a.cF[k] = (real)r.near_cF[k];

@@ -234,8 +234,9 @@ const Row kTable1[6] = {
 
 // GPU cost model: seconds per unit of work of the float32 kernels on MI355X, fitted to
 // the kernels' event times at N = 10^6 on the cube for two windows and grid sizes (float64
-// takes about twice as long in every term but the near field's, about three times).  It
-// only ranks candidate discretisations, all of which meet the error model.
+// takes about twice as long in every term, the near field's included since its candidate
+// test runs on the matrix cores in float32 for both forms: the same ranking serves both).
+// It only ranks candidate discretisations, all of which meet the error model.
 constexpr double kCostNearPair = 5.6e-12;   // per neighbour pair within r_c
 constexpr double kCostSpreadSlot = 1.0e-10; // per particle per gridding lane update (x planes of a wave x 64-node passes)
 constexpr double kCostGatherPt = 1.7e-13;   // per particle per window point of the gathering
@@ -1008,7 +1009,7 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         M = std::min(M, 4000);
         c.M = M;
         sog_weights(c.b, c.sigma, c.omega, M, c.w, c.s);
-        double near_cost = kCostNearPair * (r.prec == SOG_PREC_FP64 ? 3.0 : 1.0) * (double)n * rho *
+        double near_cost = kCostNearPair * (double)n * rho *
                            neighbour_volume(rc, r.L[2]);
         // candidate splits: m = -1 (all long) .. last l with s_l <= 2 Lz
         int mlo = -1, mhi = -1;
