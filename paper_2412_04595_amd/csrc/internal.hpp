@@ -44,18 +44,17 @@ constexpr int kSpreadStage = 32;  // particles whose window weights the gridding
 constexpr size_t kTileLdsBytes = 81920;  // the largest budget
 inline size_t tile_lds_budget(int Pw, size_t real_bytes) { return (real_bytes == 4 && Pw <= 9) ? 53248 : kTileLdsBytes; }
 
-// LDS layout of the mid-range gridding kernel: the tile plus its (P_w - 1) halo, 64 sink
-// slots for masked lanes, and per staged particle its y and z window weights (2 P_w) and
-// its x weights rotated for the four plane groups (16 reals); then, on a 32-byte boundary,
-// the staged particles' offsets from their grid points and charges (real4 each), the four
-// groups' plane offsets (int4) and the x nodes (int).
-// LDS of the gridding kernel: the tile's halo block plus 4 ceil(P_w / 4) - P_w padding
-// planes, 64 sink slots, the staged weights (kSpreadStage x (2 P_w + 1 + 16) reals), then
-// 32-byte aligned particle records.
+// LDS layout of the mid-range gridding kernel: the tile plus its (P_w - 1) halo (and
+// 4 ceil(P_w / 4) - P_w padding planes), 64 sink slots for masked lanes, and per staged
+// particle its y and z window weights and a zero (2 P_w + 1 reals); then, on a 32-byte
+// boundary, the staged particles' x weights rotated for the four plane groups (16 reals
+// each, read four at a time), their offsets from their grid points and charges (real4
+// each), the four groups' plane offsets (int4) and the x nodes (int).
 inline size_t spread_lds_offset_records(size_t real_bytes, int Pw, int Bx, int By, int Bz) {
     const size_t plane = (size_t)(By + Pw - 1) * (Bz + Pw - 1);
     const size_t tot = (size_t)(Bx + Pw - 1 + 4 * ((Pw + 3) / 4) - Pw) * plane;
-    return ((tot + 64 + (size_t)kSpreadStage * (2 * Pw + 17)) * real_bytes + 31) / 32 * 32;
+    return ((tot + 64 + (size_t)kSpreadStage * (2 * Pw + 1)) * real_bytes + 31) / 32 * 32 +
+           (size_t)kSpreadStage * 16 * real_bytes;
 }
 inline size_t spread_lds_bytes(size_t real_bytes, int Pw, int Bx, int By, int Bz) {
     return spread_lds_offset_records(real_bytes, Pw, Bx, By, Bz) + (size_t)kSpreadStage * (4 * real_bytes + 20);

@@ -278,8 +278,11 @@ struct SpreadK {
     real* halo = reinterpret_cast<real*>(smem_raw);
     unsigned char* hb = smem_raw;                  // byte view: node offsets are LDS addresses
     real* wyzs = halo + totp + 64;                 // kSpreadStage x NW: wy, wz, 0
-    real* wxs = wyzs + kSpreadStage * NW;          // kSpreadStage x 16: q wx rotated per wave
-    const size_t rec_off = ((((size_t)totp + 64 + (size_t)kSpreadStage * (NW + 16)) * sizeof(real)) + 31) & ~(size_t)31;
+    // kSpreadStage x 16: q wx rotated per wave, on a 32-byte boundary so that a wave reads
+    // its four in one vector load
+    const size_t wx_off = ((((size_t)totp + 64 + (size_t)kSpreadStage * NW) * sizeof(real)) + 31) & ~(size_t)31;
+    real* wxs = reinterpret_cast<real*>(smem_raw + wx_off);
+    const size_t rec_off = wx_off + (size_t)kSpreadStage * 16 * sizeof(real);
     vec4<real>* sup = reinterpret_cast<vec4<real>*>(smem_raw + rec_off);  // kSpreadStage: u, q
     int4* meta = reinterpret_cast<int4*>(sup + kSpreadStage);  // per wave: byte offset of its first plane
     int* slx = reinterpret_cast<int*>(meta + kSpreadStage);      // x node of the particle in the block
@@ -348,9 +351,11 @@ struct SpreadK {
         int mk = metaw[0];
         real wx4[4], wy[NPASS], wz[NPASS];
         {
-            const real* wq = wxs + wave * 4;
-#pragma unroll
-            for (int pl = 0; pl < 4; ++pl) wx4[pl] = wq[pl];
+            const vec4<real> w4 = *reinterpret_cast<const vec4<real>*>(wxs + wave * 4);
+            wx4[0] = w4.x;
+            wx4[1] = w4.y;
+            wx4[2] = w4.z;
+            wx4[3] = w4.w;
 #pragma unroll
             for (int ps = 0; ps < NPASS; ++ps) {
                 wy[ps] = wyzs[oy2[ps]];
@@ -376,9 +381,11 @@ struct SpreadK {
             {
                 const int in = min(i + 1, cnt - 1);
                 mk = metaw[4 * in];
-                const real* wq = wxs + in * 16 + wave * 4;
-#pragma unroll
-                for (int pl = 0; pl < 4; ++pl) wx4[pl] = wq[pl];
+                const vec4<real> w4 = *reinterpret_cast<const vec4<real>*>(wxs + in * 16 + wave * 4);
+                wx4[0] = w4.x;
+                wx4[1] = w4.y;
+                wx4[2] = w4.z;
+                wx4[3] = w4.w;
                 const real* wp = wyzs + in * NW;
 #pragma unroll
                 for (int ps = 0; ps < NPASS; ++ps) {
