@@ -218,28 +218,46 @@ def cpu_baseline(tol):
                        f"(near {tm['short']:.1f}, mid {tm['mid']:.1f}, long {tm['long']:.1f}){note}")
 
 
-def run_form(sog, torch, xt, qt, box, N, tol, precision, steps, warmup, params=None, deterministic=False):
-    s = sog.Solver(box, N, tol, precision=precision, on_device=True, check_inputs=False, timing=True, params=params,
-                   deterministic=deterministic)
+def run_form(sog, torch, xt, qt, box, N, tol, precision, steps, warmup, params=None, deterministic=False,
+             autotune=False):
+    """Times `steps` calls of a plan as the library runs them by default (the call's
+    kernels replayed as one HIP graph): that is the step time.  A second plan with the same
+    parameters and kernel timing on (HIP events around every kernel, launched one by one)
+    then runs as many calls for the per-kernel durations of the roofline."""
+    s = sog.Solver(box, N, tol, precision=precision, on_device=True, check_inputs=False, params=params,
+                   deterministic=deterministic, autotune=autotune)
+    tuning = s.tuning()
+    info, sizes = s.info(), s.sizes()
     # one checked call first: inputs valid, neutral, z in range
-    chk = sog.Solver(box, N, tol, precision=precision, on_device=True, check_inputs=True, timing=False,
-                     params=params)
+    chk = sog.Solver(box, N, tol, precision=precision, on_device=True, check_inputs=True, params=params)
     chk(xt, qt)
     chk.close()
     for _ in range(warmup):
         s(xt, qt)
-    torch.cuda.synchronize()
-    s.reset_kernel_times()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         U, phi, F = s(xt, qt)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
-    kt = s.kernel_times()
-    info, sizes = s.info(), s.sizes()
     s.close()
-    return dict(dt=dt, U=U, phi=phi, F=F, kt=kt, info=info, sizes=sizes)
+    # the same parameters, kernel by kernel with events
+    keep = ("b", "r0", "omega", "rc", "M", "m", "set_m", "mid_I", "mid_Izs", "mid_Pw", "mid_S", "mid_window",
+            "mid_beta", "mid_nu", "long_form", "long_P", "long_nk", "long_I", "long_Pw", "long_S", "long_Q")
+    st = sog.Solver(box, N, tol, precision=precision, on_device=True, check_inputs=False, timing=True,
+                    params={k: info[k] for k in keep}, deterministic=deterministic)
+    for _ in range(warmup):
+        st(xt, qt)
+    torch.cuda.synchronize()
+    st.reset_kernel_times()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st(xt, qt)
+    torch.cuda.synchronize()
+    dt_eager = (time.perf_counter() - t0) / steps
+    kt = st.kernel_times()
+    st.close()
+    return dict(dt=dt, dt_eager=dt_eager, U=U, phi=phi, F=F, kt=kt, info=info, sizes=sizes, tuning=tuning)
 
 
 def secondary(sog, torch, name, tol, steps):
@@ -352,6 +370,7 @@ def main():
     ap.add_argument("--no-kb", action="store_true", help="skip the KB-window run of the headline workload")
     ap.add_argument("--no-deterministic", action="store_true",
                     help="skip the deterministic-mode run of the headline workload")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the autotuned runs of the headline workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run three 256 MiB device-to-device copies (the known-size copy that scales the "
                          "HBM counters of a profiling run)")
@@ -430,6 +449,19 @@ def main():
               "kernels_ms_per_step": {k: round(v[0] / max(5, args.steps // 2), 4) for k, v in
                                       sorted(rk["kt"].items(), key=lambda kv: -kv[1][0]) if k in ("mid_spread", "mid_gather")}}
         log(f"[bench] {args.workload} fp32 KB window {rk['dt'] * 1e3:.3f} ms/step")
+    # the same workload with an autotuned plan (the planner's three cheapest r_c timed on a
+    # uniform sample, the fastest kept)
+    tuned = None
+    if not args.no_autotune:
+        for prec in ("fp32", "fp64"):
+            if prec == "fp64" and args.no_fp64:
+                continue
+            rt = run_form(sog, torch, xt, qt, box, N, args.tol, prec, max(5, args.steps // 2), 2, autotune=True)
+            tuned = tuned or {}
+            tuned[prec] = {"value": N / rt["dt"], "unit": "particles/s", "ms_per_step": rt["dt"] * 1e3,
+                           "plan": {k: rt["info"][k] for k in ("rc", "m", "mid_I", "mid_Pw", "long_P")},
+                           "tuning_ms": [[round(rc, 4), m, round(ms, 4)] for rc, m, ms in rt["tuning"]]}
+            log(f"[bench] {args.workload} {prec} autotuned {rt['dt'] * 1e3:.3f} ms/step (r_c {rt['info']['rc']:.3f})")
     # the same workload in the deterministic mode (canonical bin orders, coloured gridding)
     det = None
     if not args.no_deterministic:
@@ -469,6 +501,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": r32["dt"] * 1e3,
+        "ms_per_step_eager_timed": r32["dt_eager"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -486,6 +519,7 @@ def main():
         "roofline_kernels": others,
         "kb_window": kb,
         "deterministic": det,
+        "autotuned": tuned,
         "strongly_confined": confined,
         "batched": batched,
         "cpu_baseline": cpu,

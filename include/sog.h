@@ -146,6 +146,18 @@ typedef struct {
                                 /*    grid in a fixed order of tile colours (no atomics)      */
                                 /*    instead of with atomics; 0: the faster atomic form,     */
                                 /*    whose sums may differ in the last bits between calls   */
+    int32_t eager;              /* 1: every call launches its kernels one by one; 0: the     */
+                                /*    first call captures them into a HIP graph that later    */
+                                /*    calls replay (sog_energy_potential_force; inputs and    */
+                                /*    outputs pass through plan buffers).  timing and         */
+                                /*    static_workspace plans are always eager.                */
+    int32_t autotune;           /* 1: measure instead of model: the planner's cheapest few    */
+                                /*    discretisations by its cost model (the cheapest of each */
+                                /*    of three r_c) are each built and timed on the device on */
+                                /*    uniformly random neutral charges of the plan's size and */
+                                /*    box, and the fastest is kept (sog_plan_tuning reports    */
+                                /*    them); plan creation then costs a few solves.  Not with */
+                                /*    static_workspace.                                       */
 } sog_options;
 
 /* Fill *opt with the defaults: FP64, device 0, default stream, host pointers, checks on,
@@ -204,6 +216,12 @@ sog_status sog_potential_parts(sog_plan_t plan, const double* x, const double* q
  * use for this box, n, tol and options.  Works on a machine without a GPU. */
 sog_status sog_plan_resolve(const double box[3], int64_t n, double tol, const sog_options* opt,
                             sog_params* out);
+
+/* The discretisations an autotuned plan timed (options.autotune): up to max of them, in
+ * the order timed, with r_c, the range split m and the milliseconds per call on the
+ * synthetic sample; *count = 0 for a plan that was not autotuned.  The plan's own
+ * parameters (sog_plan_info) are those of the fastest. */
+sog_status sog_plan_tuning(sog_plan_t plan, int32_t max, int32_t* count, double* rc, int32_t* m, double* ms);
 
 /* The resolved parameters of a plan. */
 sog_status sog_plan_info(sog_plan_t plan, sog_params* out);

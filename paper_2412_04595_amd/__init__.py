@@ -17,6 +17,7 @@ from ._lib import (SOG_LONG_AUTO, SOG_LONG_DIRECT, SOG_LONG_FFT, SOG_PREC_FP32_B
                    sog_energy_potential_gradient, sog_kernel_times,
                    sog_kernel_times_reset,
                    sog_last_error, sog_options_default, sog_plan, sog_plan_ex, sog_plan_info, sog_plan_resolve,
+                   sog_plan_tuning,
                    sog_plan_sizes_get,
                    sog_potential_parts, sog_status_string)
 
@@ -25,11 +26,13 @@ LONG_FORM = {"auto": SOG_LONG_AUTO, "direct": SOG_LONG_DIRECT, "fft": SOG_LONG_F
 
 
 def make_options(precision="fp64", device=0, stream=None, on_device=False, check_inputs=True, timing=False,
-                 params=None, static_workspace=False, deterministic=False):
+                 params=None, static_workspace=False, deterministic=False, autotune=False, eager=False):
     """sog_options from keyword arguments; ``params`` is a dict of sog_params fields."""
     o = sog_options_default()
+    o.eager = int(bool(eager))
     o.static_workspace = int(bool(static_workspace))
     o.deterministic = int(bool(deterministic))
+    o.autotune = int(bool(autotune))
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     o.device = int(device)
     o.stream = stream
@@ -64,7 +67,8 @@ class Solver:
     the work is queued on torch's current stream."""
 
     def __init__(self, box, n, tol, precision="fp64", device=0, on_device=False, check_inputs=True,
-                 timing=False, params=None, stream=None, static_workspace=False, deterministic=False):
+                 timing=False, params=None, stream=None, static_workspace=False, deterministic=False,
+                 autotune=False, eager=False):
         self.box = tuple(float(v) for v in box)
         self.n = int(n)
         self.on_device = bool(on_device)
@@ -73,7 +77,7 @@ class Solver:
             import torch
             stream = torch.cuda.current_stream(self.device).cuda_stream
         self.options = make_options(precision, device, stream, on_device, check_inputs, timing, params,
-                                    static_workspace, deterministic)
+                                    static_workspace, deterministic, autotune, eager)
         self.plan = sog_plan_ex(self.box, self.n, float(tol), self.options)
 
     def close(self):
@@ -140,6 +144,10 @@ class Solver:
 
     def info(self):
         return sog_plan_info(self.plan).as_dict()
+
+    def tuning(self):
+        """[(rc, m, ms), ...] timed by an autotuned plan ([] otherwise)."""
+        return sog_plan_tuning(self.plan)
 
     def sizes(self):
         s = sog_plan_sizes_get(self.plan)

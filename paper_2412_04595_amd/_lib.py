@@ -37,6 +37,7 @@ EXPORTS = (
     "sog_potential_parts",
     "sog_plan_resolve",
     "sog_plan_info",
+    "sog_plan_tuning",
     "sog_plan_sizes_get",
     "sog_kernel_times",
     "sog_kernel_times_reset",
@@ -76,6 +77,7 @@ class sog_options(C.Structure):
         ("precision", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p),
         ("pointers_on_device", C.c_int32), ("check_inputs", C.c_int32), ("timing", C.c_int32),
         ("params", sog_params), ("static_workspace", C.c_int32), ("deterministic", C.c_int32),
+        ("eager", C.c_int32), ("autotune", C.c_int32),
     ]
 
 
@@ -225,6 +227,16 @@ def sog_plan_info(plan):
     p = sog_params()
     _check(lib().sog_plan_info(plan, C.byref(p)))
     return p
+
+
+def sog_plan_tuning(plan, max_count=16):
+    """[(rc, m, ms), ...] of the discretisations an autotuned plan timed ([] otherwise)."""
+    cnt = C.c_int32(0)
+    rc = (C.c_double * max_count)()
+    m = (C.c_int32 * max_count)()
+    ms = (C.c_double * max_count)()
+    _check(lib().sog_plan_tuning(plan, int(max_count), C.byref(cnt), rc, m, ms))
+    return [(rc[i], m[i], ms[i]) for i in range(min(cnt.value, max_count))]
 
 
 def sog_plan_sizes_get(plan):

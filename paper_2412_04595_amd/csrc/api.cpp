@@ -157,7 +157,7 @@ sog_status build_plan(Plan& p) {
     const int64_t n = r.n;
     Allocator A;  // tables, written once here
     Layout W;     // per-call buffers
-    if (!p.on_device) {
+    if (!p.on_device || p.graphable) {  // host staging, or the graph's fixed inputs and outputs
         W.get(ws.x, 3 * n * 8);
         W.get(ws.q, n * 8);
         W.get(ws.phi, n * 8);
@@ -446,6 +446,12 @@ void free_plan(Plan& p) {
                     ws.wpoly, p.region};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
+    if (p.gexec) (void)hipGraphExecDestroy(p.gexec);
+    if (p.graph) (void)hipGraphDestroy(p.graph);
+    if (p.cap) (void)hipStreamDestroy(p.cap);
+    p.gexec = nullptr;
+    p.graph = nullptr;
+    p.cap = nullptr;
     p.region = nullptr;
     ws = Workspace();
     for (hipEvent_t ev : p.ev_pool) (void)hipEventDestroy(ev);
@@ -490,6 +496,9 @@ hipError_t collect_timers(Plan& p) {
     return e;
 }
 
+static sog_status launch_call(Plan& p, const double* x, const double* q, double* dphi, double* dforce, double* dgrad,
+                              double* denergy, double* phi_parts, double* grad_parts);
+
 sog_status run(Plan& p, const double* x_in, const double* q_in, double* energy, double* phi, double* force,
                double* grad, double* phi_parts, double* grad_parts) {
     if (!x_in || !q_in) {
@@ -509,6 +518,97 @@ sog_status run(Plan& p, const double* x_in, const double* q_in, double* energy, 
         x = ws.x;
         q = ws.q;
     }
+    const bool graph = p.graphable && !grad && !phi_parts && !grad_parts;
+    if (graph) {
+        // the graph reads its inputs from and writes its outputs to the plan's buffers
+        if (p.on_device) {
+            e = hipMemcpyAsync(ws.x, x_in, 3 * n * 8, hipMemcpyDeviceToDevice, p.stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(ws.q, q_in, n * 8, hipMemcpyDeviceToDevice, p.stream);
+            if (e != hipSuccess) return hip_status(e, "input copy");
+        }
+        if (!p.gexec) {
+            if (!p.cap && (e = hipStreamCreateWithFlags(&p.cap, hipStreamNonBlocking)) != hipSuccess)
+                return hip_status(e, "capture stream");
+            const hipStream_t caller = p.stream;
+            p.stream = p.cap;
+            e = hipStreamBeginCapture(p.cap, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) {
+                p.stream = caller;
+                return hip_status(e, "graph capture");
+            }
+            const sog_status ls = launch_call(p, ws.x, ws.q, ws.phi, ws.force, nullptr, ws.energy, nullptr, nullptr);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(p.cap, &g);
+            p.stream = caller;
+            if (ls != SOG_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return ls;
+            }
+            if (e != hipSuccess) return hip_status(e, "graph capture");
+            p.graph = g;
+            if ((e = hipGraphInstantiate(&p.gexec, p.graph, nullptr, nullptr, 0)) != hipSuccess) {
+                p.gexec = nullptr;
+                return hip_status(e, "graph instantiation");
+            }
+        }
+        if ((e = hipGraphLaunch(p.gexec, p.stream)) != hipSuccess) return hip_status(e, "graph launch");
+        if (p.on_device) {
+            if (phi && e == hipSuccess) e = hipMemcpyAsync(phi, ws.phi, n * 8, hipMemcpyDeviceToDevice, p.stream);
+            if (force && e == hipSuccess) e = hipMemcpyAsync(force, ws.force, 3 * n * 8, hipMemcpyDeviceToDevice, p.stream);
+            if (energy && e == hipSuccess) e = hipMemcpyAsync(energy, ws.energy, 8, hipMemcpyDeviceToDevice, p.stream);
+            if (e != hipSuccess) return hip_status(e, "output copy");
+        }
+    } else {
+        double* dphi = p.on_device ? phi : (phi ? ws.phi : nullptr);
+        double* dforce = p.on_device ? force : (force ? ws.force : nullptr);
+        // host mode stages the gradient in the force buffer (the entry points ask for one of them)
+        double* dgrad = p.on_device ? grad : (grad ? ws.force : nullptr);
+        double* denergy = p.on_device ? energy : (energy ? ws.energy : nullptr);
+        if (sog_status ls = launch_call(p, x, q, dphi, dforce, dgrad, denergy, phi_parts, grad_parts)) return ls;
+    }
+    if (!p.on_device && !phi_parts && !grad_parts) {
+        if (phi && e == hipSuccess) e = hipMemcpyAsync(phi, ws.phi, n * 8, hipMemcpyDeviceToHost, p.stream);
+        if (force && e == hipSuccess) e = hipMemcpyAsync(force, ws.force, 3 * n * 8, hipMemcpyDeviceToHost, p.stream);
+        if (grad && e == hipSuccess) e = hipMemcpyAsync(grad, ws.force, 3 * n * 8, hipMemcpyDeviceToHost, p.stream);
+        if (energy && e == hipSuccess) e = hipMemcpyAsync(energy, ws.energy, 8, hipMemcpyDeviceToHost, p.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+        if (e != hipSuccess) return hip_status(e, "output copy");
+    }
+    if ((e = collect_timers(p)) != hipSuccess) return hip_status(e, "timing");
+    if (p.check) {
+        double qslots[2 * kQsumSlots], qs[2] = {0.0, 0.0};
+        int st = 0;
+        e = hipMemcpyAsync(qslots, ws.qsum, sizeof(qslots), hipMemcpyDeviceToHost, p.stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&st, ws.status, 4, hipMemcpyDeviceToHost, p.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+        if (e != hipSuccess) return hip_status(e, "status copy");
+        for (int k = 0; k < kQsumSlots; ++k) {
+            qs[0] += qslots[2 * k];
+            qs[1] += qslots[2 * k + 1];
+        }
+        if (st & 1) {
+            set_error("non-finite position or charge");
+            return SOG_ERR_INVALID_ARG;
+        }
+        if (st & 2) {
+            set_error("some z is outside [0, Lz]");
+            return SOG_ERR_OUT_OF_BOX;
+        }
+        if (std::fabs(qs[0]) > 1e-10 * qs[1]) {
+            set_error("charges are not neutral (|sum q| > 1e-10 sum |q|)");
+            return SOG_ERR_NOT_NEUTRAL;
+        }
+    }
+    return SOG_OK;
+}
+
+// The kernels of one call on the plan's stream (and its side stream), from the sorts to
+// the combination: x, q on the device; outputs (device) as requested, or the parts.
+static sog_status launch_call(Plan& p, const double* x, const double* q, double* dphi, double* dforce, double* dgrad,
+                              double* denergy, double* phi_parts, double* grad_parts) {
+    Workspace& ws = p.ws;
+    const int64_t n = p.r.n;
+    hipError_t e = hipSuccess;
     // Two streams: the near field and the long range on the plan's side stream, the mid
     // range on the caller's stream (they share no buffers: separate sort keys, scan space
     // and part records).  The ALU-bound near-field kernel waits for the gridding so that it
@@ -564,45 +664,7 @@ sog_status run(Plan& p, const double* x_in, const double* q_in, double* energy, 
             if (e != hipSuccess) return hip_status(e, "parts");
         }
     } else {
-        double* dphi = p.on_device ? phi : (phi ? ws.phi : nullptr);
-        double* dforce = p.on_device ? force : (force ? ws.force : nullptr);
-        // host mode stages the gradient in the force buffer (the entry points ask for one of them)
-        double* dgrad = p.on_device ? grad : (grad ? ws.force : nullptr);
-        double* denergy = p.on_device ? energy : (energy ? ws.energy : nullptr);
         if ((e = launch_combine(p, q, dphi, dforce, dgrad, denergy)) != hipSuccess) return hip_status(e, "combine");
-        if (!p.on_device) {
-            if (phi && e == hipSuccess) e = hipMemcpyAsync(phi, ws.phi, n * 8, hipMemcpyDeviceToHost, p.stream);
-            if (force && e == hipSuccess) e = hipMemcpyAsync(force, ws.force, 3 * n * 8, hipMemcpyDeviceToHost, p.stream);
-            if (grad && e == hipSuccess) e = hipMemcpyAsync(grad, ws.force, 3 * n * 8, hipMemcpyDeviceToHost, p.stream);
-            if (energy && e == hipSuccess) e = hipMemcpyAsync(energy, ws.energy, 8, hipMemcpyDeviceToHost, p.stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
-            if (e != hipSuccess) return hip_status(e, "output copy");
-        }
-    }
-    if ((e = collect_timers(p)) != hipSuccess) return hip_status(e, "timing");
-    if (p.check) {
-        double qslots[2 * kQsumSlots], qs[2] = {0.0, 0.0};
-        int st = 0;
-        e = hipMemcpyAsync(qslots, ws.qsum, sizeof(qslots), hipMemcpyDeviceToHost, p.stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(&st, ws.status, 4, hipMemcpyDeviceToHost, p.stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
-        if (e != hipSuccess) return hip_status(e, "status copy");
-        for (int k = 0; k < kQsumSlots; ++k) {
-            qs[0] += qslots[2 * k];
-            qs[1] += qslots[2 * k + 1];
-        }
-        if (st & 1) {
-            set_error("non-finite position or charge");
-            return SOG_ERR_INVALID_ARG;
-        }
-        if (st & 2) {
-            set_error("some z is outside [0, Lz]");
-            return SOG_ERR_OUT_OF_BOX;
-        }
-        if (std::fabs(qs[0]) > 1e-10 * qs[1]) {
-            set_error("charges are not neutral (|sum q| > 1e-10 sum |q|)");
-            return SOG_ERR_NOT_NEUTRAL;
-        }
     }
     return SOG_OK;
 }
@@ -877,6 +939,9 @@ sog_status sog_plan(const double box[3], int64_t n, double tol, sog_plan_t* out)
     return sog_plan_ex(box, n, tol, nullptr, out);
 }
 
+static sog_status create_plan(const double box[3], int64_t n, double tol, const sog_options& opt, Plan** out);
+static sog_status autotune_plan(const double box[3], int64_t n, double tol, const sog_options& opt, Plan** out);
+
 sog_status sog_plan_ex(const double box[3], int64_t n, double tol, const sog_options* opt_in, sog_plan_t* out) {
     if (!out || !box) {
         set_error("box and out must not be NULL");
@@ -886,6 +951,23 @@ sog_status sog_plan_ex(const double box[3], int64_t n, double tol, const sog_opt
     sog_options opt;
     sog_options_default(&opt);
     if (opt_in) opt = *opt_in;
+    if (opt.autotune != 0 && opt.autotune != 1) {
+        set_error("autotune must be 0 or 1");
+        return SOG_ERR_INVALID_ARG;
+    }
+    if (opt.autotune && opt.static_workspace) {
+        set_error("autotune is not available with static_workspace");
+        return SOG_ERR_INVALID_ARG;
+    }
+    Plan* p = nullptr;
+    sog_status s = opt.autotune ? autotune_plan(box, n, tol, opt, &p) : create_plan(box, n, tol, opt, &p);
+    if (s == SOG_OK) *out = reinterpret_cast<sog_plan_t>(p);
+    return s;
+}
+
+// One plan from resolved options (the body of sog_plan_ex).
+static sog_status create_plan(const double box[3], int64_t n, double tol, const sog_options& opt, Plan** out) {
+    *out = nullptr;
     Plan* p = new (std::nothrow) Plan();
     if (!p) {
         set_error("host allocation failed");
@@ -904,6 +986,7 @@ sog_status sog_plan_ex(const double box[3], int64_t n, double tol, const sog_opt
     p->check = opt.check_inputs != 0;
     p->timing = opt.timing != 0;
     p->static_region = opt.static_workspace != 0;
+    p->graphable = !opt.eager && !opt.timing && !opt.static_workspace;
     if (p->static_region && p->timing) {
         set_error("timing is not available with static_workspace (it creates events during calls)");
         delete p;
@@ -958,7 +1041,154 @@ sog_status sog_plan_ex(const double box[3], int64_t n, double tol, const sog_opt
         delete p;
         return s;
     }
-    *out = reinterpret_cast<sog_plan_t>(p);
+    *out = p;
+    return SOG_OK;
+}
+
+// Autotuning: the planner's cheapest discretisations by its cost model, one per distinct
+// r_c up to kTuneCandidates, each built as a plan (device pointers, no checks, no
+// timing) and timed on the plan's stream with HIP events (one warm-up call, then
+// kTuneCalls) on uniformly random positions in the box with charges +1, -1 alternating
+// (the last one 0 for odd n: neutral); the fastest (r_c, m) is then planned with the
+// caller's options.  Inputs other than uniform ones may rank the candidates differently.
+constexpr int kTuneCandidates = 3;
+constexpr int kTuneCalls = 3;
+
+static sog_status autotune_plan(const double box[3], int64_t n, double tol, const sog_options& opt, Plan** out) {
+    *out = nullptr;
+    std::string err;
+    Resolved r0;
+    std::vector<PlanCandidate> cands;
+    sog_status s = resolve(box, n, tol, opt, r0, err, &cands);
+    if (s != SOG_OK) {
+        set_error(err);
+        return s;
+    }
+    std::stable_sort(cands.begin(), cands.end(),
+                     [](const PlanCandidate& a, const PlanCandidate& b) { return a.cost < b.cost; });
+    // the cheapest candidate of each r_c (the split follows r_c closely), cheapest first
+    std::vector<PlanCandidate> pick;
+    for (const PlanCandidate& c : cands) {
+        bool seen = false;
+        for (const PlanCandidate& q : pick) seen = seen || q.rc == c.rc;
+        if (!seen) pick.push_back(c);
+        if ((int)pick.size() == kTuneCandidates) break;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        set_error("no HIP device available");
+        return SOG_ERR_DEVICE;
+    }
+    if (opt.device < 0 || opt.device >= ndev) {
+        set_error("device ordinal out of range");
+        return SOG_ERR_INVALID_ARG;
+    }
+    DeviceGuard dg(opt.device);
+    // the synthetic sample, on the device
+    std::vector<double> hx((size_t)n * 3), hq((size_t)n);
+    {
+        uint64_t st = 0x9e3779b97f4a7c15ull;
+        auto next = [&]() {  // splitmix64
+            st += 0x9e3779b97f4a7c15ull;
+            uint64_t z = st;
+            z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+            z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+            return (double)((z ^ (z >> 31)) >> 11) * (1.0 / 9007199254740992.0);
+        };
+        for (int64_t i = 0; i < n; ++i) {
+            for (int d = 0; d < 3; ++d) hx[3 * i + d] = next() * box[d];
+            hq[i] = (i % 2 == 0) ? 1.0 : -1.0;
+        }
+        if (n % 2) hq[n - 1] = 0.0;
+    }
+    double *dx = nullptr, *dq = nullptr, *dphi = nullptr, *dF = nullptr, *dU = nullptr;
+    hipError_t he = hipMalloc(&dx, hx.size() * 8);
+    if (he == hipSuccess) he = hipMalloc(&dq, hq.size() * 8);
+    if (he == hipSuccess) he = hipMalloc(&dphi, (size_t)n * 8);
+    if (he == hipSuccess) he = hipMalloc(&dF, (size_t)n * 24);
+    if (he == hipSuccess) he = hipMalloc(&dU, 8);
+    if (he == hipSuccess) he = hipMemcpy(dx, hx.data(), hx.size() * 8, hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemcpy(dq, hq.data(), hq.size() * 8, hipMemcpyHostToDevice);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (he == hipSuccess) he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    auto release = [&]() {
+        (void)hipFree(dx);
+        (void)hipFree(dq);
+        (void)hipFree(dphi);
+        (void)hipFree(dF);
+        (void)hipFree(dU);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (he != hipSuccess) {
+        release();
+        return hip_status(he, "autotune sample");
+    }
+    std::vector<TunedCandidate> tuned;
+    for (const PlanCandidate& c : pick) {
+        sog_options o = opt;
+        o.autotune = 0;
+        o.timing = 0;
+        o.check_inputs = 0;
+        o.pointers_on_device = 1;
+        o.params.rc = c.rc;
+        o.params.set_m = 1;
+        o.params.m = c.m;
+        o.params.eta = 0;
+        Plan* p = nullptr;
+        if (create_plan(box, n, tol, o, &p) != SOG_OK) continue;  // not buildable: not a candidate
+        sog_status rs = SOG_OK;
+        float ms = 0;
+        for (int k = 0; k <= kTuneCalls && rs == SOG_OK; ++k) {
+            if (k == 1) he = hipEventRecord(e0, p->stream);
+            rs = run(*p, dx, dq, dU, dphi, dF, nullptr, nullptr, nullptr);
+        }
+        if (rs == SOG_OK && he == hipSuccess) he = hipEventRecord(e1, p->stream);
+        if (rs == SOG_OK && he == hipSuccess) he = hipEventSynchronize(e1);
+        if (rs == SOG_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        free_plan(*p);
+        delete p;
+        if (rs != SOG_OK || he != hipSuccess) {
+            release();
+            return rs != SOG_OK ? rs : hip_status(he, "autotune timing");
+        }
+        tuned.push_back(TunedCandidate{c.rc, c.m, (double)ms / kTuneCalls});
+    }
+    release();
+    if (tuned.empty()) {
+        set_error("autotune: no candidate plan could be built");
+        return SOG_ERR_DEVICE;
+    }
+    size_t best = 0;
+    for (size_t i = 1; i < tuned.size(); ++i)
+        if (tuned[i].ms < tuned[best].ms) best = i;
+    sog_options o = opt;
+    o.autotune = 0;
+    o.params.rc = tuned[best].rc;
+    o.params.set_m = 1;
+    o.params.m = tuned[best].m;
+    o.params.eta = 0;
+    Plan* p = nullptr;
+    s = create_plan(box, n, tol, o, &p);
+    if (s != SOG_OK) return s;
+    p->tuning = tuned;
+    *out = p;
+    return SOG_OK;
+}
+
+sog_status sog_plan_tuning(sog_plan_t plan, int32_t max, int32_t* count, double* rc, int32_t* m, double* ms) {
+    if (!plan || !count || max < 0) {
+        set_error("plan and count must not be NULL, max >= 0");
+        return SOG_ERR_INVALID_ARG;
+    }
+    const Plan& p = *reinterpret_cast<const Plan*>(plan);
+    *count = (int32_t)p.tuning.size();
+    for (int32_t i = 0; i < std::min<int32_t>(max, *count); ++i) {
+        if (rc) rc[i] = p.tuning[i].rc;
+        if (m) m[i] = p.tuning[i].m;
+        if (ms) ms[i] = p.tuning[i].ms;
+    }
     return SOG_OK;
 }
 
@@ -1019,9 +1249,14 @@ sog_status sog_energy_potential_force_static(sog_plan_t plan, const double* x, c
         DeviceGuard dg(p.device);
         if (sog_status st = static_scratch(p.device, &base)) return st;
     }
+    // launched kernel by kernel: a graph would bake in the static scratch's addresses
+    // (and instantiating one allocates)
+    const bool graphable = p.graphable;
+    p.graphable = false;
     bind_region(p, base);
     const sog_status st = run(p, x, q, energy, phi, force, nullptr, nullptr, nullptr);
     bind_region(p, p.region);
+    p.graphable = graphable;
     return st;
 }
 

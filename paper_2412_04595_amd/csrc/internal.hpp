@@ -306,9 +306,16 @@ struct Workspace {
     size_t bytes = 0;  // device bytes the plan holds: tables and its per-call region
 };
 
+struct TunedCandidate {
+    double rc;
+    int m;
+    double ms;
+};
+
 struct Plan {
     Resolved r;
     Workspace ws;
+    std::vector<TunedCandidate> tuning;  // autotuned plans: the discretisations timed
     int device = 0;
     int num_cus = 256;              // compute units of the device
     hipStream_t stream = nullptr;   // the stream kernels are launched on (the caller's, or side)
@@ -317,6 +324,12 @@ struct Plan {
     bool on_device = false;
     bool check = true;
     bool timing = false;
+    // the call's kernels replayed as a HIP graph, captured at the first call on a
+    // plan-owned stream (inputs and outputs staged in the plan's buffers)
+    bool graphable = false;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
     FFTFactors fx, fy, fz;          // mid-range FFT lengths I_x, I_y, I_z*/2
     FFTFactors f2x, f2y;            // long-range FFT form: I2x and I2y/2 (real-to-complex along y)
     // per-call buffers: one region of region_bytes (offsets in region_slots) that the plan
@@ -333,8 +346,15 @@ struct Plan {
 };
 
 // planner.cpp
+// A feasible discretisation the planner considered: its modelled cost, r_c and split m.
+struct PlanCandidate {
+    double cost;
+    double rc;
+    int m;
+};
+// cands (optional): every feasible (r_c, m) the planner's search met, with its cost
 sog_status resolve(const double box[3], int64_t n, double tol, const sog_options& opt, Resolved& r,
-                   std::string& err);
+                   std::string& err, std::vector<PlanCandidate>* cands = nullptr);
 bool factor_fft(int n, FFTFactors& f);
 int next_smooth(int n, bool even);
 void near_chebyshev(Resolved& r);

@@ -935,7 +935,7 @@ double neighbour_volume(double rc, double Lz) {
 }  // namespace
 
 sog_status resolve(const double box[3], int64_t n, double tol, const sog_options& opt, Resolved& r,
-                   std::string& err) {
+                   std::string& err, std::vector<PlanCandidate>* cands) {
     const sog_params& ov = opt.params;
     for (int d = 0; d < 3; ++d) {
         if (!(box[d] > 0) || !std::isfinite(box[d])) { err = "box lengths must be finite and > 0"; return SOG_ERR_INVALID_ARG; }
@@ -1050,6 +1050,7 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
                 }
                 cost += lc.cost;
             }
+            if (cands) cands->push_back(PlanCandidate{cost, rc, m});
             if (cost < best_cost) {
                 best_cost = cost;
                 best = c;
