@@ -294,8 +294,13 @@ constexpr int kNearWaves = 4;   // independent waves per block
 // occupancy the FFT passes and the gathering launched on the other stream find room
 // (LDS and waves) on every compute unit beside it
 constexpr int kNearBlocksPerCU = 4;
-constexpr int kNearCap = 32;    // hit-list entries per lane (a ring; power of two)
-constexpr int kNearCodeShift = 26;  // hit entry: source index | (neighbour range << 26)
+constexpr int kNearCap = 32;    // float32 hit-list entries per lane (a ring; power of two)
+constexpr int kNearCodeShift = 26;  // candidate code: source index | (neighbour range << 26)
+// the neighbour columns (dx + 1) + 3 (dy + 1) in the order of the walk, 4 bits each: the
+// unit's own column first, then opposite corners and opposite edges in turn, so that the
+// hits of consecutive blocks fall on targets on opposite sides of the column (the
+// float32 lists then fill more evenly); ranges 0 and 1 are the own column's
+constexpr unsigned long long kNearColumnOrder = 0x537162804ull;
 
 // 1/sqrt: the hardware reciprocal square root in float32 (r^2 is far from denormal here)
 __device__ __forceinline__ float near_rsqrt(float v) { return __builtin_amdgcn_rsqf(v); }
@@ -328,8 +333,8 @@ __device__ __forceinline__ void near_pair(const NearArgs<real>& a, real rx, real
 
 // The pair kernel with the candidate test on the matrix cores (float32 test; evaluation in
 // float32 or, for float64 plans, float64: see NearMfmaK).  A pass takes 32
-// targets; lanes l and l + 32 share target l % 32 and split its candidates between their
-// hit lists.  The unit's 18 candidate ranges are walked as one sequence in blocks of 32,
+// targets; lanes l and l + 32 share target l % 32 and split its candidates between them.
+// The unit's 18 candidate ranges are walked as one sequence in blocks of 32,
 // and one block against the pass's targets is a 32 x 32 matrix
 //     D[i][j] = |c_i|^2 - 2 c_i . t_j  =  r_ij^2 - |t_j|^2,
 // the product of the rows (c_x, c_y, c_z, |c|^2) and the columns (-2 t_x, -2 t_y,
@@ -339,17 +344,19 @@ __device__ __forceinline__ void near_pair(const NearArgs<real>& a, real rx, real
 // when D < r_c^2 - |t_j|^2.  Coordinates are offsets from the centre of the unit's
 // column cell in x, y and from the middle of its run in z, so |c|^2 stays below about
 // 25 cells^2 and the rounding of D is far below the cut-off's width.
-// The pairs are evaluated from the hit lists with r computed directly as t - c; the
-// target and a candidate of its own column and frame get their coordinates by adding
-// the same shift to the same stored values, so the particle paired with itself has
-// r^2 == 0 exactly and is dropped there.
+// The hits are evaluated from hit lists (float32: a ring per lane for the lane's target;
+// float64: a stack per wave, compacted across the lanes, so that every lane evaluates a
+// pair in every round whatever the spread of the hits over the targets).  r is computed
+// directly as t - c: the target and a candidate of its own column and frame get their
+// coordinates by adding the same shift to the same stored values, so the particle paired
+// with itself has r^2 == 0 exactly and is dropped there.
 typedef float near_v16f __attribute__((ext_vector_type(16)));
 
 // lane k's value of a float (the builtin moves 32-bit integers: pass the bits, not the value)
 __device__ __forceinline__ float readlane_f(float v, int k) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
 }
-constexpr int kNearMfmaRows = 16;  // hit-list slots a block appends per lane
+constexpr int kNearMfmaRows = 16;  // matrix rows per lane: candidate-target pairs a lane tests per block
 
 // F(r) and F'(r)/r from their monomial form in x = 2 r^2/r_c^2 - 1 by Horner (2 FMAs per
 // degree against the Chebyshev recurrence's 3; in float32 no less accurate on [-1, 1],
@@ -361,7 +368,7 @@ __device__ __forceinline__ void near_pair_nz(const NearArgs<float>& a, float rx,
     const float r2 = rx * rx + ry * ry + rz * rz;
     const bool nz = r2 > 0.f;
     const float q = nz ? qj : 0.f, r2s = nz ? r2 : 1.f;
-    const float xs = 2.f * r2s * a.inv_rc2 - 1.f;
+    const float xs = fmaf(r2s, 2.f * a.inv_rc2, -1.f);  // 2 r^2/r_c^2 - 1 (the factor 2 is exact)
     float F = a.mF[DEG], G = a.mG[DEG];
 #pragma unroll
     for (int k = DEG - 1; k >= 0; --k) {
@@ -402,18 +409,36 @@ struct NearMfmaK {
     static constexpr int kThreads = 64 * kNearWaves;
     static constexpr bool kF64 = sizeof(E) == 8;
     __device__ static void run(GridPos gpos, const NearArgs<E>& a) {
-    __shared__ uint32_t hits_all[kNearWaves][kNearCap * 64];
+    // The hits go to one of two sinks.  float32: a ring per lane (the lane's target, its
+    // sums in registers), drained kEval entries per lane at a time while every lane has that
+    // many.  float64: a stack per wave (codes, targets), evaluated kRound entries at a time,
+    // each pair adding its terms to its target's sums in LDS (ds_add_f64; float32 adds to
+    // LDS are far slower on this chip, so the float32 kernel keeps its sums in registers).
+    constexpr int kEval = kF64 ? 2 : 4;           // entries evaluated per lane per round
+    constexpr int kRound = 64 * kEval;            // stack: entries evaluated per round
+    constexpr int kStack = kRound - 1 + 1024;     // stack: entries left below a round + one block's hits
+    __shared__ uint32_t hits_all[kNearWaves][kF64 ? 1 : kNearCap * 64];
+    __shared__ uint32_t stack_all[kNearWaves][kF64 ? kStack : 1];
+    __shared__ uint8_t stackt_all[kNearWaves][kF64 ? kStack : 1];
+    // stack: targets' positions in the unit frame and sums (phi, grad), one array per
+    // component, so the lanes of an access spread over the banks by target
+    __shared__ E tpos_all[kNearWaves][3][kF64 ? 32 : 1];
+    __shared__ E tsum_all[kNearWaves][4][kF64 ? 32 : 1];
     __shared__ vec4<float> shift_all[kNearWaves][18];
     __shared__ vec4<E> shiftE_all[kNearWaves][kF64 ? 18 : 1];  // float64 shifts (E = double)
     __shared__ alignas(16) uint32_t codes_all[kNearWaves][32];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, half = lane >> 5, jl = lane & 31;
     uint32_t* hits = hits_all[wv];
-    vec4<float>* shift = shift_all[wv];
-    vec4<E>* shiftE = kF64 ? shiftE_all[wv] : reinterpret_cast<vec4<E>*>(shift_all[wv]);
-    uint32_t* codes = codes_all[wv];
     char* hits_bytes = reinterpret_cast<char*>(&hits_all[0][0]);
     static_assert(kNearCap * 256 == 8192, "list slot bits 8..12 between the lane and wave bits");
     const uint32_t lb = (uint32_t)wv * (kNearCap * 256) | (uint32_t)lane * 4;
+    uint32_t* stack = stack_all[wv];
+    uint8_t* stackt = stackt_all[wv];
+    auto tpos = tpos_all[wv];
+    auto tsum = tsum_all[wv];
+    vec4<float>* shift = shift_all[wv];
+    vec4<E>* shiftE = kF64 ? shiftE_all[wv] : reinterpret_cast<vec4<E>*>(shift_all[wv]);
+    uint32_t* codes = codes_all[wv];
     const int per = (a.max_units + 7) >> 3;
     const int ibeg = (gpos.bid & 7) * per, iend = min(a.max_units, ibeg + per);
     int* grab = a.grab + (gpos.bid & 7) * kGrabStride;
@@ -443,7 +468,7 @@ struct NearMfmaK {
     int rs = 0, len = 0;
     vec4<float> sk = {0.f, 0.f, 0.f, 0.f};
     if (lane < 18) {
-        const int c9 = lane >> 1, piece = lane & 1;
+        const int c9 = (int)((kNearColumnOrder >> (4 * (lane >> 1))) & 15), piece = lane & 1;
         const int dx = c9 % 3 - 1, dy = c9 / 3 - 1;
         const int ncol = imod(cx + dx, a.nc[0]) * a.nc[1] + imod(cy + dy, a.nc[1]);
         const int pa = piece ? bnd : za, pb = piece ? zb : min(zb, bnd);
@@ -499,8 +524,8 @@ struct NearMfmaK {
         for (int c = z0 + 1; c < z1; ++c)
             if (p >= a.cell_start[col * a.nc[2] + c]) tcz = c;
         // the target in the unit frame: the shift of its own column (dx = dy = 0, ranges
-        // 8 and 9) in its own frame
-        const int sti = 8 + ((tcz / kNearFrameCells) != (za / kNearFrameCells) ? 1 : 0);
+        // 0 and 1) in its own frame
+        const int sti = (tcz / kNearFrameCells) != (za / kNearFrameCells) ? 1 : 0;
         const vec4<float> st = shift[sti];
         const float tx = me.x + st.x, ty = me.y + st.y, tz = me.z + st.z;
         const float thr = act ? (float)a.rc2 + a.test_margin - (tx * tx + ty * ty + tz * tz) : -INFINITY;
@@ -515,38 +540,35 @@ struct NearMfmaK {
         }
         const float b1 = half ? -2.f * ty : -2.f * tx;
         const float b2 = half ? 1.f : -2.f * tz;
+        // float32 sink: this lane's ring [hd, tp) and sums
         E phi = 0, gx = 0, gy = 0, gz = 0;
         int tp = 0, hd = 0;
         constexpr int kMask = kNearCap - 1;
-        constexpr int kEval = kF64 ? 2 : 4;  // list entries evaluated per lane per round
+        // up to kEval entries off this lane's ring
         auto chunk = [&]() {
-            const int cnt = (tp - hd) & kMask;
-            vec4<E> o[kEval], sh[kEval];
-            int src[kEval];
-            const uint32_t dummy = (uint32_t)tb | (8u << kNearCodeShift);
+            if constexpr (!kF64) {
+                const int cnt = (tp - hd) & kMask;
+                vec4<E> o[kEval], sh[kEval];
+                int src[kEval];
 #pragma unroll
-            for (int u = 0; u < kEval; ++u) {
-                const uint32_t e = (cnt > 0) ? hits[((hd + min(u, cnt - 1)) & kMask) * 64 + lane] : dummy;
-                src[u] = (int)(e & ((1u << kNearCodeShift) - 1));
-                o[u] = a.pos[src[u]];
-                sh[u] = shiftE[e >> kNearCodeShift];
-            }
+                for (int u = 0; u < kEval; ++u) {
+                    const uint32_t e = (cnt > 0) ? hits[((hd + min(u, cnt - 1)) & kMask) * 64 + lane] : (uint32_t)tb;
+                    src[u] = (int)(e & ((1u << kNearCodeShift) - 1));
+                    o[u] = a.pos[src[u]];
+                    sh[u] = shiftE[e >> kNearCodeShift];
+                }
 #pragma unroll
-            for (int u = 0; u < kEval; ++u)
-                if (u < cnt) {
-                    E rx = txE - (o[u].x + sh[u].x), ry = tyE - (o[u].y + sh[u].y), rz = tzE - (o[u].z + sh[u].z);
-                    if constexpr (kF64) {
-                        // the float32 test admits pairs up to the margin beyond r_c: the cut
-                        // at r_c is made here; the particle itself has r^2 = 0
-                        const E r2 = rx * rx + ry * ry + rz * rz;
-                        if (r2 < a.rc2 && r2 > (E)0) near_pair<E, DEG>(a, rx, ry, rz, o[u].w, phi, gx, gy, gz, r2);
-                    } else {
+                for (int u = 0; u < kEval; ++u)
+                    if (u < cnt) {
+                        E rx = txE - (o[u].x + sh[u].x), ry = tyE - (o[u].y + sh[u].y), rz = tzE - (o[u].z + sh[u].z);
                         if (rx * rx + ry * ry + rz * rz < a.rclose2) near_close_separation(a, p, src[u], rx, ry, rz);
                         near_pair_nz<DEG>(a, rx, ry, rz, o[u].w, phi, gx, gy, gz);
                     }
-                }
-            hd = (hd + min(cnt, kEval)) & kMask;
+                hd = (hd + min(cnt, kEval)) & kMask;
+            }
         };
+        // rounds of chunks until some active lane holds fewer than kEval entries, as long as
+        // no ring lacks room for a block's kNearMfmaRows entries
         auto drain_ready = [&]() {
             while (true) {
                 const int cnt = (tp - hd) & kMask;
@@ -554,6 +576,62 @@ struct NearMfmaK {
                 chunk();
             }
         };
+        // float64 sink: the targets' positions and zeroed sums
+        if constexpr (kF64) {
+            if (half == 0) {
+                tpos[0][jl] = txE;
+                tpos[1][jl] = tyE;
+                tpos[2][jl] = tzE;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) tsum[c][jl] = (E)0;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        // the stack's entries [s0, s0 + cnt) (cnt <= kRound, wave-uniform): entry s0 + 64 u
+        // + lane for lane and round u
+        auto evaluate = [&](int s0, int cnt) {
+            if constexpr (kF64) {
+                vec4<E> o[kEval], sh[kEval];
+                int ti[kEval];
+#pragma unroll
+                for (int u = 0; u < kEval; ++u) {
+                    const bool ok = 64 * u + lane < cnt;
+                    const uint32_t e = ok ? stack[s0 + 64 * u + lane] : (uint32_t)tb;
+                    ti[u] = ok ? (int)stackt[s0 + 64 * u + lane] : 0;
+                    o[u] = a.pos[e & ((1u << kNearCodeShift) - 1)];
+                    sh[u] = shiftE[e >> kNearCodeShift];
+                }
+                // the target of entry u + 1 is read while entry u is evaluated
+                E ttx = tpos[0][ti[0]], tty = tpos[1][ti[0]], ttz = tpos[2][ti[0]];
+#pragma unroll
+                for (int u = 0; u < kEval; ++u) {
+                    const int t = ti[u];
+                    const E cx = ttx, cy = tty, cz = ttz;
+                    if (u + 1 < kEval) {
+                        ttx = tpos[0][ti[u + 1]];
+                        tty = tpos[1][ti[u + 1]];
+                        ttz = tpos[2][ti[u + 1]];
+                    }
+                    if (64 * u + lane < cnt) {
+                        const E rx = cx - (o[u].x + sh[u].x), ry = cy - (o[u].y + sh[u].y), rz = cz - (o[u].z + sh[u].z);
+                        // the float32 test admits pairs up to the margin beyond r_c: the cut
+                        // at r_c is made here; the particle itself has r^2 = 0
+                        const E r2 = rx * rx + ry * ry + rz * rz;
+                        if (r2 < a.rc2 && r2 > (E)0) {
+                            E ph = 0, fx = 0, fy = 0, fz = 0;
+                            near_pair<E, DEG>(a, rx, ry, rz, o[u].w, ph, fx, fy, fz, r2);
+                            atomicAdd(&tsum[0][t], ph);
+                            atomicAdd(&tsum[1][t], fx);
+                            atomicAdd(&tsum[2][t], fy);
+                            atomicAdd(&tsum[3][t], fz);
+                        }
+                    }
+                }
+            }
+        };
+        int top = 0;  // float64 sink: stack height (wave-uniform)
         // this lane's candidate of a block at v0: the range it falls in, its particle and
         // shift.  Every lane starts from the range holding v0 (k0, uniform, found from
         // the previous block's) and moves on to each later range that starts at or
@@ -602,7 +680,8 @@ struct NearMfmaK {
             near_v16f acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a2, b2, acc, 0, 0, 0);
-            // while the matrix core works: the next block's record, and room in the lists
+            // while the matrix core works: the next block's record, and full rounds off the
+            // top of the stack (the block's hits go on after them)
             if (v0 + 32 < total) {
                 advance(v0 + 32);
                 vn = v0 + 32 + jl < total;
@@ -612,36 +691,74 @@ struct NearMfmaK {
                 syn = sy;
                 szn = sz;
             }
-            drain_ready();
+            if constexpr (kF64) {
+                while (top >= kRound) {
+                    top -= kRound;
+                    evaluate(top, kRound);
+                }
+            } else {
+                drain_ready();
+            }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             uint4 cd[4];
 #pragma unroll
             for (int q4 = 0; q4 < 4; ++q4) cd[q4] = *reinterpret_cast<const uint4*>(&codes[8 * q4 + 4 * half]);
-            // the tail slot as a byte offset into the lists of all waves: wave, slot and
-            // lane bits are disjoint, so stepping the slot is an add and an and-or
-            uint32_t at = lb | ((uint32_t)tp << 8);
+            if constexpr (kF64) {
+                // the hits of row r of every lane go on in lane order: a lane's slot is the
+                // height plus the hits of the lanes below it
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const uint32_t cr = r % 4 == 0 ? cd[r / 4].x : r % 4 == 1 ? cd[r / 4].y : r % 4 == 2 ? cd[r / 4].z : cd[r / 4].w;
-                *reinterpret_cast<uint32_t*>(hits_bytes + at) = cr;
-                const uint32_t nx = ((at + 256u) & ((uint32_t)kMask << 8)) | lb;
-                at = acc[r] < thr ? nx : at;
+                for (int r = 0; r < 16; ++r) {
+                    const uint32_t cr = r % 4 == 0 ? cd[r / 4].x : r % 4 == 1 ? cd[r / 4].y : r % 4 == 2 ? cd[r / 4].z : cd[r / 4].w;
+                    const bool hit = acc[r] < thr;
+                    const uint64_t m = __ballot(hit);
+                    if (hit) {
+                        const int slot = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, (uint32_t)top));
+                        stack[slot] = cr;
+                        stackt[slot] = (uint8_t)jl;
+                    }
+                    top += __popcll(m);
+                }
+            } else {
+                // every row is written at this lane's tail slot, which moves on for a hit: the
+                // tail as a byte offset into the lists of all waves (wave, slot and lane bits
+                // are disjoint, so stepping the slot is an add and an and-or)
+                uint32_t at = lb | ((uint32_t)tp << 8);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const uint32_t cr = r % 4 == 0 ? cd[r / 4].x : r % 4 == 1 ? cd[r / 4].y : r % 4 == 2 ? cd[r / 4].z : cd[r / 4].w;
+                    *reinterpret_cast<uint32_t*>(hits_bytes + at) = cr;
+                    const uint32_t nx = ((at + 256u) & ((uint32_t)kMask << 8)) | lb;
+                    at = acc[r] < thr ? nx : at;
+                }
+                tp = (int)(at >> 8) & kMask;
             }
-            tp = (int)(at >> 8) & kMask;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        while (__ballot(tp != hd)) chunk();
-        phi += __shfl_xor(phi, 32, 64);
-        gx += __shfl_xor(gx, 32, 64);
-        gy += __shfl_xor(gy, 32, 64);
-        gz += __shfl_xor(gz, 32, 64);
-        if (act && half == 0) {
-            const int i = a.orig[p];
-            a.part[i] = vec4<E>{phi, gx, gy, gz};
+        if constexpr (kF64) {
+            while (top > 0) {
+                const int c = min(top, kRound);
+                top -= c;
+                evaluate(top, c);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (act && half == 0) a.part[a.orig[p]] = vec4<E>{tsum[0][jl], tsum[1][jl], tsum[2][jl], tsum[3][jl]};
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            while (__ballot(tp != hd)) chunk();
+            phi += __shfl_xor(phi, 32, 64);
+            gx += __shfl_xor(gx, 32, 64);
+            gy += __shfl_xor(gy, 32, 64);
+            gz += __shfl_xor(gz, 32, 64);
+            if (act && half == 0) a.part[a.orig[p]] = vec4<E>{phi, gx, gy, gz};
         }
     }
     }
