@@ -568,11 +568,13 @@ struct NearMfmaK {
             }
         };
         // rounds of chunks until some active lane holds fewer than kEval entries, as long as
-        // no ring lacks room for a block's kNearMfmaRows entries
+        // no ring lacks room for half a block's rows (a block's hits go on in two halves,
+        // with a check for room between them)
+        constexpr int kRoom = kNearCap - 1 - kNearMfmaRows / 2;
         auto drain_ready = [&]() {
             while (true) {
                 const int cnt = (tp - hd) & kMask;
-                if (__ballot(act && cnt < kEval) != 0 && __ballot(cnt > kNearCap - 1 - kNearMfmaRows) == 0) break;
+                if (__ballot(act && cnt < kEval) != 0 && __ballot(cnt > kRoom) == 0) break;
                 chunk();
             }
         };
@@ -724,16 +726,27 @@ struct NearMfmaK {
             } else {
                 // every row is written at this lane's tail slot, which moves on for a hit: the
                 // tail as a byte offset into the lists of all waves (wave, slot and lane bits
-                // are disjoint, so stepping the slot is an add and an and-or)
-                uint32_t at = lb | ((uint32_t)tp << 8);
+                // are disjoint, so stepping the slot is an add and an and-or).  Rows 0-7 (the
+                // block's candidates 0-15), then rounds while some ring lacks room for 8
+                // more, then rows 8-15.
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const uint32_t cr = r % 4 == 0 ? cd[r / 4].x : r % 4 == 1 ? cd[r / 4].y : r % 4 == 2 ? cd[r / 4].z : cd[r / 4].w;
-                    *reinterpret_cast<uint32_t*>(hits_bytes + at) = cr;
-                    const uint32_t nx = ((at + 256u) & ((uint32_t)kMask << 8)) | lb;
-                    at = acc[r] < thr ? nx : at;
+                for (int h8 = 0; h8 < 2; ++h8) {
+                    if (h8 == 1) {
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        while (__ballot(((tp - hd) & kMask) > kRoom)) chunk();
+                    }
+                    uint32_t at = lb | ((uint32_t)tp << 8);
+#pragma unroll
+                    for (int r = 8 * h8; r < 8 * h8 + 8; ++r) {
+                        const uint32_t cr = r % 4 == 0 ? cd[r / 4].x : r % 4 == 1 ? cd[r / 4].y : r % 4 == 2 ? cd[r / 4].z : cd[r / 4].w;
+                        *reinterpret_cast<uint32_t*>(hits_bytes + at) = cr;
+                        const uint32_t nx = ((at + 256u) & ((uint32_t)kMask << 8)) | lb;
+                        at = acc[r] < thr ? nx : at;
+                    }
+                    tp = (int)(at >> 8) & kMask;
                 }
-                tp = (int)(at >> 8) & kMask;
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
