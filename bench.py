@@ -12,6 +12,7 @@ Only this benchmark's cpu_baseline leg runs the CPU oracle (on a bounded sample)
 """
 import argparse
 import hashlib
+import re
 import json
 import math
 import os
@@ -97,11 +98,17 @@ def spread_gather_hbm(info, sizes, N, per_launch, rs):
 
 
 def source_digest():
+    """Digest of the library's sources with comments and white space taken out, so that
+    the committed profiles stay tied to the kernels' code and not to their comments."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2412_04595_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(d, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update(f.encode())
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

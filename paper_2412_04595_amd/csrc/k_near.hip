@@ -412,8 +412,9 @@ struct NearMfmaK {
     // The hits go to one of two sinks.  float32: a ring per lane (the lane's target, its
     // sums in registers), drained kEval entries per lane at a time while every lane has that
     // many.  float64: a stack per wave (codes, targets), evaluated kRound entries at a time,
-    // each pair adding its terms to its target's sums in LDS (ds_add_f64; float32 adds to
-    // LDS are far slower on this chip, so the float32 kernel keeps its sums in registers).
+    // each pair adding its terms to its target's sums in LDS (ds_add_f64; on gfx950 the
+    // float32 LDS add, ds_add_f32, runs at about a twentieth of ds_add_f64's rate, so the
+    // float32 kernel keeps its sums in registers).
     constexpr int kEval = kF64 ? 2 : 4;           // entries evaluated per lane per round
     constexpr int kRound = 64 * kEval;            // stack: entries evaluated per round
     constexpr int kStack = kRound - 1 + 1024;     // stack: entries left below a round + one block's hits
@@ -463,8 +464,9 @@ struct NearMfmaK {
     // the chunk's z extent (its targets are z-sorted): frame-relative z plus the frame base
     const float tzlo = pos32[tb].z + (float)(z0 / kNearFrameCells) * fh;
     const float tzhi = pos32[te - 1].z + (float)((z1 - 1) / kNearFrameCells) * fh;
-    // lane k < 18: range k = column (dx, dy) = k / 2, piece k % 2 of the cells from below
-    // the run to above it, cut at the frame boundary; its shift into the unit frame
+    // lane k < 18: range k = neighbour column k / 2 of the walk (kNearColumnOrder), piece
+    // k % 2 of the cells from below the run to above it, cut at the frame boundary; its
+    // shift into the unit frame
     int rs = 0, len = 0;
     vec4<float> sk = {0.f, 0.f, 0.f, 0.f};
     if (lane < 18) {
