@@ -305,28 +305,32 @@ struct SpreadK {
         for (int pl = 0; pl < NPL; ++pl) off[pl][ps] = (pl * planestep + o) * (int)sizeof(real);
     }
     const int sinkb = (totp + lane) * (int)sizeof(real);
-    // thread t holds particle t mod kSpreadStage of the next batch, loaded one batch ahead
-    // (indices clamped into the tile's list, so every load is valid and unconditional)
-    const int slot = threadIdx.x & (kSpreadStage - 1);
-    int4 gq = a.gp[min(beg + slot, end - 1)];
-    vec4<real> uq = a.up[min(beg + slot, end - 1)];
+    // thread t holds particle g0 + t of the tile's current group of kSpreadThreads
+    // particles (one load per group of batches; indices clamped into the tile's list, so
+    // every load is valid and unconditional)
+    static_assert(kSpreadThreads % kSpreadStage == 0, "a group of particles is whole batches");
+    int g0 = beg;
+    int4 gq = a.gp[min(beg + (int)threadIdx.x, end - 1)];
+    vec4<real> uq = a.up[min(beg + (int)threadIdx.x, end - 1)];
     for (int c0 = beg; c0 < end; c0 += kSpreadStage) {
         const int cnt = min(kSpreadStage, end - c0);
+        if (c0 - g0 >= kSpreadThreads) {
+            g0 += kSpreadThreads;
+            gq = a.gp[min(g0 + (int)threadIdx.x, end - 1)];
+            uq = a.up[min(g0 + (int)threadIdx.x, end - 1)];
+        }
         __syncthreads();
-        if ((int)threadIdx.x < cnt) {
+        // this thread's place in the batch
+        const int sidx = (int)threadIdx.x - (c0 - g0);
+        if (sidx >= 0 && sidx < cnt) {
             const int lx0 = gq.x - x0;
             const int corner = lx0 * HYZ + (gq.y - y0) * HZ + (gq.z - z0);
             int m[4];
 #pragma unroll
             for (int g = 0; g < 4; ++g) m[g] = (corner + ((g - lx0) & 3) * HYZ) * (int)sizeof(real);
-            meta[threadIdx.x] = int4{m[0], m[1], m[2], m[3]};
-            slx[threadIdx.x] = lx0;
-            sup[threadIdx.x] = vec4<real>{uq.x, uq.y, uq.z, uq.w};
-        }
-        {
-            const int nx = min(c0 + kSpreadStage + slot, end - 1);
-            gq = a.gp[nx];
-            uq = a.up[nx];
+            meta[sidx] = int4{m[0], m[1], m[2], m[3]};
+            slx[sidx] = lx0;
+            sup[sidx] = vec4<real>{uq.x, uq.y, uq.z, uq.w};
         }
         __syncthreads();
         // y, z weights and a zero; per wave g the x weights of its planes (x = g mod 4)
