@@ -218,8 +218,10 @@ sog_status sog_plan_resolve(const double box[3], int64_t n, double tol, const so
                             sog_params* out);
 
 /* The discretisations an autotuned plan timed (options.autotune): up to max of them, in
- * the order timed, with r_c, the range split m and the milliseconds per call on the
- * synthetic sample; *count = 0 for a plan that was not autotuned.  The plan's own
+ * the order built, with r_c, the range split m and the milliseconds per call on the
+ * synthetic sample (calls back to back; the candidates timed in turn over several
+ * rounds, each keeping its fastest); *count = 0 for a plan that was not autotuned.  The
+ * plan's own
  * parameters (sog_plan_info) are those of the fastest. */
 sog_status sog_plan_tuning(sog_plan_t plan, int32_t max, int32_t* count, double* rc, int32_t* m, double* ms);
 

@@ -1047,11 +1047,16 @@ static sog_status create_plan(const double box[3], int64_t n, double tol, const 
 
 // Autotuning: the planner's cheapest discretisations by its cost model, one per distinct
 // r_c up to kTuneCandidates, each built as a plan (device pointers, no checks, no
-// timing) and timed on the plan's stream with HIP events (one warm-up call, then
-// kTuneCalls) on uniformly random positions in the box with charges +1, -1 alternating
-// (the last one 0 for odd n: neutral); the fastest (r_c, m) is then planned with the
-// caller's options.  Inputs other than uniform ones may rank the candidates differently.
+// timing), given one warm-up call (which captures its graph), then timed on the plan's
+// stream with HIP events over kTuneCalls calls back to back (as calls follow one another
+// in use), the candidates in turn for kTuneRounds rounds (so that no candidate alone
+// meets a cold or still clocking-up device), each keeping its fastest round; inputs:
+// uniformly random positions in the box with charges +1, -1
+// alternating (the last one 0 for odd n: neutral).  The fastest (r_c, m) is then planned
+// with the caller's options.  Inputs other than uniform ones may rank the candidates
+// differently.
 constexpr int kTuneCandidates = 3;
+constexpr int kTuneRounds = 4;
 constexpr int kTuneCalls = 3;
 
 static sog_status autotune_plan(const double box[3], int64_t n, double tol, const sog_options& opt, Plan** out) {
@@ -1126,6 +1131,14 @@ static sog_status autotune_plan(const double box[3], int64_t n, double tol, cons
         return hip_status(he, "autotune sample");
     }
     std::vector<TunedCandidate> tuned;
+    std::vector<Plan*> plans;
+    auto free_plans = [&]() {
+        for (Plan* q : plans) {
+            free_plan(*q);
+            delete q;
+        }
+        plans.clear();
+    };
     for (const PlanCandidate& c : pick) {
         sog_options o = opt;
         o.autotune = 0;
@@ -1138,22 +1151,30 @@ static sog_status autotune_plan(const double box[3], int64_t n, double tol, cons
         o.params.eta = 0;
         Plan* p = nullptr;
         if (create_plan(box, n, tol, o, &p) != SOG_OK) continue;  // not buildable: not a candidate
-        sog_status rs = SOG_OK;
-        float ms = 0;
-        for (int k = 0; k <= kTuneCalls && rs == SOG_OK; ++k) {
-            if (k == 1) he = hipEventRecord(e0, p->stream);
-            rs = run(*p, dx, dq, dU, dphi, dF, nullptr, nullptr, nullptr);
+        plans.push_back(p);
+        tuned.push_back(TunedCandidate{c.rc, c.m, 0.0});
+    }
+    sog_status rs = SOG_OK;
+    for (size_t i = 0; i < plans.size() && rs == SOG_OK; ++i) {
+        rs = run(*plans[i], dx, dq, dU, dphi, dF, nullptr, nullptr, nullptr);
+        if (rs == SOG_OK && (he = hipStreamSynchronize(plans[i]->stream)) != hipSuccess) break;
+    }
+    for (int round = 0; round < kTuneRounds && rs == SOG_OK && he == hipSuccess; ++round)
+        for (size_t i = 0; i < plans.size() && rs == SOG_OK && he == hipSuccess; ++i) {
+            float ms = 0;
+            he = hipEventRecord(e0, plans[i]->stream);
+            for (int k = 0; k < kTuneCalls && rs == SOG_OK && he == hipSuccess; ++k)
+                rs = run(*plans[i], dx, dq, dU, dphi, dF, nullptr, nullptr, nullptr);
+            if (rs == SOG_OK && he == hipSuccess) he = hipEventRecord(e1, plans[i]->stream);
+            if (rs == SOG_OK && he == hipSuccess) he = hipEventSynchronize(e1);
+            if (rs == SOG_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            ms /= kTuneCalls;
+            if (rs == SOG_OK && he == hipSuccess && (round == 0 || ms < tuned[i].ms)) tuned[i].ms = ms;
         }
-        if (rs == SOG_OK && he == hipSuccess) he = hipEventRecord(e1, p->stream);
-        if (rs == SOG_OK && he == hipSuccess) he = hipEventSynchronize(e1);
-        if (rs == SOG_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-        free_plan(*p);
-        delete p;
-        if (rs != SOG_OK || he != hipSuccess) {
-            release();
-            return rs != SOG_OK ? rs : hip_status(he, "autotune timing");
-        }
-        tuned.push_back(TunedCandidate{c.rc, c.m, (double)ms / kTuneCalls});
+    free_plans();
+    if (rs != SOG_OK || he != hipSuccess) {
+        release();
+        return rs != SOG_OK ? rs : hip_status(he, "autotune timing");
     }
     release();
     if (tuned.empty()) {
