@@ -109,11 +109,14 @@ struct WinShape {
 
 // node o's polynomial weight at offset u, and its derivative in u (Horner).  Each node's
 // row holds nu + 1 coefficients, a multiple of 4 (leading zeros, which leave Horner's
-// rule exact), taken 4 at a time.
+// rule exact), taken 4 at a time.  The table (global memory, read-only during a call) is
+// read through the constant address space: where the node is the same in every lane (the
+// gathering's loops) the reads are scalar loads and the coefficients scalar operands.
+template <typename real>
+using win_table = const __attribute__((address_space(4))) real*;
 template <typename real>
 __device__ __forceinline__ real win_poly(int o, real u, const WinShape<real>& s) {
-    typedef const __attribute__((address_space(1))) real* gptr;  // the table is in global memory
-    const gptr c = (gptr)s.poly + o * (s.nu + 1);
+    const win_table<real> c = (win_table<real>)s.poly + o * (s.nu + 1);
     real w = 0;
     for (int j = 0; j <= s.nu; j += 4) {
 #pragma unroll
@@ -123,8 +126,7 @@ __device__ __forceinline__ real win_poly(int o, real u, const WinShape<real>& s)
 }
 template <typename real>
 __device__ __forceinline__ void win_poly_d(int o, real u, const WinShape<real>& s, real& w, real& dw) {
-    typedef const __attribute__((address_space(1))) real* gptr;
-    const gptr c = (gptr)s.poly + o * (s.nu + 1);
+    const win_table<real> c = (win_table<real>)s.poly + o * (s.nu + 1);
     real v = 0, d = 0;
     for (int j = 0; j <= s.nu; j += 4) {
 #pragma unroll
@@ -141,10 +143,10 @@ __device__ __forceinline__ void win_poly_d(int o, real u, const WinShape<real>& 
 template <typename real, int PW>
 __device__ __forceinline__ void win_poly_all(real u, const WinShape<real>& s, real dcoef, real* w, real* dw) {
     const int n1 = s.nu + 1;
-    // the table is in global memory (read through a flat pointer taken from the LDS copy
-    // of a batched launch's arguments, the compiler emitted an invalid aperture test)
-    typedef const __attribute__((address_space(1))) real* gptr;
-    const gptr c = (gptr)s.poly;
+    // the table is read through the constant address space (as win_poly; a flat pointer
+    // taken from the LDS copy of a batched launch's arguments made the compiler emit an
+    // invalid aperture test)
+    const win_table<real> c = (win_table<real>)s.poly;
 #pragma unroll
     for (int o = 0; o < PW; ++o) w[o] = dw[o] = 0;
     for (int j = 0; j < n1; ++j) {
