@@ -110,16 +110,18 @@ class Solver:
             return torch.empty(*shape, dtype=torch.float64, device=f"cuda:{self.device}")
         return np.empty(shape, dtype=np.float64)
 
-    def __call__(self, x, q, energy=True, potential=True, forces=True, static=False):
+    def __call__(self, x, q, energy=True, potential=True, forces=True, static=False, energy_on_device=False):
         """Returns (U, phi, force); entries not requested are None.  static: through
-        sog_energy_potential_force_static (the library's static scratch)."""
+        sog_energy_potential_force_static (the library's static scratch).  U is a float,
+        read back from the device (which waits for the call to finish), or with
+        energy_on_device a one-element tensor where the call leaves it (device plans)."""
         x, q = self._inputs(x, q)
         U = self._alloc(1) if energy else None
         phi = self._alloc(self.n) if potential else None
         F = self._alloc(self.n, 3) if forces else None
         call = sog_energy_potential_force_static if static else sog_energy_potential_force
         call(self.plan, _ptr(x), _ptr(q), _ptr(U), _ptr(phi), _ptr(F))
-        if U is not None:
+        if U is not None and not energy_on_device:
             U = float(U[0])
         return U, phi, F
 

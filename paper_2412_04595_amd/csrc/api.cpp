@@ -1049,8 +1049,10 @@ static sog_status create_plan(const double box[3], int64_t n, double tol, const 
 // r_c up to kTuneCandidates, each built as a plan (device pointers, no checks, no
 // timing), given one warm-up call (which captures its graph), then timed on the plan's
 // stream with HIP events over kTuneCalls calls back to back (as calls follow one another
-// in use), the candidates in turn for kTuneRounds rounds (so that no candidate alone
-// meets a cold or still clocking-up device), each keeping its fastest round; inputs:
+// in use) after kTuneWarm untimed ones (so that the caches hold this candidate's data,
+// not the previous one's), the candidates in turn for kTuneRounds rounds (so that no
+// candidate alone meets a cold or still clocking-up device), each keeping its fastest
+// round; inputs:
 // uniformly random positions in the box with charges +1, -1
 // alternating (the last one 0 for odd n: neutral).  The fastest (r_c, m) is then planned
 // with the caller's options.  Inputs other than uniform ones may rank the candidates
@@ -1058,6 +1060,7 @@ static sog_status create_plan(const double box[3], int64_t n, double tol, const 
 constexpr int kTuneCandidates = 3;
 constexpr int kTuneRounds = 4;
 constexpr int kTuneCalls = 3;
+constexpr int kTuneWarm = 2;
 
 static sog_status autotune_plan(const double box[3], int64_t n, double tol, const sog_options& opt, Plan** out) {
     *out = nullptr;
@@ -1162,7 +1165,9 @@ static sog_status autotune_plan(const double box[3], int64_t n, double tol, cons
     for (int round = 0; round < kTuneRounds && rs == SOG_OK && he == hipSuccess; ++round)
         for (size_t i = 0; i < plans.size() && rs == SOG_OK && he == hipSuccess; ++i) {
             float ms = 0;
-            he = hipEventRecord(e0, plans[i]->stream);
+            for (int k = 0; k < kTuneWarm && rs == SOG_OK; ++k)
+                rs = run(*plans[i], dx, dq, dU, dphi, dF, nullptr, nullptr, nullptr);
+            if (rs == SOG_OK) he = hipEventRecord(e0, plans[i]->stream);
             for (int k = 0; k < kTuneCalls && rs == SOG_OK && he == hipSuccess; ++k)
                 rs = run(*plans[i], dx, dq, dU, dphi, dF, nullptr, nullptr, nullptr);
             if (rs == SOG_OK && he == hipSuccess) he = hipEventRecord(e1, plans[i]->stream);
