@@ -78,3 +78,37 @@ def test_graph_host_pointers_and_partial_outputs():
     assert _rel(pg, pe) < 1e-12
     g.close()
     e.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_graph_calls_queued_without_host_reads(precision):
+    """Calls queued back to back with every output left on the device (the energy as a
+    one-element tensor: no host read between calls, as the benchmark times them), on
+    different inputs, each checked afterwards against an eager plan's call on its inputs."""
+    import torch
+    import paper_2412_04595_amd as sog
+    c = CASES["cube_small"]
+    x, q = workloads.uniform(c["N"], c["box"], c["seed"])
+    print(f"[gpu] graph calls queued {precision}", flush=True)
+    tol = 1e-6 if precision == "fp64" else 1e-4
+    g = sog.Solver(c["box"], c["N"], tol, precision=precision, params=gpu_params(c), on_device=True)
+    e = sog.Solver(c["box"], c["N"], tol, precision=precision, params=gpu_params(c), on_device=True, eager=True)
+    rng = np.random.default_rng(9)
+    ins, outs = [], []
+    for rep in range(5):
+        xs = x.copy()
+        xs[:, :2] += rng.uniform(-0.3, 0.3, size=(len(q), 2))
+        qs = q * (1.0 if rep % 2 == 0 else -1.0)
+        xt, qt = torch.from_numpy(xs).cuda(), torch.from_numpy(qs).cuda()
+        ins.append((xt, qt))
+        outs.append(g(xt, qt, energy_on_device=True))
+    torch.cuda.synchronize()
+    for rep, ((xt, qt), (Ug, pg, Fg)) in enumerate(zip(ins, outs)):
+        assert isinstance(Ug, torch.Tensor) and Ug.is_cuda and Ug.numel() == 1
+        Ue, pe, Fe = e(xt, qt)
+        ep, eF = _rel(pg.cpu(), pe.cpu()), _rel(Fg.cpu(), Fe.cpu())
+        eU = abs(float(Ug[0]) - Ue) / abs(Ue)
+        print(f"    call {rep}: phi {ep:.1e} F {eF:.1e} U {eU:.1e}", flush=True)
+        assert ep < TOL[precision] and eF < TOL[precision] and eU < TOL[precision]
+    g.close()
+    e.close()
