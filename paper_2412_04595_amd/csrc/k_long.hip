@@ -33,6 +33,7 @@ struct MomArgs {
     int nkx, nky, nh, P;
     int per_block;  // particles per block
     int chunk;      // particles per LDS batch (<= kMomThreads)
+    int ts, es;     // LDS row strides of the T_n rows and of the exponential rows (elements)
     int nitems;
     double* mu;     // blocks x nh x P complex
 };
@@ -63,10 +64,11 @@ struct MomentsK {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int CH = a.chunk, P = a.P;
     const int NX = 2 * a.nkx + 1, NY = a.nky + 1;
-    real* Tn = reinterpret_cast<real*>(smem_raw);                    // P x CH
-    cpx<real>* ex = reinterpret_cast<cpx<real>*>(Tn + P * CH);        // NX x CH (includes q)
-    cpx<real>* ey = ex + NX * CH;                                     // NY x CH
-    cpx<real>* red = ey + NY * CH;                                    // kMomThreads x 4
+    const int TS = a.ts, ES = a.es;
+    real* Tn = reinterpret_cast<real*>(smem_raw);                            // P rows of TS
+    cpx<real>* ex = reinterpret_cast<cpx<real>*>(Tn + ((P * TS + 3) & ~3));  // NX rows of ES (includes q)
+    cpx<real>* ey = ex + NX * ES;                                             // NY rows of ES
+    cpx<real>* red = ey + NY * ES;                                            // kMomThreads x 4
     const int PB = (P + 3) / 4;
     const int item_l = threadIdx.x / G, sub = threadIdx.x - item_l * G;
     const int item = item0 + item_l;
@@ -96,10 +98,10 @@ struct MomentsK {
                 const real tr = (real)tt;
                 real T0 = 1, T1 = tr;
                 Tn[t] = T0;
-                if (P > 1) Tn[CH + t] = T1;
+                if (P > 1) Tn[TS + t] = T1;
                 for (int k = 2; k < P; ++k) {
                     const real T2 = (real)2 * tr * T1 - T0;
-                    Tn[k * CH + t] = T2;
+                    Tn[k * TS + t] = T2;
                     T0 = T1;
                     T1 = T2;
                 }
@@ -110,31 +112,31 @@ struct MomentsK {
                 const cpx<real> e2 = {cy, -sy};
                 // e^{-i nx kx0 x} for nx = -nkx..nkx, times q
                 cpx<real> pw = {(real)qq, 0};
-                ex[a.nkx * CH + t] = pw;
+                ex[a.nkx * ES + t] = pw;
                 cpx<real> pp = pw, pm = pw;
                 for (int k = 1; k <= a.nkx; ++k) {
                     pp = cmul(pp, e1);
                     pm = cmulc(pm, e1);
-                    ex[(a.nkx + k) * CH + t] = pp;
-                    ex[(a.nkx - k) * CH + t] = pm;
+                    ex[(a.nkx + k) * ES + t] = pp;
+                    ex[(a.nkx - k) * ES + t] = pm;
                 }
                 cpx<real> py = {1, 0};
                 ey[t] = py;
                 for (int k = 1; k <= a.nky; ++k) {
                     py = cmul(py, e2);
-                    ey[k * CH + t] = py;
+                    ey[k * ES + t] = py;
                 }
             }
         }
         __syncthreads();
         if (act) {
-            const cpx<real>* exr = ex + (nxs + a.nkx) * CH;
-            const cpx<real>* eyr = ey + nys * CH;
+            const cpx<real>* exr = ex + (nxs + a.nkx) * ES;
+            const cpx<real>* eyr = ey + nys * ES;
             for (int j = sub; j < cnt; j += G) {
                 const cpx<real> e = cmul(exr[j], eyr[j]);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const real tv = Tn[min(n0 + c, P - 1) * CH + j];
+                    const real tv = Tn[min(n0 + c, P - 1) * TS + j];
                     acc[c].x += e.x * tv;
                     acc[c].y += e.y * tv;
                 }
@@ -326,17 +328,28 @@ hipError_t run_long_direct(Plan& p, const double* x, const double* q) {
     a.P = P;
     const int nb = ws.long_blocks;
     a.per_block = (n + nb - 1) / nb;
-    int CH = kMomThreads;
+    // LDS rows padded one (T_n) and four (exponentials) elements past the chunk: a wave reads
+    // 4 degree rows and 4 modes at 4 consecutive particles, and a row stride that is a multiple
+    // of the bank count puts all of them in the same 4 banks. Unpadded where only that fits.
     const size_t red_bytes = (size_t)kMomThreads * 4 * sizeof(cpx<real>);
-    auto lds_of = [&](int ch) { return (size_t)ch * (P * sizeof(real) + (NX + NY) * sizeof(cpx<real>)) + red_bytes; };
-    while (CH > 16 && lds_of(CH) > 49152) CH >>= 1;
-    if (lds_of(CH) > 65536) return hipErrorInvalidConfiguration;
+    auto lds_of = [&](int ch, int pad) {
+        return ((size_t)P * (ch + pad) + 3) / 4 * 4 * sizeof(real) + (size_t)(NX + NY) * (ch + 4 * pad) * sizeof(cpx<real>) +
+               red_bytes;
+    };
+    int CH = kMomThreads, pad = 1;
+    for (;; pad = 0, CH = kMomThreads) {
+        while (CH > 16 && lds_of(CH, pad) > 49152) CH >>= 1;
+        if (lds_of(CH, pad) <= 65536 || pad == 0) break;
+    }
+    if (lds_of(CH, pad) > 65536) return hipErrorInvalidConfiguration;
     a.chunk = CH;
+    a.ts = CH + pad;
+    a.es = CH + 4 * pad;
     a.mu = ws.long_mu;
     const int PB = (P + 3) / 4;
     const int nitems = nh * PB;
     a.nitems = nitems;
-    const size_t lds = lds_of(CH);
+    const size_t lds = lds_of(CH, pad);
     int t = timer_id(p, "long_moments");
     timer_begin(p, t);
     hipError_t e = launch<MomentsK<real>>(p, nb, lds, a);
