@@ -60,6 +60,19 @@ inline size_t spread_lds_bytes(size_t real_bytes, int Pw, int Bx, int By, int Bz
     return spread_lds_offset_records(real_bytes, Pw, Bx, By, Bz) + (size_t)kSpreadStage * (4 * real_bytes + 20);
 }
 
+// LDS of the direct long range's moments kernel (kMomThreads threads) for a batch of ch
+// particles: the P Chebyshev rows (ch + pad reals each, rounded up to 4 entries), the
+// 2 n_kx + 1 and n_ky + 1 rows of plane waves (ch + 4 pad complex each) and the threads'
+// 4 complex partial sums.  pad = 1 staggers the rows across the LDS banks.
+constexpr int kMomThreads = 256;
+constexpr int kMomMinChunk = 16;
+constexpr size_t kMomMaxLds = 65536;
+inline size_t long_moments_lds(size_t real_bytes, int P, int nkx, int nky, int ch, int pad) {
+    const size_t rows = (size_t)(2 * nkx + 1) + (size_t)(nky + 1);
+    return ((size_t)P * (ch + pad) + 3) / 4 * 4 * real_bytes + rows * (ch + 4 * pad) * 2 * real_bytes +
+           (size_t)kMomThreads * 4 * 2 * real_bytes;
+}
+
 // Row stride (complex entries) of the mid-range half spectrum: I_z*/2 + 1 rounded up to a
 // multiple of 16, so that the 16-entry row segments the y and x passes move are whole
 // 128-byte lines.

@@ -22,8 +22,6 @@ namespace sog {
 
 namespace {
 
-constexpr int kMomThreads = 256;  // an item is (mode, 4 consecutive n); G threads share an item
-
 template <typename real>
 struct MomArgs {
     const double* x;
@@ -316,7 +314,6 @@ hipError_t run_long_direct(Plan& p, const double* x, const double* q) {
     const Resolved& r = p.r;
     Workspace& ws = p.ws;
     const int n = (int)r.n, P = r.P, nh = r.nh;
-    const int NX = 2 * r.nk[0] + 1, NY = r.nk[1] + 1;
     MomArgs<real> a;
     a.x = x;
     a.q = q;
@@ -331,17 +328,13 @@ hipError_t run_long_direct(Plan& p, const double* x, const double* q) {
     // LDS rows padded one (T_n) and four (exponentials) elements past the chunk: a wave reads
     // 4 degree rows and 4 modes at 4 consecutive particles, and a row stride that is a multiple
     // of the bank count puts all of them in the same 4 banks. Unpadded where only that fits.
-    const size_t red_bytes = (size_t)kMomThreads * 4 * sizeof(cpx<real>);
-    auto lds_of = [&](int ch, int pad) {
-        return ((size_t)P * (ch + pad) + 3) / 4 * 4 * sizeof(real) + (size_t)(NX + NY) * (ch + 4 * pad) * sizeof(cpx<real>) +
-               red_bytes;
-    };
+    auto lds_of = [&](int ch, int pad) { return long_moments_lds(sizeof(real), P, r.nk[0], r.nk[1], ch, pad); };
     int CH = kMomThreads, pad = 1;
     for (;; pad = 0, CH = kMomThreads) {
-        while (CH > 16 && lds_of(CH, pad) > 49152) CH >>= 1;
-        if (lds_of(CH, pad) <= 65536 || pad == 0) break;
+        while (CH > kMomMinChunk && lds_of(CH, pad) > 49152) CH >>= 1;
+        if (lds_of(CH, pad) <= kMomMaxLds || pad == 0) break;
     }
-    if (lds_of(CH, pad) > 65536) return hipErrorInvalidConfiguration;
+    if (lds_of(CH, pad) > kMomMaxLds) return hipErrorInvalidConfiguration;
     a.chunk = CH;
     a.ts = CH + pad;
     a.es = CH + 4 * pad;

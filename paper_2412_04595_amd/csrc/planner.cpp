@@ -672,6 +672,11 @@ LongChoice plan_long(const double L[3], int64_t n, double sl, int nl, double eps
     if (!d.ok)
         d.why = "long range, direct form: " + std::to_string((long long)nh) + " modes x " + std::to_string(P) +
                 " Chebyshev terms exceed the kernel's 65536";
+    else if (long_moments_lds(prec == SOG_PREC_FP64 ? 8 : 4, P, d.nk[0], d.nk[1], kMomMinChunk, 0) > kMomMaxLds) {
+        d.ok = false;
+        d.why = "long range, direct form: " + std::to_string(2 * d.nk[0] + 1) + " + " + std::to_string(d.nk[1] + 1) +
+                " plane-wave rows exceed the moments kernel's LDS";
+    }
     // FFT form (Alg. al::long): 2D Gaussian window on an I^long grid, the mid range's error
     // rules; the z kernel exact (a table per mode) or in App. C's Taylor form (none)
     LongChoice f;
@@ -1139,6 +1144,10 @@ sog_status resolve(const double box[3], int64_t n, double tol, const sog_options
         if (r.form == SOG_LONG_DIRECT) {
             r.nh = (r.nk[0] + 1) + r.nk[1] * (2 * r.nk[0] + 1);
             if ((int64_t)r.nh * r.P > 65536) { err = "too many long-range modes for the direct form"; return SOG_ERR_INVALID_ARG; }
+            if (long_moments_lds(r.prec == SOG_PREC_FP64 ? 8 : 4, r.P, r.nk[0], r.nk[1], kMomMinChunk, 0) > kMomMaxLds) {
+                err = "too many long-range modes in x and y for the direct form's moments kernel";
+                return SOG_ERR_INVALID_ARG;
+            }
             r.Q = r.Ps = 0;
         } else {
             if (r.Pw2 < 3 || r.Pw2 > kMaxPw || (r.Pw2 % 2) == 0) { err = "long-range window must have an odd number of points in [3, 15]"; return SOG_ERR_INVALID_ARG; }

@@ -351,6 +351,26 @@ def test_unreachable_plans_name_the_limit():
     assert ei.value.status in (_lib.SOG_ERR_TOL_UNREACHABLE, _lib.SOG_ERR_INVALID_ARG)
 
 
+def test_direct_form_limited_by_the_moments_lds():
+    """The direct long range's moments kernel holds a batch of at least 16 particles' plane
+    waves (2 n_kx + 1 + n_ky + 1 rows) in LDS: 129 + 65 rows fit in float32, not in float64,
+    where a forced direct form is refused naming the limit and the automatic choice is the
+    FFT form."""
+    from tests._cases import gpu_params
+    params = gpu_params(dict(row=3, rc=2.5, M=120, m=-1, mid=None, long=dict(form="direct", P=4, nk=(64, 64))))
+    box = (40.0, 40.0, 4.0)
+    p = sog.plan_parameters(box, 600, 1e-4, "fp32", params=params)
+    assert p["long_form"] == 1 and list(p["long_nk"]) == [64, 64]
+    with pytest.raises(sog.SogError) as ei:
+        sog.plan_parameters(box, 600, 1e-6, "fp64", params=params)
+    assert ei.value.status == _lib.SOG_ERR_TOL_UNREACHABLE and "LDS" in str(ei.value)
+    auto = {k: v for k, v in params.items() if not k.startswith("long_")}
+    assert sog.plan_parameters(box, 600, 1e-6, "fp64", params=auto)["long_form"] == 2
+    # 121 + 41 rows still fit in float64, unpadded
+    p = sog.plan_parameters((24.0, 20.0, 4.0), 400, 1e-6, "fp64", params=dict(params, long_nk=[60, 40]))
+    assert p["long_form"] == 1 and list(p["long_nk"]) == [60, 40]
+
+
 def test_taylor_form_is_planned_on_request():
     """long_Q > 0 asks for App. C's Taylor form of the z kernel (2Q - 1 source planes, at most
     2Q - 1 target terms); long_Q = -1 for the exact kernel; both plan on the Table 4 box."""
