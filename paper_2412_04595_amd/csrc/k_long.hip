@@ -219,6 +219,7 @@ struct EvalArgs {
     vec4<real>* part;  // long part of each particle: phi, grad
 };
 
+// Evaluation for more Chebyshev terms than EvalRegK takes: T_n and T_n' per thread in LDS.
 // STAGED: the coefficient table (nh x P) is copied to LDS; otherwise (a table larger than
 // LDS) it is read where it is, through scalar loads (every thread reads the same entry)
 template <typename real, bool STAGED, int B>
@@ -309,6 +310,116 @@ struct EvalK {
 }
 };
 
+// P <= PR: T_n(t) and T_n'(t) in registers (loops unrolled over PR, guarded by P), the
+// coefficient table read through scalar loads (every lane reads the same entry): no LDS.
+// PR is 40 in float32 (one kernel for every plan of the batched workloads at tol 1e-4)
+// and 16 in float64 (twice the registers per term).  Terms from 16 on sit behind one test
+// of P per mode: guarded one by one they cost P = 14 more than twice the time.
+template <typename real>
+constexpr int eval_reg_terms() { return sizeof(real) == 4 ? 40 : 16; }
+constexpr int kEvalRegHead = 16;
+template <typename real, int PR>
+struct EvalRegK {
+    static constexpr int kThreads = 256;
+    __device__ static void run(GridPos gpos, const EvalArgs<real>& a) {
+    static_assert(PR >= 2, "two Chebyshev terms at least");
+    constexpr int kHead = PR < kEvalRegHead ? PR : kEvalRegHead;
+    const int P = a.P;
+    using ctab = const __attribute__((address_space(4))) cpx<real>;
+    ctab* ga = (ctab*)a.acoef;
+    const int i = gpos.bid * kThreads + threadIdx.x;
+    if (i >= a.n) return;
+    double xx = a.x[3 * i], yy = a.x[3 * i + 1], zz = a.x[3 * i + 2];
+    if (!(isfinite(xx) && isfinite(yy) && isfinite(zz))) xx = yy = zz = 0;
+    const double xc = wrap_periodic(xx, a.L[0]) - 0.5 * a.L[0];
+    const double yc = wrap_periodic(yy, a.L[1]) - 0.5 * a.L[1];
+    double tt = 2.0 * (zz - 0.5 * a.L[2]) / a.L[2];
+    tt = fmin(1.0, fmax(-1.0, tt));
+    const real tr = (real)tt;
+    real Tt[PR], Td[PR];
+    {
+        real T0 = 1, T1 = tr, U0 = 1, U1 = 2 * tr;
+        Tt[0] = 1;
+        Td[0] = 0;
+        Tt[1] = tr;
+        Td[1] = 1;
+#pragma unroll
+        for (int k = 2; k < kHead; ++k) {
+            if (k < P) {
+                const real T2 = (real)2 * tr * T1 - T0;
+                Tt[k] = T2;
+                Td[k] = (real)k * U1;
+                const real U2 = (real)2 * tr * U1 - U0;
+                T0 = T1; T1 = T2;
+                U0 = U1; U1 = U2;
+            }
+        }
+        if (PR > kHead && P > kHead) {
+#pragma unroll
+            for (int k = kHead; k < PR; ++k) {
+                if (k < P) {
+                    const real T2 = (real)2 * tr * T1 - T0;
+                    Tt[k] = T2;
+                    Td[k] = (real)k * U1;
+                    const real U2 = (real)2 * tr * U1 - U0;
+                    T0 = T1; T1 = T2;
+                    U0 = U1; U1 = U2;
+                }
+            }
+        }
+    }
+    const double kx0 = 2.0 * 3.14159265358979323846 / a.L[0], ky0 = 2.0 * 3.14159265358979323846 / a.L[1];
+    real sx, cx, sy, cy;
+    dsincos((real)(kx0 * xc), &sx, &cx);
+    dsincos((real)(ky0 * yc), &sy, &cy);
+    const cpx<real> e1 = {cx, sx}, e2 = {cy, sy};
+    real phi = 0, gx = 0, gy = 0, gz = 0;
+    const real rkx0 = (real)kx0, rky0 = (real)ky0;
+    cpx<real> eneg = {1, 0};
+    for (int k = 0; k < a.nkx; ++k) eneg = cmulc(eneg, e1);
+    cpx<real> phy = {1, 0};
+    int kk = 0;
+    for (int ny = 0; ny <= a.nky; ++ny) {
+        cpx<real> ph = (ny == 0) ? phy : cmul(phy, eneg);
+        const int nxlo = (ny == 0) ? 0 : -a.nkx;
+        for (int nx = nxlo; nx <= a.nkx; ++nx, ++kk) {
+            real ur = 0, ui = 0, dr = 0, di = 0;
+            ctab* row = ga + (size_t)kk * P;
+#pragma unroll
+            for (int k = 0; k < kHead; ++k) {
+                if (k < P) {
+                    const real c_x = row[k].x, c_y = row[k].y;
+                    ur += Tt[k] * c_x;
+                    ui += Tt[k] * c_y;
+                    dr += Td[k] * c_x;
+                    di += Td[k] * c_y;
+                }
+            }
+            if (PR > kHead && P > kHead) {
+#pragma unroll
+                for (int k = kHead; k < PR; ++k) {
+                    if (k < P) {
+                        const real c_x = row[k].x, c_y = row[k].y;
+                        ur += Tt[k] * c_x;
+                        ui += Tt[k] * c_y;
+                        dr += Td[k] * c_x;
+                        di += Td[k] * c_y;
+                    }
+                }
+            }
+            const real re = ph.x * ur - ph.y * ui, im = ph.x * ui + ph.y * ur;
+            phi += re;
+            gx -= (real)nx * rkx0 * im;
+            gy -= (real)ny * rky0 * im;
+            gz += ph.x * dr - ph.y * di;
+            ph = cmul(ph, e1);
+        }
+        phy = cmul(phy, e2);
+    }
+    a.part[i] = vec4<real>{phi, gx, gy, gz * (real)(2.0 / a.L[2])};
+}
+};
+
 template <typename real>
 hipError_t run_long_direct(Plan& p, const double* x, const double* q) {
     const Resolved& r = p.r;
@@ -377,7 +488,9 @@ hipError_t run_long_direct(Plan& p, const double* x, const double* q) {
     t = timer_id(p, "long_eval");
     timer_begin(p, t);
     const int nbl = (n + B - 1) / B;
-    if (staged)
+    if (P <= eval_reg_terms<real>())
+        e = launch<EvalRegK<real, eval_reg_terms<real>()>>(p, (n + 255) / 256, 0, ea);
+    else if (staged)
         e = B == 256 ? launch<EvalK<real, true, 256>>(p, nbl, lds2, ea)
                      : (B == 128 ? launch<EvalK<real, true, 128>>(p, nbl, lds2, ea) : launch<EvalK<real, true, 64>>(p, nbl, lds2, ea));
     else

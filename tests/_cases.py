@@ -17,10 +17,16 @@ CASES = {
     "ragged": dict(N=2000, box=(13.0, 17.0, 9.0), seed=7, row=3, rc=3.0, M=120, m=5,
                    mid=dict(I=(30, 40, 24), Izs=64, Pw=7), long=dict(form="direct", P=10, nk=(3, 4))),
     # direct long range over 4901 half-plane modes: the moments kernel's float64 LDS rows
-    # unpadded (padded ones would not fit), the evaluation reading its coefficient table where
-    # it is (too large to stage)
+    # unpadded (padded ones would not fit)
     "wide_direct": dict(N=400, box=(24.0, 20.0, 4.0), seed=17, row=3, rc=2.5, M=120, m=-1,
                         mid=None, long=dict(form="direct", P=4, nk=(60, 40))),
+    # direct long range with more Chebyshev terms than the register evaluation takes (40 in
+    # float32, 16 in float64), the coefficient table too large to stage in LDS (841 modes x
+    # 44) and small enough (8 modes x 44)
+    "deep_direct": dict(N=400, box=(24.0, 20.0, 6.0), seed=18, row=3, rc=2.5, M=120, m=-1,
+                        mid=None, long=dict(form="direct", P=44, nk=(20, 20))),
+    "deep_narrow": dict(N=400, box=(24.0, 20.0, 6.0), seed=19, row=3, rc=2.5, M=120, m=-1,
+                        mid=None, long=dict(form="direct", P=44, nk=(2, 1))),
     # flat slab, every Gaussian long range (Remark after the range-splitting definition),
     # Fourier-Chebyshev solver with 2D FFTs
     "slab_all_long_fft": dict(N=1500, box=(24.0, 20.0, 4.0), seed=8, row=3, rc=2.5, M=120, m=-1,
